@@ -1,0 +1,115 @@
+"""Seeded synthetic inputs for the T-product Sylvester equation A*X - X*B = C.
+
+This module holds no arithmetic of the solvers: it only draws random
+tensors and assembles the finite-difference matrices the workloads are made
+of.  Both the GPU path (through the tests and the benchmark) and the FP64
+oracle receive the arrays it returns.
+
+Layout: every tensor is a float64 numpy array of shape (rows, cols, p) in
+Fortran order, so that its memory is T[i + rows*j + rows*cols*k] -- the
+frontal-slice-major layout the C-ABI takes.
+
+Recipes
+-------
+* ``dense_shifted(n, s, p, seed)`` -- A slices i.i.d. N(0,1) scaled, +4 I on
+  slice 1; B slices i.i.d. N(0,1) scaled, -4 I on slice 1; C i.i.d. N(0,1).
+  Draw order A, B, C from ``numpy.random.default_rng(seed)`` with each
+  tensor filled in Fortran order.  ``noise='literal'`` scales by 1/sqrt(n)
+  (resp. 1/sqrt(s)); ``noise='pscaled'`` by 2/sqrt(n p) (resp. 2/sqrt(s p)),
+  which keeps the spectra of the Fourier slices of A and B a fixed distance
+  apart for every p (the literal recipe lets the slice spectra grow like
+  sqrt(p) until they touch).  At p = 4 both are identical.
+* ``convection_diffusion(nx, ny, s, p, seed)`` -- A slice 1 = the 5-point
+  central-difference matrix of -mu Lap(u) + c . grad(u) on the unit square
+  with Dirichlet boundary, an nx x ny interior grid (x fastest), h_x =
+  1/(nx+1), h_y = 1/(ny+1), plus 8 I; A slices 2..p dense i.i.d.
+  N(0, 1e-4); B slices i.i.d. N(0,1)/sqrt(s), -4 I on slice 1; C i.i.d.
+  N(0, 1).  Draw order: A's noise slices, B, C.
+"""
+
+import numpy as np
+
+
+def _normal_tensor(rng, rows, cols, p):
+    return rng.standard_normal(rows * cols * p).reshape((rows, cols, p), order="F")
+
+
+def dense_shifted(n, s, p, seed=0, noise="pscaled", shift=4.0):
+    """Dense random operator family with disjoint Fourier-slice spectra."""
+    rng = np.random.default_rng(seed)
+    if noise == "literal":
+        fa, fb = 1.0 / np.sqrt(n), 1.0 / np.sqrt(s)
+    elif noise == "pscaled":
+        fa, fb = 2.0 / np.sqrt(n * p), 2.0 / np.sqrt(s * p)
+    else:
+        raise ValueError(noise)
+    A = _normal_tensor(rng, n, n, p)
+    A *= fa
+    A[:, :, 0] += shift * np.eye(n)
+    B = _normal_tensor(rng, s, s, p)
+    B *= fb
+    B[:, :, 0] -= shift * np.eye(s)
+    C = _normal_tensor(rng, n, s, p)
+    return np.asfortranarray(A), np.asfortranarray(B), np.asfortranarray(C)
+
+
+def cd5_matrix(nx, ny, mu=1.0, c=(10.0, 10.0), hx=None, hy=None):
+    """Dense 5-point matrix of -mu Lap(u) + c . grad(u), Dirichlet boundary,
+    lexicographic numbering with x fastest.  Diagonal 2 mu/hx^2 + 2 mu/hy^2;
+    x-neighbours -mu/hx^2 -/+ c_x/(2 hx) (west -, east +); likewise in y."""
+    hx = 1.0 / (nx + 1) if hx is None else hx
+    hy = 1.0 / (ny + 1) if hy is None else hy
+    n = nx * ny
+    M = np.zeros((n, n))
+    d = 2 * mu / hx ** 2 + 2 * mu / hy ** 2
+    w, e = -mu / hx ** 2 - c[0] / (2 * hx), -mu / hx ** 2 + c[0] / (2 * hx)
+    so, no = -mu / hy ** 2 - c[1] / (2 * hy), -mu / hy ** 2 + c[1] / (2 * hy)
+    for iy in range(ny):
+        for ix in range(nx):
+            r = ix + nx * iy
+            M[r, r] = d
+            if ix > 0:
+                M[r, r - 1] = w
+            if ix < nx - 1:
+                M[r, r + 1] = e
+            if iy > 0:
+                M[r, r - nx] = so
+            if iy < ny - 1:
+                M[r, r + nx] = no
+    return M
+
+
+def convection_diffusion(nx, ny, s, p, seed=0, mu=1.0, c=(10.0, 10.0),
+                         noise_std=1e-2, shift=8.0):
+    """Convection-diffusion operator family (see the module docstring)."""
+    rng = np.random.default_rng(seed)
+    n = nx * ny
+    A = np.empty((n, n, p), order="F")
+    A[:, :, 0] = cd5_matrix(nx, ny, mu, c) + shift * np.eye(n)
+    if p > 1:
+        noise = rng.standard_normal(n * n * (p - 1)).reshape((n, n, p - 1), order="F")
+        noise *= noise_std
+        A[:, :, 1:] = noise
+        del noise
+    B = _normal_tensor(rng, s, s, p)
+    B *= 1.0 / np.sqrt(s)
+    B[:, :, 0] -= 4.0 * np.eye(s)
+    C = _normal_tensor(rng, n, s, p)
+    return A, np.asfortranarray(B), np.asfortranarray(C)
+
+
+# Named workloads ---------------------------------------------------------
+
+def tiny_dense(seed=0):
+    """8 x 8 x 4 operator, 6 x 6 x 4 right factor, unrestarted tGMRES."""
+    return dense_shifted(8, 6, 4, seed=seed, noise="literal")
+
+
+def cd_4096(seed=0):
+    """n = 4096 (64 x 64 grid, h = 1/65), s = 64, p = 32, dense FP64."""
+    return convection_diffusion(64, 64, 64, 32, seed=seed)
+
+
+def cd_8192(seed=0):
+    """n = 8192 (128 x 64 grid), s = 128, p = 64 (34 GB of FP64 A)."""
+    return convection_diffusion(128, 64, 128, 64, seed=seed)
