@@ -1,0 +1,189 @@
+/*
+ * tsylv.h -- C ABI of the MI355X tensor Krylov solvers for the Sylvester
+ * tensor equation  M(X) = A*X - X*B = C  under the T-product.
+ *
+ * The operation is defined in section 1, eq. (2) and section 5.2 of
+ * Bouyghf, El Guide, El Ichi, "Tensor Krylov subspace methods via the
+ * T-product for large Sylvester tensor equations" (arXiv 2405.09233);
+ * the T-product is the definition of section 2.1.
+ *
+ * Tensor layout (every tensor argument): real, frontal-slice major,
+ * column-major inside a slice (MATLAB order):
+ *     T[i + rows*j + rows*cols*k],  0 <= i < rows, 0 <= j < cols, 0 <= k < p.
+ *   A: n x n x p,   B: s x s x p,   C, X, Y: n x s x p.
+ * All tensor pointers are DEVICE pointers (HBM of the context's GPU), 8-byte
+ * aligned, holding float64.  The caller owns them; the library never frees
+ * or retains them after a synchronous call returns.
+ *
+ * Errors: every call returns a tsylv_status.  Negative values are errors and
+ * leave nothing guaranteed in the output tensor; TSYLV_NOT_CONVERGED leaves
+ * the best iterate in X.  No exception crosses this boundary.  A context is
+ * not thread-safe, except that tsylv_submit and tsylv_poll may be called from
+ * any thread.
+ */
+#ifndef TSYLV_H
+#define TSYLV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tsylv_ctx tsylv_ctx;
+
+/* Precision of the operator applies of the inner solve. */
+typedef enum {
+  TSYLV_FP64 = 0, /* everything in FP64                                     */
+  TSYLV_FP32 = 1, /* FP32 copies of the Fourier slices, FP32 basis vectors   */
+  TSYLV_BF16 = 2  /* BF16 copies of the Fourier slices (FP32 accumulation)   */
+} tsylv_prec;
+
+typedef enum {
+  TSYLV_METHOD_GMRES = 0, /* tGMRES(m), Algorithm 3                        */
+  TSYLV_METHOD_FOM = 1,   /* tFOM(m), Algorithm 3                          */
+  TSYLV_METHOD_TBA = 2    /* TBAS(m), Algorithm 8 (block size s)           */
+} tsylv_method;
+
+typedef enum {
+  TSYLV_OK = 0,
+  TSYLV_NOT_CONVERGED = 1, /* max_cycles reached; X holds the last iterate  */
+  TSYLV_PENDING = 2,       /* tsylv_poll: request not finished yet          */
+  TSYLV_EINVAL = -1,       /* bad size, pointer or option                   */
+  TSYLV_ENOMEM = -2,       /* arena too small for the workspace             */
+  TSYLV_EBREAKDOWN = -3,   /* non-invertible tube in Normalization (TBA)    */
+  TSYLV_ESINGULAR = -4,    /* singular projected problem                    */
+  TSYLV_EHIP = -5,         /* HIP runtime error                             */
+  TSYLV_ECANCELLED = -6    /* request dropped (context destroyed)           */
+} tsylv_status;
+
+/* Solver options (Algorithm 3 and Algorithm 8 inputs: m, Iter_max, tol, X0). */
+typedef struct {
+  int m;            /* restart length (Krylov steps per cycle)              */
+  int max_cycles;   /* Iter_max: maximum number of restart cycles           */
+  double tol;       /* stop when ||C - M(X)||_F / ||C||_F <= tol            */
+  int x0_given;     /* 1: X holds the initial guess on entry; 0: X0 = 0     */
+  int prec;         /* tsylv_prec of the inner applies                      */
+  int refine;       /* 1: FP64 iterative refinement around a prec solve     */
+  int inner_m;      /* restart length of the inner solve (refine = 1)       */
+  double inner_tol; /* relative tolerance of each inner solve               */
+  int max_outer;    /* maximum refinement steps                             */
+  double* res_hist; /* optional HOST buffer: relative residual estimates   */
+  int res_hist_cap; /* capacity of res_hist (entries)                       */
+} tsylv_opts;
+
+/* Result record of a solve. */
+typedef struct {
+  int status;         /* tsylv_status of the solve                          */
+  int steps;          /* applies of M inside Arnoldi (total over cycles)    */
+  int cycles;         /* restart cycles run                                 */
+  int outer;          /* refinement steps (0 without refinement)           */
+  double relres_true; /* ||C - M(X)||_F / ||C||_F, recomputed in FP64       */
+  double relres_est;  /* last cheap estimate (|gamma|, h|y|, ||H E Y||)     */
+  double seconds;     /* wall time of the call                              */
+  int res_hist_len;   /* entries written to opts->res_hist                  */
+  int fom_fallback;   /* tFOM cycles that fell back to the tGMRES solution  */
+} tsylv_info;
+
+/* Defaults: m = 30 (tGMRES/tFOM) or 10 (TBA), max_cycles = 500,
+ * tol = 1e-8, X0 = 0, FP64, no refinement, inner_m = 40, inner_tol = 1e-4,
+ * max_outer = 20. */
+void tsylv_default_opts(int method, tsylv_opts* opts);
+
+/* Create a context on HIP device `device`, issuing all work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  `arena` is a DEVICE buffer of
+ * `arena_bytes` bytes owned by the caller that holds every workspace the
+ * library needs (the HBM budget); it must outlive the context.  If `arena`
+ * is NULL the library allocates `arena_bytes` itself at creation (never on
+ * the solve path) and frees it in tsylv_destroy. */
+int tsylv_create(tsylv_ctx** out, int device, void* hip_stream, void* arena,
+                 size_t arena_bytes);
+
+/* Destroy a context: waits for submitted requests (cancelling those not yet
+ * admitted), then releases everything the library allocated. */
+int tsylv_destroy(tsylv_ctx* ctx);
+
+/* Arena bytes one synchronous call of `method` needs for these sizes
+ * (method = -1: tsylv_apply).  0 on invalid arguments. */
+size_t tsylv_workspace_bytes(int method, int64_t n, int64_t s, int64_t p,
+                             const tsylv_opts* opts);
+
+/* Y = A*X - X*B  (eq. (2)), computed as Algorithm 1 of section 2.1 does:
+ * mode-3 DFT, facewise products on the conjugate-symmetric half of the
+ * Fourier slices, inverse DFT.  Synchronous on the context stream. */
+int tsylv_apply(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p,
+                const double* A, const double* B, const double* X, double* Y,
+                int prec);
+
+/* tFOM(m), Algorithm 3 of section 3 (Galerkin condition, section 3.2). */
+int tsylv_fom(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A,
+              const double* B, const double* C, double* X,
+              const tsylv_opts* opts, tsylv_info* info);
+
+/* tGMRES(m), Algorithm 3 of section 3 (minimal residual, section 3.3).
+ * With opts->refine = 1: FP64 iterative refinement whose correction
+ * equations are solved by tGMRES(inner_m) in opts->prec. */
+int tsylv_gmres(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p,
+                const double* A, const double* B, const double* C, double* X,
+                const tsylv_opts* opts, tsylv_info* info);
+
+/* TBAS(m), Algorithm 8 of section 5.2: Tubal Block Arnoldi on A with block
+ * size s, projected equation H_m*Y - Y*B = V_m^T*R0 solved per Fourier
+ * slice in FP64. */
+int tsylv_tba(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A,
+              const double* B, const double* C, double* X,
+              const tsylv_opts* opts, tsylv_info* info);
+
+/* Asynchronous solves (continuous batching).  A request is admitted when its
+ * workspace fits in the arena; admitted requests are stepped together on the
+ * GPU.  The pointers in the request must stay valid until tsylv_poll returns
+ * a final status for its ticket. */
+typedef struct {
+  int method;                 /* tsylv_method (GMRES or FOM)                 */
+  int64_t n, s, p;
+  const double* A;            /* device pointers, layout as above           */
+  const double* B;
+  const double* C;
+  double* X;                  /* output (and X0 when opts.x0_given)         */
+  tsylv_opts opts;
+} tsylv_request;
+
+/* Queue a request; returns at once with a ticket. */
+int tsylv_submit(tsylv_ctx* ctx, const tsylv_request* req, uint64_t* ticket);
+
+/* TSYLV_PENDING while the request runs; otherwise its final status, with
+ * `info` filled (info may be NULL).  A ticket may be polled after it is
+ * final, until the context is destroyed. */
+int tsylv_poll(tsylv_ctx* ctx, uint64_t ticket, tsylv_info* info);
+
+/* Kernel timing for benchmarks.  While enabled, every launch of a timed
+ * kernel family is bracketed by HIP events recorded on the context stream
+ * (the stream the kernels run on); tsylv_profile_read folds the elapsed
+ * times into per-family totals.  Off by default. */
+typedef enum {
+  TSYLV_K_APPLY = 0, /* facewise operator apply  Ahat_k V_k - V_k Bhat_k     */
+  TSYLV_K_ORTHO = 1, /* Gram-Schmidt dots, updates, norms                     */
+  TSYLV_K_XFORM = 2, /* mode-3 DFT / inverse DFT of the tubes                 */
+  TSYLV_K_COUNT = 3
+} tsylv_kernel_id;
+
+typedef struct {
+  int64_t launches; /* timed launches since tsylv_profile(ctx, 1)           */
+  double total_ms;  /* summed event-to-event time of those launches         */
+} tsylv_kstat;
+
+/* enable != 0: reset the totals and start timing; 0: stop. */
+int tsylv_profile(tsylv_ctx* ctx, int enable);
+
+/* Synchronises the context stream and returns the totals of one family. */
+int tsylv_profile_read(tsylv_ctx* ctx, int kernel_id, tsylv_kstat* out);
+
+/* Static string describing a status code. */
+const char* tsylv_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSYLV_H */

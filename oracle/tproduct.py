@@ -212,3 +212,24 @@ def block_diag_of_dft(A):
     for k in range(p):
         out[k * n1:(k + 1) * n1, k * n2:(k + 1) * n2] = Ah[:, :, k]
     return out
+
+
+def sylv_op_entries(A, B, X, idx):
+    """Selected entries of M(X) = A*X - X*B (eq. (2)), each by its own
+    circulant sum: for (i, c, k) in idx,
+
+        M(X)[i, c, k] = sum_j A[i, :, (k-j) mod p] . X[:, c, j]
+                        - sum_j X[i, :, (k-j) mod p] . B[:, c, j].
+
+    Cost O((n + s) p) per entry, so it can spot-check operators far too
+    large for :func:`sylv_op`."""
+    p = A.shape[2]
+    out = np.zeros(len(idx))
+    for t, (i, c, k) in enumerate(idx):
+        acc = 0.0
+        for j in range(p):
+            kj = (k - j) % p
+            acc += float(A[i, :, kj] @ X[:, c, j])
+            acc -= float(X[i, :, kj] @ B[:, c, j])
+        out[t] = acc
+    return out

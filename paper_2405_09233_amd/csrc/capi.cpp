@@ -1,0 +1,216 @@
+// extern "C" boundary: argument checks, context handling, error mapping.
+#include <cstring>
+#include <new>
+
+#include "runtime.hpp"
+#include "solvers.hpp"
+
+using namespace tsylv;
+
+struct tsylv_ctx {
+  Ctx c;
+};
+
+namespace {
+
+constexpr size_t kPinned = 1 << 16;  // doubles of pinned host staging
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    return TSYLV_ENOMEM;
+  } catch (...) {
+    return TSYLV_EHIP;
+  }
+}
+
+bool dims_ok(int64_t n, int64_t s, int64_t p) {
+  return n > 0 && s > 0 && p > 0 && n <= (int64_t(1) << 20) && s <= (int64_t(1) << 20) &&
+         p <= 4096;
+}
+
+bool opts_ok(const tsylv_opts& o) {
+  return o.m >= 1 && o.m <= 1000 && o.max_cycles >= 0 && o.tol >= 0.0 &&
+         (o.prec == TSYLV_FP64 || o.prec == TSYLV_FP32 || o.prec == TSYLV_BF16);
+}
+
+void set_device(const tsylv_ctx* ctx) { TSYLV_HIP(hipSetDevice(ctx->c.device)); }
+
+}  // namespace
+
+extern "C" {
+
+void tsylv_default_opts(int method, tsylv_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->m = (method == TSYLV_METHOD_TBA) ? 10 : 30;
+  o->max_cycles = 500;
+  o->tol = 1e-8;
+  o->x0_given = 0;
+  o->prec = TSYLV_FP64;
+  o->refine = 0;
+  o->inner_m = 40;
+  o->inner_tol = 1e-4;
+  o->max_outer = 20;
+  o->res_hist = nullptr;
+  o->res_hist_cap = 0;
+}
+
+int tsylv_create(tsylv_ctx** out, int device, void* hip_stream, void* arena, size_t arena_bytes) {
+  if (!out || arena_bytes == 0) return TSYLV_EINVAL;
+  *out = nullptr;
+  return guarded([&]() {
+    int ndev = 0;
+    TSYLV_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return (int)TSYLV_EINVAL;
+    TSYLV_HIP(hipSetDevice(device));
+    auto* ctx = new tsylv_ctx();
+    ctx->c.device = device;
+    ctx->c.stream = static_cast<hipStream_t>(hip_stream);
+    if (arena == nullptr) {
+      void* p = nullptr;
+      hipError_t e = hipMalloc(&p, arena_bytes);
+      if (e != hipSuccess) {
+        delete ctx;
+        return (int)TSYLV_ENOMEM;
+      }
+      ctx->c.owns_arena = true;
+      arena = p;
+    }
+    ctx->c.arena_ptr = arena;
+    ctx->c.arena.init(static_cast<char*>(arena), arena_bytes);
+    void* hp = nullptr;
+    if (hipHostMalloc(&hp, kPinned * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      if (ctx->c.owns_arena) (void)hipFree(ctx->c.arena_ptr);
+      delete ctx;
+      return (int)TSYLV_ENOMEM;
+    }
+    ctx->c.pinned = static_cast<double*>(hp);
+    ctx->c.pinned_count = kPinned;
+    *out = ctx;
+    return (int)TSYLV_OK;
+  });
+}
+
+int tsylv_destroy(tsylv_ctx* ctx) {
+  if (!ctx) return TSYLV_EINVAL;
+  return guarded([&]() {
+    set_device(ctx);
+    (void)hipStreamSynchronize(ctx->c.stream);
+    if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
+    if (ctx->c.owns_arena) (void)hipFree(ctx->c.arena_ptr);
+    delete ctx;
+    return (int)TSYLV_OK;
+  });
+}
+
+size_t tsylv_workspace_bytes(int method, int64_t n, int64_t s, int64_t p, const tsylv_opts* opts) {
+  if (!dims_ok(n, s, p)) return 0;
+  tsylv_opts o;
+  tsylv_default_opts(method < 0 ? 0 : method, &o);
+  if (opts) o = *opts;
+  if (method == -1) return apply_workspace_bytes(n, s, p);
+  if (method == TSYLV_METHOD_GMRES || method == TSYLV_METHOD_FOM)
+    return krylov_workspace_bytes(n, s, p, o.m);
+  return 0;
+}
+
+int tsylv_apply(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
+                const double* X, double* Y, int prec) {
+  if (!ctx || !A || !B || !X || !Y || !dims_ok(n, s, p)) return TSYLV_EINVAL;
+  if (prec != TSYLV_FP64) return TSYLV_EINVAL;
+  return guarded([&]() {
+    std::lock_guard<std::mutex> g(ctx->c.sync_mu);
+    set_device(ctx);
+    return apply_spatial(ctx->c, n, s, p, A, B, X, Y);
+  });
+}
+
+static int krylov_entry(int method, tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p,
+                        const double* A, const double* B, const double* C, double* X,
+                        const tsylv_opts* opts, tsylv_info* info) {
+  if (!ctx || !A || !B || !C || !X || !dims_ok(n, s, p)) return TSYLV_EINVAL;
+  tsylv_opts o;
+  tsylv_default_opts(method, &o);
+  if (opts) o = *opts;
+  if (!opts_ok(o)) return TSYLV_EINVAL;
+  tsylv_info local;
+  std::memset(&local, 0, sizeof(local));
+  tsylv_info& inf = info ? *info : local;
+  std::memset(&inf, 0, sizeof(inf));
+  int st = guarded([&]() {
+    std::lock_guard<std::mutex> g(ctx->c.sync_mu);
+    set_device(ctx);
+    return krylov_solve(ctx->c, method, n, s, p, A, B, C, X, o, inf);
+  });
+  inf.status = st;
+  return st;
+}
+
+int tsylv_fom(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
+              const double* C, double* X, const tsylv_opts* opts, tsylv_info* info) {
+  return krylov_entry(TSYLV_METHOD_FOM, ctx, n, s, p, A, B, C, X, opts, info);
+}
+
+int tsylv_gmres(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A,
+                const double* B, const double* C, double* X, const tsylv_opts* opts,
+                tsylv_info* info) {
+  return krylov_entry(TSYLV_METHOD_GMRES, ctx, n, s, p, A, B, C, X, opts, info);
+}
+
+int tsylv_tba(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
+              const double* C, double* X, const tsylv_opts* opts, tsylv_info* info) {
+  (void)ctx; (void)n; (void)s; (void)p; (void)A; (void)B; (void)C; (void)X; (void)opts; (void)info;
+  return TSYLV_EINVAL;
+}
+
+int tsylv_submit(tsylv_ctx* ctx, const tsylv_request* req, uint64_t* ticket) {
+  (void)ctx; (void)req; (void)ticket;
+  return TSYLV_EINVAL;
+}
+
+int tsylv_poll(tsylv_ctx* ctx, uint64_t ticket, tsylv_info* info) {
+  (void)ctx; (void)ticket; (void)info;
+  return TSYLV_EINVAL;
+}
+
+int tsylv_profile(tsylv_ctx* ctx, int enable) {
+  if (!ctx) return TSYLV_EINVAL;
+  return guarded([&]() {
+    std::lock_guard<std::mutex> g(ctx->c.sync_mu);
+    set_device(ctx);
+    ctx->c.prof.enable(enable != 0);
+    return (int)TSYLV_OK;
+  });
+}
+
+int tsylv_profile_read(tsylv_ctx* ctx, int kernel_id, tsylv_kstat* out) {
+  if (!ctx || !out || kernel_id < 0 || kernel_id >= TSYLV_K_COUNT) return TSYLV_EINVAL;
+  return guarded([&]() {
+    std::lock_guard<std::mutex> g(ctx->c.sync_mu);
+    set_device(ctx);
+    ctx->c.prof.read(kernel_id, out->launches, out->total_ms);
+    return (int)TSYLV_OK;
+  });
+}
+
+const char* tsylv_strerror(int status) {
+  switch (status) {
+    case TSYLV_OK: return "ok";
+    case TSYLV_NOT_CONVERGED: return "not converged (X holds the last iterate)";
+    case TSYLV_PENDING: return "pending";
+    case TSYLV_EINVAL: return "invalid argument";
+    case TSYLV_ENOMEM: return "arena too small";
+    case TSYLV_EBREAKDOWN: return "breakdown: non-invertible tube in Normalization";
+    case TSYLV_ESINGULAR: return "singular projected problem";
+    case TSYLV_EHIP: return "HIP runtime error";
+    case TSYLV_ECANCELLED: return "cancelled";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+// Host-side launchers of the HIP kernels (all enqueue on `st`, never sync).
+#pragma once
+
+#include "common.hpp"
+
+namespace tsylv {
+namespace kern {
+
+// ---- tube transforms (mode-3 DFT as a p x p real matrix on every tube) ----
+
+// M[q*p + j]: the p x p matrix of XformKind `kind` (built on the device from
+// (j*k) mod p so the multiples of pi/2 are exact).
+void build_xform(double* M, int p, int kind, hipStream_t st);
+
+// out[q*E + e] = scale * sum_j M[q*p + j] * in[j*E + e]  for 0 <= e < E.
+void tube_xform_f64(const double* in, double* out, const double* M, int64_t E,
+                    int p, hipStream_t st);
+
+// Down-conversion of `count` doubles (round to nearest even).
+void convert_f64_f32(const double* in, float* out, int64_t count, hipStream_t st);
+void convert_f64_bf16(const double* in, uint16_t* out, int64_t count, hipStream_t st);
+void convert_f32_f64(const float* in, double* out, int64_t count, hipStream_t st);
+
+// ---- facewise operator apply (Fourier planes) ----
+//   out_k = alpha * (Ahat_k V_k - V_k Bhat_k) + beta * Y_k   for every slice k
+// (the V_k Bhat_k term is skipped when Bh == nullptr; Y may be nullptr when
+// beta == 0).  Ah: p planes n x n; Bh: p planes s x s; V, Y, out: p planes n x s.
+void apply_f64(const double* Ah, const double* Bh, const double* V, double* out,
+               const double* Y, double alpha, double beta, int64_t n, int64_t s,
+               int p, hipStream_t st);
+
+// ---- multi-vector kernels on flat vectors of N reals ----
+
+// Number of per-block partial rows used by mdot for length N.
+int mdot_chunks(int64_t N);
+
+// part[c*ldp + i] = sum_{e in chunk c} V_i[e] * w[e]  (i < nv, V_i = V + i*ldv)
+// and, if with_ww, part[c*ldp + nv] = sum w[e]^2.  ldp >= nv + with_ww.
+void mdot_partial(const double* V, int64_t ldv, int nv, const double* w,
+                  int64_t N, double* part, int ldp, int with_ww, hipStream_t st);
+
+// out[i] = sum_c part[c*ldp + i] for i < ncols, in a fixed order.
+void reduce_partials(const double* part, int nchunks, int ldp, int ncols,
+                     double* out, hipStream_t st);
+
+// w[e] -= sum_i h[i] * V_i[e]   (h on the device, nv entries)
+void mupdate(const double* V, int64_t ldv, int nv, const double* h, double* w,
+             int64_t N, hipStream_t st);
+
+// out[e] = w[e] / sqrt(*ww)
+void scale_by_rnorm(const double* w, double* out, const double* ww, int64_t N,
+                    hipStream_t st);
+
+// out[e] = a * x[e]
+void scale(const double* x, double* out, double a, int64_t N, hipStream_t st);
+
+}  // namespace kern
+}  // namespace tsylv

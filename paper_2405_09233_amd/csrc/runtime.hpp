@@ -1,0 +1,113 @@
+// Context, HBM arena and pinned host staging.
+#pragma once
+
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+
+namespace tsylv {
+
+// First-fit allocator over the caller's device buffer.  Every workspace of
+// the library comes from here: the arena size is the HBM budget.  Offsets
+// are 256-byte aligned.  Thread-safe.
+class Arena {
+ public:
+  Arena() = default;
+  void init(char* base, size_t bytes);
+  // Returns nullptr when no free block is large enough.
+  void* alloc(size_t bytes);
+  void free(void* ptr);
+  size_t capacity() const { return size_; }
+  size_t in_use() const;
+  size_t largest_free() const;
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0;
+  std::map<size_t, size_t> free_;  // offset -> size
+  std::map<size_t, size_t> used_;  // offset -> size
+  mutable std::mutex mu_;
+};
+
+// Bump allocator on top of one arena block: the workspace of one solve.
+class Workspace {
+ public:
+  Workspace(Arena& arena, size_t bytes);
+  ~Workspace();
+  Workspace(const Workspace&) = delete;
+  Workspace& operator=(const Workspace&) = delete;
+  template <typename T>
+  T* take(int64_t count) {
+    size_t b = (size_t)round_up((int64_t)(count * sizeof(T)), 256);
+    if (used_ + b > bytes_) throw Error(TSYLV_ENOMEM, "workspace plan exceeded");
+    T* p = reinterpret_cast<T*>(base_ + used_);
+    used_ += b;
+    return p;
+  }
+  static size_t bytes_for(int64_t count, size_t elem) {
+    return (size_t)round_up((int64_t)(count * elem), 256);
+  }
+
+ private:
+  Arena& arena_;
+  char* base_ = nullptr;
+  size_t bytes_ = 0;
+  size_t used_ = 0;
+};
+
+struct Scheduler;  // serving loop (serve.cpp)
+
+// HIP-event timing of kernel families (tsylv_profile).
+class Profiler {
+ public:
+  ~Profiler();
+  void enable(bool on);
+  bool on() const { return on_; }
+  void begin(int kid, hipStream_t st);
+  void end(int kid, hipStream_t st);
+  void read(int kid, int64_t& launches, double& ms);
+
+ private:
+  void fold();  // sync on the recorded events and accumulate
+  bool on_ = false;
+  std::vector<hipEvent_t> pool_;
+  size_t next_ = 0;
+  struct Pending { int kid; hipEvent_t a, b; };
+  std::vector<Pending> pending_;
+  hipEvent_t cur_start_[TSYLV_K_COUNT] = {};
+  int64_t launches_[TSYLV_K_COUNT] = {};
+  double ms_[TSYLV_K_COUNT] = {};
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool owns_arena = false;
+  void* arena_ptr = nullptr;
+  Arena arena;
+  // pinned host staging for small device->host results
+  double* pinned = nullptr;
+  size_t pinned_count = 0;
+  Scheduler* sched = nullptr;
+  std::mutex sync_mu;  // serialises synchronous calls on the context
+  Profiler prof;
+
+  double* host_buffer(size_t count);  // grows the pinned buffer as needed
+  void sync() { TSYLV_HIP(hipStreamSynchronize(stream)); }
+};
+
+// Brackets one kernel launch with profiling events when profiling is on.
+struct ProfScope {
+  Ctx& c;
+  int kid;
+  ProfScope(Ctx& ctx, int k) : c(ctx), kid(k) {
+    if (c.prof.on()) c.prof.begin(kid, c.stream);
+  }
+  ~ProfScope() {
+    if (c.prof.on()) c.prof.end(kid, c.stream);
+  }
+};
+
+}  // namespace tsylv

@@ -1,0 +1,259 @@
+"""ctypes binding of libtsylv.so (the C ABI declared in include/tsylv.h).
+
+Argument marshalling only: every step of every solve runs in the library's
+HIP kernels.  torch supplies device memory (the arena and the tensors) and
+the stream.  Loading fails loudly when the library has not been built.
+
+Tensors passed in are float64 CUDA(HIP) tensors of shape (rows, cols, p)
+whose memory is frontal-slice major and column-major inside a slice, i.e.
+``T.permute(2, 1, 0).is_contiguous()``; :func:`to_device` makes one from a
+Fortran-ordered numpy array and :func:`to_host` brings it back.
+"""
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtsylv.so")
+
+FP64, FP32, BF16 = 0, 1, 2
+GMRES, FOM, TBA = 0, 1, 2
+APPLY = -1
+
+STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "EINVAL", -2: "ENOMEM",
+          -3: "EBREAKDOWN", -4: "ESINGULAR", -5: "EHIP", -6: "ECANCELLED"}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("max_cycles", ctypes.c_int), ("tol", ctypes.c_double),
+                ("x0_given", ctypes.c_int), ("prec", ctypes.c_int), ("refine", ctypes.c_int),
+                ("inner_m", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int), ("res_hist", ctypes.POINTER(ctypes.c_double)),
+                ("res_hist_cap", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("steps", ctypes.c_int), ("cycles", ctypes.c_int),
+                ("outer", ctypes.c_int), ("relres_true", ctypes.c_double),
+                ("relres_est", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("res_hist_len", ctypes.c_int), ("fom_fallback", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class KStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+K_APPLY, K_ORTHO, K_XFORM = 0, 1, 2
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("n", ctypes.c_int64), ("s", ctypes.c_int64),
+                ("p", ctypes.c_int64), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("C", ctypes.c_void_p), ("X", ctypes.c_void_p), ("opts", Opts)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+_SIGS = {
+    "tsylv_default_opts": (None, [ctypes.c_int, ctypes.POINTER(Opts)]),
+    "tsylv_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "tsylv_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "tsylv_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                                ctypes.c_int64, ctypes.POINTER(Opts)]),
+    "tsylv_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "tsylv_fom": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Opts),
+                                 ctypes.POINTER(Info)]),
+    "tsylv_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request),
+                                    ctypes.POINTER(ctypes.c_uint64)]),
+    "tsylv_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Info)]),
+    "tsylv_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "tsylv_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "tsylv_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+}
+_SIGS["tsylv_gmres"] = _SIGS["tsylv_fom"]
+_SIGS["tsylv_tba"] = _SIGS["tsylv_fom"]
+
+EXPORTED = sorted(_SIGS)
+
+
+def load(path=None):
+    """Load libtsylv.so (once).  Raises OSError if it is missing."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            p = path or LIB_PATH
+            if not os.path.exists(p):
+                raise OSError("libtsylv.so not built (%s): run python -m "
+                              "paper_2405_09233_amd.build" % p)
+            lib = ctypes.CDLL(p)
+            for name, (res, args) in _SIGS.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+class TsylvError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = load().tsylv_strerror(status).decode()
+        super().__init__("%s: %s (%d)" % (where, msg, status))
+
+
+def default_opts(method=GMRES, **kw):
+    o = Opts()
+    load().tsylv_default_opts(method, ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def workspace_bytes(method, n, s, p, opts=None):
+    return load().tsylv_workspace_bytes(method, n, s, p, ctypes.byref(opts) if opts else None)
+
+
+# ------------------------------------------------------------ torch helpers
+
+def to_device(arr, device="cuda"):
+    """Fortran-ordered float64 (rows, cols, p) numpy array -> device tensor
+    with the library layout."""
+    import torch
+    a = np.asarray(arr, dtype=np.float64)
+    t = torch.from_numpy(np.ascontiguousarray(np.transpose(a, (2, 1, 0))))
+    return t.to(device).permute(2, 1, 0)
+
+
+def empty_device(shape, device="cuda"):
+    import torch
+    r, c, p = shape
+    return torch.empty((p, c, r), dtype=torch.float64, device=device).permute(2, 1, 0)
+
+
+def to_host(t):
+    return np.asfortranarray(np.transpose(t.permute(2, 1, 0).cpu().numpy(), (2, 1, 0)))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.permute(2, 1, 0).is_contiguous() or str(t.dtype) != "torch.float64":
+        raise ValueError("tensor must be float64 with slice-major column-major layout")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context bound to one device, one stream and one arena."""
+
+    def __init__(self, arena_bytes, device=0, stream=None, own_arena=False):
+        import torch
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.arena = None
+        aptr = None
+        if not own_arena:
+            self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8,
+                                     device="cuda:%d" % device)
+            aptr = ctypes.c_void_p(self.arena.data_ptr())
+        h = ctypes.c_void_p()
+        st = load().tsylv_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream),
+                                 aptr, ctypes.c_size_t(int(arena_bytes)))
+        if st != 0:
+            raise TsylvError(st, "tsylv_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().tsylv_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- calls -------------------------------------------------------------
+    def apply(self, A, B, X, Y=None, prec=FP64):
+        n, _, p = A.shape
+        s = B.shape[0]
+        if Y is None:
+            Y = empty_device((n, s, p), A.device)
+        st = load().tsylv_apply(self.handle, n, s, p, _ptr(A), _ptr(B), _ptr(X), _ptr(Y), prec)
+        if st != 0:
+            raise TsylvError(st, "tsylv_apply")
+        return Y
+
+    def _solve(self, fname, A, B, C, X=None, opts=None, raise_on_error=True, **kw):
+        n, _, p = A.shape
+        s = B.shape[0]
+        method = {"tsylv_gmres": GMRES, "tsylv_fom": FOM, "tsylv_tba": TBA}[fname]
+        o = opts if opts is not None else default_opts(method, **kw)
+        if X is None:
+            X = empty_device((n, s, p), A.device)
+        info = Info()
+        st = getattr(load(), fname)(self.handle, n, s, p, _ptr(A), _ptr(B), _ptr(C), _ptr(X),
+                                    ctypes.byref(o), ctypes.byref(info))
+        if st < 0 and raise_on_error:
+            raise TsylvError(st, fname)
+        return X, info
+
+    def gmres(self, A, B, C, X=None, opts=None, **kw):
+        return self._solve("tsylv_gmres", A, B, C, X, opts, **kw)
+
+    def fom(self, A, B, C, X=None, opts=None, **kw):
+        return self._solve("tsylv_fom", A, B, C, X, opts, **kw)
+
+    def tba(self, A, B, C, X=None, opts=None, **kw):
+        return self._solve("tsylv_tba", A, B, C, X, opts, **kw)
+
+    def submit(self, A, B, C, X, method=GMRES, opts=None, **kw):
+        n, _, p = A.shape
+        s = B.shape[0]
+        req = Request()
+        req.method = method
+        req.n, req.s, req.p = n, s, p
+        req.A, req.B, req.C, req.X = (t.data_ptr() for t in (A, B, C, X))
+        req.opts = opts if opts is not None else default_opts(method, **kw)
+        ticket = ctypes.c_uint64()
+        st = load().tsylv_submit(self.handle, ctypes.byref(req), ctypes.byref(ticket))
+        if st != 0:
+            raise TsylvError(st, "tsylv_submit")
+        return ticket.value
+
+    def profile(self, enable=True):
+        st = load().tsylv_profile(self.handle, 1 if enable else 0)
+        if st != 0:
+            raise TsylvError(st, "tsylv_profile")
+
+    def profile_read(self, kernel_id):
+        k = KStat()
+        st = load().tsylv_profile_read(self.handle, kernel_id, ctypes.byref(k))
+        if st != 0:
+            raise TsylvError(st, "tsylv_profile_read")
+        return k.launches, k.total_ms
+
+    def poll(self, ticket):
+        info = Info()
+        st = load().tsylv_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(info))
+        return st, info

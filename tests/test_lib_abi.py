@@ -1,0 +1,91 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/tsylv.h declares, and the ctypes structures of the binding have the
+sizes and field offsets the C compiler gives the header's structs.  No
+compute call is made (there is no GPU here)."""
+
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2405_09233_amd import tsylv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsylv.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsylv_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_header_functions():
+    lib = tsylv.load()
+    names = header_functions()
+    assert "tsylv_gmres" in names and "tsylv_poll" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert names == tsylv.EXPORTED
+
+
+def test_struct_layout_matches_header(tmp_path):
+    c = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "tsylv.h"
+#define F(T, f) printf("%s.%s %zu\n", #T, #f, offsetof(T, f));
+int main(void) {
+  printf("tsylv_opts %zu\n", sizeof(tsylv_opts));
+  printf("tsylv_info %zu\n", sizeof(tsylv_info));
+  printf("tsylv_request %zu\n", sizeof(tsylv_request));
+  F(tsylv_opts, tol) F(tsylv_opts, inner_tol) F(tsylv_opts, res_hist) F(tsylv_opts, res_hist_cap)
+  F(tsylv_info, relres_true) F(tsylv_info, seconds) F(tsylv_info, fom_fallback)
+  F(tsylv_request, n) F(tsylv_request, A) F(tsylv_request, X) F(tsylv_request, opts)
+  return 0;
+}
+'''
+    cf = tmp_path / "layout.c"
+    cf.write_text(c)
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(cf), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+    got = {k: int(v) for k, v in got.items()}
+    assert got["tsylv_opts"] == ctypes.sizeof(tsylv.Opts)
+    assert got["tsylv_info"] == ctypes.sizeof(tsylv.Info)
+    assert got["tsylv_request"] == ctypes.sizeof(tsylv.Request)
+    for key, val in got.items():
+        if "." in key:
+            sname, field = key.split(".")
+            cls = {"tsylv_opts": tsylv.Opts, "tsylv_info": tsylv.Info,
+                   "tsylv_request": tsylv.Request}[sname]
+            assert getattr(cls, field).offset == val, key
+
+
+def test_default_opts_and_workspace_query():
+    o = tsylv.default_opts(tsylv.GMRES)
+    assert (o.m, o.max_cycles, o.tol, o.prec) == (30, 500, 1e-8, tsylv.FP64)
+    assert tsylv.default_opts(tsylv.TBA).m == 10
+    n, s, p = 4096, 64, 32
+    b = tsylv.workspace_bytes(tsylv.GMRES, n, s, p, o)
+    assert b >= 8 * (p * n * n + (o.m + 3) * n * s * p)
+    assert tsylv.workspace_bytes(tsylv.GMRES, 0, s, p, o) == 0
+    assert tsylv.workspace_bytes(tsylv.APPLY, 8, 6, 4, None) > 0
+
+
+def test_strerror():
+    lib = tsylv.load()
+    assert lib.tsylv_strerror(0) == b"ok"
+    assert b"invalid" in lib.tsylv_strerror(-1)
+
+
+def test_invalid_arguments_rejected_without_gpu():
+    lib = tsylv.load()
+    assert lib.tsylv_destroy(None) == -1
+    assert lib.tsylv_gmres(None, 4, 2, 2, None, None, None, None, None, None) == -1
+    h = ctypes.c_void_p()
+    assert lib.tsylv_create(ctypes.byref(h), 0, None, None, 0) == -1

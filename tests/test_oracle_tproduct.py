@@ -132,3 +132,13 @@ def test_golden_hand_computed():
             np.testing.assert_allclose(tp.ttrans(A), expect, atol=0)
         else:
             raise AssertionError(c["kind"])
+
+
+def test_sylv_op_entries_match_full():
+    A = rand((6, 6, 5), 20)
+    B = rand((3, 3, 5), 21)
+    X = rand((6, 3, 5), 22)
+    full = tp.tprod(A, X) - tp.tprod(X, B)
+    idx = [(i, c, k) for i in range(6) for c in range(3) for k in range(5)]
+    np.testing.assert_allclose(tp.sylv_op_entries(A, B, X, idx),
+                               [full[i, c, k] for i, c, k in idx], atol=1e-13)
