@@ -68,11 +68,18 @@ def tprod(A, B):
     dt = np.result_type(A.dtype, B.dtype)
     out = np.zeros((n1, m, p), dtype=dt)
     for k in range(p):
-        acc = np.zeros((n1, m), dtype=dt)
-        for j in range(p):
-            acc += A[:, :, (k - j) % p] @ B[:, :, j]
-        out[:, :, k] = acc
+        out[:, :, k] = tprod_slice(A, B, k)
     return out
+
+
+def tprod_slice(A, B, k):
+    """Frontal slice k of A * B: sum_j A[:, :, (k - j) mod p] @ B[:, :, j]
+    (block row k of bcirc(A) times unfold(B))."""
+    p = A.shape[2]
+    acc = np.zeros((A.shape[0], B.shape[1]), dtype=np.result_type(A.dtype, B.dtype))
+    for j in range(p):
+        acc += A[:, :, (k - j) % p] @ B[:, :, j]
+    return acc
 
 
 def ttrans(A):
