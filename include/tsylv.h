@@ -88,7 +88,12 @@ typedef struct {
 
 /* Defaults: m = 30 (tGMRES/tFOM) or 10 (TBA), max_cycles = 500,
  * tol = 1e-8, X0 = 0, FP64, no refinement, inner_m = 40, inner_tol = 1e-4,
- * max_outer = 20. */
+ * max_outer = 500.
+ * Precision rules: without refinement prec must be TSYLV_FP64; with
+ * refine = 1, prec is TSYLV_FP32 or TSYLV_BF16 and each refinement step is
+ * one tGMRES/tFOM(inner_m) cycle in that precision, stopped early when its
+ * residual estimate falls below inner_tol times the current FP64 residual;
+ * X, the residual and the stopping test stay FP64. */
 void tsylv_default_opts(int method, tsylv_opts* opts);
 
 /* Create a context on HIP device `device`, issuing all work on `hip_stream`
@@ -111,7 +116,9 @@ size_t tsylv_workspace_bytes(int method, int64_t n, int64_t s, int64_t p,
 
 /* Y = A*X - X*B  (eq. (2)), computed as Algorithm 1 of section 2.1 does:
  * mode-3 DFT, facewise products on the conjugate-symmetric half of the
- * Fourier slices, inverse DFT.  Synchronous on the context stream. */
+ * Fourier slices, inverse DFT.  The transforms are FP64; `prec` selects the
+ * precision of the slice products (FP64, FP32, or BF16 inputs with FP32
+ * accumulation).  Synchronous on the context stream. */
 int tsylv_apply(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p,
                 const double* A, const double* B, const double* X, double* Y,
                 int prec);

@@ -34,8 +34,14 @@ bool dims_ok(int64_t n, int64_t s, int64_t p) {
 }
 
 bool opts_ok(const tsylv_opts& o) {
-  return o.m >= 1 && o.m <= 1000 && o.max_cycles >= 0 && o.tol >= 0.0 &&
-         (o.prec == TSYLV_FP64 || o.prec == TSYLV_FP32 || o.prec == TSYLV_BF16);
+  bool ok = o.m >= 1 && o.m <= 1000 && o.max_cycles >= 0 && o.tol >= 0.0 &&
+            (o.prec == TSYLV_FP64 || o.prec == TSYLV_FP32 || o.prec == TSYLV_BF16);
+  if (o.refine)
+    ok = ok && o.prec != TSYLV_FP64 && o.inner_m >= 1 && o.inner_m <= 1000 && o.max_outer >= 0 &&
+         o.inner_tol > 0.0 && o.inner_tol < 1.0;
+  else
+    ok = ok && o.prec == TSYLV_FP64;
+  return ok;
 }
 
 void set_device(const tsylv_ctx* ctx) { TSYLV_HIP(hipSetDevice(ctx->c.device)); }
@@ -55,7 +61,7 @@ void tsylv_default_opts(int method, tsylv_opts* o) {
   o->refine = 0;
   o->inner_m = 40;
   o->inner_tol = 1e-4;
-  o->max_outer = 20;
+  o->max_outer = 500;
   o->res_hist = nullptr;
   o->res_hist_cap = 0;
 }
@@ -115,18 +121,18 @@ size_t tsylv_workspace_bytes(int method, int64_t n, int64_t s, int64_t p, const 
   if (opts) o = *opts;
   if (method == -1) return apply_workspace_bytes(n, s, p);
   if (method == TSYLV_METHOD_GMRES || method == TSYLV_METHOD_FOM)
-    return krylov_workspace_bytes(n, s, p, o.m);
+    return krylov_workspace_bytes(n, s, p, o);
   return 0;
 }
 
 int tsylv_apply(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
                 const double* X, double* Y, int prec) {
   if (!ctx || !A || !B || !X || !Y || !dims_ok(n, s, p)) return TSYLV_EINVAL;
-  if (prec != TSYLV_FP64) return TSYLV_EINVAL;
+  if (prec != TSYLV_FP64 && prec != TSYLV_FP32 && prec != TSYLV_BF16) return TSYLV_EINVAL;
   return guarded([&]() {
     std::lock_guard<std::mutex> g(ctx->c.sync_mu);
     set_device(ctx);
-    return apply_spatial(ctx->c, n, s, p, A, B, X, Y);
+    return apply_spatial(ctx->c, n, s, p, A, B, X, Y, prec);
   });
 }
 

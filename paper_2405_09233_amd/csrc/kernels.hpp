@@ -28,6 +28,13 @@ void convert_f32_f64(const float* in, double* out, int64_t count, hipStream_t st
 void apply_f64(const double* Ah, const double* Bh, const double* V, double* out,
                const double* Y, double alpha, double beta, int64_t n, int64_t s,
                int p, hipStream_t st);
+// Same in FP32 (FP32 MFMA) and with BF16 operator planes (BF16 MFMA, the
+// vectors rounded to BF16 on the way into the product, FP32 accumulation).
+void apply_f32(const float* Ah, const float* Bh, const float* V, float* out, const float* Y,
+               double alpha, double beta, int64_t n, int64_t s, int p, hipStream_t st);
+void apply_bf16(const uint16_t* Ah, const uint16_t* Bh, const float* V, float* out,
+                const float* Y, double alpha, double beta, int64_t n, int64_t s, int p,
+                hipStream_t st);
 
 // ---- multi-vector kernels on flat vectors of N reals ----
 
@@ -36,23 +43,28 @@ int mdot_chunks(int64_t N);
 
 // part[c*ldp + i] = sum_{e in chunk c} V_i[e] * w[e]  (i < nv, V_i = V + i*ldv)
 // and, if with_ww, part[c*ldp + nv] = sum w[e]^2.  ldp >= nv + with_ww.
-void mdot_partial(const double* V, int64_t ldv, int nv, const double* w,
-                  int64_t N, double* part, int ldp, int with_ww, hipStream_t st);
+// FP32 vectors are summed in FP64.
+void mdot_partial(const double* V, int64_t ldv, int nv, const double* w, int64_t N,
+                  double* part, int ldp, int with_ww, hipStream_t st);
+void mdot_partial(const float* V, int64_t ldv, int nv, const float* w, int64_t N,
+                  double* part, int ldp, int with_ww, hipStream_t st);
 
 // out[i] = sum_c part[c*ldp + i] for i < ncols, in a fixed order.
 void reduce_partials(const double* part, int nchunks, int ldp, int ncols,
                      double* out, hipStream_t st);
 
-// w[e] -= sum_i h[i] * V_i[e]   (h on the device, nv entries)
+// w[e] -= sum_i h[i] * V_i[e]   (h on the device, nv entries; FP64 arithmetic)
 void mupdate(const double* V, int64_t ldv, int nv, const double* h, double* w,
              int64_t N, hipStream_t st);
+void mupdate(const float* V, int64_t ldv, int nv, const double* h, float* w,
+             int64_t N, hipStream_t st);
+void mupdate(const float* V, int64_t ldv, int nv, const double* h, double* w,
+             int64_t N, hipStream_t st);
 
-// out[e] = w[e] / sqrt(*ww)
-void scale_by_rnorm(const double* w, double* out, const double* ww, int64_t N,
-                    hipStream_t st);
-
-// out[e] = a * x[e]
+// out[e] = a * x[e]  (the FP64 -> FP32 form rounds the scaled value)
 void scale(const double* x, double* out, double a, int64_t N, hipStream_t st);
+void scale(const float* x, float* out, double a, int64_t N, hipStream_t st);
+void scale(const double* x, float* out, double a, int64_t N, hipStream_t st);
 
 }  // namespace kern
 }  // namespace tsylv

@@ -1,4 +1,5 @@
-// Facewise Sylvester apply in the Fourier half spectrum, FP64 on MFMA.
+// Facewise Sylvester apply in the Fourier half spectrum on MFMA
+// (FP64, FP32, and BF16 inputs with FP32 accumulation).
 //
 // Algorithm 1 of section 2.1 computes a T-product as independent products
 // of the Fourier slices; for M(X) = A*X - X*B (eq. (2)) that is
@@ -8,17 +9,17 @@
 // K = n + s:
 //     W_k = [ Ahat_k | -V_k ] [ V_k ; Bhat_k ],
 // so the whole apply is a batched complex GEMM with the small V_k Bhat_k
-// term riding in the last K panel.  Complex products are four real
-// v_mfma_f64_16x16x4 per 16 x 16 x 4 block (Re += Ar Vr - Ai Vi,
-// Im += Ar Vi + Ai Vr).
+// term riding in the last K panels.  A complex product is four real MFMAs
+// per block (Re += Ar Vr - Ai Vi, Im += Ar Vi + Ai Vr).  The Tubal Block
+// Arnoldi process needs Ahat_k V_k alone (useB = 0, K = n).
 //
 // Tiling: a workgroup (4 waves) owns a TM x TN tile of W_k and streams the
-// TM rows of [Ahat_k | -V_k] once through LDS in TK-deep panels, the matching
-// panels of [V_k ; Bhat_k] come from L2.  The next panel is loaded into
-// registers while the current one is multiplied.  Tiles are numbered slice
-// major and handed out so that each XCD (workgroups go round-robin over the
-// 8 XCDs) works through a contiguous range: the V_k of a slice stays in one
-// XCD's L2 instead of being fetched by all eight.
+// TM rows of [Ahat_k | -V_k] once through LDS in TK-deep panels; the
+// matching panels of [V_k ; Bhat_k] come from L2.  The next panel is loaded
+// into registers while the current one is multiplied.  Tiles are numbered
+// slice major and handed out so that each XCD (workgroups go round-robin over
+// the 8 XCDs) works through a contiguous range: the V_k of a slice stays in
+// one XCD's L2 instead of being fetched by all eight.
 #include "kernels.hpp"
 
 namespace tsylv {
@@ -27,23 +28,118 @@ namespace kern {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int NT = 256;
-constexpr int TK = 16;
 
-__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
 }
 
+// Per-precision MFMA traits.  TA: storage type of the operator planes, TV:
+// of the vectors, L: LDS element type, frag: one lane's MFMA operand.
+//   FP64: v_mfma_f64_16x16x4; A element (i, k) in lane i + 16 k; result
+//         (i, j) in lane j + 16 (i % 4), register i / 4.
+//   FP32: v_mfma_f32_16x16x4; same operand layout; result (i, j) in lane
+//         j + 16 (i / 4), register i % 4.
+//   BF16: v_mfma_f32_16x16x32_bf16; lane i + 16 q holds A(i, 8q .. 8q+7)
+//         (B likewise with columns); FP32 accumulation, FP32 result layout.
+struct Bf16 {};
+
+template <typename TA>
+struct Mma;
+
+template <>
+struct Mma<double> {
+  using TV = double;
+  using L = double;
+  using frag = double;
+  using acc_t = d4;
+  static constexpr int TK = 16, KB = 4;
+  __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static int row(int r, int lk) { return 4 * r + lk; }
+  __device__ static L a_in(double x) { return x; }
+  __device__ static L v_in(double x) { return x; }
+  __device__ static L neg(L x) { return -x; }
+  template <int LD>
+  __device__ static frag ld(const L (*S)[LD], int ks, int lk, int i) { return S[ks + lk][i]; }
+  __device__ static frag negf(frag x) { return -x; }
+  __device__ static acc_t mma(frag a, frag b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mma<float> {
+  using TV = float;
+  using L = float;
+  using frag = float;
+  using acc_t = f4;
+  static constexpr int TK = 16, KB = 4;
+  __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static int row(int r, int lk) { return 4 * lk + r; }
+  __device__ static L a_in(float x) { return x; }
+  __device__ static L v_in(float x) { return x; }
+  __device__ static L neg(L x) { return -x; }
+  template <int LD>
+  __device__ static frag ld(const L (*S)[LD], int ks, int lk, int i) { return S[ks + lk][i]; }
+  __device__ static frag negf(frag x) { return -x; }
+  __device__ static acc_t mma(frag a, frag b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mma<Bf16> {
+  using TV = float;
+  using L = uint16_t;
+  using frag = bf8;
+  using acc_t = f4;
+  static constexpr int TK = 32, KB = 32;
+  __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static int row(int r, int lk) { return 4 * lk + r; }
+  __device__ static L a_in(uint16_t x) { return x; }
+  __device__ static L v_in(float x) { return f32_to_bf16_bits(x); }
+  __device__ static L neg(L x) { return (uint16_t)(x ^ 0x8000u); }
+  template <int LD>
+  __device__ static frag ld(const L (*S)[LD], int ks, int lk, int i) {
+    frag f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] = __builtin_bit_cast(__bf16, S[ks + 8 * lk + e][i]);
+    return f;
+  }
+  __device__ static frag negf(frag x) {
+    u16x8 u = __builtin_bit_cast(u16x8, x);
+    u ^= (unsigned short)0x8000u;
+    return __builtin_bit_cast(frag, u);
+  }
+  __device__ static acc_t mma(frag a, frag b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// storage type of the operator planes for a traits tag
+template <typename Tag> struct Store { using T = Tag; };
+template <> struct Store<Bf16> { using T = uint16_t; };
+
+template <typename Tag>
 struct ApplyArgs {
-  const double* Ah;
-  const double* Bh;
-  const double* V;
-  double* out;
-  const double* Y;
+  using TA = typename Store<Tag>::T;
+  using TV = typename Mma<Tag>::TV;
+  const TA* Ah;
+  const TA* Bh;
+  const TV* V;
+  TV* out;
+  const TV* Y;
   double alpha, beta;
   int64_t n, s;
   int p;
+  int useB;      // include the -V_k Bhat_k term
   int nrt, nct;  // row tiles, column tiles per slice
   int total;     // tiles over all slices
 };
@@ -56,9 +152,17 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
   return x * q + (x < r ? x : r) + b / 8;
 }
 
-template <int TM, int TN, int RB, int CB, bool CPLX>
-__device__ __forceinline__ void apply_tile(const ApplyArgs& a, int k, int rt, int ct,
-                                           double (*As)[TK][TM], double (*Bs)[TK][TN + 1]) {
+template <typename Tag, int TM, int TN, int RB, int CB, bool CPLX>
+__device__ __forceinline__ void apply_tile(const ApplyArgs<Tag>& a, int k, int rt, int ct,
+                                           typename Mma<Tag>::L (*As)[Mma<Tag>::TK][TM],
+                                           typename Mma<Tag>::L (*Bs)[Mma<Tag>::TK][TN + 1]) {
+  using M = Mma<Tag>;
+  using L = typename M::L;
+  using TA = typename Store<Tag>::T;
+  using TV = typename M::TV;
+  using frag = typename M::frag;
+  using acc_t = typename M::acc_t;
+  constexpr int TK = M::TK, KB = M::KB;
   constexpr int WR = TM / (16 * RB);  // waves along rows
   constexpr int WC = TN / (16 * CB);  // waves along columns
   static_assert(WR * WC == NT / 64, "4 waves per workgroup");
@@ -66,16 +170,16 @@ __device__ __forceinline__ void apply_tile(const ApplyArgs& a, int k, int rt, in
   constexpr int NB = TK * TN / NT;    // B-panel elements per thread and plane
   static_assert(NA * NT == TM * TK && NB * NT == TK * TN, "panel split");
 
-  const int64_t n = a.n, s = a.s, K = n + s;
+  const int64_t n = a.n, s = a.s, K = a.useB ? n + s : n;
   int qr, qi;
   slice_planes(a.p, k, qr, qi);
   const int64_t nn = n * n, ns = n * s, ss = s * s;
-  const double* Ar = a.Ah + qr * nn;
-  const double* Ai = CPLX ? a.Ah + qi * nn : nullptr;
-  const double* Vr = a.V + qr * ns;
-  const double* Vi = CPLX ? a.V + qi * ns : nullptr;
-  const double* Br = a.Bh + qr * ss;
-  const double* Bi = CPLX ? a.Bh + qi * ss : nullptr;
+  const TA* Ar = a.Ah + qr * nn;
+  const TA* Ai = CPLX ? a.Ah + qi * nn : nullptr;
+  const TV* Vr = a.V + qr * ns;
+  const TV* Vi = CPLX ? a.V + qi * ns : nullptr;
+  const TA* Br = a.Bh + qr * ss;
+  const TA* Bi = CPLX ? a.Bh + qi * ss : nullptr;
   const int64_t m0 = (int64_t)rt * TM, c0 = (int64_t)ct * TN;
 
   const int tid = threadIdx.x;
@@ -83,16 +187,17 @@ __device__ __forceinline__ void apply_tile(const ApplyArgs& a, int k, int rt, in
   const int wr = wave % WR, wc = wave / WR;
   const int lr = lane & 15, lk = lane >> 4;
 
-  d4 accr[RB][CB], acci[RB][CB];
+  acc_t accr[RB][CB], acci[RB][CB];
 #pragma unroll
   for (int i = 0; i < RB; ++i)
 #pragma unroll
     for (int j = 0; j < CB; ++j) {
-      accr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      acci[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accr[i][j] = M::zero();
+      acci[i][j] = M::zero();
     }
 
-  double pa_r[NA], pa_i[NA], pb_r[NB], pb_i[NB];
+  L pa_r[NA], pa_i[NA], pb_r[NB], pb_i[NB];
+  const L zl = M::v_in((TV)0);
 
   // Element (row, kk) of the [Ahat | -V] panel and (kk, col) of [V ; Bhat].
   auto load_panels = [&](int64_t k0) {
@@ -101,16 +206,16 @@ __device__ __forceinline__ void apply_tile(const ApplyArgs& a, int k, int rt, in
       const int idx = tid + NT * u;
       const int row = idx % TM, kk = idx / TM;
       const int64_t gr = m0 + row, gk = k0 + kk;
-      double vr = 0.0, vi = 0.0;
+      L vr = zl, vi = zl;
       if (gr < n) {
         if (gk < n) {
           const int64_t off = gr + n * gk;
-          vr = Ar[off];
-          if (CPLX) vi = Ai[off];
+          vr = M::a_in(Ar[off]);
+          if (CPLX) vi = M::a_in(Ai[off]);
         } else if (gk < K) {
           const int64_t off = gr + n * (gk - n);
-          vr = -Vr[off];
-          if (CPLX) vi = -Vi[off];
+          vr = M::neg(M::v_in(Vr[off]));
+          if (CPLX) vi = M::neg(M::v_in(Vi[off]));
         }
       }
       pa_r[u] = vr;
@@ -121,16 +226,16 @@ __device__ __forceinline__ void apply_tile(const ApplyArgs& a, int k, int rt, in
       const int idx = tid + NT * u;
       const int kk = idx % TK, col = idx / TK;
       const int64_t gk = k0 + kk, gc = c0 + col;
-      double vr = 0.0, vi = 0.0;
+      L vr = zl, vi = zl;
       if (gc < s) {
         if (gk < n) {
           const int64_t off = gk + n * gc;
-          vr = Vr[off];
-          if (CPLX) vi = Vi[off];
+          vr = M::v_in(Vr[off]);
+          if (CPLX) vi = M::v_in(Vi[off]);
         } else if (gk < K) {
           const int64_t off = (gk - n) + s * gc;
-          vr = Br[off];
-          if (CPLX) vi = Bi[off];
+          vr = M::a_in(Br[off]);
+          if (CPLX) vi = M::a_in(Bi[off]);
         }
       }
       pb_r[u] = vr;
@@ -160,42 +265,51 @@ __device__ __forceinline__ void apply_tile(const ApplyArgs& a, int k, int rt, in
     __syncthreads();
     if (k0 + TK < K) load_panels(k0 + TK);  // in flight during the MFMAs below
 #pragma unroll
-    for (int ks = 0; ks < TK; ks += 4) {
-      double far_[RB], fai[RB], fbr[CB], fbi[CB];
+    for (int ks = 0; ks < TK; ks += KB) {
+      frag far_[RB], fai[RB], fain[RB], fbr[CB], fbi[CB];
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
         const int row = (wr * RB + i) * 16 + lr;
-        far_[i] = As[0][ks + lk][row];
-        if (CPLX) fai[i] = As[1][ks + lk][row];
+        far_[i] = M::template ld<TM>(As[0], ks, lk, row);
+        if (CPLX) {
+          fai[i] = M::template ld<TM>(As[1], ks, lk, row);
+          fain[i] = M::negf(fai[i]);
+        }
       }
 #pragma unroll
       for (int j = 0; j < CB; ++j) {
         const int col = (wc * CB + j) * 16 + lr;
-        fbr[j] = Bs[0][ks + lk][col];
-        if (CPLX) fbi[j] = Bs[1][ks + lk][col];
+        fbr[j] = M::template ld<TN + 1>(Bs[0], ks, lk, col);
+        if (CPLX) fbi[j] = M::template ld<TN + 1>(Bs[1], ks, lk, col);
       }
+      // Dependent MFMAs on one accumulator are kept apart: a full sweep
+      // over the blocks separates the two updates of every accumulator.
 #pragma unroll
       for (int i = 0; i < RB; ++i)
 #pragma unroll
         for (int j = 0; j < CB; ++j) {
-          accr[i][j] = mfma(far_[i], fbr[j], accr[i][j]);
-          if (CPLX) {
-            accr[i][j] = mfma(-fai[i], fbi[j], accr[i][j]);
-            acci[i][j] = mfma(far_[i], fbi[j], acci[i][j]);
-            acci[i][j] = mfma(fai[i], fbr[j], acci[i][j]);
-          }
+          accr[i][j] = M::mma(far_[i], fbr[j], accr[i][j]);
+          if (CPLX) acci[i][j] = M::mma(far_[i], fbi[j], acci[i][j]);
         }
+      if (CPLX) {
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            accr[i][j] = M::mma(fain[i], fbi[j], accr[i][j]);
+            acci[i][j] = M::mma(fai[i], fbr[j], acci[i][j]);
+          }
+      }
     }
     __syncthreads();
   }
 
-  // Epilogue: out = alpha * W + beta * Y.  The FP64 16 x 16 result block
-  // keeps element (i, j) in lane j + 16 (i mod 4), register i / 4, so lane
-  // (lr, lk) holds rows lk, lk + 4, lk + 8, lk + 12 of column lr.
-  double* Or = a.out + qr * ns;
-  double* Oi = CPLX ? a.out + qi * ns : nullptr;
-  const double* Yr = a.Y ? a.Y + qr * ns : nullptr;
-  const double* Yi = (a.Y && CPLX) ? a.Y + qi * ns : nullptr;
+  // Epilogue: out = alpha * W + beta * Y (row of result register r given by
+  // the traits; column lr of each 16 x 16 block).
+  TV* Or = a.out + qr * ns;
+  TV* Oi = CPLX ? a.out + qi * ns : nullptr;
+  const TV* Yr = a.Y ? a.Y + qr * ns : nullptr;
+  const TV* Yi = (a.Y && CPLX) ? a.Y + qi * ns : nullptr;
 #pragma unroll
   for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -204,59 +318,87 @@ __device__ __forceinline__ void apply_tile(const ApplyArgs& a, int k, int rt, in
       if (col >= s) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + (wr * RB + i) * 16 + 4 * r + lk;
+        const int64_t row = m0 + (wr * RB + i) * 16 + M::row(r, lk);
         if (row >= n) continue;
         const int64_t off = row + n * col;
-        double vr = a.alpha * accr[i][j][r];
-        if (a.beta != 0.0) vr = fma(a.beta, Yr[off], vr);
-        Or[off] = vr;
+        double vr = a.alpha * (double)accr[i][j][r];
+        if (a.beta != 0.0) vr = fma(a.beta, (double)Yr[off], vr);
+        Or[off] = (TV)vr;
         if (CPLX) {
-          double vi = a.alpha * acci[i][j][r];
-          if (a.beta != 0.0) vi = fma(a.beta, Yi[off], vi);
-          Oi[off] = vi;
+          double vi = a.alpha * (double)acci[i][j][r];
+          if (a.beta != 0.0) vi = fma(a.beta, (double)Yi[off], vi);
+          Oi[off] = (TV)vi;
         }
       }
     }
 }
 
-template <int TM, int TN, int RB, int CB>
-__global__ __launch_bounds__(NT) void apply_mfma_f64_kernel(ApplyArgs a) {
-  __shared__ double As[2][TK][TM];
-  __shared__ double Bs[2][TK][TN + 1];
+template <typename Tag, int TM, int TN, int RB, int CB>
+__global__ __launch_bounds__(NT) void apply_mfma_kernel(ApplyArgs<Tag> a) {
+  using L = typename Mma<Tag>::L;
+  constexpr int TK = Mma<Tag>::TK;
+  __shared__ L As[2][TK][TM];
+  __shared__ L Bs[2][TK][TN + 1];
   const int t = xcd_tile(blockIdx.x, a.total);
   const int ct = t % a.nct;
   const int rt = (t / a.nct) % a.nrt;
   const int k = t / (a.nct * a.nrt);
   const bool real_slice = (k == 0) || (2 * k == a.p);
   if (real_slice)
-    apply_tile<TM, TN, RB, CB, false>(a, k, rt, ct, As, Bs);
+    apply_tile<Tag, TM, TN, RB, CB, false>(a, k, rt, ct, As, Bs);
   else
-    apply_tile<TM, TN, RB, CB, true>(a, k, rt, ct, As, Bs);
+    apply_tile<Tag, TM, TN, RB, CB, true>(a, k, rt, ct, As, Bs);
 }
 
-template <int TM, int TN, int RB, int CB>
-void launch_apply(ApplyArgs a, hipStream_t st) {
+template <typename Tag, int TM, int TN, int RB, int CB>
+void launch_apply(ApplyArgs<Tag> a, hipStream_t st) {
   a.nrt = (int)((a.n + TM - 1) / TM);
   a.nct = (int)((a.s + TN - 1) / TN);
   a.total = num_slices(a.p) * a.nrt * a.nct;
-  hipLaunchKernelGGL((apply_mfma_f64_kernel<TM, TN, RB, CB>), dim3(a.total), dim3(NT), 0, st, a);
+  hipLaunchKernelGGL((apply_mfma_kernel<Tag, TM, TN, RB, CB>), dim3(a.total), dim3(NT), 0, st, a);
   TSYLV_LAUNCH_CHECK();
+}
+
+template <typename Tag>
+void dispatch(ApplyArgs<Tag> a, hipStream_t st) {
+  // Column tile as wide as s needs (up to 64) so small s does not waste MFMA work.
+  if (a.s <= 16)
+    launch_apply<Tag, 128, 16, 2, 1>(a, st);
+  else if (a.s <= 32)
+    launch_apply<Tag, 64, 32, 1, 2>(a, st);
+  else
+    launch_apply<Tag, 32, 64, 1, 2>(a, st);
+}
+
+template <typename Tag>
+void apply_any(const typename Store<Tag>::T* Ah, const typename Store<Tag>::T* Bh,
+               const typename Mma<Tag>::TV* V, typename Mma<Tag>::TV* out,
+               const typename Mma<Tag>::TV* Y, double alpha, double beta, int64_t n, int64_t s,
+               int p, bool useB, hipStream_t st) {
+  if (n <= 0 || s <= 0 || p <= 0) return;
+  if (beta != 0.0 && Y == nullptr) throw Error(TSYLV_EINVAL, "apply: beta != 0 needs Y");
+  if (useB && Bh == nullptr) throw Error(TSYLV_EINVAL, "apply: missing Bhat");
+  ApplyArgs<Tag> a{Ah, Bh, V, out, beta != 0.0 ? Y : nullptr, alpha, beta, n, s, p,
+                   useB ? 1 : 0, 0, 0, 0};
+  dispatch<Tag>(a, st);
 }
 
 }  // namespace
 
 void apply_f64(const double* Ah, const double* Bh, const double* V, double* out, const double* Y,
                double alpha, double beta, int64_t n, int64_t s, int p, hipStream_t st) {
-  if (n <= 0 || s <= 0 || p <= 0) return;
-  if (beta != 0.0 && Y == nullptr) throw Error(TSYLV_EINVAL, "apply: beta != 0 needs Y");
-  ApplyArgs a{Ah, Bh, V, out, beta != 0.0 ? Y : nullptr, alpha, beta, n, s, p, 0, 0, 0};
-  // Column tile as wide as s needs (up to 64) so small s does not waste MFMA work.
-  if (s <= 16)
-    launch_apply<128, 16, 2, 1>(a, st);
-  else if (s <= 32)
-    launch_apply<64, 32, 1, 2>(a, st);
-  else
-    launch_apply<32, 64, 1, 2>(a, st);
+  apply_any<double>(Ah, Bh, V, out, Y, alpha, beta, n, s, p, Bh != nullptr, st);
+}
+
+void apply_f32(const float* Ah, const float* Bh, const float* V, float* out, const float* Y,
+               double alpha, double beta, int64_t n, int64_t s, int p, hipStream_t st) {
+  apply_any<float>(Ah, Bh, V, out, Y, alpha, beta, n, s, p, Bh != nullptr, st);
+}
+
+void apply_bf16(const uint16_t* Ah, const uint16_t* Bh, const float* V, float* out,
+                const float* Y, double alpha, double beta, int64_t n, int64_t s, int p,
+                hipStream_t st) {
+  apply_any<Bf16>(Ah, Bh, V, out, Y, alpha, beta, n, s, p, Bh != nullptr, st);
 }
 
 }  // namespace kern

@@ -163,9 +163,10 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// grid: (nchunks, ceil((nv + with_ww) / kVG))
+// grid: (nchunks, ceil((nv + with_ww) / kVG)).  Vectors of type T, sums in FP64.
+template <typename T>
 __global__ __launch_bounds__(kBlock) void mdot_kernel(
-    const double* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ w,
+    const T* __restrict__ V, int64_t ldv, int nv, const T* __restrict__ w,
     int64_t N, double* __restrict__ part, int ldp, int with_ww) {
   const int ncols = nv + with_ww;
   const int g0 = blockIdx.y * kVG;
@@ -176,11 +177,11 @@ __global__ __launch_bounds__(kBlock) void mdot_kernel(
   for (int t = 0; t < kEPT; ++t) {
     int64_t e = base + t * kBlock + threadIdx.x;
     if (e < N) {
-      double we = w[e];
+      double we = (double)w[e];
 #pragma unroll
       for (int v = 0; v < kVG; ++v) {
         int i = g0 + v;
-        if (i < nv) acc[v] = fma(V[(int64_t)i * ldv + e], we, acc[v]);
+        if (i < nv) acc[v] = fma((double)V[(int64_t)i * ldv + e], we, acc[v]);
         else if (i == nv && with_ww) acc[v] = fma(we, we, acc[v]);
       }
     }
@@ -222,32 +223,26 @@ __global__ __launch_bounds__(kBlock) void reduce_partials_kernel(
 
 constexpr int kMaxUpd = 1024;
 
+// w[e] -= sum_i h[i] V_i[e]; basis of type TB, target of type TW, FP64 arithmetic.
+template <typename TB, typename TW>
 __global__ __launch_bounds__(kBlock) void mupdate_kernel(
-    const double* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ h,
-    double* __restrict__ w, int64_t N) {
+    const TB* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ h,
+    TW* __restrict__ w, int64_t N) {
   __shared__ double hs[kMaxUpd];
   for (int i = threadIdx.x; i < nv; i += kBlock) hs[i] = h[i];
   __syncthreads();
   int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e >= N) return;
-  double acc = w[e];
-  for (int i = 0; i < nv; ++i) acc = fma(-hs[i], V[(int64_t)i * ldv + e], acc);
-  w[e] = acc;
+  double acc = (double)w[e];
+  for (int i = 0; i < nv; ++i) acc = fma(-hs[i], (double)V[(int64_t)i * ldv + e], acc);
+  w[e] = (TW)acc;
 }
 
-__global__ void scale_by_rnorm_kernel(const double* __restrict__ w, double* __restrict__ out,
-                                      const double* __restrict__ ww, int64_t N) {
-  const double inv = 1.0 / sqrt(ww[0]);
+template <typename TI, typename TO>
+__global__ void scale_kernel(const TI* __restrict__ x, TO* __restrict__ out, double a, int64_t N) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = w[i] * inv;
-}
-
-__global__ void scale_kernel(const double* __restrict__ x, double* __restrict__ out, double a,
-                             int64_t N) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = a * x[i];
+    out[i] = (TO)(a * (double)x[i]);
 }
 
 inline int stream_grid(int64_t count) {
@@ -306,14 +301,26 @@ void convert_f64_bf16(const double* in, uint16_t* out, int64_t count, hipStream_
 
 int mdot_chunks(int64_t N) { return (int)((N + kChunk - 1) / kChunk); }
 
-void mdot_partial(const double* V, int64_t ldv, int nv, const double* w, int64_t N,
-                  double* part, int ldp, int with_ww, hipStream_t st) {
+template <typename T>
+static void mdot_any(const T* V, int64_t ldv, int nv, const T* w, int64_t N, double* part,
+                     int ldp, int with_ww, hipStream_t st) {
   int ncols = nv + (with_ww ? 1 : 0);
   if (ncols == 0 || N <= 0) return;
+  if (ncols > ldp) throw Error(TSYLV_EINVAL, "mdot: partial row too short");
   dim3 grid(mdot_chunks(N), (ncols + kVG - 1) / kVG);
-  hipLaunchKernelGGL(mdot_kernel, grid, dim3(kBlock), 0, st, V, ldv, nv, w, N, part, ldp,
+  hipLaunchKernelGGL(mdot_kernel<T>, grid, dim3(kBlock), 0, st, V, ldv, nv, w, N, part, ldp,
                      with_ww ? 1 : 0);
   TSYLV_LAUNCH_CHECK();
+}
+
+void mdot_partial(const double* V, int64_t ldv, int nv, const double* w, int64_t N,
+                  double* part, int ldp, int with_ww, hipStream_t st) {
+  mdot_any<double>(V, ldv, nv, w, N, part, ldp, with_ww, st);
+}
+
+void mdot_partial(const float* V, int64_t ldv, int nv, const float* w, int64_t N, double* part,
+                  int ldp, int with_ww, hipStream_t st) {
+  mdot_any<float>(V, ldv, nv, w, N, part, ldp, with_ww, st);
 }
 
 void reduce_partials(const double* part, int nchunks, int ldp, int ncols, double* out,
@@ -324,24 +331,46 @@ void reduce_partials(const double* part, int nchunks, int ldp, int ncols, double
   TSYLV_LAUNCH_CHECK();
 }
 
-void mupdate(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t N,
-             hipStream_t st) {
+template <typename TB, typename TW>
+static void mupdate_any(const TB* V, int64_t ldv, int nv, const double* h, TW* w, int64_t N,
+                        hipStream_t st) {
   if (nv == 0 || N <= 0) return;
   if (nv > kMaxUpd) throw Error(TSYLV_EINVAL, "mupdate: too many vectors");
   dim3 grid((unsigned)((N + kBlock - 1) / kBlock));
-  hipLaunchKernelGGL(mupdate_kernel, grid, dim3(kBlock), 0, st, V, ldv, nv, h, w, N);
+  hipLaunchKernelGGL((mupdate_kernel<TB, TW>), grid, dim3(kBlock), 0, st, V, ldv, nv, h, w, N);
   TSYLV_LAUNCH_CHECK();
 }
 
-void scale_by_rnorm(const double* w, double* out, const double* ww, int64_t N, hipStream_t st) {
-  hipLaunchKernelGGL(scale_by_rnorm_kernel, dim3(stream_grid(N)), dim3(kBlock), 0, st, w, out,
-                     ww, N);
+void mupdate(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t N,
+             hipStream_t st) {
+  mupdate_any<double, double>(V, ldv, nv, h, w, N, st);
+}
+
+void mupdate(const float* V, int64_t ldv, int nv, const double* h, float* w, int64_t N,
+             hipStream_t st) {
+  mupdate_any<float, float>(V, ldv, nv, h, w, N, st);
+}
+
+void mupdate(const float* V, int64_t ldv, int nv, const double* h, double* w, int64_t N,
+             hipStream_t st) {
+  mupdate_any<float, double>(V, ldv, nv, h, w, N, st);
+}
+
+template <typename TI, typename TO>
+static void scale_any(const TI* x, TO* out, double a, int64_t N, hipStream_t st) {
+  hipLaunchKernelGGL((scale_kernel<TI, TO>), dim3(stream_grid(N)), dim3(kBlock), 0, st, x, out,
+                     a, N);
   TSYLV_LAUNCH_CHECK();
 }
 
 void scale(const double* x, double* out, double a, int64_t N, hipStream_t st) {
-  hipLaunchKernelGGL(scale_kernel, dim3(stream_grid(N)), dim3(kBlock), 0, st, x, out, a, N);
-  TSYLV_LAUNCH_CHECK();
+  scale_any<double, double>(x, out, a, N, st);
+}
+void scale(const float* x, float* out, double a, int64_t N, hipStream_t st) {
+  scale_any<float, float>(x, out, a, N, st);
+}
+void scale(const double* x, float* out, double a, int64_t N, hipStream_t st) {
+  scale_any<double, float>(x, out, a, N, st);
 }
 
 }  // namespace kern

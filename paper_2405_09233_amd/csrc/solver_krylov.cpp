@@ -1,4 +1,5 @@
-// tGMRES(m) and tFOM(m): Algorithm 3 of section 3, on the GPU.
+// tGMRES(m) and tFOM(m) -- Algorithm 3 of section 3 -- on the GPU, and the
+// mixed-precision iterative refinement built on them.
 //
 // Representation.  Every vector of the Krylov process (C, R, V_j, X) is kept
 // in the orthonormal real Fourier representation: tube-wise, the half
@@ -24,8 +25,19 @@
 // Hessenberg matrix for tGMRES (residual proposition of section 3.3,
 // ||R_j|| = |gamma_{j+1}|), LU with partial pivoting of H_j for tFOM
 // (section 3.2, ||R_j|| = h_{j+1,j} |y_j|).
+//
+// Mixed precision (not in the paper): the restart loop of Algorithm 3 is
+// kept in FP64 -- R = C - M(X) with the FP64 Fourier slices, X += d in FP64
+// -- while each correction d is one tGMRES(inner_m) cycle on M d = R with
+// FP32 basis vectors and the operator applied from FP32 or BF16 copies of
+// the Fourier slices (FP32 accumulation); the Hessenberg least-squares
+// problem stays FP64.  This is iterative refinement whose inner solver is
+// one restart cycle, so it converges like restarted tGMRES as long as the
+// low-precision operator error is small against each cycle's reduction.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <functional>
 #include <vector>
 
 #include "kernels.hpp"
@@ -38,34 +50,87 @@ namespace {
 
 constexpr double kEps = 2.220446049250313e-16;
 
-struct KrylovPlan {
-  int64_t n, s, p, N, ldv;
-  int m;
-  int nchunks, ldp;
-  size_t bytes;
+// The operator M in Fourier planes, in FP64 and (optionally) one low
+// precision copy used by the inner solves.
+struct Operator {
+  int64_t n = 0, s = 0, p = 0;
+  const double* Ah64 = nullptr;
+  const double* Bh64 = nullptr;
+  const float* Ah32 = nullptr;
+  const float* Bh32 = nullptr;
+  const uint16_t* Ahb = nullptr;
+  const uint16_t* Bhb = nullptr;
+  int low = TSYLV_FP32;  // precision of the float-vector applies
 };
 
-KrylovPlan plan_krylov(int64_t n, int64_t s, int64_t p, int m) {
-  KrylovPlan P;
-  P.n = n;
-  P.s = s;
-  P.p = p;
-  P.N = n * s * p;
-  P.ldv = round_up(P.N, 64);
-  P.m = m;
-  P.nchunks = kern::mdot_chunks(P.N);
-  P.ldp = m + 2;
-  size_t b = 0;
-  b += Workspace::bytes_for(p * n * n, 8);       // Ah
-  b += Workspace::bytes_for(p * s * s, 8);       // Bh
-  b += 3 * Workspace::bytes_for(p * p, 8);       // transforms
-  b += 2 * Workspace::bytes_for(P.N, 8);         // Zc, Zx
-  b += Workspace::bytes_for((int64_t)(m + 1) * P.ldv, 8);  // basis
-  b += Workspace::bytes_for((int64_t)P.nchunks * P.ldp, 8);  // partials
-  b += 4 * Workspace::bytes_for(m + 2, 8);       // h1, h2, ww, y
-  P.bytes = b;
-  return P;
+void op_apply(Ctx& ctx, const Operator& op, const double* V, double* out, const double* Y,
+              double alpha, double beta) {
+  ProfScope ps(ctx, TSYLV_K_APPLY);
+  kern::apply_f64(op.Ah64, op.Bh64, V, out, Y, alpha, beta, op.n, op.s, (int)op.p, ctx.stream);
 }
+
+void op_apply(Ctx& ctx, const Operator& op, const float* V, float* out, const float* Y,
+              double alpha, double beta) {
+  ProfScope ps(ctx, TSYLV_K_APPLY);
+  if (op.low == TSYLV_BF16)
+    kern::apply_bf16(op.Ahb, op.Bhb, V, out, Y, alpha, beta, op.n, op.s, (int)op.p, ctx.stream);
+  else
+    kern::apply_f32(op.Ah32, op.Bh32, V, out, Y, alpha, beta, op.n, op.s, (int)op.p, ctx.stream);
+}
+
+// Reduction buffers shared by the norm and dot kernels.
+struct RedBuf {
+  double* part = nullptr;
+  int nchunks = 0, ldp = 0;
+  double* d_ww = nullptr;
+  double* h_ww = nullptr;
+};
+
+// ||v||^2 of one FP64 or FP32 vector, to the host.
+template <typename TV>
+double norm2(Ctx& ctx, const RedBuf& r, const TV* v, int64_t N) {
+  kern::mdot_partial((const TV*)nullptr, 0, 0, v, N, r.part, r.ldp, 1, ctx.stream);
+  kern::reduce_partials(r.part, r.nchunks, r.ldp, 1, r.d_ww, ctx.stream);
+  TSYLV_HIP(hipMemcpyAsync(r.h_ww, r.d_ww, sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  ctx.sync();
+  return r.h_ww[0];
+}
+
+// Device and pinned buffers of one Arnoldi cycle with basis type TV.
+template <typename TV>
+struct CycleWS {
+  TV* basis = nullptr;
+  int64_t ldv = 0;
+  int m = 0;
+  RedBuf red;
+  double *d_h1 = nullptr, *d_h2 = nullptr, *d_y = nullptr;
+  double *h_h1 = nullptr, *h_h2 = nullptr, *h_y = nullptr;
+  TV* V(int j) const { return basis + (int64_t)j * ldv; }
+
+  static size_t bytes(int64_t N, int m) {
+    int64_t ldv = round_up(N, 64);
+    int nch = kern::mdot_chunks(N);
+    return Workspace::bytes_for((int64_t)(m + 1) * ldv, sizeof(TV)) +
+           Workspace::bytes_for((int64_t)nch * (m + 2), 8) + 4 * Workspace::bytes_for(m + 2, 8);
+  }
+  // host: pinned staging of 4 (m + 2) doubles
+  void carve(Workspace& ws, int64_t N, int m_, double* host) {
+    m = m_;
+    ldv = round_up(N, 64);
+    basis = ws.take<TV>((int64_t)(m + 1) * ldv);
+    red.nchunks = kern::mdot_chunks(N);
+    red.ldp = m + 2;
+    red.part = ws.take<double>((int64_t)red.nchunks * red.ldp);
+    d_h1 = ws.take<double>(m + 2);
+    d_h2 = ws.take<double>(m + 2);
+    red.d_ww = ws.take<double>(m + 2);
+    d_y = ws.take<double>(m + 2);
+    h_h1 = host;
+    h_h2 = host + (m + 2);
+    red.h_ww = host + 2 * (m + 2);
+    h_y = host + 3 * (m + 2);
+  }
+};
 
 // Progressive Givens QR of the (j+1) x j Hessenberg matrix (tGMRES).
 struct Givens {
@@ -150,187 +215,272 @@ bool fom_solve(const std::vector<std::vector<double>>& Hcols, size_t k, double b
   return true;
 }
 
+struct CycleOut {
+  std::vector<double> y;  // coefficients of X += V_k (*) y
+  size_t k = 0;           // steps taken
+  double est = 0.0;       // last residual estimate (absolute)
+  bool fom_fallback = false;
+};
+
+// One restart cycle of Algorithm 3 (steps 4(a)-(b)): up to m steps of
+// tArnoldi on the normalised start vector in w.V(0), stopping early when the
+// residual estimate drops to stop_abs or on a happy breakdown.
+template <typename TV>
+CycleOut arnoldi_cycle(Ctx& ctx, int method, const Operator& op, CycleWS<TV>& w, int64_t N,
+                       double beta, double stop_abs, int m,
+                       const std::function<void(double)>& record) {
+  hipStream_t st = ctx.stream;
+  const RedBuf& r = w.red;
+  Givens giv(beta);
+  std::vector<std::vector<double>> Hcols;
+  std::vector<double> y_fom;
+  bool fom_ok = false;
+  CycleOut out;
+  for (int j = 0; j < m; ++j) {
+    const int nv = j + 1;
+    TV* W = w.V(j + 1);
+    // Algorithm 2 step 3(a): W = M(V_j)
+    op_apply(ctx, op, (const TV*)w.V(j), W, (const TV*)nullptr, 1.0, 0.0);
+    // step 3(b), CGS2: two passes of h = V^T W, W -= V h
+    if (ctx.prof.on()) ctx.prof.begin(TSYLV_K_ORTHO, st);
+    kern::mdot_partial((const TV*)w.basis, w.ldv, nv, (const TV*)W, N, r.part, r.ldp, 1, st);
+    kern::reduce_partials(r.part, r.nchunks, r.ldp, nv + 1, w.d_h1, st);
+    kern::mupdate((const TV*)w.basis, w.ldv, nv, w.d_h1, W, N, st);
+    kern::mdot_partial((const TV*)w.basis, w.ldv, nv, (const TV*)W, N, r.part, r.ldp, 0, st);
+    kern::reduce_partials(r.part, r.nchunks, r.ldp, nv, w.d_h2, st);
+    kern::mupdate((const TV*)w.basis, w.ldv, nv, w.d_h2, W, N, st);
+    // step 3(d): h_{j+1,j} = ||W||_F
+    kern::mdot_partial((const TV*)nullptr, 0, 0, (const TV*)W, N, r.part, r.ldp, 1, st);
+    kern::reduce_partials(r.part, r.nchunks, r.ldp, 1, r.d_ww, st);
+    if (ctx.prof.on()) ctx.prof.end(TSYLV_K_ORTHO, st);
+    TSYLV_HIP(hipMemcpyAsync(w.h_h1, w.d_h1, (nv + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+    TSYLV_HIP(hipMemcpyAsync(w.h_h2, w.d_h2, nv * sizeof(double), hipMemcpyDeviceToHost, st));
+    TSYLV_HIP(hipMemcpyAsync(r.h_ww, r.d_ww, sizeof(double), hipMemcpyDeviceToHost, st));
+    ctx.sync();
+    std::vector<double> h(nv + 1);
+    for (int i = 0; i < nv; ++i) h[i] = w.h_h1[i] + w.h_h2[i];
+    const double w0 = std::sqrt(w.h_h1[nv]);
+    double hn = std::sqrt(r.h_ww[0]);
+    const bool breakdown = !(hn > 16.0 * kEps * w0);
+    if (breakdown) hn = 0.0;
+    h[nv] = hn;
+    out.k = (size_t)nv;
+    double est;
+    if (method == TSYLV_METHOD_GMRES) {
+      est = giv.add(h);
+    } else {
+      giv.add(h);  // keeps the tGMRES fallback available
+      Hcols.push_back(h);
+      fom_ok = fom_solve(Hcols, out.k, beta, y_fom);
+      est = fom_ok ? hn * std::fabs(y_fom[out.k - 1]) : INFINITY;
+    }
+    out.est = est;
+    record(est);
+    if (breakdown || est <= stop_abs) break;
+    // step 3(e): V_{j+1} = W / h_{j+1,j}
+    kern::scale((const TV*)W, W, 1.0 / hn, N, st);
+  }
+  // Algorithm 3 step 4(b): the small problem.
+  if (method == TSYLV_METHOD_GMRES) {
+    out.y = giv.solve(out.k);
+  } else if (fom_ok) {
+    out.y = y_fom;
+  } else {
+    out.fom_fallback = true;
+    out.y = giv.solve(out.k);
+  }
+  return out;
+}
+
+// Adds V_k (*) y to X (Algorithm 3 step 4(c)); X is FP64, V of type TV.
+template <typename TV>
+void add_combination(Ctx& ctx, CycleWS<TV>& w, const CycleOut& c, double* X, int64_t N) {
+  for (size_t i = 0; i < c.k; ++i) w.h_y[i] = -c.y[i];
+  TSYLV_HIP(hipMemcpyAsync(w.d_y, w.h_y, c.k * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
+  kern::mupdate((const TV*)w.basis, w.ldv, (int)c.k, w.d_y, X, N, ctx.stream);
+}
+
+struct Setup {
+  double *Ah, *Bh, *xf_op, *xf_fwd, *xf_inv, *Zc, *Zx;
+};
+
+size_t setup_bytes(int64_t n, int64_t s, int64_t p) {
+  const int64_t N = n * s * p;
+  return Workspace::bytes_for(p * n * n, 8) + Workspace::bytes_for(p * s * s, 8) +
+         3 * Workspace::bytes_for(p * p, 8) + 2 * Workspace::bytes_for(N, 8);
+}
+
+// Algorithm 1 step 1 for the operator (unscaled DFT planes of A and B) and
+// the orthonormal planes of C and X0.
+Setup setup_fourier(Ctx& ctx, Workspace& ws, int64_t n, int64_t s, int64_t p, const double* A,
+                    const double* B, const double* C, const double* X, bool x0_given) {
+  hipStream_t st = ctx.stream;
+  const int64_t N = n * s * p;
+  Setup S;
+  S.Ah = ws.take<double>(p * n * n);
+  S.Bh = ws.take<double>(p * s * s);
+  S.xf_op = ws.take<double>(p * p);
+  S.xf_fwd = ws.take<double>(p * p);
+  S.xf_inv = ws.take<double>(p * p);
+  S.Zc = ws.take<double>(N);
+  S.Zx = ws.take<double>(N);
+  kern::build_xform(S.xf_op, (int)p, XF_OPERATOR, st);
+  kern::build_xform(S.xf_fwd, (int)p, XF_FORWARD, st);
+  kern::build_xform(S.xf_inv, (int)p, XF_INVERSE, st);
+  {
+    ProfScope ps(ctx, TSYLV_K_XFORM);
+    kern::tube_xform_f64(A, S.Ah, S.xf_op, n * n, (int)p, st);
+  }
+  kern::tube_xform_f64(B, S.Bh, S.xf_op, s * s, (int)p, st);
+  kern::tube_xform_f64(C, S.Zc, S.xf_fwd, n * s, (int)p, st);
+  if (x0_given)
+    kern::tube_xform_f64(X, S.Zx, S.xf_fwd, n * s, (int)p, st);
+  else
+    TSYLV_HIP(hipMemsetAsync(S.Zx, 0, N * sizeof(double), st));
+  return S;
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
 }  // namespace
 
-size_t krylov_workspace_bytes(int64_t n, int64_t s, int64_t p, int m) {
-  return plan_krylov(n, s, p, m).bytes;
+size_t krylov_workspace_bytes(int64_t n, int64_t s, int64_t p, const tsylv_opts& o) {
+  const int64_t N = n * s * p;
+  size_t b = setup_bytes(n, s, p);
+  if (!o.refine) return b + CycleWS<double>::bytes(N, o.m);
+  b += Workspace::bytes_for(N, 8);  // FP64 residual
+  b += CycleWS<float>::bytes(N, o.inner_m);
+  if (o.prec == TSYLV_BF16)
+    b += Workspace::bytes_for(p * n * n, 2) + Workspace::bytes_for(p * s * s, 2);
+  else
+    b += Workspace::bytes_for(p * n * n, 4) + Workspace::bytes_for(p * s * s, 4);
+  return b;
 }
 
 int krylov_solve(Ctx& ctx, int method, int64_t n, int64_t s, int64_t p, const double* A,
                  const double* B, const double* C, double* X, const tsylv_opts& o,
                  tsylv_info& info) {
   auto t0 = std::chrono::steady_clock::now();
-  const int m = o.m;
-  const KrylovPlan P = plan_krylov(n, s, p, m);
+  const bool refine = o.refine != 0;
+  const int64_t N = n * s * p;
   hipStream_t st = ctx.stream;
-  Workspace ws(ctx.arena, P.bytes);
-  double* Ah = ws.take<double>(p * n * n);
-  double* Bh = ws.take<double>(p * s * s);
-  double* xf_op = ws.take<double>(p * p);
-  double* xf_fwd = ws.take<double>(p * p);
-  double* xf_inv = ws.take<double>(p * p);
-  double* Zc = ws.take<double>(P.N);
-  double* Zx = ws.take<double>(P.N);
-  double* basis = ws.take<double>((int64_t)(m + 1) * P.ldv);
-  double* part = ws.take<double>((int64_t)P.nchunks * P.ldp);
-  double* d_h1 = ws.take<double>(m + 2);
-  double* d_h2 = ws.take<double>(m + 2);
-  double* d_ww = ws.take<double>(m + 2);
-  double* d_y = ws.take<double>(m + 2);
-  double* hbuf = ctx.host_buffer(4 * (size_t)(m + 2));
-  double* h_h1 = hbuf;
-  double* h_h2 = hbuf + (m + 2);
-  double* h_ww = hbuf + 2 * (m + 2);
-  double* h_y = hbuf + 3 * (m + 2);
-  const int64_t N = P.N;
-  auto V = [&](int j) { return basis + (int64_t)j * P.ldv; };
+  Workspace ws(ctx.arena, krylov_workspace_bytes(n, s, p, o));
+  Setup S = setup_fourier(ctx, ws, n, s, p, A, B, C, X, o.x0_given != 0);
+  Operator op;
+  op.n = n;
+  op.s = s;
+  op.p = p;
+  op.Ah64 = S.Ah;
+  op.Bh64 = S.Bh;
 
-  // ||w||^2 of one vector, to the host.
-  auto norm2 = [&](const double* w) {
-    kern::mdot_partial(nullptr, 0, 0, w, N, part, P.ldp, 1, st);
-    kern::reduce_partials(part, P.nchunks, P.ldp, 1, d_ww, st);
-    TSYLV_HIP(hipMemcpyAsync(h_ww, d_ww, sizeof(double), hipMemcpyDeviceToHost, st));
-    ctx.sync();
-    return h_ww[0];
-  };
-
-  // Setup: Fourier planes of A, B (operator) and C, X0 (vectors), Algorithm 1 step 1.
-  kern::build_xform(xf_op, (int)p, XF_OPERATOR, st);
-  kern::build_xform(xf_fwd, (int)p, XF_FORWARD, st);
-  kern::build_xform(xf_inv, (int)p, XF_INVERSE, st);
-  {
-    ProfScope ps(ctx, TSYLV_K_XFORM);
-    kern::tube_xform_f64(A, Ah, xf_op, n * n, (int)p, st);
+  CycleWS<double> w64;
+  CycleWS<float> w32;
+  double* R64 = nullptr;
+  const int m_cycle = refine ? o.inner_m : o.m;
+  double* host = ctx.host_buffer(4 * (size_t)(m_cycle + 2));
+  if (!refine) {
+    w64.carve(ws, N, o.m, host);
+  } else {
+    R64 = ws.take<double>(N);
+    w32.carve(ws, N, o.inner_m, host);
+    op.low = o.prec == TSYLV_BF16 ? TSYLV_BF16 : TSYLV_FP32;
+    if (op.low == TSYLV_BF16) {
+      uint16_t* Ab = ws.take<uint16_t>(p * n * n);
+      uint16_t* Bb = ws.take<uint16_t>(p * s * s);
+      kern::convert_f64_bf16(S.Ah, Ab, p * n * n, st);
+      kern::convert_f64_bf16(S.Bh, Bb, p * s * s, st);
+      op.Ahb = Ab;
+      op.Bhb = Bb;
+    } else {
+      float* Af = ws.take<float>(p * n * n);
+      float* Bf = ws.take<float>(p * s * s);
+      kern::convert_f64_f32(S.Ah, Af, p * n * n, st);
+      kern::convert_f64_f32(S.Bh, Bf, p * s * s, st);
+      op.Ah32 = Af;
+      op.Bh32 = Bf;
+    }
   }
-  kern::tube_xform_f64(B, Bh, xf_op, s * s, (int)p, st);
-  kern::tube_xform_f64(C, Zc, xf_fwd, n * s, (int)p, st);
-  if (o.x0_given)
-    kern::tube_xform_f64(X, Zx, xf_fwd, n * s, (int)p, st);
-  else
-    TSYLV_HIP(hipMemsetAsync(Zx, 0, N * sizeof(double), st));
+  const RedBuf& red = refine ? w32.red : w64.red;
 
-  const double cnorm = std::sqrt(norm2(Zc));
-  info.steps = info.cycles = 0;
+  // ||C||_F (Parseval: the planes of C are orthonormal coordinates)
+  const double cnorm = std::sqrt(norm2<double>(ctx, red, S.Zc, N));
+  info.steps = info.cycles = info.outer = 0;
   info.relres_est = 0.0;
   info.res_hist_len = 0;
   info.fom_fallback = 0;
-  auto record = [&](double est) {
+  auto record = [&](double est_abs) {
+    double est = est_abs / cnorm;
     info.relres_est = est;
     if (o.res_hist && info.res_hist_len < o.res_hist_cap) o.res_hist[info.res_hist_len++] = est;
   };
 
-  int status = TSYLV_NOT_CONVERGED;
   if (cnorm == 0.0) {
     TSYLV_HIP(hipMemsetAsync(X, 0, N * sizeof(double), st));
     ctx.sync();
     info.relres_true = 0.0;
     info.status = TSYLV_OK;
-    info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info.seconds = seconds_since(t0);
     return TSYLV_OK;
   }
 
-  for (int cycle = 0;; ++cycle) {
-    // R0 = C - M(X0)  (Algorithm 3, step 3), into basis slot 0.
-    if (cycle == 0 && !o.x0_given)
-      TSYLV_HIP(hipMemcpyAsync(V(0), Zc, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  int status = TSYLV_NOT_CONVERGED;
+  const int max_iter = refine ? o.max_outer : o.max_cycles;
+  for (int it = 0;; ++it) {
+    // R0 = C - M(X0)  (Algorithm 3, step 3), in FP64.
+    double* R = refine ? R64 : w64.V(0);
+    if (it == 0 && !o.x0_given)
+      TSYLV_HIP(hipMemcpyAsync(R, S.Zc, N * sizeof(double), hipMemcpyDeviceToDevice, st));
     else
-      {
-        ProfScope ps(ctx, TSYLV_K_APPLY);
-        kern::apply_f64(Ah, Bh, Zx, V(0), Zc, -1.0, 1.0, n, s, (int)p, st);
-      }
-    const double beta = std::sqrt(norm2(V(0)));
+      op_apply(ctx, op, (const double*)S.Zx, R, (const double*)S.Zc, -1.0, 1.0);
+    const double beta = std::sqrt(norm2<double>(ctx, red, R, N));
     info.relres_true = beta / cnorm;
     if (info.relres_true <= o.tol) {
       status = TSYLV_OK;
       break;
     }
-    if (cycle >= o.max_cycles) break;
+    if (it >= max_iter) break;
     info.cycles++;
-    kern::scale(V(0), V(0), 1.0 / beta, N, st);
-
-    Givens giv(beta);
-    std::vector<std::vector<double>> Hcols;
-    std::vector<double> y_fom;
-    size_t k = 0;
-    bool fom_ok = false;
-    for (int j = 0; j < m; ++j) {
-      const int nv = j + 1;
-      double* W = V(j + 1);
-      // Algorithm 2 step 3(a): W = M(V_j)
-      {
-        ProfScope ps(ctx, TSYLV_K_APPLY);
-        kern::apply_f64(Ah, Bh, V(j), W, nullptr, 1.0, 0.0, n, s, (int)p, st);
-      }
-      // step 3(b), CGS2: two passes of h = V^T W, W -= V h
-      if (ctx.prof.on()) ctx.prof.begin(TSYLV_K_ORTHO, st);
-      kern::mdot_partial(basis, P.ldv, nv, W, N, part, P.ldp, 1, st);
-      kern::reduce_partials(part, P.nchunks, P.ldp, nv + 1, d_h1, st);
-      kern::mupdate(basis, P.ldv, nv, d_h1, W, N, st);
-      kern::mdot_partial(basis, P.ldv, nv, W, N, part, P.ldp, 0, st);
-      kern::reduce_partials(part, P.nchunks, P.ldp, nv, d_h2, st);
-      kern::mupdate(basis, P.ldv, nv, d_h2, W, N, st);
-      // step 3(d): h_{j+1,j} = ||W||_F
-      kern::mdot_partial(nullptr, 0, 0, W, N, part, P.ldp, 1, st);
-      kern::reduce_partials(part, P.nchunks, P.ldp, 1, d_ww, st);
-      if (ctx.prof.on()) ctx.prof.end(TSYLV_K_ORTHO, st);
-      TSYLV_HIP(hipMemcpyAsync(h_h1, d_h1, (nv + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
-      TSYLV_HIP(hipMemcpyAsync(h_h2, d_h2, nv * sizeof(double), hipMemcpyDeviceToHost, st));
-      TSYLV_HIP(hipMemcpyAsync(h_ww, d_ww, sizeof(double), hipMemcpyDeviceToHost, st));
-      ctx.sync();
-      info.steps++;
-      std::vector<double> h(nv + 1);
-      for (int i = 0; i < nv; ++i) h[i] = h_h1[i] + h_h2[i];
-      const double w0 = std::sqrt(h_h1[nv]);
-      double hn = std::sqrt(h_ww[0]);
-      bool breakdown = !(hn > 16.0 * kEps * w0);
-      if (breakdown) hn = 0.0;
-      h[nv] = hn;
-      k = (size_t)nv;
-      double est;
-      if (method == TSYLV_METHOD_GMRES) {
-        est = giv.add(h);
-      } else {
-        giv.add(h);  // keeps the tGMRES fallback available
-        Hcols.push_back(h);
-        fom_ok = fom_solve(Hcols, k, beta, y_fom);
-        est = fom_ok ? hn * std::fabs(y_fom[k - 1]) : INFINITY;
-      }
-      record(est / cnorm);
-      if (breakdown || est <= o.tol * cnorm) break;
-      // step 3(e): V_{j+1} = W / h_{j+1,j}
-      kern::scale(W, W, 1.0 / hn, N, st);
-    }
-    // Algorithm 3 step 4(b)-(c): small problem, X = X0 + V_k (*) y.
-    std::vector<double> y;
-    if (method == TSYLV_METHOD_GMRES) {
-      y = giv.solve(k);
-    } else if (fom_ok) {
-      y = y_fom;
+    if (!refine) {
+      kern::scale((const double*)R, R, 1.0 / beta, N, st);
+      CycleOut c = arnoldi_cycle<double>(ctx, method, op, w64, N, beta, o.tol * cnorm, o.m, record);
+      info.steps += (int)c.k;
+      info.fom_fallback += c.fom_fallback ? 1 : 0;
+      add_combination(ctx, w64, c, S.Zx, N);
     } else {
-      info.fom_fallback++;
-      y = giv.solve(k);
+      info.outer++;
+      kern::scale((const double*)R, w32.V(0), 1.0 / beta, N, st);  // rounds to FP32
+      const double stop = std::max(o.inner_tol * beta, 0.5 * o.tol * cnorm);
+      CycleOut c = arnoldi_cycle<float>(ctx, method, op, w32, N, beta, stop, o.inner_m, record);
+      info.steps += (int)c.k;
+      info.fom_fallback += c.fom_fallback ? 1 : 0;
+      add_combination(ctx, w32, c, S.Zx, N);
     }
-    for (size_t i = 0; i < k; ++i) h_y[i] = -y[i];
-    TSYLV_HIP(hipMemcpyAsync(d_y, h_y, k * sizeof(double), hipMemcpyHostToDevice, st));
-    kern::mupdate(basis, P.ldv, (int)k, d_y, Zx, N, st);
   }
   // Algorithm 1 step 3: back to the spatial domain.
-  kern::tube_xform_f64(Zx, X, xf_inv, n * s, (int)p, st);
+  {
+    ProfScope ps(ctx, TSYLV_K_XFORM);
+    kern::tube_xform_f64(S.Zx, X, S.xf_inv, n * s, (int)p, st);
+  }
   ctx.sync();
   info.status = status;
-  info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  info.seconds = seconds_since(t0);
   return status;
 }
 
-// Y = A*X - X*B through the Fourier planes (Algorithm 1).
+// Y = A*X - X*B through the Fourier planes (Algorithm 1), with the slice
+// products in the requested precision.
 size_t apply_workspace_bytes(int64_t n, int64_t s, int64_t p) {
   int64_t N = n * s * p;
   return Workspace::bytes_for(p * n * n, 8) + Workspace::bytes_for(p * s * s, 8) +
-         3 * Workspace::bytes_for(p * p, 8) + 2 * Workspace::bytes_for(N, 8);
+         3 * Workspace::bytes_for(p * p, 8) + 2 * Workspace::bytes_for(N, 8) +
+         Workspace::bytes_for(p * n * n, 4) + Workspace::bytes_for(p * s * s, 4) +
+         2 * Workspace::bytes_for(N, 4);
 }
 
 int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
-                  const double* X, double* Y) {
+                  const double* X, double* Y, int prec) {
   hipStream_t st = ctx.stream;
   const int64_t N = n * s * p;
   Workspace ws(ctx.arena, apply_workspace_bytes(n, s, p));
@@ -347,7 +497,30 @@ int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, co
   kern::tube_xform_f64(A, Ah, xf_op, n * n, (int)p, st);
   kern::tube_xform_f64(B, Bh, xf_op, s * s, (int)p, st);
   kern::tube_xform_f64(X, Zx, xf_fwd, n * s, (int)p, st);
-  kern::apply_f64(Ah, Bh, Zx, Zy, nullptr, 1.0, 0.0, n, s, (int)p, st);
+  if (prec == TSYLV_FP64) {
+    ProfScope ps(ctx, TSYLV_K_APPLY);
+    kern::apply_f64(Ah, Bh, Zx, Zy, nullptr, 1.0, 0.0, n, s, (int)p, st);
+  } else {
+    float* Vf = ws.take<float>(N);
+    float* Wf = ws.take<float>(N);
+    kern::convert_f64_f32(Zx, Vf, N, st);
+    if (prec == TSYLV_BF16) {
+      uint16_t* Ab = reinterpret_cast<uint16_t*>(ws.take<float>(p * n * n));
+      uint16_t* Bb = reinterpret_cast<uint16_t*>(ws.take<float>(p * s * s));
+      kern::convert_f64_bf16(Ah, Ab, p * n * n, st);
+      kern::convert_f64_bf16(Bh, Bb, p * s * s, st);
+      ProfScope ps(ctx, TSYLV_K_APPLY);
+      kern::apply_bf16(Ab, Bb, Vf, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st);
+    } else {
+      float* Af = ws.take<float>(p * n * n);
+      float* Bf = ws.take<float>(p * s * s);
+      kern::convert_f64_f32(Ah, Af, p * n * n, st);
+      kern::convert_f64_f32(Bh, Bf, p * s * s, st);
+      ProfScope ps(ctx, TSYLV_K_APPLY);
+      kern::apply_f32(Af, Bf, Vf, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st);
+    }
+    kern::convert_f32_f64(Wf, Zy, N, st);
+  }
   kern::tube_xform_f64(Zy, Y, xf_inv, n * s, (int)p, st);
   ctx.sync();
   return TSYLV_OK;
