@@ -1,15 +1,23 @@
-"""Benchmark: tGMRES solves/s to true relative residual 1e-8 on one MI355X.
+"""Benchmark: tGMRES solves/s to true relative residual 1e-8 on one MI355X,
+mixed precision vs FP64, with per-solve latency percentiles.
 
 One "step" is one whole solve through the C ABI: from device-resident
-spatial A, B, C (mode-3 DFT of A, B, C, restarted tGMRES(30) in the Fourier
+spatial A, B, C (mode-3 DFT of A, B, C, the Krylov iteration in the Fourier
 planes, inverse DFT of X) to device-resident spatial X.  Inputs are synthetic
-(see paper_2405_09233_amd/workloads.py) and already in HBM when timing
-starts.
+(paper_2405_09233_amd/workloads.py) and already in HBM when timing starts.
 
-Prints ONE JSON line.  Extra fields: per-solve latency percentiles, the
-step count of a solve, the roofline of the dominant kernel (the facewise
-apply, timed live with HIP events on the library's stream) and the FP64
-oracle timed on a bounded sample on the host cores.
+Paths timed (each: W warm-up solves, then K timed solves):
+  fp64      restarted tGMRES(30), everything FP64
+  mixed     FP64 iterative refinement; each correction one tGMRES(40) cycle
+            with FP32 basis vectors and FP32 MFMA slice products
+  bf16      the same with BF16 slice products (FP32 accumulation)
+A path counts only if every timed solve reaches true FP64 relres <= tol.
+`value` is the solves/s of the fastest valid path; every path is reported.
+
+Prints ONE JSON line.  The roofline object is for the dominant kernel of the
+path that gives `value` (the facewise slice-product kernel), timed live with
+HIP events on the library's stream; cpu_baseline is the FP64 oracle timed on a
+bounded sample on the host cores.
 """
 
 import argparse
@@ -24,23 +32,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "tGMRES solves/s at relres 1e-8, mixed vs FP64; p50/p99 solve latency"
-PEAK_FP64 = 78.6e12   # FP64 (vector = matrix) FLOP/s, MI355X
-PEAK_HBM = 8.0e12     # bytes/s
+PEAKS = {  # MI355X dense peaks, FLOP/s
+    "fp64": 78.6e12, "mixed": 157.3e12, "bf16": 2.5e15}
+PEAK_HBM = 8.0e12
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def apply_work(n, s, p, elem=8):
-    """Algorithmic flops and bytes of one facewise apply W = Ahat V - V Bhat on
-    the half spectrum: real slices (DC, and Nyquist for even p) cost
-    2(n^2 s + n s^2) flops, complex slices 8(n^2 s + n s^2); bytes = the p
-    planes of Ahat and Bhat read once, V read once, W written once."""
+def apply_work(n, s, p, elem):
+    """Algorithmic flops and HBM bytes of one facewise apply
+    W = Ahat V - V Bhat on the half spectrum: real slices (DC, and Nyquist for
+    even p) cost 2(n^2 s + n s^2) flops, complex slices 8(n^2 s + n s^2);
+    bytes = the p planes of Ahat and Bhat (elem bytes each) read once, V read
+    and W written once (vector element size vbytes)."""
     n_real = 2 if p % 2 == 0 else 1
     n_cplx = (p - n_real) // 2
     flops = (2 * n_real + 8 * n_cplx) * (n * n * s + n * s * s)
-    bytes_ = elem * p * (n * n + s * s + 2 * n * s)
+    ab, vb = elem
+    bytes_ = p * (ab * (n * n + s * s) + 2 * vb * n * s)
     return flops, bytes_
 
 
@@ -77,8 +88,54 @@ def cpu_baseline(A, B, C, applies_per_solve, avg_basis):
             "kind": "oracle",
             "sample": "oracle at n=%d s=%d p=%d: frontal slice 0 of M(V) by circulant sums "
                       "(%.2f s, x p = one apply) and one MGS sweep against 16 basis vectors "
-                      "(%.2f s); scaled by %d applies of M per solve and a mean basis of %.1f "
-                      "vectors" % (n, s, p, t_slice, t_mgs, applies_per_solve, avg_basis)}
+                      "(%.2f s); scaled by %d applies of M per FP64 solve and a mean basis of "
+                      "%.1f vectors" % (n, s, p, t_slice, t_mgs, applies_per_solve, avg_basis)}
+
+
+def run_path(ctx, tsylv, dev_in, opts, steps, warmup, name):
+    import torch
+    Ad, Bd, Cd, Xd = dev_in
+    for w in range(warmup):
+        _, info = ctx.gmres(Ad, Bd, Cd, X=Xd, opts=opts)
+        log("%s warmup %d: status=%d steps=%d cycles=%d relres=%.3e %.3fs"
+            % (name, w, info.status, info.steps, info.cycles, info.relres_true, info.seconds))
+    ctx.profile(True)
+    lat, infos = [], []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(steps):
+        ts = time.perf_counter()
+        _, info = ctx.gmres(Ad, Bd, Cd, X=Xd, opts=opts)
+        lat.append(time.perf_counter() - ts)
+        infos.append(info.as_dict())
+        log("%s solve %d: status=%d steps=%d cycles=%d relres=%.3e %.3fs"
+            % (name, k, info.status, info.steps, info.cycles, info.relres_true, lat[-1]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    la, ms_apply = ctx.profile_read(tsylv.K_APPLY)
+    ll, ms_low = ctx.profile_read(tsylv.K_APPLY_LOW)
+    lo, ms_ortho = ctx.profile_read(tsylv.K_ORTHO)
+    lx, ms_xform = ctx.profile_read(tsylv.K_XFORM)
+    ctx.profile(False)
+    # the dominant slice-product kernel of the path: FP64, or the low one
+    dom_l, dom_ms = (ll, ms_low) if ll > 0 else (la, ms_apply)
+    ok = all(i["status"] == 0 and i["relres_true"] <= opts.tol for i in infos)
+    return {
+        "valid": ok,
+        "solves_per_s": steps / elapsed,
+        "ms_per_solve": elapsed / steps * 1e3,
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                       "p99": float(np.percentile(lat, 99) * 1e3)},
+        "steps": infos[-1]["steps"], "cycles": infos[-1]["cycles"],
+        "outer": infos[-1]["outer"], "relres_true": infos[-1]["relres_true"],
+        "applies_per_solve": (la + ll) // max(1, steps),
+        "apply_launches": dom_l, "apply_avg_ms": dom_ms / max(1, dom_l),
+        "time_split_ms_per_solve": {"apply_fp64": ms_apply / steps,
+                                    "apply_low": ms_low / steps,
+                                    "orthogonalisation": ms_ortho / steps,
+                                    "dft": ms_xform / steps},
+        "elapsed_s": elapsed,
+    }
 
 
 def main():
@@ -87,7 +144,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--m", type=int, default=30)
+    ap.add_argument("--inner-m", type=int, default=40)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--paths", default="fp64,mixed,bf16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--grid", type=int, nargs=2, default=[64, 64])
     ap.add_argument("--s", type=int, default=64)
@@ -100,7 +159,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
+    import torch  # noqa: F401
     from paper_2405_09233_amd import tsylv, workloads
 
     nx, ny = args.grid
@@ -111,76 +170,71 @@ def main():
     dev = "cuda:0"
     Ad, Bd, Cd = (tsylv.to_device(T, dev) for T in (A, B, C))
     Xd = tsylv.empty_device((n, s, p), dev)
-    opts = tsylv.default_opts(tsylv.GMRES, m=args.m, tol=args.tol, max_cycles=2000)
-    need = tsylv.workspace_bytes(tsylv.GMRES, n, s, p, opts)
+    path_opts = {
+        "fp64": tsylv.default_opts(tsylv.GMRES, m=args.m, tol=args.tol, max_cycles=2000),
+        "mixed": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.FP32, inner_m=args.inner_m,
+                                    inner_tol=1e-4, tol=args.tol, max_outer=2000),
+        "bf16": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.BF16, inner_m=args.inner_m,
+                                   inner_tol=1e-4, tol=args.tol, max_outer=300),
+    }
+    paths = [x for x in args.paths.split(",") if x]
+    need = max(tsylv.workspace_bytes(tsylv.GMRES, n, s, p, path_opts[x]) for x in paths)
     ctx = tsylv.Context(need + (64 << 20), device=0)
+    res = {}
+    for name in paths:
+        res[name] = run_path(ctx, tsylv, (Ad, Bd, Cd, Xd), path_opts[name], args.steps,
+                             args.warmup, name)
 
-    for w in range(args.warmup):
-        _, info = ctx.gmres(Ad, Bd, Cd, X=Xd, opts=opts)
-        log("warmup %d: status=%d steps=%d cycles=%d relres=%.3e %.3fs"
-            % (w, info.status, info.steps, info.cycles, info.relres_true, info.seconds))
+    valid = [x for x in paths if res[x]["valid"]]
+    best = max(valid, key=lambda x: res[x]["solves_per_s"]) if valid else paths[0]
+    r = res[best]
+    elem = {"fp64": (8, 8), "mixed": (4, 4), "bf16": (2, 4)}[best]
+    flops, bytes_ = apply_work(n, s, p, elem)
+    avg_s = r["apply_avg_ms"] / 1e3
+    achieved_flops = flops / avg_s
+    achieved_bw = bytes_ / avg_s
+    if best == "bf16":
+        roofline = {"bound": "hbm", "achieved": achieved_bw / 1e9, "peak": PEAK_HBM / 1e9,
+                    "unit": "GB/s", "frac": achieved_bw / PEAK_HBM}
+    else:
+        peak = PEAKS[best]
+        roofline = {"bound": "mfma", "achieved": achieved_flops / 1e12, "peak": peak / 1e12,
+                    "unit": "TFLOP/s", "frac": achieved_flops / peak}
+    roofline.update({"traffic": None, "kernel": "apply_mfma_kernel (%s)" % best,
+                     "avg_launch_ms": r["apply_avg_ms"], "launches": r["apply_launches"],
+                     "algorithmic_flops_per_launch": flops,
+                     "algorithmic_bytes_per_launch": bytes_})
 
-    ctx.profile(True)
-    lat = []
-    infos = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        ts = time.perf_counter()
-        _, info = ctx.gmres(Ad, Bd, Cd, X=Xd, opts=opts)
-        lat.append(time.perf_counter() - ts)
-        infos.append(info.as_dict())
-        log("solve %d: status=%d steps=%d cycles=%d relres=%.3e %.3fs"
-            % (k, info.status, info.steps, info.cycles, info.relres_true, lat[-1]))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    la, ms_apply = ctx.profile_read(tsylv.K_APPLY)
-    lo, ms_ortho = ctx.profile_read(tsylv.K_ORTHO)
-    lx, ms_xform = ctx.profile_read(tsylv.K_XFORM)
-    ctx.profile(False)
-
-    ok = all(i["status"] == 0 and i["relres_true"] <= args.tol for i in infos)
-    steps_per_solve = infos[-1]["steps"]
-    applies_per_solve = la // max(1, args.steps)
-    flops, bytes_ = apply_work(n, s, p)
-    avg_apply_s = ms_apply / 1e3 / max(1, la)
-    achieved = flops / avg_apply_s
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
-                "kernel": "apply_f64_kernel", "avg_launch_ms": avg_apply_s * 1e3,
-                "launches": la, "hbm_GBps_algorithmic": bytes_ / avg_apply_s / 1e9}
-
+    dtype = {"fp64": "f64", "mixed": "f32 (inner) + f64 (refinement)",
+             "bf16": "bf16 x bf16 -> f32 (inner) + f64 (refinement)"}[best]
     out = {
         "metric": METRIC,
-        "value": args.steps / elapsed if ok else 0.0,
+        "value": r["solves_per_s"] if r["valid"] else 0.0,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": r["ms_per_solve"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": "convection-diffusion n=%d (%dx%d grid, mu=1, c=(10,10)) + "
-                               "dense N(0,1e-4) slices, s=%d, p=%d; tGMRES(%d) to true relres "
-                               "%.0e, FP64" % (n, nx, ny, s, p, args.m, args.tol),
-                   "n": n, "s": s, "p": p, "m": args.m, "tol": args.tol, "precision": "fp64"},
-        "valid": ok,
-        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                       "p99": float(np.percentile(lat, 99) * 1e3)},
-        "solve": {"steps": steps_per_solve, "cycles": infos[-1]["cycles"],
-                  "relres_true": infos[-1]["relres_true"], "applies": applies_per_solve},
-        "time_split_ms_per_solve": {"apply": ms_apply / args.steps,
-                                    "orthogonalisation": ms_ortho / args.steps,
-                                    "dft_of_A": ms_xform / args.steps},
+        "config": {"workload": "convection-diffusion n=%d (%dx%d grid, mu=1, c=(10,10), +8I) + "
+                               "dense N(0,1e-4) slices, s=%d, p=%d; tGMRES to true relres %.0e "
+                               "(path %s)" % (n, nx, ny, s, p, args.tol, best),
+                   "n": n, "s": s, "p": p, "m": args.m, "inner_m": args.inner_m,
+                   "tol": args.tol, "path": best},
+        "latency_ms": r["latency_ms"],
+        "paths": res,
+        "mixed_vs_fp64": (res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"]
+                          if "mixed" in res and "fp64" in res else None),
         "roofline": roofline,
     }
     if not args.no_cpu:
         log("timing the oracle sample on the host ...")
-        avg_basis = (args.m + 1) / 2.0
-        out["cpu_baseline"] = cpu_baseline(A, B, C, applies_per_solve, avg_basis)
+        fp = res.get("fp64", r)
+        out["cpu_baseline"] = cpu_baseline(A, B, C, fp["applies_per_solve"], (args.m + 1) / 2.0)
     ctx.close()
     print(json.dumps(out), flush=True)
 

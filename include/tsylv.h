@@ -169,10 +169,11 @@ int tsylv_poll(tsylv_ctx* ctx, uint64_t ticket, tsylv_info* info);
  * (the stream the kernels run on); tsylv_profile_read folds the elapsed
  * times into per-family totals.  Off by default. */
 typedef enum {
-  TSYLV_K_APPLY = 0, /* facewise operator apply  Ahat_k V_k - V_k Bhat_k     */
-  TSYLV_K_ORTHO = 1, /* Gram-Schmidt dots, updates, norms                     */
-  TSYLV_K_XFORM = 2, /* mode-3 DFT / inverse DFT of the tubes                 */
-  TSYLV_K_COUNT = 3
+  TSYLV_K_APPLY = 0,     /* FP64 facewise apply  Ahat_k V_k - V_k Bhat_k      */
+  TSYLV_K_ORTHO = 1,     /* Gram-Schmidt dots, updates, norms                  */
+  TSYLV_K_XFORM = 2,     /* mode-3 DFT of A and inverse DFT of X               */
+  TSYLV_K_APPLY_LOW = 3, /* FP32 / BF16 facewise apply (refinement inner)      */
+  TSYLV_K_COUNT = 4
 } tsylv_kernel_id;
 
 typedef struct {

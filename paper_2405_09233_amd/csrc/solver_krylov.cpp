@@ -71,7 +71,7 @@ void op_apply(Ctx& ctx, const Operator& op, const double* V, double* out, const 
 
 void op_apply(Ctx& ctx, const Operator& op, const float* V, float* out, const float* Y,
               double alpha, double beta) {
-  ProfScope ps(ctx, TSYLV_K_APPLY);
+  ProfScope ps(ctx, TSYLV_K_APPLY_LOW);
   if (op.low == TSYLV_BF16)
     kern::apply_bf16(op.Ahb, op.Bhb, V, out, Y, alpha, beta, op.n, op.s, (int)op.p, ctx.stream);
   else
@@ -509,14 +509,14 @@ int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, co
       uint16_t* Bb = reinterpret_cast<uint16_t*>(ws.take<float>(p * s * s));
       kern::convert_f64_bf16(Ah, Ab, p * n * n, st);
       kern::convert_f64_bf16(Bh, Bb, p * s * s, st);
-      ProfScope ps(ctx, TSYLV_K_APPLY);
+      ProfScope ps(ctx, TSYLV_K_APPLY_LOW);
       kern::apply_bf16(Ab, Bb, Vf, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st);
     } else {
       float* Af = ws.take<float>(p * n * n);
       float* Bf = ws.take<float>(p * s * s);
       kern::convert_f64_f32(Ah, Af, p * n * n, st);
       kern::convert_f64_f32(Bh, Bf, p * s * s, st);
-      ProfScope ps(ctx, TSYLV_K_APPLY);
+      ProfScope ps(ctx, TSYLV_K_APPLY_LOW);
       kern::apply_f32(Af, Bf, Vf, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st);
     }
     kern::convert_f32_f64(Wf, Zy, N, st);

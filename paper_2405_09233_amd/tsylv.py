@@ -49,7 +49,7 @@ class KStat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
-K_APPLY, K_ORTHO, K_XFORM = 0, 1, 2
+K_APPLY, K_ORTHO, K_XFORM, K_APPLY_LOW = 0, 1, 2, 3
 
 
 class Request(ctypes.Structure):
