@@ -122,6 +122,12 @@ size_t tsylv_workspace_bytes(int method, int64_t n, int64_t s, int64_t p, const 
   if (method == -1) return apply_workspace_bytes(n, s, p);
   if (method == TSYLV_METHOD_GMRES || method == TSYLV_METHOD_FOM)
     return krylov_workspace_bytes(n, s, p, o);
+  if (method == TSYLV_METHOD_TBA) {
+    if (n < 2 * s) return 0;
+    int m = o.m;
+    if ((int64_t)(m + 1) * s > n) m = (int)(n / s) - 1;
+    return tba_workspace_bytes(n, s, p, m);
+  }
   return 0;
 }
 
@@ -170,8 +176,22 @@ int tsylv_gmres(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A
 
 int tsylv_tba(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
               const double* C, double* X, const tsylv_opts* opts, tsylv_info* info) {
-  (void)ctx; (void)n; (void)s; (void)p; (void)A; (void)B; (void)C; (void)X; (void)opts; (void)info;
-  return TSYLV_EINVAL;
+  if (!ctx || !A || !B || !C || !X || !dims_ok(n, s, p) || n < 2 * s) return TSYLV_EINVAL;
+  tsylv_opts o;
+  tsylv_default_opts(TSYLV_METHOD_TBA, &o);
+  if (opts) o = *opts;
+  if (!opts_ok(o)) return TSYLV_EINVAL;
+  tsylv_info local;
+  std::memset(&local, 0, sizeof(local));
+  tsylv_info& inf = info ? *info : local;
+  std::memset(&inf, 0, sizeof(inf));
+  int st = guarded([&]() {
+    std::lock_guard<std::mutex> g(ctx->c.sync_mu);
+    set_device(ctx);
+    return tba_solve(ctx->c, n, s, p, A, B, C, X, o, inf);
+  });
+  inf.status = st;
+  return st;
 }
 
 int tsylv_submit(tsylv_ctx* ctx, const tsylv_request* req, uint64_t* ticket) {

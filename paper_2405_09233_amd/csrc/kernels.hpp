@@ -66,5 +66,32 @@ void scale(const double* x, double* out, double a, int64_t N, hipStream_t st);
 void scale(const float* x, float* out, double a, int64_t N, hipStream_t st);
 void scale(const double* x, float* out, double a, int64_t N, hipStream_t st);
 
+// ---- batched planar-complex FP64 GEMM over the Fourier slices ----
+
+// Element (r, c) of slice k of a planar matrix sits at
+//   base + q * plane + r + (c % cb) * ld + (c / cb) * bs
+// where q is the Re (or Im) plane of slice k in the half-spectrum layout.
+struct PMat {
+  const double* base;
+  int64_t plane, ld, cb, bs;
+};
+
+inline PMat dense_pmat(const double* base, int64_t plane, int64_t ld) {
+  return PMat{base, plane, ld, (int64_t)1 << 40, 0};
+}
+
+// Number of K splits zgemm uses when given a partial buffer, and the size of
+// that buffer in doubles.
+int zgemm_splits(int64_t M, int64_t N, int64_t K, int p);
+int64_t zgemm_partial_elems(int64_t M, int64_t N, int64_t K, int p);
+
+// C_k = alpha op(A_k) B_k + beta C_k for every slice k, op(A) = A (M x K) or
+// A^H (A stored K x M) when conjA.  C is dense: plane stride planeC, leading
+// dimension ldC, and must not overlap A or B.  With `partial` non-null the
+// contraction is split over K (partial: zgemm_partial_elems doubles).
+void zgemm(const PMat& A, bool conjA, const PMat& B, double* C, int64_t planeC, int64_t ldC,
+           int64_t M, int64_t N, int64_t K, double alpha, double beta, int p, double* partial,
+           hipStream_t st);
+
 }  // namespace kern
 }  // namespace tsylv

@@ -300,9 +300,11 @@ void add_combination(Ctx& ctx, CycleWS<TV>& w, const CycleOut& c, double* X, int
   kern::mupdate((const TV*)w.basis, w.ldv, (int)c.k, w.d_y, X, N, ctx.stream);
 }
 
-struct Setup {
-  double *Ah, *Bh, *xf_op, *xf_fwd, *xf_inv, *Zc, *Zx;
-};
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
 
 size_t setup_bytes(int64_t n, int64_t s, int64_t p) {
   const int64_t N = n * s * p;
@@ -339,12 +341,6 @@ Setup setup_fourier(Ctx& ctx, Workspace& ws, int64_t n, int64_t s, int64_t p, co
     TSYLV_HIP(hipMemsetAsync(S.Zx, 0, N * sizeof(double), st));
   return S;
 }
-
-double seconds_since(std::chrono::steady_clock::time_point t0) {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-}
-
-}  // namespace
 
 size_t krylov_workspace_bytes(int64_t n, int64_t s, int64_t p, const tsylv_opts& o) {
   const int64_t N = n * s * p;

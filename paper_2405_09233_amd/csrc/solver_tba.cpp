@@ -1,0 +1,357 @@
+// TBAS(m): the restarted Tubal-Block-Arnoldi Sylvester solver of section 5.2
+// (Algorithm 8), on the GPU.
+//
+// In the Fourier domain every step of the Tubal Block Arnoldi process
+// (Algorithm 7) is a per-slice complex matrix operation (eq. (5) decouples
+// the slices; the T-transpose is the per-slice conjugate transpose):
+//   W_k = Ahat_k V_{j,k}                       (A only, not M)
+//   H_{ij,k} = V_{i,k}^H W_k,  W_k -= V_{i,k} H_{ij,k}     (block CGS2 here;
+//                                               the printed block MGS is
+//                                               the same in exact arithmetic)
+//   [V_{j+1}, H_{j+1,j}] = Tubal-QR(W)         (Algorithm 6)
+// Tubal-QR with the Normalization of section 5.1 read as the symmetric
+// positive tube (hat a_k = ||W_k||) is, slice by slice, the thin QR with a
+// real positive diagonal; we compute it as Cholesky QR done twice (CholQR2:
+// R = R2 R1 keeps that diagonal positive), which reaches the same factors.
+//
+// Representation: R and X are kept in the orthonormal scaled planes of the
+// Krylov solvers (slice k scaled by c_k = sqrt(w_k / p)); the basis blocks
+// are the unscaled orthonormal Fourier slices Q_k.  Then H_ij is scale free,
+// H0 (from the QR of R0) and the projected solution Y carry the factor c_k,
+// and X += V Y stays in the scaled representation; the residual estimate of
+// the proposition of section 5.2, ||H_{m+1,m} E_m Y||_F, is the plain norm
+// of the stored slices (Parseval).
+//
+// The projected equation H_m Y - Y B = V_m^T R0 = [H0; 0] (eq. (TBslowrank))
+// is solved per slice on the host in FP64 by Bartels-Stewart with the Schur
+// form of Bhat_k (host_linalg), the slices spread over host threads.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <thread>
+#include <vector>
+
+#include "host_linalg.hpp"
+#include "kernels.hpp"
+#include "runtime.hpp"
+#include "solvers.hpp"
+
+namespace tsylv {
+
+namespace {
+
+using host::cplx;
+constexpr double kEps = 2.220446049250313e-16;
+
+// Planar buffer [plane][col][row] <-> per-slice complex matrix (column-major).
+void unpack(const std::vector<double>& buf, int p, int k, int rows, int cols, cplx* out) {
+  int qr, qi;
+  slice_planes(p, k, qr, qi);
+  const size_t pl = (size_t)rows * cols;
+  for (size_t e = 0; e < pl; ++e)
+    out[e] = cplx(buf[qr * pl + e], qi < 0 ? 0.0 : buf[qi * pl + e]);
+}
+
+void pack(const cplx* in, int p, int k, int rows, int cols, std::vector<double>& buf) {
+  int qr, qi;
+  slice_planes(p, k, qr, qi);
+  const size_t pl = (size_t)rows * cols;
+  for (size_t e = 0; e < pl; ++e) {
+    buf[qr * pl + e] = in[e].real();
+    if (qi >= 0) buf[qi * pl + e] = in[e].imag();
+  }
+}
+
+template <typename F>
+void parallel_slices(int ph, F&& f) {
+  int nt = (int)std::thread::hardware_concurrency();
+  if (nt < 1) nt = 1;
+  if (nt > 16) nt = 16;
+  if (nt > ph) nt = ph;
+  if (nt <= 1) {
+    for (int k = 0; k < ph; ++k) f(k);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t]() {
+      for (int k = t; k < ph; k += nt) f(k);
+    });
+  for (auto& x : th) x.join();
+}
+
+struct TbaWS {
+  int64_t n, s, p, N, ldv;
+  int m, ph;
+  double *R, *T, *basis, *G, *Gq, *Rinv, *Y, *partial;
+  double *part, *d_ww;
+  int nchunks;
+  double* V(int j) const { return basis + (int64_t)j * ldv; }
+};
+
+// Largest split-K partial buffer over the Gram products of one cycle.
+int64_t tba_partial_elems(int64_t n, int64_t s, int64_t p, int m) {
+  int64_t e = 0;
+  for (int j = 1; j <= m; ++j) e = std::max(e, kern::zgemm_partial_elems(j * s, s, n, (int)p));
+  return e;
+}
+
+size_t tba_ws_bytes(int64_t n, int64_t s, int64_t p, int m) {
+  const int64_t N = n * s * p, ldv = round_up(N, 64), ms = (int64_t)m * s;
+  const int64_t part = tba_partial_elems(n, s, p, m);
+  return setup_bytes(n, s, p) + 2 * Workspace::bytes_for(N, 8) +
+         Workspace::bytes_for((int64_t)(m + 1) * ldv, 8) + Workspace::bytes_for(p * ms * s, 8) +
+         2 * Workspace::bytes_for(p * s * s, 8) + Workspace::bytes_for(p * ms * s, 8) +
+         Workspace::bytes_for(part, 8) + Workspace::bytes_for(kern::mdot_chunks(N) * 2, 8) +
+         Workspace::bytes_for(8, 8);
+}
+
+double dev_norm2(Ctx& ctx, const TbaWS& w, const double* v) {
+  kern::mdot_partial((const double*)nullptr, 0, 0, v, w.N, w.part, 2, 1, ctx.stream);
+  kern::reduce_partials(w.part, w.nchunks, 2, 1, w.d_ww, ctx.stream);
+  double h = 0.0;
+  TSYLV_HIP(hipMemcpyAsync(&h, w.d_ww, sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  ctx.sync();
+  return h;
+}
+
+// Tubal-QR (Algorithm 6) of the n x s block in `Win`, slice by slice, by
+// CholQR2: Qout receives the orthonormal slices, Rk[k] (s x s, upper
+// triangular, real positive diagonal) the R factor of slice k.  `unscale`
+// multiplies the diagonal by 1/c_k for the tube test (Win in scaled planes).
+// Returns false on a non-invertible tube (Normalization breakdown).
+bool tubal_qr(Ctx& ctx, const TbaWS& w, const double* Win, double* Qout,
+              std::vector<std::vector<cplx>>& Rk, bool scaled) {
+  const int s = (int)w.s, p = (int)w.p, ph = w.ph;
+  const int64_t n = w.n, ns = n * w.s, ss = w.s * w.s;
+  std::vector<double> hbuf((size_t)p * ss);
+  std::vector<std::vector<cplx>> R1(ph, std::vector<cplx>((size_t)s * s));
+  bool ok = true;
+  const double* src = Win;
+  for (int pass = 0; pass < 2; ++pass) {
+    // Gram of every slice: W_k^H W_k
+    kern::zgemm(kern::dense_pmat(src, ns, n), true, kern::dense_pmat(src, ns, n), w.Gq, ss,
+                w.s, w.s, w.s, n, 1.0, 0.0, p, w.partial, ctx.stream);
+    TSYLV_HIP(hipMemcpyAsync(hbuf.data(), w.Gq, hbuf.size() * 8, hipMemcpyDeviceToHost, ctx.stream));
+    ctx.sync();
+    std::vector<double> rinv((size_t)p * ss, 0.0);
+    std::vector<int> good(ph, 1);
+    parallel_slices(ph, [&](int k) {
+      std::vector<cplx> G((size_t)s * s), Ri((size_t)s * s);
+      unpack(hbuf, p, k, s, s, G.data());
+      if (!host::cholesky_upper(G.data(), s, 1e3 * kEps * kEps)) {
+        good[k] = 0;
+        return;
+      }
+      host::tri_inv_upper(G.data(), Ri.data(), s);
+      pack(Ri.data(), p, k, s, s, rinv);  // writes only this slice's planes
+      if (pass == 0)
+        R1[k] = G;
+      else
+        host::matmul(G.data(), R1[k].data(), Rk[k].data(), s, s, s);  // R = R2 R1
+    });
+    for (int k = 0; k < ph; ++k) ok = ok && good[k];
+    if (!ok) return false;
+    TSYLV_HIP(hipMemcpyAsync(w.Rinv, rinv.data(), rinv.size() * 8, hipMemcpyHostToDevice,
+                             ctx.stream));
+    double* dst = (pass == 0) ? w.T : Qout;
+    kern::zgemm(kern::dense_pmat(src, ns, n), false, kern::dense_pmat(w.Rinv, ss, w.s), dst, ns, n,
+                n, w.s, w.s, 1.0, 0.0, p, nullptr, ctx.stream);
+    ctx.sync();  // rinv (host) must outlive the copy
+    src = w.T;
+  }
+  // Tube test of the Normalization: hat a_k = R_k(jj, jj) (/ c_k in scaled planes)
+  for (int jj = 0; jj < s; ++jj) {
+    double amin = INFINITY, amax = 0.0;
+    for (int k = 0; k < ph; ++k) {
+      const bool real_slice = (k == 0) || (2 * k == p);
+      const double ck = std::sqrt((real_slice ? 1.0 : 2.0) / p);
+      double a = Rk[k][jj + (size_t)s * jj].real();
+      if (scaled) a /= ck;
+      amin = std::min(amin, a);
+      amax = std::max(amax, a);
+    }
+    if (!(amin > 16.0 * kEps * amax)) return false;
+  }
+  return true;
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+size_t tba_workspace_bytes(int64_t n, int64_t s, int64_t p, int m) {
+  return tba_ws_bytes(n, s, p, m);
+}
+
+int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
+              const double* C, double* X, const tsylv_opts& o, tsylv_info& info) {
+  auto t0 = std::chrono::steady_clock::now();
+  // The block Krylov space of one slice must fit in C^n: (m + 1) s <= n.
+  int m = o.m;
+  if ((int64_t)(m + 1) * s > n) m = (int)(n / s) - 1;
+  if (m < 1) throw Error(TSYLV_EINVAL, "TBA needs n >= 2 s");
+  hipStream_t st = ctx.stream;
+  Workspace ws(ctx.arena, tba_ws_bytes(n, s, p, m));
+  Setup S = setup_fourier(ctx, ws, n, s, p, A, B, C, X, o.x0_given != 0);
+  TbaWS w;
+  w.n = n;
+  w.s = s;
+  w.p = p;
+  w.N = n * s * p;
+  w.ldv = round_up(w.N, 64);
+  w.m = m;
+  w.ph = num_slices((int)p);
+  const int64_t ms = (int64_t)m * s, ns = n * s, ss = s * s;
+  w.R = ws.take<double>(w.N);
+  w.T = ws.take<double>(w.N);
+  w.basis = ws.take<double>((int64_t)(m + 1) * w.ldv);
+  w.G = ws.take<double>(p * ms * s);
+  w.Gq = ws.take<double>(p * ss);
+  w.Rinv = ws.take<double>(p * ss);
+  w.Y = ws.take<double>(p * ms * s);
+  w.partial = ws.take<double>(tba_partial_elems(n, s, p, m));
+  w.nchunks = kern::mdot_chunks(w.N);
+  w.part = ws.take<double>((int64_t)w.nchunks * 2);
+  w.d_ww = ws.take<double>(8);
+  const int ph = w.ph, si = (int)s, msi = (int)ms;
+
+  // Bhat (operator planes, unscaled) on the host for the projected solves.
+  std::vector<double> hB((size_t)p * ss);
+  TSYLV_HIP(hipMemcpyAsync(hB.data(), S.Bh, hB.size() * 8, hipMemcpyDeviceToHost, st));
+  const double cnorm = std::sqrt(dev_norm2(ctx, w, S.Zc));
+  info.steps = info.cycles = info.outer = 0;
+  info.res_hist_len = 0;
+  info.relres_est = 0.0;
+  if (cnorm == 0.0) {
+    TSYLV_HIP(hipMemsetAsync(X, 0, w.N * sizeof(double), st));
+    ctx.sync();
+    info.relres_true = 0.0;
+    info.status = TSYLV_OK;
+    info.seconds = seconds_since(t0);
+    return TSYLV_OK;
+  }
+  std::vector<std::vector<cplx>> Hk(ph, std::vector<cplx>((size_t)(ms + s) * ms));
+  std::vector<std::vector<cplx>> H0(ph, std::vector<cplx>((size_t)ss));
+  std::vector<std::vector<cplx>> Rq(ph, std::vector<cplx>((size_t)ss));
+  std::vector<double> hG((size_t)p * ms * s), hG2((size_t)p * ms * s), hY((size_t)p * ms * s, 0.0);
+  int status = TSYLV_NOT_CONVERGED;
+
+  for (int cycle = 0;; ++cycle) {
+    // R0 = C - M(X0) (Algorithm 8 step 2)
+    if (cycle == 0 && !o.x0_given) {
+      TSYLV_HIP(hipMemcpyAsync(w.R, S.Zc, w.N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    } else {
+      ProfScope ps(ctx, TSYLV_K_APPLY);
+      kern::apply_f64(S.Ah, S.Bh, S.Zx, w.R, S.Zc, -1.0, 1.0, n, s, (int)p, st);
+    }
+    info.relres_true = std::sqrt(dev_norm2(ctx, w, w.R)) / cnorm;
+    if (info.relres_true <= o.tol) {
+      status = TSYLV_OK;
+      break;
+    }
+    if (cycle >= o.max_cycles) break;
+    info.cycles++;
+    // Algorithm 7 step 2: [V_1, H0] = Tubal-QR(R0)
+    if (!tubal_qr(ctx, w, w.R, w.V(0), H0, true)) throw Error(TSYLV_EBREAKDOWN, "Tubal-QR(R0)");
+    for (auto& h : Hk) std::fill(h.begin(), h.end(), cplx(0.0));
+    for (int j = 0; j < m; ++j) {
+      const int64_t J = (int64_t)(j + 1) * s;
+      double* W = w.V(j + 1);
+      {
+        ProfScope ps(ctx, TSYLV_K_APPLY);
+        kern::apply_f64(S.Ah, nullptr, w.V(j), W, nullptr, 1.0, 0.0, n, s, (int)p, st);  // A only
+      }
+      // block CGS2: H_{0..j, j} = V^H W (twice), W -= V H
+      const kern::PMat Vb{w.basis, ns, n, s, w.ldv};
+      if (ctx.prof.on()) ctx.prof.begin(TSYLV_K_ORTHO, st);
+      for (int pass = 0; pass < 2; ++pass) {
+        kern::zgemm(Vb, true, kern::dense_pmat(W, ns, n), w.G, J * s, J, J, s, n, 1.0, 0.0,
+                    (int)p, w.partial, st);
+        kern::zgemm(Vb, false, kern::dense_pmat(w.G, J * s, J), W, ns, n, n, s, J, -1.0, 1.0,
+                    (int)p, nullptr, st);
+        std::vector<double>& dst = pass == 0 ? hG : hG2;
+        TSYLV_HIP(hipMemcpyAsync(dst.data(), w.G, (size_t)p * J * s * 8, hipMemcpyDeviceToHost, st));
+      }
+      if (ctx.prof.on()) ctx.prof.end(TSYLV_K_ORTHO, st);
+      ctx.sync();
+      const int Ji = (int)J;
+      parallel_slices(ph, [&](int k) {
+        std::vector<cplx> g1((size_t)Ji * si), g2((size_t)Ji * si);
+        unpack(hG, (int)p, k, Ji, si, g1.data());
+        unpack(hG2, (int)p, k, Ji, si, g2.data());
+        const int ldh = msi + si;
+        for (int c = 0; c < si; ++c)
+          for (int r = 0; r < Ji; ++r)
+            Hk[k][r + (size_t)ldh * (j * si + c)] = g1[r + (size_t)Ji * c] + g2[r + (size_t)Ji * c];
+      });
+      // Tubal-QR(W) -> V_{j+1}, H_{j+1,j}
+      const bool qr_ok = tubal_qr(ctx, w, W, W, Rq, false);
+      if (!qr_ok) {
+        if (j < m - 1) throw Error(TSYLV_EBREAKDOWN, "Tubal-QR in TBA");
+        for (auto& r : Rq) std::fill(r.begin(), r.end(), cplx(0.0));  // H_{m+1,m} = 0
+      }
+      for (int k = 0; k < ph; ++k) {
+        const int ldh = msi + si;
+        for (int c = 0; c < si; ++c)
+          for (int r = 0; r < si; ++r)
+            Hk[k][(size_t)(J + r) + (size_t)ldh * (j * si + c)] = Rq[k][r + (size_t)si * c];
+      }
+      info.steps++;
+    }
+    // Algorithm 8 step 3(b): H_m Y - Y B = [H0; 0] per slice (Algorithm 5 on the host)
+    std::vector<int> good(ph, 1);
+    double est2 = 0.0;
+    std::vector<double> est_k(ph, 0.0);
+    parallel_slices(ph, [&](int k) {
+      const int ldh = msi + si;
+      std::vector<cplx> Hm((size_t)msi * msi), Bk((size_t)si * si), C1((size_t)msi * si, 0.0),
+          Yk((size_t)msi * si);
+      for (int c = 0; c < msi; ++c)
+        for (int r = 0; r < msi; ++r) Hm[r + (size_t)msi * c] = Hk[k][r + (size_t)ldh * c];
+      unpack(hB, (int)p, k, si, si, Bk.data());
+      for (int c = 0; c < si; ++c)
+        for (int r = 0; r < si; ++r) C1[r + (size_t)msi * c] = H0[k][r + (size_t)si * c];
+      if (!host::sylvester_banded(Hm.data(), msi, si, Bk.data(), si, C1.data(), Yk.data())) {
+        good[k] = 0;
+        return;
+      }
+      pack(Yk.data(), (int)p, k, msi, si, hY);
+      // residual estimate: || H_{m+1,m} Y_m ||_F for this slice
+      double e = 0.0;
+      for (int c = 0; c < si; ++c)
+        for (int r = 0; r < si; ++r) {
+          cplx v = 0.0;
+          for (int l = 0; l < si; ++l)
+            v += Hk[k][(size_t)(msi + r) + (size_t)ldh * ((m - 1) * si + l)] *
+                 Yk[(size_t)((m - 1) * si + l) + (size_t)msi * c];
+          e += (k == 0 || 2 * k == (int)p) ? v.real() * v.real() : std::norm(v);
+        }
+      est_k[k] = e;
+    });
+    for (int k = 0; k < ph; ++k) {
+      if (!good[k]) throw Error(TSYLV_ESINGULAR, "projected Sylvester equation");
+      est2 += est_k[k];
+    }
+    info.relres_est = std::sqrt(est2) / cnorm;
+    if (o.res_hist && info.res_hist_len < o.res_hist_cap)
+      o.res_hist[info.res_hist_len++] = info.relres_est;
+    // Algorithm 8 step 3(c): X = X0 + V_m Y
+    TSYLV_HIP(hipMemcpyAsync(w.Y, hY.data(), hY.size() * 8, hipMemcpyHostToDevice, st));
+    kern::zgemm(kern::PMat{w.basis, ns, n, s, w.ldv}, false, kern::dense_pmat(w.Y, ms * s, ms),
+                S.Zx, ns, n, n, s, ms, 1.0, 1.0, (int)p, nullptr, st);
+    ctx.sync();
+  }
+  {
+    ProfScope ps(ctx, TSYLV_K_XFORM);
+    kern::tube_xform_f64(S.Zx, X, S.xf_inv, n * s, (int)p, st);
+  }
+  ctx.sync();
+  info.status = status;
+  info.seconds = seconds_since(t0);
+  return status;
+}
+
+}  // namespace tsylv

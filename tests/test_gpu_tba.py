@@ -1,0 +1,109 @@
+"""GPU parity of tsylv_tba (TBAS(m), Algorithm 8) against the oracle.
+
+Bars (FP64):
+  * one restart cycle: the Galerkin solution over the block Krylov space of
+    A and R0 is unique, so the GPU iterate (block CGS2, CholQR2, per-slice
+    Bartels-Stewart) equals the oracle's (block MGS, tubal MGS, spatial
+    t-Bartels-Stewart) to ~1e-9 relative, and so do the true residual and
+    the residual estimate of the proposition of section 5.2;
+  * converged solutions within 1e-8 of the Kronecker / t-BS solution;
+  * a right-hand side with a non-invertible tube makes Normalization break
+    down in both (oracle: Breakdown, GPU: TSYLV_EBREAKDOWN).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import krylov as kr
+from oracle import kron, tbs
+from paper_2405_09233_amd import workloads, tsylv
+from gpu_util import ctx, dev, host, say, rel
+
+
+def gpu_tba(A, B, C, **kw):
+    X, info = ctx().tba(dev(A), dev(B), dev(C), raise_on_error=False, **kw)
+    return host(X), info
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,s,p,m", [(24, 3, 3, 3), (20, 2, 4, 4), (18, 1, 2, 5), (30, 4, 1, 3),
+                                     (16, 2, 5, 2), (40, 5, 6, 3)])
+def test_one_cycle_matches_oracle(n, s, p, m):
+    say("tba one cycle", n, s, p, m)
+    A, B, C = workloads.dense_shifted(n, s, p, seed=n * 3 + p)
+    X, info = gpu_tba(A, B, C, m=m, tol=1e-300, max_cycles=1)
+    assert info.status == 1 and info.cycles == 1, info.as_dict()
+    Xo, io = kr.tbas(A, B, C, m=m, tol=1e-300, max_cycles=1)
+    assert rel(X, Xo) <= 1e-9
+    assert info.relres_true == pytest.approx(io["relres_true"], rel=1e-7)
+    assert info.relres_est == pytest.approx(io["est_hist"][0], rel=1e-6, abs=1e-14)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,s,p,m", [(24, 3, 3, 3), (30, 2, 2, 4), (21, 1, 4, 6), (36, 4, 5, 2)])
+def test_converged_vs_exact(n, s, p, m):
+    say("tba converged", n, s, p, m)
+    A, B, C = workloads.dense_shifted(n, s, p, seed=5 * n + s)
+    X, info = gpu_tba(A, B, C, m=m, tol=1e-11, max_cycles=300)
+    assert info.status == 0, info.as_dict()
+    assert info.relres_true <= 1e-11
+    Xk = kron.kron_solve(A, B, C) if n * s * p <= 700 else tbs.t_bartels_stewart(A, B, C)
+    assert rel(X, Xk) <= 1e-8
+    Xo, io = kr.tbas(A, B, C, m=m, tol=1e-11, max_cycles=300)
+    assert abs(info.cycles - io["cycles"]) <= 1
+
+
+@pytest.mark.gpu
+def test_convection_diffusion_vs_tbs():
+    say("tba cd 8x8, s=4, p=4")
+    A, B, C = workloads.convection_diffusion(8, 8, 4, 4, seed=2)
+    X, info = gpu_tba(A, B, C, m=6, tol=1e-11, max_cycles=200)
+    assert info.status == 0, info.as_dict()
+    assert rel(X, tbs.t_bartels_stewart(A, B, C)) <= 1e-8
+
+
+@pytest.mark.gpu
+def test_restart_length_clamped_to_space():
+    # (m + 1) s > n: the block Krylov space of a slice cannot exceed C^n
+    say("tba clamp")
+    A, B, C = workloads.dense_shifted(12, 4, 3, seed=4)
+    X, info = gpu_tba(A, B, C, m=10, tol=1e-11, max_cycles=200)
+    assert info.status == 0, info.as_dict()
+    assert rel(X, kron.kron_solve(A, B, C)) <= 1e-8
+
+
+@pytest.mark.gpu
+def test_normalization_breakdown():
+    say("tba breakdown")
+    A, B, C = workloads.dense_shifted(10, 2, 4, seed=8)
+    C = C.copy()
+    C[:, 0, :] = C[:, 0, :1]       # tube of column 0 constant: zero Fourier coefficients k > 0
+    with pytest.raises(kr.Breakdown):
+        kr.tbas(A, B, C, m=2, tol=1e-10, max_cycles=5)
+    X, info = gpu_tba(A, B, C, m=2, tol=1e-10, max_cycles=5)
+    assert info.status == -3
+
+
+@pytest.mark.gpu
+def test_invalid_sizes():
+    A, B, C = workloads.dense_shifted(5, 3, 2, seed=1)   # n < 2 s
+    X, info = gpu_tba(A, B, C, m=2)
+    assert info.status == -1
+
+
+@pytest.mark.gpu
+def test_medium_convection_diffusion():
+    """n = 1024 (32 x 32 grid), s = 16, p = 8, TBAS(4) to 1e-9; checked by the
+    true residual (recomputed by tsylv_apply) and against FP64 tGMRES."""
+    say("tba medium 1024/16/8")
+    A, B, C = workloads.convection_diffusion(32, 32, 16, 8, seed=0)
+    c = ctx()
+    Ad, Bd, Cd = dev(A), dev(B), dev(C)
+    X, info = c.tba(Ad, Bd, Cd, m=4, tol=1e-9, max_cycles=400)
+    say("cycles", info.cycles, "relres", info.relres_true, "s", info.seconds)
+    assert info.status == 0, info.as_dict()
+    R = C - host(c.apply(Ad, Bd, X))
+    assert np.linalg.norm(R) / np.linalg.norm(C) <= 1.05e-9
+    Xg, ig = c.gmres(Ad, Bd, Cd, m=30, tol=1e-11)
+    assert ig.status == 0
+    assert rel(host(X), host(Xg)) <= 1e-6
