@@ -46,6 +46,15 @@ bool opts_ok(const tsylv_opts& o) {
 
 void set_device(const tsylv_ctx* ctx) { TSYLV_HIP(hipSetDevice(ctx->c.device)); }
 
+// Early rejection: the info record (if any) still carries the status.
+int reject(tsylv_info* info, int status) {
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->status = status;
+  }
+  return status;
+}
+
 }  // namespace
 
 extern "C" {
@@ -145,11 +154,11 @@ int tsylv_apply(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A
 static int krylov_entry(int method, tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p,
                         const double* A, const double* B, const double* C, double* X,
                         const tsylv_opts* opts, tsylv_info* info) {
-  if (!ctx || !A || !B || !C || !X || !dims_ok(n, s, p)) return TSYLV_EINVAL;
+  if (!ctx || !A || !B || !C || !X || !dims_ok(n, s, p)) return reject(info, TSYLV_EINVAL);
   tsylv_opts o;
   tsylv_default_opts(method, &o);
   if (opts) o = *opts;
-  if (!opts_ok(o)) return TSYLV_EINVAL;
+  if (!opts_ok(o)) return reject(info, TSYLV_EINVAL);
   tsylv_info local;
   std::memset(&local, 0, sizeof(local));
   tsylv_info& inf = info ? *info : local;
@@ -176,11 +185,12 @@ int tsylv_gmres(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A
 
 int tsylv_tba(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
               const double* C, double* X, const tsylv_opts* opts, tsylv_info* info) {
-  if (!ctx || !A || !B || !C || !X || !dims_ok(n, s, p) || n < 2 * s) return TSYLV_EINVAL;
+  if (!ctx || !A || !B || !C || !X || !dims_ok(n, s, p) || n < 2 * s)
+    return reject(info, TSYLV_EINVAL);
   tsylv_opts o;
   tsylv_default_opts(TSYLV_METHOD_TBA, &o);
   if (opts) o = *opts;
-  if (!opts_ok(o)) return TSYLV_EINVAL;
+  if (!opts_ok(o) || o.refine) return reject(info, TSYLV_EINVAL);
   tsylv_info local;
   std::memset(&local, 0, sizeof(local));
   tsylv_info& inf = info ? *info : local;

@@ -11,8 +11,11 @@
 //   [V_{j+1}, H_{j+1,j}] = Tubal-QR(W)         (Algorithm 6)
 // Tubal-QR with the Normalization of section 5.1 read as the symmetric
 // positive tube (hat a_k = ||W_k||) is, slice by slice, the thin QR with a
-// real positive diagonal; we compute it as Cholesky QR done twice (CholQR2:
-// R = R2 R1 keeps that diagonal positive), which reaches the same factors.
+// real positive diagonal; we compute it by shifted Cholesky QR followed by
+// two plain Cholesky QR passes (shifted CholQR3: the shift keeps the first
+// Cholesky factorisation defined for blocks with condition numbers up to
+// about 1/eps, R = R3 R2 R1 keeps the diagonal positive), which reaches the
+// same factors as the tubal modified Gram-Schmidt of Algorithm 6.
 //
 // Representation: R and X are kept in the orthonormal scaled planes of the
 // Krylov solvers (slice k scaled by c_k = sqrt(w_k / p)); the basis blocks
@@ -116,19 +119,24 @@ double dev_norm2(Ctx& ctx, const TbaWS& w, const double* v) {
 }
 
 // Tubal-QR (Algorithm 6) of the n x s block in `Win`, slice by slice, by
-// CholQR2: Qout receives the orthonormal slices, Rk[k] (s x s, upper
-// triangular, real positive diagonal) the R factor of slice k.  `unscale`
-// multiplies the diagonal by 1/c_k for the tube test (Win in scaled planes).
-// Returns false on a non-invertible tube (Normalization breakdown).
+// shifted CholQR3: Qout receives the orthonormal slices, Rk[k] (s x s, upper
+// triangular, real positive diagonal) the R factor of slice k.  With
+// `scaled` the block is in scaled planes and the diagonal is divided by c_k
+// for the tube test.  Returns false on a non-invertible tube (Normalization
+// breakdown).
 bool tubal_qr(Ctx& ctx, const TbaWS& w, const double* Win, double* Qout,
               std::vector<std::vector<cplx>>& Rk, bool scaled) {
   const int s = (int)w.s, p = (int)w.p, ph = w.ph;
   const int64_t n = w.n, ns = n * w.s, ss = w.s * w.s;
   std::vector<double> hbuf((size_t)p * ss);
-  std::vector<std::vector<cplx>> R1(ph, std::vector<cplx>((size_t)s * s));
+  std::vector<std::vector<cplx>> Racc(ph, std::vector<cplx>((size_t)s * s));
   bool ok = true;
   const double* src = Win;
-  for (int pass = 0; pass < 2; ++pass) {
+  constexpr int kPasses = 3;
+  // Shift of the first pass (Fukaya et al., shifted CholeskyQR):
+  // sigma = 11 (n s + s (s + 1)) u ||W_k||_2^2, with trace(G_k) >= ||W_k||_2^2.
+  const double shift_factor = 11.0 * ((double)n * s + (double)s * (s + 1)) * kEps;
+  for (int pass = 0; pass < kPasses; ++pass) {
     // Gram of every slice: W_k^H W_k
     kern::zgemm(kern::dense_pmat(src, ns, n), true, kern::dense_pmat(src, ns, n), w.Gq, ss,
                 w.s, w.s, w.s, n, 1.0, 0.0, p, w.partial, ctx.stream);
@@ -139,27 +147,40 @@ bool tubal_qr(Ctx& ctx, const TbaWS& w, const double* Win, double* Qout,
     parallel_slices(ph, [&](int k) {
       std::vector<cplx> G((size_t)s * s), Ri((size_t)s * s);
       unpack(hbuf, p, k, s, s, G.data());
+      if (pass == 0) {
+        double tr = 0.0;
+        for (int i = 0; i < s; ++i) tr += G[i + (size_t)s * i].real();
+        for (int i = 0; i < s; ++i) G[i + (size_t)s * i] += shift_factor * tr;
+      }
       if (!host::cholesky_upper(G.data(), s, 1e3 * kEps * kEps)) {
         good[k] = 0;
         return;
       }
       host::tri_inv_upper(G.data(), Ri.data(), s);
       pack(Ri.data(), p, k, s, s, rinv);  // writes only this slice's planes
-      if (pass == 0)
-        R1[k] = G;
-      else
-        host::matmul(G.data(), R1[k].data(), Rk[k].data(), s, s, s);  // R = R2 R1
+      if (pass == 0) {
+        Racc[k] = G;
+      } else {
+        std::vector<cplx> t((size_t)s * s);
+        host::matmul(G.data(), Racc[k].data(), t.data(), s, s, s);  // R = R_pass ... R_1
+        Racc[k] = t;
+      }
     });
     for (int k = 0; k < ph; ++k) ok = ok && good[k];
     if (!ok) return false;
     TSYLV_HIP(hipMemcpyAsync(w.Rinv, rinv.data(), rinv.size() * 8, hipMemcpyHostToDevice,
                              ctx.stream));
-    double* dst = (pass == 0) ? w.T : Qout;
+    // passes alternate between the two buffers and end in Qout
+    double* dst = ((kPasses - 1 - pass) % 2 == 0) ? Qout : w.T;
+    if (dst == src) dst = (dst == w.T) ? Qout : w.T;
     kern::zgemm(kern::dense_pmat(src, ns, n), false, kern::dense_pmat(w.Rinv, ss, w.s), dst, ns, n,
                 n, w.s, w.s, 1.0, 0.0, p, nullptr, ctx.stream);
     ctx.sync();  // rinv (host) must outlive the copy
-    src = w.T;
+    src = dst;
   }
+  if (src != Qout)
+    TSYLV_HIP(hipMemcpyAsync(Qout, src, w.N * sizeof(double), hipMemcpyDeviceToDevice, ctx.stream));
+  for (int k = 0; k < ph; ++k) Rk[k] = Racc[k];
   // Tube test of the Normalization: hat a_k = R_k(jj, jj) (/ c_k in scaled planes)
   for (int jj = 0; jj < s; ++jj) {
     double amin = INFINITY, amax = 0.0;

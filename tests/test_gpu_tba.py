@@ -2,7 +2,7 @@
 
 Bars (FP64):
   * one restart cycle: the Galerkin solution over the block Krylov space of
-    A and R0 is unique, so the GPU iterate (block CGS2, CholQR2, per-slice
+    A and R0 is unique, so the GPU iterate (block CGS2, shifted CholQR3, per-slice
     Bartels-Stewart) equals the oracle's (block MGS, tubal MGS, spatial
     t-Bartels-Stewart) to ~1e-9 relative, and so do the true residual and
     the residual estimate of the proposition of section 5.2;
@@ -92,14 +92,16 @@ def test_invalid_sizes():
 
 
 @pytest.mark.gpu
-def test_medium_convection_diffusion():
-    """n = 1024 (32 x 32 grid), s = 16, p = 8, TBAS(4) to 1e-9; checked by the
-    true residual (recomputed by tsylv_apply) and against FP64 tGMRES."""
-    say("tba medium 1024/16/8")
+@pytest.mark.parametrize("m", [4, 8])
+def test_medium_convection_diffusion(m):
+    """n = 1024 (32 x 32 grid), s = 16, p = 8 (the Gram products take the
+    split-K path), TBAS(m) to 1e-9; checked by the true residual (recomputed
+    by tsylv_apply) and against FP64 tGMRES."""
+    say("tba medium 1024/16/8 m", m)
     A, B, C = workloads.convection_diffusion(32, 32, 16, 8, seed=0)
     c = ctx()
     Ad, Bd, Cd = dev(A), dev(B), dev(C)
-    X, info = c.tba(Ad, Bd, Cd, m=4, tol=1e-9, max_cycles=400)
+    X, info = c.tba(Ad, Bd, Cd, m=m, tol=1e-9, max_cycles=400)
     say("cycles", info.cycles, "relres", info.relres_true, "s", info.seconds)
     assert info.status == 0, info.as_dict()
     R = C - host(c.apply(Ad, Bd, X))
@@ -107,3 +109,14 @@ def test_medium_convection_diffusion():
     Xg, ig = c.gmres(Ad, Bd, Cd, m=30, tol=1e-11)
     assert ig.status == 0
     assert rel(host(X), host(Xg)) <= 1e-6
+
+
+@pytest.mark.gpu
+def test_medium_dense_vs_tbs():
+    """n = 512, s = 16, p = 4 dense operator: converged TBAS(4) against the
+    oracle's t-Bartels-Stewart solution."""
+    say("tba dense 512/16/4")
+    A, B, C = workloads.dense_shifted(512, 16, 4, seed=3)
+    X, info = gpu_tba(A, B, C, m=4, tol=1e-11, max_cycles=100)
+    assert info.status == 0, info.as_dict()
+    assert rel(X, tbs.t_bartels_stewart(A, B, C)) <= 1e-8
