@@ -3,6 +3,7 @@
 #include <new>
 
 #include "runtime.hpp"
+#include "serve.hpp"
 #include "solvers.hpp"
 
 using namespace tsylv;
@@ -115,6 +116,11 @@ int tsylv_destroy(tsylv_ctx* ctx) {
   if (!ctx) return TSYLV_EINVAL;
   return guarded([&]() {
     set_device(ctx);
+    {
+      std::lock_guard<std::mutex> g(ctx->c.sched_mu);
+      if (ctx->c.sched) scheduler_destroy(ctx->c.sched);
+      ctx->c.sched = nullptr;
+    }
     (void)hipStreamSynchronize(ctx->c.stream);
     if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
     if (ctx->c.owns_arena) (void)hipFree(ctx->c.arena_ptr);
@@ -205,13 +211,30 @@ int tsylv_tba(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A, 
 }
 
 int tsylv_submit(tsylv_ctx* ctx, const tsylv_request* req, uint64_t* ticket) {
-  (void)ctx; (void)req; (void)ticket;
-  return TSYLV_EINVAL;
+  if (!ctx || !req || !ticket) return TSYLV_EINVAL;
+  const tsylv_request& r = *req;
+  if (!r.A || !r.B || !r.C || !r.X || !dims_ok(r.n, r.s, r.p)) return TSYLV_EINVAL;
+  if (r.method != TSYLV_METHOD_GMRES && r.method != TSYLV_METHOD_FOM) return TSYLV_EINVAL;
+  if (!opts_ok(r.opts)) return TSYLV_EINVAL;
+  if (r.opts.res_hist) return TSYLV_EINVAL;  // no host history buffers across threads
+  return guarded([&]() {
+    std::lock_guard<std::mutex> g(ctx->c.sched_mu);
+    if (!ctx->c.sched) {
+      set_device(ctx);
+      ctx->c.sched = scheduler_create(ctx->c);
+    }
+    *ticket = scheduler_submit(ctx->c.sched, r);
+    return (int)TSYLV_OK;
+  });
 }
 
 int tsylv_poll(tsylv_ctx* ctx, uint64_t ticket, tsylv_info* info) {
-  (void)ctx; (void)ticket; (void)info;
-  return TSYLV_EINVAL;
+  if (!ctx) return TSYLV_EINVAL;
+  return guarded([&]() {
+    std::lock_guard<std::mutex> g(ctx->c.sched_mu);
+    if (!ctx->c.sched) return (int)TSYLV_EINVAL;
+    return scheduler_poll(ctx->c.sched, ticket, info);
+  });
 }
 
 int tsylv_profile(tsylv_ctx* ctx, int enable) {

@@ -90,7 +90,8 @@ struct Ctx {
   // pinned host staging for small device->host results
   double* pinned = nullptr;
   size_t pinned_count = 0;
-  Scheduler* sched = nullptr;
+  Scheduler* sched = nullptr;  // created by the first tsylv_submit
+  std::mutex sched_mu;
   std::mutex sync_mu;  // serialises synchronous calls on the context
   Profiler prof;
 
@@ -98,15 +99,19 @@ struct Ctx {
   void sync() { TSYLV_HIP(hipStreamSynchronize(stream)); }
 };
 
-// Brackets one kernel launch with profiling events when profiling is on.
+// Brackets kernel launches on stream `st` with profiling events when
+// profiling is on and `enabled` (the serving loop's tasks never time).
 struct ProfScope {
   Ctx& c;
   int kid;
-  ProfScope(Ctx& ctx, int k) : c(ctx), kid(k) {
-    if (c.prof.on()) c.prof.begin(kid, c.stream);
+  hipStream_t st;
+  bool on;
+  ProfScope(Ctx& ctx, int k, hipStream_t s, bool enabled = true)
+      : c(ctx), kid(k), st(s), on(enabled && ctx.prof.on()) {
+    if (on) c.prof.begin(kid, st);
   }
   ~ProfScope() {
-    if (c.prof.on()) c.prof.end(kid, c.stream);
+    if (on) c.prof.end(kid, st);
   }
 };
 

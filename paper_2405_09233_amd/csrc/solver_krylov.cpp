@@ -34,13 +34,19 @@
 // problem stays FP64.  This is iterative refinement whose inner solver is
 // one restart cycle, so it converges like restarted tGMRES as long as the
 // low-precision operator error is small against each cycle's reduction.
+//
+// The solve is a resumable state machine (krylov_task.hpp): SETUP (DFTs,
+// ||C||), RESTART (X += V y of the last cycle, R = C - M(X), ||R||), STEP
+// (one Arnoldi step), FINAL (inverse DFT).  Each phase enqueues its kernels
+// and one small device-to-host copy; the host logic runs after the stream
+// is synchronised.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
-#include <functional>
 #include <vector>
 
 #include "kernels.hpp"
+#include "krylov_task.hpp"
 #include "runtime.hpp"
 #include "solvers.hpp"
 
@@ -63,21 +69,6 @@ struct Operator {
   int low = TSYLV_FP32;  // precision of the float-vector applies
 };
 
-void op_apply(Ctx& ctx, const Operator& op, const double* V, double* out, const double* Y,
-              double alpha, double beta) {
-  ProfScope ps(ctx, TSYLV_K_APPLY);
-  kern::apply_f64(op.Ah64, op.Bh64, V, out, Y, alpha, beta, op.n, op.s, (int)op.p, ctx.stream);
-}
-
-void op_apply(Ctx& ctx, const Operator& op, const float* V, float* out, const float* Y,
-              double alpha, double beta) {
-  ProfScope ps(ctx, TSYLV_K_APPLY_LOW);
-  if (op.low == TSYLV_BF16)
-    kern::apply_bf16(op.Ahb, op.Bhb, V, out, Y, alpha, beta, op.n, op.s, (int)op.p, ctx.stream);
-  else
-    kern::apply_f32(op.Ah32, op.Bh32, V, out, Y, alpha, beta, op.n, op.s, (int)op.p, ctx.stream);
-}
-
 // Reduction buffers shared by the norm and dot kernels.
 struct RedBuf {
   double* part = nullptr;
@@ -85,16 +76,6 @@ struct RedBuf {
   double* d_ww = nullptr;
   double* h_ww = nullptr;
 };
-
-// ||v||^2 of one FP64 or FP32 vector, to the host.
-template <typename TV>
-double norm2(Ctx& ctx, const RedBuf& r, const TV* v, int64_t N) {
-  kern::mdot_partial((const TV*)nullptr, 0, 0, v, N, r.part, r.ldp, 1, ctx.stream);
-  kern::reduce_partials(r.part, r.nchunks, r.ldp, 1, r.d_ww, ctx.stream);
-  TSYLV_HIP(hipMemcpyAsync(r.h_ww, r.d_ww, sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
-  ctx.sync();
-  return r.h_ww[0];
-}
 
 // Device and pinned buffers of one Arnoldi cycle with basis type TV.
 template <typename TV>
@@ -136,7 +117,12 @@ struct CycleWS {
 struct Givens {
   std::vector<double> c, s, g;
   std::vector<std::vector<double>> R;  // R[j] = column j (j+1 entries)
-  explicit Givens(double beta) { g.push_back(beta); }
+  void reset(double beta) {
+    c.clear();
+    s.clear();
+    R.clear();
+    g.assign(1, beta);
+  }
   // Adds column h[0..j+1] (j = current size) and returns |gamma_{j+2}|.
   double add(std::vector<double> h) {
     const size_t j = R.size();
@@ -215,96 +201,15 @@ bool fom_solve(const std::vector<std::vector<double>>& Hcols, size_t k, double b
   return true;
 }
 
-struct CycleOut {
-  std::vector<double> y;  // coefficients of X += V_k (*) y
-  size_t k = 0;           // steps taken
-  double est = 0.0;       // last residual estimate (absolute)
-  bool fom_fallback = false;
-};
-
-// One restart cycle of Algorithm 3 (steps 4(a)-(b)): up to m steps of
-// tArnoldi on the normalised start vector in w.V(0), stopping early when the
-// residual estimate drops to stop_abs or on a happy breakdown.
-template <typename TV>
-CycleOut arnoldi_cycle(Ctx& ctx, int method, const Operator& op, CycleWS<TV>& w, int64_t N,
-                       double beta, double stop_abs, int m,
-                       const std::function<void(double)>& record) {
-  hipStream_t st = ctx.stream;
-  const RedBuf& r = w.red;
-  Givens giv(beta);
-  std::vector<std::vector<double>> Hcols;
-  std::vector<double> y_fom;
-  bool fom_ok = false;
-  CycleOut out;
-  for (int j = 0; j < m; ++j) {
-    const int nv = j + 1;
-    TV* W = w.V(j + 1);
-    // Algorithm 2 step 3(a): W = M(V_j)
-    op_apply(ctx, op, (const TV*)w.V(j), W, (const TV*)nullptr, 1.0, 0.0);
-    // step 3(b), CGS2: two passes of h = V^T W, W -= V h
-    if (ctx.prof.on()) ctx.prof.begin(TSYLV_K_ORTHO, st);
-    kern::mdot_partial((const TV*)w.basis, w.ldv, nv, (const TV*)W, N, r.part, r.ldp, 1, st);
-    kern::reduce_partials(r.part, r.nchunks, r.ldp, nv + 1, w.d_h1, st);
-    kern::mupdate((const TV*)w.basis, w.ldv, nv, w.d_h1, W, N, st);
-    kern::mdot_partial((const TV*)w.basis, w.ldv, nv, (const TV*)W, N, r.part, r.ldp, 0, st);
-    kern::reduce_partials(r.part, r.nchunks, r.ldp, nv, w.d_h2, st);
-    kern::mupdate((const TV*)w.basis, w.ldv, nv, w.d_h2, W, N, st);
-    // step 3(d): h_{j+1,j} = ||W||_F
-    kern::mdot_partial((const TV*)nullptr, 0, 0, (const TV*)W, N, r.part, r.ldp, 1, st);
-    kern::reduce_partials(r.part, r.nchunks, r.ldp, 1, r.d_ww, st);
-    if (ctx.prof.on()) ctx.prof.end(TSYLV_K_ORTHO, st);
-    TSYLV_HIP(hipMemcpyAsync(w.h_h1, w.d_h1, (nv + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
-    TSYLV_HIP(hipMemcpyAsync(w.h_h2, w.d_h2, nv * sizeof(double), hipMemcpyDeviceToHost, st));
-    TSYLV_HIP(hipMemcpyAsync(r.h_ww, r.d_ww, sizeof(double), hipMemcpyDeviceToHost, st));
-    ctx.sync();
-    std::vector<double> h(nv + 1);
-    for (int i = 0; i < nv; ++i) h[i] = w.h_h1[i] + w.h_h2[i];
-    const double w0 = std::sqrt(w.h_h1[nv]);
-    double hn = std::sqrt(r.h_ww[0]);
-    const bool breakdown = !(hn > 16.0 * kEps * w0);
-    if (breakdown) hn = 0.0;
-    h[nv] = hn;
-    out.k = (size_t)nv;
-    double est;
-    if (method == TSYLV_METHOD_GMRES) {
-      est = giv.add(h);
-    } else {
-      giv.add(h);  // keeps the tGMRES fallback available
-      Hcols.push_back(h);
-      fom_ok = fom_solve(Hcols, out.k, beta, y_fom);
-      est = fom_ok ? hn * std::fabs(y_fom[out.k - 1]) : INFINITY;
-    }
-    out.est = est;
-    record(est);
-    if (breakdown || est <= stop_abs) break;
-    // step 3(e): V_{j+1} = W / h_{j+1,j}
-    kern::scale((const TV*)W, W, 1.0 / hn, N, st);
-  }
-  // Algorithm 3 step 4(b): the small problem.
-  if (method == TSYLV_METHOD_GMRES) {
-    out.y = giv.solve(out.k);
-  } else if (fom_ok) {
-    out.y = y_fom;
-  } else {
-    out.fom_fallback = true;
-    out.y = giv.solve(out.k);
-  }
-  return out;
-}
-
-// Adds V_k (*) y to X (Algorithm 3 step 4(c)); X is FP64, V of type TV.
-template <typename TV>
-void add_combination(Ctx& ctx, CycleWS<TV>& w, const CycleOut& c, double* X, int64_t N) {
-  for (size_t i = 0; i < c.k; ++i) w.h_y[i] = -c.y[i];
-  TSYLV_HIP(hipMemcpyAsync(w.d_y, w.h_y, c.k * sizeof(double), hipMemcpyHostToDevice, ctx.stream));
-  kern::mupdate((const TV*)w.basis, w.ldv, (int)c.k, w.d_y, X, N, ctx.stream);
-}
-
 double seconds_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Fourier setup shared with the TBA driver
+// ---------------------------------------------------------------------------
 
 size_t setup_bytes(int64_t n, int64_t s, int64_t p) {
   const int64_t N = n * s * p;
@@ -314,9 +219,9 @@ size_t setup_bytes(int64_t n, int64_t s, int64_t p) {
 
 // Algorithm 1 step 1 for the operator (unscaled DFT planes of A and B) and
 // the orthonormal planes of C and X0.
-Setup setup_fourier(Ctx& ctx, Workspace& ws, int64_t n, int64_t s, int64_t p, const double* A,
-                    const double* B, const double* C, const double* X, bool x0_given) {
-  hipStream_t st = ctx.stream;
+Setup setup_fourier(Ctx& ctx, hipStream_t st, bool profile, Workspace& ws, int64_t n, int64_t s,
+                    int64_t p, const double* A, const double* B, const double* C, const double* X,
+                    bool x0_given) {
   const int64_t N = n * s * p;
   Setup S;
   S.Ah = ws.take<double>(p * n * n);
@@ -330,7 +235,7 @@ Setup setup_fourier(Ctx& ctx, Workspace& ws, int64_t n, int64_t s, int64_t p, co
   kern::build_xform(S.xf_fwd, (int)p, XF_FORWARD, st);
   kern::build_xform(S.xf_inv, (int)p, XF_INVERSE, st);
   {
-    ProfScope ps(ctx, TSYLV_K_XFORM);
+    ProfScope ps(ctx, TSYLV_K_XFORM, st, profile);
     kern::tube_xform_f64(A, S.Ah, S.xf_op, n * n, (int)p, st);
   }
   kern::tube_xform_f64(B, S.Bh, S.xf_op, s * s, (int)p, st);
@@ -355,118 +260,321 @@ size_t krylov_workspace_bytes(int64_t n, int64_t s, int64_t p, const tsylv_opts&
   return b;
 }
 
-int krylov_solve(Ctx& ctx, int method, int64_t n, int64_t s, int64_t p, const double* A,
-                 const double* B, const double* C, double* X, const tsylv_opts& o,
-                 tsylv_info& info) {
-  auto t0 = std::chrono::steady_clock::now();
-  const bool refine = o.refine != 0;
-  const int64_t N = n * s * p;
-  hipStream_t st = ctx.stream;
-  Workspace ws(ctx.arena, krylov_workspace_bytes(n, s, p, o));
-  Setup S = setup_fourier(ctx, ws, n, s, p, A, B, C, X, o.x0_given != 0);
-  Operator op;
-  op.n = n;
-  op.s = s;
-  op.p = p;
-  op.Ah64 = S.Ah;
-  op.Bh64 = S.Bh;
+// ---------------------------------------------------------------------------
+// The resumable solve
+// ---------------------------------------------------------------------------
 
+struct KrylovState {
+  enum Phase { SETUP, RESTART, STEP, FINAL, DONE };
+
+  Ctx& ctx;
+  hipStream_t st;
+  bool prof;
+  int method;
+  int64_t n, s, p, N;
+  double* X;
+  tsylv_opts o;
+  bool refine;
+  Workspace ws;
+  Setup S;
+  Operator op;
   CycleWS<double> w64;
   CycleWS<float> w32;
   double* R64 = nullptr;
-  const int m_cycle = refine ? o.inner_m : o.m;
-  double* host = ctx.host_buffer(4 * (size_t)(m_cycle + 2));
-  if (!refine) {
-    w64.carve(ws, N, o.m, host);
-  } else {
-    R64 = ws.take<double>(N);
-    w32.carve(ws, N, o.inner_m, host);
-    op.low = o.prec == TSYLV_BF16 ? TSYLV_BF16 : TSYLV_FP32;
-    if (op.low == TSYLV_BF16) {
-      uint16_t* Ab = ws.take<uint16_t>(p * n * n);
-      uint16_t* Bb = ws.take<uint16_t>(p * s * s);
-      kern::convert_f64_bf16(S.Ah, Ab, p * n * n, st);
-      kern::convert_f64_bf16(S.Bh, Bb, p * s * s, st);
-      op.Ahb = Ab;
-      op.Bhb = Bb;
-    } else {
-      float* Af = ws.take<float>(p * n * n);
-      float* Bf = ws.take<float>(p * s * s);
-      kern::convert_f64_f32(S.Ah, Af, p * n * n, st);
-      kern::convert_f64_f32(S.Bh, Bf, p * s * s, st);
-      op.Ah32 = Af;
-      op.Bh32 = Bf;
-    }
-  }
-  const RedBuf& red = refine ? w32.red : w64.red;
+  RedBuf* red = nullptr;
 
-  // ||C||_F (Parseval: the planes of C are orthonormal coordinates)
-  const double cnorm = std::sqrt(norm2<double>(ctx, red, S.Zc, N));
-  info.steps = info.cycles = info.outer = 0;
-  info.relres_est = 0.0;
-  info.res_hist_len = 0;
-  info.fom_fallback = 0;
-  auto record = [&](double est_abs) {
-    double est = est_abs / cnorm;
-    info.relres_est = est;
-    if (o.res_hist && info.res_hist_len < o.res_hist_cap) o.res_hist[info.res_hist_len++] = est;
-  };
-
-  if (cnorm == 0.0) {
-    TSYLV_HIP(hipMemsetAsync(X, 0, N * sizeof(double), st));
-    ctx.sync();
-    info.relres_true = 0.0;
-    info.status = TSYLV_OK;
-    info.seconds = seconds_since(t0);
-    return TSYLV_OK;
-  }
-
+  Phase phase = SETUP;
   int status = TSYLV_NOT_CONVERGED;
-  const int max_iter = refine ? o.max_outer : o.max_cycles;
-  for (int it = 0;; ++it) {
-    // R0 = C - M(X0)  (Algorithm 3, step 3), in FP64.
-    double* R = refine ? R64 : w64.V(0);
-    if (it == 0 && !o.x0_given)
-      TSYLV_HIP(hipMemcpyAsync(R, S.Zc, N * sizeof(double), hipMemcpyDeviceToDevice, st));
-    else
-      op_apply(ctx, op, (const double*)S.Zx, R, (const double*)S.Zc, -1.0, 1.0);
-    const double beta = std::sqrt(norm2<double>(ctx, red, R, N));
-    info.relres_true = beta / cnorm;
-    if (info.relres_true <= o.tol) {
-      status = TSYLV_OK;
-      break;
-    }
-    if (it >= max_iter) break;
-    info.cycles++;
+  tsylv_info info{};
+  std::chrono::steady_clock::time_point t0;
+  double cnorm = 0.0, beta = 0.0;
+  int iter = 0;               // restart cycles / refinement steps started
+  int j = 0;                  // Arnoldi step inside the cycle
+  double pending_scale = 0;   // 1 / h of the previous step (0: none)
+  bool scale_v0 = false;
+  int pending_update = 0;     // basis vectors to combine into X before the next residual
+  Givens giv;
+  std::vector<std::vector<double>> Hcols;
+  std::vector<double> y_fom;
+  bool fom_ok = false;
+
+  KrylovState(Ctx& c, hipStream_t stream, bool profile, double* pinned, int meth, int64_t n_,
+              int64_t s_, int64_t p_, const double* A, const double* B, const double* C,
+              double* X_, const tsylv_opts& opts)
+      : ctx(c), st(stream), prof(profile), method(meth), n(n_), s(s_), p(p_), N(n_ * s_ * p_),
+        X(X_), o(opts), refine(opts.refine != 0),
+        ws(c.arena, krylov_workspace_bytes(n_, s_, p_, opts)) {
+    t0 = std::chrono::steady_clock::now();
+    info.status = TSYLV_PENDING;
+    S = setup_fourier(ctx, st, prof, ws, n, s, p, A, B, C, X, o.x0_given != 0);
+    op.n = n;
+    op.s = s;
+    op.p = p;
+    op.Ah64 = S.Ah;
+    op.Bh64 = S.Bh;
     if (!refine) {
-      kern::scale((const double*)R, R, 1.0 / beta, N, st);
-      CycleOut c = arnoldi_cycle<double>(ctx, method, op, w64, N, beta, o.tol * cnorm, o.m, record);
-      info.steps += (int)c.k;
-      info.fom_fallback += c.fom_fallback ? 1 : 0;
-      add_combination(ctx, w64, c, S.Zx, N);
+      w64.carve(ws, N, o.m, pinned);
+      red = &w64.red;
     } else {
-      info.outer++;
-      kern::scale((const double*)R, w32.V(0), 1.0 / beta, N, st);  // rounds to FP32
-      const double stop = std::max(o.inner_tol * beta, 0.5 * o.tol * cnorm);
-      CycleOut c = arnoldi_cycle<float>(ctx, method, op, w32, N, beta, stop, o.inner_m, record);
-      info.steps += (int)c.k;
-      info.fom_fallback += c.fom_fallback ? 1 : 0;
-      add_combination(ctx, w32, c, S.Zx, N);
+      R64 = ws.take<double>(N);
+      w32.carve(ws, N, o.inner_m, pinned);
+      red = &w32.red;
+      op.low = o.prec == TSYLV_BF16 ? TSYLV_BF16 : TSYLV_FP32;
+      if (op.low == TSYLV_BF16) {
+        uint16_t* Ab = ws.take<uint16_t>(p * n * n);
+        uint16_t* Bb = ws.take<uint16_t>(p * s * s);
+        kern::convert_f64_bf16(S.Ah, Ab, p * n * n, st);
+        kern::convert_f64_bf16(S.Bh, Bb, p * s * s, st);
+        op.Ahb = Ab;
+        op.Bhb = Bb;
+      } else {
+        float* Af = ws.take<float>(p * n * n);
+        float* Bf = ws.take<float>(p * s * s);
+        kern::convert_f64_f32(S.Ah, Af, p * n * n, st);
+        kern::convert_f64_f32(S.Bh, Bf, p * s * s, st);
+        op.Ah32 = Af;
+        op.Bh32 = Bf;
+      }
     }
   }
-  // Algorithm 1 step 3: back to the spatial domain.
-  {
-    ProfScope ps(ctx, TSYLV_K_XFORM);
-    kern::tube_xform_f64(S.Zx, X, S.xf_inv, n * s, (int)p, st);
+
+  void apply(const double* V, double* out, const double* Y, double alpha, double beta_) {
+    ProfScope ps(ctx, TSYLV_K_APPLY, st, prof);
+    kern::apply_f64(op.Ah64, op.Bh64, V, out, Y, alpha, beta_, n, s, (int)p, st);
   }
-  ctx.sync();
-  info.status = status;
-  info.seconds = seconds_since(t0);
-  return status;
+  void apply(const float* V, float* out, const float* Y, double alpha, double beta_) {
+    ProfScope ps(ctx, TSYLV_K_APPLY_LOW, st, prof);
+    if (op.low == TSYLV_BF16)
+      kern::apply_bf16(op.Ahb, op.Bhb, V, out, Y, alpha, beta_, n, s, (int)p, st);
+    else
+      kern::apply_f32(op.Ah32, op.Bh32, V, out, Y, alpha, beta_, n, s, (int)p, st);
+  }
+
+  // ||v||^2 to red->h_ww[0] after the next synchronisation.
+  void enqueue_norm2(const double* v) {
+    kern::mdot_partial((const double*)nullptr, 0, 0, v, N, red->part, red->ldp, 1, st);
+    kern::reduce_partials(red->part, red->nchunks, red->ldp, 1, red->d_ww, st);
+    TSYLV_HIP(hipMemcpyAsync(red->h_ww, red->d_ww, sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+
+  // Algorithm 2 step 3 for the current j: W = M(V_j), CGS2, ||W||.
+  template <typename TV>
+  void enqueue_step(CycleWS<TV>& w) {
+    const int nv = j + 1;
+    TV* W = w.V(j + 1);
+    if (pending_scale != 0.0) {  // step 3(e) of the previous step: V_j = W / h_{j,j-1}
+      kern::scale((const TV*)w.V(j), w.V(j), pending_scale, N, st);
+      pending_scale = 0.0;
+    }
+    apply((const TV*)w.V(j), W, (const TV*)nullptr, 1.0, 0.0);
+    const RedBuf& r = w.red;
+    ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
+    kern::mdot_partial((const TV*)w.basis, w.ldv, nv, (const TV*)W, N, r.part, r.ldp, 1, st);
+    kern::reduce_partials(r.part, r.nchunks, r.ldp, nv + 1, w.d_h1, st);
+    kern::mupdate((const TV*)w.basis, w.ldv, nv, w.d_h1, W, N, st);
+    kern::mdot_partial((const TV*)w.basis, w.ldv, nv, (const TV*)W, N, r.part, r.ldp, 0, st);
+    kern::reduce_partials(r.part, r.nchunks, r.ldp, nv, w.d_h2, st);
+    kern::mupdate((const TV*)w.basis, w.ldv, nv, w.d_h2, W, N, st);
+    kern::mdot_partial((const TV*)nullptr, 0, 0, (const TV*)W, N, r.part, r.ldp, 1, st);
+    kern::reduce_partials(r.part, r.nchunks, r.ldp, 1, r.d_ww, st);
+    TSYLV_HIP(hipMemcpyAsync(w.h_h1, w.d_h1, (nv + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+    TSYLV_HIP(hipMemcpyAsync(w.h_h2, w.d_h2, nv * sizeof(double), hipMemcpyDeviceToHost, st));
+    TSYLV_HIP(hipMemcpyAsync(r.h_ww, r.d_ww, sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+
+  // Consumes a step's h column; returns true when the cycle ends.
+  template <typename TV>
+  bool complete_step(CycleWS<TV>& w, double stop_abs) {
+    const int nv = j + 1;
+    std::vector<double> h(nv + 1);
+    for (int i = 0; i < nv; ++i) h[i] = w.h_h1[i] + w.h_h2[i];
+    const double w0 = std::sqrt(w.h_h1[nv]);
+    double hn = std::sqrt(w.red.h_ww[0]);
+    const bool breakdown = !(hn > 16.0 * kEps * w0);  // reading: h_{j+1,j} = 0
+    if (breakdown) hn = 0.0;
+    h[nv] = hn;
+    info.steps++;
+    double est;
+    if (method == TSYLV_METHOD_GMRES) {
+      est = giv.add(h);
+    } else {
+      giv.add(h);  // keeps the tGMRES fallback available
+      Hcols.push_back(h);
+      fom_ok = fom_solve(Hcols, (size_t)nv, beta, y_fom);
+      est = fom_ok ? hn * std::fabs(y_fom[nv - 1]) : INFINITY;
+    }
+    info.relres_est = est / cnorm;
+    if (o.res_hist && info.res_hist_len < o.res_hist_cap)
+      o.res_hist[info.res_hist_len++] = info.relres_est;
+    const int mcyc = refine ? o.inner_m : o.m;
+    if (breakdown || est <= stop_abs || nv >= mcyc) {
+      // Algorithm 3 step 4(b): the small problem; 4(c) is enqueued next.
+      std::vector<double> y;
+      if (method == TSYLV_METHOD_GMRES) {
+        y = giv.solve((size_t)nv);
+      } else if (fom_ok) {
+        y = y_fom;
+      } else {
+        info.fom_fallback++;
+        y = giv.solve((size_t)nv);
+      }
+      for (int i = 0; i < nv; ++i) w.h_y[i] = -y[i];
+      pending_update = nv;
+      return true;
+    }
+    pending_scale = 1.0 / hn;
+    ++j;
+    return false;
+  }
+
+  // Algorithm 3 step 4(c): X += V_k (*) y (X FP64, V of type TV).
+  template <typename TV>
+  void enqueue_update(CycleWS<TV>& w) {
+    TSYLV_HIP(hipMemcpyAsync(w.d_y, w.h_y, pending_update * sizeof(double), hipMemcpyHostToDevice,
+                             st));
+    kern::mupdate((const TV*)w.basis, w.ldv, pending_update, w.d_y, S.Zx, N, st);
+    pending_update = 0;
+  }
+
+  void enqueue() {
+    switch (phase) {
+      case SETUP:
+        enqueue_norm2(S.Zc);  // ||C||_F (Parseval)
+        break;
+      case RESTART: {
+        if (pending_update) {
+          if (refine)
+            enqueue_update(w32);
+          else
+            enqueue_update(w64);
+        }
+        // R0 = C - M(X0)  (Algorithm 3, step 3), in FP64.
+        double* R = refine ? R64 : w64.V(0);
+        if (iter == 0 && !o.x0_given)
+          TSYLV_HIP(hipMemcpyAsync(R, S.Zc, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+        else
+          apply((const double*)S.Zx, R, (const double*)S.Zc, -1.0, 1.0);
+        enqueue_norm2(R);
+        break;
+      }
+      case STEP:
+        if (scale_v0) {
+          if (refine)
+            kern::scale((const double*)R64, w32.V(0), 1.0 / beta, N, st);  // rounds to FP32
+          else
+            kern::scale((const double*)w64.V(0), w64.V(0), 1.0 / beta, N, st);
+          scale_v0 = false;
+        }
+        if (refine)
+          enqueue_step(w32);
+        else
+          enqueue_step(w64);
+        break;
+      case FINAL: {
+        // Algorithm 1 step 3: back to the spatial domain.
+        ProfScope ps(ctx, TSYLV_K_XFORM, st, prof);
+        if (cnorm == 0.0)
+          TSYLV_HIP(hipMemsetAsync(X, 0, N * sizeof(double), st));
+        else
+          kern::tube_xform_f64(S.Zx, X, S.xf_inv, n * s, (int)p, st);
+        break;
+      }
+      case DONE:
+        break;
+    }
+  }
+
+  void complete() {
+    switch (phase) {
+      case SETUP:
+        cnorm = std::sqrt(red->h_ww[0]);
+        if (cnorm == 0.0) {
+          info.relres_true = 0.0;
+          status = TSYLV_OK;
+          phase = FINAL;
+        } else {
+          phase = RESTART;
+        }
+        break;
+      case RESTART: {
+        beta = std::sqrt(red->h_ww[0]);
+        info.relres_true = beta / cnorm;
+        const int max_iter = refine ? o.max_outer : o.max_cycles;
+        if (info.relres_true <= o.tol) {
+          status = TSYLV_OK;
+          phase = FINAL;
+        } else if (iter >= max_iter) {
+          status = TSYLV_NOT_CONVERGED;
+          phase = FINAL;
+        } else {
+          ++iter;
+          info.cycles++;
+          if (refine) info.outer++;
+          giv.reset(beta);
+          Hcols.clear();
+          fom_ok = false;
+          j = 0;
+          pending_scale = 0.0;
+          scale_v0 = true;
+          phase = STEP;
+        }
+        break;
+      }
+      case STEP: {
+        const double stop = refine ? std::max(o.inner_tol * beta, 0.5 * o.tol * cnorm)
+                                   : o.tol * cnorm;
+        const bool end = refine ? complete_step(w32, stop) : complete_step(w64, stop);
+        if (end) phase = RESTART;
+        break;
+      }
+      case FINAL:
+        phase = DONE;
+        info.status = status;
+        info.seconds = seconds_since(t0);
+        break;
+      case DONE:
+        break;
+    }
+  }
+};
+
+KrylovTask::KrylovTask(Ctx& ctx, hipStream_t st, bool profile, double* pinned, int method,
+                       int64_t n, int64_t s, int64_t p, const double* A, const double* B,
+                       const double* C, double* X, const tsylv_opts& o)
+    : s_(new KrylovState(ctx, st, profile, pinned, method, n, s, p, A, B, C, X, o)) {}
+
+KrylovTask::~KrylovTask() = default;
+
+size_t KrylovTask::pinned_doubles(const tsylv_opts& o) {
+  return 4 * (size_t)((o.refine ? o.inner_m : o.m) + 2);
 }
 
+void KrylovTask::enqueue() { s_->enqueue(); }
+void KrylovTask::complete() { s_->complete(); }
+bool KrylovTask::done() const { return s_->phase == KrylovState::DONE; }
+int KrylovTask::status() const { return s_->status; }
+const tsylv_info& KrylovTask::info() const { return s_->info; }
+hipStream_t KrylovTask::stream() const { return s_->st; }
+
+int krylov_solve(Ctx& ctx, int method, int64_t n, int64_t s, int64_t p, const double* A,
+                 const double* B, const double* C, double* X, const tsylv_opts& o,
+                 tsylv_info& info) {
+  KrylovTask t(ctx, ctx.stream, true, ctx.host_buffer(KrylovTask::pinned_doubles(o)), method, n, s,
+               p, A, B, C, X, o);
+  while (!t.done()) {
+    t.enqueue();
+    ctx.sync();
+    t.complete();
+  }
+  info = t.info();
+  return t.status();
+}
+
+// ---------------------------------------------------------------------------
 // Y = A*X - X*B through the Fourier planes (Algorithm 1), with the slice
 // products in the requested precision.
+// ---------------------------------------------------------------------------
+
 size_t apply_workspace_bytes(int64_t n, int64_t s, int64_t p) {
   int64_t N = n * s * p;
   return Workspace::bytes_for(p * n * n, 8) + Workspace::bytes_for(p * s * s, 8) +
@@ -494,7 +602,7 @@ int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, co
   kern::tube_xform_f64(B, Bh, xf_op, s * s, (int)p, st);
   kern::tube_xform_f64(X, Zx, xf_fwd, n * s, (int)p, st);
   if (prec == TSYLV_FP64) {
-    ProfScope ps(ctx, TSYLV_K_APPLY);
+    ProfScope ps(ctx, TSYLV_K_APPLY, st);
     kern::apply_f64(Ah, Bh, Zx, Zy, nullptr, 1.0, 0.0, n, s, (int)p, st);
   } else {
     float* Vf = ws.take<float>(N);
@@ -505,14 +613,14 @@ int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, co
       uint16_t* Bb = reinterpret_cast<uint16_t*>(ws.take<float>(p * s * s));
       kern::convert_f64_bf16(Ah, Ab, p * n * n, st);
       kern::convert_f64_bf16(Bh, Bb, p * s * s, st);
-      ProfScope ps(ctx, TSYLV_K_APPLY_LOW);
+      ProfScope ps(ctx, TSYLV_K_APPLY_LOW, st);
       kern::apply_bf16(Ab, Bb, Vf, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st);
     } else {
       float* Af = ws.take<float>(p * n * n);
       float* Bf = ws.take<float>(p * s * s);
       kern::convert_f64_f32(Ah, Af, p * n * n, st);
       kern::convert_f64_f32(Bh, Bf, p * s * s, st);
-      ProfScope ps(ctx, TSYLV_K_APPLY_LOW);
+      ProfScope ps(ctx, TSYLV_K_APPLY_LOW, st);
       kern::apply_f32(Af, Bf, Vf, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st);
     }
     kern::convert_f32_f64(Wf, Zy, N, st);

@@ -216,7 +216,7 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
   if (m < 1) throw Error(TSYLV_EINVAL, "TBA needs n >= 2 s");
   hipStream_t st = ctx.stream;
   Workspace ws(ctx.arena, tba_ws_bytes(n, s, p, m));
-  Setup S = setup_fourier(ctx, ws, n, s, p, A, B, C, X, o.x0_given != 0);
+  Setup S = setup_fourier(ctx, st, true, ws, n, s, p, A, B, C, X, o.x0_given != 0);
   TbaWS w;
   w.n = n;
   w.s = s;
@@ -265,7 +265,7 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
     if (cycle == 0 && !o.x0_given) {
       TSYLV_HIP(hipMemcpyAsync(w.R, S.Zc, w.N * sizeof(double), hipMemcpyDeviceToDevice, st));
     } else {
-      ProfScope ps(ctx, TSYLV_K_APPLY);
+      ProfScope ps(ctx, TSYLV_K_APPLY, st);
       kern::apply_f64(S.Ah, S.Bh, S.Zx, w.R, S.Zc, -1.0, 1.0, n, s, (int)p, st);
     }
     info.relres_true = std::sqrt(dev_norm2(ctx, w, w.R)) / cnorm;
@@ -282,7 +282,7 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
       const int64_t J = (int64_t)(j + 1) * s;
       double* W = w.V(j + 1);
       {
-        ProfScope ps(ctx, TSYLV_K_APPLY);
+        ProfScope ps(ctx, TSYLV_K_APPLY, st);
         kern::apply_f64(S.Ah, nullptr, w.V(j), W, nullptr, 1.0, 0.0, n, s, (int)p, st);  // A only
       }
       // block CGS2: H_{0..j, j} = V^H W (twice), W -= V H
@@ -366,7 +366,7 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
     ctx.sync();
   }
   {
-    ProfScope ps(ctx, TSYLV_K_XFORM);
+    ProfScope ps(ctx, TSYLV_K_XFORM, st);
     kern::tube_xform_f64(S.Zx, X, S.xf_inv, n * s, (int)p, st);
   }
   ctx.sync();

@@ -11,8 +11,9 @@ struct Setup {
   double *Ah, *Bh, *xf_op, *xf_fwd, *xf_inv, *Zc, *Zx;
 };
 size_t setup_bytes(int64_t n, int64_t s, int64_t p);
-Setup setup_fourier(Ctx& ctx, Workspace& ws, int64_t n, int64_t s, int64_t p, const double* A,
-                    const double* B, const double* C, const double* X, bool x0_given);
+Setup setup_fourier(Ctx& ctx, hipStream_t st, bool profile, Workspace& ws, int64_t n, int64_t s,
+                    int64_t p, const double* A, const double* B, const double* C, const double* X,
+                    bool x0_given);
 
 size_t tba_workspace_bytes(int64_t n, int64_t s, int64_t p, int m);
 int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
