@@ -28,11 +28,17 @@ void convert_f32_f64(const float* in, double* out, int64_t count, hipStream_t st
 void apply_f64(const double* Ah, const double* Bh, const double* V, double* out,
                const double* Y, double alpha, double beta, int64_t n, int64_t s,
                int p, hipStream_t st);
-// Same in FP32 (FP32 MFMA) and with BF16 operator planes (BF16 MFMA, the
-// vectors rounded to BF16 on the way into the product, FP32 accumulation).
+// Same in FP32 (FP32 MFMA).
 void apply_f32(const float* Ah, const float* Bh, const float* V, float* out, const float* Y,
                double alpha, double beta, int64_t n, int64_t s, int p, hipStream_t st);
-void apply_bf16(const uint16_t* Ah, const uint16_t* Bh, const float* V, float* out,
+
+// BF16 operator planes (BF16 MFMA, the vectors rounded to BF16 on the way
+// into the product, FP32 accumulation).  `At` holds the operator in the tiled
+// MFMA lane order written by tile_operator_bf16 (bf16_tiled_elems elements);
+// `Bb` the plain BF16 planes of Bhat (s x s column-major) or null.
+int64_t bf16_tiled_elems(int64_t n, int p);
+void tile_operator_bf16(const double* Ah, uint16_t* At, int64_t n, int p, hipStream_t st);
+void apply_bf16(const uint16_t* At, const uint16_t* Bb, const float* V, float* out,
                 const float* Y, double alpha, double beta, int64_t n, int64_t s, int p,
                 hipStream_t st);
 

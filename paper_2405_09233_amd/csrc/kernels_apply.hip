@@ -1,5 +1,5 @@
-// Facewise Sylvester apply in the Fourier half spectrum on MFMA
-// (FP64, FP32, and BF16 inputs with FP32 accumulation).
+// Facewise Sylvester apply in the Fourier half spectrum on MFMA (FP64 and
+// FP32; the BF16 variant is kernels_apply_bf16.hip).
 //
 // Algorithm 1 of section 2.1 computes a T-product as independent products
 // of the Fourier slices; for M(X) = A*X - X*B (eq. (2)) that is
@@ -29,17 +29,8 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int NT = 256;
-
-__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return (uint16_t)(u >> 16);
-}
 
 // Per-precision MFMA traits.  TA: storage type of the operator planes, TV:
 // of the vectors, L: LDS element type, frag: one lane's MFMA operand.
@@ -47,10 +38,6 @@ __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
 //         (i, j) in lane j + 16 (i % 4), register i / 4.
 //   FP32: v_mfma_f32_16x16x4; same operand layout; result (i, j) in lane
 //         j + 16 (i / 4), register i % 4.
-//   BF16: v_mfma_f32_16x16x32_bf16; lane i + 16 q holds A(i, 8q .. 8q+7)
-//         (B likewise with columns); FP32 accumulation, FP32 result layout.
-struct Bf16 {};
-
 template <typename TA>
 struct Mma;
 
@@ -94,38 +81,8 @@ struct Mma<float> {
   }
 };
 
-template <>
-struct Mma<Bf16> {
-  using TV = float;
-  using L = uint16_t;
-  using frag = bf8;
-  using acc_t = f4;
-  static constexpr int TK = 32, KB = 32;
-  __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
-  __device__ static int row(int r, int lk) { return 4 * lk + r; }
-  __device__ static L a_in(uint16_t x) { return x; }
-  __device__ static L v_in(float x) { return f32_to_bf16_bits(x); }
-  __device__ static L neg(L x) { return (uint16_t)(x ^ 0x8000u); }
-  template <int LD>
-  __device__ static frag ld(const L (*S)[LD], int ks, int lk, int i) {
-    frag f;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) f[e] = __builtin_bit_cast(__bf16, S[ks + 8 * lk + e][i]);
-    return f;
-  }
-  __device__ static frag negf(frag x) {
-    u16x8 u = __builtin_bit_cast(u16x8, x);
-    u ^= (unsigned short)0x8000u;
-    return __builtin_bit_cast(frag, u);
-  }
-  __device__ static acc_t mma(frag a, frag b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-  }
-};
-
 // storage type of the operator planes for a traits tag
 template <typename Tag> struct Store { using T = Tag; };
-template <> struct Store<Bf16> { using T = uint16_t; };
 
 template <typename Tag>
 struct ApplyArgs {
@@ -393,12 +350,6 @@ void apply_f64(const double* Ah, const double* Bh, const double* V, double* out,
 void apply_f32(const float* Ah, const float* Bh, const float* V, float* out, const float* Y,
                double alpha, double beta, int64_t n, int64_t s, int p, hipStream_t st) {
   apply_any<float>(Ah, Bh, V, out, Y, alpha, beta, n, s, p, Bh != nullptr, st);
-}
-
-void apply_bf16(const uint16_t* Ah, const uint16_t* Bh, const float* V, float* out,
-                const float* Y, double alpha, double beta, int64_t n, int64_t s, int p,
-                hipStream_t st) {
-  apply_any<Bf16>(Ah, Bh, V, out, Y, alpha, beta, n, s, p, Bh != nullptr, st);
 }
 
 }  // namespace kern

@@ -254,7 +254,8 @@ size_t krylov_workspace_bytes(int64_t n, int64_t s, int64_t p, const tsylv_opts&
   b += Workspace::bytes_for(N, 8);  // FP64 residual
   b += CycleWS<float>::bytes(N, o.inner_m);
   if (o.prec == TSYLV_BF16)
-    b += Workspace::bytes_for(p * n * n, 2) + Workspace::bytes_for(p * s * s, 2);
+    b += Workspace::bytes_for(kern::bf16_tiled_elems(n, (int)p), 2) +
+         Workspace::bytes_for(p * s * s, 2);
   else
     b += Workspace::bytes_for(p * n * n, 4) + Workspace::bytes_for(p * s * s, 4);
   return b;
@@ -321,9 +322,9 @@ struct KrylovState {
       red = &w32.red;
       op.low = o.prec == TSYLV_BF16 ? TSYLV_BF16 : TSYLV_FP32;
       if (op.low == TSYLV_BF16) {
-        uint16_t* Ab = ws.take<uint16_t>(p * n * n);
+        uint16_t* Ab = ws.take<uint16_t>(kern::bf16_tiled_elems(n, (int)p));
         uint16_t* Bb = ws.take<uint16_t>(p * s * s);
-        kern::convert_f64_bf16(S.Ah, Ab, p * n * n, st);
+        kern::tile_operator_bf16(S.Ah, Ab, n, (int)p, st);
         kern::convert_f64_bf16(S.Bh, Bb, p * s * s, st);
         op.Ahb = Ab;
         op.Bhb = Bb;
@@ -579,8 +580,9 @@ size_t apply_workspace_bytes(int64_t n, int64_t s, int64_t p) {
   int64_t N = n * s * p;
   return Workspace::bytes_for(p * n * n, 8) + Workspace::bytes_for(p * s * s, 8) +
          3 * Workspace::bytes_for(p * p, 8) + 2 * Workspace::bytes_for(N, 8) +
-         Workspace::bytes_for(p * n * n, 4) + Workspace::bytes_for(p * s * s, 4) +
-         2 * Workspace::bytes_for(N, 4);
+         std::max(Workspace::bytes_for(p * n * n, 4),
+                  Workspace::bytes_for(kern::bf16_tiled_elems(n, (int)p), 2)) +
+         Workspace::bytes_for(p * s * s, 4) + 2 * Workspace::bytes_for(N, 4);
 }
 
 int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
@@ -609,9 +611,9 @@ int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, co
     float* Wf = ws.take<float>(N);
     kern::convert_f64_f32(Zx, Vf, N, st);
     if (prec == TSYLV_BF16) {
-      uint16_t* Ab = reinterpret_cast<uint16_t*>(ws.take<float>(p * n * n));
+      uint16_t* Ab = ws.take<uint16_t>(kern::bf16_tiled_elems(n, (int)p));
       uint16_t* Bb = reinterpret_cast<uint16_t*>(ws.take<float>(p * s * s));
-      kern::convert_f64_bf16(Ah, Ab, p * n * n, st);
+      kern::tile_operator_bf16(Ah, Ab, n, (int)p, st);
       kern::convert_f64_bf16(Bh, Bb, p * s * s, st);
       ProfScope ps(ctx, TSYLV_K_APPLY_LOW, st);
       kern::apply_bf16(Ab, Bb, Vf, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st);
