@@ -200,7 +200,11 @@ def main():
         peak = PEAKS[best]
         roofline = {"bound": "mfma", "achieved": achieved_flops / 1e12, "peak": peak / 1e12,
                     "unit": "TFLOP/s", "frac": achieved_flops / peak}
-    roofline.update({"traffic": None, "kernel": "apply_mfma_kernel (%s)" % best,
+    kernel = {"fp64": "apply_mfma_kernel<double> (FP64 slice products)",
+              "mixed": "apply_mfma_kernel<float> (FP32 slice products)",
+              "bf16": "tile_v_bf16_kernel + apply_bf16_kernel (BF16 slice products; "
+                      "both launches of one apply call are timed)"}[best]
+    roofline.update({"traffic": None, "kernel": kernel,
                      "avg_launch_ms": r["apply_avg_ms"], "launches": r["apply_launches"],
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_bytes_per_launch": bytes_})

@@ -35,12 +35,14 @@ void apply_f32(const float* Ah, const float* Bh, const float* V, float* out, con
 // BF16 operator planes (BF16 MFMA, the vectors rounded to BF16 on the way
 // into the product, FP32 accumulation).  `At` holds the operator in the tiled
 // MFMA lane order written by tile_operator_bf16 (bf16_tiled_elems elements);
-// `Bb` the plain BF16 planes of Bhat (s x s column-major) or null.
+// `Bb` the plain BF16 planes of Bhat (s x s column-major) or null.  `Vt` is
+// scratch of bf16_vtiled_elems elements that receives V in the same order.
 int64_t bf16_tiled_elems(int64_t n, int p);
+int64_t bf16_vtiled_elems(int64_t n, int64_t s, int p);
 void tile_operator_bf16(const double* Ah, uint16_t* At, int64_t n, int p, hipStream_t st);
-void apply_bf16(const uint16_t* At, const uint16_t* Bb, const float* V, float* out,
-                const float* Y, double alpha, double beta, int64_t n, int64_t s, int p,
-                hipStream_t st);
+void apply_bf16(const uint16_t* At, const uint16_t* Bb, const float* V, uint16_t* Vt,
+                float* out, const float* Y, double alpha, double beta, int64_t n, int64_t s,
+                int p, hipStream_t st);
 
 // ---- multi-vector kernels on flat vectors of N reals ----
 
@@ -66,6 +68,23 @@ void mupdate(const float* V, int64_t ldv, int nv, const double* h, float* w,
              int64_t N, hipStream_t st);
 void mupdate(const float* V, int64_t ldv, int nv, const double* h, double* w,
              int64_t N, hipStream_t st);
+
+// Fused CGS2 passes over a basis whose vectors V_i are stored unnormalised
+// with sigma[i] = 1 / ||V_i|| (device array).  ortho_chunks(N) partial rows.
+//   ortho_dots:   part[c][i] = sigma_i V_i . w (i < nv), part[c][nv] = ||w||^2
+//   ortho_update: w -= sum_i h[i] sigma[i] V_i; then mode 0: part[c][i] =
+//                 sigma_i V_i . w (the next pass), mode 1: part[c][0] = ||w||^2
+// nv <= ortho_max_vectors(fp32).
+int ortho_chunks(int64_t N);
+int ortho_max_vectors(bool fp32);
+void ortho_dots(const double* V, int64_t ldv, int nv, const double* sigma, const double* w,
+                int64_t N, double* part, int ldp, hipStream_t st);
+void ortho_dots(const float* V, int64_t ldv, int nv, const double* sigma, const float* w,
+                int64_t N, double* part, int ldp, hipStream_t st);
+void ortho_update(const double* V, int64_t ldv, int nv, const double* h, const double* sigma,
+                  double* w, int64_t N, double* part, int ldp, int mode, hipStream_t st);
+void ortho_update(const float* V, int64_t ldv, int nv, const double* h, const double* sigma,
+                  float* w, int64_t N, double* part, int ldp, int mode, hipStream_t st);
 
 // out[e] = a * x[e]  (the FP64 -> FP32 form rounds the scaled value)
 void scale(const double* x, double* out, double a, int64_t N, hipStream_t st);

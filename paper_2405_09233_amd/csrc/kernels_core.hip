@@ -245,6 +245,270 @@ __global__ void scale_kernel(const TI* __restrict__ x, TO* __restrict__ out, dou
     out[i] = (TO)(a * (double)x[i]);
 }
 
+// ---- fused CGS2 passes over a lazily normalised basis ----------------
+// The basis vectors V_i are stored unnormalised; sigma[i] = 1 / ||V_i|| makes
+// sigma_i V_i orthonormal.  Every wave works on its own tiles of 16 x EPL
+// contiguous elements; within a tile the 64 lanes form 4 groups of 16, and
+// group g holds vectors g, g + 4, g + 8, ... (VPW of them), EPL contiguous
+// elements of each per lane.  The update w -= sum c_i V_i is summed over the
+// groups with two lane shuffles, so waves never wait on each other; a block
+// owns kOChunk elements and combines its four waves' partial sums once, at
+// the end.  All sums run in FP64 in a fixed order.
+
+constexpr int kOWaves = kBlock / 64;
+constexpr int kOGroups = 4;  // vector groups per wave
+constexpr int kOChunk = 8192;
+
+template <typename T, int EPL>
+struct OVec;
+template <>
+struct OVec<float, 2> {
+  using type = float2;
+};
+template <>
+struct OVec<float, 4> {
+  using type = float4;
+};
+template <>
+struct OVec<double, 1> {
+  using type = double;
+};
+template <>
+struct OVec<double, 2> {
+  using type = double2;
+};
+
+// Sum over the 16 lanes of a group (fixed xor tree).
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// out[col(k)] = sum over the block of acc[k], for the columns this lane's
+// group owns; cols[k] < 0 skips k.  One barrier.
+template <int NA>
+__device__ __forceinline__ void oblock_store(const double (&acc)[NA], const int (&cols)[NA],
+                                             int ncols, const double* __restrict__ scale,
+                                             double* __restrict__ out) {
+  constexpr int MAXC = NA * kOGroups;
+  __shared__ double red[kOWaves][MAXC];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    const double r = group_sum(acc[k]);
+    if ((lane & 15) == 0 && cols[k] >= 0) red[wid][cols[k]] = r;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncols; c += kBlock) {
+    double r = red[0][c];
+#pragma unroll
+    for (int q = 1; q < kOWaves; ++q) r += red[q][c];
+    out[c] = scale ? r * scale[c] : r;
+  }
+}
+
+// Loads this lane's EPL elements of its group's VPW vectors for the tile at
+// `off`.  FULL (the whole tile lies below `lim`, a wave-uniform test): every
+// load is issued unconditionally so that all are in flight together; slots
+// past nv read vector nv - 1 again (cache lines another lane group of the
+// wave loads at the same time) and are neutralised by the callers (zero
+// coefficient, zero weight).  Otherwise each element is guarded and the
+// slots past nv are zero.
+template <bool FULL, typename T, int VPW, int EPL>
+__device__ __forceinline__ void oload_tile(const T* __restrict__ V, int64_t ldv, int nv, int g,
+                                           const T* __restrict__ w, int64_t off, int64_t lim,
+                                           T (&v)[VPW][EPL]) {
+  using VT = typename OVec<T, EPL>::type;
+#pragma unroll
+  for (int k = 0; k < VPW; ++k) {
+    const int i = g + kOGroups * k;
+    if (FULL) {
+      const T* src = V + (int64_t)min(i, nv - 1) * ldv;
+      const VT t = *reinterpret_cast<const VT*>(src + off);
+      const T* tp = reinterpret_cast<const T*>(&t);
+#pragma unroll
+      for (int l = 0; l < EPL; ++l) v[k][l] = tp[l];
+    } else {
+#pragma unroll
+      for (int l = 0; l < EPL; ++l)
+        v[k][l] = (i < nv && off + l < lim) ? V[(int64_t)i * ldv + off + l] : (T)0;
+    }
+  }
+}
+
+template <bool FULL, typename T, int EPL>
+__device__ __forceinline__ void oload_w(const T* __restrict__ w, int64_t off, int64_t lim,
+                                        T (&v)[EPL]) {
+  using VT = typename OVec<T, EPL>::type;
+  if (FULL) {
+    const VT t = *reinterpret_cast<const VT*>(w + off);
+    const T* tp = reinterpret_cast<const T*>(&t);
+#pragma unroll
+    for (int l = 0; l < EPL; ++l) v[l] = tp[l];
+  } else {
+#pragma unroll
+    for (int l = 0; l < EPL; ++l) v[l] = (off + l < lim) ? w[off + l] : (T)0;
+  }
+}
+
+template <bool FULL, typename T, int VPW, int EPL>
+__device__ __forceinline__ void odots_tile(const T* __restrict__ V, int64_t ldv, int nv, int g,
+                                           const T* __restrict__ w, int64_t off, int64_t lim,
+                                           double (&acc)[VPW], double& ww) {
+  T wv[EPL];
+  oload_w<FULL, T, EPL>(w, off, lim, wv);
+  T v[VPW][EPL];
+  oload_tile<FULL, T, VPW, EPL>(V, ldv, nv, g, w, off, lim, v);
+#pragma unroll
+  for (int k = 0; k < VPW; ++k)
+#pragma unroll
+    for (int l = 0; l < EPL; ++l) acc[k] = fma((double)v[k][l], (double)wv[l], acc[k]);
+#pragma unroll
+  for (int l = 0; l < EPL; ++l) ww = fma((double)wv[l], (double)wv[l], ww);
+}
+
+// part[c][i] = sigma_i sum_e V_i[e] w[e] (i < nv), part[c][nv] = sum_e w[e]^2
+// over chunk c.
+template <typename T, int VPW, int EPL>
+__global__ __launch_bounds__(kBlock) void ortho_dots_kernel(
+    const T* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ sigma,
+    const T* __restrict__ w, int64_t N, double* __restrict__ part, int ldp) {
+  constexpr int TE = 16 * EPL;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int g = lane >> 4;
+  double acc[VPW], ww = 0.0;
+#pragma unroll
+  for (int k = 0; k < VPW; ++k) acc[k] = 0.0;
+  const int64_t base = (int64_t)blockIdx.x * kOChunk;
+  const int64_t end = min(N, base + kOChunk);
+  for (int64_t t0 = base + wid * TE; t0 < end; t0 += kOWaves * TE) {
+    const int64_t off = t0 + (lane & 15) * EPL;
+    if (t0 + TE <= end)
+      odots_tile<true, T, VPW, EPL>(V, ldv, nv, g, w, off, end, acc, ww);
+    else
+      odots_tile<false, T, VPW, EPL>(V, ldv, nv, g, w, off, end, acc, ww);
+  }
+  double* out = part + (int64_t)blockIdx.x * ldp;
+  double all[VPW + 1];
+  int cols[VPW + 1];
+#pragma unroll
+  for (int k = 0; k < VPW; ++k) {
+    const int i = g + kOGroups * k;
+    // unconditional product: a select on acc would let the compiler drop
+    // (and branch around) the loads of the unused slots
+    all[k] = acc[k] * ((i < nv) ? sigma[i] : 0.0);
+    cols[k] = (i < nv) ? i : -1;
+  }
+  all[VPW] = ww;  // every group saw the same w; group 0 reports it
+  cols[VPW] = (g == 0) ? nv : -1;
+  oblock_store<VPW + 1>(all, cols, nv + 1, nullptr, out);
+}
+
+template <bool FULL, typename T, int VPW, int EPL>
+__device__ __forceinline__ void oupdate_tile(const T* __restrict__ V, int64_t ldv, int nv, int g,
+                                             const double (&cs)[VPW], T* __restrict__ w,
+                                             int64_t off, int64_t lim, int mode,
+                                             double (&acc)[VPW], double& ww) {
+  T v[VPW][EPL];
+  oload_tile<FULL, T, VPW, EPL>(V, ldv, nv, g, w, off, lim, v);
+  double x[EPL];
+  {
+    T wv[EPL];
+    oload_w<FULL, T, EPL>(w, off, lim, wv);
+#pragma unroll
+    for (int l = 0; l < EPL; ++l) x[l] = (g == 0) ? (double)wv[l] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < VPW; ++k)
+#pragma unroll
+    for (int l = 0; l < EPL; ++l) x[l] = fma(-cs[k], (double)v[k][l], x[l]);
+  T xt[EPL];
+#pragma unroll
+  for (int l = 0; l < EPL; ++l) {
+    // (p0 + p1) + (p2 + p3) in every group: the same bits in all four
+    double y = x[l] + __shfl_xor(x[l], 16, 64);
+    y += __shfl_xor(y, 32, 64);
+    xt[l] = (T)y;
+  }
+  if (g == 0) {
+    if (FULL) {
+      using VT = typename OVec<T, EPL>::type;
+      VT t;
+      T* tp = reinterpret_cast<T*>(&t);
+#pragma unroll
+      for (int l = 0; l < EPL; ++l) tp[l] = xt[l];
+      *reinterpret_cast<VT*>(w + off) = t;
+    } else {
+#pragma unroll
+      for (int l = 0; l < EPL; ++l)
+        if (off + l < lim) w[off + l] = xt[l];
+    }
+  }
+  if (mode == 0) {
+    // Widen the basis values again here rather than keeping the widened
+    // copies from the update live (FP32: half the registers).
+#pragma unroll
+    for (int k = 0; k < VPW; ++k)
+#pragma unroll
+      for (int l = 0; l < EPL; ++l) asm volatile("" : "+v"(v[k][l]));
+#pragma unroll
+    for (int k = 0; k < VPW; ++k)
+#pragma unroll
+      for (int l = 0; l < EPL; ++l) acc[k] = fma((double)v[k][l], (double)xt[l], acc[k]);
+  } else {
+#pragma unroll
+    for (int l = 0; l < EPL; ++l) ww = fma((double)xt[l], (double)xt[l], ww);
+  }
+}
+
+// w -= sum_i h[i] sigma[i] V_i; then (mode 0) part[c][i] = sigma_i V_i . w for
+// the next CGS pass, or (mode 1) part[c][0] = ||w||^2.
+template <typename T, int VPW, int EPL>
+__global__ __launch_bounds__(kBlock) void ortho_update_kernel(
+    const T* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ h,
+    const double* __restrict__ sigma, T* __restrict__ w, int64_t N, double* __restrict__ part,
+    int ldp, int mode) {
+  constexpr int TE = 16 * EPL;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int g = lane >> 4;
+  double cs[VPW], acc[VPW];
+#pragma unroll
+  for (int k = 0; k < VPW; ++k) {
+    const int i = g + kOGroups * k;
+    cs[k] = (i < nv) ? h[i] * sigma[i] : 0.0;
+    acc[k] = 0.0;
+  }
+  double ww = 0.0;
+  const int64_t base = (int64_t)blockIdx.x * kOChunk;
+  const int64_t end = min(N, base + kOChunk);
+  for (int64_t t0 = base + wid * TE; t0 < end; t0 += kOWaves * TE) {
+    const int64_t off = t0 + (lane & 15) * EPL;
+    if (t0 + TE <= end)
+      oupdate_tile<true, T, VPW, EPL>(V, ldv, nv, g, cs, w, off, end, mode, acc, ww);
+    else
+      oupdate_tile<false, T, VPW, EPL>(V, ldv, nv, g, cs, w, off, end, mode, acc, ww);
+  }
+  double* out = part + (int64_t)blockIdx.x * ldp;
+  if (mode == 0) {
+    double all[VPW];
+    int cols[VPW];
+#pragma unroll
+    for (int k = 0; k < VPW; ++k) {
+      const int i = g + kOGroups * k;
+      all[k] = acc[k] * ((i < nv) ? sigma[i] : 0.0);
+      cols[k] = (i < nv) ? i : -1;
+    }
+    oblock_store<VPW>(all, cols, nv, nullptr, out);
+  } else {
+    double all[1] = {ww};
+    int cols[1] = {g == 0 ? 0 : -1};
+    oblock_store<1>(all, cols, 1, nullptr, out);
+  }
+}
+
 inline int stream_grid(int64_t count) {
   int64_t b = (count + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
@@ -354,6 +618,100 @@ void mupdate(const float* V, int64_t ldv, int nv, const double* h, float* w, int
 void mupdate(const float* V, int64_t ldv, int nv, const double* h, double* w, int64_t N,
              hipStream_t st) {
   mupdate_any<float, double>(V, ldv, nv, h, w, N, st);
+}
+
+int ortho_chunks(int64_t N) { return (int)((N + kOChunk - 1) / kOChunk); }
+
+int ortho_max_vectors(bool) { return 16 * kOGroups; }
+
+// elements per lane: 16-byte accesses for FP64, 8-byte for FP32 (fewer
+// registers per wave, more waves per SIMD)
+template <typename T>
+constexpr int ortho_epl() {
+  return sizeof(T) == 8 ? 2 : 2;
+}
+
+template <typename T>
+static void ortho_check(const T* V, int64_t ldv, const T* w) {
+  constexpr int EPL = ortho_epl<T>();
+  constexpr uintptr_t align = sizeof(T) * EPL;
+  if ((reinterpret_cast<uintptr_t>(V) | reinterpret_cast<uintptr_t>(w)) % align != 0 ||
+      ldv % EPL != 0)
+    throw Error(TSYLV_EINVAL, "ortho: basis not aligned");
+}
+
+template <typename T, int VPW>
+static void ortho_dots_t(const T* V, int64_t ldv, int nv, const double* sigma, const T* w,
+                         int64_t N, double* part, int ldp, hipStream_t st) {
+  hipLaunchKernelGGL((ortho_dots_kernel<T, VPW, ortho_epl<T>()>), dim3(ortho_chunks(N)),
+                     dim3(kBlock), 0, st, V, ldv, nv, sigma, w, N, part, ldp);
+  TSYLV_LAUNCH_CHECK();
+}
+
+template <typename T, int VPW>
+static void ortho_update_t(const T* V, int64_t ldv, int nv, const double* h, const double* sigma,
+                           T* w, int64_t N, double* part, int ldp, int mode, hipStream_t st) {
+  hipLaunchKernelGGL((ortho_update_kernel<T, VPW, ortho_epl<T>()>), dim3(ortho_chunks(N)),
+                     dim3(kBlock), 0, st, V, ldv, nv, h, sigma, w, N, part, ldp, mode);
+  TSYLV_LAUNCH_CHECK();
+}
+
+// vectors per lane group for nv basis vectors
+static int ortho_vpw(int nv) {
+  static const int sizes[] = {1, 2, 3, 4, 6, 8, 10, 12, 14, 16};
+  const int need = (nv + kOGroups - 1) / kOGroups;
+  for (int v : sizes)
+    if (need <= v) return v;
+  throw Error(TSYLV_EINVAL, "ortho: too many basis vectors");
+}
+
+#define TSYLV_OVPW_CASES(F) \
+  F(1) F(2) F(3) F(4) F(6) F(8) F(10) F(12) F(14) F(16)
+
+template <typename T>
+static void ortho_dots_any(const T* V, int64_t ldv, int nv, const double* sigma, const T* w,
+                           int64_t N, double* part, int ldp, hipStream_t st) {
+  if (nv < 1 || nv + 1 > ldp) throw Error(TSYLV_EINVAL, "ortho: bad vector count");
+  if (N <= 0) return;
+  ortho_check(V, ldv, w);
+  switch (ortho_vpw(nv)) {
+#define F(K) \
+  case K: ortho_dots_t<T, K>(V, ldv, nv, sigma, w, N, part, ldp, st); break;
+    TSYLV_OVPW_CASES(F)
+#undef F
+  }
+}
+
+template <typename T>
+static void ortho_update_any(const T* V, int64_t ldv, int nv, const double* h,
+                             const double* sigma, T* w, int64_t N, double* part, int ldp,
+                             int mode, hipStream_t st) {
+  if (nv < 1 || nv > ldp) throw Error(TSYLV_EINVAL, "ortho: bad vector count");
+  if (N <= 0) return;
+  ortho_check(V, ldv, (const T*)w);
+  switch (ortho_vpw(nv)) {
+#define F(K) \
+  case K: ortho_update_t<T, K>(V, ldv, nv, h, sigma, w, N, part, ldp, mode, st); break;
+    TSYLV_OVPW_CASES(F)
+#undef F
+  }
+}
+
+void ortho_dots(const double* V, int64_t ldv, int nv, const double* sigma, const double* w,
+                int64_t N, double* part, int ldp, hipStream_t st) {
+  ortho_dots_any<double>(V, ldv, nv, sigma, w, N, part, ldp, st);
+}
+void ortho_dots(const float* V, int64_t ldv, int nv, const double* sigma, const float* w,
+                int64_t N, double* part, int ldp, hipStream_t st) {
+  ortho_dots_any<float>(V, ldv, nv, sigma, w, N, part, ldp, st);
+}
+void ortho_update(const double* V, int64_t ldv, int nv, const double* h, const double* sigma,
+                  double* w, int64_t N, double* part, int ldp, int mode, hipStream_t st) {
+  ortho_update_any<double>(V, ldv, nv, h, sigma, w, N, part, ldp, mode, st);
+}
+void ortho_update(const float* V, int64_t ldv, int nv, const double* h, const double* sigma,
+                  float* w, int64_t N, double* part, int ldp, int mode, hipStream_t st) {
+  ortho_update_any<float>(V, ldv, nv, h, sigma, w, N, part, ldp, mode, st);
 }
 
 template <typename TI, typename TO>

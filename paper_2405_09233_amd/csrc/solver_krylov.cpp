@@ -66,6 +66,7 @@ struct Operator {
   const float* Bh32 = nullptr;
   const uint16_t* Ahb = nullptr;
   const uint16_t* Bhb = nullptr;
+  uint16_t* Vtb = nullptr;  // scratch: the BF16 apply's tiled copy of V
   int low = TSYLV_FP32;  // precision of the float-vector applies
 };
 
@@ -84,32 +85,34 @@ struct CycleWS {
   int64_t ldv = 0;
   int m = 0;
   RedBuf red;
-  double *d_h1 = nullptr, *d_h2 = nullptr, *d_y = nullptr;
-  double *h_h1 = nullptr, *h_h2 = nullptr, *h_y = nullptr;
+  double *d_h1 = nullptr, *d_h2 = nullptr, *d_y = nullptr, *d_sigma = nullptr;
+  double *h_h1 = nullptr, *h_h2 = nullptr, *h_y = nullptr, *h_sigma = nullptr;
   TV* V(int j) const { return basis + (int64_t)j * ldv; }
 
   static size_t bytes(int64_t N, int m) {
     int64_t ldv = round_up(N, 64);
     int nch = kern::mdot_chunks(N);
     return Workspace::bytes_for((int64_t)(m + 1) * ldv, sizeof(TV)) +
-           Workspace::bytes_for((int64_t)nch * (m + 2), 8) + 4 * Workspace::bytes_for(m + 2, 8);
+           Workspace::bytes_for((int64_t)nch * (m + 2), 8) + 5 * Workspace::bytes_for(m + 2, 8);
   }
-  // host: pinned staging of 4 (m + 2) doubles
+  // host: pinned staging of 5 (m + 2) doubles
   void carve(Workspace& ws, int64_t N, int m_, double* host) {
     m = m_;
     ldv = round_up(N, 64);
     basis = ws.take<TV>((int64_t)(m + 1) * ldv);
-    red.nchunks = kern::mdot_chunks(N);
+    red.nchunks = kern::mdot_chunks(N);  // >= ortho_chunks(N)
     red.ldp = m + 2;
     red.part = ws.take<double>((int64_t)red.nchunks * red.ldp);
     d_h1 = ws.take<double>(m + 2);
     d_h2 = ws.take<double>(m + 2);
     red.d_ww = ws.take<double>(m + 2);
     d_y = ws.take<double>(m + 2);
+    d_sigma = ws.take<double>(m + 2);
     h_h1 = host;
     h_h2 = host + (m + 2);
     red.h_ww = host + 2 * (m + 2);
     h_y = host + 3 * (m + 2);
+    h_sigma = host + 4 * (m + 2);
   }
 };
 
@@ -255,7 +258,8 @@ size_t krylov_workspace_bytes(int64_t n, int64_t s, int64_t p, const tsylv_opts&
   b += CycleWS<float>::bytes(N, o.inner_m);
   if (o.prec == TSYLV_BF16)
     b += Workspace::bytes_for(kern::bf16_tiled_elems(n, (int)p), 2) +
-         Workspace::bytes_for(p * s * s, 2);
+         Workspace::bytes_for(p * s * s, 2) +
+         Workspace::bytes_for(kern::bf16_vtiled_elems(n, s, (int)p), 2);
   else
     b += Workspace::bytes_for(p * n * n, 4) + Workspace::bytes_for(p * s * s, 4);
   return b;
@@ -291,8 +295,12 @@ struct KrylovState {
   double cnorm = 0.0, beta = 0.0;
   int iter = 0;               // restart cycles / refinement steps started
   int j = 0;                  // Arnoldi step inside the cycle
-  double pending_scale = 0;   // 1 / h of the previous step (0: none)
+  double pending_scale = 0;   // 1 / h of the previous step (0: none; unfused path)
   bool scale_v0 = false;
+  // Fused CGS2 (restart length within ortho_max_vectors): basis vectors kept
+  // unnormalised, sigma_i = 1 / ||V_i|| carried to the apply (alpha) and the
+  // Gram-Schmidt kernels, so no separate scaling sweep.
+  bool fused = false;
   int pending_update = 0;     // basis vectors to combine into X before the next residual
   Givens giv;
   std::vector<std::vector<double>> Hcols;
@@ -313,6 +321,7 @@ struct KrylovState {
     op.p = p;
     op.Ah64 = S.Ah;
     op.Bh64 = S.Bh;
+    fused = (refine ? o.inner_m : o.m) + 1 <= kern::ortho_max_vectors(refine);
     if (!refine) {
       w64.carve(ws, N, o.m, pinned);
       red = &w64.red;
@@ -328,6 +337,7 @@ struct KrylovState {
         kern::convert_f64_bf16(S.Bh, Bb, p * s * s, st);
         op.Ahb = Ab;
         op.Bhb = Bb;
+        op.Vtb = ws.take<uint16_t>(kern::bf16_vtiled_elems(n, s, (int)p));
       } else {
         float* Af = ws.take<float>(p * n * n);
         float* Bf = ws.take<float>(p * s * s);
@@ -346,7 +356,7 @@ struct KrylovState {
   void apply(const float* V, float* out, const float* Y, double alpha, double beta_) {
     ProfScope ps(ctx, TSYLV_K_APPLY_LOW, st, prof);
     if (op.low == TSYLV_BF16)
-      kern::apply_bf16(op.Ahb, op.Bhb, V, out, Y, alpha, beta_, n, s, (int)p, st);
+      kern::apply_bf16(op.Ahb, op.Bhb, V, op.Vtb, out, Y, alpha, beta_, n, s, (int)p, st);
     else
       kern::apply_f32(op.Ah32, op.Bh32, V, out, Y, alpha, beta_, n, s, (int)p, st);
   }
@@ -363,21 +373,39 @@ struct KrylovState {
   void enqueue_step(CycleWS<TV>& w) {
     const int nv = j + 1;
     TV* W = w.V(j + 1);
-    if (pending_scale != 0.0) {  // step 3(e) of the previous step: V_j = W / h_{j,j-1}
-      kern::scale((const TV*)w.V(j), w.V(j), pending_scale, N, st);
-      pending_scale = 0.0;
-    }
-    apply((const TV*)w.V(j), W, (const TV*)nullptr, 1.0, 0.0);
     const RedBuf& r = w.red;
-    ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
-    kern::mdot_partial((const TV*)w.basis, w.ldv, nv, (const TV*)W, N, r.part, r.ldp, 1, st);
-    kern::reduce_partials(r.part, r.nchunks, r.ldp, nv + 1, w.d_h1, st);
-    kern::mupdate((const TV*)w.basis, w.ldv, nv, w.d_h1, W, N, st);
-    kern::mdot_partial((const TV*)w.basis, w.ldv, nv, (const TV*)W, N, r.part, r.ldp, 0, st);
-    kern::reduce_partials(r.part, r.nchunks, r.ldp, nv, w.d_h2, st);
-    kern::mupdate((const TV*)w.basis, w.ldv, nv, w.d_h2, W, N, st);
-    kern::mdot_partial((const TV*)nullptr, 0, 0, (const TV*)W, N, r.part, r.ldp, 1, st);
-    kern::reduce_partials(r.part, r.nchunks, r.ldp, 1, r.d_ww, st);
+    if (fused) {
+      // W = M(sigma_j V_j); CGS2 against sigma_i V_i in three sweeps.
+      TSYLV_HIP(hipMemcpyAsync(w.d_sigma, w.h_sigma, nv * sizeof(double), hipMemcpyHostToDevice,
+                               st));
+      apply((const TV*)w.V(j), W, (const TV*)nullptr, w.h_sigma[j], 0.0);
+      ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
+      const int och = kern::ortho_chunks(N);
+      kern::ortho_dots((const TV*)w.basis, w.ldv, nv, w.d_sigma, (const TV*)W, N, r.part, r.ldp,
+                       st);
+      kern::reduce_partials(r.part, och, r.ldp, nv + 1, w.d_h1, st);
+      kern::ortho_update((const TV*)w.basis, w.ldv, nv, w.d_h1, w.d_sigma, W, N, r.part, r.ldp, 0,
+                         st);
+      kern::reduce_partials(r.part, och, r.ldp, nv, w.d_h2, st);
+      kern::ortho_update((const TV*)w.basis, w.ldv, nv, w.d_h2, w.d_sigma, W, N, r.part, r.ldp, 1,
+                         st);
+      kern::reduce_partials(r.part, och, r.ldp, 1, r.d_ww, st);
+    } else {
+      if (pending_scale != 0.0) {  // step 3(e) of the previous step: V_j = W / h_{j,j-1}
+        kern::scale((const TV*)w.V(j), w.V(j), pending_scale, N, st);
+        pending_scale = 0.0;
+      }
+      apply((const TV*)w.V(j), W, (const TV*)nullptr, 1.0, 0.0);
+      ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
+      kern::mdot_partial((const TV*)w.basis, w.ldv, nv, (const TV*)W, N, r.part, r.ldp, 1, st);
+      kern::reduce_partials(r.part, r.nchunks, r.ldp, nv + 1, w.d_h1, st);
+      kern::mupdate((const TV*)w.basis, w.ldv, nv, w.d_h1, W, N, st);
+      kern::mdot_partial((const TV*)w.basis, w.ldv, nv, (const TV*)W, N, r.part, r.ldp, 0, st);
+      kern::reduce_partials(r.part, r.nchunks, r.ldp, nv, w.d_h2, st);
+      kern::mupdate((const TV*)w.basis, w.ldv, nv, w.d_h2, W, N, st);
+      kern::mdot_partial((const TV*)nullptr, 0, 0, (const TV*)W, N, r.part, r.ldp, 1, st);
+      kern::reduce_partials(r.part, r.nchunks, r.ldp, 1, r.d_ww, st);
+    }
     TSYLV_HIP(hipMemcpyAsync(w.h_h1, w.d_h1, (nv + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
     TSYLV_HIP(hipMemcpyAsync(w.h_h2, w.d_h2, nv * sizeof(double), hipMemcpyDeviceToHost, st));
     TSYLV_HIP(hipMemcpyAsync(r.h_ww, r.d_ww, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -419,11 +447,14 @@ struct KrylovState {
         info.fom_fallback++;
         y = giv.solve((size_t)nv);
       }
-      for (int i = 0; i < nv; ++i) w.h_y[i] = -y[i];
+      for (int i = 0; i < nv; ++i) w.h_y[i] = -y[i] * (fused ? w.h_sigma[i] : 1.0);
       pending_update = nv;
       return true;
     }
-    pending_scale = 1.0 / hn;
+    if (fused)
+      w.h_sigma[j + 1] = 1.0 / hn;  // V_{j+1} stays unnormalised (step 3(e) folded in)
+    else
+      pending_scale = 1.0 / hn;
     ++j;
     return false;
   }
@@ -460,10 +491,14 @@ struct KrylovState {
       }
       case STEP:
         if (scale_v0) {
-          if (refine)
+          if (refine) {
             kern::scale((const double*)R64, w32.V(0), 1.0 / beta, N, st);  // rounds to FP32
-          else
+            w32.h_sigma[0] = 1.0;
+          } else if (fused) {
+            w64.h_sigma[0] = 1.0 / beta;  // V_0 = R kept unnormalised
+          } else {
             kern::scale((const double*)w64.V(0), w64.V(0), 1.0 / beta, N, st);
+          }
           scale_v0 = false;
         }
         if (refine)
@@ -547,7 +582,7 @@ KrylovTask::KrylovTask(Ctx& ctx, hipStream_t st, bool profile, double* pinned, i
 KrylovTask::~KrylovTask() = default;
 
 size_t KrylovTask::pinned_doubles(const tsylv_opts& o) {
-  return 4 * (size_t)((o.refine ? o.inner_m : o.m) + 2);
+  return 5 * (size_t)((o.refine ? o.inner_m : o.m) + 2);
 }
 
 void KrylovTask::enqueue() { s_->enqueue(); }
@@ -582,7 +617,8 @@ size_t apply_workspace_bytes(int64_t n, int64_t s, int64_t p) {
          3 * Workspace::bytes_for(p * p, 8) + 2 * Workspace::bytes_for(N, 8) +
          std::max(Workspace::bytes_for(p * n * n, 4),
                   Workspace::bytes_for(kern::bf16_tiled_elems(n, (int)p), 2)) +
-         Workspace::bytes_for(p * s * s, 4) + 2 * Workspace::bytes_for(N, 4);
+         Workspace::bytes_for(p * s * s, 4) + 2 * Workspace::bytes_for(N, 4) +
+         Workspace::bytes_for(kern::bf16_vtiled_elems(n, s, (int)p), 2);
 }
 
 int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
@@ -615,8 +651,9 @@ int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, co
       uint16_t* Bb = reinterpret_cast<uint16_t*>(ws.take<float>(p * s * s));
       kern::tile_operator_bf16(Ah, Ab, n, (int)p, st);
       kern::convert_f64_bf16(Bh, Bb, p * s * s, st);
+      uint16_t* Vt = ws.take<uint16_t>(kern::bf16_vtiled_elems(n, s, (int)p));
       ProfScope ps(ctx, TSYLV_K_APPLY_LOW, st);
-      kern::apply_bf16(Ab, Bb, Vf, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st);
+      kern::apply_bf16(Ab, Bb, Vf, Vt, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st);
     } else {
       float* Af = ws.take<float>(p * n * n);
       float* Bf = ws.take<float>(p * s * s);

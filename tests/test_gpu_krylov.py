@@ -101,6 +101,36 @@ def test_zero_rhs_and_exact_x0():
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("m", [1, 2, 63, 64])
+def test_one_cycle_at_fused_orthogonalisation_limit(m):
+    """Restart lengths up to 63 orthogonalise against a lazily normalised
+    basis with fused CGS2 sweeps; 64 and longer take the plain four-sweep
+    path.  Both must give the oracle's one-cycle iterate, here on a problem
+    whose n s p = 9450 entries span two element chunks and end in a partial
+    16-byte group."""
+    say("one cycle at fused limit", m)
+    n, s, p = 150, 9, 7
+    A, B, C = workloads.dense_shifted(n, s, p, seed=5)
+    X, info = solve("gmres", A, B, C, m=m, tol=1e-300, max_cycles=1)
+    assert info.status == 1 and info.steps == m
+    Xo, io = kr.tkrylov_solve(A, B, C, method="gmres", m=m, tol=1e-300, max_cycles=1,
+                              early_exit=False)
+    assert rel(X, Xo) <= 1e-10
+    assert info.relres_true == pytest.approx(io["relres_true"], rel=1e-8)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("inner_m", [63, 64])
+def test_refined_at_fused_orthogonalisation_limit(inner_m):
+    say("refined at fused limit", inner_m)
+    n, s, p = 150, 9, 7
+    A, B, C = workloads.dense_shifted(n, s, p, seed=6)
+    X, info = solve("gmres", A, B, C, refine=1, prec=tsylv.FP32, inner_m=inner_m, tol=1e-10)
+    assert info.status == 0, info.as_dict()
+    assert rel(X, tbs.t_bartels_stewart(A, B, C)) <= 1e-7
+
+
+@pytest.mark.gpu
 def test_residual_history_monotone():
     say("residual history")
     A, B, C = workloads.dense_shifted(30, 4, 4, seed=9)
