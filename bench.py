@@ -92,6 +92,29 @@ def cpu_baseline(A, B, C, applies_per_solve, avg_basis):
                       "%.1f vectors" % (n, s, p, t_slice, t_mgs, applies_per_solve, avg_basis)}
 
 
+def measured_traffic(path, shape):
+    """HBM bytes per apply call from the committed counter summary, or None
+    for another path or shape, or when the kernel source has changed since
+    the counters were taken."""
+    if path != "bf16" or tuple(shape) != (4096, 64, 32):
+        return None
+    import hashlib
+    import re
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        txt = open(os.path.join(here, "profiles",
+                                "apply_bf16_traffic_cd4096_s64_p32.md")).read()
+        src = open(os.path.join(here, "paper_2405_09233_amd", "csrc",
+                                "kernels_apply_bf16.hip"), "rb").read()
+    except OSError:
+        return None
+    m = re.search(r"sha256 at measurement:\s*([0-9a-f]{64})", txt)
+    t = re.search(r"traffic_bytes_per_call:\s*([0-9.eE+]+)", txt)
+    if not m or not t or hashlib.sha256(src).hexdigest() != m.group(1):
+        return None
+    return float(t.group(1))
+
+
 def run_path(ctx, tsylv, dev_in, opts, steps, warmup, name):
     import torch
     Ad, Bd, Cd, Xd = dev_in
@@ -151,6 +174,9 @@ def main():
     ap.add_argument("--grid", type=int, nargs=2, default=[64, 64])
     ap.add_argument("--s", type=int, default=64)
     ap.add_argument("--p", type=int, default=32)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB three times "
+                         "(reference kernel for the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -161,6 +187,16 @@ def main():
 
     import torch  # noqa: F401
     from paper_2405_09233_amd import tsylv, workloads
+
+    if args.copy_calib_mib > 0:
+        nbytes = args.copy_calib_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x %d MiB" % args.copy_calib_mib)
+        del src, dst
 
     nx, ny = args.grid
     t0 = time.perf_counter()
@@ -204,7 +240,7 @@ def main():
               "mixed": "apply_mfma_kernel<float> (FP32 slice products)",
               "bf16": "tile_v_bf16_kernel + apply_bf16_kernel (BF16 slice products; "
                       "both launches of one apply call are timed)"}[best]
-    roofline.update({"traffic": None, "kernel": kernel,
+    roofline.update({"traffic": measured_traffic(best, (n, s, p)), "kernel": kernel,
                      "avg_launch_ms": r["apply_avg_ms"], "launches": r["apply_launches"],
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_bytes_per_launch": bytes_})
