@@ -238,7 +238,7 @@ def main():
                     "unit": "TFLOP/s", "frac": achieved_flops / peak}
     kernel = {"fp64": "apply_mfma_kernel<double> (FP64 slice products)",
               "mixed": "apply_mfma_kernel<float> (FP32 slice products)",
-              "bf16": "tile_v_bf16_kernel + apply_bf16_kernel (BF16 slice products; "
+              "bf16": "tile_v_bf16_kernel + apply_bf16_wg_kernel (BF16 slice products; "
                       "both launches of one apply call are timed)"}[best]
     roofline.update({"traffic": measured_traffic(best, (n, s, p)), "kernel": kernel,
                      "avg_launch_ms": r["apply_avg_ms"], "launches": r["apply_launches"],

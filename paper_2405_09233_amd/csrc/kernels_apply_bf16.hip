@@ -3,19 +3,23 @@
 //
 // W_k = Ahat_k V_k - V_k Bhat_k (Algorithm 1 step 2 for eq. (2)).  Both MFMA
 // operands are stored in the lane order of v_mfma_f32_16x16x32_bf16, so every
-// operand fragment is one coalesced 16-byte load per lane and no LDS or
-// barrier is needed:
+// operand fragment is one coalesced 16-byte access per lane:
 //   * the operator planes, rounded to BF16 once at setup: plane q, 16-row
 //     block rb, 32-deep k block kb form one 1 KB chunk whose lane i + 16 g
 //     holds A(16 rb + i, 32 kb + 8 g .. 8 g + 7);
 //   * the Krylov vector, rounded to BF16 at the start of every apply into a
 //     scratch buffer: plane q, 16-column block cb, k block kb form one chunk
 //     whose lane i + 16 g holds V(32 kb + 8 g .. 8 g + 7, 16 cb + i).
-// A wave owns R row blocks and CB column blocks of one slice and walks k with
-// the next k block's fragments in flight.  The operator (the only large
-// stream) is read once from HBM; a slice's V fragments (s n / 8 KB) are shared
-// by all its waves through L2, which the XCD-contiguous tile order keeps on
-// one XCD.  The small -V_k Bhat_k term is a short extra contraction over s.
+// A workgroup owns a column tile and a row range of one slice sized so that
+// all workgroups stream the same number of operator bytes (a complex slice
+// has two planes, a real one one) and the grid fills whole rounds of the
+// CUs.  Each wave streams its own 16 operator rows straight from HBM into a
+// register ring D k blocks deep; the V chunks of the column tile, needed by
+// every wave, pass through LDS in double-buffered phases of P k blocks (one
+// barrier per phase).  The operator is read from HBM once; V (s n / 8 KB per
+// slice) once per workgroup, mostly from L2, which the XCD-contiguous tile
+// order keeps on one XCD.  The small -V_k Bhat_k term is a short extra
+// contraction over s in the epilogue.
 #include "kernels.hpp"
 
 namespace tsylv {
@@ -27,8 +31,6 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int NT = 256;  // 4 waves, one 16-row block each
 
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
   uint32_t u = __float_as_uint(f);
@@ -131,84 +133,14 @@ __device__ __forceinline__ bf8 ld8(const uint16_t* p) {
   return __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(p));
 }
 
-// One wave: row blocks rb0 .. rb0 + R - 1, column blocks cb0 .. cb0 + CB - 1
-// of slice k.  All R row blocks and CB column blocks exist in the tiled
-// buffers (zero padded), so the main loop has no conditions.
-template <int CB, int R, int D, bool CPLX>
-__device__ __forceinline__ void bf16_wave(const Bf16Args& a, int k, int64_t rb0, int64_t cb0) {
-  int qr, qi;
-  slice_planes(a.p, k, qr, qi);
-  const int64_t n = a.n, s = a.s, ns = n * s, nkb = a.nkb;
+// The -V_k Bhat_k term (a short contraction over s straight from global
+// memory) and the epilogue out = alpha W + beta Y for R x CB blocks.
+template <int CB, int R, bool CPLX>
+__device__ __forceinline__ void bf16_finish(const Bf16Args& a, int qr, int qi, int64_t rb0,
+                                            int64_t cb0, f4 (&accr)[R][CB], f4 (&acci)[R][CB]) {
+  const int64_t n = a.n, s = a.s, ns = n * s;
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
-  const uint16_t* Ar[R];
-  const uint16_t* Ai[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    Ar[r] = a.At + ((int64_t)qr * a.nrb + rb0 + r) * nkb * 512 + lane * 8;
-    Ai[r] = CPLX ? a.At + ((int64_t)qi * a.nrb + rb0 + r) * nkb * 512 + lane * 8 : nullptr;
-  }
-  const uint16_t* Br[CB];
-  const uint16_t* Bi[CB];
-#pragma unroll
-  for (int j = 0; j < CB; ++j) {
-    Br[j] = a.Vt + ((int64_t)qr * a.ncb + cb0 + j) * nkb * 512 + lane * 8;
-    Bi[j] = CPLX ? a.Vt + ((int64_t)qi * a.ncb + cb0 + j) * nkb * 512 + lane * 8 : nullptr;
-  }
-
-  f4 accr[R][CB], acci[R][CB];
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-#pragma unroll
-    for (int j = 0; j < CB; ++j) {
-      accr[r][j] = f4{0.f, 0.f, 0.f, 0.f};
-      acci[r][j] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-
-  // Ring of D fragment sets: set u holds k block kb0 + u; after its MFMAs are
-  // issued it is refilled with k block kb0 + u + D, so D k blocks of the
-  // operator stream are in flight per wave.
-  bf8 ar[D][R], ai[D][R], br[D][CB], bi[D][CB];
-  auto load = [&](int64_t kb, int u) {
-    const int64_t o = kb * 512;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      ar[u][r] = ld8(Ar[r] + o);
-      if (CPLX) ai[u][r] = ld8(Ai[r] + o);
-    }
-#pragma unroll
-    for (int j = 0; j < CB; ++j) {
-      br[u][j] = ld8(Br[j] + o);
-      if (CPLX) bi[u][j] = ld8(Bi[j] + o);
-    }
-  };
-#pragma unroll
-  for (int u = 0; u < D; ++u)
-    if (u < nkb) load(u, u);
-  for (int64_t kb0 = 0; kb0 < nkb; kb0 += D) {
-#pragma unroll
-    for (int u = 0; u < D; ++u) {
-      const int64_t kb = kb0 + u;
-      if (kb < nkb) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          bf8 mai;
-          if (CPLX) mai = neg8(ai[u][r]);
-#pragma unroll
-          for (int j = 0; j < CB; ++j) {
-            accr[r][j] = mma(ar[u][r], br[u][j], accr[r][j]);
-            if (CPLX) {
-              acci[r][j] = mma(ar[u][r], bi[u][j], acci[r][j]);
-              accr[r][j] = mma(mai, bi[u][j], accr[r][j]);
-              acci[r][j] = mma(ai[u][r], br[u][j], acci[r][j]);
-            }
-          }
-        }
-        if (kb + D < nkb) load(kb + D, u);
-      }
-    }
-  }
-
   const float* Vr = a.V + qr * ns;
   const float* Vi = CPLX ? a.V + qi * ns : nullptr;
 #pragma unroll
@@ -284,51 +216,198 @@ __device__ __forceinline__ void bf16_wave(const Bf16Args& a, int k, int64_t rb0,
   }
 }
 
-// Workgroup = 4 independent waves on consecutive row groups of one slice.
-template <int CB, int R, int D>
-__global__ __launch_bounds__(NT) void apply_bf16_kernel(Bf16Args a) {
+// Balanced variant: a workgroup of NW waves owns one column tile and a
+// contiguous range of row blocks of ONE slice -- G row blocks of a complex
+// slice or 2 G of a real one (half the work each) -- so every workgroup has
+// the same amount of operator to stream and the launch has no ragged last
+// round.  Its waves walk their row blocks (one per wave at a time, 16 rows)
+// in lock step, sharing each phase of V chunks through LDS.
+struct WgPlan {
+  int G;        // complex row blocks per workgroup (multiple of NW)
+  int wr, wc;   // workgroups per real / complex slice and column tile
+};
+
+template <int CB, int D, int P, int NW, bool CPLX>
+__device__ __forceinline__ void bf16_wg_tasks(const Bf16Args& a, const WgPlan& pl, int k,
+                                              int64_t rb_begin, int64_t rb_count, int64_t cb0,
+                                              uint16_t* lds) {
+  constexpr int NPL = CPLX ? 2 : 1;
+  constexpr int CPK = NPL * CB;
+  constexpr int CH = P * CPK;
+  static_assert(CH % NW == 0, "every wave stages the same number of chunks");
+  constexpr int NPASS = CH / NW;
+  int qr, qi;
+  slice_planes(a.p, k, qr, qi);
+  const int64_t nkb = a.nkb, nrb_real = (a.n + 15) / 16;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint16_t* Vsrc[NPASS];
+#pragma unroll
+  for (int v = 0; v < NPASS; ++v) {
+    const int c = v * NW + wave;
+    const int kl = c / CPK, pln = (c % CPK) / CB, j = c % CB;
+    const int q = pln ? qi : qr;
+    Vsrc[v] = a.Vt + (((int64_t)q * a.ncb + cb0 + j) * nkb + kl) * 512 + lane * 8;
+  }
+  const int64_t nph = nkb / P;
+  const int64_t ntask = (rb_count + NW - 1) / NW;
+  for (int64_t task = 0; task < ntask; ++task) {
+    const int64_t rb_want = rb_begin + task * NW + wave;
+    const bool store = rb_want < rb_begin + rb_count && rb_want < nrb_real;
+    const int64_t rb = min(rb_want, a.nrb - 1);  // past the end: any valid block, not stored
+    const uint16_t* Ar = a.At + ((int64_t)qr * a.nrb + rb) * nkb * 512 + lane * 8;
+    const uint16_t* Ai = CPLX ? a.At + ((int64_t)qi * a.nrb + rb) * nkb * 512 + lane * 8 : nullptr;
+    u16x8 stage[NPASS];
+    auto fetch = [&](int64_t ph) {
+#pragma unroll
+      for (int v = 0; v < NPASS; ++v)
+        stage[v] = *reinterpret_cast<const u16x8*>(Vsrc[v] + ph * P * 512);
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+      for (int v = 0; v < NPASS; ++v)
+        *reinterpret_cast<u16x8*>(lds + ((int64_t)buf * CH + v * NW + wave) * 512 + lane * 8) =
+            stage[v];
+    };
+    auto frag = [&](int buf, int kl, int pln, int j) -> bf8 {
+      return __builtin_bit_cast(
+          bf8, *reinterpret_cast<const u16x8*>(
+                   lds + ((int64_t)buf * CH + kl * CPK + pln * CB + j) * 512 + lane * 8));
+    };
+    f4 accr[1][CB], acci[1][CB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      accr[0][j] = f4{0.f, 0.f, 0.f, 0.f};
+      acci[0][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+    bf8 ar[D], ai[D];
+    auto loadA = [&](int64_t kb, int u) {
+      ar[u] = ld8(Ar + kb * 512);
+      if (CPLX) ai[u] = ld8(Ai + kb * 512);
+    };
+    fetch(0);
+#pragma unroll
+    for (int u = 0; u < D; ++u) loadA(u, u);
+    put(0);
+    __syncthreads();
+    for (int64_t ph = 0; ph < nph; ++ph) {
+      const int buf = (int)(ph & 1);
+      fetch(min(ph + 1, nph - 1));
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < P; ++u) {
+        const int d = u % D;
+        bf8 br[CB], bi[CB];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+          br[j] = frag(buf, u, 0, j);
+          if (CPLX) bi[j] = frag(buf, u, 1, j);
+        }
+        bf8 mai;
+        if (CPLX) mai = neg8(ai[d]);
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+          accr[0][j] = mma(ar[d], br[j], accr[0][j]);
+          if (CPLX) {
+            acci[0][j] = mma(ar[d], bi[j], acci[0][j]);
+            accr[0][j] = mma(mai, bi[j], accr[0][j]);
+            acci[0][j] = mma(ai[d], br[j], acci[0][j]);
+          }
+        }
+        // keep the refill right behind the MFMAs that free its slot
+        __builtin_amdgcn_sched_barrier(0);
+        loadA(min(ph * P + u + D, nkb - 1), d);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      put(buf ^ 1);
+      __syncthreads();
+    }
+    if (store) bf16_finish<CB, 1, CPLX>(a, qr, qi, rb, cb0, accr, acci);
+  }
+}
+
+template <int CB, int D, int P, int NW>
+__global__ __launch_bounds__(NW * 64) void apply_bf16_wg_kernel(Bf16Args a, WgPlan pl) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
   const int t = xcd_tile(blockIdx.x, a.total);
   const int ct = t % a.nct;
-  const int rt = (t / a.nct) % a.nrt;
-  const int k = t / (a.nct * a.nrt);
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t rb0 = ((int64_t)rt * (NT / 64) + wave) * R;
-  if (rb0 >= (a.n + 15) / 16) return;  // whole wave past the last row
+  int w = t / a.nct;  // workgroup index within the slice-major order
+  const int nsl = num_slices(a.p);
+  int k = 0;
+  for (; k < nsl; ++k) {
+    const bool real = (k == 0) || (2 * k == a.p);
+    const int wk = real ? pl.wr : pl.wc;
+    if (w < wk) break;
+    w -= wk;
+  }
+  const bool real = (k == 0) || (2 * k == a.p);
+  const int64_t span = real ? 2 * (int64_t)pl.G : pl.G;
+  const int64_t rb_begin = (int64_t)w * span;
   const int64_t cb0 = (int64_t)ct * CB;
-  if ((k == 0) || (2 * k == a.p))
-    bf16_wave<CB, R, D, false>(a, k, rb0, cb0);
+  if (real)
+    bf16_wg_tasks<CB, D, P, NW, false>(a, pl, k, rb_begin, span, cb0, lds);
   else
-    bf16_wave<CB, R, D, true>(a, k, rb0, cb0);
+    bf16_wg_tasks<CB, D, P, NW, true>(a, pl, k, rb_begin, span, cb0, lds);
 }
 
-// Row blocks are padded to a multiple of kRowPad (the largest 4 R) and
-// column blocks to a multiple of kColPad (the largest CB).
+// Row blocks are padded to a multiple of kRowPad and column blocks to a
+// multiple of kColPad (the largest CB).
 constexpr int64_t kRowPad = 16, kColPad = 4;
+// k blocks are padded to a multiple of kKPad, which every ring depth divides.
+constexpr int64_t kKPad = 8;
 
-template <int CB, int R, int D>
-void launch(Bf16Args a, hipStream_t st) {
-  a.nrt = (int)(((a.n + 15) / 16 + 4 * R - 1) / (4 * R));
+// Picks G (complex row blocks per workgroup, a multiple of NW) so that the
+// number of workgroups fills whole rounds of one workgroup per CU.
+inline WgPlan plan_wg(int64_t n, int p, int nct, int nw, int ncu) {
+  const int64_t nrb = (n + 15) / 16;
+  const int nsl = num_slices(p), nreal = (p % 2 == 0 && p > 1) ? 2 : 1;
+  const int ncplx = nsl - nreal;
+  WgPlan best{nw, 0, 0};
+  double best_cost = 1e300;
+  for (int64_t G = nw; G <= std::max<int64_t>(nw, ((nrb + nw - 1) / nw) * nw); G += nw) {
+    const int wr = (int)((nrb + 2 * G - 1) / (2 * G)), wc = (int)((nrb + G - 1) / G);
+    const int64_t total = (int64_t)nct * (nreal * wr + ncplx * wc);
+    const double cost = (double)((total + ncu - 1) / ncu) * (double)G;
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = WgPlan{(int)G, wr, wc};
+    }
+  }
+  return best;
+}
+
+template <int CB, int D, int P, int NW>
+void launch_wg(Bf16Args a, int ncu, hipStream_t st) {
+  static_assert(kKPad % P == 0 && P % D == 0, "phase and ring must divide the k padding");
   a.nct = (int)((a.s + 16 * CB - 1) / (16 * CB));
-  a.total = num_slices(a.p) * a.nrt * a.nct;
-  hipLaunchKernelGGL((apply_bf16_kernel<CB, R, D>), dim3(a.total), dim3(NT), 0, st, a);
+  const WgPlan pl = plan_wg(a.n, a.p, a.nct, NW, ncu);
+  const int nsl = num_slices(a.p), nreal = (a.p % 2 == 0 && a.p > 1) ? 2 : 1;
+  a.total = a.nct * (nreal * pl.wr + (nsl - nreal) * pl.wc);
+  const size_t lds = 2 * (size_t)P * 2 * CB * 1024;  // two buffers of complex phases
+  TSYLV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_bf16_wg_kernel<CB, D, P, NW>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((apply_bf16_wg_kernel<CB, D, P, NW>), dim3(a.total), dim3(NW * 64), lds, st,
+                     a, pl);
   TSYLV_LAUNCH_CHECK();
 }
+
 
 }  // namespace
 
 static int64_t row_blocks(int64_t n) { return ((n + 15) / 16 + kRowPad - 1) / kRowPad * kRowPad; }
+static int64_t k_blocks(int64_t n) { return ((n + 31) / 32 + kKPad - 1) / kKPad * kKPad; }
 static int64_t col_blocks(int64_t s) { return ((s + 15) / 16 + kColPad - 1) / kColPad * kColPad; }
 
 int64_t bf16_tiled_elems(int64_t n, int p) {
-  return (int64_t)p * row_blocks(n) * ((n + 31) / 32) * 512;
+  return (int64_t)p * row_blocks(n) * k_blocks(n) * 512;
 }
 
 int64_t bf16_vtiled_elems(int64_t n, int64_t s, int p) {
-  return (int64_t)p * col_blocks(s) * ((n + 31) / 32) * 512;
+  return (int64_t)p * col_blocks(s) * k_blocks(n) * 512;
 }
 
 void tile_operator_bf16(const double* Ah, uint16_t* At, int64_t n, int p, hipStream_t st) {
-  const int64_t nrb = row_blocks(n), nkb = (n + 31) / 32;
+  const int64_t nrb = row_blocks(n), nkb = k_blocks(n);
   const int64_t total = (int64_t)p * nrb * nkb * 64;
   int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
   hipLaunchKernelGGL(tile_bf16_kernel, dim3(blocks), dim3(256), 0, st, Ah, At, n, p, nrb, nkb);
@@ -353,7 +432,7 @@ void apply_bf16(const uint16_t* At, const uint16_t* Bb, const float* V, uint16_t
   a.s = s;
   a.p = p;
   a.nrb = row_blocks(n);
-  a.nkb = (n + 31) / 32;
+  a.nkb = k_blocks(n);
   a.ncb = col_blocks(s);
   {
     const int64_t total = (int64_t)p * a.ncb * a.nkb * 64;
@@ -362,14 +441,17 @@ void apply_bf16(const uint16_t* At, const uint16_t* Bb, const float* V, uint16_t
                        a.nkb);
     TSYLV_LAUNCH_CHECK();
   }
-  // (column blocks, row blocks, ring depth) per wave, from a sweep at
-  // n = 4096, p = 32 and n = 8192, p = 64
+  int dev = 0, ncu = 0;
+  TSYLV_HIP(hipGetDevice(&dev));
+  TSYLV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  // (column blocks, ring depth, phase length, waves) from a sweep at
+  // n = 4096, p = 32, s = 16 / 32 / 64 and n = 8192, p = 64, s = 128
   if (s <= 16)
-    launch<1, 1, 2>(a, st);
+    launch_wg<1, 8, 8, 4>(a, ncu, st);
   else if (s <= 32)
-    launch<2, 2, 4>(a, st);
+    launch_wg<2, 8, 8, 4>(a, ncu, st);
   else
-    launch<4, 2, 3>(a, st);
+    launch_wg<4, 4, 8, 8>(a, ncu, st);
 }
 
 }  // namespace kern
