@@ -240,5 +240,43 @@ bool sylvester_banded(const cplx* H, int ms, int band, const cplx* B, int s, con
   return true;
 }
 
+double eig_from_schur(const cplx* T, const cplx* U, int n, cplx* lam, cplx* W, cplx* Winv) {
+  std::vector<cplx> Q((size_t)n * n, 0.0), Qi((size_t)n * n);
+  double tmax = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = i; j < n; ++j) tmax = std::max(tmax, std::abs(at(T, n, i, j)));
+  for (int j = 0; j < n; ++j) {
+    lam[j] = at(T, n, j, j);
+    at(Q.data(), n, j, j) = 1.0;
+    for (int i = j - 1; i >= 0; --i) {
+      cplx v = 0.0;
+      for (int l = i + 1; l <= j; ++l) v += at(T, n, i, l) * at(Q.data(), n, l, j);
+      const cplx d = at(T, n, i, i) - lam[j];
+      if (!(std::abs(d) > kEps * tmax)) return INFINITY;  // (nearly) repeated eigenvalue
+      at(Q.data(), n, i, j) = -v / d;
+    }
+    double nrm = 0.0;
+    for (int i = 0; i <= j; ++i) nrm += std::norm(at(Q.data(), n, i, j));
+    nrm = std::sqrt(nrm);
+    for (int i = 0; i <= j; ++i) at(Q.data(), n, i, j) /= nrm;
+  }
+  tri_inv_upper(Q.data(), Qi.data(), n);
+  double nq = 0.0, nqi = 0.0;
+  for (size_t e = 0; e < (size_t)n * n; ++e) {
+    nq += std::norm(Q[e]);
+    nqi += std::norm(Qi[e]);
+  }
+  matmul(U, Q.data(), W, n, n, n);
+  // Winv = Qi U^H
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      cplx v = 0.0;
+      for (int l = 0; l < n; ++l) v += at(Qi.data(), n, i, l) * std::conj(at(U, n, j, l));
+      at(Winv, n, i, j) = v;
+    }
+  const double kappa = std::sqrt(nq) * std::sqrt(nqi);
+  return std::isfinite(kappa) ? kappa : INFINITY;
+}
+
 }  // namespace host
 }  // namespace tsylv

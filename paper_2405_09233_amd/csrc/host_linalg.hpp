@@ -42,5 +42,12 @@ bool schur(cplx* A, cplx* U, int n);
 bool sylvester_banded(const cplx* H, int ms, int band, const cplx* B, int s, const cplx* C1,
                       cplx* Y);
 
+// Eigendecomposition B = W diag(lam) W^{-1} from B's complex Schur form
+// B = U T U^H: the eigenvectors of the triangular T (back substitution, unit
+// 2-norm columns) form an upper triangular Q, W = U Q, W^{-1} = Q^{-1} U^H.
+// Returns the condition estimate ||Q||_F ||Q^{-1}||_F (infinite when two
+// eigenvalues coincide to working precision); B is not needed, only T, U.
+double eig_from_schur(const cplx* T, const cplx* U, int n, cplx* lam, cplx* W, cplx* Winv);
+
 }  // namespace host
 }  // namespace tsylv

@@ -105,6 +105,19 @@ inline PMat dense_pmat(const double* base, int64_t plane, int64_t ld) {
   return PMat{base, plane, ld, (int64_t)1 << 40, 0};
 }
 
+// Projected equations of TBAS(m) on the device (kernels_projected.hip):
+// solves (Hm_k - lam_{k,j} I) z = d for the nsys = p_h s systems k s + j.
+// Hm: p_h interleaved-complex ms x ms column-major slices, lower bandwidth s
+// (block upper Hessenberg); lam: nsys shifts; D: p_h interleaved s x s
+// slices, column j = the first s rows of system (k, j)'s right-hand side
+// (the rest is zero); z: nsys x ms, receives the solutions; Wrk (nsys s ms)
+// and U (nsys proj_u_stride(s, m)) complex scratch; info: nsys flags, 1 where
+// a pivot vanished.  Requires 1 <= s <= proj_max_block(), ms = m s.
+int proj_max_block();
+int64_t proj_u_stride(int s, int m);
+void proj_solve(const double* Hm, const double* lam, const double* D, double* z, double* Wrk,
+                double* U, int* info, int ms, int s, int m, int nsys, hipStream_t st);
+
 // Number of K splits zgemm uses when given a partial buffer, and the size of
 // that buffer in doubles.
 int zgemm_splits(int64_t M, int64_t N, int64_t K, int p);

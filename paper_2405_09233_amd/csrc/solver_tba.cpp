@@ -26,11 +26,21 @@
 // of the stored slices (Parseval).
 //
 // The projected equation H_m Y - Y B = V_m^T R0 = [H0; 0] (eq. (TBslowrank))
-// is solved per slice on the host in FP64 by Bartels-Stewart with the Schur
-// form of Bhat_k (host_linalg), the slices spread over host threads.
+// is solved in FP64.  Bhat_k does not change during a solve, so it is
+// diagonalised once per solve on the host, Bhat_k = W_k diag(lam) W_k^{-1}
+// (from its complex Schur form); with Z = Y W the equation splits into p_h s
+// independent shifted block-Hessenberg systems, solved on the device
+// (kern::proj_solve), and Y = Z W^{-1}.  Where that is not safe -- s above
+// the device kernel's block limit, or an ill-conditioned eigenvector basis
+// (kappa(W_k) > 1e8) -- or a shifted system hits a zero pivot, the cycle uses
+// the host Bartels-Stewart solve with the Schur form of Bhat_k (triangular
+// recursion over the columns, host_linalg), the slices spread over host
+// threads.  TSYLV_TBA_HOST_PROJECTED=1 in the environment forces the host
+// solve (used by the tests to compare the two).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <thread>
 #include <vector>
 
@@ -99,6 +109,33 @@ int64_t tba_partial_elems(int64_t n, int64_t s, int64_t p, int m) {
   return e;
 }
 
+// Device buffers of the projected solve (interleaved complex doubles).
+struct ProjWS {
+  double *Hm = nullptr, *lam = nullptr, *D = nullptr, *z = nullptr, *Wrk = nullptr, *U = nullptr;
+  int* info = nullptr;
+  static bool possible(int64_t s) { return s <= kern::proj_max_block(); }
+  static size_t bytes(int64_t s, int64_t p, int m) {
+    if (!possible(s)) return 0;
+    const int64_t ph = num_slices((int)p), ms = (int64_t)m * s, nsys = ph * s;
+    return Workspace::bytes_for(2 * ph * ms * ms, 8) + Workspace::bytes_for(2 * nsys, 8) +
+           Workspace::bytes_for(2 * ph * s * s, 8) + Workspace::bytes_for(2 * nsys * ms, 8) +
+           Workspace::bytes_for(2 * nsys * s * ms, 8) +
+           Workspace::bytes_for(2 * nsys * kern::proj_u_stride((int)s, m), 8) +
+           Workspace::bytes_for(nsys, 4);
+  }
+  void carve(Workspace& ws, int64_t s, int64_t p, int m) {
+    if (!possible(s)) return;
+    const int64_t ph = num_slices((int)p), ms = (int64_t)m * s, nsys = ph * s;
+    Hm = ws.take<double>(2 * ph * ms * ms);
+    lam = ws.take<double>(2 * nsys);
+    D = ws.take<double>(2 * ph * s * s);
+    z = ws.take<double>(2 * nsys * ms);
+    Wrk = ws.take<double>(2 * nsys * s * ms);
+    U = ws.take<double>(2 * nsys * kern::proj_u_stride((int)s, m));
+    info = ws.take<int>(nsys);
+  }
+};
+
 size_t tba_ws_bytes(int64_t n, int64_t s, int64_t p, int m) {
   const int64_t N = n * s * p, ldv = round_up(N, 64), ms = (int64_t)m * s;
   const int64_t part = tba_partial_elems(n, s, p, m);
@@ -106,7 +143,7 @@ size_t tba_ws_bytes(int64_t n, int64_t s, int64_t p, int m) {
          Workspace::bytes_for((int64_t)(m + 1) * ldv, 8) + Workspace::bytes_for(p * ms * s, 8) +
          2 * Workspace::bytes_for(p * s * s, 8) + Workspace::bytes_for(p * ms * s, 8) +
          Workspace::bytes_for(part, 8) + Workspace::bytes_for(kern::mdot_chunks(N) * 2, 8) +
-         Workspace::bytes_for(8, 8);
+         Workspace::bytes_for(8, 8) + ProjWS::bytes(s, p, m);
 }
 
 double dev_norm2(Ctx& ctx, const TbaWS& w, const double* v) {
@@ -238,11 +275,42 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
   w.part = ws.take<double>((int64_t)w.nchunks * 2);
   w.d_ww = ws.take<double>(8);
   const int ph = w.ph, si = (int)s, msi = (int)ms;
+  ProjWS pw;
+  pw.carve(ws, s, p, m);
 
   // Bhat (operator planes, unscaled) on the host for the projected solves.
   std::vector<double> hB((size_t)p * ss);
   TSYLV_HIP(hipMemcpyAsync(hB.data(), S.Bh, hB.size() * 8, hipMemcpyDeviceToHost, st));
   const double cnorm = std::sqrt(dev_norm2(ctx, w, S.Zc));
+  // Bhat_k = W_k diag(lam_k) W_k^{-1}, once per solve, for the device solve.
+  const char* force_host = std::getenv("TSYLV_TBA_HOST_PROJECTED");
+  bool dev_proj = ProjWS::possible(s) && !(force_host && force_host[0] == '1');
+  std::vector<std::vector<cplx>> Wk(ph), Wik(ph);
+  std::vector<cplx> lam_all((size_t)ph * si);
+  if (dev_proj) {
+    std::vector<double> kap(ph, INFINITY);
+    parallel_slices(ph, [&](int k) {
+      std::vector<cplx> T((size_t)ss), Uq((size_t)ss);
+      unpack(hB, (int)p, k, si, si, T.data());
+      Wk[k].assign((size_t)ss, 0.0);
+      Wik[k].assign((size_t)ss, 0.0);
+      if (!host::schur(T.data(), Uq.data(), si)) return;
+      kap[k] = host::eig_from_schur(T.data(), Uq.data(), si, &lam_all[(size_t)k * si],
+                                    Wk[k].data(), Wik[k].data());
+    });
+    for (int k = 0; k < ph; ++k) dev_proj = dev_proj && kap[k] < 1e8;
+    if (dev_proj)
+      TSYLV_HIP(hipMemcpyAsync(pw.lam, lam_all.data(), lam_all.size() * sizeof(cplx),
+                               hipMemcpyHostToDevice, st));
+  }
+  std::vector<cplx> hHm, hD, hz;
+  std::vector<int> hinfo;
+  if (dev_proj) {
+    hHm.resize((size_t)ph * msi * msi);
+    hD.resize((size_t)ph * ss);
+    hz.resize((size_t)ph * si * msi);
+    hinfo.resize((size_t)ph * si);
+  }
   info.steps = info.cycles = info.outer = 0;
   info.res_hist_len = 0;
   info.relres_est = 0.0;
@@ -322,23 +390,12 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
       }
       info.steps++;
     }
-    // Algorithm 8 step 3(b): H_m Y - Y B = [H0; 0] per slice (Algorithm 5 on the host)
+    // Algorithm 8 step 3(b): H_m Y - Y B = [H0; 0] per slice
     std::vector<int> good(ph, 1);
     double est2 = 0.0;
     std::vector<double> est_k(ph, 0.0);
-    parallel_slices(ph, [&](int k) {
+    auto finish_slice = [&](int k, const std::vector<cplx>& Yk) {
       const int ldh = msi + si;
-      std::vector<cplx> Hm((size_t)msi * msi), Bk((size_t)si * si), C1((size_t)msi * si, 0.0),
-          Yk((size_t)msi * si);
-      for (int c = 0; c < msi; ++c)
-        for (int r = 0; r < msi; ++r) Hm[r + (size_t)msi * c] = Hk[k][r + (size_t)ldh * c];
-      unpack(hB, (int)p, k, si, si, Bk.data());
-      for (int c = 0; c < si; ++c)
-        for (int r = 0; r < si; ++r) C1[r + (size_t)msi * c] = H0[k][r + (size_t)si * c];
-      if (!host::sylvester_banded(Hm.data(), msi, si, Bk.data(), si, C1.data(), Yk.data())) {
-        good[k] = 0;
-        return;
-      }
       pack(Yk.data(), (int)p, k, msi, si, hY);
       // residual estimate: || H_{m+1,m} Y_m ||_F for this slice
       double e = 0.0;
@@ -351,7 +408,58 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
           e += (k == 0 || 2 * k == (int)p) ? v.real() * v.real() : std::norm(v);
         }
       est_k[k] = e;
-    });
+    };
+    bool dev_done = false;
+    if (dev_proj) {
+      // device: (Hm_k - lam_{k,j} I) z_{k,j} = (H0_k W_k) e_j, then Y_k = Z_k W_k^{-1}
+      parallel_slices(ph, [&](int k) {
+        const int ldh = msi + si;
+        for (int c = 0; c < msi; ++c)
+          for (int r = 0; r < msi; ++r)
+            hHm[(size_t)k * msi * msi + r + (size_t)msi * c] = Hk[k][r + (size_t)ldh * c];
+        host::matmul(H0[k].data(), Wk[k].data(), &hD[(size_t)k * ss], si, si, si);
+      });
+      TSYLV_HIP(hipMemcpyAsync(pw.Hm, hHm.data(), hHm.size() * sizeof(cplx),
+                               hipMemcpyHostToDevice, st));
+      TSYLV_HIP(hipMemcpyAsync(pw.D, hD.data(), hD.size() * sizeof(cplx), hipMemcpyHostToDevice,
+                               st));
+      kern::proj_solve(pw.Hm, pw.lam, pw.D, pw.z, pw.Wrk, pw.U, pw.info, msi, si, m, ph * si, st);
+      TSYLV_HIP(hipMemcpyAsync(hz.data(), pw.z, hz.size() * sizeof(cplx), hipMemcpyDeviceToHost,
+                               st));
+      TSYLV_HIP(hipMemcpyAsync(hinfo.data(), pw.info, hinfo.size() * sizeof(int),
+                               hipMemcpyDeviceToHost, st));
+      ctx.sync();
+      bool fine = true;
+      for (size_t i = 0; i < hinfo.size(); ++i) fine = fine && hinfo[i] == 0;
+      for (size_t i = 0; fine && i < hz.size(); ++i)
+        fine = std::isfinite(hz[i].real()) && std::isfinite(hz[i].imag());
+      if (fine) {
+        parallel_slices(ph, [&](int k) {
+          std::vector<cplx> Yk((size_t)msi * si);
+          host::matmul(&hz[(size_t)k * si * msi], Wik[k].data(), Yk.data(), msi, si, si);
+          finish_slice(k, Yk);
+        });
+        dev_done = true;
+      }
+    }
+    if (!dev_done) {
+      // host: Bartels-Stewart with the Schur form of Bhat_k (Algorithm 5)
+      parallel_slices(ph, [&](int k) {
+        const int ldh = msi + si;
+        std::vector<cplx> Hm((size_t)msi * msi), Bk((size_t)si * si), C1((size_t)msi * si, 0.0),
+            Yk((size_t)msi * si);
+        for (int c = 0; c < msi; ++c)
+          for (int r = 0; r < msi; ++r) Hm[r + (size_t)msi * c] = Hk[k][r + (size_t)ldh * c];
+        unpack(hB, (int)p, k, si, si, Bk.data());
+        for (int c = 0; c < si; ++c)
+          for (int r = 0; r < si; ++r) C1[r + (size_t)msi * c] = H0[k][r + (size_t)si * c];
+        if (!host::sylvester_banded(Hm.data(), msi, si, Bk.data(), si, C1.data(), Yk.data())) {
+          good[k] = 0;
+          return;
+        }
+        finish_slice(k, Yk);
+      });
+    }
     for (int k = 0; k < ph; ++k) {
       if (!good[k]) throw Error(TSYLV_ESINGULAR, "projected Sylvester equation");
       est2 += est_k[k];

@@ -58,6 +58,19 @@ int main() {
     bool ok = tsylv::host::sylvester_banded(H.data(), ms, band, B.data(), s, C.data(), Y.data());
     std::printf("%d\n", ok ? 1 : 0);
     write_mat(Y);
+  } else if (cmd == "eig") {
+    int n;
+    std::cin >> n;
+    auto A = read_mat((size_t)n * n);
+    std::vector<cplx> U((size_t)n * n), lam(n), W((size_t)n * n), Wi((size_t)n * n);
+    bool ok = tsylv::host::schur(A.data(), U.data(), n);
+    double kappa = ok ? tsylv::host::eig_from_schur(A.data(), U.data(), n, lam.data(), W.data(),
+                                                   Wi.data())
+                      : -1.0;
+    std::printf("%d %.17g\n", ok ? 1 : 0, kappa);
+    write_mat(lam);
+    write_mat(W);
+    write_mat(Wi);
   }
   return 0;
 }

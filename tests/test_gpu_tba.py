@@ -120,3 +120,23 @@ def test_medium_dense_vs_tbs():
     X, info = gpu_tba(A, B, C, m=4, tol=1e-11, max_cycles=100)
     assert info.status == 0, info.as_dict()
     assert rel(X, tbs.t_bartels_stewart(A, B, C)) <= 1e-8
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,s,p,m", [(24, 3, 3, 3), (40, 5, 6, 3), (200, 16, 4, 4), (260, 64, 3, 3),
+                                     (140, 65, 2, 1), (96, 1, 5, 7)])
+def test_device_and_host_projected_solves_agree(n, s, p, m, monkeypatch):
+    """The projected equation of a TBAS cycle solved on the device (Bhat_k
+    diagonalised, p_h s shifted block-Hessenberg systems) and on the host
+    (Bartels-Stewart with the Schur form of Bhat_k): the same cycle iterate.
+    s = 65 exceeds the device kernel's block limit and takes the host path in
+    both runs."""
+    say("tba projected device vs host", n, s, p, m)
+    A, B, C = workloads.dense_shifted(n, s, p, seed=n + s)
+    Xd, idv = gpu_tba(A, B, C, m=m, tol=1e-300, max_cycles=1)
+    monkeypatch.setenv("TSYLV_TBA_HOST_PROJECTED", "1")
+    Xh, ihs = gpu_tba(A, B, C, m=m, tol=1e-300, max_cycles=1)
+    assert idv.status == 1 and ihs.status == 1, (idv.as_dict(), ihs.as_dict())
+    assert rel(Xd, Xh) <= 1e-10
+    assert idv.relres_est == pytest.approx(ihs.relres_est, rel=1e-8, abs=1e-15)
+    assert idv.relres_true == pytest.approx(ihs.relres_true, rel=1e-8)

@@ -108,3 +108,33 @@ def test_sylvester_banded(exe, m, s):
     assert out[0] == "1"
     Y, _ = parse(out, 1, (ms, s))
     np.testing.assert_allclose(Y, scipy.linalg.solve_sylvester(H, -B, C1), atol=1e-10)
+
+
+@pytest.mark.parametrize("n,real", [(1, False), (3, True), (8, False), (24, True), (64, False)])
+def test_eig_from_schur(exe, n, real):
+    """B = W diag(lam) W^{-1} (the diagonalisation the device projected solve
+    of TBAS uses), against the definition and numpy's eigenvalues."""
+    rng = np.random.default_rng(100 + n)
+    B = rng.standard_normal((n, n)) / np.sqrt(n) if real else crand(rng, n, n) / np.sqrt(2 * n)
+    B -= 4 * np.eye(n)
+    out = run(exe, "eig %d" % n, [B])
+    ok, kappa = out[0].split()
+    assert ok == "1" and np.isfinite(float(kappa)) and float(kappa) >= 1.0
+    lam, pos = parse(out, 1, (n, 1))
+    W, pos = parse(out, pos, (n, n))
+    Wi, _ = parse(out, pos, (n, n))
+    lam = lam.ravel()
+    np.testing.assert_allclose(Wi @ W, np.eye(n), atol=1e-11 * float(kappa))
+    np.testing.assert_allclose(B @ W, W * lam[None, :], atol=1e-11 * n)
+    np.testing.assert_allclose(np.linalg.norm(W, axis=0), 1.0, atol=1e-12)
+    ev = np.linalg.eigvals(B)
+    assert np.abs(lam[:, None] - ev[None, :]).min(axis=1).max() <= 1e-10
+    assert np.abs(ev[:, None] - lam[None, :]).min(axis=1).max() <= 1e-10
+
+
+def test_eig_from_schur_defective(exe):
+    """A Jordan block has no eigenvector basis: infinite condition."""
+    B = np.array([[2.0, 1.0], [0.0, 2.0]])
+    out = run(exe, "eig 2", [B])
+    ok, kappa = out[0].split()
+    assert ok == "1" and not np.isfinite(float(kappa))
