@@ -227,29 +227,62 @@ __global__ __launch_bounds__(kPB) void proj_panel_kernel(ProjArgs a, int b) {
       tile[r + LD * cc] = v;
     }
     __syncthreads();
+    // Thread (rr, g): row rr, tile columns g, g + G, ... (at most CPT of
+    // them), so each L entry read from LDS serves all of the thread's columns.
+    constexpr int CPT = kTC / (kPB / kPMax);
+    const int G = kPB / s, rr = tid % s, g = tid / s;
+    const bool act = g < G;
     // U rows: L11^{-1} times the top half (X holds L11^{-1} below the diagonal)
-    double2 u[(kPMax * kTC + kPB - 1) / kPB];
-    int nu = 0;
-    for (int e = tid; e < s * kTC; e += kPB, ++nu) {
-      const int r = e % s, cc = e / s;
-      double2 t = tile[r + LD * cc];
-      for (int l = 0; l < r; ++l) t = cadd(t, cmul(P[r + LD * l], tile[l + LD * cc]));
-      u[nu] = t;
+    double2 acc[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int cc = g + G * q;
+      acc[q] = (act && cc < kTC) ? tile[rr + LD * cc] : make_double2(0.0, 0.0);
+    }
+    if (act) {
+#pragma unroll 4
+      for (int l = 0; l < rr; ++l) {
+        const double2 x = P[rr + LD * l];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          const int cc = g + G * q;
+          if (cc < kTC) acc[q] = cadd(acc[q], cmul(x, tile[l + LD * cc]));
+        }
+      }
     }
     __syncthreads();
-    nu = 0;
-    for (int e = tid; e < s * kTC; e += kPB, ++nu) {
-      const int r = e % s, cc = e / s, gc = col + cc;
-      tile[r + LD * cc] = u[nu];
-      if (gc < ms) Ub[r + (int64_t)s * (gc - col0)] = u[nu];
+    if (act) {
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int cc = g + G * q, gc = col + cc;
+        if (cc < kTC) {
+          tile[rr + LD * cc] = acc[q];
+          if (gc < ms) Ub[rr + (int64_t)s * (gc - col0)] = acc[q];
+        }
+      }
     }
     __syncthreads();
     // next row block: bottom half minus L21 times the U rows
-    for (int e = tid; e < s * kTC; e += kPB) {
-      const int r = e % s, cc = e / s, gc = col + cc;
-      double2 t = tile[s + r + LD * cc];
-      for (int l = 0; l < s; ++l) t = csub(t, cmul(P[s + r + LD * l], tile[l + LD * cc]));
-      if (gc < ms) W[r + (int64_t)s * gc] = t;
+    if (act) {
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int cc = g + G * q;
+        acc[q] = cc < kTC ? tile[s + rr + LD * cc] : make_double2(0.0, 0.0);
+      }
+#pragma unroll 4
+      for (int l = 0; l < s; ++l) {
+        const double2 x = P[s + rr + LD * l];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          const int cc = g + G * q;
+          if (cc < kTC) acc[q] = csub(acc[q], cmul(x, tile[l + LD * cc]));
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int cc = g + G * q, gc = col + cc;
+        if (cc < kTC && gc < ms) W[rr + (int64_t)s * gc] = acc[q];
+      }
     }
     __syncthreads();
   }

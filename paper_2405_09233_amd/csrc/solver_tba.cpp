@@ -57,7 +57,7 @@ using host::cplx;
 constexpr double kEps = 2.220446049250313e-16;
 
 // Planar buffer [plane][col][row] <-> per-slice complex matrix (column-major).
-void unpack(const std::vector<double>& buf, int p, int k, int rows, int cols, cplx* out) {
+void unpack(const double* buf, int p, int k, int rows, int cols, cplx* out) {
   int qr, qi;
   slice_planes(p, k, qr, qi);
   const size_t pl = (size_t)rows * cols;
@@ -65,7 +65,7 @@ void unpack(const std::vector<double>& buf, int p, int k, int rows, int cols, cp
     out[e] = cplx(buf[qr * pl + e], qi < 0 ? 0.0 : buf[qi * pl + e]);
 }
 
-void pack(const cplx* in, int p, int k, int rows, int cols, std::vector<double>& buf) {
+void pack(const cplx* in, int p, int k, int rows, int cols, double* buf) {
   int qr, qi;
   slice_planes(p, k, qr, qi);
   const size_t pl = (size_t)rows * cols;
@@ -74,6 +74,21 @@ void pack(const cplx* in, int p, int k, int rows, int cols, std::vector<double>&
     if (qi >= 0) buf[qi * pl + e] = in[e].imag();
   }
 }
+
+// Page-locked host memory for the per-step transfers of a solve.
+struct PinnedBuf {
+  double* p = nullptr;
+  explicit PinnedBuf(size_t count) {
+    void* h = nullptr;
+    TSYLV_HIP(hipHostMalloc(&h, std::max<size_t>(count, 1) * sizeof(double), hipHostMallocDefault));
+    p = static_cast<double*>(h);
+  }
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+};
 
 template <typename F>
 void parallel_slices(int ph, F&& f) {
@@ -162,10 +177,9 @@ double dev_norm2(Ctx& ctx, const TbaWS& w, const double* v) {
 // for the tube test.  Returns false on a non-invertible tube (Normalization
 // breakdown).
 bool tubal_qr(Ctx& ctx, const TbaWS& w, const double* Win, double* Qout,
-              std::vector<std::vector<cplx>>& Rk, bool scaled) {
+              std::vector<std::vector<cplx>>& Rk, bool scaled, double* hbuf, double* rinv) {
   const int s = (int)w.s, p = (int)w.p, ph = w.ph;
   const int64_t n = w.n, ns = n * w.s, ss = w.s * w.s;
-  std::vector<double> hbuf((size_t)p * ss);
   std::vector<std::vector<cplx>> Racc(ph, std::vector<cplx>((size_t)s * s));
   bool ok = true;
   const double* src = Win;
@@ -177,9 +191,9 @@ bool tubal_qr(Ctx& ctx, const TbaWS& w, const double* Win, double* Qout,
     // Gram of every slice: W_k^H W_k
     kern::zgemm(kern::dense_pmat(src, ns, n), true, kern::dense_pmat(src, ns, n), w.Gq, ss,
                 w.s, w.s, w.s, n, 1.0, 0.0, p, w.partial, ctx.stream);
-    TSYLV_HIP(hipMemcpyAsync(hbuf.data(), w.Gq, hbuf.size() * 8, hipMemcpyDeviceToHost, ctx.stream));
+    TSYLV_HIP(hipMemcpyAsync(hbuf, w.Gq, (size_t)p * ss * 8, hipMemcpyDeviceToHost, ctx.stream));
     ctx.sync();
-    std::vector<double> rinv((size_t)p * ss, 0.0);
+    std::fill(rinv, rinv + (size_t)p * ss, 0.0);
     std::vector<int> good(ph, 1);
     parallel_slices(ph, [&](int k) {
       std::vector<cplx> G((size_t)s * s), Ri((size_t)s * s);
@@ -205,7 +219,7 @@ bool tubal_qr(Ctx& ctx, const TbaWS& w, const double* Win, double* Qout,
     });
     for (int k = 0; k < ph; ++k) ok = ok && good[k];
     if (!ok) return false;
-    TSYLV_HIP(hipMemcpyAsync(w.Rinv, rinv.data(), rinv.size() * 8, hipMemcpyHostToDevice,
+    TSYLV_HIP(hipMemcpyAsync(w.Rinv, rinv, (size_t)p * ss * 8, hipMemcpyHostToDevice,
                              ctx.stream));
     // passes alternate between the two buffers and end in Qout
     double* dst = ((kPasses - 1 - pass) % 2 == 0) ? Qout : w.T;
@@ -291,7 +305,7 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
     std::vector<double> kap(ph, INFINITY);
     parallel_slices(ph, [&](int k) {
       std::vector<cplx> T((size_t)ss), Uq((size_t)ss);
-      unpack(hB, (int)p, k, si, si, T.data());
+      unpack(hB.data(), (int)p, k, si, si, T.data());
       Wk[k].assign((size_t)ss, 0.0);
       Wik[k].assign((size_t)ss, 0.0);
       if (!host::schur(T.data(), Uq.data(), si)) return;
@@ -303,13 +317,35 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
       TSYLV_HIP(hipMemcpyAsync(pw.lam, lam_all.data(), lam_all.size() * sizeof(cplx),
                                hipMemcpyHostToDevice, st));
   }
-  std::vector<cplx> hHm, hD, hz;
-  std::vector<int> hinfo;
+  // page-locked staging for everything that crosses PCIe every step / cycle
+  const size_t nss = (size_t)p * ss, nG = (size_t)p * ms * s;
+  const size_t nHm = (size_t)ph * msi * msi, nD = (size_t)ph * ss, nz = (size_t)ph * si * msi,
+               ninfo = (size_t)ph * si;
+  size_t total = 2 * nss + 3 * nG;
+  if (dev_proj) total += 2 * (nHm + nD + nz) + (ninfo + 1) / 2;
+  PinnedBuf pin(total);
+  double* q = pin.p;
+  double* qr_buf = q;
+  q += nss;
+  double* qr_rinv = q;
+  q += nss;
+  double* hG = q;
+  q += nG;
+  double* hG2 = q;
+  q += nG;
+  double* hY = q;
+  q += nG;
+  std::fill(hY, hY + nG, 0.0);
+  cplx *hHm = nullptr, *hD = nullptr, *hz = nullptr;
+  int* hinfo = nullptr;
   if (dev_proj) {
-    hHm.resize((size_t)ph * msi * msi);
-    hD.resize((size_t)ph * ss);
-    hz.resize((size_t)ph * si * msi);
-    hinfo.resize((size_t)ph * si);
+    hHm = reinterpret_cast<cplx*>(q);
+    q += 2 * nHm;
+    hD = reinterpret_cast<cplx*>(q);
+    q += 2 * nD;
+    hz = reinterpret_cast<cplx*>(q);
+    q += 2 * nz;
+    hinfo = reinterpret_cast<int*>(q);
   }
   info.steps = info.cycles = info.outer = 0;
   info.res_hist_len = 0;
@@ -325,7 +361,6 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
   std::vector<std::vector<cplx>> Hk(ph, std::vector<cplx>((size_t)(ms + s) * ms));
   std::vector<std::vector<cplx>> H0(ph, std::vector<cplx>((size_t)ss));
   std::vector<std::vector<cplx>> Rq(ph, std::vector<cplx>((size_t)ss));
-  std::vector<double> hG((size_t)p * ms * s), hG2((size_t)p * ms * s), hY((size_t)p * ms * s, 0.0);
   int status = TSYLV_NOT_CONVERGED;
 
   for (int cycle = 0;; ++cycle) {
@@ -344,7 +379,8 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
     if (cycle >= o.max_cycles) break;
     info.cycles++;
     // Algorithm 7 step 2: [V_1, H0] = Tubal-QR(R0)
-    if (!tubal_qr(ctx, w, w.R, w.V(0), H0, true)) throw Error(TSYLV_EBREAKDOWN, "Tubal-QR(R0)");
+    if (!tubal_qr(ctx, w, w.R, w.V(0), H0, true, qr_buf, qr_rinv))
+      throw Error(TSYLV_EBREAKDOWN, "Tubal-QR(R0)");
     for (auto& h : Hk) std::fill(h.begin(), h.end(), cplx(0.0));
     for (int j = 0; j < m; ++j) {
       const int64_t J = (int64_t)(j + 1) * s;
@@ -361,8 +397,8 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
                     (int)p, w.partial, st);
         kern::zgemm(Vb, false, kern::dense_pmat(w.G, J * s, J), W, ns, n, n, s, J, -1.0, 1.0,
                     (int)p, nullptr, st);
-        std::vector<double>& dst = pass == 0 ? hG : hG2;
-        TSYLV_HIP(hipMemcpyAsync(dst.data(), w.G, (size_t)p * J * s * 8, hipMemcpyDeviceToHost, st));
+        double* dst = pass == 0 ? hG : hG2;
+        TSYLV_HIP(hipMemcpyAsync(dst, w.G, (size_t)p * J * s * 8, hipMemcpyDeviceToHost, st));
       }
       if (ctx.prof.on()) ctx.prof.end(TSYLV_K_ORTHO, st);
       ctx.sync();
@@ -377,7 +413,7 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
             Hk[k][r + (size_t)ldh * (j * si + c)] = g1[r + (size_t)Ji * c] + g2[r + (size_t)Ji * c];
       });
       // Tubal-QR(W) -> V_{j+1}, H_{j+1,j}
-      const bool qr_ok = tubal_qr(ctx, w, W, W, Rq, false);
+      const bool qr_ok = tubal_qr(ctx, w, W, W, Rq, false, qr_buf, qr_rinv);
       if (!qr_ok) {
         if (j < m - 1) throw Error(TSYLV_EBREAKDOWN, "Tubal-QR in TBA");
         for (auto& r : Rq) std::fill(r.begin(), r.end(), cplx(0.0));  // H_{m+1,m} = 0
@@ -419,19 +455,15 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
             hHm[(size_t)k * msi * msi + r + (size_t)msi * c] = Hk[k][r + (size_t)ldh * c];
         host::matmul(H0[k].data(), Wk[k].data(), &hD[(size_t)k * ss], si, si, si);
       });
-      TSYLV_HIP(hipMemcpyAsync(pw.Hm, hHm.data(), hHm.size() * sizeof(cplx),
-                               hipMemcpyHostToDevice, st));
-      TSYLV_HIP(hipMemcpyAsync(pw.D, hD.data(), hD.size() * sizeof(cplx), hipMemcpyHostToDevice,
-                               st));
+      TSYLV_HIP(hipMemcpyAsync(pw.Hm, hHm, nHm * sizeof(cplx), hipMemcpyHostToDevice, st));
+      TSYLV_HIP(hipMemcpyAsync(pw.D, hD, nD * sizeof(cplx), hipMemcpyHostToDevice, st));
       kern::proj_solve(pw.Hm, pw.lam, pw.D, pw.z, pw.Wrk, pw.U, pw.info, msi, si, m, ph * si, st);
-      TSYLV_HIP(hipMemcpyAsync(hz.data(), pw.z, hz.size() * sizeof(cplx), hipMemcpyDeviceToHost,
-                               st));
-      TSYLV_HIP(hipMemcpyAsync(hinfo.data(), pw.info, hinfo.size() * sizeof(int),
-                               hipMemcpyDeviceToHost, st));
+      TSYLV_HIP(hipMemcpyAsync(hz, pw.z, nz * sizeof(cplx), hipMemcpyDeviceToHost, st));
+      TSYLV_HIP(hipMemcpyAsync(hinfo, pw.info, ninfo * sizeof(int), hipMemcpyDeviceToHost, st));
       ctx.sync();
       bool fine = true;
-      for (size_t i = 0; i < hinfo.size(); ++i) fine = fine && hinfo[i] == 0;
-      for (size_t i = 0; fine && i < hz.size(); ++i)
+      for (size_t i = 0; i < ninfo; ++i) fine = fine && hinfo[i] == 0;
+      for (size_t i = 0; fine && i < nz; ++i)
         fine = std::isfinite(hz[i].real()) && std::isfinite(hz[i].imag());
       if (fine) {
         parallel_slices(ph, [&](int k) {
@@ -450,7 +482,7 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
             Yk((size_t)msi * si);
         for (int c = 0; c < msi; ++c)
           for (int r = 0; r < msi; ++r) Hm[r + (size_t)msi * c] = Hk[k][r + (size_t)ldh * c];
-        unpack(hB, (int)p, k, si, si, Bk.data());
+        unpack(hB.data(), (int)p, k, si, si, Bk.data());
         for (int c = 0; c < si; ++c)
           for (int r = 0; r < si; ++r) C1[r + (size_t)msi * c] = H0[k][r + (size_t)si * c];
         if (!host::sylvester_banded(Hm.data(), msi, si, Bk.data(), si, C1.data(), Yk.data())) {
@@ -468,7 +500,7 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
     if (o.res_hist && info.res_hist_len < o.res_hist_cap)
       o.res_hist[info.res_hist_len++] = info.relres_est;
     // Algorithm 8 step 3(c): X = X0 + V_m Y
-    TSYLV_HIP(hipMemcpyAsync(w.Y, hY.data(), hY.size() * 8, hipMemcpyHostToDevice, st));
+    TSYLV_HIP(hipMemcpyAsync(w.Y, hY, nG * 8, hipMemcpyHostToDevice, st));
     kern::zgemm(kern::PMat{w.basis, ns, n, s, w.ldv}, false, kern::dense_pmat(w.Y, ms * s, ms),
                 S.Zx, ns, n, n, s, ms, 1.0, 1.0, (int)p, nullptr, st);
     ctx.sync();
