@@ -118,8 +118,9 @@ def measured_traffic(path, shape):
 def run_path(ctx, tsylv, dev_in, opts, steps, warmup, name):
     import torch
     Ad, Bd, Cd, Xd = dev_in
+    solve = ctx.tba if name == "tba" else ctx.gmres
     for w in range(warmup):
-        _, info = ctx.gmres(Ad, Bd, Cd, X=Xd, opts=opts)
+        _, info = solve(Ad, Bd, Cd, X=Xd, opts=opts)
         log("%s warmup %d: status=%d steps=%d cycles=%d relres=%.3e %.3fs"
             % (name, w, info.status, info.steps, info.cycles, info.relres_true, info.seconds))
     ctx.profile(True)
@@ -128,7 +129,7 @@ def run_path(ctx, tsylv, dev_in, opts, steps, warmup, name):
     t_start = time.perf_counter()
     for k in range(steps):
         ts = time.perf_counter()
-        _, info = ctx.gmres(Ad, Bd, Cd, X=Xd, opts=opts)
+        _, info = solve(Ad, Bd, Cd, X=Xd, opts=opts)
         lat.append(time.perf_counter() - ts)
         infos.append(info.as_dict())
         log("%s solve %d: status=%d steps=%d cycles=%d relres=%.3e %.3fs"
@@ -172,7 +173,7 @@ def main():
                          "BF16 path, 32 for the FP32 path, the fastest in a sweep of 16..48)")
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--paths", default="fp64,mixed,bf16")
+    ap.add_argument("--paths", default="fp64,mixed,bf16,tba")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--grid", type=int, nargs=2, default=[64, 64])
     ap.add_argument("--s", type=int, default=64)
@@ -217,16 +218,20 @@ def main():
         "bf16": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.BF16,
                                    inner_m=args.inner_m or 24,
                                    inner_tol=args.inner_tol, tol=args.tol, max_outer=300),
+        # TBAS(10), reported beside the tGMRES paths (not a candidate for value)
+        "tba": tsylv.default_opts(tsylv.TBA, m=10, tol=args.tol, max_cycles=500),
     }
+    method = {"fp64": tsylv.GMRES, "mixed": tsylv.GMRES, "bf16": tsylv.GMRES, "tba": tsylv.TBA}
     paths = [x for x in args.paths.split(",") if x]
-    need = max(tsylv.workspace_bytes(tsylv.GMRES, n, s, p, path_opts[x]) for x in paths)
+    need = max(tsylv.workspace_bytes(method[x], n, s, p, path_opts[x]) for x in paths)
     ctx = tsylv.Context(need + (64 << 20), device=0)
     res = {}
     for name in paths:
-        res[name] = run_path(ctx, tsylv, (Ad, Bd, Cd, Xd), path_opts[name], args.steps,
-                             args.warmup, name)
+        # one TBAS solve takes seconds: two timed solves, no warm-up
+        st_, wu_ = (min(args.steps, 2), 0) if name == "tba" else (args.steps, args.warmup)
+        res[name] = run_path(ctx, tsylv, (Ad, Bd, Cd, Xd), path_opts[name], st_, wu_, name)
 
-    valid = [x for x in paths if res[x]["valid"]]
+    valid = [x for x in paths if res[x]["valid"] and x != "tba"]
     best = max(valid, key=lambda x: res[x]["solves_per_s"]) if valid else paths[0]
     r = res[best]
     elem = {"fp64": (8, 8), "mixed": (4, 4), "bf16": (2, 4)}[best]

@@ -227,7 +227,7 @@ struct WgPlan {
   int wr, wc;   // workgroups per real / complex slice and column tile
 };
 
-template <int CB, int D, int P, int NW, bool CPLX>
+template <int CB, int D, int P, int NW, int R, bool CPLX>
 __device__ __forceinline__ void bf16_wg_tasks(const Bf16Args& a, const WgPlan& pl, int k,
                                               int64_t rb_begin, int64_t rb_count, int64_t cb0,
                                               uint16_t* lds) {
@@ -250,13 +250,21 @@ __device__ __forceinline__ void bf16_wg_tasks(const Bf16Args& a, const WgPlan& p
     Vsrc[v] = a.Vt + (((int64_t)q * a.ncb + cb0 + j) * nkb + kl) * 512 + lane * 8;
   }
   const int64_t nph = nkb / P;
-  const int64_t ntask = (rb_count + NW - 1) / NW;
+  const int64_t ntask = (rb_count + NW * R - 1) / (NW * R);
   for (int64_t task = 0; task < ntask; ++task) {
-    const int64_t rb_want = rb_begin + task * NW + wave;
-    const bool store = rb_want < rb_begin + rb_count && rb_want < nrb_real;
-    const int64_t rb = min(rb_want, a.nrb - 1);  // past the end: any valid block, not stored
-    const uint16_t* Ar = a.At + ((int64_t)qr * a.nrb + rb) * nkb * 512 + lane * 8;
-    const uint16_t* Ai = CPLX ? a.At + ((int64_t)qi * a.nrb + rb) * nkb * 512 + lane * 8 : nullptr;
+    // this wave's R consecutive row blocks
+    const uint16_t* Ar[R];
+    const uint16_t* Ai[R];
+    int64_t rbs[R];
+    bool store[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t rb_want = rb_begin + (task * NW + wave) * R + r;
+      store[r] = rb_want < rb_begin + rb_count && rb_want < nrb_real;
+      rbs[r] = min(rb_want, a.nrb - 1);  // past the end: any valid block, not stored
+      Ar[r] = a.At + ((int64_t)qr * a.nrb + rbs[r]) * nkb * 512 + lane * 8;
+      Ai[r] = CPLX ? a.At + ((int64_t)qi * a.nrb + rbs[r]) * nkb * 512 + lane * 8 : nullptr;
+    }
     u16x8 stage[NPASS];
     auto fetch = [&](int64_t ph) {
 #pragma unroll
@@ -274,16 +282,21 @@ __device__ __forceinline__ void bf16_wg_tasks(const Bf16Args& a, const WgPlan& p
           bf8, *reinterpret_cast<const u16x8*>(
                    lds + ((int64_t)buf * CH + kl * CPK + pln * CB + j) * 512 + lane * 8));
     };
-    f4 accr[1][CB], acci[1][CB];
+    f4 accr[R][CB], acci[R][CB];
 #pragma unroll
-    for (int j = 0; j < CB; ++j) {
-      accr[0][j] = f4{0.f, 0.f, 0.f, 0.f};
-      acci[0][j] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-    bf8 ar[D], ai[D];
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        accr[r][j] = f4{0.f, 0.f, 0.f, 0.f};
+        acci[r][j] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+    bf8 ar[D][R], ai[D][R];
     auto loadA = [&](int64_t kb, int u) {
-      ar[u] = ld8(Ar + kb * 512);
-      if (CPLX) ai[u] = ld8(Ai + kb * 512);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        ar[u][r] = ld8(Ar[r] + kb * 512);
+        if (CPLX) ai[u][r] = ld8(Ai[r] + kb * 512);
+      }
     };
     fetch(0);
 #pragma unroll
@@ -303,15 +316,18 @@ __device__ __forceinline__ void bf16_wg_tasks(const Bf16Args& a, const WgPlan& p
           br[j] = frag(buf, u, 0, j);
           if (CPLX) bi[j] = frag(buf, u, 1, j);
         }
-        bf8 mai;
-        if (CPLX) mai = neg8(ai[d]);
 #pragma unroll
-        for (int j = 0; j < CB; ++j) {
-          accr[0][j] = mma(ar[d], br[j], accr[0][j]);
-          if (CPLX) {
-            acci[0][j] = mma(ar[d], bi[j], acci[0][j]);
-            accr[0][j] = mma(mai, bi[j], accr[0][j]);
-            acci[0][j] = mma(ai[d], br[j], acci[0][j]);
+        for (int r = 0; r < R; ++r) {
+          bf8 mai;
+          if (CPLX) mai = neg8(ai[d][r]);
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            accr[r][j] = mma(ar[d][r], br[j], accr[r][j]);
+            if (CPLX) {
+              acci[r][j] = mma(ar[d][r], bi[j], acci[r][j]);
+              accr[r][j] = mma(mai, bi[j], accr[r][j]);
+              acci[r][j] = mma(ai[d][r], br[j], acci[r][j]);
+            }
           }
         }
         // keep the refill right behind the MFMAs that free its slot
@@ -322,11 +338,21 @@ __device__ __forceinline__ void bf16_wg_tasks(const Bf16Args& a, const WgPlan& p
       put(buf ^ 1);
       __syncthreads();
     }
-    if (store) bf16_finish<CB, 1, CPLX>(a, qr, qi, rb, cb0, accr, acci);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!store[r]) continue;
+      f4 fr[1][CB], fi[1][CB];
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        fr[0][j] = accr[r][j];
+        fi[0][j] = acci[r][j];
+      }
+      bf16_finish<CB, 1, CPLX>(a, qr, qi, rbs[r], cb0, fr, fi);
+    }
   }
 }
 
-template <int CB, int D, int P, int NW>
+template <int CB, int D, int P, int NW, int R>
 __global__ __launch_bounds__(NW * 64) void apply_bf16_wg_kernel(Bf16Args a, WgPlan pl) {
   extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
   const int t = xcd_tile(blockIdx.x, a.total);
@@ -345,9 +371,9 @@ __global__ __launch_bounds__(NW * 64) void apply_bf16_wg_kernel(Bf16Args a, WgPl
   const int64_t rb_begin = (int64_t)w * span;
   const int64_t cb0 = (int64_t)ct * CB;
   if (real)
-    bf16_wg_tasks<CB, D, P, NW, false>(a, pl, k, rb_begin, span, cb0, lds);
+    bf16_wg_tasks<CB, D, P, NW, R, false>(a, pl, k, rb_begin, span, cb0, lds);
   else
-    bf16_wg_tasks<CB, D, P, NW, true>(a, pl, k, rb_begin, span, cb0, lds);
+    bf16_wg_tasks<CB, D, P, NW, R, true>(a, pl, k, rb_begin, span, cb0, lds);
 }
 
 // Row blocks are padded to a multiple of kRowPad and column blocks to a
@@ -376,18 +402,19 @@ inline WgPlan plan_wg(int64_t n, int p, int nct, int nw, int ncu) {
   return best;
 }
 
-template <int CB, int D, int P, int NW>
+template <int CB, int D, int P, int NW, int R>
 void launch_wg(Bf16Args a, int ncu, hipStream_t st) {
   static_assert(kKPad % P == 0 && P % D == 0, "phase and ring must divide the k padding");
   a.nct = (int)((a.s + 16 * CB - 1) / (16 * CB));
-  const WgPlan pl = plan_wg(a.n, a.p, a.nct, NW, ncu);
+  const WgPlan pl = plan_wg(a.n, a.p, a.nct, NW * R, ncu);
   const int nsl = num_slices(a.p), nreal = (a.p % 2 == 0 && a.p > 1) ? 2 : 1;
   a.total = a.nct * (nreal * pl.wr + (nsl - nreal) * pl.wc);
   const size_t lds = 2 * (size_t)P * 2 * CB * 1024;  // two buffers of complex phases
-  TSYLV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_bf16_wg_kernel<CB, D, P, NW>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((apply_bf16_wg_kernel<CB, D, P, NW>), dim3(a.total), dim3(NW * 64), lds, st,
-                     a, pl);
+  TSYLV_HIP(hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&apply_bf16_wg_kernel<CB, D, P, NW, R>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((apply_bf16_wg_kernel<CB, D, P, NW, R>), dim3(a.total), dim3(NW * 64), lds,
+                     st, a, pl);
   TSYLV_LAUNCH_CHECK();
 }
 
@@ -444,14 +471,17 @@ void apply_bf16(const uint16_t* At, const uint16_t* Bb, const float* V, uint16_t
   int dev = 0, ncu = 0;
   TSYLV_HIP(hipGetDevice(&dev));
   TSYLV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  // (column blocks, ring depth, phase length, waves) from a sweep at
-  // n = 4096, p = 32, s = 16 / 32 / 64 and n = 8192, p = 64, s = 128
+  // (column blocks, ring depth, phase length, waves, row blocks per wave)
+  // from a sweep at n = 4096, p = 32, s = 16 / 32 / 64 and n = 8192, p = 64,
+  // s = 128
   if (s <= 16)
-    launch_wg<1, 8, 8, 4>(a, ncu, st);
+    launch_wg<1, 8, 8, 4, 1>(a, ncu, st);
   else if (s <= 32)
-    launch_wg<2, 8, 8, 4>(a, ncu, st);
+    launch_wg<2, 8, 8, 4, 1>(a, ncu, st);
+  else if (s <= 64)
+    launch_wg<4, 4, 8, 8, 1>(a, ncu, st);
   else
-    launch_wg<4, 4, 8, 8>(a, ncu, st);
+    launch_wg<4, 2, 8, 8, 2>(a, ncu, st);
 }
 
 }  // namespace kern

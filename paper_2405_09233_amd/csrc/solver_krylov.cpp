@@ -93,7 +93,8 @@ struct CycleWS {
     int64_t ldv = round_up(N, 64);
     int nch = kern::mdot_chunks(N);
     return Workspace::bytes_for((int64_t)(m + 1) * ldv, sizeof(TV)) +
-           Workspace::bytes_for((int64_t)nch * (m + 2), 8) + 5 * Workspace::bytes_for(m + 2, 8);
+           Workspace::bytes_for((int64_t)nch * (m + 2), 8) + Workspace::bytes_for(3 * (m + 2), 8) +
+           2 * Workspace::bytes_for(m + 2, 8);
   }
   // host: pinned staging of 5 (m + 2) doubles
   void carve(Workspace& ws, int64_t N, int m_, double* host) {
@@ -103,9 +104,10 @@ struct CycleWS {
     red.nchunks = kern::mdot_chunks(N);  // >= ortho_chunks(N)
     red.ldp = m + 2;
     red.part = ws.take<double>((int64_t)red.nchunks * red.ldp);
-    d_h1 = ws.take<double>(m + 2);
-    d_h2 = ws.take<double>(m + 2);
-    red.d_ww = ws.take<double>(m + 2);
+    // h1, h2 and ||w||^2 side by side on both ends, so one copy returns them
+    d_h1 = ws.take<double>(3 * (m + 2));
+    d_h2 = d_h1 + (m + 2);
+    red.d_ww = d_h1 + 2 * (m + 2);
     d_y = ws.take<double>(m + 2);
     d_sigma = ws.take<double>(m + 2);
     h_h1 = host;
@@ -406,9 +408,9 @@ struct KrylovState {
       kern::mdot_partial((const TV*)nullptr, 0, 0, (const TV*)W, N, r.part, r.ldp, 1, st);
       kern::reduce_partials(r.part, r.nchunks, r.ldp, 1, r.d_ww, st);
     }
-    TSYLV_HIP(hipMemcpyAsync(w.h_h1, w.d_h1, (nv + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
-    TSYLV_HIP(hipMemcpyAsync(w.h_h2, w.d_h2, nv * sizeof(double), hipMemcpyDeviceToHost, st));
-    TSYLV_HIP(hipMemcpyAsync(r.h_ww, r.d_ww, sizeof(double), hipMemcpyDeviceToHost, st));
+    // h1 (nv + 1 values), h2 (nv) and ||w||^2 in one copy (same layout on host)
+    TSYLV_HIP(hipMemcpyAsync(w.h_h1, w.d_h1, (2 * (w.m + 2) + 1) * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
   }
 
   // Consumes a step's h column; returns true when the cycle ends.
