@@ -86,6 +86,21 @@ void ortho_update(const double* V, int64_t ldv, int nv, const double* h, const d
 void ortho_update(const float* V, int64_t ldv, int nv, const double* h, const double* sigma,
                   float* w, int64_t N, double* part, int ldp, int mode, hipStream_t st);
 
+// Delayed reorthogonalisation sweeps (V: nv basis vectors, sigma as above):
+//   ortho_dots2:   part[c] = [sigma_i V_i . u, sigma_i V_i . w, u . w, u . u,
+//                  w . w] (2 nv + 3 values, ldp >= 2 nv + 3);
+//   ortho_update2: coef = [ac (nv), bc (nv), alpha, gamma]; u <- u - sum ac_i
+//                  V_i (if u is not null), then w <- alpha w + sum bc_i V_i +
+//                  gamma u.
+void ortho_dots2(const double* V, int64_t ldv, int nv, const double* sigma, const double* u,
+                 const double* w, int64_t N, double* part, int ldp, hipStream_t st);
+void ortho_dots2(const float* V, int64_t ldv, int nv, const double* sigma, const float* u,
+                 const float* w, int64_t N, double* part, int ldp, hipStream_t st);
+void ortho_update2(const double* V, int64_t ldv, int nv, const double* coef, double* u, double* w,
+                   int64_t N, hipStream_t st);
+void ortho_update2(const float* V, int64_t ldv, int nv, const double* coef, float* u, float* w,
+                   int64_t N, hipStream_t st);
+
 // out[e] = a * x[e]  (the FP64 -> FP32 form rounds the scaled value)
 void scale(const double* x, double* out, double a, int64_t N, hipStream_t st);
 void scale(const float* x, float* out, double a, int64_t N, hipStream_t st);

@@ -509,6 +509,155 @@ __global__ __launch_bounds__(kBlock) void ortho_update_kernel(
   }
 }
 
+// ---- delayed reorthogonalisation (one projection sweep + one update sweep
+// per Arnoldi step; see the Krylov driver) ---------------------------------
+
+// part[c] = [sigma_i V_i . u (i < nv), sigma_i V_i . w (i < nv), u . w,
+//            u . u, w . w] over chunk c (2 nv + 3 values).
+template <typename T, int VPW, int EPL>
+__global__ __launch_bounds__(kBlock) void ortho_dots2_kernel(
+    const T* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ sigma,
+    const T* __restrict__ u, const T* __restrict__ w, int64_t N, double* __restrict__ part,
+    int ldp) {
+  constexpr int TE = 16 * EPL;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4;
+  double aa[VPW], ab[VPW], uw = 0.0, uu = 0.0, ww = 0.0;
+#pragma unroll
+  for (int k = 0; k < VPW; ++k) aa[k] = ab[k] = 0.0;
+  const int64_t base = (int64_t)blockIdx.x * kOChunk;
+  const int64_t end = min(N, base + kOChunk);
+  for (int64_t t0 = base + wid * TE; t0 < end; t0 += kOWaves * TE) {
+    const int64_t off = t0 + (lane & 15) * EPL;
+    T uv[EPL], wv[EPL], v[VPW][EPL];
+    if (t0 + TE <= end) {
+      oload_w<true, T, EPL>(u, off, end, uv);
+      oload_w<true, T, EPL>(w, off, end, wv);
+      oload_tile<true, T, VPW, EPL>(V, ldv, nv, g, w, off, end, v);
+    } else {
+      oload_w<false, T, EPL>(u, off, end, uv);
+      oload_w<false, T, EPL>(w, off, end, wv);
+      oload_tile<false, T, VPW, EPL>(V, ldv, nv, g, w, off, end, v);
+    }
+#pragma unroll
+    for (int k = 0; k < VPW; ++k)
+#pragma unroll
+      for (int l = 0; l < EPL; ++l) {
+        aa[k] = fma((double)v[k][l], (double)uv[l], aa[k]);
+        ab[k] = fma((double)v[k][l], (double)wv[l], ab[k]);
+      }
+#pragma unroll
+    for (int l = 0; l < EPL; ++l) {
+      uw = fma((double)uv[l], (double)wv[l], uw);
+      uu = fma((double)uv[l], (double)uv[l], uu);
+      ww = fma((double)wv[l], (double)wv[l], ww);
+    }
+  }
+  double* out = part + (int64_t)blockIdx.x * ldp;
+  double all[2 * VPW + 3];
+  int cols[2 * VPW + 3];
+#pragma unroll
+  for (int k = 0; k < VPW; ++k) {
+    const int i = g + kOGroups * k;
+    const double sg = (i < nv) ? sigma[i] : 0.0;
+    all[k] = aa[k] * sg;
+    all[VPW + k] = ab[k] * sg;
+    cols[k] = (i < nv) ? i : -1;
+    cols[VPW + k] = (i < nv) ? nv + i : -1;
+  }
+  all[2 * VPW] = uw;  // every group saw the same u and w; group 0 reports
+  all[2 * VPW + 1] = uu;
+  all[2 * VPW + 2] = ww;
+  cols[2 * VPW] = (g == 0) ? 2 * nv : -1;
+  cols[2 * VPW + 1] = (g == 0) ? 2 * nv + 1 : -1;
+  cols[2 * VPW + 2] = (g == 0) ? 2 * nv + 2 : -1;
+  oblock_store<2 * VPW + 3>(all, cols, 2 * nv + 3, nullptr, out);
+}
+
+// coef = [ac (nv), bc (nv), alpha, gamma] (FP64):
+//   u <- v = u - sum_i ac_i V_i                       (when u is given)
+//   w <- alpha w + sum_i bc_i V_i + gamma v            (gamma only with u)
+template <typename T, int VPW, int EPL>
+__global__ __launch_bounds__(kBlock) void ortho_update2_kernel(
+    const T* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ coef,
+    T* __restrict__ u, T* __restrict__ w, int64_t N) {
+  constexpr int TE = 16 * EPL;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4;
+  double ca[VPW], cb[VPW];
+#pragma unroll
+  for (int k = 0; k < VPW; ++k) {
+    const int i = g + kOGroups * k;
+    ca[k] = (i < nv) ? coef[i] : 0.0;
+    cb[k] = (i < nv) ? coef[nv + i] : 0.0;
+  }
+  const double alpha = coef[2 * nv], gamma = coef[2 * nv + 1];
+  const bool has_u = u != nullptr;
+  const int64_t base = (int64_t)blockIdx.x * kOChunk;
+  const int64_t end = min(N, base + kOChunk);
+  for (int64_t t0 = base + wid * TE; t0 < end; t0 += kOWaves * TE) {
+    const int64_t off = t0 + (lane & 15) * EPL;
+    const bool full = t0 + TE <= end;
+    T v[VPW][EPL], wv[EPL], uv[EPL];
+    if (full) {
+      oload_tile<true, T, VPW, EPL>(V, ldv, nv, g, w, off, end, v);
+      oload_w<true, T, EPL>(w, off, end, wv);
+      if (has_u) oload_w<true, T, EPL>(u, off, end, uv);
+    } else {
+      oload_tile<false, T, VPW, EPL>(V, ldv, nv, g, w, off, end, v);
+      oload_w<false, T, EPL>(w, off, end, wv);
+      if (has_u) oload_w<false, T, EPL>(u, off, end, uv);
+    }
+    T vt[EPL], wt[EPL];
+#pragma unroll
+    for (int l = 0; l < EPL; ++l) {
+      double pa = 0.0, pb = 0.0;
+#pragma unroll
+      for (int k = 0; k < VPW; ++k) {
+        pa = fma(ca[k], (double)v[k][l], pa);
+        pb = fma(cb[k], (double)v[k][l], pb);
+      }
+      // (p0 + p1) + (p2 + p3) in every group: the same bits in all four
+      double sa = pa + __shfl_xor(pa, 16, 64);
+      sa += __shfl_xor(sa, 32, 64);
+      double sb = pb + __shfl_xor(pb, 16, 64);
+      sb += __shfl_xor(sb, 32, 64);
+      double nw = fma(alpha, (double)wv[l], sb);
+      if (has_u) {
+        vt[l] = (T)((double)uv[l] - sa);
+        nw = fma(gamma, (double)vt[l], nw);
+      }
+      wt[l] = (T)nw;
+    }
+    if (g == 0) {
+      if (full) {
+        using VT = typename OVec<T, EPL>::type;
+        VT tw;
+        T* tp = reinterpret_cast<T*>(&tw);
+#pragma unroll
+        for (int l = 0; l < EPL; ++l) tp[l] = wt[l];
+        *reinterpret_cast<VT*>(w + off) = tw;
+        if (has_u) {
+          VT tv;
+          T* tq = reinterpret_cast<T*>(&tv);
+#pragma unroll
+          for (int l = 0; l < EPL; ++l) tq[l] = vt[l];
+          *reinterpret_cast<VT*>(u + off) = tv;
+        }
+      } else {
+#pragma unroll
+        for (int l = 0; l < EPL; ++l)
+          if (off + l < end) {
+            w[off + l] = wt[l];
+            if (has_u) u[off + l] = vt[l];
+          }
+      }
+    }
+  }
+}
+
 inline int stream_grid(int64_t count) {
   int64_t b = (count + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
@@ -712,6 +861,65 @@ void ortho_update(const double* V, int64_t ldv, int nv, const double* h, const d
 void ortho_update(const float* V, int64_t ldv, int nv, const double* h, const double* sigma,
                   float* w, int64_t N, double* part, int ldp, int mode, hipStream_t st) {
   ortho_update_any<float>(V, ldv, nv, h, sigma, w, N, part, ldp, mode, st);
+}
+
+template <typename T>
+static void ortho_dots2_any(const T* V, int64_t ldv, int nv, const double* sigma, const T* u,
+                            const T* w, int64_t N, double* part, int ldp, hipStream_t st) {
+  if (nv < 1 || 2 * nv + 3 > ldp) throw Error(TSYLV_EINVAL, "ortho: bad vector count");
+  if (N <= 0) return;
+  ortho_check(V, ldv, w);
+  ortho_check(V, ldv, u);
+  const dim3 grid(ortho_chunks(N)), block(kBlock);
+  constexpr int EPL = ortho_epl<T>();
+  switch (ortho_vpw(nv)) {
+#define F(K)                                                                                   \
+  case K:                                                                                      \
+    hipLaunchKernelGGL((ortho_dots2_kernel<T, K, EPL>), grid, block, 0, st, V, ldv, nv, sigma, \
+                       u, w, N, part, ldp);                                                    \
+    break;
+    TSYLV_OVPW_CASES(F)
+#undef F
+  }
+  TSYLV_LAUNCH_CHECK();
+}
+
+template <typename T>
+static void ortho_update2_any(const T* V, int64_t ldv, int nv, const double* coef, T* u, T* w,
+                              int64_t N, hipStream_t st) {
+  if (nv < 1) throw Error(TSYLV_EINVAL, "ortho: bad vector count");
+  if (N <= 0) return;
+  ortho_check(V, ldv, (const T*)w);
+  if (u) ortho_check(V, ldv, (const T*)u);
+  const dim3 grid(ortho_chunks(N)), block(kBlock);
+  constexpr int EPL = ortho_epl<T>();
+  switch (ortho_vpw(nv)) {
+#define F(K)                                                                                    \
+  case K:                                                                                       \
+    hipLaunchKernelGGL((ortho_update2_kernel<T, K, EPL>), grid, block, 0, st, V, ldv, nv, coef, \
+                       u, w, N);                                                                \
+    break;
+    TSYLV_OVPW_CASES(F)
+#undef F
+  }
+  TSYLV_LAUNCH_CHECK();
+}
+
+void ortho_dots2(const double* V, int64_t ldv, int nv, const double* sigma, const double* u,
+                 const double* w, int64_t N, double* part, int ldp, hipStream_t st) {
+  ortho_dots2_any<double>(V, ldv, nv, sigma, u, w, N, part, ldp, st);
+}
+void ortho_dots2(const float* V, int64_t ldv, int nv, const double* sigma, const float* u,
+                 const float* w, int64_t N, double* part, int ldp, hipStream_t st) {
+  ortho_dots2_any<float>(V, ldv, nv, sigma, u, w, N, part, ldp, st);
+}
+void ortho_update2(const double* V, int64_t ldv, int nv, const double* coef, double* u, double* w,
+                   int64_t N, hipStream_t st) {
+  ortho_update2_any<double>(V, ldv, nv, coef, u, w, N, st);
+}
+void ortho_update2(const float* V, int64_t ldv, int nv, const double* coef, float* u, float* w,
+                   int64_t N, hipStream_t st) {
+  ortho_update2_any<float>(V, ldv, nv, coef, u, w, N, st);
 }
 
 template <typename TI, typename TO>

@@ -31,7 +31,7 @@ namespace tsylv {
 
 namespace {
 constexpr int kSlots = 8;
-constexpr size_t kPinnedPerSlot = 5 * (1000 + 2);  // KrylovTask::pinned_doubles for m <= 1000
+constexpr size_t kPinnedPerSlot = 7 * (1000 + 2) + 2;  // KrylovTask::pinned_doubles, m <= 1000
 }  // namespace
 
 struct Scheduler {

@@ -42,6 +42,7 @@
 // is synchronised.
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <vector>
 
@@ -89,27 +90,30 @@ struct CycleWS {
   double *h_h1 = nullptr, *h_h2 = nullptr, *h_y = nullptr, *h_sigma = nullptr;
   TV* V(int j) const { return basis + (int64_t)j * ldv; }
 
+  // sigma (m + 2) followed by the update coefficients of the delayed sweeps
+  static int64_t coef_len(int m) { return 3 * (int64_t)(m + 2) + 2; }
   static size_t bytes(int64_t N, int m) {
     int64_t ldv = round_up(N, 64);
     int nch = kern::mdot_chunks(N);
     return Workspace::bytes_for((int64_t)(m + 1) * ldv, sizeof(TV)) +
-           Workspace::bytes_for((int64_t)nch * (m + 2), 8) + Workspace::bytes_for(3 * (m + 2), 8) +
-           2 * Workspace::bytes_for(m + 2, 8);
+           Workspace::bytes_for((int64_t)nch * (2 * m + 4), 8) +
+           Workspace::bytes_for(3 * (m + 2), 8) + Workspace::bytes_for(m + 2, 8) +
+           Workspace::bytes_for(coef_len(m), 8);
   }
-  // host: pinned staging of 5 (m + 2) doubles
+  // host: pinned staging of 7 (m + 2) + 2 doubles
   void carve(Workspace& ws, int64_t N, int m_, double* host) {
     m = m_;
     ldv = round_up(N, 64);
     basis = ws.take<TV>((int64_t)(m + 1) * ldv);
     red.nchunks = kern::mdot_chunks(N);  // >= ortho_chunks(N)
-    red.ldp = m + 2;
+    red.ldp = 2 * m + 4;                 // up to 2 nv + 3 sums per chunk
     red.part = ws.take<double>((int64_t)red.nchunks * red.ldp);
     // h1, h2 and ||w||^2 side by side on both ends, so one copy returns them
     d_h1 = ws.take<double>(3 * (m + 2));
     d_h2 = d_h1 + (m + 2);
     red.d_ww = d_h1 + 2 * (m + 2);
     d_y = ws.take<double>(m + 2);
-    d_sigma = ws.take<double>(m + 2);
+    d_sigma = ws.take<double>(coef_len(m));
     h_h1 = host;
     h_h2 = host + (m + 2);
     red.h_ww = host + 2 * (m + 2);
@@ -303,6 +307,15 @@ struct KrylovState {
   // unnormalised, sigma_i = 1 / ||V_i|| carried to the apply (alpha) and the
   // Gram-Schmidt kernels, so no separate scaling sweep.
   bool fused = false;
+  // Delayed reorthogonalisation (the default with the fused kernels): one
+  // projection sweep and one update sweep per step, see enqueue_round.
+  bool delayed = false;
+  int dj = 0;                 // round of the delayed process
+  bool final_round = false;   // the next round finalises the last column, no apply
+  std::vector<double> h1p;    // first-pass coefficients of the pending column
+  double w2prev = 0.0;        // ||M q_{dj-1}||^2, reference of the breakdown test
+  int nv_upd = 0;             // update sweep: basis vectors it combines
+  int corr_slot = -1;         // update sweep: slot it corrects (-1: none)
   int pending_update = 0;     // basis vectors to combine into X before the next residual
   Givens giv;
   std::vector<std::vector<double>> Hcols;
@@ -324,6 +337,10 @@ struct KrylovState {
     op.Ah64 = S.Ah;
     op.Bh64 = S.Bh;
     fused = (refine ? o.inner_m : o.m) + 1 <= kern::ortho_max_vectors(refine);
+    {
+      const char* f = std::getenv("TSYLV_KRYLOV_CGS2");  // force the three-sweep CGS2 path
+      delayed = fused && !(f && f[0] == '1');
+    }
     if (!refine) {
       w64.carve(ws, N, o.m, pinned);
       red = &w64.red;
@@ -411,6 +428,183 @@ struct KrylovState {
     // h1 (nv + 1 values), h2 (nv) and ||w||^2 in one copy (same layout on host)
     TSYLV_HIP(hipMemcpyAsync(w.h_h1, w.d_h1, (2 * (w.m + 2) + 1) * sizeof(double),
                              hipMemcpyDeviceToHost, st));
+  }
+
+  // ---- delayed reorthogonalisation --------------------------------------
+  // CGS2 with the second projection of each vector delayed to the next step
+  // (the low-synchronisation DCGS2 scheme of Bielich et al., 2022), so that a
+  // step reads the basis twice instead of three times.  Slot j holds u_j,
+  // the once-projected new direction, until the next round corrects it.
+  // Round j >= 1 enqueues
+  //   * the update sweep of round j - 1: slot j - 1 <- v_{j-1} = u_{j-1} -
+  //     Q a (its reprojection) and slot j <- u_j (the first projection of
+  //     M q_{j-1}, expressed through W' = M u_{j-1} of that round);
+  //   * W' = M u_j into slot j + 1;
+  //   * one sweep for a = Q^T u_j, b = Q^T W', u_j . W', ||u_j||^2, ||W'||^2
+  //     over the final vectors q_0..q_{j-1} (Q).
+  // Completing it finalises column j - 1 of H: h_{0..j-1} += a and
+  // h_{j,j-1} = nu = ||u_j - Q a|| (from the exact ||u_j||^2), so q_j =
+  // (u_j - Q a) / nu; with M q_i = Q H e_i for the finished columns,
+  // M q_j = (W' - Q g) / nu (g = H a), which gives the first projection of
+  // the next column from the sweep's scalars alone.  The last round of a
+  // cycle skips the apply (it only needs a and ||u_j||^2).  In exact
+  // arithmetic the Hessenberg matrix equals CGS2's.
+  template <typename TV>
+  void enqueue_round(CycleWS<TV>& w) {
+    const RedBuf& r = w.red;
+    const int och = kern::ortho_chunks(N);
+    double* d_coef = w.d_sigma + (w.m + 2);
+    if (dj == 0) {
+      TSYLV_HIP(hipMemcpyAsync(w.d_sigma, w.h_sigma, sizeof(double), hipMemcpyHostToDevice, st));
+      apply((const TV*)w.V(0), w.V(1), (const TV*)nullptr, w.h_sigma[0], 0.0);
+      ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
+      kern::ortho_dots((const TV*)w.basis, w.ldv, 1, w.d_sigma, (const TV*)w.V(1), N, r.part,
+                       r.ldp, st);
+      kern::reduce_partials(r.part, och, r.ldp, 2, w.d_h1, st);
+    } else {
+      TSYLV_HIP(hipMemcpyAsync(w.d_sigma, w.h_sigma, (w.m + 2 + 2 * nv_upd + 2) * sizeof(double),
+                               hipMemcpyHostToDevice, st));
+      {
+        ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
+        kern::ortho_update2((const TV*)w.basis, w.ldv, nv_upd, d_coef,
+                            corr_slot >= 0 ? w.V(corr_slot) : (TV*)nullptr, w.V(dj), N, st);
+      }
+      if (final_round) {
+        ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
+        kern::ortho_dots((const TV*)w.basis, w.ldv, dj, w.d_sigma, (const TV*)w.V(dj), N, r.part,
+                         r.ldp, st);
+        kern::reduce_partials(r.part, och, r.ldp, dj + 1, w.d_h1, st);
+      } else {
+        apply((const TV*)w.V(dj), w.V(dj + 1), (const TV*)nullptr, 1.0, 0.0);
+        ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
+        kern::ortho_dots2((const TV*)w.basis, w.ldv, dj, w.d_sigma, (const TV*)w.V(dj),
+                          (const TV*)w.V(dj + 1), N, r.part, r.ldp, st);
+        kern::reduce_partials(r.part, och, r.ldp, 2 * dj + 3, w.d_h1, st);
+      }
+    }
+    TSYLV_HIP(hipMemcpyAsync(w.h_h1, w.d_h1, (2 * (w.m + 2) + 1) * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+  }
+
+  // Decides whether the round after the current one is the cycle's last: by
+  // count, or when the column it will finalise (first projection h1p, norm
+  // estimated by Pythagoras) already meets the stopping test.
+  void plan_next_round(double stop_abs) {
+    const int mcyc = refine ? o.inner_m : o.m;
+    const int next = dj + 1;
+    final_round = next >= mcyc;
+    if (final_round) return;
+    double h2 = 0.0;
+    for (double v : h1p) h2 += v * v;
+    const double nu2 = w2prev - h2;
+    if (!(nu2 > 256.0 * kEps * kEps * w2prev)) {
+      final_round = true;  // (near) breakdown ahead
+      return;
+    }
+    if (method == TSYLV_METHOD_GMRES) {
+      Givens t = giv;
+      std::vector<double> h(h1p);
+      h.push_back(std::sqrt(nu2));
+      if (t.add(h) <= stop_abs) final_round = true;
+    }
+  }
+
+  template <typename TV>
+  bool complete_round(CycleWS<TV>& w, double stop_abs) {
+    const double* res = w.h_h1;
+    const int mcyc = refine ? o.inner_m : o.m;
+    double* coef = w.h_sigma + (w.m + 2);
+    if (dj == 0) {
+      // q_0 . W' and ||M q_0||^2; the update forms u_1 = W' - h q_0
+      h1p.assign(1, res[0]);
+      w2prev = res[1];
+      nv_upd = 1;
+      corr_slot = -1;
+      coef[0] = 0.0;
+      coef[1] = -res[0] * w.h_sigma[0];
+      coef[2] = 1.0;
+      coef[3] = 0.0;
+      plan_next_round(stop_abs);
+      dj = 1;
+      return false;
+    }
+    const int j = dj;
+    std::vector<double> a(res, res + j), b;
+    double c = 0.0, d, e = 0.0;
+    if (final_round) {
+      d = res[j];
+    } else {
+      b.assign(res + j, res + 2 * j);
+      c = res[2 * j];
+      d = res[2 * j + 1];
+      e = res[2 * j + 2];
+    }
+    double na2 = 0.0;
+    for (double v : a) na2 += v * v;
+    const double nu2 = d - na2;
+    const bool breakdown = !(nu2 > 256.0 * kEps * kEps * w2prev);  // reading: h_{j+1,j} = 0
+    const double nu = breakdown ? 0.0 : std::sqrt(nu2);
+    std::vector<double> h(j + 1);
+    for (int i = 0; i < j; ++i) h[i] = h1p[i] + a[i];
+    h[j] = nu;
+    info.steps++;
+    Hcols.push_back(h);
+    double est;
+    if (method == TSYLV_METHOD_GMRES) {
+      est = giv.add(h);
+    } else {
+      giv.add(h);  // keeps the tGMRES fallback available
+      fom_ok = fom_solve(Hcols, (size_t)j, beta, y_fom);
+      est = fom_ok ? nu * std::fabs(y_fom[j - 1]) : INFINITY;
+    }
+    info.relres_est = est / cnorm;
+    if (o.res_hist && info.res_hist_len < o.res_hist_cap)
+      o.res_hist[info.res_hist_len++] = info.relres_est;
+    if (breakdown || est <= stop_abs || j >= mcyc || final_round) {
+      std::vector<double> y;
+      if (method == TSYLV_METHOD_GMRES) {
+        y = giv.solve((size_t)j);
+      } else if (fom_ok) {
+        y = y_fom;
+      } else {
+        info.fom_fallback++;
+        y = giv.solve((size_t)j);
+      }
+      for (int i = 0; i < j; ++i) w.h_y[i] = -y[i] * w.h_sigma[i];
+      pending_update = j;
+      return true;
+    }
+    // q_j = (u_j - Q a) / nu;  g = H a over the finished columns 0..j-1
+    w.h_sigma[j] = 1.0 / nu;
+    std::vector<double> g(j + 1, 0.0);
+    for (int i = 0; i < j; ++i)
+      for (int l = 0; l <= i + 1 && l <= j; ++l) g[l] += Hcols[i][l] * a[i];
+    double ab = 0.0;
+    for (int l = 0; l < j; ++l) ab += a[l] * b[l];
+    const double qjw = (c - ab) / nu;  // q_j . W'
+    std::vector<double> h1n(j + 1);
+    for (int l = 0; l < j; ++l) h1n[l] = (b[l] - g[l]) / nu;
+    h1n[j] = (qjw - g[j]) / nu;
+    // ||M q_j||^2 = ||W' - Q g||^2 / nu^2
+    double gw = 0.0, gg = 0.0;
+    for (int l = 0; l < j; ++l) gw += g[l] * b[l];
+    gw += g[j] * qjw;
+    for (double v : g) gg += v * v;
+    w2prev = std::max(0.0, (e - 2.0 * gw + gg) / (nu * nu));
+    // update sweep: v_j = u_j - sum a_l q_l;  u_{j+1} = M q_j - sum h1n_l q_l
+    //   = W' / nu - sum_{l<j} (g_l / nu + h1n_l) q_l - (g_j / nu + h1n_j) v_j / nu
+    nv_upd = j;
+    corr_slot = j;
+    for (int l = 0; l < j; ++l) {
+      coef[l] = a[l] * w.h_sigma[l];
+      coef[j + l] = -(g[l] / nu + h1n[l]) * w.h_sigma[l];
+    }
+    coef[2 * j] = 1.0 / nu;
+    coef[2 * j + 1] = -(g[j] / nu + h1n[j]) / nu;
+    h1p = h1n;
+    plan_next_round(stop_abs);
+    dj = j + 1;
+    return false;
   }
 
   // Consumes a step's h column; returns true when the cycle ends.
@@ -503,10 +697,16 @@ struct KrylovState {
           }
           scale_v0 = false;
         }
-        if (refine)
+        if (delayed) {
+          if (refine)
+            enqueue_round(w32);
+          else
+            enqueue_round(w64);
+        } else if (refine) {
           enqueue_step(w32);
-        else
+        } else {
           enqueue_step(w64);
+        }
         break;
       case FINAL: {
         // Algorithm 1 step 3: back to the spatial domain.
@@ -552,6 +752,8 @@ struct KrylovState {
           Hcols.clear();
           fom_ok = false;
           j = 0;
+          dj = 0;
+          final_round = false;
           pending_scale = 0.0;
           scale_v0 = true;
           phase = STEP;
@@ -561,7 +763,8 @@ struct KrylovState {
       case STEP: {
         const double stop = refine ? std::max(o.inner_tol * beta, 0.5 * o.tol * cnorm)
                                    : o.tol * cnorm;
-        const bool end = refine ? complete_step(w32, stop) : complete_step(w64, stop);
+        const bool end = delayed ? (refine ? complete_round(w32, stop) : complete_round(w64, stop))
+                                 : (refine ? complete_step(w32, stop) : complete_step(w64, stop));
         if (end) phase = RESTART;
         break;
       }
@@ -584,7 +787,7 @@ KrylovTask::KrylovTask(Ctx& ctx, hipStream_t st, bool profile, double* pinned, i
 KrylovTask::~KrylovTask() = default;
 
 size_t KrylovTask::pinned_doubles(const tsylv_opts& o) {
-  return 5 * (size_t)((o.refine ? o.inner_m : o.m) + 2);
+  return 7 * (size_t)((o.refine ? o.inner_m : o.m) + 2) + 2;
 }
 
 void KrylovTask::enqueue() { s_->enqueue(); }

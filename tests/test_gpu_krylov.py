@@ -171,3 +171,24 @@ def test_full_size_tgmres_cd4096():
     # sampled residual entries: GPU and oracle agree to rounding of M(X)
     scale = np.abs(A).max() * np.abs(Xh).max() * (n + s) * p * 64 * np.finfo(float).eps
     assert np.abs(Ro - Rg).max() <= scale
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("method", ["gmres", "fom"])
+@pytest.mark.parametrize("n,s,p,m", [(40, 6, 5, 10), (150, 9, 7, 30), (33, 5, 4, 1)])
+def test_delayed_and_three_sweep_cgs2_agree(method, n, s, p, m, monkeypatch):
+    """The default orthogonalisation (second projection delayed to the next
+    step: two basis sweeps per step) and the three-sweep CGS2 build the same
+    Hessenberg matrix in exact arithmetic: one cycle gives the same iterate,
+    and converged solves reach the same solution."""
+    say("delayed vs cgs2", method, n, s, p, m)
+    A, B, C = workloads.dense_shifted(n, s, p, seed=17 + n)
+    Xd, idl = solve(method, A, B, C, m=m, tol=1e-300, max_cycles=1)
+    Xc1, _ = solve(method, A, B, C, m=m, tol=1e-12, max_cycles=200)
+    monkeypatch.setenv("TSYLV_KRYLOV_CGS2", "1")
+    Xc, icg = solve(method, A, B, C, m=m, tol=1e-300, max_cycles=1)
+    Xc2, _ = solve(method, A, B, C, m=m, tol=1e-12, max_cycles=200)
+    assert idl.steps == icg.steps == m
+    assert rel(Xd, Xc) <= 1e-10
+    assert idl.relres_true == pytest.approx(icg.relres_true, rel=1e-8)
+    assert rel(Xc1, Xc2) <= 1e-9
