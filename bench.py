@@ -8,11 +8,18 @@ planes, inverse DFT of X) to device-resident spatial X.  Inputs are synthetic
 
 Paths timed (each: W warm-up solves, then K timed solves):
   fp64      restarted tGMRES(30), everything FP64
-  mixed     FP64 iterative refinement; each correction one tGMRES(40) cycle
+  mixed     FP64 iterative refinement; each correction one tGMRES(32) cycle
             with FP32 basis vectors and FP32 MFMA slice products
-  bf16      the same with BF16 slice products (FP32 accumulation)
+  bf16      the same (tGMRES(24) cycles) with BF16 slice products (FP32
+            accumulation)
+  tba       TBAS(10), reported beside them (not a candidate for `value`)
 A path counts only if every timed solve reaches true FP64 relres <= tol.
-`value` is the solves/s of the fastest valid path; every path is reported.
+`value` is the solves/s of the fastest valid tGMRES path; every path is
+reported.  Two further measurements ride along (skip with --no-extra):
+  tiny      the 8 x 8 x 4 dense case, unrestarted tGMRES to 1e-12: latency
+  serving   open-loop Poisson arrivals of small requests of uneven (n, s, p)
+            through tsylv_submit / tsylv_poll (the serving loop): p50/p99
+            latency and throughput, FP64 and BF16-refined.
 
 Prints ONE JSON line.  The roofline object is for the dominant kernel of the
 path that gives `value` (the facewise slice-product kernel), timed live with
@@ -90,6 +97,105 @@ def cpu_baseline(A, B, C, applies_per_solve, avg_basis):
                       "(%.2f s, x p = one apply) and one MGS sweep against 16 basis vectors "
                       "(%.2f s); scaled by %d applies of M per FP64 solve and a mean basis of "
                       "%.1f vectors" % (n, s, p, t_slice, t_mgs, applies_per_solve, avg_basis)}
+
+
+def tiny_latency(tsylv, workloads, reps=100):
+    """The 8 x 8 x 4 dense case, unrestarted tGMRES (m = 192) to relres 1e-12:
+    median and p99 wall time of one synchronous solve (device-resident input)."""
+    import torch
+    A, B, C = workloads.tiny_dense(0)
+    ctx = tsylv.Context(64 << 20, device=0)
+    Ad, Bd, Cd = (tsylv.to_device(T, "cuda:0") for T in (A, B, C))
+    Xd = tsylv.empty_device(C.shape, "cuda:0")
+    o = tsylv.default_opts(tsylv.GMRES, m=C.size, tol=1e-12, max_cycles=2)
+    lat, ok = [], True
+    for r in range(reps + 10):
+        t0 = time.perf_counter()
+        _, info = ctx.gmres(Ad, Bd, Cd, X=Xd, opts=o)
+        dt = time.perf_counter() - t0
+        ok = ok and info.status == 0 and info.relres_true <= 1e-12
+        if r >= 10:
+            lat.append(dt)
+    torch.cuda.synchronize()
+    ctx.close()
+    return {"workload": "dense 8x8x4 (A slices N(0,1)/sqrt(8) + 4I on slice 1, B N(0,1)/sqrt(6) "
+                        "- 4I), unrestarted tGMRES to relres 1e-12",
+            "valid": bool(ok), "solves": reps, "steps": info.steps,
+            "latency_us": {"p50": float(np.percentile(lat, 50) * 1e6),
+                           "p99": float(np.percentile(lat, 99) * 1e6)}}
+
+
+def serving(tsylv, workloads, rate, duration, npool=96, seed=50):
+    """Open-loop serving run: requests of uneven size arrive as a Poisson
+    process (exponential gaps, `rate` per second, for `duration` seconds) and
+    go through tsylv_submit / tsylv_poll.  Sizes follow the serving recipe of
+    the workload set scaled to one GPU for a short run: n log-uniform in
+    [128, 1024], s log-uniform in [8, 64], p uniform in {4..16}, dense
+    p-scaled-noise instances (a pool of `npool`, reused when idle), tol 1e-8.
+    Latency runs from the scheduled arrival to the completion seen by poll."""
+    import torch
+    rng = np.random.default_rng(seed)
+    pool = []
+    for i in range(npool):
+        n = int(round(np.exp(rng.uniform(np.log(128), np.log(1024)))))
+        s = int(round(np.exp(rng.uniform(np.log(8), np.log(64)))))
+        p = int(rng.integers(4, 17))
+        A, B, C = workloads.dense_shifted(n, s, p, seed=5000 + i)
+        pool.append([tsylv.to_device(A, "cuda:0"), tsylv.to_device(B, "cuda:0"),
+                     tsylv.to_device(C, "cuda:0"), tsylv.empty_device(C.shape, "cuda:0"),
+                     (n, s, p)])
+    torch.cuda.synchronize()
+    opts = {
+        "fp64": tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-8, max_cycles=2000),
+        "bf16": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.BF16, inner_m=24,
+                                   inner_tol=1e-4, tol=1e-8, max_outer=300),
+    }
+    out = {"recipe": "n log-uniform [128, 1024], s log-uniform [8, 64], p uniform {4..16}, "
+                     "dense instances with p-scaled noise, Poisson arrivals %.0f/s for %.0f s, "
+                     "tol 1e-8, at most 8 solves on the GPU at once" % (rate, duration)}
+    for name, o in opts.items():
+        ctx = tsylv.Context(16 << 30, device=0)
+        gaps = rng.exponential(1.0 / rate, size=int(rate * duration * 2) + 16)
+        arrivals = np.cumsum(gaps)
+        arrivals = arrivals[arrivals < duration]
+        busy = [False] * npool
+        inflight = {}  # ticket -> (pool index, arrival time)
+        lat, bad, nxt = [], 0, 0
+        t0 = time.perf_counter()
+        i = 0
+        while i < len(arrivals) or inflight:
+            now = time.perf_counter() - t0
+            while i < len(arrivals) and arrivals[i] <= now:
+                for _ in range(npool):
+                    nxt = (nxt + 1) % npool
+                    if not busy[nxt]:
+                        break
+                else:
+                    break  # every instance in flight: try again on the next pass
+                Ad, Bd, Cd, Xd, _ = pool[nxt]
+                busy[nxt] = True
+                inflight[ctx.submit(Ad, Bd, Cd, Xd, method=tsylv.GMRES, opts=o)] = (nxt, arrivals[i])
+                i += 1
+            for t in list(inflight):
+                st, info = ctx.poll(t)
+                if st != 2:
+                    k, ta = inflight.pop(t)
+                    busy[k] = False
+                    lat.append(time.perf_counter() - t0 - ta)
+                    if st != 0 or info.relres_true > 1e-8:
+                        bad += 1
+            time.sleep(0.0002)
+        span = time.perf_counter() - t0
+        ctx.close()
+        lat = np.array(lat)
+        out[name] = {"requests": int(len(lat)), "failed": int(bad),
+                     "throughput_per_s": float(len(lat) / span),
+                     "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                                    "p99": float(np.percentile(lat, 99) * 1e3),
+                                    "mean": float(lat.mean() * 1e3)}}
+        log("serving %s: %d requests, p50 %.1f ms, p99 %.1f ms" % (
+            name, len(lat), out[name]["latency_ms"]["p50"], out[name]["latency_ms"]["p99"]))
+    return out
 
 
 def measured_traffic(path, shape):
@@ -175,6 +281,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--paths", default="fp64,mixed,bf16,tba")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the tiny and serving runs")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--grid", type=int, nargs=2, default=[64, 64])
     ap.add_argument("--s", type=int, default=64)
     ap.add_argument("--p", type=int, default=32)
@@ -280,13 +389,20 @@ def main():
         "paths": res,
         "mixed_vs_fp64": (res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"]
                           if "mixed" in res and "fp64" in res else None),
+        "bf16_vs_fp64": (res["bf16"]["solves_per_s"] / res["fp64"]["solves_per_s"]
+                         if "bf16" in res and "fp64" in res else None),
         "roofline": roofline,
     }
+    ctx.close()
+    if not args.no_extra:
+        log("tiny case latency ...")
+        out["tiny"] = tiny_latency(tsylv, workloads)
+        log("serving run ...")
+        out["serving"] = serving(tsylv, workloads, args.serve_rate, args.serve_seconds)
     if not args.no_cpu:
         log("timing the oracle sample on the host ...")
         fp = res.get("fp64", r)
         out["cpu_baseline"] = cpu_baseline(A, B, C, fp["applies_per_solve"], (args.m + 1) / 2.0)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

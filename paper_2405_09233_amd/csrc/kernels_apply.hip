@@ -109,17 +109,17 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
   return x * q + (x < r ? x : r) + b / 8;
 }
 
-template <typename Tag, int TM, int TN, int RB, int CB, bool CPLX>
+template <typename Tag, int TM, int TN, int RB, int CB, int TK, bool CPLX>
 __device__ __forceinline__ void apply_tile(const ApplyArgs<Tag>& a, int k, int rt, int ct,
-                                           typename Mma<Tag>::L (*As)[Mma<Tag>::TK][TM],
-                                           typename Mma<Tag>::L (*Bs)[Mma<Tag>::TK][TN + 1]) {
+                                           typename Mma<Tag>::L (*As)[TK][TM],
+                                           typename Mma<Tag>::L (*Bs)[TK][TN + 1]) {
   using M = Mma<Tag>;
   using L = typename M::L;
   using TA = typename Store<Tag>::T;
   using TV = typename M::TV;
   using frag = typename M::frag;
   using acc_t = typename M::acc_t;
-  constexpr int TK = M::TK, KB = M::KB;
+  constexpr int KB = M::KB;
   constexpr int WR = TM / (16 * RB);  // waves along rows
   constexpr int WC = TN / (16 * CB);  // waves along columns
   static_assert(WR * WC == NT / 64, "4 waves per workgroup");
@@ -290,10 +290,9 @@ __device__ __forceinline__ void apply_tile(const ApplyArgs<Tag>& a, int k, int r
     }
 }
 
-template <typename Tag, int TM, int TN, int RB, int CB>
+template <typename Tag, int TM, int TN, int RB, int CB, int TK>
 __global__ __launch_bounds__(NT) void apply_mfma_kernel(ApplyArgs<Tag> a) {
   using L = typename Mma<Tag>::L;
-  constexpr int TK = Mma<Tag>::TK;
   __shared__ L As[2][TK][TM];
   __shared__ L Bs[2][TK][TN + 1];
   const int t = xcd_tile(blockIdx.x, a.total);
@@ -302,17 +301,18 @@ __global__ __launch_bounds__(NT) void apply_mfma_kernel(ApplyArgs<Tag> a) {
   const int k = t / (a.nct * a.nrt);
   const bool real_slice = (k == 0) || (2 * k == a.p);
   if (real_slice)
-    apply_tile<Tag, TM, TN, RB, CB, false>(a, k, rt, ct, As, Bs);
+    apply_tile<Tag, TM, TN, RB, CB, TK, false>(a, k, rt, ct, As, Bs);
   else
-    apply_tile<Tag, TM, TN, RB, CB, true>(a, k, rt, ct, As, Bs);
+    apply_tile<Tag, TM, TN, RB, CB, TK, true>(a, k, rt, ct, As, Bs);
 }
 
-template <typename Tag, int TM, int TN, int RB, int CB>
+template <typename Tag, int TM, int TN, int RB, int CB, int TK = Mma<Tag>::TK>
 void launch_apply(ApplyArgs<Tag> a, hipStream_t st) {
   a.nrt = (int)((a.n + TM - 1) / TM);
   a.nct = (int)((a.s + TN - 1) / TN);
   a.total = num_slices(a.p) * a.nrt * a.nct;
-  hipLaunchKernelGGL((apply_mfma_kernel<Tag, TM, TN, RB, CB>), dim3(a.total), dim3(NT), 0, st, a);
+  hipLaunchKernelGGL((apply_mfma_kernel<Tag, TM, TN, RB, CB, TK>), dim3(a.total), dim3(NT), 0, st,
+                     a);
   TSYLV_LAUNCH_CHECK();
 }
 
