@@ -25,6 +25,14 @@ Recipes
   1/(nx+1), h_y = 1/(ny+1), plus 8 I; A slices 2..p dense i.i.d.
   N(0, 1e-4); B slices i.i.d. N(0,1)/sqrt(s), -4 I on slice 1; C i.i.d.
   N(0, 1).  Draw order: A's noise slices, B, C.
+* ``ex3(n, s, p, mu, seed)`` -- the convection-diffusion family of the
+  paper's experiment (section 6): frontal slice i (i = 1..p) of A is
+  mu/h1^2 tridiag(-1, 2, -1) + a_i/(4 h1) T, of B the same with s, h2 and b_i,
+  where T is the banded matrix with 1 on the first subdiagonal, 3 on the
+  diagonal, -5 on the first and 1 on the second superdiagonal; a_i = i,
+  b_i = p + i, h1 = 1/(n+1), h2 = 1/(s+1).  C is uniform on [0, 1) (the
+  experiment uses MATLAB's rand; its stream is not reproduced).  The paper
+  does not give mu; it is a parameter here.
 """
 
 import numpy as np
@@ -113,3 +121,29 @@ def cd_4096(seed=0):
 def cd_8192(seed=0):
     """n = 8192 (128 x 64 grid), s = 128, p = 64 (34 GB of FP64 A)."""
     return convection_diffusion(128, 64, 128, 64, seed=seed)
+
+
+def _ex3_slice(size, h, mu, coef):
+    """mu/h^2 tridiag(-1, 2, -1) + coef/(4 h) T (T: 1 / 3 / -5 / 1 on the
+    sub-, main, first and second super-diagonal)."""
+    M = np.zeros((size, size))
+    i = np.arange(size)
+    M[i, i] = 2.0 * mu / h ** 2 + 3.0 * coef / (4.0 * h)
+    M[i[1:], i[:-1]] = -mu / h ** 2 + 1.0 * coef / (4.0 * h)
+    M[i[:-1], i[1:]] = -mu / h ** 2 - 5.0 * coef / (4.0 * h)
+    M[i[:-2], i[2:]] = 1.0 * coef / (4.0 * h)
+    return M
+
+
+def ex3(n, s, p, mu=1.0, seed=0):
+    """The paper's convection-diffusion experiment family (see the module
+    docstring); Table 1 uses n in {1000, 2000}, s = 3, p = 2."""
+    rng = np.random.default_rng(seed)
+    h1, h2 = 1.0 / (n + 1), 1.0 / (s + 1)
+    A = np.empty((n, n, p), order="F")
+    B = np.empty((s, s, p), order="F")
+    for i in range(1, p + 1):
+        A[:, :, i - 1] = _ex3_slice(n, h1, mu, float(i))
+        B[:, :, i - 1] = _ex3_slice(s, h2, mu, float(p + i))
+    C = rng.random(n * s * p).reshape((n, s, p), order="F")
+    return A, B, np.asfortranarray(C)

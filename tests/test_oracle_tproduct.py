@@ -142,3 +142,25 @@ def test_sylv_op_entries_match_full():
     idx = [(i, c, k) for i in range(6) for c in range(3) for k in range(5)]
     np.testing.assert_allclose(tp.sylv_op_entries(A, B, X, idx),
                                [full[i, c, k] for i, c, k in idx], atol=1e-13)
+
+
+def test_ex3_workload_structure():
+    """The experiment family's slices: mu/h^2 tridiag(-1, 2, -1) + c/(4h) T
+    with T's stencil (1, 3, -5, 1) summing to zero, so every row with a full
+    stencil annihilates the constant vector; the slices are banded (one
+    subdiagonal, two superdiagonals) and C lies in [0, 1)."""
+    from paper_2405_09233_amd import workloads
+    n, s, p = 20, 5, 3
+    A, B, C = workloads.ex3(n, s, p, mu=0.3, seed=4)
+    for T, size in [(A, n), (B, s)]:
+        for i in range(p):
+            M = T[:, :, i]
+            assert np.allclose(np.tril(M, -2), 0) and np.allclose(np.triu(M, 3), 0)
+            ones = M @ np.ones(size)
+            assert np.allclose(ones[1:size - 2], 0, atol=1e-9 * np.abs(M).max())
+    # slice i differs from slice 1 only by (a_i - a_1)/(4 h) T
+    h1 = 1.0 / (n + 1)
+    D = (A[:, :, 1] - A[:, :, 0]) * 4 * h1
+    assert np.allclose(np.diag(D), 3) and np.allclose(np.diag(D, 1), -5)
+    assert np.allclose(np.diag(D, 2), 1) and np.allclose(np.diag(D, -1), 1)
+    assert C.min() >= 0 and C.max() < 1
