@@ -48,6 +48,8 @@ struct Mma<double> {
   using frag = double;
   using acc_t = d4;
   static constexpr int TK = 16, KB = 4;
+  // LDS row padding (elements) and the column swizzle of the B panel
+  static constexpr int PADA = 0, PADB = 1, SWB = 0;
   __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
   __device__ static int row(int r, int lk) { return 4 * r + lk; }
   __device__ static L a_in(double x) { return x; }
@@ -68,6 +70,12 @@ struct Mma<float> {
   using frag = float;
   using acc_t = f4;
   static constexpr int TK = 16, KB = 4;
+  // 4-byte elements: rows padded by 16 so that the 4 k rows a wave reads at
+  // once fall into disjoint bank ranges; the B panel is written with k
+  // fastest across lanes, so its column is XORed with bits 2..3 of k, which
+  // spreads those writes over all banks and leaves each 16-column block of a
+  // row where it was (reads of one k step see one constant XOR)
+  static constexpr int PADA = 16, PADB = 16, SWB = 12;
   __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
   __device__ static int row(int r, int lk) { return 4 * lk + r; }
   __device__ static L a_in(float x) { return x; }
@@ -110,9 +118,10 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
 }
 
 template <typename Tag, int TM, int TN, int RB, int CB, int TK, bool CPLX>
-__device__ __forceinline__ void apply_tile(const ApplyArgs<Tag>& a, int k, int rt, int ct,
-                                           typename Mma<Tag>::L (*As)[TK][TM],
-                                           typename Mma<Tag>::L (*Bs)[TK][TN + 1]) {
+__device__ __forceinline__ void apply_tile(
+    const ApplyArgs<Tag>& a, int k, int rt, int ct,
+    typename Mma<Tag>::L (*As)[TK][TM + Mma<Tag>::PADA],
+    typename Mma<Tag>::L (*Bs)[TK][TN + Mma<Tag>::PADB]) {
   using M = Mma<Tag>;
   using L = typename M::L;
   using TA = typename Store<Tag>::T;
@@ -211,8 +220,9 @@ __device__ __forceinline__ void apply_tile(const ApplyArgs<Tag>& a, int k, int r
     for (int u = 0; u < NB; ++u) {
       const int idx = tid + NT * u;
       const int kk = idx % TK, col = idx / TK;
-      Bs[0][kk][col] = pb_r[u];
-      if (CPLX) Bs[1][kk][col] = pb_i[u];
+      const int pc = col ^ (kk & M::SWB);
+      Bs[0][kk][pc] = pb_r[u];
+      if (CPLX) Bs[1][kk][pc] = pb_i[u];
     }
   };
 
@@ -227,17 +237,18 @@ __device__ __forceinline__ void apply_tile(const ApplyArgs<Tag>& a, int k, int r
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
         const int row = (wr * RB + i) * 16 + lr;
-        far_[i] = M::template ld<TM>(As[0], ks, lk, row);
+        far_[i] = M::template ld<TM + M::PADA>(As[0], ks, lk, row);
         if (CPLX) {
-          fai[i] = M::template ld<TM>(As[1], ks, lk, row);
+          fai[i] = M::template ld<TM + M::PADA>(As[1], ks, lk, row);
           fain[i] = M::negf(fai[i]);
         }
       }
 #pragma unroll
       for (int j = 0; j < CB; ++j) {
-        const int col = (wc * CB + j) * 16 + lr;
-        fbr[j] = M::template ld<TN + 1>(Bs[0], ks, lk, col);
-        if (CPLX) fbi[j] = M::template ld<TN + 1>(Bs[1], ks, lk, col);
+        // ks is a multiple of 4, so (ks + lk) & SWB == ks & SWB
+        const int col = ((wc * CB + j) * 16 + lr) ^ (ks & M::SWB);
+        fbr[j] = M::template ld<TN + M::PADB>(Bs[0], ks, lk, col);
+        if (CPLX) fbi[j] = M::template ld<TN + M::PADB>(Bs[1], ks, lk, col);
       }
       // Dependent MFMAs on one accumulator are kept apart: a full sweep
       // over the blocks separates the two updates of every accumulator.
@@ -293,8 +304,8 @@ __device__ __forceinline__ void apply_tile(const ApplyArgs<Tag>& a, int k, int r
 template <typename Tag, int TM, int TN, int RB, int CB, int TK>
 __global__ __launch_bounds__(NT) void apply_mfma_kernel(ApplyArgs<Tag> a) {
   using L = typename Mma<Tag>::L;
-  __shared__ L As[2][TK][TM];
-  __shared__ L Bs[2][TK][TN + 1];
+  __shared__ L As[2][TK][TM + Mma<Tag>::PADA];
+  __shared__ L Bs[2][TK][TN + Mma<Tag>::PADB];
   const int t = xcd_tile(blockIdx.x, a.total);
   const int ct = t % a.nct;
   const int rt = (t / a.nct) % a.nrt;

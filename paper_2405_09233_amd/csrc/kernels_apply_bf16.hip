@@ -6,7 +6,10 @@
 // operand fragment is one coalesced 16-byte access per lane:
 //   * the operator planes, rounded to BF16 once at setup: plane q, 16-row
 //     block rb, 32-deep k block kb form one 1 KB chunk whose lane i + 16 g
-//     holds A(16 rb + i, 32 kb + 8 g .. 8 g + 7);
+//     holds A(16 rb + i, 32 kb + 8 g .. 8 g + 7).  Within a plane the chunks
+//     run in the order (rb / 8, kb, rb % 8), so the 8 row blocks that waves
+//     of one workgroup stream side by side read 8 KB of contiguous memory
+//     per k block;
 //   * the Krylov vector, rounded to BF16 at the start of every apply into a
 //     scratch buffer: plane q, 16-column block cb, k block kb form one chunk
 //     whose lane i + 16 g holds V(32 kb + 8 g .. 8 g + 7, 16 cb + i).
@@ -26,6 +29,10 @@ namespace tsylv {
 namespace kern {
 
 namespace {
+
+// Row blocks per group of the operator's chunk order (divides the row-block
+// padding).
+constexpr int64_t kRowGroup = 8;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -73,7 +80,9 @@ __global__ void tile_bf16_kernel(const double* __restrict__ Ah, uint16_t* __rest
        t += (int64_t)gridDim.x * blockDim.x) {
     const int L = (int)(t % 64);
     const int64_t chunk = t / 64;
-    const int64_t kb = chunk % nkb, rb = (chunk / nkb) % nrb, q = chunk / (nkb * nrb);
+    const int64_t q = chunk / (nkb * nrb), c = chunk % (nkb * nrb);
+    const int64_t kb = (c % (nkb * kRowGroup)) / kRowGroup;
+    const int64_t rb = c / (nkb * kRowGroup) * kRowGroup + c % kRowGroup;
     const int64_t row = 16 * rb + (L % 16), k0 = 32 * kb + 8 * (L / 16);
     u16x8 v;
 #pragma unroll
@@ -129,8 +138,11 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
   return x * q + (x < r ? x : r) + b / 8;
 }
 
-__device__ __forceinline__ bf8 ld8(const uint16_t* p) {
-  return __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(p));
+// Operator chunks are read exactly once per apply: non-temporal loads keep
+// them from pushing the V chunks, which every workgroup of a slice re-reads,
+// out of L2.
+__device__ __forceinline__ bf8 ld8_stream(const uint16_t* p) {
+  return __builtin_bit_cast(bf8, __builtin_nontemporal_load(reinterpret_cast<const u16x8*>(p)));
 }
 
 // The -V_k Bhat_k term (a short contraction over s straight from global
@@ -262,8 +274,10 @@ __device__ __forceinline__ void bf16_wg_tasks(const Bf16Args& a, const WgPlan& p
       const int64_t rb_want = rb_begin + (task * NW + wave) * R + r;
       store[r] = rb_want < rb_begin + rb_count && rb_want < nrb_real;
       rbs[r] = min(rb_want, a.nrb - 1);  // past the end: any valid block, not stored
-      Ar[r] = a.At + ((int64_t)qr * a.nrb + rbs[r]) * nkb * 512 + lane * 8;
-      Ai[r] = CPLX ? a.At + ((int64_t)qi * a.nrb + rbs[r]) * nkb * 512 + lane * 8 : nullptr;
+      // chunk (rb, kb) of a plane sits at ((rb / 8) nkb + kb) 8 + rb % 8
+      const int64_t rofs = ((rbs[r] / kRowGroup) * nkb * kRowGroup + rbs[r] % kRowGroup) * 512;
+      Ar[r] = a.At + (int64_t)qr * a.nrb * nkb * 512 + rofs + lane * 8;
+      Ai[r] = CPLX ? a.At + (int64_t)qi * a.nrb * nkb * 512 + rofs + lane * 8 : nullptr;
     }
     u16x8 stage[NPASS];
     auto fetch = [&](int64_t ph) {
@@ -294,8 +308,8 @@ __device__ __forceinline__ void bf16_wg_tasks(const Bf16Args& a, const WgPlan& p
     auto loadA = [&](int64_t kb, int u) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        ar[u][r] = ld8(Ar[r] + kb * 512);
-        if (CPLX) ai[u][r] = ld8(Ai[r] + kb * 512);
+        ar[u][r] = ld8_stream(Ar[r] + kb * (kRowGroup * 512));
+        if (CPLX) ai[u][r] = ld8_stream(Ai[r] + kb * (kRowGroup * 512));
       }
     };
     fetch(0);
@@ -379,6 +393,7 @@ __global__ __launch_bounds__(NW * 64) void apply_bf16_wg_kernel(Bf16Args a, WgPl
 // Row blocks are padded to a multiple of kRowPad and column blocks to a
 // multiple of kColPad (the largest CB).
 constexpr int64_t kRowPad = 16, kColPad = 4;
+static_assert(kRowPad % kRowGroup == 0, "row groups tile the padded row blocks");
 // k blocks are padded to a multiple of kKPad, which every ring depth divides.
 constexpr int64_t kKPad = 8;
 
@@ -475,13 +490,11 @@ void apply_bf16(const uint16_t* At, const uint16_t* Bb, const float* V, uint16_t
   // from a sweep at n = 4096, p = 32, s = 16 / 32 / 64 and n = 8192, p = 64,
   // s = 128
   if (s <= 16)
-    launch_wg<1, 8, 8, 4, 1>(a, ncu, st);
+    launch_wg<1, 4, 8, 8, 2>(a, ncu, st);
   else if (s <= 32)
-    launch_wg<2, 8, 8, 4, 1>(a, ncu, st);
-  else if (s <= 64)
-    launch_wg<4, 4, 8, 8, 1>(a, ncu, st);
+    launch_wg<2, 2, 4, 8, 2>(a, ncu, st);
   else
-    launch_wg<4, 2, 8, 8, 2>(a, ncu, st);
+    launch_wg<4, 2, 2, 8, 2>(a, ncu, st);
 }
 
 }  // namespace kern
