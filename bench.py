@@ -11,7 +11,8 @@ Paths timed (each: W warm-up solves, then K timed solves):
   mixed     FP64 iterative refinement; each correction one tGMRES(32) cycle
             with FP32 basis vectors and FP32 MFMA slice products
   bf16      the same (tGMRES(24) cycles) with BF16 slice products (FP32
-            accumulation)
+            accumulation) and the inner basis kept as tiled BF16 vectors
+            (TSYLV_BF16_BASIS=fp32 keeps FP32 vectors instead)
   tba       TBAS(10), reported beside them (not a candidate for `value`)
 A path counts only if every timed solve reaches true FP64 relres <= tol.
 `value` is the solves/s of the fastest valid tGMRES path; every path is
@@ -198,11 +199,11 @@ def serving(tsylv, workloads, rate, duration, npool=96, seed=50):
     return out
 
 
-def measured_traffic(path, shape):
+def measured_traffic(path, shape, tiled):
     """HBM bytes per apply call from the committed counter summary, or None
-    for another path or shape, or when the kernel source has changed since
-    the counters were taken."""
-    if path != "bf16" or tuple(shape) != (4096, 64, 32):
+    for another path or shape, for the FP32-vector form of the BF16 path, or
+    when the kernel source has changed since the counters were taken."""
+    if path != "bf16" or not tiled or tuple(shape) != (4096, 64, 32):
         return None
     import hashlib
     import re
@@ -343,7 +344,11 @@ def main():
     valid = [x for x in paths if res[x]["valid"] and x != "tba"]
     best = max(valid, key=lambda x: res[x]["solves_per_s"]) if valid else paths[0]
     r = res[best]
-    elem = {"fp64": (8, 8), "mixed": (4, 4), "bf16": (2, 4)}[best]
+    # the BF16 path's vectors are tiled BF16 when the library keeps its inner
+    # basis that way (fused Gram-Schmidt: inner_m + 1 <= 64), else FP32
+    bf16_tiled = (os.environ.get("TSYLV_BF16_BASIS") != "fp32"
+                  and path_opts["bf16"].inner_m + 1 <= 64) if best == "bf16" else False
+    elem = {"fp64": (8, 8), "mixed": (4, 4), "bf16": (2, 2) if bf16_tiled else (2, 4)}[best]
     flops, bytes_ = apply_work(n, s, p, elem)
     avg_s = r["apply_avg_ms"] / 1e3
     achieved_flops = flops / avg_s
@@ -357,15 +362,18 @@ def main():
                     "unit": "TFLOP/s", "frac": achieved_flops / peak}
     kernel = {"fp64": "apply_mfma_kernel<double> (FP64 slice products)",
               "mixed": "apply_mfma_kernel<float> (FP32 slice products)",
-              "bf16": "tile_v_bf16_kernel + apply_bf16_wg_kernel (BF16 slice products; "
-                      "both launches of one apply call are timed)"}[best]
-    roofline.update({"traffic": measured_traffic(best, (n, s, p)), "kernel": kernel,
+              "bf16": ("apply_bf16_wg_kernel (BF16 slice products on tiled BF16 vectors; "
+                       "one launch per apply call)") if bf16_tiled else
+                      ("tile_v_bf16_kernel + apply_bf16_wg_kernel (BF16 slice products; "
+                       "both launches of one apply call are timed)")}[best]
+    roofline.update({"traffic": measured_traffic(best, (n, s, p), bf16_tiled), "kernel": kernel,
                      "avg_launch_ms": r["apply_avg_ms"], "launches": r["apply_launches"],
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_bytes_per_launch": bytes_})
 
     dtype = {"fp64": "f64", "mixed": "f32 (inner) + f64 (refinement)",
-             "bf16": "bf16 x bf16 -> f32 (inner) + f64 (refinement)"}[best]
+             "bf16": "bf16 x bf16 -> f32 (inner; BF16 basis) + f64 (refinement)"
+             if bf16_tiled else "bf16 x bf16 -> f32 (inner) + f64 (refinement)"}[best]
     out = {
         "metric": METRIC,
         "value": r["solves_per_s"] if r["valid"] else 0.0,

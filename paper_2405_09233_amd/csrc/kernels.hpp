@@ -44,6 +44,27 @@ void apply_bf16(const uint16_t* At, const uint16_t* Bb, const float* V, uint16_t
                 float* out, const float* Y, double alpha, double beta, int64_t n, int64_t s,
                 int p, hipStream_t st);
 
+// ---- BF16 Krylov vectors (the inner basis of the BF16-refined solves) ----
+// A vector of p Fourier planes n x s stored as BF16 bits in the tiled order
+// of the BF16 apply's V operand: plane q, 16-column block cb, 32-row block kb
+// form one 512-element chunk whose lane i + 16 g holds rows 32 kb + 8 g ..
+// + 7 of column 16 cb + i.  bf16_vtiled_elems(n, s, p) elements; the padding
+// (rows >= n, columns >= s) is zero, and every kernel below keeps it zero.
+struct bf16t {
+  uint16_t bits;
+};
+// Xt = tiled(a X) (X: p planes n x s, FP64), padding written as zero.
+void tile_scale_bf16(const double* X, bf16t* Xt, double a, int64_t n, int64_t s, int p,
+                     hipStream_t st);
+// X -= sum_i y[i] untiled(V_i) (y on the device, nv entries, FP64 sums; the
+// sign of mupdate).
+void untile_update_bf16(const bf16t* V, int64_t ldv, int nv, const double* y, double* X,
+                        int64_t n, int64_t s, int p, hipStream_t st);
+// out = alpha (Ahat_k V_k - V_k Bhat_k) for every slice, V and out tiled
+// (out's padding written as zero; out must not alias V).
+void apply_bf16_tiled(const uint16_t* At, const uint16_t* Bb, const bf16t* V, bf16t* out,
+                      double alpha, int64_t n, int64_t s, int p, hipStream_t st);
+
 // ---- multi-vector kernels on flat vectors of N reals ----
 
 // Number of per-block partial rows used by mdot for length N.
@@ -71,6 +92,8 @@ void mupdate(const float* V, int64_t ldv, int nv, const double* h, double* w,
 
 // Fused CGS2 passes over a basis whose vectors V_i are stored unnormalised
 // with sigma[i] = 1 / ||V_i|| (device array).  ortho_chunks(N) partial rows.
+// BF16 vectors are widened on load and the results rounded to nearest even
+// on store; every sum runs in FP64.
 //   ortho_dots:   part[c][i] = sigma_i V_i . w (i < nv), part[c][nv] = ||w||^2
 //   ortho_update: w -= sum_i h[i] sigma[i] V_i; then mode 0: part[c][i] =
 //                 sigma_i V_i . w (the next pass), mode 1: part[c][0] = ||w||^2
@@ -85,6 +108,10 @@ void ortho_update(const double* V, int64_t ldv, int nv, const double* h, const d
                   double* w, int64_t N, double* part, int ldp, int mode, hipStream_t st);
 void ortho_update(const float* V, int64_t ldv, int nv, const double* h, const double* sigma,
                   float* w, int64_t N, double* part, int ldp, int mode, hipStream_t st);
+void ortho_dots(const bf16t* V, int64_t ldv, int nv, const double* sigma, const bf16t* w,
+                int64_t N, double* part, int ldp, hipStream_t st);
+void ortho_update(const bf16t* V, int64_t ldv, int nv, const double* h, const double* sigma,
+                  bf16t* w, int64_t N, double* part, int ldp, int mode, hipStream_t st);
 
 // Delayed reorthogonalisation sweeps (V: nv basis vectors, sigma as above):
 //   ortho_dots2:   part[c] = [sigma_i V_i . u, sigma_i V_i . w, u . w, u . u,
@@ -99,6 +126,10 @@ void ortho_dots2(const float* V, int64_t ldv, int nv, const double* sigma, const
 void ortho_update2(const double* V, int64_t ldv, int nv, const double* coef, double* u, double* w,
                    int64_t N, hipStream_t st);
 void ortho_update2(const float* V, int64_t ldv, int nv, const double* coef, float* u, float* w,
+                   int64_t N, hipStream_t st);
+void ortho_dots2(const bf16t* V, int64_t ldv, int nv, const double* sigma, const bf16t* u,
+                 const bf16t* w, int64_t N, double* part, int ldp, hipStream_t st);
+void ortho_update2(const bf16t* V, int64_t ldv, int nv, const double* coef, bf16t* u, bf16t* w,
                    int64_t N, hipStream_t st);
 
 // out[e] = a * x[e]  (the FP64 -> FP32 form rounds the scaled value)

@@ -37,6 +37,7 @@ constexpr int64_t kRowGroup = 8;
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
@@ -118,12 +119,67 @@ __global__ void tile_v_bf16_kernel(const float* __restrict__ V, uint16_t* __rest
   }
 }
 
+// Tiled BF16 copy of a X for FP64 planes X (same order as tile_v_bf16_kernel;
+// a X rounded to FP32, then to the nearest-even BF16).
+__global__ void tile_scale_bf16_kernel(const double* __restrict__ X, uint16_t* __restrict__ Xt,
+                                       double a, int64_t n, int64_t s, int p, int64_t ncb,
+                                       int64_t nkb) {
+  const int64_t total = (int64_t)p * ncb * nkb * 64;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int L = (int)(t % 64);
+    const int64_t chunk = t / 64;
+    const int64_t kb = chunk % nkb, cb = (chunk / nkb) % ncb, q = chunk / (nkb * ncb);
+    const int64_t col = 16 * cb + (L % 16), k0 = 32 * kb + 8 * (L / 16);
+    const double* src = X + q * n * s + n * col;
+    u16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      v[e] = (col < s && k0 + e < n) ? bf16_bits((float)(a * src[k0 + e])) : (uint16_t)0;
+    *reinterpret_cast<u16x8*>(Xt + t * 8) = v;
+  }
+}
+
+// X -= sum_i y[i] V_i for tiled BF16 vectors V_i and FP64 planes X: every
+// thread owns one lane slot of a chunk (8 consecutive rows of one column),
+// sums the nv vectors in FP64 in index order and subtracts from the 8 rows
+// of X.
+__global__ void untile_update_bf16_kernel(const uint16_t* __restrict__ V, int64_t ldv, int nv,
+                                          const double* __restrict__ y, double* __restrict__ X,
+                                          int64_t n, int64_t s, int p, int64_t ncb,
+                                          int64_t nkb) {
+  const int64_t total = (int64_t)p * ncb * nkb * 64;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int L = (int)(t % 64);
+    const int64_t chunk = t / 64;
+    const int64_t kb = chunk % nkb, cb = (chunk / nkb) % ncb, q = chunk / (nkb * ncb);
+    const int64_t col = 16 * cb + (L % 16), k0 = 32 * kb + 8 * (L / 16);
+    if (col >= s || k0 >= n) continue;
+    double acc[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[e] = 0.0;
+    for (int i = 0; i < nv; ++i) {
+      const u16x8 v = *reinterpret_cast<const u16x8*>(V + i * ldv + t * 8);
+      const double c = y[i];
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        acc[e] = fma(c, (double)__uint_as_float((uint32_t)v[e] << 16), acc[e]);
+    }
+    double* dst = X + q * n * s + n * col;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (k0 + e < n) dst[k0 + e] -= acc[e];
+  }
+}
+
 struct Bf16Args {
   const uint16_t* At;  // tiled operator planes (nrb x nkb chunks per plane)
   const uint16_t* Bb;  // bf16 planes of Bhat (s x s column-major), or null
   const uint16_t* Vt;  // tiled V planes (ncb x nkb chunks per plane)
-  const float* V;
+  const float* V;      // V in FP32 planes (null when the vectors are tiled)
   float* out;
+  uint16_t* outt;      // tiled BF16 output (the tiled-vector form)
   const float* Y;
   double alpha, beta;
   int64_t n, s;
@@ -147,14 +203,20 @@ __device__ __forceinline__ bf8 ld8_stream(const uint16_t* p) {
 
 // The -V_k Bhat_k term (a short contraction over s straight from global
 // memory) and the epilogue out = alpha W + beta Y for R x CB blocks.
-template <int CB, int R, bool CPLX>
+// Element (row, col) of plane q of a tiled vector (see tile_v_bf16_kernel).
+__device__ __forceinline__ int64_t tiled_at(const Bf16Args& a, int q, int64_t row, int64_t col) {
+  return (((int64_t)q * a.ncb + col / 16) * a.nkb + row / 32) * 512 +
+         ((col % 16) + 16 * ((row % 32) / 8)) * 8 + row % 8;
+}
+
+template <int CB, int R, bool CPLX, bool TIO>
 __device__ __forceinline__ void bf16_finish(const Bf16Args& a, int qr, int qi, int64_t rb0,
                                             int64_t cb0, f4 (&accr)[R][CB], f4 (&acci)[R][CB]) {
   const int64_t n = a.n, s = a.s, ns = n * s;
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lg = lane >> 4;
-  const float* Vr = a.V + qr * ns;
-  const float* Vi = CPLX ? a.V + qi * ns : nullptr;
+  const float* Vr = TIO ? nullptr : a.V + qr * ns;
+  const float* Vi = (CPLX && !TIO) ? a.V + qi * ns : nullptr;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t row = 16 * (rb0 + r) + li;
@@ -168,8 +230,15 @@ __device__ __forceinline__ void bf16_finish(const Bf16Args& a, int qr, int qi, i
         for (int e = 0; e < 8; ++e) {
           const int64_t kk = k1 + 8 * lg + e;
           const bool ok = row < n && kk < s;
-          fr[e] = ok ? (uint16_t)(bf16_bits(Vr[row + n * kk]) ^ 0x8000u) : (uint16_t)0;
-          if (CPLX) fi[e] = ok ? (uint16_t)(bf16_bits(Vi[row + n * kk]) ^ 0x8000u) : (uint16_t)0;
+          if (TIO) {
+            fr[e] = ok ? (uint16_t)(a.Vt[tiled_at(a, qr, row, kk)] ^ 0x8000u) : (uint16_t)0;
+            if (CPLX)
+              fi[e] = ok ? (uint16_t)(a.Vt[tiled_at(a, qi, row, kk)] ^ 0x8000u) : (uint16_t)0;
+          } else {
+            fr[e] = ok ? (uint16_t)(bf16_bits(Vr[row + n * kk]) ^ 0x8000u) : (uint16_t)0;
+            if (CPLX)
+              fi[e] = ok ? (uint16_t)(bf16_bits(Vi[row + n * kk]) ^ 0x8000u) : (uint16_t)0;
+          }
         }
         const bf8 nvr = __builtin_bit_cast(bf8, fr);  // -Re V
         bf8 nvi, pvi;
@@ -202,6 +271,28 @@ __device__ __forceinline__ void bf16_finish(const Bf16Args& a, int qr, int qi, i
 
     // Epilogue (FP32 result layout: element (i, j) in lane j + 16 (i / 4),
     // register i % 4).
+    if (TIO) {
+      // Rows 16 rb + 4 lg .. + 3 of column col are 4 consecutive elements of
+      // one lane slot of the tiled output: one 8-byte store.  Rows >= n and
+      // columns >= s are written as zero (they are the tiled padding).
+      const int64_t rb = rb0 + r;
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        const int64_t col = 16 * (cb0 + j) + li;
+        const int64_t at = tiled_at(a, 0, 16 * rb + 4 * lg, col);
+        const int64_t plane = a.ncb * a.nkb * 512;
+        u16x4 vr, vi;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = col < s && 16 * rb + 4 * lg + e < n;
+          vr[e] = ok ? bf16_bits((float)(a.alpha * (double)accr[r][j][e])) : (uint16_t)0;
+          if (CPLX) vi[e] = ok ? bf16_bits((float)(a.alpha * (double)acci[r][j][e])) : (uint16_t)0;
+        }
+        *reinterpret_cast<u16x4*>(a.outt + qr * plane + at) = vr;
+        if (CPLX) *reinterpret_cast<u16x4*>(a.outt + qi * plane + at) = vi;
+      }
+      continue;
+    }
     float* Or = a.out + qr * ns;
     float* Oi = CPLX ? a.out + qi * ns : nullptr;
     const float* Yr = a.Y ? a.Y + qr * ns : nullptr;
@@ -239,7 +330,7 @@ struct WgPlan {
   int wr, wc;   // workgroups per real / complex slice and column tile
 };
 
-template <int CB, int D, int P, int NW, int R, bool CPLX>
+template <int CB, int D, int P, int NW, int R, bool CPLX, bool TIO>
 __device__ __forceinline__ void bf16_wg_tasks(const Bf16Args& a, const WgPlan& pl, int k,
                                               int64_t rb_begin, int64_t rb_count, int64_t cb0,
                                               uint16_t* lds) {
@@ -361,12 +452,12 @@ __device__ __forceinline__ void bf16_wg_tasks(const Bf16Args& a, const WgPlan& p
         fr[0][j] = accr[r][j];
         fi[0][j] = acci[r][j];
       }
-      bf16_finish<CB, 1, CPLX>(a, qr, qi, rbs[r], cb0, fr, fi);
+      bf16_finish<CB, 1, CPLX, TIO>(a, qr, qi, rbs[r], cb0, fr, fi);
     }
   }
 }
 
-template <int CB, int D, int P, int NW, int R>
+template <int CB, int D, int P, int NW, int R, bool TIO>
 __global__ __launch_bounds__(NW * 64) void apply_bf16_wg_kernel(Bf16Args a, WgPlan pl) {
   extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
   const int t = xcd_tile(blockIdx.x, a.total);
@@ -385,9 +476,9 @@ __global__ __launch_bounds__(NW * 64) void apply_bf16_wg_kernel(Bf16Args a, WgPl
   const int64_t rb_begin = (int64_t)w * span;
   const int64_t cb0 = (int64_t)ct * CB;
   if (real)
-    bf16_wg_tasks<CB, D, P, NW, R, false>(a, pl, k, rb_begin, span, cb0, lds);
+    bf16_wg_tasks<CB, D, P, NW, R, false, TIO>(a, pl, k, rb_begin, span, cb0, lds);
   else
-    bf16_wg_tasks<CB, D, P, NW, R, true>(a, pl, k, rb_begin, span, cb0, lds);
+    bf16_wg_tasks<CB, D, P, NW, R, true, TIO>(a, pl, k, rb_begin, span, cb0, lds);
 }
 
 // Row blocks are padded to a multiple of kRowPad and column blocks to a
@@ -417,7 +508,7 @@ inline WgPlan plan_wg(int64_t n, int p, int nct, int nw, int ncu) {
   return best;
 }
 
-template <int CB, int D, int P, int NW, int R>
+template <int CB, int D, int P, int NW, int R, bool TIO>
 void launch_wg(Bf16Args a, int ncu, hipStream_t st) {
   static_assert(kKPad % P == 0 && P % D == 0, "phase and ring must divide the k padding");
   a.nct = (int)((a.s + 16 * CB - 1) / (16 * CB));
@@ -426,9 +517,9 @@ void launch_wg(Bf16Args a, int ncu, hipStream_t st) {
   a.total = a.nct * (nreal * pl.wr + (nsl - nreal) * pl.wc);
   const size_t lds = 2 * (size_t)P * 2 * CB * 1024;  // two buffers of complex phases
   TSYLV_HIP(hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&apply_bf16_wg_kernel<CB, D, P, NW, R>),
+      reinterpret_cast<const void*>(&apply_bf16_wg_kernel<CB, D, P, NW, R, TIO>),
       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((apply_bf16_wg_kernel<CB, D, P, NW, R>), dim3(a.total), dim3(NW * 64), lds,
+  hipLaunchKernelGGL((apply_bf16_wg_kernel<CB, D, P, NW, R, TIO>), dim3(a.total), dim3(NW * 64), lds,
                      st, a, pl);
   TSYLV_LAUNCH_CHECK();
 }
@@ -454,6 +545,22 @@ void tile_operator_bf16(const double* Ah, uint16_t* At, int64_t n, int p, hipStr
   int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
   hipLaunchKernelGGL(tile_bf16_kernel, dim3(blocks), dim3(256), 0, st, Ah, At, n, p, nrb, nkb);
   TSYLV_LAUNCH_CHECK();
+}
+
+// (column blocks, ring depth, phase length, waves, row blocks per wave)
+// from a sweep at n = 4096, p = 32, s = 16 / 32 / 64 and n = 8192, p = 64,
+// s = 128
+template <bool TIO>
+void launch_cfg(const Bf16Args& a, hipStream_t st) {
+  int dev = 0, ncu = 0;
+  TSYLV_HIP(hipGetDevice(&dev));
+  TSYLV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  if (a.s <= 16)
+    launch_wg<1, 4, 8, 8, 2, TIO>(a, ncu, st);
+  else if (a.s <= 32)
+    launch_wg<2, 2, 4, 8, 2, TIO>(a, ncu, st);
+  else
+    launch_wg<4, 2, 2, 8, 2, TIO>(a, ncu, st);
 }
 
 void apply_bf16(const uint16_t* At, const uint16_t* Bb, const float* V, uint16_t* Vt,
@@ -483,18 +590,51 @@ void apply_bf16(const uint16_t* At, const uint16_t* Bb, const float* V, uint16_t
                        a.nkb);
     TSYLV_LAUNCH_CHECK();
   }
-  int dev = 0, ncu = 0;
-  TSYLV_HIP(hipGetDevice(&dev));
-  TSYLV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  // (column blocks, ring depth, phase length, waves, row blocks per wave)
-  // from a sweep at n = 4096, p = 32, s = 16 / 32 / 64 and n = 8192, p = 64,
-  // s = 128
-  if (s <= 16)
-    launch_wg<1, 4, 8, 8, 2>(a, ncu, st);
-  else if (s <= 32)
-    launch_wg<2, 2, 4, 8, 2>(a, ncu, st);
-  else
-    launch_wg<4, 2, 2, 8, 2>(a, ncu, st);
+  launch_cfg<false>(a, st);
+}
+
+void apply_bf16_tiled(const uint16_t* At, const uint16_t* Bb, const bf16t* V, bf16t* out,
+                      double alpha, int64_t n, int64_t s, int p, hipStream_t st) {
+  if (n <= 0 || s <= 0 || p <= 0) return;
+  if (reinterpret_cast<const void*>(V) == reinterpret_cast<const void*>(out))
+    throw Error(TSYLV_EINVAL, "apply: tiled output must not alias the input");
+  Bf16Args a{};
+  a.At = At;
+  a.Bb = Bb;
+  a.Vt = reinterpret_cast<const uint16_t*>(V);
+  a.outt = reinterpret_cast<uint16_t*>(out);
+  a.alpha = alpha;
+  a.n = n;
+  a.s = s;
+  a.p = p;
+  a.nrb = row_blocks(n);
+  a.nkb = k_blocks(n);
+  a.ncb = col_blocks(s);
+  launch_cfg<true>(a, st);
+}
+
+void tile_scale_bf16(const double* X, bf16t* Xt, double a, int64_t n, int64_t s, int p,
+                     hipStream_t st) {
+  if (n <= 0 || s <= 0 || p <= 0) return;
+  const int64_t ncb = col_blocks(s), nkb = k_blocks(n);
+  const int64_t total = (int64_t)p * ncb * nkb * 64;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(tile_scale_bf16_kernel, dim3(blocks), dim3(256), 0, st, X,
+                     reinterpret_cast<uint16_t*>(Xt), a, n, s, p, ncb, nkb);
+  TSYLV_LAUNCH_CHECK();
+}
+
+void untile_update_bf16(const bf16t* V, int64_t ldv, int nv, const double* y, double* X,
+                        int64_t n, int64_t s, int p, hipStream_t st) {
+  if (nv <= 0 || n <= 0 || s <= 0 || p <= 0) return;
+  if (ldv % 8 != 0 || reinterpret_cast<uintptr_t>(V) % 16 != 0)
+    throw Error(TSYLV_EINVAL, "untile_update: basis not aligned");
+  const int64_t ncb = col_blocks(s), nkb = k_blocks(n);
+  const int64_t total = (int64_t)p * ncb * nkb * 64;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(untile_update_bf16_kernel, dim3(blocks), dim3(256), 0, st,
+                     reinterpret_cast<const uint16_t*>(V), ldv, nv, y, X, n, s, p, ncb, nkb);
+  TSYLV_LAUNCH_CHECK();
 }
 
 }  // namespace kern

@@ -259,8 +259,44 @@ constexpr int kOWaves = kBlock / 64;
 constexpr int kOGroups = 4;  // vector groups per wave
 constexpr int kOChunk = 8192;
 
+// Device view of kern::bf16t: widens exactly to FP64, and is built from an
+// FP64 value by rounding to FP32 and then to the nearest-even BF16.
+struct OB16 {
+  uint16_t bits;
+  OB16() = default;
+  __device__ explicit OB16(double x) {
+    uint32_t u = __float_as_uint((float)x);
+    if ((u & 0x7f800000u) == 0x7f800000u) {
+      bits = (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));  // inf stays inf, NaN quiet
+    } else {
+      u += 0x7fffu + ((u >> 16) & 1u);
+      bits = (uint16_t)(u >> 16);
+    }
+  }
+  __device__ operator double() const { return (double)__uint_as_float((uint32_t)bits << 16); }
+};
+static_assert(sizeof(OB16) == sizeof(bf16t), "OB16 is a view of bf16t");
+struct alignas(8) OB16x4 {
+  OB16 e[4];
+};
+
+// Keeps a loaded value in its register until here (an empty asm the
+// compiler cannot see through).
+template <typename T>
+__device__ __forceinline__ void opin(T& x) {
+  asm volatile("" : "+v"(x));
+}
+template <>
+__device__ __forceinline__ void opin(OB16& x) {
+  asm volatile("" : "+v"(x.bits));
+}
+
 template <typename T, int EPL>
 struct OVec;
+template <>
+struct OVec<OB16, 4> {
+  using type = OB16x4;
+};
 template <>
 struct OVec<float, 2> {
   using type = float2;
@@ -452,7 +488,7 @@ __device__ __forceinline__ void oupdate_tile(const T* __restrict__ V, int64_t ld
 #pragma unroll
     for (int k = 0; k < VPW; ++k)
 #pragma unroll
-      for (int l = 0; l < EPL; ++l) asm volatile("" : "+v"(v[k][l]));
+      for (int l = 0; l < EPL; ++l) opin(v[k][l]);
 #pragma unroll
     for (int k = 0; k < VPW; ++k)
 #pragma unroll
@@ -773,8 +809,9 @@ int ortho_chunks(int64_t N) { return (int)((N + kOChunk - 1) / kOChunk); }
 
 int ortho_max_vectors(bool) { return 16 * kOGroups; }
 
-// elements per lane: 16-byte accesses for both types (measured faster than
-// 8-byte FP32 accesses despite the extra registers)
+// elements per lane: 16-byte accesses for FP64 and FP32 (measured faster than
+// 8-byte FP32 accesses despite the extra registers), 8-byte ones for BF16
+// (four values per lane keep the register count of the FP32 kernels)
 template <typename T>
 constexpr int ortho_epl() {
   return sizeof(T) == 8 ? 2 : 4;
@@ -863,6 +900,17 @@ void ortho_update(const float* V, int64_t ldv, int nv, const double* h, const do
   ortho_update_any<float>(V, ldv, nv, h, sigma, w, N, part, ldp, mode, st);
 }
 
+void ortho_dots(const bf16t* V, int64_t ldv, int nv, const double* sigma, const bf16t* w,
+                int64_t N, double* part, int ldp, hipStream_t st) {
+  ortho_dots_any<OB16>(reinterpret_cast<const OB16*>(V), ldv, nv, sigma,
+                       reinterpret_cast<const OB16*>(w), N, part, ldp, st);
+}
+void ortho_update(const bf16t* V, int64_t ldv, int nv, const double* h, const double* sigma,
+                  bf16t* w, int64_t N, double* part, int ldp, int mode, hipStream_t st) {
+  ortho_update_any<OB16>(reinterpret_cast<const OB16*>(V), ldv, nv, h, sigma,
+                         reinterpret_cast<OB16*>(w), N, part, ldp, mode, st);
+}
+
 template <typename T>
 static void ortho_dots2_any(const T* V, int64_t ldv, int nv, const double* sigma, const T* u,
                             const T* w, int64_t N, double* part, int ldp, hipStream_t st) {
@@ -920,6 +968,17 @@ void ortho_update2(const double* V, int64_t ldv, int nv, const double* coef, dou
 void ortho_update2(const float* V, int64_t ldv, int nv, const double* coef, float* u, float* w,
                    int64_t N, hipStream_t st) {
   ortho_update2_any<float>(V, ldv, nv, coef, u, w, N, st);
+}
+void ortho_dots2(const bf16t* V, int64_t ldv, int nv, const double* sigma, const bf16t* u,
+                 const bf16t* w, int64_t N, double* part, int ldp, hipStream_t st) {
+  ortho_dots2_any<OB16>(reinterpret_cast<const OB16*>(V), ldv, nv, sigma,
+                        reinterpret_cast<const OB16*>(u), reinterpret_cast<const OB16*>(w), N,
+                        part, ldp, st);
+}
+void ortho_update2(const bf16t* V, int64_t ldv, int nv, const double* coef, bf16t* u, bf16t* w,
+                   int64_t N, hipStream_t st) {
+  ortho_update2_any<OB16>(reinterpret_cast<const OB16*>(V), ldv, nv, coef,
+                          reinterpret_cast<OB16*>(u), reinterpret_cast<OB16*>(w), N, st);
 }
 
 template <typename TI, typename TO>

@@ -42,8 +42,10 @@
 // is synchronised.
 #include <algorithm>
 #include <chrono>
-#include <cstdlib>
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -83,6 +85,7 @@ struct RedBuf {
 template <typename TV>
 struct CycleWS {
   TV* basis = nullptr;
+  int64_t len = 0;  // elements per vector (the tiled length for BF16 vectors)
   int64_t ldv = 0;
   int m = 0;
   RedBuf red;
@@ -103,6 +106,7 @@ struct CycleWS {
   // host: pinned staging of 7 (m + 2) + 2 doubles
   void carve(Workspace& ws, int64_t N, int m_, double* host) {
     m = m_;
+    len = N;
     ldv = round_up(N, 64);
     basis = ws.take<TV>((int64_t)(m + 1) * ldv);
     red.nchunks = kern::mdot_chunks(N);  // >= ortho_chunks(N)
@@ -256,11 +260,29 @@ Setup setup_fourier(Ctx& ctx, hipStream_t st, bool profile, Workspace& ws, int64
   return S;
 }
 
+// The fused Gram-Schmidt kernels take the whole cycle's basis at once.
+static bool fused_cycle(const tsylv_opts& o) {
+  return (o.refine ? o.inner_m : o.m) + 1 <= kern::ortho_max_vectors(o.refine != 0);
+}
+
+// BF16-refined solves keep their inner basis as tiled BF16 vectors (the
+// layout the BF16 apply reads), halving the Gram-Schmidt traffic; with the
+// fused kernels only.  TSYLV_BF16_BASIS=fp32 keeps FP32 vectors instead.
+static bool bf16_basis(const tsylv_opts& o) {
+  if (!o.refine || o.prec != TSYLV_BF16 || !fused_cycle(o)) return false;
+  const char* f = std::getenv("TSYLV_BF16_BASIS");
+  return !(f && std::strcmp(f, "fp32") == 0);
+}
+
 size_t krylov_workspace_bytes(int64_t n, int64_t s, int64_t p, const tsylv_opts& o) {
   const int64_t N = n * s * p;
   size_t b = setup_bytes(n, s, p);
   if (!o.refine) return b + CycleWS<double>::bytes(N, o.m);
   b += Workspace::bytes_for(N, 8);  // FP64 residual
+  if (bf16_basis(o))
+    return b + CycleWS<kern::bf16t>::bytes(kern::bf16_vtiled_elems(n, s, (int)p), o.inner_m) +
+           Workspace::bytes_for(kern::bf16_tiled_elems(n, (int)p), 2) +
+           Workspace::bytes_for(p * s * s, 2);
   b += CycleWS<float>::bytes(N, o.inner_m);
   if (o.prec == TSYLV_BF16)
     b += Workspace::bytes_for(kern::bf16_tiled_elems(n, (int)p), 2) +
@@ -291,6 +313,8 @@ struct KrylovState {
   Operator op;
   CycleWS<double> w64;
   CycleWS<float> w32;
+  CycleWS<kern::bf16t> w16;
+  bool tiled = false;  // inner basis in tiled BF16 (w16) instead of FP32 (w32)
   double* R64 = nullptr;
   RedBuf* red = nullptr;
 
@@ -336,7 +360,8 @@ struct KrylovState {
     op.p = p;
     op.Ah64 = S.Ah;
     op.Bh64 = S.Bh;
-    fused = (refine ? o.inner_m : o.m) + 1 <= kern::ortho_max_vectors(refine);
+    fused = fused_cycle(o);
+    tiled = bf16_basis(o);
     {
       const char* f = std::getenv("TSYLV_KRYLOV_CGS2");  // force the three-sweep CGS2 path
       delayed = fused && !(f && f[0] == '1');
@@ -344,6 +369,22 @@ struct KrylovState {
     if (!refine) {
       w64.carve(ws, N, o.m, pinned);
       red = &w64.red;
+    } else if (tiled) {
+      R64 = ws.take<double>(N);
+      const int64_t Nt = kern::bf16_vtiled_elems(n, s, (int)p);
+      w16.carve(ws, Nt, o.inner_m, pinned);
+      red = &w16.red;
+      // The tiled padding (rows >= n, columns >= s) must read as zero; the
+      // kernels that write basis vectors keep it so.
+      if (Nt != N)
+        TSYLV_HIP(hipMemsetAsync(w16.basis, 0, (size_t)(o.inner_m + 1) * w16.ldv * 2, st));
+      op.low = TSYLV_BF16;
+      uint16_t* Ab = ws.take<uint16_t>(kern::bf16_tiled_elems(n, (int)p));
+      uint16_t* Bb = ws.take<uint16_t>(p * s * s);
+      kern::tile_operator_bf16(S.Ah, Ab, n, (int)p, st);
+      kern::convert_f64_bf16(S.Bh, Bb, p * s * s, st);
+      op.Ahb = Ab;
+      op.Bhb = Bb;
     } else {
       R64 = ws.take<double>(N);
       w32.carve(ws, N, o.inner_m, pinned);
@@ -380,10 +421,18 @@ struct KrylovState {
       kern::apply_f32(op.Ah32, op.Bh32, V, out, Y, alpha, beta_, n, s, (int)p, st);
   }
 
+  void apply(const kern::bf16t* V, kern::bf16t* out, const kern::bf16t* Y, double alpha,
+             double beta_) {
+    ProfScope ps(ctx, TSYLV_K_APPLY_LOW, st, prof);
+    if (Y || beta_ != 0.0) throw Error(TSYLV_EINVAL, "apply: tiled vectors take no Y");
+    kern::apply_bf16_tiled(op.Ahb, op.Bhb, V, out, alpha, n, s, (int)p, st);
+  }
+
   // ||v||^2 to red->h_ww[0] after the next synchronisation.
   void enqueue_norm2(const double* v) {
     kern::mdot_partial((const double*)nullptr, 0, 0, v, N, red->part, red->ldp, 1, st);
-    kern::reduce_partials(red->part, red->nchunks, red->ldp, 1, red->d_ww, st);
+    // chunks of v's own length (a tiled basis has longer vectors than v)
+    kern::reduce_partials(red->part, kern::mdot_chunks(N), red->ldp, 1, red->d_ww, st);
     TSYLV_HIP(hipMemcpyAsync(red->h_ww, red->d_ww, sizeof(double), hipMemcpyDeviceToHost, st));
   }
 
@@ -395,20 +444,23 @@ struct KrylovState {
     const RedBuf& r = w.red;
     if (fused) {
       // W = M(sigma_j V_j); CGS2 against sigma_i V_i in three sweeps.
+      const int64_t L = w.len;
       TSYLV_HIP(hipMemcpyAsync(w.d_sigma, w.h_sigma, nv * sizeof(double), hipMemcpyHostToDevice,
                                st));
       apply((const TV*)w.V(j), W, (const TV*)nullptr, w.h_sigma[j], 0.0);
       ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
-      const int och = kern::ortho_chunks(N);
-      kern::ortho_dots((const TV*)w.basis, w.ldv, nv, w.d_sigma, (const TV*)W, N, r.part, r.ldp,
+      const int och = kern::ortho_chunks(L);
+      kern::ortho_dots((const TV*)w.basis, w.ldv, nv, w.d_sigma, (const TV*)W, L, r.part, r.ldp,
                        st);
       kern::reduce_partials(r.part, och, r.ldp, nv + 1, w.d_h1, st);
-      kern::ortho_update((const TV*)w.basis, w.ldv, nv, w.d_h1, w.d_sigma, W, N, r.part, r.ldp, 0,
+      kern::ortho_update((const TV*)w.basis, w.ldv, nv, w.d_h1, w.d_sigma, W, L, r.part, r.ldp, 0,
                          st);
       kern::reduce_partials(r.part, och, r.ldp, nv, w.d_h2, st);
-      kern::ortho_update((const TV*)w.basis, w.ldv, nv, w.d_h2, w.d_sigma, W, N, r.part, r.ldp, 1,
+      kern::ortho_update((const TV*)w.basis, w.ldv, nv, w.d_h2, w.d_sigma, W, L, r.part, r.ldp, 1,
                          st);
       kern::reduce_partials(r.part, och, r.ldp, 1, r.d_ww, st);
+    } else if constexpr (std::is_same_v<TV, kern::bf16t>) {
+      throw Error(TSYLV_EINVAL, "krylov: BF16 vectors need the fused kernels");
     } else {
       if (pending_scale != 0.0) {  // step 3(e) of the previous step: V_j = W / h_{j,j-1}
         kern::scale((const TV*)w.V(j), w.V(j), pending_scale, N, st);
@@ -452,13 +504,14 @@ struct KrylovState {
   template <typename TV>
   void enqueue_round(CycleWS<TV>& w) {
     const RedBuf& r = w.red;
-    const int och = kern::ortho_chunks(N);
+    const int64_t L = w.len;
+    const int och = kern::ortho_chunks(L);
     double* d_coef = w.d_sigma + (w.m + 2);
     if (dj == 0) {
       TSYLV_HIP(hipMemcpyAsync(w.d_sigma, w.h_sigma, sizeof(double), hipMemcpyHostToDevice, st));
       apply((const TV*)w.V(0), w.V(1), (const TV*)nullptr, w.h_sigma[0], 0.0);
       ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
-      kern::ortho_dots((const TV*)w.basis, w.ldv, 1, w.d_sigma, (const TV*)w.V(1), N, r.part,
+      kern::ortho_dots((const TV*)w.basis, w.ldv, 1, w.d_sigma, (const TV*)w.V(1), L, r.part,
                        r.ldp, st);
       kern::reduce_partials(r.part, och, r.ldp, 2, w.d_h1, st);
     } else {
@@ -467,18 +520,18 @@ struct KrylovState {
       {
         ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
         kern::ortho_update2((const TV*)w.basis, w.ldv, nv_upd, d_coef,
-                            corr_slot >= 0 ? w.V(corr_slot) : (TV*)nullptr, w.V(dj), N, st);
+                            corr_slot >= 0 ? w.V(corr_slot) : (TV*)nullptr, w.V(dj), L, st);
       }
       if (final_round) {
         ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
-        kern::ortho_dots((const TV*)w.basis, w.ldv, dj, w.d_sigma, (const TV*)w.V(dj), N, r.part,
+        kern::ortho_dots((const TV*)w.basis, w.ldv, dj, w.d_sigma, (const TV*)w.V(dj), L, r.part,
                          r.ldp, st);
         kern::reduce_partials(r.part, och, r.ldp, dj + 1, w.d_h1, st);
       } else {
         apply((const TV*)w.V(dj), w.V(dj + 1), (const TV*)nullptr, 1.0, 0.0);
         ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
         kern::ortho_dots2((const TV*)w.basis, w.ldv, dj, w.d_sigma, (const TV*)w.V(dj),
-                          (const TV*)w.V(dj + 1), N, r.part, r.ldp, st);
+                          (const TV*)w.V(dj + 1), L, r.part, r.ldp, st);
         kern::reduce_partials(r.part, och, r.ldp, 2 * dj + 3, w.d_h1, st);
       }
     }
@@ -660,7 +713,10 @@ struct KrylovState {
   void enqueue_update(CycleWS<TV>& w) {
     TSYLV_HIP(hipMemcpyAsync(w.d_y, w.h_y, pending_update * sizeof(double), hipMemcpyHostToDevice,
                              st));
-    kern::mupdate((const TV*)w.basis, w.ldv, pending_update, w.d_y, S.Zx, N, st);
+    if constexpr (std::is_same_v<TV, kern::bf16t>)
+      kern::untile_update_bf16(w.basis, w.ldv, pending_update, w.d_y, S.Zx, n, s, (int)p, st);
+    else
+      kern::mupdate((const TV*)w.basis, w.ldv, pending_update, w.d_y, S.Zx, N, st);
     pending_update = 0;
   }
 
@@ -671,7 +727,9 @@ struct KrylovState {
         break;
       case RESTART: {
         if (pending_update) {
-          if (refine)
+          if (tiled)
+            enqueue_update(w16);
+          else if (refine)
             enqueue_update(w32);
           else
             enqueue_update(w64);
@@ -687,7 +745,10 @@ struct KrylovState {
       }
       case STEP:
         if (scale_v0) {
-          if (refine) {
+          if (tiled) {
+            kern::tile_scale_bf16(R64, w16.V(0), 1.0 / beta, n, s, (int)p, st);
+            w16.h_sigma[0] = 1.0;
+          } else if (refine) {
             kern::scale((const double*)R64, w32.V(0), 1.0 / beta, N, st);  // rounds to FP32
             w32.h_sigma[0] = 1.0;
           } else if (fused) {
@@ -698,10 +759,14 @@ struct KrylovState {
           scale_v0 = false;
         }
         if (delayed) {
-          if (refine)
+          if (tiled)
+            enqueue_round(w16);
+          else if (refine)
             enqueue_round(w32);
           else
             enqueue_round(w64);
+        } else if (tiled) {
+          enqueue_step(w16);
         } else if (refine) {
           enqueue_step(w32);
         } else {
@@ -763,8 +828,13 @@ struct KrylovState {
       case STEP: {
         const double stop = refine ? std::max(o.inner_tol * beta, 0.5 * o.tol * cnorm)
                                    : o.tol * cnorm;
-        const bool end = delayed ? (refine ? complete_round(w32, stop) : complete_round(w64, stop))
-                                 : (refine ? complete_step(w32, stop) : complete_step(w64, stop));
+        bool end;
+        if (tiled)
+          end = delayed ? complete_round(w16, stop) : complete_step(w16, stop);
+        else if (refine)
+          end = delayed ? complete_round(w32, stop) : complete_step(w32, stop);
+        else
+          end = delayed ? complete_round(w64, stop) : complete_step(w64, stop);
         if (end) phase = RESTART;
         break;
       }

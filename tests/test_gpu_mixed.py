@@ -59,6 +59,28 @@ def test_refined_solve_dense(prec, n, s, p):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("basis", ["bf16", "fp32"])
+@pytest.mark.parametrize("n,s,p,method", [(40, 6, 4, "gmres"), (300, 70, 5, "gmres"),
+                                          (256, 64, 2, "gmres"), (90, 20, 3, "fom")])
+def test_bf16_refined_basis_storage(basis, n, s, p, method, monkeypatch):
+    """BF16-refined solves with the inner Krylov basis stored as tiled BF16
+    vectors (the default) and as FP32 vectors: both reach the FP64 residual
+    target and the oracle's solution within the refined bar.  The sizes
+    cover tiled padding in rows and columns, none at all (n = 256, s = 64),
+    two column tiles (s = 70) and a real-only spectrum (p = 2 has two real
+    slices)."""
+    monkeypatch.setenv("TSYLV_BF16_BASIS", basis)
+    say("bf16 refined basis", basis, n, s, p, method)
+    A, B, C = workloads.dense_shifted(n, s, p, seed=5 * n + s + p)
+    solve = getattr(ctx(), method)
+    X, info = solve(dev(A), dev(B), dev(C), refine=1, prec=tsylv.BF16, inner_m=20,
+                    inner_tol=1e-4, tol=1e-10, max_outer=300)
+    assert info.status == 0, info.as_dict()
+    assert info.relres_true <= 1e-10 and info.outer >= 1
+    assert rel(host(X), tbs.t_bartels_stewart(A, B, C)) <= 1e-7
+
+
+@pytest.mark.gpu
 def test_refined_fom_fp32():
     say("refined tFOM fp32")
     A, B, C = workloads.dense_shifted(36, 4, 4, seed=2)
