@@ -17,7 +17,8 @@ Paths timed (each: W warm-up solves, then K timed solves):
 A path counts only if every timed solve reaches true FP64 relres <= tol.
 `value` is the solves/s of the fastest valid tGMRES path; every path is
 reported.  Two further measurements ride along (skip with --no-extra):
-  tiny      the 8 x 8 x 4 dense case, unrestarted tGMRES to 1e-12: latency
+  tiny      the 8 x 8 x 4 dense case, unrestarted tGMRES to 1e-12: latency,
+            and the same instance through the t-Bartels-Stewart direct solve
   serving   open-loop Poisson arrivals of small requests of uneven (n, s, p)
             through tsylv_submit / tsylv_poll (the serving loop): p50/p99
             latency and throughput, FP64 and BF16-refined.
@@ -117,13 +118,25 @@ def tiny_latency(tsylv, workloads, reps=100):
         ok = ok and info.status == 0 and info.relres_true <= 1e-12
         if r >= 10:
             lat.append(dt)
+    # the same instance through the t-Bartels-Stewart direct solve
+    lat_d, ok_d = [], True
+    for r in range(reps + 10):
+        t0 = time.perf_counter()
+        _, info_d = ctx.tbs(Ad, Bd, Cd, X=Xd)
+        dt = time.perf_counter() - t0
+        ok_d = ok_d and info_d.status == 0 and info_d.relres_true <= 1e-12
+        if r >= 10:
+            lat_d.append(dt)
     torch.cuda.synchronize()
     ctx.close()
     return {"workload": "dense 8x8x4 (A slices N(0,1)/sqrt(8) + 4I on slice 1, B N(0,1)/sqrt(6) "
                         "- 4I), unrestarted tGMRES to relres 1e-12",
             "valid": bool(ok), "solves": reps, "steps": info.steps,
             "latency_us": {"p50": float(np.percentile(lat, 50) * 1e6),
-                           "p99": float(np.percentile(lat, 99) * 1e6)}}
+                           "p99": float(np.percentile(lat, 99) * 1e6)},
+            "tbs": {"valid": bool(ok_d), "relres_true": info_d.relres_true,
+                    "latency_us": {"p50": float(np.percentile(lat_d, 50) * 1e6),
+                                   "p99": float(np.percentile(lat_d, 99) * 1e6)}}}
 
 
 def serving(tsylv, workloads, rate, duration, npool=96, seed=50):

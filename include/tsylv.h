@@ -43,7 +43,8 @@ typedef enum {
 typedef enum {
   TSYLV_METHOD_GMRES = 0, /* tGMRES(m), Algorithm 3                        */
   TSYLV_METHOD_FOM = 1,   /* tFOM(m), Algorithm 3                          */
-  TSYLV_METHOD_TBA = 2    /* TBAS(m), Algorithm 8 (block size s)           */
+  TSYLV_METHOD_TBA = 2,   /* TBAS(m), Algorithm 8 (block size s)           */
+  TSYLV_METHOD_TBS = 3    /* t-Bartels-Stewart direct solve, Algorithm 5   */
 } tsylv_method;
 
 typedef enum {
@@ -142,12 +143,26 @@ int tsylv_tba(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A,
               const double* B, const double* C, double* X,
               const tsylv_opts* opts, tsylv_info* info);
 
+/* t-Bartels-Stewart, Algorithm 5 of section 4 (with the t-Schur
+ * decomposition of Algorithm 4): the direct method for small sizes,
+ * 1 <= n, s <= 64 (TSYLV_EINVAL otherwise).  Each Fourier slice is reduced
+ * to complex Schur form on the GPU (one wavefront per slice), the triangular
+ * equation solved by back substitution and transformed back.  Only opts->tol
+ * is read (opts may be NULL): the status is TSYLV_OK when the true relative
+ * residual, recomputed in FP64 and returned in info->relres_true, is <= tol,
+ * else TSYLV_NOT_CONVERGED with the direct solution in X;
+ * TSYLV_ESINGULAR when a slice's spectra of Ahat and Bhat meet (no unique
+ * solution), TSYLV_EBREAKDOWN when a Schur iteration does not converge. */
+int tsylv_tbs(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A,
+              const double* B, const double* C, double* X,
+              const tsylv_opts* opts, tsylv_info* info);
+
 /* Asynchronous solves (continuous batching).  A request is admitted when its
  * workspace fits in the arena; admitted requests are stepped together on the
  * GPU.  The pointers in the request must stay valid until tsylv_poll returns
  * a final status for its ticket. */
 typedef struct {
-  int method;                 /* tsylv_method (GMRES or FOM)                 */
+  int method;                 /* tsylv_method (GMRES, FOM or TBS)            */
   int64_t n, s, p;
   const double* A;            /* device pointers, layout as above           */
   const double* B;

@@ -2,6 +2,7 @@
 #include <cstring>
 #include <new>
 
+#include "kernels.hpp"
 #include "runtime.hpp"
 #include "serve.hpp"
 #include "solvers.hpp"
@@ -43,6 +44,10 @@ bool opts_ok(const tsylv_opts& o) {
   else
     ok = ok && o.prec == TSYLV_FP64;
   return ok;
+}
+
+bool tbs_dims_ok(int64_t n, int64_t s) {
+  return n >= 1 && s >= 1 && n <= kern::tbs_max_size() && s <= kern::tbs_max_size();
 }
 
 void set_device(const tsylv_ctx* ctx) { TSYLV_HIP(hipSetDevice(ctx->c.device)); }
@@ -136,7 +141,9 @@ size_t tsylv_workspace_bytes(int method, int64_t n, int64_t s, int64_t p, const 
   if (opts) o = *opts;
   if (method == -1) return apply_workspace_bytes(n, s, p);
   if (method == TSYLV_METHOD_GMRES || method == TSYLV_METHOD_FOM)
-    return krylov_workspace_bytes(n, s, p, o);
+    return krylov_workspace_bytes(method, n, s, p, o);
+  if (method == TSYLV_METHOD_TBS)
+    return tbs_dims_ok(n, s) ? krylov_workspace_bytes(method, n, s, p, o) : 0;
   if (method == TSYLV_METHOD_TBA) {
     if (n < 2 * s) return 0;
     int m = o.m;
@@ -189,6 +196,15 @@ int tsylv_gmres(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A
   return krylov_entry(TSYLV_METHOD_GMRES, ctx, n, s, p, A, B, C, X, opts, info);
 }
 
+int tsylv_tbs(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
+              const double* C, double* X, const tsylv_opts* opts, tsylv_info* info) {
+  if (!tbs_dims_ok(n, s)) return reject(info, TSYLV_EINVAL);
+  tsylv_opts o;
+  tsylv_default_opts(TSYLV_METHOD_TBS, &o);
+  if (opts) o.tol = opts->tol;  // the direct solve reads the tolerance only
+  return krylov_entry(TSYLV_METHOD_TBS, ctx, n, s, p, A, B, C, X, &o, info);
+}
+
 int tsylv_tba(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
               const double* C, double* X, const tsylv_opts* opts, tsylv_info* info) {
   if (!ctx || !A || !B || !C || !X || !dims_ok(n, s, p) || n < 2 * s)
@@ -214,7 +230,11 @@ int tsylv_submit(tsylv_ctx* ctx, const tsylv_request* req, uint64_t* ticket) {
   if (!ctx || !req || !ticket) return TSYLV_EINVAL;
   const tsylv_request& r = *req;
   if (!r.A || !r.B || !r.C || !r.X || !dims_ok(r.n, r.s, r.p)) return TSYLV_EINVAL;
-  if (r.method != TSYLV_METHOD_GMRES && r.method != TSYLV_METHOD_FOM) return TSYLV_EINVAL;
+  if (r.method != TSYLV_METHOD_GMRES && r.method != TSYLV_METHOD_FOM &&
+      r.method != TSYLV_METHOD_TBS)
+    return TSYLV_EINVAL;
+  if (r.method == TSYLV_METHOD_TBS && (!tbs_dims_ok(r.n, r.s) || r.opts.refine))
+    return TSYLV_EINVAL;
   if (!opts_ok(r.opts)) return TSYLV_EINVAL;
   if (r.opts.res_hist) return TSYLV_EINVAL;  // no host history buffers across threads
   return guarded([&]() {
@@ -264,8 +284,10 @@ const char* tsylv_strerror(int status) {
     case TSYLV_PENDING: return "pending";
     case TSYLV_EINVAL: return "invalid argument";
     case TSYLV_ENOMEM: return "arena too small";
-    case TSYLV_EBREAKDOWN: return "breakdown: non-invertible tube in Normalization";
-    case TSYLV_ESINGULAR: return "singular projected problem";
+    case TSYLV_EBREAKDOWN:
+      return "breakdown: non-invertible tube in Normalization, or a Schur iteration that did "
+             "not converge";
+    case TSYLV_ESINGULAR: return "singular (projected) problem";
     case TSYLV_EHIP: return "HIP runtime error";
     case TSYLV_ECANCELLED: return "cancelled";
     default: return "unknown status";

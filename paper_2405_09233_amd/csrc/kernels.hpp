@@ -65,6 +65,17 @@ void untile_update_bf16(const bf16t* V, int64_t ldv, int nv, const double* y, do
 void apply_bf16_tiled(const uint16_t* At, const uint16_t* Bb, const bf16t* V, bf16t* out,
                       double alpha, int64_t n, int64_t s, int p, hipStream_t st);
 
+// ---- t-Bartels-Stewart direct solve on the Fourier slices ----
+// Xhat_k from Ahat_k Xhat_k - Xhat_k Bhat_k = Chat_k for every slice of the
+// half spectrum (Ah, Bh: operator planes; Zc, Zx: vector planes), n, s <=
+// tbs_max_size().  `scratch` holds 2 tbs_scratch_complex(n, s, p) doubles;
+// *info (device int, zero on entry) is raised to 1 if a Schur iteration did
+// not converge and to 2 if a slice's triangular equation is singular.
+int tbs_max_size();
+int64_t tbs_scratch_complex(int64_t n, int64_t s, int p);
+void tbs_solve(const double* Ah, const double* Bh, const double* Zc, double* Zx, int64_t n,
+               int64_t s, int p, double* scratch, int* info, hipStream_t st);
+
 // ---- multi-vector kernels on flat vectors of N reals ----
 
 // Number of per-block partial rows used by mdot for length N.

@@ -105,7 +105,7 @@ struct Scheduler {
     std::unique_lock<std::mutex> lk(mu);
     while (!queue.empty() && !free_slots.empty()) {
       Queued q = queue.front();
-      const size_t need = krylov_workspace_bytes(q.r.n, q.r.s, q.r.p, q.r.opts);
+      const size_t need = krylov_workspace_bytes(q.r.method, q.r.n, q.r.s, q.r.p, q.r.opts);
       if (need > ctx.arena.capacity()) {  // can never fit
         queue.pop_front();
         tsylv_info inf{};

@@ -274,9 +274,13 @@ static bool bf16_basis(const tsylv_opts& o) {
   return !(f && std::strcmp(f, "fp32") == 0);
 }
 
-size_t krylov_workspace_bytes(int64_t n, int64_t s, int64_t p, const tsylv_opts& o) {
+size_t krylov_workspace_bytes(int method, int64_t n, int64_t s, int64_t p, const tsylv_opts& o) {
   const int64_t N = n * s * p;
   size_t b = setup_bytes(n, s, p);
+  if (method == TSYLV_METHOD_TBS)  // residual slot + reduction buffers, Schur scratch, flag
+    return b + CycleWS<double>::bytes(N, 1) +
+           Workspace::bytes_for(2 * kern::tbs_scratch_complex(n, s, (int)p), 8) +
+           Workspace::bytes_for(1, sizeof(int));
   if (!o.refine) return b + CycleWS<double>::bytes(N, o.m);
   b += Workspace::bytes_for(N, 8);  // FP64 residual
   if (bf16_basis(o))
@@ -298,7 +302,9 @@ size_t krylov_workspace_bytes(int64_t n, int64_t s, int64_t p, const tsylv_opts&
 // ---------------------------------------------------------------------------
 
 struct KrylovState {
-  enum Phase { SETUP, RESTART, STEP, FINAL, DONE };
+  // DIRECT: the t-Bartels-Stewart solve (method TBS) in place of the Krylov
+  // phases RESTART / STEP.
+  enum Phase { SETUP, RESTART, STEP, DIRECT, FINAL, DONE };
 
   Ctx& ctx;
   hipStream_t st;
@@ -317,6 +323,8 @@ struct KrylovState {
   bool tiled = false;  // inner basis in tiled BF16 (w16) instead of FP32 (w32)
   double* R64 = nullptr;
   RedBuf* red = nullptr;
+  double* tbs_scratch = nullptr;  // method TBS: Schur factors and products per slice
+  int* tbs_flag = nullptr;        // method TBS: 0, or 1 / 2 (Schur failure / singular)
 
   Phase phase = SETUP;
   int status = TSYLV_NOT_CONVERGED;
@@ -351,7 +359,7 @@ struct KrylovState {
               double* X_, const tsylv_opts& opts)
       : ctx(c), st(stream), prof(profile), method(meth), n(n_), s(s_), p(p_), N(n_ * s_ * p_),
         X(X_), o(opts), refine(opts.refine != 0),
-        ws(c.arena, krylov_workspace_bytes(n_, s_, p_, opts)) {
+        ws(c.arena, krylov_workspace_bytes(meth, n_, s_, p_, opts)) {
     t0 = std::chrono::steady_clock::now();
     info.status = TSYLV_PENDING;
     S = setup_fourier(ctx, st, prof, ws, n, s, p, A, B, C, X, o.x0_given != 0);
@@ -366,7 +374,12 @@ struct KrylovState {
       const char* f = std::getenv("TSYLV_KRYLOV_CGS2");  // force the three-sweep CGS2 path
       delayed = fused && !(f && f[0] == '1');
     }
-    if (!refine) {
+    if (method == TSYLV_METHOD_TBS) {
+      w64.carve(ws, N, 1, pinned);
+      red = &w64.red;
+      tbs_scratch = ws.take<double>(2 * kern::tbs_scratch_complex(n, s, (int)p));
+      tbs_flag = ws.take<int>(1);
+    } else if (!refine) {
       w64.carve(ws, N, o.m, pinned);
       red = &w64.red;
     } else if (tiled) {
@@ -725,6 +738,16 @@ struct KrylovState {
       case SETUP:
         enqueue_norm2(S.Zc);  // ||C||_F (Parseval)
         break;
+      case DIRECT: {
+        // Algorithm 5 on every Fourier slice, then R = C - M(X) in FP64.
+        TSYLV_HIP(hipMemsetAsync(tbs_flag, 0, sizeof(int), st));
+        kern::tbs_solve(S.Ah, S.Bh, S.Zc, S.Zx, n, s, (int)p, tbs_scratch, tbs_flag, st);
+        double* R = w64.V(0);
+        apply((const double*)S.Zx, R, (const double*)S.Zc, -1.0, 1.0);
+        enqueue_norm2(R);
+        TSYLV_HIP(hipMemcpyAsync(w64.h_y, tbs_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        break;
+      }
       case RESTART: {
         if (pending_update) {
           if (tiled)
@@ -796,9 +819,23 @@ struct KrylovState {
           status = TSYLV_OK;
           phase = FINAL;
         } else {
-          phase = RESTART;
+          phase = method == TSYLV_METHOD_TBS ? DIRECT : RESTART;
         }
         break;
+      case DIRECT: {
+        int flag = 0;
+        std::memcpy(&flag, w64.h_y, sizeof(int));
+        info.relres_true = std::sqrt(red->h_ww[0]) / cnorm;
+        info.relres_est = info.relres_true;
+        if (flag == 2)
+          status = TSYLV_ESINGULAR;
+        else if (flag == 1)
+          status = TSYLV_EBREAKDOWN;
+        else
+          status = info.relres_true <= o.tol ? TSYLV_OK : TSYLV_NOT_CONVERGED;
+        phase = FINAL;
+        break;
+      }
       case RESTART: {
         beta = std::sqrt(red->h_ww[0]);
         info.relres_true = beta / cnorm;

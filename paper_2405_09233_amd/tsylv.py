@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtsylv.so")
 
 FP64, FP32, BF16 = 0, 1, 2
-GMRES, FOM, TBA = 0, 1, 2
+GMRES, FOM, TBA, TBS = 0, 1, 2, 3
 APPLY = -1
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "EINVAL", -2: "ENOMEM",
@@ -84,6 +84,7 @@ _SIGS = {
 }
 _SIGS["tsylv_gmres"] = _SIGS["tsylv_fom"]
 _SIGS["tsylv_tba"] = _SIGS["tsylv_fom"]
+_SIGS["tsylv_tbs"] = _SIGS["tsylv_fom"]
 
 EXPORTED = sorted(_SIGS)
 
@@ -207,7 +208,8 @@ class Context:
     def _solve(self, fname, A, B, C, X=None, opts=None, raise_on_error=True, **kw):
         n, _, p = A.shape
         s = B.shape[0]
-        method = {"tsylv_gmres": GMRES, "tsylv_fom": FOM, "tsylv_tba": TBA}[fname]
+        method = {"tsylv_gmres": GMRES, "tsylv_fom": FOM, "tsylv_tba": TBA,
+                  "tsylv_tbs": TBS}[fname]
         o = opts if opts is not None else default_opts(method, **kw)
         if X is None:
             X = empty_device((n, s, p), A.device)
@@ -226,6 +228,9 @@ class Context:
 
     def tba(self, A, B, C, X=None, opts=None, **kw):
         return self._solve("tsylv_tba", A, B, C, X, opts, **kw)
+
+    def tbs(self, A, B, C, X=None, opts=None, **kw):
+        return self._solve("tsylv_tbs", A, B, C, X, opts, **kw)
 
     def submit(self, A, B, C, X, method=GMRES, opts=None, **kw):
         n, _, p = A.shape

@@ -89,3 +89,14 @@ def test_invalid_arguments_rejected_without_gpu():
     assert lib.tsylv_gmres(None, 4, 2, 2, None, None, None, None, None, None) == -1
     h = ctypes.c_void_p()
     assert lib.tsylv_create(ctypes.byref(h), 0, None, None, 0) == -1
+
+
+def test_tbs_workspace_bounds():
+    """tsylv_workspace_bytes of the direct solve: positive up to n, s = 64,
+    zero (invalid) past it; host-only, no GPU call."""
+    assert tsylv.workspace_bytes(tsylv.TBS, 8, 6, 4) > 0
+    assert tsylv.workspace_bytes(tsylv.TBS, 64, 64, 33) > 0
+    assert tsylv.workspace_bytes(tsylv.TBS, 65, 6, 4) == 0
+    assert tsylv.workspace_bytes(tsylv.TBS, 8, 65, 4) == 0
+    small = tsylv.workspace_bytes(tsylv.TBS, 8, 6, 4)
+    assert tsylv.workspace_bytes(tsylv.TBS, 8, 6, 8) > small
