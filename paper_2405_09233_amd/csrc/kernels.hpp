@@ -143,6 +143,15 @@ void ortho_dots2(const bf16t* V, int64_t ldv, int nv, const double* sigma, const
 void ortho_update2(const bf16t* V, int64_t ldv, int nv, const double* coef, bf16t* u, bf16t* w,
                    int64_t N, hipStream_t st);
 
+// One round of the delayed CGS2 process on the device (the arithmetic of the
+// Krylov driver's host step, for a cycle enqueued at once): consumes the
+// round's reduced sums `res`, finalises Hessenberg column j - 1 in H
+// (leading dimension ldh), and unless final_round writes sigma[j], the next
+// update coefficients `coef` and first projection `h1p`; scal = [||M
+// q_{j-1}||^2, round of a breakdown or -1].  0 <= j <= 63.
+void dcgs2_round(const double* res, int j, bool final_round, int ldh, double* H, double* h1p,
+                 double* sigma, double* coef, double* scal, hipStream_t st);
+
 // out[e] = a * x[e]  (the FP64 -> FP32 form rounds the scaled value)
 void scale(const double* x, double* out, double a, int64_t N, hipStream_t st);
 void scale(const float* x, float* out, double a, int64_t N, hipStream_t st);

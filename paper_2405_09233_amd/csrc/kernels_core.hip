@@ -694,6 +694,106 @@ __global__ __launch_bounds__(kBlock) void ortho_update2_kernel(
   }
 }
 
+// Device side of one round of the delayed CGS2 process (the arithmetic the
+// Krylov driver does on the host between rounds, done here so that a whole
+// restart cycle can be enqueued at once).  State: H (column i, entries
+// 0..i+1, at H + i ldh), h1p (first projection of the pending column),
+// sigma, scal = [||M q_{j-1}||^2, round of a breakdown or -1].  Round 0
+// consumes [q_0 . W', ||W'||^2]; round j >= 1 the 2 j + 3 sums of the
+// projection sweep (or, in the final round, the j + 1 sums [Q^T u_j,
+// ||u_j||^2]) and finalises column j - 1; unless final it writes the
+// coefficients of the next update sweep [ac (j), bc (j), alpha, gamma],
+// sigma_j and the next h1p.  After a breakdown every later round writes zero
+// coefficients (the vectors become zero, never NaN).  One block of 64
+// threads; sums in index order.
+__global__ __launch_bounds__(64) void dcgs2_round_kernel(const double* __restrict__ res, int j,
+                                                         int final_round, int ldh,
+                                                         double* __restrict__ H,
+                                                         double* __restrict__ h1p,
+                                                         double* __restrict__ sigma,
+                                                         double* __restrict__ coef,
+                                                         double* __restrict__ scal) {
+  constexpr double eps = 2.220446049250313e-16;
+  __shared__ double a[64], b[64], g[65], sh[4];
+  const int t = threadIdx.x;
+  if (j == 0) {
+    if (t == 0) {
+      h1p[0] = res[0];
+      scal[0] = res[1];
+      scal[1] = -1.0;
+      coef[0] = 0.0;
+      coef[1] = -res[0] * sigma[0];
+      coef[2] = 1.0;
+      coef[3] = 0.0;
+    }
+    return;
+  }
+  if (scal[1] >= 0.0) {  // the cycle broke down earlier: inert coefficients
+    for (int l = t; l < 2 * j + 2; l += 64) coef[l] = 0.0;
+    if (t == 0) sigma[j] = 0.0;
+    return;
+  }
+  if (t < j) {
+    a[t] = res[t];
+    b[t] = final_round ? 0.0 : res[j + t];
+  }
+  __syncthreads();
+  if (t == 0) {
+    const double d = final_round ? res[j] : res[2 * j + 1];
+    double na2 = 0.0;
+    for (int l = 0; l < j; ++l) na2 += a[l] * a[l];
+    const double nu2 = d - na2;
+    const bool breakdown = !(nu2 > 256.0 * eps * eps * scal[0]);
+    const double nu = breakdown ? 0.0 : sqrt(nu2);
+    H[j + (int64_t)ldh * (j - 1)] = nu;
+    sh[0] = nu;
+    sh[1] = breakdown ? 1.0 : 0.0;
+    if (breakdown) scal[1] = (double)j;
+  }
+  if (t < j) H[t + (int64_t)ldh * (j - 1)] = h1p[t] + a[t];
+  __syncthreads();
+  const double nu = sh[0];
+  if (final_round || sh[1] != 0.0) {
+    if (!final_round) {
+      for (int l = t; l < 2 * j + 2; l += 64) coef[l] = 0.0;
+      if (t == 0) sigma[j] = 0.0;
+    }
+    return;
+  }
+  // g = H a over the finished columns 0..j-1 (H(l, i) is zero for l > i + 1)
+  if (t <= j) {
+    double acc = 0.0;
+    for (int i = (t > 0 ? t - 1 : 0); i < j; ++i) acc += H[t + (int64_t)ldh * i] * a[i];
+    g[t] = acc;
+  }
+  __syncthreads();
+  if (t == 0) {
+    const double c = res[2 * j], e = res[2 * j + 2];
+    double ab = 0.0;
+    for (int l = 0; l < j; ++l) ab += a[l] * b[l];
+    const double qjw = (c - ab) / nu;  // q_j . W'
+    double gw = 0.0, gg = 0.0;
+    for (int l = 0; l < j; ++l) gw += g[l] * b[l];
+    gw += g[j] * qjw;
+    for (int l = 0; l <= j; ++l) gg += g[l] * g[l];
+    scal[0] = fmax(0.0, (e - 2.0 * gw + gg) / (nu * nu));
+    sh[2] = qjw;
+  }
+  __syncthreads();
+  if (t < j) {
+    const double hn = (b[t] - g[t]) / nu;
+    coef[t] = a[t] * sigma[t];
+    coef[j + t] = -(g[t] / nu + hn) * sigma[t];
+    h1p[t] = hn;
+  } else if (t == j) {
+    const double hn = (sh[2] - g[j]) / nu;
+    coef[2 * j] = 1.0 / nu;
+    coef[2 * j + 1] = -(g[j] / nu + hn) / nu;
+    h1p[j] = hn;
+    sigma[j] = 1.0 / nu;
+  }
+}
+
 inline int stream_grid(int64_t count) {
   int64_t b = (count + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
@@ -803,6 +903,14 @@ void mupdate(const float* V, int64_t ldv, int nv, const double* h, float* w, int
 void mupdate(const float* V, int64_t ldv, int nv, const double* h, double* w, int64_t N,
              hipStream_t st) {
   mupdate_any<float, double>(V, ldv, nv, h, w, N, st);
+}
+
+void dcgs2_round(const double* res, int j, bool final_round, int ldh, double* H, double* h1p,
+                 double* sigma, double* coef, double* scal, hipStream_t st) {
+  if (j < 0 || j > 63) throw Error(TSYLV_EINVAL, "dcgs2_round: round out of range");
+  hipLaunchKernelGGL(dcgs2_round_kernel, dim3(1), dim3(64), 0, st, res, j, final_round ? 1 : 0,
+                     ldh, H, h1p, sigma, coef, scal);
+  TSYLV_LAUNCH_CHECK();
 }
 
 int ortho_chunks(int64_t N) { return (int)((N + kOChunk - 1) / kOChunk); }

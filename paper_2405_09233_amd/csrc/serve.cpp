@@ -31,7 +31,9 @@ namespace tsylv {
 
 namespace {
 constexpr int kSlots = 8;
-constexpr size_t kPinnedPerSlot = 7 * (1000 + 2) + 2;  // KrylovTask::pinned_doubles, m <= 1000
+// KrylovTask::pinned_doubles for m <= 1000 (a device-driven cycle, m <= 63,
+// needs at most 7 * 65 + 2 + 65 * 64 + 2 of them)
+constexpr size_t kPinnedPerSlot = 7 * (1000 + 2) + 2;
 }  // namespace
 
 struct Scheduler {
@@ -120,6 +122,8 @@ struct Scheduler {
       lk.unlock();
       Active a{q.ticket, slot, nullptr, 0};
       try {
+        if (KrylovTask::pinned_doubles(q.r.opts) > kPinnedPerSlot)
+          throw Error(TSYLV_EINVAL, "serve: restart length too large");
         a.task.reset(new KrylovTask(ctx, streams[slot], false, pinned + slot * kPinnedPerSlot,
                                     q.r.method, q.r.n, q.r.s, q.r.p, q.r.A, q.r.B, q.r.C, q.r.X,
                                     q.r.opts));

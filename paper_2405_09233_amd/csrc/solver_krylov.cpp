@@ -91,20 +91,31 @@ struct CycleWS {
   RedBuf red;
   double *d_h1 = nullptr, *d_h2 = nullptr, *d_y = nullptr, *d_sigma = nullptr;
   double *h_h1 = nullptr, *h_h2 = nullptr, *h_y = nullptr, *h_sigma = nullptr;
+  // device-driven cycles: the Hessenberg columns (ldh = m + 2 per column),
+  // the pending first projection and [w2prev, breakdown round], with their
+  // pinned copies (H and scal side by side so one copy returns both)
+  double *d_H = nullptr, *d_h1p = nullptr, *d_scal = nullptr;
+  double *h_H = nullptr, *h_scal = nullptr;
   TV* V(int j) const { return basis + (int64_t)j * ldv; }
+  int ldh() const { return m + 2; }
+  static int64_t hess_len(int m) { return (int64_t)(m + 2) * (m + 1) + 2; }
 
   // sigma (m + 2) followed by the update coefficients of the delayed sweeps
   static int64_t coef_len(int m) { return 3 * (int64_t)(m + 2) + 2; }
-  static size_t bytes(int64_t N, int m) {
+  static size_t bytes(int64_t N, int m, bool device_cycle = false) {
     int64_t ldv = round_up(N, 64);
     int nch = kern::mdot_chunks(N);
     return Workspace::bytes_for((int64_t)(m + 1) * ldv, sizeof(TV)) +
            Workspace::bytes_for((int64_t)nch * (2 * m + 4), 8) +
            Workspace::bytes_for(3 * (m + 2), 8) + Workspace::bytes_for(m + 2, 8) +
-           Workspace::bytes_for(coef_len(m), 8);
+           Workspace::bytes_for(coef_len(m), 8) +
+           (device_cycle ? Workspace::bytes_for(hess_len(m), 8) +
+                               Workspace::bytes_for(m + 2, 8)
+                         : 0);
   }
-  // host: pinned staging of 7 (m + 2) + 2 doubles
-  void carve(Workspace& ws, int64_t N, int m_, double* host) {
+  // host: pinned staging of 7 (m + 2) + 2 doubles, plus hess_len(m) for a
+  // device-driven cycle
+  void carve(Workspace& ws, int64_t N, int m_, double* host, bool device_cycle = false) {
     m = m_;
     len = N;
     ldv = round_up(N, 64);
@@ -123,6 +134,13 @@ struct CycleWS {
     red.h_ww = host + 2 * (m + 2);
     h_y = host + 3 * (m + 2);
     h_sigma = host + 4 * (m + 2);
+    if (device_cycle) {
+      d_H = ws.take<double>(hess_len(m));
+      d_scal = d_H + (int64_t)(m + 2) * (m + 1);
+      d_h1p = ws.take<double>(m + 2);
+      h_H = host + 7 * (m + 2) + 2;
+      h_scal = h_H + (int64_t)(m + 2) * (m + 1);
+    }
   }
 };
 
@@ -274,6 +292,22 @@ static bool bf16_basis(const tsylv_opts& o) {
   return !(f && std::strcmp(f, "fp32") == 0);
 }
 
+// Delayed CGS2 (two sweeps per step) unless TSYLV_KRYLOV_CGS2=1 forces the
+// three-sweep form.
+static bool delayed_cgs2(const tsylv_opts& o) {
+  const char* f = std::getenv("TSYLV_KRYLOV_CGS2");
+  return fused_cycle(o) && !(f && f[0] == '1');
+}
+
+// Refinement's inner cycles run device-driven (every round enqueued at once,
+// the round arithmetic on the device, one synchronisation per cycle) with
+// the delayed process; TSYLV_KRYLOV_DEVICE_CYCLE=0 steps them from the host.
+static bool device_cycle(const tsylv_opts& o) {
+  if (!o.refine || !delayed_cgs2(o)) return false;
+  const char* f = std::getenv("TSYLV_KRYLOV_DEVICE_CYCLE");
+  return !(f && f[0] == '0');
+}
+
 size_t krylov_workspace_bytes(int method, int64_t n, int64_t s, int64_t p, const tsylv_opts& o) {
   const int64_t N = n * s * p;
   size_t b = setup_bytes(n, s, p);
@@ -283,11 +317,13 @@ size_t krylov_workspace_bytes(int method, int64_t n, int64_t s, int64_t p, const
            Workspace::bytes_for(1, sizeof(int));
   if (!o.refine) return b + CycleWS<double>::bytes(N, o.m);
   b += Workspace::bytes_for(N, 8);  // FP64 residual
+  const bool dc = device_cycle(o);
   if (bf16_basis(o))
-    return b + CycleWS<kern::bf16t>::bytes(kern::bf16_vtiled_elems(n, s, (int)p), o.inner_m) +
+    return b +
+           CycleWS<kern::bf16t>::bytes(kern::bf16_vtiled_elems(n, s, (int)p), o.inner_m, dc) +
            Workspace::bytes_for(kern::bf16_tiled_elems(n, (int)p), 2) +
            Workspace::bytes_for(p * s * s, 2);
-  b += CycleWS<float>::bytes(N, o.inner_m);
+  b += CycleWS<float>::bytes(N, o.inner_m, dc);
   if (o.prec == TSYLV_BF16)
     b += Workspace::bytes_for(kern::bf16_tiled_elems(n, (int)p), 2) +
          Workspace::bytes_for(p * s * s, 2) +
@@ -321,6 +357,7 @@ struct KrylovState {
   CycleWS<float> w32;
   CycleWS<kern::bf16t> w16;
   bool tiled = false;  // inner basis in tiled BF16 (w16) instead of FP32 (w32)
+  bool devcyc = false;  // inner cycles enqueued whole (enqueue_cycle / complete_cycle)
   double* R64 = nullptr;
   RedBuf* red = nullptr;
   double* tbs_scratch = nullptr;  // method TBS: Schur factors and products per slice
@@ -370,10 +407,8 @@ struct KrylovState {
     op.Bh64 = S.Bh;
     fused = fused_cycle(o);
     tiled = bf16_basis(o);
-    {
-      const char* f = std::getenv("TSYLV_KRYLOV_CGS2");  // force the three-sweep CGS2 path
-      delayed = fused && !(f && f[0] == '1');
-    }
+    delayed = delayed_cgs2(o);
+    devcyc = device_cycle(o);
     if (method == TSYLV_METHOD_TBS) {
       w64.carve(ws, N, 1, pinned);
       red = &w64.red;
@@ -385,7 +420,7 @@ struct KrylovState {
     } else if (tiled) {
       R64 = ws.take<double>(N);
       const int64_t Nt = kern::bf16_vtiled_elems(n, s, (int)p);
-      w16.carve(ws, Nt, o.inner_m, pinned);
+      w16.carve(ws, Nt, o.inner_m, pinned, devcyc);
       red = &w16.red;
       // The tiled padding (rows >= n, columns >= s) must read as zero; the
       // kernels that write basis vectors keep it so.
@@ -400,7 +435,7 @@ struct KrylovState {
       op.Bhb = Bb;
     } else {
       R64 = ws.take<double>(N);
-      w32.carve(ws, N, o.inner_m, pinned);
+      w32.carve(ws, N, o.inner_m, pinned, devcyc);
       red = &w32.red;
       op.low = o.prec == TSYLV_BF16 ? TSYLV_BF16 : TSYLV_FP32;
       if (op.low == TSYLV_BF16) {
@@ -550,6 +585,94 @@ struct KrylovState {
     }
     TSYLV_HIP(hipMemcpyAsync(w.h_h1, w.d_h1, (2 * (w.m + 2) + 1) * sizeof(double),
                              hipMemcpyDeviceToHost, st));
+  }
+
+  // A whole inner cycle of the delayed process (rounds 0..M of
+  // enqueue_round) enqueued at once: dcgs2_round does each round's
+  // arithmetic on the device, so the host synchronises once per cycle and
+  // then runs the Givens / LU step over the finished columns
+  // (complete_cycle).  The columns, the basis and the coefficients are those
+  // of the host-driven rounds; only the early exit on the estimate happens
+  // after the fact, by truncating to the first column that meets it.
+  template <typename TV>
+  void enqueue_cycle(CycleWS<TV>& w) {
+    const RedBuf& r = w.red;
+    const int64_t L = w.len;
+    const int och = kern::ortho_chunks(L);
+    const int M = o.inner_m, ldh = w.ldh();
+    double* d_coef = w.d_sigma + (w.m + 2);
+    TSYLV_HIP(hipMemcpyAsync(w.d_sigma, w.h_sigma, sizeof(double), hipMemcpyHostToDevice, st));
+    apply((const TV*)w.V(0), w.V(1), (const TV*)nullptr, w.h_sigma[0], 0.0);
+    {
+      ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
+      kern::ortho_dots((const TV*)w.basis, w.ldv, 1, w.d_sigma, (const TV*)w.V(1), L, r.part,
+                       r.ldp, st);
+      kern::reduce_partials(r.part, och, r.ldp, 2, w.d_h1, st);
+      kern::dcgs2_round(w.d_h1, 0, false, ldh, w.d_H, w.d_h1p, w.d_sigma, d_coef, w.d_scal, st);
+    }
+    for (int rr = 1; rr <= M; ++rr) {
+      const bool fin = rr == M;
+      {
+        ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
+        kern::ortho_update2((const TV*)w.basis, w.ldv, rr == 1 ? 1 : rr - 1, d_coef,
+                            rr == 1 ? (TV*)nullptr : w.V(rr - 1), w.V(rr), L, st);
+      }
+      if (!fin) apply((const TV*)w.V(rr), w.V(rr + 1), (const TV*)nullptr, 1.0, 0.0);
+      ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
+      if (fin) {
+        kern::ortho_dots((const TV*)w.basis, w.ldv, rr, w.d_sigma, (const TV*)w.V(rr), L, r.part,
+                         r.ldp, st);
+        kern::reduce_partials(r.part, och, r.ldp, rr + 1, w.d_h1, st);
+      } else {
+        kern::ortho_dots2((const TV*)w.basis, w.ldv, rr, w.d_sigma, (const TV*)w.V(rr),
+                          (const TV*)w.V(rr + 1), L, r.part, r.ldp, st);
+        kern::reduce_partials(r.part, och, r.ldp, 2 * rr + 3, w.d_h1, st);
+      }
+      kern::dcgs2_round(w.d_h1, rr, fin, ldh, w.d_H, w.d_h1p, w.d_sigma, d_coef, w.d_scal, st);
+    }
+    TSYLV_HIP(hipMemcpyAsync(w.h_H, w.d_H, CycleWS<TV>::hess_len(w.m) * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+    TSYLV_HIP(hipMemcpyAsync(w.h_sigma, w.d_sigma, (M + 1) * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+  }
+
+  template <typename TV>
+  bool complete_cycle(CycleWS<TV>& w, double stop_abs) {
+    const int M = o.inner_m, ldh = w.ldh();
+    const int broken = (int)w.h_scal[1];  // round that met h = 0, or -1
+    int J = broken >= 1 ? broken : M;     // rounds 1..J finalised columns 0..J-1
+    for (int i = 0; i < J; ++i) {
+      std::vector<double> h(w.h_H + (int64_t)ldh * i, w.h_H + (int64_t)ldh * i + i + 2);
+      info.steps++;
+      Hcols.push_back(h);
+      double est;
+      if (method == TSYLV_METHOD_GMRES) {
+        est = giv.add(h);
+      } else {
+        giv.add(h);
+        fom_ok = fom_solve(Hcols, (size_t)(i + 1), beta, y_fom);
+        est = fom_ok ? h[i + 1] * std::fabs(y_fom[i]) : INFINITY;
+      }
+      info.relres_est = est / cnorm;
+      if (o.res_hist && info.res_hist_len < o.res_hist_cap)
+        o.res_hist[info.res_hist_len++] = info.relres_est;
+      if (est <= stop_abs) {
+        J = i + 1;
+        break;
+      }
+    }
+    std::vector<double> y;
+    if (method == TSYLV_METHOD_GMRES) {
+      y = giv.solve((size_t)J);
+    } else if (fom_ok) {
+      y = y_fom;
+    } else {
+      info.fom_fallback++;
+      y = giv.solve((size_t)J);
+    }
+    for (int i = 0; i < J; ++i) w.h_y[i] = -y[i] * w.h_sigma[i];
+    pending_update = J;
+    return true;
   }
 
   // Decides whether the round after the current one is the cycle's last: by
@@ -781,7 +904,12 @@ struct KrylovState {
           }
           scale_v0 = false;
         }
-        if (delayed) {
+        if (devcyc) {
+          if (tiled)
+            enqueue_cycle(w16);
+          else
+            enqueue_cycle(w32);
+        } else if (delayed) {
           if (tiled)
             enqueue_round(w16);
           else if (refine)
@@ -866,7 +994,9 @@ struct KrylovState {
         const double stop = refine ? std::max(o.inner_tol * beta, 0.5 * o.tol * cnorm)
                                    : o.tol * cnorm;
         bool end;
-        if (tiled)
+        if (devcyc)
+          end = tiled ? complete_cycle(w16, stop) : complete_cycle(w32, stop);
+        else if (tiled)
           end = delayed ? complete_round(w16, stop) : complete_step(w16, stop);
         else if (refine)
           end = delayed ? complete_round(w32, stop) : complete_step(w32, stop);
@@ -894,7 +1024,8 @@ KrylovTask::KrylovTask(Ctx& ctx, hipStream_t st, bool profile, double* pinned, i
 KrylovTask::~KrylovTask() = default;
 
 size_t KrylovTask::pinned_doubles(const tsylv_opts& o) {
-  return 7 * (size_t)((o.refine ? o.inner_m : o.m) + 2) + 2;
+  const int m = o.refine ? o.inner_m : o.m;
+  return 7 * (size_t)(m + 2) + 2 + (device_cycle(o) ? (size_t)CycleWS<float>::hess_len(m) : 0);
 }
 
 void KrylovTask::enqueue() { s_->enqueue(); }
