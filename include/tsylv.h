@@ -196,8 +196,14 @@ typedef struct {
   double total_ms;  /* summed event-to-event time of those launches         */
 } tsylv_kstat;
 
-/* enable != 0: reset the totals and start timing; 0: stop. */
+/* enable != 0: reset the totals and start timing every family; 0: stop. */
 int tsylv_profile(tsylv_ctx* ctx, int enable);
+
+/* The same for the families whose bit (1 << tsylv_kernel_id) is set in
+ * `mask` only (0: stop): timing a family puts two event records around each
+ * of its launches on the stream, so a benchmark times the family it reports
+ * and leaves the others untimed. */
+int tsylv_profile_families(tsylv_ctx* ctx, unsigned mask);
 
 /* Synchronises the context stream and returns the totals of one family. */
 int tsylv_profile_read(tsylv_ctx* ctx, int kernel_id, tsylv_kstat* out);

@@ -262,7 +262,17 @@ int tsylv_profile(tsylv_ctx* ctx, int enable) {
   return guarded([&]() {
     std::lock_guard<std::mutex> g(ctx->c.sync_mu);
     set_device(ctx);
-    ctx->c.prof.enable(enable != 0);
+    ctx->c.prof.enable(enable != 0 ? (1u << TSYLV_K_COUNT) - 1u : 0u);
+    return (int)TSYLV_OK;
+  });
+}
+
+int tsylv_profile_families(tsylv_ctx* ctx, unsigned mask) {
+  if (!ctx || (mask >> TSYLV_K_COUNT) != 0) return TSYLV_EINVAL;
+  return guarded([&]() {
+    std::lock_guard<std::mutex> g(ctx->c.sync_mu);
+    set_device(ctx);
+    ctx->c.prof.enable(mask);
     return (int)TSYLV_OK;
   });
 }

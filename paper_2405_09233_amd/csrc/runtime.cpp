@@ -83,7 +83,8 @@ Profiler::~Profiler() {
   for (auto e : pool_) (void)hipEventDestroy(e);
 }
 
-void Profiler::enable(bool on) {
+void Profiler::enable(unsigned mask) {
+  const bool on = mask != 0;
   if (on) {
     if (pool_.empty()) {
       pool_.resize(8192);
@@ -98,7 +99,7 @@ void Profiler::enable(bool on) {
   } else {
     fold();
   }
-  on_ = on;
+  mask_ = mask;
 }
 
 void Profiler::fold() {

@@ -63,15 +63,17 @@ struct Scheduler;  // serving loop (serve.cpp)
 class Profiler {
  public:
   ~Profiler();
-  void enable(bool on);
-  bool on() const { return on_; }
+  // mask: bit k times family k (0 stops timing)
+  void enable(unsigned mask);
+  bool on() const { return mask_ != 0; }
+  bool on(int kid) const { return (mask_ >> kid) & 1u; }
   void begin(int kid, hipStream_t st);
   void end(int kid, hipStream_t st);
   void read(int kid, int64_t& launches, double& ms);
 
  private:
   void fold();  // sync on the recorded events and accumulate
-  bool on_ = false;
+  unsigned mask_ = 0;
   std::vector<hipEvent_t> pool_;
   size_t next_ = 0;
   struct Pending { int kid; hipEvent_t a, b; };
@@ -107,7 +109,7 @@ struct ProfScope {
   hipStream_t st;
   bool on;
   ProfScope(Ctx& ctx, int k, hipStream_t s, bool enabled = true)
-      : c(ctx), kid(k), st(s), on(enabled && ctx.prof.on()) {
+      : c(ctx), kid(k), st(s), on(enabled && ctx.prof.on(k)) {
     if (on) c.prof.begin(kid, st);
   }
   ~ProfScope() {

@@ -299,14 +299,18 @@ static bool delayed_cgs2(const tsylv_opts& o) {
   return fused_cycle(o) && !(f && f[0] == '1');
 }
 
-// Refinement's inner cycles run device-driven (every round enqueued at once,
-// the round arithmetic on the device, one synchronisation per cycle) with
-// the delayed process; TSYLV_KRYLOV_DEVICE_CYCLE=0 steps them from the host.
-static bool device_cycle(const tsylv_opts& o) {
-  if (!o.refine || !delayed_cgs2(o)) return false;
+// Refinement's inner cycles may run device-driven (rounds enqueued in
+// chunks, the round arithmetic on the device) with the delayed process:
+// 1 (default) after a cycle that ran all its rounds, 2 always,
+// 0 (TSYLV_KRYLOV_DEVICE_CYCLE=0) never.
+static int device_cycle_mode(const tsylv_opts& o) {
+  if (!o.refine || !delayed_cgs2(o)) return 0;
   const char* f = std::getenv("TSYLV_KRYLOV_DEVICE_CYCLE");
-  return !(f && f[0] == '0');
+  if (f && f[0] == '0') return 0;
+  if (f && f[0] == '2') return 2;
+  return 1;
 }
+static bool device_cycle(const tsylv_opts& o) { return device_cycle_mode(o) != 0; }
 
 size_t krylov_workspace_bytes(int method, int64_t n, int64_t s, int64_t p, const tsylv_opts& o) {
   const int64_t N = n * s * p;
@@ -357,7 +361,7 @@ struct KrylovState {
   CycleWS<float> w32;
   CycleWS<kern::bf16t> w16;
   bool tiled = false;  // inner basis in tiled BF16 (w16) instead of FP32 (w32)
-  bool devcyc = false;  // inner cycles enqueued whole (enqueue_cycle / complete_cycle)
+  bool devcyc = false;  // inner cycles enqueued in chunks (enqueue_chunk / complete_chunk)
   double* R64 = nullptr;
   RedBuf* red = nullptr;
   double* tbs_scratch = nullptr;  // method TBS: Schur factors and products per slice
@@ -409,6 +413,7 @@ struct KrylovState {
     tiled = bf16_basis(o);
     delayed = delayed_cgs2(o);
     devcyc = device_cycle(o);
+    dcmode = device_cycle_mode(o);
     if (method == TSYLV_METHOD_TBS) {
       w64.carve(ws, N, 1, pinned);
       red = &w64.red;
@@ -587,30 +592,45 @@ struct KrylovState {
                              hipMemcpyDeviceToHost, st));
   }
 
-  // A whole inner cycle of the delayed process (rounds 0..M of
-  // enqueue_round) enqueued at once: dcgs2_round does each round's
-  // arithmetic on the device, so the host synchronises once per cycle and
-  // then runs the Givens / LU step over the finished columns
-  // (complete_cycle).  The columns, the basis and the coefficients are those
-  // of the host-driven rounds; only the early exit on the estimate happens
-  // after the fact, by truncating to the first column that meets it.
+  // Inner cycles of the delayed process enqueued in chunks of rounds:
+  // dcgs2_round does each round's arithmetic on the device, so the host
+  // synchronises once per chunk (4, then 8, then 16 ... rounds) and runs the
+  // Givens / LU step over the columns the chunk finished (complete_chunk).
+  // The columns, the basis and the coefficients are those of the
+  // host-driven rounds; a cycle that meets its stopping test inside a chunk
+  // is truncated at that column (the same solution as stopping there), so
+  // at most one chunk of rounds is spent past the stop.
+  // A cycle runs device-driven only when the previous one of the solve ended
+  // by count: cycles that stop early on the estimate (small, easy systems)
+  // stay host-driven, which stops them at the exact step.
+  int dcmode = 0;           // device_cycle_mode of the options
+  bool last_full = false;  // the previous cycle ran all its rounds
+  bool dev_now = false;    // the current cycle is device-driven
+  int cyc_next = 0;   // next round to enqueue
+  int cyc_chunk = 4;  // rounds in the next chunk
+  int cyc_cols = 0;   // columns the host has processed
+
   template <typename TV>
-  void enqueue_cycle(CycleWS<TV>& w) {
+  void enqueue_chunk(CycleWS<TV>& w) {
     const RedBuf& r = w.red;
     const int64_t L = w.len;
     const int och = kern::ortho_chunks(L);
     const int M = o.inner_m, ldh = w.ldh();
     double* d_coef = w.d_sigma + (w.m + 2);
-    TSYLV_HIP(hipMemcpyAsync(w.d_sigma, w.h_sigma, sizeof(double), hipMemcpyHostToDevice, st));
-    apply((const TV*)w.V(0), w.V(1), (const TV*)nullptr, w.h_sigma[0], 0.0);
-    {
-      ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
-      kern::ortho_dots((const TV*)w.basis, w.ldv, 1, w.d_sigma, (const TV*)w.V(1), L, r.part,
-                       r.ldp, st);
-      kern::reduce_partials(r.part, och, r.ldp, 2, w.d_h1, st);
-      kern::dcgs2_round(w.d_h1, 0, false, ldh, w.d_H, w.d_h1p, w.d_sigma, d_coef, w.d_scal, st);
-    }
-    for (int rr = 1; rr <= M; ++rr) {
+    const int last = std::min(M, cyc_next + cyc_chunk - 1);
+    for (int rr = cyc_next; rr <= last; ++rr) {
+      if (rr == 0) {
+        TSYLV_HIP(hipMemcpyAsync(w.d_sigma, w.h_sigma, sizeof(double), hipMemcpyHostToDevice,
+                                 st));
+        apply((const TV*)w.V(0), w.V(1), (const TV*)nullptr, w.h_sigma[0], 0.0);
+        ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
+        kern::ortho_dots((const TV*)w.basis, w.ldv, 1, w.d_sigma, (const TV*)w.V(1), L, r.part,
+                         r.ldp, st);
+        kern::reduce_partials(r.part, och, r.ldp, 2, w.d_h1, st);
+        kern::dcgs2_round(w.d_h1, 0, false, ldh, w.d_H, w.d_h1p, w.d_sigma, d_coef, w.d_scal,
+                          st);
+        continue;
+      }
       const bool fin = rr == M;
       {
         ProfScope ps(ctx, TSYLV_K_ORTHO, st, prof);
@@ -630,18 +650,29 @@ struct KrylovState {
       }
       kern::dcgs2_round(w.d_h1, rr, fin, ldh, w.d_H, w.d_h1p, w.d_sigma, d_coef, w.d_scal, st);
     }
+    cyc_next = last + 1;
+    cyc_chunk *= 2;
+    // the finished columns and [w2prev, breakdown], and sigma, back to the host
     TSYLV_HIP(hipMemcpyAsync(w.h_H, w.d_H, CycleWS<TV>::hess_len(w.m) * sizeof(double),
                              hipMemcpyDeviceToHost, st));
     TSYLV_HIP(hipMemcpyAsync(w.h_sigma, w.d_sigma, (M + 1) * sizeof(double),
                              hipMemcpyDeviceToHost, st));
   }
 
+  // Returns true when the cycle ends (its correction is then pending).
   template <typename TV>
-  bool complete_cycle(CycleWS<TV>& w, double stop_abs) {
+  bool complete_chunk(CycleWS<TV>& w, double stop_abs) {
     const int M = o.inner_m, ldh = w.ldh();
-    const int broken = (int)w.h_scal[1];  // round that met h = 0, or -1
-    int J = broken >= 1 ? broken : M;     // rounds 1..J finalised columns 0..J-1
-    for (int i = 0; i < J; ++i) {
+    const int broken = (int)w.h_scal[1];         // round that met h = 0, or -1
+    int done = std::min(cyc_next - 1, M);        // rounds 1..done finished columns 0..done-1
+    bool end = cyc_next > M;
+    if (broken >= 1 && broken <= done) {
+      done = broken;
+      end = true;
+    }
+    int J = done;
+    bool est_stop = false;
+    for (int i = cyc_cols; i < done; ++i) {
       std::vector<double> h(w.h_H + (int64_t)ldh * i, w.h_H + (int64_t)ldh * i + i + 2);
       info.steps++;
       Hcols.push_back(h);
@@ -658,9 +689,15 @@ struct KrylovState {
         o.res_hist[info.res_hist_len++] = info.relres_est;
       if (est <= stop_abs) {
         J = i + 1;
+        end = true;
+        est_stop = true;
         break;
       }
     }
+    const bool early = est_stop || (broken >= 1 && broken <= std::min(cyc_next - 1, M));
+    cyc_cols = J;
+    if (!end) return false;
+    last_full = !early && J == M;
     std::vector<double> y;
     if (method == TSYLV_METHOD_GMRES) {
       y = giv.solve((size_t)J);
@@ -750,6 +787,7 @@ struct KrylovState {
     if (o.res_hist && info.res_hist_len < o.res_hist_cap)
       o.res_hist[info.res_hist_len++] = info.relres_est;
     if (breakdown || est <= stop_abs || j >= mcyc || final_round) {
+      last_full = !breakdown && !(est <= stop_abs) && j >= mcyc;
       std::vector<double> y;
       if (method == TSYLV_METHOD_GMRES) {
         y = giv.solve((size_t)j);
@@ -904,11 +942,11 @@ struct KrylovState {
           }
           scale_v0 = false;
         }
-        if (devcyc) {
+        if (dev_now) {
           if (tiled)
-            enqueue_cycle(w16);
+            enqueue_chunk(w16);
           else
-            enqueue_cycle(w32);
+            enqueue_chunk(w32);
         } else if (delayed) {
           if (tiled)
             enqueue_round(w16);
@@ -984,6 +1022,10 @@ struct KrylovState {
           j = 0;
           dj = 0;
           final_round = false;
+          cyc_next = 0;
+          cyc_chunk = 4;
+          cyc_cols = 0;
+          dev_now = dcmode == 2 || (dcmode == 1 && last_full);
           pending_scale = 0.0;
           scale_v0 = true;
           phase = STEP;
@@ -994,8 +1036,8 @@ struct KrylovState {
         const double stop = refine ? std::max(o.inner_tol * beta, 0.5 * o.tol * cnorm)
                                    : o.tol * cnorm;
         bool end;
-        if (devcyc)
-          end = tiled ? complete_cycle(w16, stop) : complete_cycle(w32, stop);
+        if (dev_now)
+          end = tiled ? complete_chunk(w16, stop) : complete_chunk(w32, stop);
         else if (tiled)
           end = delayed ? complete_round(w16, stop) : complete_step(w16, stop);
         else if (refine)

@@ -391,7 +391,7 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
       }
       // block CGS2: H_{0..j, j} = V^H W (twice), W -= V H
       const kern::PMat Vb{w.basis, ns, n, s, w.ldv};
-      if (ctx.prof.on()) ctx.prof.begin(TSYLV_K_ORTHO, st);
+      if (ctx.prof.on(TSYLV_K_ORTHO)) ctx.prof.begin(TSYLV_K_ORTHO, st);
       for (int pass = 0; pass < 2; ++pass) {
         kern::zgemm(Vb, true, kern::dense_pmat(W, ns, n), w.G, J * s, J, J, s, n, 1.0, 0.0,
                     (int)p, w.partial, st);
@@ -400,7 +400,7 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
         double* dst = pass == 0 ? hG : hG2;
         TSYLV_HIP(hipMemcpyAsync(dst, w.G, (size_t)p * J * s * 8, hipMemcpyDeviceToHost, st));
       }
-      if (ctx.prof.on()) ctx.prof.end(TSYLV_K_ORTHO, st);
+      if (ctx.prof.on(TSYLV_K_ORTHO)) ctx.prof.end(TSYLV_K_ORTHO, st);
       ctx.sync();
       const int Ji = (int)J;
       parallel_slices(ph, [&](int k) {

@@ -80,6 +80,7 @@ _SIGS = {
     "tsylv_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Info)]),
     "tsylv_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "tsylv_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "tsylv_profile_families": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint]),
     "tsylv_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
 }
 _SIGS["tsylv_gmres"] = _SIGS["tsylv_fom"]
@@ -246,8 +247,15 @@ class Context:
             raise TsylvError(st, "tsylv_submit")
         return ticket.value
 
-    def profile(self, enable=True):
-        st = load().tsylv_profile(self.handle, 1 if enable else 0)
+    def profile(self, enable=True, families=None):
+        """Start (every family, or the kernel ids in `families`) or stop timing."""
+        if families is None or not enable:
+            st = load().tsylv_profile(self.handle, 1 if enable else 0)
+        else:
+            mask = 0
+            for k in families:
+                mask |= 1 << k
+            st = load().tsylv_profile_families(self.handle, mask)
         if st != 0:
             raise TsylvError(st, "tsylv_profile")
 

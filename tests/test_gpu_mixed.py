@@ -85,15 +85,16 @@ def test_bf16_refined_basis_storage(basis, n, s, p, method, monkeypatch):
 @pytest.mark.parametrize("method", ["gmres", "fom"])
 @pytest.mark.parametrize("n,s,p,inner_m", [(120, 10, 5, 16), (6, 2, 2, 30), (40, 6, 4, 1)])
 def test_device_and_host_driven_inner_cycles_agree(prec, method, n, s, p, inner_m, monkeypatch):
-    """Refinement's inner cycles enqueued whole, with the delayed-CGS2 round
-    arithmetic on the device (the default), against the same cycles stepped
-    from the host: both reach the target and agree.  (6, 2, 2) has a Krylov
+    """Refinement's inner cycles enqueued in chunks, with the delayed-CGS2
+    round arithmetic on the device (always, and the default: after a cycle
+    that ran all its rounds), against the same cycles stepped from the host:
+    all reach the target and agree.  (6, 2, 2) has a Krylov
     space of dimension nsp = 24 < inner_m, so its cycles end on the estimate
     or on a breakdown inside the cycle; inner_m = 1 is the shortest cycle."""
     say("device vs host inner cycles", prec, method, n, s, p, inner_m)
     A, B, C = workloads.dense_shifted(n, s, p, seed=13 * n + p)
     out = {}
-    for mode in ("1", "0"):
+    for mode in ("2", "1", "0"):  # always / after a full cycle (default) / never
         monkeypatch.setenv("TSYLV_KRYLOV_DEVICE_CYCLE", mode)
         X, info = getattr(ctx(), method)(dev(A), dev(B), dev(C), refine=1, prec=prec,
                                          inner_m=inner_m, inner_tol=1e-4, tol=1e-10,
@@ -101,9 +102,10 @@ def test_device_and_host_driven_inner_cycles_agree(prec, method, n, s, p, inner_
         assert info.status == 0, (mode, info.as_dict())
         assert info.relres_true <= 1e-10
         out[mode] = (host(X), info.steps)
+    assert rel(out["2"][0], out["0"][0]) <= 1e-8
     assert rel(out["1"][0], out["0"][0]) <= 1e-8
     Xk = tbs.t_bartels_stewart(A, B, C)
-    assert rel(out["1"][0], Xk) <= 1e-7
+    assert rel(out["2"][0], Xk) <= 1e-7
 
 
 @pytest.mark.gpu
