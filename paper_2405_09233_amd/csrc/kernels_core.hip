@@ -279,6 +279,9 @@ static_assert(sizeof(OB16) == sizeof(bf16t), "OB16 is a view of bf16t");
 struct alignas(8) OB16x4 {
   OB16 e[4];
 };
+struct alignas(16) OB16x8 {
+  OB16 e[8];
+};
 
 // Keeps a loaded value in its register until here (an empty asm the
 // compiler cannot see through).
@@ -296,6 +299,10 @@ struct OVec;
 template <>
 struct OVec<OB16, 4> {
   using type = OB16x4;
+};
+template <>
+struct OVec<OB16, 8> {
+  using type = OB16x8;
 };
 template <>
 struct OVec<float, 2> {
@@ -614,82 +621,108 @@ __global__ __launch_bounds__(kBlock) void ortho_dots2_kernel(
 // coef = [ac (nv), bc (nv), alpha, gamma] (FP64):
 //   u <- v = u - sum_i ac_i V_i                       (when u is given)
 //   w <- alpha w + sum_i bc_i V_i + gamma v            (gamma only with u)
-template <typename T, int VPW, int EPL>
+// Every thread owns EL consecutive elements (one 16-byte access per vector)
+// and streams the nv basis vectors over them, eight loads in flight, summing
+// in FP64 in index order: no cross-lane sums, and each vector is read once.
+template <typename T, int EL>
 __global__ __launch_bounds__(kBlock) void ortho_update2_kernel(
     const T* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ coef,
     T* __restrict__ u, T* __restrict__ w, int64_t N) {
-  constexpr int TE = 16 * EPL;
-  const int lane = threadIdx.x & 63;
-  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int g = lane >> 4;
-  double ca[VPW], cb[VPW];
-#pragma unroll
-  for (int k = 0; k < VPW; ++k) {
-    const int i = g + kOGroups * k;
-    ca[k] = (i < nv) ? coef[i] : 0.0;
-    cb[k] = (i < nv) ? coef[nv + i] : 0.0;
-  }
+  using VT = typename OVec<T, EL>::type;
+  constexpr int UN = 8;
   const double alpha = coef[2 * nv], gamma = coef[2 * nv + 1];
   const bool has_u = u != nullptr;
-  const int64_t base = (int64_t)blockIdx.x * kOChunk;
-  const int64_t end = min(N, base + kOChunk);
-  for (int64_t t0 = base + wid * TE; t0 < end; t0 += kOWaves * TE) {
-    const int64_t off = t0 + (lane & 15) * EPL;
-    const bool full = t0 + TE <= end;
-    T v[VPW][EPL], wv[EPL], uv[EPL];
-    if (full) {
-      oload_tile<true, T, VPW, EPL>(V, ldv, nv, g, w, off, end, v);
-      oload_w<true, T, EPL>(w, off, end, wv);
-      if (has_u) oload_w<true, T, EPL>(u, off, end, uv);
-    } else {
-      oload_tile<false, T, VPW, EPL>(V, ldv, nv, g, w, off, end, v);
-      oload_w<false, T, EPL>(w, off, end, wv);
-      if (has_u) oload_w<false, T, EPL>(u, off, end, uv);
-    }
-    T vt[EPL], wt[EPL];
+  const int64_t slots = (N + EL - 1) / EL;
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < slots;
+       t += (int64_t)gridDim.x * kBlock) {
+    const int64_t off = t * EL;
+    double pa[EL], pb[EL];
 #pragma unroll
-    for (int l = 0; l < EPL; ++l) {
-      double pa = 0.0, pb = 0.0;
+    for (int l = 0; l < EL; ++l) pa[l] = pb[l] = 0.0;
+    T wv[EL], uv[EL], vt[EL], wt[EL];
+    if (off + EL <= N) {
+      int i = 0;
+      for (; i + UN <= nv; i += UN) {
+        VT x[UN];
 #pragma unroll
-      for (int k = 0; k < VPW; ++k) {
-        pa = fma(ca[k], (double)v[k][l], pa);
-        pb = fma(cb[k], (double)v[k][l], pb);
+        for (int q = 0; q < UN; ++q)
+          x[q] = *reinterpret_cast<const VT*>(V + (int64_t)(i + q) * ldv + off);
+#pragma unroll
+        for (int q = 0; q < UN; ++q) {
+          const double ca = coef[i + q], cb = coef[nv + i + q];
+          const T* xe = reinterpret_cast<const T*>(&x[q]);
+#pragma unroll
+          for (int l = 0; l < EL; ++l) {
+            pa[l] = fma(ca, (double)xe[l], pa[l]);
+            pb[l] = fma(cb, (double)xe[l], pb[l]);
+          }
+        }
       }
-      // (p0 + p1) + (p2 + p3) in every group: the same bits in all four
-      double sa = pa + __shfl_xor(pa, 16, 64);
-      sa += __shfl_xor(sa, 32, 64);
-      double sb = pb + __shfl_xor(pb, 16, 64);
-      sb += __shfl_xor(sb, 32, 64);
-      double nw = fma(alpha, (double)wv[l], sb);
+      for (; i < nv; ++i) {
+        const VT x = *reinterpret_cast<const VT*>(V + (int64_t)i * ldv + off);
+        const double ca = coef[i], cb = coef[nv + i];
+        const T* xe = reinterpret_cast<const T*>(&x);
+#pragma unroll
+        for (int l = 0; l < EL; ++l) {
+          pa[l] = fma(ca, (double)xe[l], pa[l]);
+          pb[l] = fma(cb, (double)xe[l], pb[l]);
+        }
+      }
+      const VT wx = *reinterpret_cast<const VT*>(w + off);
+      const T* we = reinterpret_cast<const T*>(&wx);
+#pragma unroll
+      for (int l = 0; l < EL; ++l) wv[l] = we[l];
       if (has_u) {
-        vt[l] = (T)((double)uv[l] - sa);
+        const VT ux = *reinterpret_cast<const VT*>(u + off);
+        const T* ue = reinterpret_cast<const T*>(&ux);
+#pragma unroll
+        for (int l = 0; l < EL; ++l) uv[l] = ue[l];
+      }
+    } else {
+      for (int i = 0; i < nv; ++i) {
+        const double ca = coef[i], cb = coef[nv + i];
+#pragma unroll
+        for (int l = 0; l < EL; ++l) {
+          const double x = off + l < N ? (double)V[(int64_t)i * ldv + off + l] : 0.0;
+          pa[l] = fma(ca, x, pa[l]);
+          pb[l] = fma(cb, x, pb[l]);
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < EL; ++l) {
+        wv[l] = off + l < N ? w[off + l] : (T)0;
+        uv[l] = (has_u && off + l < N) ? u[off + l] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < EL; ++l) {
+      double nw = fma(alpha, (double)wv[l], pb[l]);
+      if (has_u) {
+        vt[l] = (T)((double)uv[l] - pa[l]);
         nw = fma(gamma, (double)vt[l], nw);
       }
       wt[l] = (T)nw;
     }
-    if (g == 0) {
-      if (full) {
-        using VT = typename OVec<T, EPL>::type;
-        VT tw;
-        T* tp = reinterpret_cast<T*>(&tw);
+    if (off + EL <= N) {
+      VT tw;
+      T* tp = reinterpret_cast<T*>(&tw);
 #pragma unroll
-        for (int l = 0; l < EPL; ++l) tp[l] = wt[l];
-        *reinterpret_cast<VT*>(w + off) = tw;
-        if (has_u) {
-          VT tv;
-          T* tq = reinterpret_cast<T*>(&tv);
+      for (int l = 0; l < EL; ++l) tp[l] = wt[l];
+      *reinterpret_cast<VT*>(w + off) = tw;
+      if (has_u) {
+        VT tv;
+        T* tq = reinterpret_cast<T*>(&tv);
 #pragma unroll
-          for (int l = 0; l < EPL; ++l) tq[l] = vt[l];
-          *reinterpret_cast<VT*>(u + off) = tv;
-        }
-      } else {
-#pragma unroll
-        for (int l = 0; l < EPL; ++l)
-          if (off + l < end) {
-            w[off + l] = wt[l];
-            if (has_u) u[off + l] = vt[l];
-          }
+        for (int l = 0; l < EL; ++l) tq[l] = vt[l];
+        *reinterpret_cast<VT*>(u + off) = tv;
       }
+    } else {
+#pragma unroll
+      for (int l = 0; l < EL; ++l)
+        if (off + l < N) {
+          w[off + l] = wt[l];
+          if (has_u) u[off + l] = vt[l];
+        }
     }
   }
 }
@@ -1045,19 +1078,14 @@ static void ortho_update2_any(const T* V, int64_t ldv, int nv, const double* coe
                               int64_t N, hipStream_t st) {
   if (nv < 1) throw Error(TSYLV_EINVAL, "ortho: bad vector count");
   if (N <= 0) return;
-  ortho_check(V, ldv, (const T*)w);
-  if (u) ortho_check(V, ldv, (const T*)u);
-  const dim3 grid(ortho_chunks(N)), block(kBlock);
-  constexpr int EPL = ortho_epl<T>();
-  switch (ortho_vpw(nv)) {
-#define F(K)                                                                                    \
-  case K:                                                                                       \
-    hipLaunchKernelGGL((ortho_update2_kernel<T, K, EPL>), grid, block, 0, st, V, ldv, nv, coef, \
-                       u, w, N);                                                                \
-    break;
-    TSYLV_OVPW_CASES(F)
-#undef F
-  }
+  constexpr int EL = 16 / (int)sizeof(T);  // one 16-byte access per vector and thread
+  if ((reinterpret_cast<uintptr_t>(V) | reinterpret_cast<uintptr_t>(w) |
+       reinterpret_cast<uintptr_t>(u)) % 16 != 0 || ldv % EL != 0)
+    throw Error(TSYLV_EINVAL, "ortho: basis not aligned");
+  const int64_t slots = (N + EL - 1) / EL;
+  const int blocks = (int)std::min<int64_t>((slots + kBlock - 1) / kBlock, 16384);
+  hipLaunchKernelGGL((ortho_update2_kernel<T, EL>), dim3(blocks), dim3(kBlock), 0, st, V, ldv, nv,
+                     coef, u, w, N);
   TSYLV_LAUNCH_CHECK();
 }
 
