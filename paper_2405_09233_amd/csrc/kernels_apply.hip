@@ -20,6 +20,8 @@
 // slice major and handed out so that each XCD (workgroups go round-robin over
 // the 8 XCDs) works through a contiguous range: the V_k of a slice stays in
 // one XCD's L2 instead of being fetched by all eight.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace tsylv {
@@ -334,6 +336,8 @@ void dispatch(ApplyArgs<Tag> a, hipStream_t st) {
     launch_apply<Tag, 128, 16, 2, 1>(a, st);
   else if (a.s <= 32)
     launch_apply<Tag, 64, 32, 1, 2>(a, st);
+  else if (std::is_same<Tag, float>::value)
+    launch_apply<Tag, 64, 64, 1, 4>(a, st);  // FP32: 5 % faster at n = 4096, s = 64
   else
     launch_apply<Tag, 32, 64, 1, 2>(a, st);
 }
