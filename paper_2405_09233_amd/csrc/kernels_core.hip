@@ -747,7 +747,10 @@ __global__ __launch_bounds__(64) void dcgs2_round_kernel(const double* __restric
                                                          double* __restrict__ coef,
                                                          double* __restrict__ scal) {
   constexpr double eps = 2.220446049250313e-16;
-  __shared__ double a[64], b[64], g[65], sh[4];
+  // everything the round reads is staged in LDS first (one parallel load),
+  // so the sequential part runs on LDS latencies
+  __shared__ double Hs[64][65];  // Hs[i][l] = H(l, i), the finished columns i < j
+  __shared__ double a[64], b[64], g[65], hp[65], sg[64], sh[8];
   const int t = threadIdx.x;
   if (j == 0) {
     if (t == 0) {
@@ -769,24 +772,40 @@ __global__ __launch_bounds__(64) void dcgs2_round_kernel(const double* __restric
   if (t < j) {
     a[t] = res[t];
     b[t] = final_round ? 0.0 : res[j + t];
+    hp[t] = h1p[t];
+    sg[t] = sigma[t];
   }
+  if (t == 0) {
+    sh[0] = final_round ? res[j] : res[2 * j + 1];  // d
+    sh[1] = final_round ? 0.0 : res[2 * j];         // c
+    sh[2] = final_round ? 0.0 : res[2 * j + 2];     // e
+    sh[3] = scal[0];                                // w2prev
+  }
+  // columns 0..j-2 of H (rows 0..i+1 of column i), eight loads in flight
+#pragma unroll 8
+  for (int i = 0; i < 62; ++i)
+    if (i + 1 < j && t <= i + 1) Hs[i][t] = H[t + (int64_t)ldh * i];
   __syncthreads();
   if (t == 0) {
-    const double d = final_round ? res[j] : res[2 * j + 1];
     double na2 = 0.0;
     for (int l = 0; l < j; ++l) na2 += a[l] * a[l];
-    const double nu2 = d - na2;
-    const bool breakdown = !(nu2 > 256.0 * eps * eps * scal[0]);
+    const double nu2 = sh[0] - na2;
+    const bool breakdown = !(nu2 > 256.0 * eps * eps * sh[3]);
     const double nu = breakdown ? 0.0 : sqrt(nu2);
     H[j + (int64_t)ldh * (j - 1)] = nu;
-    sh[0] = nu;
-    sh[1] = breakdown ? 1.0 : 0.0;
+    Hs[j - 1][j] = nu;
+    sh[4] = nu;
+    sh[5] = breakdown ? 1.0 : 0.0;
     if (breakdown) scal[1] = (double)j;
   }
-  if (t < j) H[t + (int64_t)ldh * (j - 1)] = h1p[t] + a[t];
+  if (t < j) {
+    const double hv = hp[t] + a[t];
+    H[t + (int64_t)ldh * (j - 1)] = hv;
+    Hs[j - 1][t] = hv;
+  }
   __syncthreads();
-  const double nu = sh[0];
-  if (final_round || sh[1] != 0.0) {
+  const double nu = sh[4];
+  if (final_round || sh[5] != 0.0) {
     if (!final_round) {
       for (int l = t; l < 2 * j + 2; l += 64) coef[l] = 0.0;
       if (t == 0) sigma[j] = 0.0;
@@ -796,30 +815,29 @@ __global__ __launch_bounds__(64) void dcgs2_round_kernel(const double* __restric
   // g = H a over the finished columns 0..j-1 (H(l, i) is zero for l > i + 1)
   if (t <= j) {
     double acc = 0.0;
-    for (int i = (t > 0 ? t - 1 : 0); i < j; ++i) acc += H[t + (int64_t)ldh * i] * a[i];
+    for (int i = (t > 0 ? t - 1 : 0); i < j; ++i) acc += Hs[i][t] * a[i];
     g[t] = acc;
   }
   __syncthreads();
   if (t == 0) {
-    const double c = res[2 * j], e = res[2 * j + 2];
     double ab = 0.0;
     for (int l = 0; l < j; ++l) ab += a[l] * b[l];
-    const double qjw = (c - ab) / nu;  // q_j . W'
+    const double qjw = (sh[1] - ab) / nu;  // q_j . W'
     double gw = 0.0, gg = 0.0;
     for (int l = 0; l < j; ++l) gw += g[l] * b[l];
     gw += g[j] * qjw;
     for (int l = 0; l <= j; ++l) gg += g[l] * g[l];
-    scal[0] = fmax(0.0, (e - 2.0 * gw + gg) / (nu * nu));
-    sh[2] = qjw;
+    scal[0] = fmax(0.0, (sh[2] - 2.0 * gw + gg) / (nu * nu));
+    sh[6] = qjw;
   }
   __syncthreads();
   if (t < j) {
     const double hn = (b[t] - g[t]) / nu;
-    coef[t] = a[t] * sigma[t];
-    coef[j + t] = -(g[t] / nu + hn) * sigma[t];
+    coef[t] = a[t] * sg[t];
+    coef[j + t] = -(g[t] / nu + hn) * sg[t];
     h1p[t] = hn;
   } else if (t == j) {
-    const double hn = (sh[2] - g[j]) / nu;
+    const double hn = (sh[6] - g[j]) / nu;
     coef[2 * j] = 1.0 / nu;
     coef[2 * j + 1] = -(g[j] / nu + hn) / nu;
     h1p[j] = hn;
