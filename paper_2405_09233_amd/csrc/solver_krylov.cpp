@@ -342,9 +342,8 @@ size_t krylov_workspace_bytes(int method, int64_t n, int64_t s, int64_t p, const
 // ---------------------------------------------------------------------------
 
 struct KrylovState {
-  // DIRECT: the t-Bartels-Stewart solve (method TBS) in place of the Krylov
-  // phases RESTART / STEP.
-  enum Phase { SETUP, RESTART, STEP, DIRECT, FINAL, DONE };
+  // (method TBS completes in its SETUP phase: enqueue_direct)
+  enum Phase { SETUP, RESTART, STEP, FINAL, DONE };
 
   Ctx& ctx;
   hipStream_t st;
@@ -894,21 +893,51 @@ struct KrylovState {
     pending_update = 0;
   }
 
+  // Method TBS in one pass (one synchronisation): ||C||, Algorithm 5 on
+  // every Fourier slice, R = C - M(X) and ||R|| in FP64, the inverse DFT of
+  // X; the two norms and the flag come back together.
+  void enqueue_direct() {
+    const RedBuf& r = w64.red;
+    const int nch = kern::mdot_chunks(N);
+    kern::mdot_partial((const double*)nullptr, 0, 0, S.Zc, N, r.part, r.ldp, 1, st);
+    kern::reduce_partials(r.part, nch, r.ldp, 1, w64.d_h1, st);
+    TSYLV_HIP(hipMemsetAsync(tbs_flag, 0, sizeof(int), st));
+    kern::tbs_solve(S.Ah, S.Bh, S.Zc, S.Zx, n, s, (int)p, tbs_scratch, tbs_flag, st);
+    double* R = w64.V(0);
+    apply((const double*)S.Zx, R, (const double*)S.Zc, -1.0, 1.0);
+    kern::mdot_partial((const double*)nullptr, 0, 0, R, N, r.part, r.ldp, 1, st);
+    kern::reduce_partials(r.part, nch, r.ldp, 1, w64.d_h1 + 1, st);
+    {
+      ProfScope ps(ctx, TSYLV_K_XFORM, st, prof);
+      kern::tube_xform_f64(S.Zx, X, S.xf_inv, n * s, (int)p, st);
+    }
+    TSYLV_HIP(hipMemcpyAsync(w64.h_h1, w64.d_h1, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    TSYLV_HIP(hipMemcpyAsync(w64.h_y, tbs_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  }
+
+  void complete_direct() {
+    int flag = 0;
+    std::memcpy(&flag, w64.h_y, sizeof(int));
+    cnorm = std::sqrt(w64.h_h1[0]);
+    info.relres_true = cnorm > 0.0 ? std::sqrt(w64.h_h1[1]) / cnorm : 0.0;
+    info.relres_est = info.relres_true;
+    if (flag == 2)
+      status = TSYLV_ESINGULAR;
+    else if (flag == 1)
+      status = TSYLV_EBREAKDOWN;
+    else
+      status = info.relres_true <= o.tol ? TSYLV_OK : TSYLV_NOT_CONVERGED;
+  }
+
   void enqueue() {
     switch (phase) {
       case SETUP:
+        if (method == TSYLV_METHOD_TBS) {
+          enqueue_direct();
+          break;
+        }
         enqueue_norm2(S.Zc);  // ||C||_F (Parseval)
         break;
-      case DIRECT: {
-        // Algorithm 5 on every Fourier slice, then R = C - M(X) in FP64.
-        TSYLV_HIP(hipMemsetAsync(tbs_flag, 0, sizeof(int), st));
-        kern::tbs_solve(S.Ah, S.Bh, S.Zc, S.Zx, n, s, (int)p, tbs_scratch, tbs_flag, st);
-        double* R = w64.V(0);
-        apply((const double*)S.Zx, R, (const double*)S.Zc, -1.0, 1.0);
-        enqueue_norm2(R);
-        TSYLV_HIP(hipMemcpyAsync(w64.h_y, tbs_flag, sizeof(int), hipMemcpyDeviceToHost, st));
-        break;
-      }
       case RESTART: {
         if (pending_update) {
           if (tiled)
@@ -979,29 +1008,23 @@ struct KrylovState {
   void complete() {
     switch (phase) {
       case SETUP:
+        if (method == TSYLV_METHOD_TBS) {
+          complete_direct();
+          phase = DONE;
+          info.status = status;
+          info.seconds = seconds_since(t0);
+          break;
+        }
         cnorm = std::sqrt(red->h_ww[0]);
         if (cnorm == 0.0) {
           info.relres_true = 0.0;
           status = TSYLV_OK;
           phase = FINAL;
         } else {
-          phase = method == TSYLV_METHOD_TBS ? DIRECT : RESTART;
+          phase = RESTART;
         }
         break;
-      case DIRECT: {
-        int flag = 0;
-        std::memcpy(&flag, w64.h_y, sizeof(int));
-        info.relres_true = std::sqrt(red->h_ww[0]) / cnorm;
-        info.relres_est = info.relres_true;
-        if (flag == 2)
-          status = TSYLV_ESINGULAR;
-        else if (flag == 1)
-          status = TSYLV_EBREAKDOWN;
-        else
-          status = info.relres_true <= o.tol ? TSYLV_OK : TSYLV_NOT_CONVERGED;
-        phase = FINAL;
-        break;
-      }
+
       case RESTART: {
         beta = std::sqrt(red->h_ww[0]);
         info.relres_true = beta / cnorm;
