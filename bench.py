@@ -139,6 +139,70 @@ def tiny_latency(tsylv, workloads, reps=100):
                                    "p99": float(np.percentile(lat_d, 99) * 1e6)}}}
 
 
+def _open_loop(tsylv, ctx, pool, o, rate, duration, rng):
+    """Poisson arrivals (exponential gaps, `rate` per second, for `duration`
+    seconds) over a pool of (A, B, C, X, ...) instances; an instance still in
+    flight is not resubmitted.  Latency runs from the scheduled arrival to the
+    completion seen by poll.  Returns (latencies in s, failures, span in s)."""
+    npool = len(pool)
+    gaps = rng.exponential(1.0 / rate, size=int(rate * duration * 2) + 16)
+    arrivals = np.cumsum(gaps)
+    arrivals = arrivals[arrivals < duration]
+    busy = [False] * npool
+    inflight = {}  # ticket -> (pool index, arrival time)
+    lat, bad, nxt = [], 0, 0
+    t0 = time.perf_counter()
+    i = 0
+    while i < len(arrivals) or inflight:
+        now = time.perf_counter() - t0
+        while i < len(arrivals) and arrivals[i] <= now:
+            for _ in range(npool):
+                nxt = (nxt + 1) % npool
+                if not busy[nxt]:
+                    break
+            else:
+                break  # every instance in flight: try again on the next pass
+            Ad, Bd, Cd, Xd = pool[nxt][:4]
+            busy[nxt] = True
+            inflight[ctx.submit(Ad, Bd, Cd, Xd, method=tsylv.GMRES, opts=o)] = (nxt, arrivals[i])
+            i += 1
+        for t in list(inflight):
+            st, info = ctx.poll(t)
+            if st != 2:
+                k, ta = inflight.pop(t)
+                busy[k] = False
+                lat.append(time.perf_counter() - t0 - ta)
+                if st != 0 or info.relres_true > 1e-8:
+                    bad += 1
+        time.sleep(0.0002)
+    return np.array(lat), bad, time.perf_counter() - t0
+
+
+def _batch(tsylv, ctx, pool, o):
+    """Every instance of the pool submitted at once; the serving loop drains
+    them.  Returns (solves/s = len(pool) / time to the last completion,
+    failures, completion times in s).  A fixed batch weighs every size of the
+    mix once, where a closed loop would count the small requests over and
+    over."""
+    t0 = time.perf_counter()
+    pending = {}
+    for k, inst in enumerate(pool):
+        Ad, Bd, Cd, Xd = inst[:4]
+        pending[ctx.submit(Ad, Bd, Cd, Xd, method=tsylv.GMRES, opts=o)] = k
+    done, bad = [], 0
+    while pending:
+        for t in list(pending):
+            st, info = ctx.poll(t)
+            if st != 2:
+                pending.pop(t)
+                done.append(time.perf_counter() - t0)
+                if st != 0 or info.relres_true > 1e-8:
+                    bad += 1
+        time.sleep(0.0002)
+    span = time.perf_counter() - t0
+    return len(pool) / span, bad, np.array(done)
+
+
 def serving(tsylv, workloads, rate, duration, npool=96, seed=50):
     """Open-loop serving run: requests of uneven size arrive as a Poisson
     process (exponential gaps, `rate` per second, for `duration` seconds) and
@@ -146,7 +210,9 @@ def serving(tsylv, workloads, rate, duration, npool=96, seed=50):
     the workload set scaled to one GPU for a short run: n log-uniform in
     [128, 1024], s log-uniform in [8, 64], p uniform in {4..16}, dense
     p-scaled-noise instances (a pool of `npool`, reused when idle), tol 1e-8.
-    Latency runs from the scheduled arrival to the completion seen by poll."""
+    Latency runs from the scheduled arrival to the completion seen by poll.
+    Then the batch throughput: the whole pool submitted at once and drained
+    -- where batched mixed precision has to beat per-instance FP64."""
     import torch
     rng = np.random.default_rng(seed)
     pool = []
@@ -166,49 +232,90 @@ def serving(tsylv, workloads, rate, duration, npool=96, seed=50):
     }
     out = {"recipe": "n log-uniform [128, 1024], s log-uniform [8, 64], p uniform {4..16}, "
                      "dense instances with p-scaled noise, Poisson arrivals %.0f/s for %.0f s, "
-                     "tol 1e-8, at most 8 solves on the GPU at once" % (rate, duration)}
+                     "tol 1e-8, at most 8 solves on the GPU at once; batch: the pool of %d "
+                     "submitted at once" % (rate, duration, npool)}
     for name, o in opts.items():
         ctx = tsylv.Context(16 << 30, device=0)
-        gaps = rng.exponential(1.0 / rate, size=int(rate * duration * 2) + 16)
-        arrivals = np.cumsum(gaps)
-        arrivals = arrivals[arrivals < duration]
-        busy = [False] * npool
-        inflight = {}  # ticket -> (pool index, arrival time)
-        lat, bad, nxt = [], 0, 0
-        t0 = time.perf_counter()
-        i = 0
-        while i < len(arrivals) or inflight:
-            now = time.perf_counter() - t0
-            while i < len(arrivals) and arrivals[i] <= now:
-                for _ in range(npool):
-                    nxt = (nxt + 1) % npool
-                    if not busy[nxt]:
-                        break
-                else:
-                    break  # every instance in flight: try again on the next pass
-                Ad, Bd, Cd, Xd, _ = pool[nxt]
-                busy[nxt] = True
-                inflight[ctx.submit(Ad, Bd, Cd, Xd, method=tsylv.GMRES, opts=o)] = (nxt, arrivals[i])
-                i += 1
-            for t in list(inflight):
-                st, info = ctx.poll(t)
-                if st != 2:
-                    k, ta = inflight.pop(t)
-                    busy[k] = False
-                    lat.append(time.perf_counter() - t0 - ta)
-                    if st != 0 or info.relres_true > 1e-8:
-                        bad += 1
-            time.sleep(0.0002)
-        span = time.perf_counter() - t0
+        lat, bad, span = _open_loop(tsylv, ctx, pool, o, rate, duration, rng)
         ctx.close()
-        lat = np.array(lat)
+        ctx = tsylv.Context(16 << 30, device=0)
+        cap, bad_cap, _ = _batch(tsylv, ctx, pool, o)
+        ctx.close()
         out[name] = {"requests": int(len(lat)), "failed": int(bad),
+                     "throughput_per_s": float(len(lat) / span),
+                     "batch_solves_per_s": float(cap),
+                     "batch_failed": int(bad_cap),
+                     "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                                    "p99": float(np.percentile(lat, 99) * 1e3),
+                                    "mean": float(lat.mean() * 1e3)}}
+        log("serving %s: %d requests, p50 %.1f ms, p99 %.1f ms; batch of %d: %.0f solves/s" % (
+            name, len(lat), out[name]["latency_ms"]["p50"], out[name]["latency_ms"]["p99"],
+            npool, cap))
+    return out
+
+
+def serving_full(tsylv, rate=40.0, duration=10.0, npool=128, seed=51):
+    """Serving at the recipe's full sizes: n log-uniform in [128, 4096], s
+    log-uniform in [8, 256], p uniform in {4..64}, dense instances with
+    p-scaled noise (A slices N(0,1) 2/sqrt(n p) + 4 I on slice 1, B slices
+    N(0,1) 2/sqrt(s p) - 4 I, C N(0,1)), generated on the device by torch's
+    seeded normal generator; tol 1e-8, at most 8 solves on the GPU at once in
+    a 96 GB arena.  Batch throughput (the pool of `npool` submitted at once)
+    and an open-loop Poisson run at `rate` per second for `duration` s."""
+    import torch
+    rng = np.random.default_rng(seed)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(seed)
+
+    def tensor(rows, cols, p, scale, shift):
+        base = torch.randn((p, cols, rows), generator=gen, device="cuda:0",
+                           dtype=torch.float64) * scale
+        if shift:
+            base[0] += shift * torch.eye(rows, device="cuda:0", dtype=torch.float64)
+        return base.permute(2, 1, 0)  # (rows, cols, p), frontal-slice-major memory
+
+    pool, sizes = [], []
+    for i in range(npool):
+        n = int(round(np.exp(rng.uniform(np.log(128), np.log(4096)))))
+        s = int(round(np.exp(rng.uniform(np.log(8), np.log(256)))))
+        p = int(rng.integers(4, 65))
+        A = tensor(n, n, p, 2.0 / np.sqrt(n * p), 4.0)
+        B = tensor(s, s, p, 2.0 / np.sqrt(s * p), -4.0)
+        C = tensor(n, s, p, 1.0, 0.0)
+        X = torch.empty((p, s, n), device="cuda:0", dtype=torch.float64).permute(2, 1, 0)
+        pool.append((A, B, C, X))
+        sizes.append(n * n * p * 8)
+    torch.cuda.synchronize()
+    opts = {
+        "fp64": tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-8, max_cycles=2000),
+        "bf16": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.BF16, inner_m=24,
+                                   inner_tol=1e-4, tol=1e-8, max_outer=300),
+    }
+    out = {"recipe": "n log-uniform [128, 4096], s log-uniform [8, 256], p uniform {4..64}, "
+                     "dense p-scaled-noise instances generated on the device (pool of %d, "
+                     "mean A %.2f GB, largest %.1f GB), tol 1e-8, at most 8 solves on the GPU "
+                     "at once, 96 GB arena; batch: the pool submitted at once; open loop: "
+                     "Poisson arrivals %.0f/s for %.0f s" %
+                     (npool, float(np.mean(sizes)) / 1e9, max(sizes) / 1e9, rate, duration)}
+    for name, o in opts.items():
+        ctx = tsylv.Context(96 << 30, device=0)
+        rate_b, bad_b, done = _batch(tsylv, ctx, pool, o)
+        lat, bad, span = _open_loop(tsylv, ctx, pool, o, rate, duration, rng)
+        ctx.close()
+        out[name] = {"batch_solves_per_s": float(rate_b), "batch_failed": int(bad_b),
+                     "batch_completion_s": {"p50": float(np.percentile(done, 50)),
+                                            "max": float(done.max())},
+                     "requests": int(len(lat)), "failed": int(bad),
                      "throughput_per_s": float(len(lat) / span),
                      "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                                     "p99": float(np.percentile(lat, 99) * 1e3),
                                     "mean": float(lat.mean() * 1e3)}}
-        log("serving %s: %d requests, p50 %.1f ms, p99 %.1f ms" % (
-            name, len(lat), out[name]["latency_ms"]["p50"], out[name]["latency_ms"]["p99"]))
+        log("serving (full sizes) %s: batch of %d: %.1f solves/s; Poisson %.0f/s: %d requests, "
+            "p50 %.1f ms, p99 %.1f ms; failed %d + %d" % (
+                name, npool, rate_b, rate, len(lat), out[name]["latency_ms"]["p50"],
+                out[name]["latency_ms"]["p99"], bad_b, bad))
+    out["bf16_vs_fp64_batch"] = (out["bf16"]["batch_solves_per_s"]
+                                 / max(out["fp64"]["batch_solves_per_s"], 1e-30))
     return out
 
 
@@ -303,6 +410,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the tiny and serving runs")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--no-serve-full", action="store_true",
+                    help="skip the batch at the full serving sizes")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving measurements")
     ap.add_argument("--grid", type=int, nargs=2, default=[64, 64])
     ap.add_argument("--s", type=int, default=64)
     ap.add_argument("--p", type=int, default=32)
@@ -329,6 +440,13 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 x %d MiB" % args.copy_calib_mib)
         del src, dst
+
+    if args.serve_only:
+        out = {"serving": serving(tsylv, workloads, args.serve_rate, args.serve_seconds)}
+        if not args.no_serve_full:
+            out["serving"]["full_sizes"] = serving_full(tsylv)
+        print(json.dumps(out), flush=True)
+        return
 
     nx, ny = args.grid
     t0 = time.perf_counter()
@@ -425,6 +543,9 @@ def main():
         out["tiny"] = tiny_latency(tsylv, workloads)
         log("serving run ...")
         out["serving"] = serving(tsylv, workloads, args.serve_rate, args.serve_seconds)
+        if not args.no_serve_full:
+            log("serving at full sizes ...")
+            out["serving"]["full_sizes"] = serving_full(tsylv)
     if not args.no_cpu:
         log("timing the oracle sample on the host ...")
         fp = res.get("fp64", r)

@@ -2,14 +2,15 @@
 // tGMRES / tFOM solves (project addition, not in the paper).
 //
 // A scheduler thread owns up to kSlots active solves, each a KrylovTask on its
-// own HIP stream (default priority).  Every round it
-//   1. admits queued requests in FIFO order while a slot is free and the
+// own HIP stream (default priority).  It loops:
+//   1. admit queued requests in FIFO order while a slot is free and the
 //      request's workspace fits in the arena (the HBM budget);
-//   2. enqueues the next phase of every active solve -- their kernels run
-//      concurrently on the device;
-//   3. synchronises each solve's stream and runs its host step (Givens, LU,
-//      restart test), retiring finished solves and freeing their slot and
-//      workspace.
+//   2. for every active solve: if no phase is in flight, enqueue its next
+//      phase; if its stream has finished the phase (hipStreamQuery), run the
+//      host step (Givens, LU, restart test) and enqueue the next phase at
+//      once -- each solve advances at its own pace, not in lock step with
+//      the slowest;
+//   3. retire finished solves, freeing their slot and workspace.
 // A request therefore joins while others are mid-solve and its work overlaps
 // theirs.  Each solve runs exactly the kernels and host arithmetic of a
 // synchronous call (the same KrylovTask; reductions are fixed-order), so its
@@ -61,6 +62,7 @@ struct Scheduler {
     int slot;
     std::unique_ptr<KrylovTask> task;
     int error = 0;
+    bool in_flight = false;  // a phase is enqueued and not yet completed
   };
   std::vector<Active> active;
   std::vector<int> free_slots;
@@ -155,27 +157,30 @@ struct Scheduler {
           continue;
         }
       }
+      bool progressed = false;
       for (auto& a : active) {
         if (a.error || !a.task) continue;
         try {
-          a.task->enqueue();
+          if (a.in_flight) {
+            const hipError_t q = hipStreamQuery(a.task->stream());
+            if (q == hipErrorNotReady) continue;
+            TSYLV_HIP(q);
+            a.in_flight = false;
+            a.task->complete();
+            progressed = true;
+          }
+          if (!a.task->done()) {
+            a.task->enqueue();
+            a.in_flight = true;
+            progressed = true;
+          }
         } catch (const Error& e) {
           a.error = e.status;
         } catch (...) {
           a.error = TSYLV_EHIP;
         }
       }
-      for (auto& a : active) {
-        if (a.error || !a.task) continue;
-        try {
-          TSYLV_HIP(hipStreamSynchronize(a.task->stream()));
-          a.task->complete();
-        } catch (const Error& e) {
-          a.error = e.status;
-        } catch (...) {
-          a.error = TSYLV_EHIP;
-        }
-      }
+      if (!progressed) std::this_thread::yield();
       // retire finished and failed solves; their workspace returns to the arena
       for (size_t i = 0; i < active.size();) {
         Active& a = active[i];
