@@ -157,10 +157,32 @@ int tsylv_tbs(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A,
               const double* B, const double* C, double* X,
               const tsylv_opts* opts, tsylv_info* info);
 
+/* Synthetic instances drawn on the device (a project addition for serving
+ * workloads; not in the paper).  Writes the dense instance of `seed`:
+ *   A = 2/sqrt(n p) Z_A + 4 I,  B = 2/sqrt(s p) Z_B - 4 I  (the identity on
+ *   frontal slice 1 only),  C = Z_C,
+ * with Z i.i.d. N(0,1) from a counter-based stream: Philox4x64-10 (Salmon
+ * et al., SC'11) keyed by (seed, tensor id: A 0, B 1, C 2); element (i,j,k)
+ * of a rows x cols x p tensor, e = i + rows*j, takes the block at counter
+ * (e, k/4, 0, 0); its words w give uniforms ((w >> 12) + 1/2) 2^-52 and
+ * Box-Muller pairs (cos, sin) for k%4 = 0,1 from words 0,1 and k%4 = 2,3
+ * from words 2,3.  The product with the scale is rounded, then the shift
+ * added.  The noise scaling keeps the spectra of the Fourier slices of A and
+ * B about 4 apart for every p, so the equation is uniquely solvable.
+ * A (n x n x p), B (s x s x p), C (n x s x p): device pointers in the layout
+ * above, any of them NULL to skip it.  Runs on the context stream and returns
+ * after completion.  Values agree with a host evaluation of the same
+ * definition to the rounding of log, sin and cos. */
+int tsylv_generate(tsylv_ctx* ctx, uint64_t seed, int64_t n, int64_t s, int64_t p, double* A,
+                   double* B, double* C);
+
 /* Asynchronous solves (continuous batching).  A request is admitted when its
  * workspace fits in the arena; admitted requests are stepped together on the
  * GPU.  The pointers in the request must stay valid until tsylv_poll returns
- * a final status for its ticket. */
+ * a final status for its ticket.  A request with A, B and C all NULL solves
+ * the synthetic instance of `gen_seed` (tsylv_generate), drawn on the device
+ * inside its setup transforms, so that the spatial tensors are never stored
+ * (p <= 64; the generation counts in the request's latency). */
 typedef struct {
   int method;                 /* tsylv_method (GMRES, FOM or TBS)            */
   int64_t n, s, p;
@@ -169,6 +191,7 @@ typedef struct {
   const double* C;
   double* X;                  /* output (and X0 when opts.x0_given)         */
   tsylv_opts opts;
+  uint64_t gen_seed;          /* instance seed when A, B and C are NULL     */
 } tsylv_request;
 
 /* Queue a request; returns at once with a ticket. */

@@ -226,10 +226,27 @@ int tsylv_tba(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A, 
   return st;
 }
 
+int tsylv_generate(tsylv_ctx* ctx, uint64_t seed, int64_t n, int64_t s, int64_t p, double* A,
+                   double* B, double* C) {
+  if (!ctx || !dims_ok(n, s, p)) return TSYLV_EINVAL;
+  return guarded([&]() {
+    std::lock_guard<std::mutex> g(ctx->c.sync_mu);
+    set_device(ctx);
+    hipStream_t st = ctx->c.stream;
+    if (A) kern::gen_tensor_f64(gen_instance(seed, 0, n, s, p), A, n * n, (int)p, st);
+    if (B) kern::gen_tensor_f64(gen_instance(seed, 1, n, s, p), B, s * s, (int)p, st);
+    if (C) kern::gen_tensor_f64(gen_instance(seed, 2, n, s, p), C, n * s, (int)p, st);
+    ctx->c.sync();
+    return (int)TSYLV_OK;
+  });
+}
+
 int tsylv_submit(tsylv_ctx* ctx, const tsylv_request* req, uint64_t* ticket) {
   if (!ctx || !req || !ticket) return TSYLV_EINVAL;
   const tsylv_request& r = *req;
-  if (!r.A || !r.B || !r.C || !r.X || !dims_ok(r.n, r.s, r.p)) return TSYLV_EINVAL;
+  const bool given = r.A && r.B && r.C, generated = !r.A && !r.B && !r.C;
+  if (!(given || generated) || !r.X || !dims_ok(r.n, r.s, r.p)) return TSYLV_EINVAL;
+  if (generated && r.p > kern::kGenXformMaxP) return TSYLV_EINVAL;
   if (r.method != TSYLV_METHOD_GMRES && r.method != TSYLV_METHOD_FOM &&
       r.method != TSYLV_METHOD_TBS)
     return TSYLV_EINVAL;

@@ -16,6 +16,22 @@ void build_xform(double* M, int p, int kind, hipStream_t st);
 void tube_xform_f64(const double* in, double* out, const double* M, int64_t E,
                     int p, hipStream_t st);
 
+// Synthetic instances from the counter-based stream of philox.hpp (tensor
+// `g`, frontal slices of E = rows x cols elements).  gen_tensor_f64 writes
+// the spatial tensor; tube_xform_gen_f64 writes what tube_xform_f64 would
+// make of it, bit for bit, without storing it (p <= kGenXformMaxP).
+constexpr int kGenXformMaxP = 64;
+struct GenTensor {
+  uint64_t seed;
+  uint64_t id;    // 0: A, 1: B, 2: C
+  int64_t rows;   // column-major rows x cols frontal slices
+  double scale;   // value = scale * z, rounded ...
+  double shift;   // ... then + shift on the diagonal of frontal slice 1
+};
+void gen_tensor_f64(const GenTensor& g, double* out, int64_t E, int p, hipStream_t st);
+void tube_xform_gen_f64(const GenTensor& g, double* out, const double* M, int64_t E, int p,
+                        hipStream_t st);
+
 // Down-conversion of `count` doubles (round to nearest even).
 void convert_f64_f32(const double* in, float* out, int64_t count, hipStream_t st);
 void convert_f64_bf16(const double* in, uint16_t* out, int64_t count, hipStream_t st);

@@ -16,6 +16,8 @@
 
 #include <hip/hip_bf16.h>
 
+#include "philox.hpp"
+
 namespace tsylv {
 namespace kern {
 
@@ -69,25 +71,76 @@ __global__ void build_xform_kernel(double* M, int p, int kind) {
 }
 
 template <int PMAX>
-__global__ __launch_bounds__(kBlock) void tube_xform_kernel(
-    const double* __restrict__ in, double* __restrict__ out,
-    const double* __restrict__ M, int64_t E, int p) {
-  __shared__ double Ms[PMAX * PMAX];
+__device__ __forceinline__ void stage_xform(double* Ms, const double* __restrict__ M, int p) {
   for (int t = threadIdx.x; t < PMAX * PMAX; t += kBlock) {
     int q = t / PMAX, j = t % PMAX;
     Ms[t] = (q < p && j < p) ? M[q * p + j] : 0.0;
   }
   __syncthreads();
-  int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= E) return;
-  double v[PMAX];
-#pragma unroll
-  for (int j = 0; j < PMAX; ++j) v[j] = (j < p) ? in[(int64_t)j * E + e] : 0.0;
+}
+
+// out[q E + e] for every q from the tube v (zero past p): one fixed fma
+// order, shared by the transforms of stored and of generated tubes.
+template <int PMAX>
+__device__ __forceinline__ void xform_store(const double* Ms, const double (&v)[PMAX],
+                                            double* __restrict__ out, int64_t E, int64_t e,
+                                            int p) {
   for (int q = 0; q < p; ++q) {
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < PMAX; ++j) acc = fma(Ms[q * PMAX + j], v[j], acc);
     out[(int64_t)q * E + e] = acc;
+  }
+}
+
+template <int PMAX>
+__global__ __launch_bounds__(kBlock) void tube_xform_kernel(
+    const double* __restrict__ in, double* __restrict__ out,
+    const double* __restrict__ M, int64_t E, int p) {
+  __shared__ double Ms[PMAX * PMAX];
+  stage_xform<PMAX>(Ms, M, p);
+  int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= E) return;
+  double v[PMAX];
+#pragma unroll
+  for (int j = 0; j < PMAX; ++j) v[j] = (j < p) ? in[(int64_t)j * E + e] : 0.0;
+  xform_store<PMAX>(Ms, v, out, E, e, p);
+}
+
+// The transform of a generated tensor: each thread draws its tube from the
+// counter-based stream in registers, so the spatial tensor is never stored.
+template <int PMAX>
+__global__ __launch_bounds__(kBlock) void tube_xform_gen_kernel(
+    GenTensor g, double* __restrict__ out, const double* __restrict__ M, int64_t E, int p) {
+  __shared__ double Ms[PMAX * PMAX];
+  stage_xform<PMAX>(Ms, M, p);
+  int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= E) return;
+  double v[PMAX];
+#pragma unroll
+  for (int kb = 0; kb < PMAX / 4; ++kb) {
+    double x[4] = {0.0, 0.0, 0.0, 0.0};
+    if (4 * kb < p) gen_block4(g, e, kb, x);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[4 * kb + q] = (4 * kb + q < p) ? x[q] : 0.0;
+  }
+  xform_store<PMAX>(Ms, v, out, E, e, p);
+}
+
+// The spatial tensor itself: one thread per position e, its tube written
+// four slices at a time (each store row coalesced across the wavefront).
+__global__ __launch_bounds__(kBlock) void gen_tensor_kernel(GenTensor g, double* __restrict__ out,
+                                                            int64_t E, int p) {
+  const int64_t nkb = (p + 3) / 4;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < E;
+       e += (int64_t)gridDim.x * kBlock) {
+    for (int64_t kb = 0; kb < nkb; ++kb) {
+      double x[4];
+      gen_block4(g, e, kb, x);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (4 * kb + q < p) out[(4 * kb + q) * E + e] = x[q];
+    }
   }
 }
 
@@ -878,6 +931,30 @@ void tube_xform_f64(const double* in, double* out, const double* M, int64_t E, i
     hipLaunchKernelGGL(tube_xform_kernel<64>, grid, dim3(kBlock), 0, st, in, out, M, E, p);
   else
     hipLaunchKernelGGL(tube_xform_generic_kernel, grid, dim3(kBlock), 0, st, in, out, M, E, p);
+  TSYLV_LAUNCH_CHECK();
+}
+
+void tube_xform_gen_f64(const GenTensor& g, double* out, const double* M, int64_t E, int p,
+                        hipStream_t st) {
+  if (E <= 0) return;
+  if (p > kGenXformMaxP) throw Error(TSYLV_EINVAL, "generated transform: p > 64");
+  dim3 grid((unsigned)((E + kBlock - 1) / kBlock));
+  if (p <= 4)
+    hipLaunchKernelGGL(tube_xform_gen_kernel<4>, grid, dim3(kBlock), 0, st, g, out, M, E, p);
+  else if (p <= 8)
+    hipLaunchKernelGGL(tube_xform_gen_kernel<8>, grid, dim3(kBlock), 0, st, g, out, M, E, p);
+  else if (p <= 16)
+    hipLaunchKernelGGL(tube_xform_gen_kernel<16>, grid, dim3(kBlock), 0, st, g, out, M, E, p);
+  else if (p <= 32)
+    hipLaunchKernelGGL(tube_xform_gen_kernel<32>, grid, dim3(kBlock), 0, st, g, out, M, E, p);
+  else
+    hipLaunchKernelGGL(tube_xform_gen_kernel<64>, grid, dim3(kBlock), 0, st, g, out, M, E, p);
+  TSYLV_LAUNCH_CHECK();
+}
+
+void gen_tensor_f64(const GenTensor& g, double* out, int64_t E, int p, hipStream_t st) {
+  if (E <= 0 || p <= 0) return;
+  hipLaunchKernelGGL(gen_tensor_kernel, dim3(stream_grid(E)), dim3(kBlock), 0, st, g, out, E, p);
   TSYLV_LAUNCH_CHECK();
 }
 

@@ -22,10 +22,12 @@ class KrylovTask {
  public:
   // Validated arguments; the workspace is taken from `arena` here (throws
   // TSYLV_ENOMEM if it does not fit).  `pinned` must hold pinned_doubles(o)
-  // doubles of page-locked host memory owned by the caller.
+  // doubles of page-locked host memory owned by the caller.  With `gen`
+  // non-null, A, B and C are ignored and the synthetic instance of seed
+  // *gen is drawn on the device inside the setup transforms (p <= 64).
   KrylovTask(Ctx& ctx, hipStream_t st, bool profile, double* pinned, int method, int64_t n,
              int64_t s, int64_t p, const double* A, const double* B, const double* C, double* X,
-             const tsylv_opts& o);
+             const tsylv_opts& o, const uint64_t* gen = nullptr);
   ~KrylovTask();
   KrylovTask(const KrylovTask&) = delete;
   KrylovTask& operator=(const KrylovTask&) = delete;

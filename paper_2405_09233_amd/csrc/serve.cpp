@@ -128,7 +128,7 @@ struct Scheduler {
           throw Error(TSYLV_EINVAL, "serve: restart length too large");
         a.task.reset(new KrylovTask(ctx, streams[slot], false, pinned + slot * kPinnedPerSlot,
                                     q.r.method, q.r.n, q.r.s, q.r.p, q.r.A, q.r.B, q.r.C, q.r.X,
-                                    q.r.opts));
+                                    q.r.opts, q.r.A ? nullptr : &q.r.gen_seed));
       } catch (const Error& e) {
         if (e.status == TSYLV_ENOMEM) {  // fragmentation: retry later, at the head
           lk.lock();

@@ -250,9 +250,29 @@ size_t setup_bytes(int64_t n, int64_t s, int64_t p) {
 
 // Algorithm 1 step 1 for the operator (unscaled DFT planes of A and B) and
 // the orthonormal planes of C and X0.
+kern::GenTensor gen_instance(uint64_t seed, int which, int64_t n, int64_t s, int64_t p) {
+  kern::GenTensor g;
+  g.seed = seed;
+  g.id = (uint64_t)which;
+  if (which == 0) {
+    g.rows = n;
+    g.scale = 2.0 / std::sqrt((double)(n * p));
+    g.shift = 4.0;
+  } else if (which == 1) {
+    g.rows = s;
+    g.scale = 2.0 / std::sqrt((double)(s * p));
+    g.shift = -4.0;
+  } else {
+    g.rows = n;
+    g.scale = 1.0;
+    g.shift = 0.0;
+  }
+  return g;
+}
+
 Setup setup_fourier(Ctx& ctx, hipStream_t st, bool profile, Workspace& ws, int64_t n, int64_t s,
                     int64_t p, const double* A, const double* B, const double* C, const double* X,
-                    bool x0_given) {
+                    bool x0_given, const uint64_t* gen) {
   const int64_t N = n * s * p;
   Setup S;
   S.Ah = ws.take<double>(p * n * n);
@@ -265,12 +285,21 @@ Setup setup_fourier(Ctx& ctx, hipStream_t st, bool profile, Workspace& ws, int64
   kern::build_xform(S.xf_op, (int)p, XF_OPERATOR, st);
   kern::build_xform(S.xf_fwd, (int)p, XF_FORWARD, st);
   kern::build_xform(S.xf_inv, (int)p, XF_INVERSE, st);
-  {
-    ProfScope ps(ctx, TSYLV_K_XFORM, st, profile);
-    kern::tube_xform_f64(A, S.Ah, S.xf_op, n * n, (int)p, st);
+  if (gen) {
+    {
+      ProfScope ps(ctx, TSYLV_K_XFORM, st, profile);
+      kern::tube_xform_gen_f64(gen_instance(*gen, 0, n, s, p), S.Ah, S.xf_op, n * n, (int)p, st);
+    }
+    kern::tube_xform_gen_f64(gen_instance(*gen, 1, n, s, p), S.Bh, S.xf_op, s * s, (int)p, st);
+    kern::tube_xform_gen_f64(gen_instance(*gen, 2, n, s, p), S.Zc, S.xf_fwd, n * s, (int)p, st);
+  } else {
+    {
+      ProfScope ps(ctx, TSYLV_K_XFORM, st, profile);
+      kern::tube_xform_f64(A, S.Ah, S.xf_op, n * n, (int)p, st);
+    }
+    kern::tube_xform_f64(B, S.Bh, S.xf_op, s * s, (int)p, st);
+    kern::tube_xform_f64(C, S.Zc, S.xf_fwd, n * s, (int)p, st);
   }
-  kern::tube_xform_f64(B, S.Bh, S.xf_op, s * s, (int)p, st);
-  kern::tube_xform_f64(C, S.Zc, S.xf_fwd, n * s, (int)p, st);
   if (x0_given)
     kern::tube_xform_f64(X, S.Zx, S.xf_fwd, n * s, (int)p, st);
   else
@@ -396,13 +425,13 @@ struct KrylovState {
 
   KrylovState(Ctx& c, hipStream_t stream, bool profile, double* pinned, int meth, int64_t n_,
               int64_t s_, int64_t p_, const double* A, const double* B, const double* C,
-              double* X_, const tsylv_opts& opts)
+              double* X_, const tsylv_opts& opts, const uint64_t* gen)
       : ctx(c), st(stream), prof(profile), method(meth), n(n_), s(s_), p(p_), N(n_ * s_ * p_),
         X(X_), o(opts), refine(opts.refine != 0),
         ws(c.arena, krylov_workspace_bytes(meth, n_, s_, p_, opts)) {
     t0 = std::chrono::steady_clock::now();
     info.status = TSYLV_PENDING;
-    S = setup_fourier(ctx, st, prof, ws, n, s, p, A, B, C, X, o.x0_given != 0);
+    S = setup_fourier(ctx, st, prof, ws, n, s, p, A, B, C, X, o.x0_given != 0, gen);
     op.n = n;
     op.s = s;
     op.p = p;
@@ -1083,8 +1112,8 @@ struct KrylovState {
 
 KrylovTask::KrylovTask(Ctx& ctx, hipStream_t st, bool profile, double* pinned, int method,
                        int64_t n, int64_t s, int64_t p, const double* A, const double* B,
-                       const double* C, double* X, const tsylv_opts& o)
-    : s_(new KrylovState(ctx, st, profile, pinned, method, n, s, p, A, B, C, X, o)) {}
+                       const double* C, double* X, const tsylv_opts& o, const uint64_t* gen)
+    : s_(new KrylovState(ctx, st, profile, pinned, method, n, s, p, A, B, C, X, o, gen)) {}
 
 KrylovTask::~KrylovTask() = default;
 

@@ -1,6 +1,7 @@
 // Driver entry points used by the C ABI.
 #pragma once
 
+#include "kernels.hpp"
 #include "runtime.hpp"
 
 namespace tsylv {
@@ -11,9 +12,16 @@ struct Setup {
   double *Ah, *Bh, *xf_op, *xf_fwd, *xf_inv, *Zc, *Zx;
 };
 size_t setup_bytes(int64_t n, int64_t s, int64_t p);
+// With `gen` non-null, A, B and C are not read: the instance of seed *gen
+// (gen_instance) is drawn inside the transforms (p <= 64).
 Setup setup_fourier(Ctx& ctx, hipStream_t st, bool profile, Workspace& ws, int64_t n, int64_t s,
                     int64_t p, const double* A, const double* B, const double* C, const double* X,
-                    bool x0_given);
+                    bool x0_given, const uint64_t* gen = nullptr);
+
+// The synthetic dense instance of `seed` (p-scaled noise): tensor `which`
+// (0: A, 1: B, 2: C) of the counter-based stream.  A = 2/sqrt(n p) Z + 4 I
+// and B = 2/sqrt(s p) Z - 4 I on frontal slice 1, C = Z.
+kern::GenTensor gen_instance(uint64_t seed, int which, int64_t n, int64_t s, int64_t p);
 
 size_t tba_workspace_bytes(int64_t n, int64_t s, int64_t p, int m);
 int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,

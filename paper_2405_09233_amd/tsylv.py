@@ -55,7 +55,8 @@ K_APPLY, K_ORTHO, K_XFORM, K_APPLY_LOW = 0, 1, 2, 3
 class Request(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("n", ctypes.c_int64), ("s", ctypes.c_int64),
                 ("p", ctypes.c_int64), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
-                ("C", ctypes.c_void_p), ("X", ctypes.c_void_p), ("opts", Opts)]
+                ("C", ctypes.c_void_p), ("X", ctypes.c_void_p), ("opts", Opts),
+                ("gen_seed", ctypes.c_uint64)]
 
 
 _lib = None
@@ -77,6 +78,9 @@ _SIGS = {
                                  ctypes.POINTER(Info)]),
     "tsylv_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request),
                                     ctypes.POINTER(ctypes.c_uint64)]),
+    "tsylv_generate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64,
+                                      ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
     "tsylv_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Info)]),
     "tsylv_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "tsylv_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -233,13 +237,32 @@ class Context:
     def tbs(self, A, B, C, X=None, opts=None, **kw):
         return self._solve("tsylv_tbs", A, B, C, X, opts, **kw)
 
-    def submit(self, A, B, C, X, method=GMRES, opts=None, **kw):
-        n, _, p = A.shape
-        s = B.shape[0]
+    def generate(self, seed, n, s, p, device=None):
+        """The synthetic instance of `seed` (tsylv_generate) as device
+        tensors A, B, C."""
+        dev = device if device is not None else "cuda:%d" % self.device
+        A, B, C = (empty_device(sh, dev) for sh in ((n, n, p), (s, s, p), (n, s, p)))
+        st = load().tsylv_generate(self.handle, seed, n, s, p, _ptr(A), _ptr(B), _ptr(C))
+        if st != 0:
+            raise TsylvError(st, "tsylv_generate")
+        return A, B, C
+
+    def submit(self, A, B, C, X, method=GMRES, opts=None, seed=None, **kw):
+        """Queue a solve.  With A, B and C None the request solves the
+        synthetic instance of `seed`, drawn on the device (its shape is X's)."""
         req = Request()
         req.method = method
+        if A is None and B is None and C is None:
+            if seed is None:
+                raise ValueError("a generated request needs a seed")
+            n, s, p = X.shape
+            req.gen_seed = seed
+        else:
+            n, _, p = A.shape
+            s = B.shape[0]
+            req.A, req.B, req.C = (_ptr(t).value for t in (A, B, C))
         req.n, req.s, req.p = n, s, p
-        req.A, req.B, req.C, req.X = (t.data_ptr() for t in (A, B, C, X))
+        req.X = _ptr(X).value
         req.opts = opts if opts is not None else default_opts(method, **kw)
         ticket = ctypes.c_uint64()
         st = load().tsylv_submit(self.handle, ctypes.byref(req), ctypes.byref(ticket))

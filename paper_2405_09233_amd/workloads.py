@@ -33,6 +33,17 @@ Recipes
   b_i = p + i, h1 = 1/(n+1), h2 = 1/(s+1).  C is uniform on [0, 1) (the
   experiment uses MATLAB's rand; its stream is not reproduced).  The paper
   does not give mu; it is a parameter here.
+* ``philox_instance(seed, n, s, p)`` -- the dense p-scaled recipe drawn from
+  a counter-based generator, so that the device can make the same instance
+  in place (tsylv_generate, and serving requests that carry only a seed).
+  Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11), key = (seed,
+  tensor id) with A = 0, B = 1, C = 2.  Element (i, j, k) of a rows x cols x p
+  tensor, e = i + rows j, uses the four words of the block at counter
+  (e, floor(k / 4), 0, 0): uniforms u_r = ((w_r >> 12) + 1/2) 2^-52 (exact,
+  in (0, 1)), and Box-Muller on (u0, u1) gives k % 4 = 0 (cos) and 1 (sin),
+  on (u2, u3) k % 4 = 2 and 3: z = sqrt(-2 log u) cos(2 pi u') resp. sin.
+  A = (2/sqrt(n p)) z + 4 I on slice 1, B = (2/sqrt(s p)) z - 4 I on slice 1
+  (product rounded, then the shift added), C = z.
 """
 
 import numpy as np
@@ -147,3 +158,66 @@ def ex3(n, s, p, mu=1.0, seed=0):
         B[:, :, i - 1] = _ex3_slice(s, h2, mu, float(p + i))
     C = rng.random(n * s * p).reshape((n, s, p), order="F")
     return A, B, np.asfortranarray(C)
+
+
+# ------------------------------------------------------------ counter-based
+
+_PHILOX_M = (0xD2E7470EE14C6C93, 0xCA5A826395121157)  # round multipliers
+_PHILOX_W = (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B)  # key schedule (Weyl)
+_M32 = np.uint64(0xFFFFFFFF)
+
+
+def _mulhilo64(a, m):
+    """(high, low) 64-bit halves of the 128-bit product of uint64 array `a`
+    and the constant `m`, from 32-bit partial products."""
+    a0, a1 = a & _M32, a >> np.uint64(32)
+    m0, m1 = np.uint64(m & 0xFFFFFFFF), np.uint64(m >> 32)
+    p00, p01, p10, p11 = a0 * m0, a0 * m1, a1 * m0, a1 * m1
+    mid = (p00 >> np.uint64(32)) + (p01 & _M32) + (p10 & _M32)
+    hi = p11 + (p01 >> np.uint64(32)) + (p10 >> np.uint64(32)) + (mid >> np.uint64(32))
+    lo = a * np.uint64(m)
+    return hi, lo
+
+
+def philox4x64(c0, c1, c2, c3, k0, k1, rounds=10):
+    """Philox4x64-`rounds` on uint64 counter arrays (c0..c3) under the key
+    (k0, k1); returns the four output word arrays."""
+    c = [np.asarray(x, dtype=np.uint64) for x in (c0, c1, c2, c3)]
+    k = [int(k0) & (2**64 - 1), int(k1) & (2**64 - 1)]
+    with np.errstate(over="ignore"):
+        for _ in range(rounds):
+            hi0, lo0 = _mulhilo64(c[0], _PHILOX_M[0])
+            hi1, lo1 = _mulhilo64(c[2], _PHILOX_M[1])
+            c = [hi1 ^ c[1] ^ np.uint64(k[0]), lo1, hi0 ^ c[3] ^ np.uint64(k[1]), lo0]
+            k = [(k[0] + _PHILOX_W[0]) & (2**64 - 1), (k[1] + _PHILOX_W[1]) & (2**64 - 1)]
+    return c
+
+
+def philox_normal_tensor(seed, tensor_id, rows, cols, p):
+    """N(0,1) tensor (rows, cols, p), Fortran order, from the counter-based
+    stream described in the module docstring."""
+    E = rows * cols
+    out = np.empty((E, p), order="F")
+    e = np.arange(E, dtype=np.uint64)
+    zero = np.zeros(E, dtype=np.uint64)
+    for kb in range((p + 3) // 4):
+        w = philox4x64(e, np.full(E, kb, dtype=np.uint64), zero, zero, seed, tensor_id)
+        u = [((x >> np.uint64(12)).astype(np.float64) + 0.5) * 2.0**-52 for x in w]
+        for half in range(2):
+            r = np.sqrt(-2.0 * np.log(u[2 * half]))
+            t = 2.0 * np.pi * u[2 * half + 1]
+            for trig, k in ((np.cos, 4 * kb + 2 * half), (np.sin, 4 * kb + 2 * half + 1)):
+                if k < p:
+                    out[:, k] = r * trig(t)
+    return out.reshape((rows, cols, p), order="F")
+
+
+def philox_instance(seed, n, s, p, shift=4.0):
+    """The dense p-scaled instance of `seed` drawn from the counter-based
+    stream (the instance tsylv_generate writes on the device)."""
+    A = philox_normal_tensor(seed, 0, n, n, p) * (2.0 / np.sqrt(n * p))
+    A[:, :, 0] += shift * np.eye(n)
+    B = philox_normal_tensor(seed, 1, s, s, p) * (2.0 / np.sqrt(s * p))
+    B[:, :, 0] -= shift * np.eye(s)
+    C = philox_normal_tensor(seed, 2, n, s, p)
+    return np.asfortranarray(A), np.asfortranarray(B), np.asfortranarray(C)
