@@ -254,55 +254,76 @@ def serving(tsylv, workloads, rate, duration, npool=96, seed=50):
     return out
 
 
-def serving_full(tsylv, rate=40.0, duration=10.0, npool=128, seed=51):
+def _draw_full_size(rng):
+    n = int(round(np.exp(rng.uniform(np.log(128), np.log(4096)))))
+    s = int(round(np.exp(rng.uniform(np.log(8), np.log(256)))))
+    p = int(rng.integers(4, 65))
+    return n, s, p
+
+
+def _served_generated(tsylv, ctx, o, sizes, ids, arrivals=None):
+    """Requests that carry only a seed (the request id): each draws its own
+    instance on the device inside the serving loop.  With `arrivals` None all
+    are submitted at once; otherwise request i is submitted at arrivals[i]
+    seconds (open loop).  Returns (latencies from the scheduled arrival in s,
+    failures, span in s)."""
+    t0 = time.perf_counter()
+    pending = {}  # ticket -> (X, arrival)
+    lat, bad, i = [], 0, 0
+    while i < len(sizes) or pending:
+        now = time.perf_counter() - t0
+        while i < len(sizes) and (arrivals is None or arrivals[i] <= now):
+            X = tsylv.empty_device(sizes[i], "cuda:0")
+            ta = 0.0 if arrivals is None else arrivals[i]
+            pending[ctx.submit(None, None, None, X, method=tsylv.GMRES, opts=o,
+                               seed=int(ids[i]))] = (X, ta)
+            i += 1
+        for t in list(pending):
+            st, info = ctx.poll(t)
+            if st != 2:
+                _, ta = pending.pop(t)
+                lat.append(time.perf_counter() - t0 - ta)
+                if st != 0 or info.relres_true > 1e-8:
+                    bad += 1
+        time.sleep(0.0002)
+    return np.array(lat), bad, time.perf_counter() - t0
+
+
+def serving_full(tsylv, rate=40.0, duration=10.0, nbatch=128, seed=50):
     """Serving at the recipe's full sizes: n log-uniform in [128, 4096], s
-    log-uniform in [8, 256], p uniform in {4..64}, dense instances with
-    p-scaled noise (A slices N(0,1) 2/sqrt(n p) + 4 I on slice 1, B slices
-    N(0,1) 2/sqrt(s p) - 4 I, C N(0,1)), generated on the device by torch's
-    seeded normal generator; tol 1e-8, at most 8 solves on the GPU at once in
-    a 96 GB arena.  Batch throughput (the pool of `npool` submitted at once)
-    and an open-loop Poisson run at `rate` per second for `duration` s."""
-    import torch
+    log-uniform in [8, 256], p uniform in {4..64}; every request carries only
+    a seed (its id) and draws its dense p-scaled-noise instance on the device
+    (tsylv_generate's definition) inside the serving loop, so latency
+    includes the generation; tol 1e-8, at most 8 solves on the GPU at once,
+    admitted by a 200 GB arena.  A batch of `nbatch` requests submitted at
+    once (solves/s = nbatch / time to the last completion: each size of the
+    mix weighs once) and an open-loop Poisson run at `rate` per second for
+    `duration` s."""
     rng = np.random.default_rng(seed)
-    gen = torch.Generator(device="cuda:0")
-    gen.manual_seed(seed)
-
-    def tensor(rows, cols, p, scale, shift):
-        base = torch.randn((p, cols, rows), generator=gen, device="cuda:0",
-                           dtype=torch.float64) * scale
-        if shift:
-            base[0] += shift * torch.eye(rows, device="cuda:0", dtype=torch.float64)
-        return base.permute(2, 1, 0)  # (rows, cols, p), frontal-slice-major memory
-
-    pool, sizes = [], []
-    for i in range(npool):
-        n = int(round(np.exp(rng.uniform(np.log(128), np.log(4096)))))
-        s = int(round(np.exp(rng.uniform(np.log(8), np.log(256)))))
-        p = int(rng.integers(4, 65))
-        A = tensor(n, n, p, 2.0 / np.sqrt(n * p), 4.0)
-        B = tensor(s, s, p, 2.0 / np.sqrt(s * p), -4.0)
-        C = tensor(n, s, p, 1.0, 0.0)
-        X = torch.empty((p, s, n), device="cuda:0", dtype=torch.float64).permute(2, 1, 0)
-        pool.append((A, B, C, X))
-        sizes.append(n * n * p * 8)
-    torch.cuda.synchronize()
+    batch = [_draw_full_size(rng) for _ in range(nbatch)]
+    gaps = rng.exponential(1.0 / rate, size=int(rate * duration * 2) + 16)
+    arrivals = np.cumsum(gaps)
+    arrivals = arrivals[arrivals < duration]
+    stream = [_draw_full_size(rng) for _ in range(len(arrivals))]
+    mean_a = float(np.mean([n * n * p * 8 for n, _, p in batch + stream]))
     opts = {
         "fp64": tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-8, max_cycles=2000),
         "bf16": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.BF16, inner_m=24,
                                    inner_tol=1e-4, tol=1e-8, max_outer=300),
     }
-    out = {"recipe": "n log-uniform [128, 4096], s log-uniform [8, 256], p uniform {4..64}, "
-                     "dense p-scaled-noise instances generated on the device (pool of %d, "
-                     "mean A %.2f GB, largest %.1f GB), tol 1e-8, at most 8 solves on the GPU "
-                     "at once, 96 GB arena; batch: the pool submitted at once; open loop: "
-                     "Poisson arrivals %.0f/s for %.0f s" %
-                     (npool, float(np.mean(sizes)) / 1e9, max(sizes) / 1e9, rate, duration)}
+    out = {"recipe": "n log-uniform [128, 4096], s log-uniform [8, 256], p uniform {4..64}; each "
+                     "request carries its id as seed and draws its dense p-scaled-noise instance "
+                     "on the device (mean A %.2f GB); tol 1e-8, at most 8 solves on the GPU at "
+                     "once, 200 GB arena; batch: %d requests submitted at once; open loop: "
+                     "Poisson arrivals %.0f/s for %.0f s (%d requests)" %
+                     (mean_a / 1e9, nbatch, rate, duration, len(arrivals))}
     for name, o in opts.items():
-        ctx = tsylv.Context(96 << 30, device=0)
-        rate_b, bad_b, done = _batch(tsylv, ctx, pool, o)
-        lat, bad, span = _open_loop(tsylv, ctx, pool, o, rate, duration, rng)
+        ctx = tsylv.Context(200 << 30, device=0)
+        done, bad_b, span_b = _served_generated(tsylv, ctx, o, batch, np.arange(nbatch))
+        lat, bad, span = _served_generated(tsylv, ctx, o, stream,
+                                           nbatch + np.arange(len(stream)), arrivals)
         ctx.close()
-        out[name] = {"batch_solves_per_s": float(rate_b), "batch_failed": int(bad_b),
+        out[name] = {"batch_solves_per_s": float(nbatch / span_b), "batch_failed": int(bad_b),
                      "batch_completion_s": {"p50": float(np.percentile(done, 50)),
                                             "max": float(done.max())},
                      "requests": int(len(lat)), "failed": int(bad),
@@ -312,7 +333,7 @@ def serving_full(tsylv, rate=40.0, duration=10.0, npool=128, seed=51):
                                     "mean": float(lat.mean() * 1e3)}}
         log("serving (full sizes) %s: batch of %d: %.1f solves/s; Poisson %.0f/s: %d requests, "
             "p50 %.1f ms, p99 %.1f ms; failed %d + %d" % (
-                name, npool, rate_b, rate, len(lat), out[name]["latency_ms"]["p50"],
+                name, nbatch, nbatch / span_b, rate, len(lat), out[name]["latency_ms"]["p50"],
                 out[name]["latency_ms"]["p99"], bad_b, bad))
     out["bf16_vs_fp64_batch"] = (out["bf16"]["batch_solves_per_s"]
                                  / max(out["fp64"]["batch_solves_per_s"], 1e-30))

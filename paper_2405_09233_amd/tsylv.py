@@ -183,9 +183,12 @@ class Context:
         self.handle = h
 
     def close(self):
+        """Destroy the library context (finishes admitted requests, cancels
+        queued ones) and release the arena."""
         if getattr(self, "handle", None):
             load().tsylv_destroy(self.handle)
             self.handle = None
+        self.arena = None
 
     def __del__(self):
         try:
