@@ -231,6 +231,30 @@ int tsylv_profile_families(tsylv_ctx* ctx, unsigned mask);
 /* Synchronises the context stream and returns the totals of one family. */
 int tsylv_profile_read(tsylv_ctx* ctx, int kernel_id, tsylv_kstat* out);
 
+/* Tile autotuner of the facewise apply (a project addition; the paper does
+ * not tune).  The apply kernel has tsylv_apply_variants(prec) tile shapes,
+ * all valid for every (n, s, p) and all computing the same products; by
+ * default the shape follows s.  tsylv_autotune times every variant at
+ * (n, s, p) in precision `prec` (`reps` >= 1 launches each, on operands of
+ * that shape carved from the arena: the arena must hold them), keeps the
+ * fastest in the context's table, and every later apply of that exact shape
+ * and precision on the context uses it (solves, refinement, serving).
+ * `best` (may be NULL) receives the chosen variant; ms[v] for v < ms_cap
+ * (ms may be NULL) the average launch time of variant v in milliseconds.
+ * Synchronous on the context stream. */
+int tsylv_apply_variants(int prec);
+int tsylv_autotune(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, int prec, int reps,
+                   int* best, float* ms, int ms_cap);
+/* Set (variant >= 0) or clear (variant = -1) the table entry of a shape. */
+int tsylv_tune_set(tsylv_ctx* ctx, int prec, int64_t n, int64_t s, int64_t p, int variant);
+/* The entry of a shape in *variant (-1: none, the default is used). */
+int tsylv_tune_get(tsylv_ctx* ctx, int prec, int64_t n, int64_t s, int64_t p, int* variant);
+/* Write the table to a text file (a header line "tsylv-tune 1", then one
+ * line "prec n s p variant" per entry) / merge such a file into the table
+ * (TSYLV_EINVAL, and nothing merged, when any line is malformed). */
+int tsylv_tune_save(tsylv_ctx* ctx, const char* path);
+int tsylv_tune_load(tsylv_ctx* ctx, const char* path);
+
 /* Static string describing a status code. */
 const char* tsylv_strerror(int status);
 

@@ -294,6 +294,54 @@ int tsylv_profile_families(tsylv_ctx* ctx, unsigned mask) {
   });
 }
 
+int tsylv_apply_variants(int prec) {
+  if (prec != TSYLV_FP64 && prec != TSYLV_FP32 && prec != TSYLV_BF16) return TSYLV_EINVAL;
+  return kern::apply_variant_count(prec);
+}
+
+int tsylv_autotune(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, int prec, int reps,
+                   int* best, float* ms, int ms_cap) {
+  if (!ctx || !dims_ok(n, s, p) || tsylv_apply_variants(prec) < 0 || reps < 1 || reps > 1000 ||
+      ms_cap < 0)
+    return TSYLV_EINVAL;
+  return guarded([&]() {
+    std::lock_guard<std::mutex> g(ctx->c.sync_mu);
+    set_device(ctx);
+    autotune(ctx->c, n, s, p, prec, reps, best, ms, ms_cap);
+    return (int)TSYLV_OK;
+  });
+}
+
+int tsylv_tune_set(tsylv_ctx* ctx, int prec, int64_t n, int64_t s, int64_t p, int variant) {
+  if (!ctx || !dims_ok(n, s, p)) return TSYLV_EINVAL;
+  return guarded([&]() {
+    ctx->c.tune.set(prec, n, s, p, variant);
+    return (int)TSYLV_OK;
+  });
+}
+
+int tsylv_tune_get(tsylv_ctx* ctx, int prec, int64_t n, int64_t s, int64_t p, int* variant) {
+  if (!ctx || !variant || tsylv_apply_variants(prec) < 0) return TSYLV_EINVAL;
+  *variant = ctx->c.tune.get(prec, n, s, p);
+  return TSYLV_OK;
+}
+
+int tsylv_tune_save(tsylv_ctx* ctx, const char* path) {
+  if (!ctx || !path) return TSYLV_EINVAL;
+  return guarded([&]() {
+    tune_save(ctx->c, path);
+    return (int)TSYLV_OK;
+  });
+}
+
+int tsylv_tune_load(tsylv_ctx* ctx, const char* path) {
+  if (!ctx || !path) return TSYLV_EINVAL;
+  return guarded([&]() {
+    tune_load(ctx->c, path);
+    return (int)TSYLV_OK;
+  });
+}
+
 int tsylv_profile_read(tsylv_ctx* ctx, int kernel_id, tsylv_kstat* out) {
   if (!ctx || !out || kernel_id < 0 || kernel_id >= TSYLV_K_COUNT) return TSYLV_EINVAL;
   return guarded([&]() {

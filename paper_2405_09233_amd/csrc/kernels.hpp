@@ -41,12 +41,18 @@ void convert_f32_f64(const float* in, double* out, int64_t count, hipStream_t st
 //   out_k = alpha * (Ahat_k V_k - V_k Bhat_k) + beta * Y_k   for every slice k
 // (the V_k Bhat_k term is skipped when Bh == nullptr; Y may be nullptr when
 // beta == 0).  Ah: p planes n x n; Bh: p planes s x s; V, Y, out: p planes n x s.
+// `variant` picks the tile shape (0 .. apply_variant_count(prec) - 1; -1:
+// the default for s); every variant computes the same products.
 void apply_f64(const double* Ah, const double* Bh, const double* V, double* out,
                const double* Y, double alpha, double beta, int64_t n, int64_t s,
-               int p, hipStream_t st);
+               int p, hipStream_t st, int variant = -1);
 // Same in FP32 (FP32 MFMA).
 void apply_f32(const float* Ah, const float* Bh, const float* V, float* out, const float* Y,
-               double alpha, double beta, int64_t n, int64_t s, int p, hipStream_t st);
+               double alpha, double beta, int64_t n, int64_t s, int p, hipStream_t st,
+               int variant = -1);
+int apply_variant_count(int prec);             // tsylv_prec
+int apply_default_variant(int prec, int64_t s);
+int bf16_default_variant(int64_t s);
 
 // BF16 operator planes (BF16 MFMA, the vectors rounded to BF16 on the way
 // into the product, FP32 accumulation).  `At` holds the operator in the tiled
@@ -58,7 +64,7 @@ int64_t bf16_vtiled_elems(int64_t n, int64_t s, int p);
 void tile_operator_bf16(const double* Ah, uint16_t* At, int64_t n, int p, hipStream_t st);
 void apply_bf16(const uint16_t* At, const uint16_t* Bb, const float* V, uint16_t* Vt,
                 float* out, const float* Y, double alpha, double beta, int64_t n, int64_t s,
-                int p, hipStream_t st);
+                int p, hipStream_t st, int variant = -1);
 
 // ---- BF16 Krylov vectors (the inner basis of the BF16-refined solves) ----
 // A vector of p Fourier planes n x s stored as BF16 bits in the tiled order
@@ -79,7 +85,8 @@ void untile_update_bf16(const bf16t* V, int64_t ldv, int nv, const double* y, do
 // out = alpha (Ahat_k V_k - V_k Bhat_k) for every slice, V and out tiled
 // (out's padding written as zero; out must not alias V).
 void apply_bf16_tiled(const uint16_t* At, const uint16_t* Bb, const bf16t* V, bf16t* out,
-                      double alpha, int64_t n, int64_t s, int p, hipStream_t st);
+                      double alpha, int64_t n, int64_t s, int p, hipStream_t st,
+                      int variant = -1);
 
 // ---- t-Bartels-Stewart direct solve on the Fourier slices ----
 // Xhat_k from Ahat_k Xhat_k - Xhat_k Bhat_k = Chat_k for every slice of the

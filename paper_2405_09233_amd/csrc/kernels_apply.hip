@@ -329,42 +329,64 @@ void launch_apply(ApplyArgs<Tag> a, hipStream_t st) {
   TSYLV_LAUNCH_CHECK();
 }
 
+// Tile variants (TM x TN workgroup tile, RB x CB 16 x 16 blocks per wave),
+// the candidates of the autotuner; every one is valid for every shape.
 template <typename Tag>
-void dispatch(ApplyArgs<Tag> a, hipStream_t st) {
-  // Column tile as wide as s needs (up to 64) so small s does not waste MFMA work.
-  if (a.s <= 16)
-    launch_apply<Tag, 128, 16, 2, 1>(a, st);
-  else if (a.s <= 32)
-    launch_apply<Tag, 64, 32, 1, 2>(a, st);
-  else if (std::is_same<Tag, float>::value)
-    launch_apply<Tag, 64, 64, 1, 4>(a, st);  // FP32: 5 % faster at n = 4096, s = 64
-  else
-    launch_apply<Tag, 32, 64, 1, 2>(a, st);
+void launch_variant(int v, ApplyArgs<Tag> a, hipStream_t st) {
+  switch (v) {
+    case 0: launch_apply<Tag, 128, 16, 2, 1>(a, st); break;
+    case 1: launch_apply<Tag, 64, 32, 1, 2>(a, st); break;
+    case 2: launch_apply<Tag, 32, 64, 1, 2>(a, st); break;
+    case 3: launch_apply<Tag, 64, 64, 1, 4>(a, st); break;
+    case 4: launch_apply<Tag, 64, 64, 2, 2>(a, st); break;
+    case 5: launch_apply<Tag, 128, 32, 2, 2>(a, st); break;
+    default: throw Error(TSYLV_EINVAL, "apply: unknown tile variant");
+  }
+}
+
+// Without a tuned choice: a column tile as wide as s needs (up to 64), so
+// small s does not waste MFMA work; FP32 at s > 32 takes 64 x 64 tiles (5 %
+// faster at n = 4096, s = 64).
+template <typename Tag>
+int default_variant(int64_t s) {
+  if (s <= 16) return 0;
+  if (s <= 32) return 1;
+  return std::is_same<Tag, float>::value ? 3 : 2;
 }
 
 template <typename Tag>
 void apply_any(const typename Store<Tag>::T* Ah, const typename Store<Tag>::T* Bh,
                const typename Mma<Tag>::TV* V, typename Mma<Tag>::TV* out,
                const typename Mma<Tag>::TV* Y, double alpha, double beta, int64_t n, int64_t s,
-               int p, bool useB, hipStream_t st) {
+               int p, bool useB, int variant, hipStream_t st) {
   if (n <= 0 || s <= 0 || p <= 0) return;
   if (beta != 0.0 && Y == nullptr) throw Error(TSYLV_EINVAL, "apply: beta != 0 needs Y");
   if (useB && Bh == nullptr) throw Error(TSYLV_EINVAL, "apply: missing Bhat");
   ApplyArgs<Tag> a{Ah, Bh, V, out, beta != 0.0 ? Y : nullptr, alpha, beta, n, s, p,
                    useB ? 1 : 0, 0, 0, 0};
-  dispatch<Tag>(a, st);
+  launch_variant<Tag>(variant >= 0 ? variant : default_variant<Tag>(s), a, st);
 }
 
 }  // namespace
 
 void apply_f64(const double* Ah, const double* Bh, const double* V, double* out, const double* Y,
-               double alpha, double beta, int64_t n, int64_t s, int p, hipStream_t st) {
-  apply_any<double>(Ah, Bh, V, out, Y, alpha, beta, n, s, p, Bh != nullptr, st);
+               double alpha, double beta, int64_t n, int64_t s, int p, hipStream_t st,
+               int variant) {
+  apply_any<double>(Ah, Bh, V, out, Y, alpha, beta, n, s, p, Bh != nullptr, variant, st);
 }
 
 void apply_f32(const float* Ah, const float* Bh, const float* V, float* out, const float* Y,
-               double alpha, double beta, int64_t n, int64_t s, int p, hipStream_t st) {
-  apply_any<float>(Ah, Bh, V, out, Y, alpha, beta, n, s, p, Bh != nullptr, st);
+               double alpha, double beta, int64_t n, int64_t s, int p, hipStream_t st,
+               int variant) {
+  apply_any<float>(Ah, Bh, V, out, Y, alpha, beta, n, s, p, Bh != nullptr, variant, st);
+}
+
+int apply_variant_count(int prec) { return prec == TSYLV_BF16 ? 3 : 6; }
+
+int apply_default_variant(int prec, int64_t s) {
+  if (prec == TSYLV_FP64) return default_variant<double>(s);
+  if (prec == TSYLV_FP32) return default_variant<float>(s);
+  return bf16_default_variant(s);
 }
 
 }  // namespace kern

@@ -527,6 +527,8 @@ void launch_wg(Bf16Args a, int ncu, hipStream_t st) {
 
 }  // namespace
 
+int bf16_default_variant(int64_t s) { return s <= 16 ? 0 : (s <= 32 ? 1 : 2); }
+
 static int64_t row_blocks(int64_t n) { return ((n + 15) / 16 + kRowPad - 1) / kRowPad * kRowPad; }
 static int64_t k_blocks(int64_t n) { return ((n + 31) / 32 + kKPad - 1) / kKPad * kKPad; }
 static int64_t col_blocks(int64_t s) { return ((s + 15) / 16 + kColPad - 1) / kColPad * kColPad; }
@@ -547,25 +549,27 @@ void tile_operator_bf16(const double* Ah, uint16_t* At, int64_t n, int p, hipStr
   TSYLV_LAUNCH_CHECK();
 }
 
-// (column blocks, ring depth, phase length, waves, row blocks per wave)
-// from a sweep at n = 4096, p = 32, s = 16 / 32 / 64 and n = 8192, p = 64,
-// s = 128
+// Variants (column blocks, ring depth, phase length, waves, row blocks per
+// wave), the autotuner's candidates; the default per s is the best of a
+// sweep at n = 4096, p = 32, s = 16 / 32 / 64 and n = 8192, p = 64, s = 128.
 template <bool TIO>
-void launch_cfg(const Bf16Args& a, hipStream_t st) {
-  int dev = 0, ncu = 0;
+void launch_cfg(const Bf16Args& a, int variant, hipStream_t st) {
+  static int ncu_cached[64] = {};
+  int dev = 0;
   TSYLV_HIP(hipGetDevice(&dev));
-  TSYLV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  if (a.s <= 16)
-    launch_wg<1, 4, 8, 8, 2, TIO>(a, ncu, st);
-  else if (a.s <= 32)
-    launch_wg<2, 2, 4, 8, 2, TIO>(a, ncu, st);
-  else
-    launch_wg<4, 2, 2, 8, 2, TIO>(a, ncu, st);
+  int& ncu = ncu_cached[dev & 63];
+  if (ncu == 0) TSYLV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  switch (variant >= 0 ? variant : bf16_default_variant(a.s)) {
+    case 0: launch_wg<1, 4, 8, 8, 2, TIO>(a, ncu, st); break;
+    case 1: launch_wg<2, 2, 4, 8, 2, TIO>(a, ncu, st); break;
+    case 2: launch_wg<4, 2, 2, 8, 2, TIO>(a, ncu, st); break;
+    default: throw Error(TSYLV_EINVAL, "apply: unknown BF16 variant");
+  }
 }
 
 void apply_bf16(const uint16_t* At, const uint16_t* Bb, const float* V, uint16_t* Vt,
                 float* out, const float* Y, double alpha, double beta, int64_t n, int64_t s,
-                int p, hipStream_t st) {
+                int p, hipStream_t st, int variant) {
   if (n <= 0 || s <= 0 || p <= 0) return;
   if (beta != 0.0 && Y == nullptr) throw Error(TSYLV_EINVAL, "apply: beta != 0 needs Y");
   Bf16Args a{};
@@ -590,11 +594,11 @@ void apply_bf16(const uint16_t* At, const uint16_t* Bb, const float* V, uint16_t
                        a.nkb);
     TSYLV_LAUNCH_CHECK();
   }
-  launch_cfg<false>(a, st);
+  launch_cfg<false>(a, variant, st);
 }
 
 void apply_bf16_tiled(const uint16_t* At, const uint16_t* Bb, const bf16t* V, bf16t* out,
-                      double alpha, int64_t n, int64_t s, int p, hipStream_t st) {
+                      double alpha, int64_t n, int64_t s, int p, hipStream_t st, int variant) {
   if (n <= 0 || s <= 0 || p <= 0) return;
   if (reinterpret_cast<const void*>(V) == reinterpret_cast<const void*>(out))
     throw Error(TSYLV_EINVAL, "apply: tiled output must not alias the input");
@@ -610,7 +614,7 @@ void apply_bf16_tiled(const uint16_t* At, const uint16_t* Bb, const bf16t* V, bf
   a.nrb = row_blocks(n);
   a.nkb = k_blocks(n);
   a.ncb = col_blocks(s);
-  launch_cfg<true>(a, st);
+  launch_cfg<true>(a, variant, st);
 }
 
 void tile_scale_bf16(const double* X, bf16t* Xt, double a, int64_t n, int64_t s, int p,

@@ -1,7 +1,9 @@
 // Context, HBM arena and pinned host staging.
 #pragma once
 
+#include <array>
 #include <map>
+#include <string>
 #include <mutex>
 #include <vector>
 
@@ -83,6 +85,23 @@ class Profiler {
   double ms_[TSYLV_K_COUNT] = {};
 };
 
+// Tile choices of the facewise apply per (precision, n, s, p), filled by
+// the autotuner (tune.cpp) or set by the caller; thread-safe.  get() returns
+// -1 (the default for s) for a shape with no entry.
+class TuneTable {
+ public:
+  int get(int prec, int64_t n, int64_t s, int64_t p) const;
+  void set(int prec, int64_t n, int64_t s, int64_t p, int variant);  // -1 erases
+  size_t size() const;
+  // Text form: a header line, then one "prec n s p variant" line per entry.
+  std::string serialize() const;
+  void parse(const std::string& text);  // validates everything before it adds
+
+ private:
+  std::map<std::array<int64_t, 4>, int> m_;
+  mutable std::mutex mu_;
+};
+
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -96,6 +115,7 @@ struct Ctx {
   std::mutex sched_mu;
   std::mutex sync_mu;  // serialises synchronous calls on the context
   Profiler prof;
+  TuneTable tune;
 
   double* host_buffer(size_t count);  // grows the pinned buffer as needed
   void sync() { TSYLV_HIP(hipStreamSynchronize(stream)); }

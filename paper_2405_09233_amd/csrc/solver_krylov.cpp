@@ -71,6 +71,7 @@ struct Operator {
   const uint16_t* Bhb = nullptr;
   uint16_t* Vtb = nullptr;  // scratch: the BF16 apply's tiled copy of V
   int low = TSYLV_FP32;  // precision of the float-vector applies
+  int var64 = -1, var_low = -1;  // tile variants (-1: the default for s)
 };
 
 // Reduction buffers shared by the norm and dot kernels.
@@ -437,6 +438,7 @@ struct KrylovState {
     op.p = p;
     op.Ah64 = S.Ah;
     op.Bh64 = S.Bh;
+    op.var64 = ctx.tune.get(TSYLV_FP64, n, s, p);
     fused = fused_cycle(o);
     tiled = bf16_basis(o);
     delayed = delayed_cgs2(o);
@@ -460,6 +462,7 @@ struct KrylovState {
       if (Nt != N)
         TSYLV_HIP(hipMemsetAsync(w16.basis, 0, (size_t)(o.inner_m + 1) * w16.ldv * 2, st));
       op.low = TSYLV_BF16;
+      op.var_low = ctx.tune.get(TSYLV_BF16, n, s, p);
       uint16_t* Ab = ws.take<uint16_t>(kern::bf16_tiled_elems(n, (int)p));
       uint16_t* Bb = ws.take<uint16_t>(p * s * s);
       kern::tile_operator_bf16(S.Ah, Ab, n, (int)p, st);
@@ -471,6 +474,7 @@ struct KrylovState {
       w32.carve(ws, N, o.inner_m, pinned, devcyc);
       red = &w32.red;
       op.low = o.prec == TSYLV_BF16 ? TSYLV_BF16 : TSYLV_FP32;
+      op.var_low = ctx.tune.get(op.low, n, s, p);
       if (op.low == TSYLV_BF16) {
         uint16_t* Ab = ws.take<uint16_t>(kern::bf16_tiled_elems(n, (int)p));
         uint16_t* Bb = ws.take<uint16_t>(p * s * s);
@@ -492,21 +496,22 @@ struct KrylovState {
 
   void apply(const double* V, double* out, const double* Y, double alpha, double beta_) {
     ProfScope ps(ctx, TSYLV_K_APPLY, st, prof);
-    kern::apply_f64(op.Ah64, op.Bh64, V, out, Y, alpha, beta_, n, s, (int)p, st);
+    kern::apply_f64(op.Ah64, op.Bh64, V, out, Y, alpha, beta_, n, s, (int)p, st, op.var64);
   }
   void apply(const float* V, float* out, const float* Y, double alpha, double beta_) {
     ProfScope ps(ctx, TSYLV_K_APPLY_LOW, st, prof);
     if (op.low == TSYLV_BF16)
-      kern::apply_bf16(op.Ahb, op.Bhb, V, op.Vtb, out, Y, alpha, beta_, n, s, (int)p, st);
+      kern::apply_bf16(op.Ahb, op.Bhb, V, op.Vtb, out, Y, alpha, beta_, n, s, (int)p, st,
+                       op.var_low);
     else
-      kern::apply_f32(op.Ah32, op.Bh32, V, out, Y, alpha, beta_, n, s, (int)p, st);
+      kern::apply_f32(op.Ah32, op.Bh32, V, out, Y, alpha, beta_, n, s, (int)p, st, op.var_low);
   }
 
   void apply(const kern::bf16t* V, kern::bf16t* out, const kern::bf16t* Y, double alpha,
              double beta_) {
     ProfScope ps(ctx, TSYLV_K_APPLY_LOW, st, prof);
     if (Y || beta_ != 0.0) throw Error(TSYLV_EINVAL, "apply: tiled vectors take no Y");
-    kern::apply_bf16_tiled(op.Ahb, op.Bhb, V, out, alpha, n, s, (int)p, st);
+    kern::apply_bf16_tiled(op.Ahb, op.Bhb, V, out, alpha, n, s, (int)p, st, op.var_low);
   }
 
   // ||v||^2 to red->h_ww[0] after the next synchronisation.
@@ -1178,7 +1183,8 @@ int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, co
   kern::tube_xform_f64(X, Zx, xf_fwd, n * s, (int)p, st);
   if (prec == TSYLV_FP64) {
     ProfScope ps(ctx, TSYLV_K_APPLY, st);
-    kern::apply_f64(Ah, Bh, Zx, Zy, nullptr, 1.0, 0.0, n, s, (int)p, st);
+    kern::apply_f64(Ah, Bh, Zx, Zy, nullptr, 1.0, 0.0, n, s, (int)p, st,
+                    ctx.tune.get(TSYLV_FP64, n, s, p));
   } else {
     float* Vf = ws.take<float>(N);
     float* Wf = ws.take<float>(N);
@@ -1190,14 +1196,16 @@ int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, co
       kern::convert_f64_bf16(Bh, Bb, p * s * s, st);
       uint16_t* Vt = ws.take<uint16_t>(kern::bf16_vtiled_elems(n, s, (int)p));
       ProfScope ps(ctx, TSYLV_K_APPLY_LOW, st);
-      kern::apply_bf16(Ab, Bb, Vf, Vt, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st);
+      kern::apply_bf16(Ab, Bb, Vf, Vt, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st,
+                       ctx.tune.get(TSYLV_BF16, n, s, p));
     } else {
       float* Af = ws.take<float>(p * n * n);
       float* Bf = ws.take<float>(p * s * s);
       kern::convert_f64_f32(Ah, Af, p * n * n, st);
       kern::convert_f64_f32(Bh, Bf, p * s * s, st);
       ProfScope ps(ctx, TSYLV_K_APPLY_LOW, st);
-      kern::apply_f32(Af, Bf, Vf, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st);
+      kern::apply_f32(Af, Bf, Vf, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st,
+                      ctx.tune.get(TSYLV_FP32, n, s, p));
     }
     kern::convert_f32_f64(Wf, Zy, N, st);
   }

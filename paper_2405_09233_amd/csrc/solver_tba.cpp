@@ -268,6 +268,7 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
   hipStream_t st = ctx.stream;
   Workspace ws(ctx.arena, tba_ws_bytes(n, s, p, m));
   Setup S = setup_fourier(ctx, st, true, ws, n, s, p, A, B, C, X, o.x0_given != 0);
+  const int var64 = ctx.tune.get(TSYLV_FP64, n, s, p);
   TbaWS w;
   w.n = n;
   w.s = s;
@@ -369,7 +370,7 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
       TSYLV_HIP(hipMemcpyAsync(w.R, S.Zc, w.N * sizeof(double), hipMemcpyDeviceToDevice, st));
     } else {
       ProfScope ps(ctx, TSYLV_K_APPLY, st);
-      kern::apply_f64(S.Ah, S.Bh, S.Zx, w.R, S.Zc, -1.0, 1.0, n, s, (int)p, st);
+      kern::apply_f64(S.Ah, S.Bh, S.Zx, w.R, S.Zc, -1.0, 1.0, n, s, (int)p, st, var64);
     }
     info.relres_true = std::sqrt(dev_norm2(ctx, w, w.R)) / cnorm;
     if (info.relres_true <= o.tol) {
@@ -387,7 +388,8 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
       double* W = w.V(j + 1);
       {
         ProfScope ps(ctx, TSYLV_K_APPLY, st);
-        kern::apply_f64(S.Ah, nullptr, w.V(j), W, nullptr, 1.0, 0.0, n, s, (int)p, st);  // A only
+        kern::apply_f64(S.Ah, nullptr, w.V(j), W, nullptr, 1.0, 0.0, n, s, (int)p, st,
+                        var64);  // A only
       }
       // block CGS2: H_{0..j, j} = V^H W (twice), W -= V H
       const kern::PMat Vb{w.basis, ns, n, s, w.ldv};

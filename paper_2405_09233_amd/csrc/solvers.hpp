@@ -36,4 +36,13 @@ int krylov_solve(Ctx& ctx, int method, int64_t n, int64_t s, int64_t p, const do
                  const double* B, const double* C, double* X, const tsylv_opts& o,
                  tsylv_info& info);
 
+// Autotuner (tune.cpp): times every tile variant of the apply at (n, s, p)
+// in precision `prec` (`reps` launches each), stores the fastest in
+// ctx.tune and returns the number of variants; ms_out[v] (v < ms_cap) gets
+// variant v's average launch time.
+int autotune(Ctx& ctx, int64_t n, int64_t s, int64_t p, int prec, int reps, int* best,
+             float* ms_out, int ms_cap);
+void tune_save(const Ctx& ctx, const char* path);
+void tune_load(Ctx& ctx, const char* path);
+
 }  // namespace tsylv

@@ -1,0 +1,171 @@
+// Autotuner of the facewise apply's tile shape (project addition, not in the
+// paper).  For one (precision, n, s, p) it times every tile variant of the
+// apply kernel on operands of that shape carved from the arena, keeps the
+// fastest in the context's table (which every later apply of that shape
+// uses) and reports the times.  The table is saved to and loaded from a
+// small text file, so a tuned choice is measured once per machine.
+#include <cstdio>
+#include <fstream>
+#include <sstream>
+#include <vector>
+
+#include "kernels.hpp"
+#include "runtime.hpp"
+#include "solvers.hpp"
+
+namespace tsylv {
+
+namespace {
+constexpr const char* kTuneHeader = "tsylv-tune 1";
+
+bool prec_ok(int prec) { return prec == TSYLV_FP64 || prec == TSYLV_FP32 || prec == TSYLV_BF16; }
+}  // namespace
+
+int TuneTable::get(int prec, int64_t n, int64_t s, int64_t p) const {
+  std::lock_guard<std::mutex> g(mu_);
+  auto it = m_.find({(int64_t)prec, n, s, p});
+  return it == m_.end() ? -1 : it->second;
+}
+
+void TuneTable::set(int prec, int64_t n, int64_t s, int64_t p, int variant) {
+  if (!prec_ok(prec) || variant < -1 || variant >= kern::apply_variant_count(prec))
+    throw Error(TSYLV_EINVAL, "tune: bad precision or variant");
+  std::lock_guard<std::mutex> g(mu_);
+  if (variant < 0)
+    m_.erase({(int64_t)prec, n, s, p});
+  else
+    m_[{(int64_t)prec, n, s, p}] = variant;
+}
+
+size_t TuneTable::size() const {
+  std::lock_guard<std::mutex> g(mu_);
+  return m_.size();
+}
+
+std::string TuneTable::serialize() const {
+  std::lock_guard<std::mutex> g(mu_);
+  std::ostringstream o;
+  o << kTuneHeader << "\n";
+  for (auto& kv : m_)
+    o << kv.first[0] << " " << kv.first[1] << " " << kv.first[2] << " " << kv.first[3] << " "
+      << kv.second << "\n";
+  return o.str();
+}
+
+void TuneTable::parse(const std::string& text) {
+  std::istringstream in(text);
+  std::string line;
+  if (!std::getline(in, line) || line != kTuneHeader)
+    throw Error(TSYLV_EINVAL, "tune file: bad header");
+  std::vector<std::pair<std::array<int64_t, 4>, int>> add;
+  while (std::getline(in, line)) {
+    if (line.empty()) continue;
+    std::istringstream ls(line);
+    int64_t prec, n, s, p;
+    int v;
+    std::string rest;
+    if (!(ls >> prec >> n >> s >> p >> v) || (ls >> rest) || !prec_ok((int)prec) || n <= 0 ||
+        s <= 0 || p <= 0 || v < 0 || v >= kern::apply_variant_count((int)prec))
+      throw Error(TSYLV_EINVAL, "tune file: bad entry");
+    add.push_back({{prec, n, s, p}, v});
+  }
+  std::lock_guard<std::mutex> g(mu_);
+  for (auto& e : add) m_[e.first] = e.second;
+}
+
+int autotune(Ctx& ctx, int64_t n, int64_t s, int64_t p, int prec, int reps, int* best,
+             float* ms_out, int ms_cap) {
+  const int nv = kern::apply_variant_count(prec);
+  const int64_t N = n * s * p;
+  hipStream_t st = ctx.stream;
+  // operands of the shape: operator planes, B planes, input and output vectors
+  int64_t ea, eb, ev;
+  size_t el;
+  if (prec == TSYLV_BF16) {
+    ea = kern::bf16_tiled_elems(n, (int)p);
+    eb = p * s * s;
+    ev = kern::bf16_vtiled_elems(n, s, (int)p);
+    el = 2;
+  } else {
+    ea = p * n * n;
+    eb = p * s * s;
+    ev = N;
+    el = prec == TSYLV_FP64 ? 8 : 4;
+  }
+  Workspace ws(ctx.arena, Workspace::bytes_for(ea, el) + Workspace::bytes_for(eb, el) +
+                              2 * Workspace::bytes_for(ev, el));
+  char* A = ws.take<char>(ea * el);
+  char* B = ws.take<char>(eb * el);
+  char* V = ws.take<char>(ev * el);
+  char* W = ws.take<char>(ev * el);
+  // Normal, nonzero values (0.0078 in every format) so the timing sees the
+  // data path of real operands; the results are discarded.
+  const unsigned pat = prec == TSYLV_BF16 ? 0x3C003C00u : (prec == TSYLV_FP32 ? 0x3C000000u
+                                                                              : 0x3F800000u);
+  for (auto buf : {std::make_pair(A, ea), std::make_pair(B, eb), std::make_pair(V, ev)})
+    TSYLV_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(buf.first), pat,
+                                (size_t)buf.second * el / 4, st));
+  auto launch = [&](int v) {
+    if (prec == TSYLV_FP64)
+      kern::apply_f64(reinterpret_cast<double*>(A), reinterpret_cast<double*>(B),
+                      reinterpret_cast<double*>(V), reinterpret_cast<double*>(W), nullptr, 1.0,
+                      0.0, n, s, (int)p, st, v);
+    else if (prec == TSYLV_FP32)
+      kern::apply_f32(reinterpret_cast<float*>(A), reinterpret_cast<float*>(B),
+                      reinterpret_cast<float*>(V), reinterpret_cast<float*>(W), nullptr, 1.0, 0.0,
+                      n, s, (int)p, st, v);
+    else
+      kern::apply_bf16_tiled(reinterpret_cast<uint16_t*>(A), reinterpret_cast<uint16_t*>(B),
+                             reinterpret_cast<kern::bf16t*>(V), reinterpret_cast<kern::bf16t*>(W),
+                             1.0, n, s, (int)p, st, v);
+  };
+  hipEvent_t e0, e1;
+  TSYLV_HIP(hipEventCreate(&e0));
+  TSYLV_HIP(hipEventCreate(&e1));
+  int bi = -1;
+  float bms = 0.0f;
+  try {
+    for (int v = 0; v < nv; ++v) {
+      launch(v);  // warm-up (code object load, caches)
+      TSYLV_HIP(hipEventRecord(e0, st));
+      for (int r = 0; r < reps; ++r) launch(v);
+      TSYLV_HIP(hipEventRecord(e1, st));
+      TSYLV_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      TSYLV_HIP(hipEventElapsedTime(&ms, e0, e1));
+      ms /= (float)reps;
+      if (ms_out && v < ms_cap) ms_out[v] = ms;
+      if (bi < 0 || ms < bms) {
+        bi = v;
+        bms = ms;
+      }
+    }
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  TSYLV_HIP(hipEventDestroy(e0));
+  TSYLV_HIP(hipEventDestroy(e1));
+  ctx.tune.set(prec, n, s, p, bi);
+  if (best) *best = bi;
+  return nv;
+}
+
+void tune_save(const Ctx& ctx, const char* path) {
+  std::ofstream f(path, std::ios::trunc);
+  if (!f) throw Error(TSYLV_EINVAL, "tune: cannot write the file");
+  f << ctx.tune.serialize();
+  if (!f) throw Error(TSYLV_EINVAL, "tune: write failed");
+}
+
+void tune_load(Ctx& ctx, const char* path) {
+  std::ifstream f(path);
+  if (!f) throw Error(TSYLV_EINVAL, "tune: cannot read the file");
+  std::stringstream ss;
+  ss << f.rdbuf();
+  ctx.tune.parse(ss.str());
+}
+
+}  // namespace tsylv

@@ -81,6 +81,17 @@ _SIGS = {
     "tsylv_generate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64,
                                       ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "tsylv_apply_variants": (ctypes.c_int, [ctypes.c_int]),
+    "tsylv_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float),
+                                      ctypes.c_int]),
+    "tsylv_tune_set": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                                      ctypes.c_int64, ctypes.c_int64, ctypes.c_int]),
+    "tsylv_tune_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                                      ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_int)]),
+    "tsylv_tune_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "tsylv_tune_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "tsylv_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Info)]),
     "tsylv_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "tsylv_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -152,6 +163,14 @@ def empty_device(shape, device="cuda"):
 
 def to_host(t):
     return np.asfortranarray(np.transpose(t.permute(2, 1, 0).cpu().numpy(), (2, 1, 0)))
+
+
+def apply_variants(prec):
+    """Number of tile variants of the apply kernel in precision `prec`."""
+    n = load().tsylv_apply_variants(prec)
+    if n < 0:
+        raise TsylvError(n, "tsylv_apply_variants")
+    return n
 
 
 def _ptr(t):
@@ -272,6 +291,39 @@ class Context:
         if st != 0:
             raise TsylvError(st, "tsylv_submit")
         return ticket.value
+
+    def autotune(self, n, s, p, prec=FP64, reps=5):
+        """Time every tile variant of the apply at (n, s, p); the fastest is
+        used from now on.  Returns (best variant, [ms per variant])."""
+        nv = apply_variants(prec)
+        ms = (ctypes.c_float * nv)()
+        best = ctypes.c_int(-1)
+        st = load().tsylv_autotune(self.handle, n, s, p, prec, reps, ctypes.byref(best), ms, nv)
+        if st != 0:
+            raise TsylvError(st, "tsylv_autotune")
+        return best.value, [float(x) for x in ms]
+
+    def tune_set(self, n, s, p, prec, variant):
+        st = load().tsylv_tune_set(self.handle, prec, n, s, p, variant)
+        if st != 0:
+            raise TsylvError(st, "tsylv_tune_set")
+
+    def tune_get(self, n, s, p, prec):
+        v = ctypes.c_int(-1)
+        st = load().tsylv_tune_get(self.handle, prec, n, s, p, ctypes.byref(v))
+        if st != 0:
+            raise TsylvError(st, "tsylv_tune_get")
+        return v.value
+
+    def tune_save(self, path):
+        st = load().tsylv_tune_save(self.handle, os.fsencode(path))
+        if st != 0:
+            raise TsylvError(st, "tsylv_tune_save")
+
+    def tune_load(self, path):
+        st = load().tsylv_tune_load(self.handle, os.fsencode(path))
+        if st != 0:
+            raise TsylvError(st, "tsylv_tune_load")
 
     def profile(self, enable=True, families=None):
         """Start (every family, or the kernel ids in `families`) or stop timing."""
