@@ -431,6 +431,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the tiny and serving runs")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=6.0)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default apply tiles")
     ap.add_argument("--no-serve-full", action="store_true",
                     help="skip the batch at the full serving sizes")
     ap.add_argument("--serve-only", action="store_true",
@@ -492,6 +493,19 @@ def main():
     paths = [x for x in args.paths.split(",") if x]
     need = max(tsylv.workspace_bytes(method[x], n, s, p, path_opts[x]) for x in paths)
     ctx = tsylv.Context(need + (64 << 20), device=0)
+    # tile shapes of the apply picked by the autotuner for this shape (every
+    # later apply of the shape on the context uses the choice)
+    tuned = {}
+    if not args.no_tune:
+        precs = [("fp64", tsylv.FP64)]
+        if "mixed" in paths:
+            precs.append(("fp32", tsylv.FP32))
+        if "bf16" in paths:
+            precs.append(("bf16", tsylv.BF16))
+        for pname, prec in precs:
+            bv, ms = ctx.autotune(n, s, p, prec=prec, reps=5)
+            tuned[pname] = {"best": bv, "ms": ms}
+            log("autotune %s: variant %d (%s ms)" % (pname, bv, ", ".join("%.3f" % x for x in ms)))
     res = {}
     for name in paths:
         # one TBAS solve takes seconds: two timed solves, no warm-up
@@ -557,6 +571,7 @@ def main():
         "bf16_vs_fp64": (res["bf16"]["solves_per_s"] / res["fp64"]["solves_per_s"]
                          if "bf16" in res and "fp64" in res else None),
         "roofline": roofline,
+        "autotune": tuned,
     }
     ctx.close()
     if not args.no_extra:
