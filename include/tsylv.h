@@ -157,6 +157,34 @@ int tsylv_tbs(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A,
               const double* B, const double* C, double* X,
               const tsylv_opts* opts, tsylv_info* info);
 
+/* Batched solves (a project addition for workloads of many independent
+ * instances of uneven size; the method per instance is Algorithm 3 --
+ * restarted tGMRES(m) -- with the Arnoldi process of Algorithm 2 done as
+ * classical Gram-Schmidt applied twice and the Givens update of section
+ * 3.3).  All instances advance in lockstep: every kernel launch of an
+ * Arnoldi step serves the whole batch (work items over the instances'
+ * tiles and vector chunks), the Givens rotations and the stop tests run on
+ * the device, and one step is captured as a HIP graph and replayed, so the
+ * host synchronises a few times per cycle rather than per instance and
+ * step.  Instances stop individually (their work items turn idle).
+ * opts: FP64 only (refine = 0), 1 <= m <= 63; tol, max_cycles and x0_given
+ * as for tsylv_gmres (opts may be NULL: m = 30).  Each instance's result
+ * does not depend on the rest of the batch (it is bitwise the same alone).
+ * infos[i] receives instance i's record (seconds: the whole batch).
+ * Returns TSYLV_OK when every instance converged, TSYLV_NOT_CONVERGED when
+ * some did not (see infos), or an error for the batch. */
+typedef struct {
+  int64_t n, s, p;
+  const double* A;  /* device pointers, layout as above */
+  const double* B;
+  const double* C;
+  double* X;        /* output (and X0 when opts.x0_given) */
+} tsylv_problem;
+
+size_t tsylv_batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_opts* opts);
+int tsylv_gmres_batch(tsylv_ctx* ctx, int count, const tsylv_problem* probs,
+                      const tsylv_opts* opts, tsylv_info* infos);
+
 /* Synthetic instances drawn on the device (a project addition for serving
  * workloads; not in the paper).  Writes the dense instance of `seed`:
  *   A = 2/sqrt(n p) Z_A + 4 I,  B = 2/sqrt(s p) Z_B - 4 I  (the identity on

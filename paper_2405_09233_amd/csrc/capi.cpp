@@ -1,4 +1,5 @@
 // extern "C" boundary: argument checks, context handling, error mapping.
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -224,6 +225,42 @@ int tsylv_tba(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A, 
   });
   inf.status = st;
   return st;
+}
+
+static bool batch_ok(int count, const tsylv_problem* probs, const tsylv_opts& o) {
+  if (count < 1 || count > 65536 || !probs) return false;
+  if (o.refine || o.m < 1 || o.m > kern::kBatchMaxM || !opts_ok(o) || o.res_hist) return false;
+  int64_t chunks = 0;
+  for (int i = 0; i < count; ++i) {
+    const tsylv_problem& q = probs[i];
+    if (!q.A || !q.B || !q.C || !q.X || !dims_ok(q.n, q.s, q.p)) return false;
+    chunks += (q.n * q.s * q.p + kern::kBatchChunk - 1) / kern::kBatchChunk;
+  }
+  return chunks < (int64_t(1) << 30);
+}
+
+size_t tsylv_batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_opts* opts) {
+  tsylv_opts o;
+  tsylv_default_opts(TSYLV_METHOD_GMRES, &o);
+  if (opts) o = *opts;
+  if (!batch_ok(count, probs, o)) return 0;
+  return batch_workspace_bytes(count, probs, o);
+}
+
+int tsylv_gmres_batch(tsylv_ctx* ctx, int count, const tsylv_problem* probs,
+                      const tsylv_opts* opts, tsylv_info* infos) {
+  if (!ctx || !infos) return TSYLV_EINVAL;
+  tsylv_opts o;
+  tsylv_default_opts(TSYLV_METHOD_GMRES, &o);
+  if (opts) o = *opts;
+  if (!batch_ok(count, probs, o)) return TSYLV_EINVAL;
+  const char* g = std::getenv("TSYLV_BATCH_GRAPH");
+  const bool use_graph = !(g && g[0] == '0');
+  return guarded([&]() {
+    std::lock_guard<std::mutex> lk(ctx->c.sync_mu);
+    set_device(ctx);
+    return gmres_batch(ctx->c, count, probs, o, infos, use_graph);
+  });
 }
 
 int tsylv_generate(tsylv_ctx* ctx, uint64_t seed, int64_t n, int64_t s, int64_t p, double* A,

@@ -220,5 +220,85 @@ void zgemm(const PMat& A, bool conjA, const PMat& B, double* C, int64_t planeC, 
            int64_t M, int64_t N, int64_t K, double alpha, double beta, int p, double* partial,
            hipStream_t st);
 
+
+// ---- batched lockstep tGMRES (many independent instances per launch) ----
+//
+// Every launch serves all instances of a batch: blockIdx.x runs over the
+// concatenated work of the instances (apply tiles, or vector chunks of
+// kBatchChunk elements), each block finds its instance by binary search over
+// the instances' first work index, and the step index j is read from device
+// memory, so one captured step replays for every j.  An instance's
+// arithmetic (its chunks, tiles and fixed-order reductions) does not depend
+// on the other instances.
+
+constexpr int64_t kBatchChunk = 8192;  // elements per vector work item
+constexpr int kBatchMaxM = 63;         // restart length limit (H columns)
+
+struct BatchItem {
+  const double* Ah;
+  const double* Bh;
+  double* V;          // basis: m + 1 vectors at stride ldv
+  double* W;          // work vector of the step
+  const double* Zc;   // orthonormal planes of C
+  double* Zx;         // orthonormal planes of X (the iterate)
+  double* H;          // (m + 1) x m, column-major, Givens-rotated in place
+  double* cs;         // rotations (m)
+  double* sn;
+  double* g;          // rotated right-hand side (m + 1)
+  double* y;          // least-squares solution of the cycle (m)
+  double* coef;       // CGS coefficients of the current pass (m + 1)
+  int64_t n, s, N, ldv;
+  int p;
+  int chunk0, nchunks;  // vector work items
+};
+
+struct BatchState {
+  int active;   // stepping in the current cycle
+  int done;     // converged or out of cycles: no more work
+  int jdone;    // steps taken in the current cycle
+  int status;   // tsylv_status once done
+  int steps, cycles;
+  int pad0, pad1;
+  double beta;   // ||R|| at the start of the cycle
+  double cnorm;  // ||C||
+  double hn;     // ||W|| after the Gram-Schmidt passes of the step
+  double est;    // residual estimate |g_{j+1}|
+};
+
+// Apply tiles of one tile variant over a subset of the batch, in order of
+// their first tile.
+struct BatchApplyRef {
+  int item, tile0, nrt, nct;
+};
+
+enum BatchMode {
+  BM_STEP = 0,      // apply: W = M(V_j); dots: V_0..V_j . W; update: W -= V c
+  BM_WNORM = 1,     // dots: W . W; reduce: ||W||, Givens, stop test
+  BM_RESID = 2,     // apply: V_0 = Zc - M(Zx); dots: V_0 . V_0; reduce: restart
+  BM_CNORM = 3,     // dots: Zc . Zc; reduce: ||C||
+  BM_PASS2 = 4,     // reduce: second CGS pass (adds to H)
+  BM_XUPDATE = 5,   // update: Zx += V y
+  BM_RESID0 = 6,    // reduce: restart test on the initial residual (no cycle counted)
+};
+
+int batch_apply_variant(int64_t s);
+// Tiles of one instance under a batch tile variant (row and column tiles out).
+int batch_apply_tiles(int variant, int64_t n, int64_t s, int p, int* nrt, int* nct);
+void batch_apply(const BatchItem* items, const BatchApplyRef* refs, int nref, int total_tiles,
+                 int variant, BatchState* st, const int* jp, int mode, hipStream_t st_);
+void batch_dots(const BatchItem* items, int count, int total_chunks, const BatchState* st,
+                const int* jp, double* part, int ldp, int mode, hipStream_t s);
+void batch_reduce(const BatchItem* items, int count, BatchState* st, const int* jp,
+                  const double* part, int ldp, int mode, int m, double tol, int max_cycles,
+                  hipStream_t s);
+void batch_update(const BatchItem* items, int count, int total_chunks, const BatchState* st,
+                  const int* jp, int mode, hipStream_t s);
+void batch_scale(const BatchItem* items, int count, int total_chunks, const BatchState* st,
+                 const int* jp, int mode, hipStream_t s);
+void batch_backsub(const BatchItem* items, int count, const BatchState* st, int m,
+                   hipStream_t s);
+void batch_set_j(int* jp, int value, hipStream_t s);
+void batch_advance(int* jp, hipStream_t s);
+
 }  // namespace kern
 }  // namespace tsylv

@@ -354,6 +354,62 @@ int default_variant(int64_t s) {
   return std::is_same<Tag, float>::value ? 3 : 2;
 }
 
+// Batched apply: the tiles of many instances in one launch (their first
+// tiles in refs, ascending).  STEP: W = M(V_j) for the stepping instances;
+// RESID: V_0 = Zc - M(Zx) for the instances not done.
+// (The mode is a template parameter, as in the batched vector kernels.)
+template <int TM, int TN, int RB, int CB, int MODE>
+__global__ __launch_bounds__(NT) void apply_batch_kernel(const BatchItem* __restrict__ items,
+                                                         const BatchApplyRef* __restrict__ refs,
+                                                         int nref, int total,
+                                                         const BatchState* __restrict__ st,
+                                                         const int* __restrict__ jp) {
+  using M = Mma<double>;
+  using L = typename M::L;
+  constexpr int TK = M::TK;
+  __shared__ L As[2][TK][TM + M::PADA];
+  __shared__ L Bs[2][TK][TN + M::PADB];
+  const int t = xcd_tile(blockIdx.x, total);
+  int lo = 0, hi = nref - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (refs[mid].tile0 <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchApplyRef r = refs[lo];
+  const BatchItem& it = items[r.item];
+  const bool on = (MODE == BM_STEP) ? st[r.item].active != 0 : st[r.item].done == 0;
+  if (!on) return;
+  const int lt = t - r.tile0;
+  const int ct = lt % r.nct;
+  const int rt = (lt / r.nct) % r.nrt;
+  const int k = lt / (r.nct * r.nrt);
+  ApplyArgs<double> a{};
+  a.Ah = it.Ah;
+  a.Bh = it.Bh;
+  a.n = it.n;
+  a.s = it.s;
+  a.p = it.p;
+  a.useB = 1;
+  if constexpr (MODE == BM_STEP) {
+    a.V = it.V + (int64_t)(*jp) * it.ldv;
+    a.out = it.W;
+    a.Y = nullptr;
+    a.alpha = 1.0;
+    a.beta = 0.0;
+  } else {
+    a.V = it.Zx;
+    a.out = it.V;
+    a.Y = it.Zc;
+    a.alpha = -1.0;
+    a.beta = 1.0;
+  }
+  if ((k == 0) || (2 * k == a.p))
+    apply_tile<double, TM, TN, RB, CB, TK, false>(a, k, rt, ct, As, Bs);
+  else
+    apply_tile<double, TM, TN, RB, CB, TK, true>(a, k, rt, ct, As, Bs);
+}
+
 template <typename Tag>
 void apply_any(const typename Store<Tag>::T* Ah, const typename Store<Tag>::T* Bh,
                const typename Mma<Tag>::TV* V, typename Mma<Tag>::TV* out,
@@ -379,6 +435,41 @@ void apply_f32(const float* Ah, const float* Bh, const float* V, float* out, con
                double alpha, double beta, int64_t n, int64_t s, int p, hipStream_t st,
                int variant) {
   apply_any<float>(Ah, Bh, V, out, Y, alpha, beta, n, s, p, Bh != nullptr, variant, st);
+}
+
+template <int TM, int TN, int RB, int CB>
+static void launch_batch(const BatchItem* items, const BatchApplyRef* refs, int nref, int total,
+                         BatchState* st, const int* jp, int mode, hipStream_t s) {
+  if (mode == BM_STEP)
+    hipLaunchKernelGGL((apply_batch_kernel<TM, TN, RB, CB, BM_STEP>), dim3(total), dim3(NT), 0, s,
+                       items, refs, nref, total, st, jp);
+  else if (mode == BM_RESID)
+    hipLaunchKernelGGL((apply_batch_kernel<TM, TN, RB, CB, BM_RESID>), dim3(total), dim3(NT), 0,
+                       s, items, refs, nref, total, st, jp);
+  else
+    throw Error(TSYLV_EINVAL, "batch apply: mode");
+}
+
+void batch_apply(const BatchItem* items, const BatchApplyRef* refs, int nref, int total_tiles,
+                 int variant, BatchState* st, const int* jp, int mode, hipStream_t st_) {
+  if (nref <= 0 || total_tiles <= 0) return;
+  switch (variant) {
+    case 0: launch_batch<128, 16, 2, 1>(items, refs, nref, total_tiles, st, jp, mode, st_); break;
+    case 1: launch_batch<64, 32, 1, 2>(items, refs, nref, total_tiles, st, jp, mode, st_); break;
+    case 2: launch_batch<32, 64, 1, 2>(items, refs, nref, total_tiles, st, jp, mode, st_); break;
+    default: throw Error(TSYLV_EINVAL, "batch apply: unsupported tile variant");
+  }
+  TSYLV_LAUNCH_CHECK();
+}
+
+// Tile shape of an instance in a batched apply: the default of its s, so an
+// instance computes the same bits in any batch.
+int batch_apply_variant(int64_t s) { return default_variant<double>(s); }
+int batch_apply_tiles(int variant, int64_t n, int64_t s, int p, int* nrt, int* nct) {
+  static const int tm[3] = {128, 64, 32}, tn[3] = {16, 32, 64};
+  *nrt = (int)((n + tm[variant] - 1) / tm[variant]);
+  *nct = (int)((s + tn[variant] - 1) / tn[variant]);
+  return num_slices(p) * *nrt * *nct;
 }
 
 int apply_variant_count(int prec) { return prec == TSYLV_BF16 ? 3 : 6; }

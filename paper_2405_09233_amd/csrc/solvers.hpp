@@ -36,6 +36,11 @@ int krylov_solve(Ctx& ctx, int method, int64_t n, int64_t s, int64_t p, const do
                  const double* B, const double* C, double* X, const tsylv_opts& o,
                  tsylv_info& info);
 
+// Batched lockstep tGMRES (batch.cpp): FP64, restart length o.m <= 63.
+size_t batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o);
+int gmres_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts& o,
+                tsylv_info* infos, bool use_graph);
+
 // Autotuner (tune.cpp): times every tile variant of the apply at (n, s, p)
 // in precision `prec` (`reps` launches each), stores the fastest in
 // ctx.tune and returns the number of variants; ms_out[v] (v < ms_cap) gets

@@ -59,6 +59,12 @@ class Request(ctypes.Structure):
                 ("gen_seed", ctypes.c_uint64)]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("s", ctypes.c_int64), ("p", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("X", ctypes.c_void_p)]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -81,6 +87,10 @@ _SIGS = {
     "tsylv_generate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64,
                                       ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "tsylv_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_void_p,
+                                                      ctypes.POINTER(Opts)]),
+    "tsylv_gmres_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.POINTER(Opts), ctypes.c_void_p]),
     "tsylv_apply_variants": (ctypes.c_int, [ctypes.c_int]),
     "tsylv_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.c_int64, ctypes.c_int, ctypes.c_int,
@@ -258,6 +268,33 @@ class Context:
 
     def tbs(self, A, B, C, X=None, opts=None, **kw):
         return self._solve("tsylv_tbs", A, B, C, X, opts, **kw)
+
+    @staticmethod
+    def _problems(items):
+        probs = (Problem * len(items))()
+        for k, (A, B, C, X) in enumerate(items):
+            n, _, p = A.shape
+            probs[k].n, probs[k].s, probs[k].p = n, B.shape[0], p
+            probs[k].A, probs[k].B, probs[k].C, probs[k].X = (_ptr(t).value for t in (A, B, C, X))
+        return probs
+
+    def gmres_batch(self, items, opts=None, raise_on_error=True, **kw):
+        """Batched lockstep tGMRES over `items`, a list of (A, B, C, X)
+        device tensors (X receives the solution).  Returns the list of
+        per-instance Info records."""
+        probs = self._problems(items)
+        o = opts if opts is not None else default_opts(GMRES, **kw)
+        infos = (Info * len(items))()
+        st = load().tsylv_gmres_batch(self.handle, len(items), probs, ctypes.byref(o), infos)
+        if st < 0 and raise_on_error:
+            raise TsylvError(st, "tsylv_gmres_batch")
+        return list(infos)
+
+    @staticmethod
+    def batch_workspace_bytes(items, opts=None, **kw):
+        o = opts if opts is not None else default_opts(GMRES, **kw)
+        return load().tsylv_batch_workspace_bytes(len(items), Context._problems(items),
+                                                  ctypes.byref(o))
 
     def generate(self, seed, n, s, p, device=None):
         """The synthetic instance of `seed` (tsylv_generate) as device

@@ -42,9 +42,11 @@ int main(void) {
   printf("tsylv_opts %zu\n", sizeof(tsylv_opts));
   printf("tsylv_info %zu\n", sizeof(tsylv_info));
   printf("tsylv_request %zu\n", sizeof(tsylv_request));
+  printf("tsylv_problem %zu\n", sizeof(tsylv_problem));
   F(tsylv_opts, tol) F(tsylv_opts, inner_tol) F(tsylv_opts, res_hist) F(tsylv_opts, res_hist_cap)
   F(tsylv_info, relres_true) F(tsylv_info, seconds) F(tsylv_info, fom_fallback)
   F(tsylv_request, n) F(tsylv_request, A) F(tsylv_request, X) F(tsylv_request, opts)
+  F(tsylv_request, gen_seed) F(tsylv_problem, p) F(tsylv_problem, A) F(tsylv_problem, X)
   return 0;
 }
 '''
@@ -58,11 +60,12 @@ int main(void) {
     assert got["tsylv_opts"] == ctypes.sizeof(tsylv.Opts)
     assert got["tsylv_info"] == ctypes.sizeof(tsylv.Info)
     assert got["tsylv_request"] == ctypes.sizeof(tsylv.Request)
+    assert got["tsylv_problem"] == ctypes.sizeof(tsylv.Problem)
     for key, val in got.items():
         if "." in key:
             sname, field = key.split(".")
             cls = {"tsylv_opts": tsylv.Opts, "tsylv_info": tsylv.Info,
-                   "tsylv_request": tsylv.Request}[sname]
+                   "tsylv_request": tsylv.Request, "tsylv_problem": tsylv.Problem}[sname]
             assert getattr(cls, field).offset == val, key
 
 
@@ -75,6 +78,26 @@ def test_default_opts_and_workspace_query():
     assert b >= 8 * (p * n * n + (o.m + 3) * n * s * p)
     assert tsylv.workspace_bytes(tsylv.GMRES, 0, s, p, o) == 0
     assert tsylv.workspace_bytes(tsylv.APPLY, 8, 6, 4, None) > 0
+
+
+def test_batch_workspace_query():
+    """The batch plan's byte count without a device: each instance's
+    Fourier setup and basis plus the shared tables; malformed batches give 0."""
+    probs = (tsylv.Problem * 2)()
+    for k, (n, s, p) in enumerate([(100, 8, 5), (40, 3, 2)]):
+        probs[k].n, probs[k].s, probs[k].p = n, s, p
+        probs[k].A = probs[k].B = probs[k].C = probs[k].X = 4096  # never dereferenced
+    o = tsylv.default_opts(tsylv.GMRES, m=20)
+    lib = tsylv.load()
+    b = lib.tsylv_batch_workspace_bytes(2, probs, ctypes.byref(o))
+    floor = sum(8 * (p * n * n + p * s * s + 3 * p * p + (o.m + 4) * n * s * p)
+                for n, s, p in [(100, 8, 5), (40, 3, 2)])
+    assert b >= floor
+    assert lib.tsylv_batch_workspace_bytes(0, probs, ctypes.byref(o)) == 0
+    o.m = 64  # beyond the batch's restart limit
+    assert lib.tsylv_batch_workspace_bytes(2, probs, ctypes.byref(o)) == 0
+    o = tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.FP32)
+    assert lib.tsylv_batch_workspace_bytes(2, probs, ctypes.byref(o)) == 0
 
 
 def test_strerror():
