@@ -340,6 +340,90 @@ def serving_full(tsylv, rate=40.0, duration=10.0, nbatch=128, seed=50):
     return out
 
 
+def batched_shapes(kind, count, seed):
+    """Instance sizes of the batched workloads (numpy default_rng(seed)):
+    'large' n = 32 round(U[256, 2048] / 32), s U{16..128}, p {8, 16, 32};
+    'small' n U{32..256}, s U{2..16}, p U{2..8}."""
+    rng = np.random.default_rng(seed)
+    shapes = []
+    for _ in range(count):
+        if kind == "large":
+            shapes.append((int(32 * round(rng.uniform(256, 2048) / 32)),
+                           int(rng.integers(16, 129)), int(rng.choice([8, 16, 32]))))
+        else:
+            shapes.append((int(rng.integers(32, 257)), int(rng.integers(2, 17)),
+                           int(rng.integers(2, 9))))
+    return shapes
+
+
+def batched(tsylv, kind="large", count=64, m=30, seed=40):
+    """A batched workload: `count` independent instances of the sizes of
+    batched_shapes(kind), instance i the dense p-scaled-noise instance of
+    Philox seed 4000 + i drawn on the device (tsylv_generate); FP64
+    tGMRES(m) to 1e-8.  Timed three ways on the same instances: the batched
+    lockstep solve (one launch per step stage for all), the serving loop (all
+    submitted at once, up to 8 overlapping solves), and one synchronous solve
+    after another."""
+    import torch
+    shapes = batched_shapes(kind, count, seed)
+    opts = tsylv.default_opts(tsylv.GMRES, m=m, tol=1e-8, max_cycles=500)
+    ctx0 = tsylv.Context(64 << 20, device=0)
+    items = []
+    for k, (n, s, p) in enumerate(shapes):
+        A, B, C = ctx0.generate(4000 + k, n, s, p)
+        items.append((A, B, C, torch.zeros_like(C)))
+    ctx0.close()
+    need = tsylv.Context.batch_workspace_bytes(items, opts=opts)
+    ctx = tsylv.Context(need + (256 << 20), device=0)
+    sizes = {"large": "n = 32 round(U[256, 2048] / 32), s U{16..128}, p {8, 16, 32}",
+             "small": "n U{32..256}, s U{2..16}, p U{2..8}"}[kind]
+    out = {"workload": "%d instances, %s (rng seed %d), dense p-scaled-noise instances drawn "
+                       "on the device (Philox seeds 4000 + i), FP64 tGMRES(%d) to 1e-8; A %.2f GB "
+                       "in total" % (count, sizes, seed, m,
+                                     sum(n * n * p * 8 for n, s, p in shapes) / 1e9)}
+    # warm-up on two instances (code objects, graph path)
+    ctx.gmres_batch(items[:2], opts=opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = ctx.gmres_batch(items, opts=opts, raise_on_error=False)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    okb = all(i.status == 0 and i.relres_true <= 1e-8 for i in infos)
+    out["batched"] = {"solves_per_s": count / tb, "seconds": tb, "valid": bool(okb),
+                      "steps_total": int(sum(i.steps for i in infos))}
+    log("batched %s: lockstep batch %.3f s (%.1f solves/s, valid %s)"
+        % (kind, tb, count / tb, okb))
+    ctx.close()
+    ctx = tsylv.Context(max(tsylv.workspace_bytes(tsylv.GMRES, n, s, p, opts)
+                            for n, s, p in shapes) * 8 + (256 << 20), device=0)
+    t0 = time.perf_counter()
+    tickets = [ctx.submit(A, B, C, X, method=tsylv.GMRES, opts=opts) for A, B, C, X in items]
+    oks = True
+    for t in tickets:
+        while True:
+            st, info = ctx.poll(t)
+            if st != 2:
+                break
+            time.sleep(0.0002)
+        oks = oks and st == 0 and info.relres_true <= 1e-8
+    ts = time.perf_counter() - t0
+    out["serving_loop"] = {"solves_per_s": count / ts, "seconds": ts, "valid": bool(oks)}
+    log("batched %s: serving loop %.3f s (%.1f solves/s)" % (kind, ts, count / ts))
+    t0 = time.perf_counter()
+    okq = True
+    for A, B, C, X in items:
+        _, info = ctx.gmres(A, B, C, X=X, opts=opts)
+        okq = okq and info.status == 0 and info.relres_true <= 1e-8
+    torch.cuda.synchronize()
+    tq = time.perf_counter() - t0
+    ctx.close()
+    out["sequential"] = {"solves_per_s": count / tq, "seconds": tq, "valid": bool(okq)}
+    log("batched %s: one after another %.3f s (%.1f solves/s)" % (kind, tq, count / tq))
+    out["batched_vs_sequential"] = tq / tb
+    out["batched_vs_serving"] = ts / tb
+    return out
+
+
 def measured_traffic(path, shape, tiled):
     """HBM bytes per apply call from the committed counter summary, or None
     for another path or shape, for the FP32-vector form of the BF16 path, or
@@ -432,6 +516,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--no-tune", action="store_true", help="keep the default apply tiles")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
+    ap.add_argument("--batched-only", action="store_true", help="run only the batched workload")
     ap.add_argument("--no-serve-full", action="store_true",
                     help="skip the batch at the full serving sizes")
     ap.add_argument("--serve-only", action="store_true",
@@ -462,6 +548,11 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 x %d MiB" % args.copy_calib_mib)
         del src, dst
+
+    if args.batched_only:
+        print(json.dumps({"batched": {"large": batched(tsylv, "large", 64),
+                                      "small": batched(tsylv, "small", 256)}}), flush=True)
+        return
 
     if args.serve_only:
         out = {"serving": serving(tsylv, workloads, args.serve_rate, args.serve_seconds)}
@@ -579,6 +670,10 @@ def main():
         out["tiny"] = tiny_latency(tsylv, workloads)
         log("serving run ...")
         out["serving"] = serving(tsylv, workloads, args.serve_rate, args.serve_seconds)
+        if not args.no_batched:
+            log("batched workload ...")
+            out["batched"] = {"large": batched(tsylv, "large", 64),
+                              "small": batched(tsylv, "small", 256)}
         if not args.no_serve_full:
             log("serving at full sizes ...")
             out["serving"]["full_sizes"] = serving_full(tsylv)

@@ -8,8 +8,10 @@
 // Hessenberg matrix, rotations) on the device.  One Arnoldi step of the whole
 // batch is a fixed sequence of launches, each covering every instance:
 //   apply (one launch per tile variant present)  W = M(V_j)
-//   dots / reduce / update, twice                W -= V (V^T W)
-//   dots / reduce                                ||W||, Givens, stop test
+//   dots / reduce / update                       W -= V (V^T W), and ||W||^2
+//   dots / reduce / update, where needed         the same again (second pass)
+//   dots / reduce                                ||W|| (second-pass instances),
+//                                                Givens, stop test
 //   scale                                        V_{j+1} = W / ||W||
 //   advance                                      j += 1 (device counter)
 // Since j lives in device memory, the step is captured once as a HIP graph
@@ -62,7 +64,7 @@ size_t batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_
   }
   b += Workspace::bytes_for((int64_t)count, sizeof(kern::BatchItem)) +
        Workspace::bytes_for((int64_t)count, sizeof(kern::BatchState)) +
-       Workspace::bytes_for(chunks * (o.m + 2), 8) +
+       Workspace::bytes_for(chunks * (o.m + 3), 8) +
        kVariants * Workspace::bytes_for((int64_t)count, sizeof(kern::BatchApplyRef)) +
        Workspace::bytes_for(1, sizeof(int));
   return b;
@@ -76,7 +78,7 @@ int gmres_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opt
   BatchPlan plan;
   plan.count = count;
   plan.m = m;
-  plan.ldp = m + 2;
+  plan.ldp = m + 3;
 
   // ---- workspace and per-instance setup (Algorithm 1 step 1) ----
   Workspace ws(ctx.arena, batch_workspace_bytes(count, probs, o));
@@ -163,11 +165,12 @@ int gmres_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opt
   auto step = [&](hipStream_t s) {
     apply_all(kern::BM_STEP, s);
     for (int pass = 0; pass < 2; ++pass) {
-      kern::batch_dots(d_items, count, plan.total_chunks, d_state, d_j, d_part, plan.ldp,
-                       kern::BM_STEP, s);
-      kern::batch_reduce(d_items, count, d_state, d_j, d_part, plan.ldp,
-                         pass == 0 ? kern::BM_STEP : kern::BM_PASS2, m, o.tol, o.max_cycles, s);
-      kern::batch_update(d_items, count, plan.total_chunks, d_state, d_j, kern::BM_STEP, s);
+      // the second pass runs only for the instances whose first pass cancelled
+      const int md = pass == 0 ? kern::BM_STEP : kern::BM_PASS2;
+      kern::batch_dots(d_items, count, plan.total_chunks, d_state, d_j, d_part, plan.ldp, md, s);
+      kern::batch_reduce(d_items, count, d_state, d_j, d_part, plan.ldp, md, m, o.tol,
+                         o.max_cycles, s);
+      kern::batch_update(d_items, count, plan.total_chunks, d_state, d_j, md, s);
     }
     kern::batch_dots(d_items, count, plan.total_chunks, d_state, d_j, d_part, plan.ldp,
                      kern::BM_WNORM, s);

@@ -258,11 +258,14 @@ struct BatchState {
   int jdone;    // steps taken in the current cycle
   int status;   // tsylv_status once done
   int steps, cycles;
-  int pad0, pad1;
+  int reorth;    // the current step takes the second Gram-Schmidt pass
+  int pad0;
   double beta;   // ||R|| at the start of the cycle
   double cnorm;  // ||C||
   double hn;     // ||W|| after the Gram-Schmidt passes of the step
   double est;    // residual estimate |g_{j+1}|
+  double mv2;    // ||M(V_j)||^2 of the current step
+  double pad1;
 };
 
 // Apply tiles of one tile variant over a subset of the batch, in order of
@@ -272,11 +275,11 @@ struct BatchApplyRef {
 };
 
 enum BatchMode {
-  BM_STEP = 0,      // apply: W = M(V_j); dots: V_0..V_j . W; update: W -= V c
-  BM_WNORM = 1,     // dots: W . W; reduce: ||W||, Givens, stop test
+  BM_STEP = 0,      // apply: W = M(V_j); dots: V_0..V_j . W and W . W; update: W -= V c
+  BM_WNORM = 1,     // dots: W . W (reorth steps); reduce: ||W||, Givens, stop test
   BM_RESID = 2,     // apply: V_0 = Zc - M(Zx); dots: V_0 . V_0; reduce: restart
   BM_CNORM = 3,     // dots: Zc . Zc; reduce: ||C||
-  BM_PASS2 = 4,     // reduce: second CGS pass (adds to H)
+  BM_PASS2 = 4,     // dots / reduce / update of the second pass (reorth steps only)
   BM_XUPDATE = 5,   // update: Zx += V y
   BM_RESID0 = 6,    // reduce: restart test on the initial residual (no cycle counted)
 };

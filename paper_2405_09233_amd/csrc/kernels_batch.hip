@@ -9,7 +9,11 @@
 // (coalesced: element base + 256 q + thread).  Dot products reduce within a
 // wave by shuffles, across the four waves in a fixed order, and across the
 // chunks of an instance in chunk order (batch_reduce), so an instance's
-// numbers do not depend on the rest of the batch.  The small per-instance
+// numbers do not depend on the rest of the batch.  The second Gram-Schmidt
+// pass is taken only when the first one cancelled more than 1 - 1/sqrt(2) of
+// ||W|| (the criterion of Daniel, Gragg, Kaufman and Stewart, Math. Comp.
+// 1976); otherwise ||W|| after the pass follows from Pythagoras, and the
+// step reads the basis twice instead of four times.  The small per-instance
 // arithmetic (the Givens rotations of section 3.3, the restart test of
 // Algorithm 3, the triangular solve for y) runs in one wave per instance.
 #include "kernels.hpp"
@@ -50,16 +54,21 @@ __global__ __launch_bounds__(kBT) void batch_dots_kernel(const BatchItem* __rest
   const int i = find_chunk_item(items, count, c);
   const BatchItem& it = items[i];
   bool on;
-  if constexpr (MODE == BM_STEP || MODE == BM_WNORM)
+  if constexpr (MODE == BM_STEP)
     on = st[i].active != 0;
+  else if constexpr (MODE == BM_PASS2 || MODE == BM_WNORM)
+    on = st[i].active != 0 && st[i].reorth != 0;
   else if constexpr (MODE == BM_RESID)
     on = st[i].done == 0;
   else
     on = true;
   if (!on) return;
   const double* x;
-  int nv = 1;
+  int nv = 1;  // columns: V_l . x for l < nv - (STEP ? 1 : 0), STEP adds x . x
   if constexpr (MODE == BM_STEP) {
+    x = it.W;
+    nv = *jp + 2;
+  } else if constexpr (MODE == BM_PASS2) {
     x = it.W;
     nv = *jp + 1;
   } else if constexpr (MODE == BM_WNORM) {
@@ -78,9 +87,10 @@ __global__ __launch_bounds__(kBT) void batch_dots_kernel(const BatchItem* __rest
     const int64_t e = base + q * kBT + tid;
     xv[q] = e < end ? x[e] : 0.0;
   }
-  __shared__ double red[kBT / 64][kBatchMaxM + 1];
+  __shared__ double red[kBT / 64][kBatchMaxM + 2];
+  const int nbasis = (MODE == BM_STEP) ? nv - 1 : ((MODE == BM_PASS2) ? nv : 0);
   for (int l = 0; l < nv; ++l) {
-    const double* v = (MODE == BM_STEP) ? it.V + (int64_t)l * it.ldv : x;
+    const double* v = (l < nbasis) ? it.V + (int64_t)l * it.ldv : x;
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
@@ -115,17 +125,19 @@ __global__ __launch_bounds__(64) void batch_reduce_kernel(const BatchItem* __res
   constexpr bool kResid = MODE == BM_RESID || MODE == BM_RESID0;
   constexpr bool kGs = MODE == BM_STEP || MODE == BM_PASS2;
   bool on;
-  if constexpr (kGs || MODE == BM_WNORM)
+  if constexpr (MODE == BM_STEP || MODE == BM_WNORM)
     on = S.active != 0;
+  else if constexpr (MODE == BM_PASS2)
+    on = S.active != 0 && S.reorth != 0;
   else if constexpr (kResid)
     on = S.done == 0;
   else
     on = true;
   if (!on) return;
   const int j = *jp;
-  const int nv = kGs ? j + 1 : 1;
+  const int nv = (MODE == BM_STEP) ? j + 2 : ((MODE == BM_PASS2) ? j + 1 : 1);
   const int lane = threadIdx.x;
-  __shared__ double sums[kBatchMaxM + 1];
+  __shared__ double sums[kBatchMaxM + 2];
   if (lane < nv) {
     double acc = 0.0;
     for (int q = 0; q < it.nchunks; ++q) acc += part[(int64_t)(it.chunk0 + q) * ldp + lane];
@@ -134,10 +146,24 @@ __global__ __launch_bounds__(64) void batch_reduce_kernel(const BatchItem* __res
   __syncthreads();
   const int ldh = m + 1;
   if constexpr (kGs) {
-    if (lane < nv) {
+    if (lane <= j) {
       double* h = it.H + (int64_t)j * ldh;
       h[lane] = (MODE == BM_STEP) ? sums[lane] : h[lane] + sums[lane];
       it.coef[lane] = sums[lane];
+    }
+    if (MODE == BM_STEP && lane == 0) {
+      // ||W - V h||^2 = ||W||^2 - ||h||^2 when V is orthonormal
+      const double ww = sums[j + 1];
+      double hh = 0.0;
+      for (int l = 0; l <= j; ++l) hh += sums[l] * sums[l];
+      const double rem = ww - hh;
+      S.mv2 = ww;
+      if (rem > 0.5 * ww) {
+        S.reorth = 0;
+        S.hn = sqrt(rem);
+      } else {
+        S.reorth = 1;
+      }
     }
     return;
   }
@@ -148,9 +174,8 @@ __global__ __launch_bounds__(64) void batch_reduce_kernel(const BatchItem* __res
   }
   if constexpr (MODE == BM_WNORM) {
     double* h = it.H + (int64_t)j * ldh;
-    const double hn = sqrt(sums[0]);
-    double mv2 = hn * hn;  // ||M(V_j)||^2 = sum h^2 + ||W||^2 (orthogonal parts)
-    for (int l = 0; l <= j; ++l) mv2 += h[l] * h[l];
+    const double hn = S.reorth ? sqrt(sums[0]) : S.hn;
+    const double mv2 = S.mv2;
     h[j + 1] = hn;
     for (int l = 0; l < j; ++l) {
       const double a = h[l], b = h[l + 1];
@@ -209,8 +234,10 @@ __global__ __launch_bounds__(kBT) void batch_update_kernel(const BatchItem* __re
   const int i = find_chunk_item(items, count, c);
   const BatchItem& it = items[i];
   const BatchState& S = st[i];
-  constexpr bool kStep = MODE == BM_STEP;
-  const bool on = kStep ? S.active != 0 : (S.done == 0 && S.jdone > 0);
+  constexpr bool kStep = MODE == BM_STEP || MODE == BM_PASS2;
+  const bool on = (MODE == BM_STEP)    ? S.active != 0
+                  : (MODE == BM_PASS2) ? (S.active != 0 && S.reorth != 0)
+                                       : (S.done == 0 && S.jdone > 0);
   if (!on) return;
   const int nv = kStep ? *jp + 1 : S.jdone;
   const double* cf;
@@ -316,6 +343,9 @@ void batch_dots(const BatchItem* items, int count, int total_chunks, const Batch
     case BM_STEP:
       hipLaunchKernelGGL(batch_dots_kernel<BM_STEP>, g, b, 0, s, items, count, st, jp, part, ldp);
       break;
+    case BM_PASS2:
+      hipLaunchKernelGGL(batch_dots_kernel<BM_PASS2>, g, b, 0, s, items, count, st, jp, part, ldp);
+      break;
     case BM_WNORM:
       hipLaunchKernelGGL(batch_dots_kernel<BM_WNORM>, g, b, 0, s, items, count, st, jp, part, ldp);
       break;
@@ -361,6 +391,8 @@ void batch_update(const BatchItem* items, int count, int total_chunks, const Bat
   const dim3 g(total_chunks), b(kBT);
   if (mode == BM_STEP)
     hipLaunchKernelGGL(batch_update_kernel<BM_STEP>, g, b, 0, s, items, count, st, jp);
+  else if (mode == BM_PASS2)
+    hipLaunchKernelGGL(batch_update_kernel<BM_PASS2>, g, b, 0, s, items, count, st, jp);
   else if (mode == BM_XUPDATE)
     hipLaunchKernelGGL(batch_update_kernel<BM_XUPDATE>, g, b, 0, s, items, count, st, jp);
   else
