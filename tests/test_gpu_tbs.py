@@ -98,9 +98,10 @@ def test_served_tbs_equals_synchronous():
         Xg = torch.zeros_like(Cd)
         ta = c.submit(Ad, Bd, Cd, Xa, method=tsylv.TBS)
         tg = c.submit(Ad, Bd, Cd, Xg, method=tsylv.GMRES, m=20, tol=1e-10)
-        jobs.append((Xs, Xa, ta, tg, A, B, C))
+        # the device inputs stay referenced until their requests are final
+        jobs.append((Xs, Xa, ta, tg, (Ad, Bd, Cd, Xg)))
     deadline = time.time() + 60.0
-    for Xs, Xa, ta, tg, A, B, C in jobs:
+    for Xs, Xa, ta, tg, _ in jobs:
         for t in (ta, tg):
             while True:
                 st, info = c.poll(t)
