@@ -563,6 +563,7 @@ void launch_cfg(const Bf16Args& a, int variant, hipStream_t st) {
     case 0: launch_wg<1, 4, 8, 8, 2, TIO>(a, ncu, st); break;
     case 1: launch_wg<2, 2, 4, 8, 2, TIO>(a, ncu, st); break;
     case 2: launch_wg<4, 2, 2, 8, 2, TIO>(a, ncu, st); break;
+    case 3: launch_wg<4, 8, 8, 8, 1, TIO>(a, ncu, st); break;
     default: throw Error(TSYLV_EINVAL, "apply: unknown BF16 variant");
   }
 }
