@@ -329,8 +329,9 @@ void launch_apply(ApplyArgs<Tag> a, hipStream_t st) {
   TSYLV_LAUNCH_CHECK();
 }
 
-// Tile variants (TM x TN workgroup tile, RB x CB 16 x 16 blocks per wave),
-// the candidates of the autotuner; every one is valid for every shape.
+// Tile variants (TM x TN workgroup tile, RB x CB 16 x 16 blocks per wave, k
+// panel depth), the candidates of the autotuner; every one is valid for
+// every shape.
 template <typename Tag>
 void launch_variant(int v, ApplyArgs<Tag> a, hipStream_t st) {
   switch (v) {
@@ -340,6 +341,8 @@ void launch_variant(int v, ApplyArgs<Tag> a, hipStream_t st) {
     case 3: launch_apply<Tag, 64, 64, 1, 4>(a, st); break;
     case 4: launch_apply<Tag, 64, 64, 2, 2>(a, st); break;
     case 5: launch_apply<Tag, 128, 32, 2, 2>(a, st); break;
+    case 6: launch_apply<Tag, 32, 64, 1, 2, 32>(a, st); break;  // 32-deep k panels
+    case 7: launch_apply<Tag, 64, 32, 1, 2, 32>(a, st); break;
     default: throw Error(TSYLV_EINVAL, "apply: unknown tile variant");
   }
 }
@@ -472,7 +475,7 @@ int batch_apply_tiles(int variant, int64_t n, int64_t s, int p, int* nrt, int* n
   return num_slices(p) * *nrt * *nct;
 }
 
-int apply_variant_count(int prec) { return prec == TSYLV_BF16 ? 4 : 6; }
+int apply_variant_count(int prec) { return prec == TSYLV_BF16 ? 4 : 8; }
 
 int apply_default_variant(int prec, int64_t s) {
   if (prec == TSYLV_FP64) return default_variant<double>(s);
