@@ -19,9 +19,16 @@
 // kCheckEvery steps to end a cycle early when no instance is stepping.  At
 // a cycle's end: y = R^{-1} g, X += V y, the true residual R = C - M(X), and
 // the restart test of Algorithm 3 -- again one launch each for the batch.
+// The batch can be split into up to kGroups groups of balanced apply work,
+// each with its own tables, stream and graph, so that the applies of one
+// group could run beside the Gram-Schmidt sweeps of another; an instance's
+// arithmetic is the same in any group.  Measured with four groups: no gain
+// on 64 instances of n up to 2048 (each group's apply grid already fills
+// the GPU) and slower small batches (more launches), so one group is used.
 #include <chrono>
 #include <cstring>
 #include <memory>
+#include <algorithm>
 #include <vector>
 
 #include "kernels.hpp"
@@ -34,6 +41,7 @@ namespace {
 
 constexpr int kCheckEvery = 8;
 constexpr int kVariants = 3;
+constexpr int kGroups = 1;  // independent lockstep groups per batch (see above)
 
 struct BatchPlan {
   int count = 0, m = 0;
@@ -67,29 +75,78 @@ size_t batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_
        Workspace::bytes_for(chunks * (o.m + 3), 8) +
        kVariants * Workspace::bytes_for((int64_t)count, sizeof(kern::BatchApplyRef)) +
        Workspace::bytes_for(1, sizeof(int));
+  // each group rounds its own seven tables up to 256 bytes
+  b += (size_t)std::min(kGroups, count) * (kVariants + 4) * 256;
   return b;
 }
+
+namespace {
+
+// One lockstep group: its own tables, reduction buffer, step counter,
+// stream and captured step.  The groups of a batch are independent, so
+// their launches overlap on the device (the MFMA-bound applies of one group
+// beside the HBM-bound Gram-Schmidt sweeps of another).
+struct Group {
+  std::vector<int> ids;                 // instances (indices into the batch)
+  std::vector<kern::BatchItem> items;
+  BatchPlan plan;
+  kern::BatchItem* d_items = nullptr;
+  kern::BatchState* d_state = nullptr;
+  double* d_part = nullptr;
+  kern::BatchApplyRef* d_refs[kVariants] = {nullptr, nullptr, nullptr};
+  int* d_j = nullptr;
+  hipStream_t stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<kern::BatchState> flags;
+  bool live = true;      // some instance not done
+  bool stepping = true;  // some instance stepping in the current cycle
+};
+
+}  // namespace
 
 int gmres_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts& o,
                 tsylv_info* infos, bool use_graph) {
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t st = ctx.stream;
   const int m = o.m;
-  BatchPlan plan;
-  plan.count = count;
-  plan.m = m;
-  plan.ldp = m + 3;
+
+  // ---- groups: up to kGroups, balanced by apply work (n^2 s p) ----
+  const int ngroups = std::min(kGroups, count);
+  std::vector<Group> groups(ngroups);
+  {
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    auto work = [&](int i) { return (double)probs[i].n * probs[i].n * probs[i].s * probs[i].p; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    std::vector<double> load(ngroups, 0.0);
+    for (int i : order) {
+      int g = 0;
+      for (int h = 1; h < ngroups; ++h)
+        if (load[h] < load[g]) g = h;
+      load[g] += work(i);
+      groups[g].ids.push_back(i);
+    }
+    for (auto& G : groups) std::sort(G.ids.begin(), G.ids.end());
+  }
 
   // ---- workspace and per-instance setup (Algorithm 1 step 1) ----
   Workspace ws(ctx.arena, batch_workspace_bytes(count, probs, o));
-  // on any exit, let the stream drain before the workspace returns to the arena
-  struct SyncOnExit {
+  // on any exit, let every stream drain before the workspace returns to the
+  // arena, then release the groups' streams and graphs
+  struct Drain {
     hipStream_t s;
-    ~SyncOnExit() { (void)hipStreamSynchronize(s); }
-  } drain{st};
-  std::vector<kern::BatchItem> items(count);
+    std::vector<Group>* gs;
+    ~Drain() {
+      (void)hipStreamSynchronize(s);
+      for (auto& G : *gs) {
+        if (G.stream) (void)hipStreamSynchronize(G.stream);
+        if (G.exec) (void)hipGraphExecDestroy(G.exec);
+        if (G.stream) (void)hipStreamDestroy(G.stream);
+      }
+    }
+  } drain{st, &groups};
   std::vector<Setup> setups(count);
-  int64_t chunk0 = 0;
+  std::vector<kern::BatchItem> all(count);
   for (int i = 0; i < count; ++i) {
     const tsylv_problem& q = probs[i];
     const int64_t N = q.n * q.s * q.p;
@@ -97,7 +154,7 @@ int gmres_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opt
     Setup S = setup_fourier(ctx, st, false, ws, q.n, q.s, q.p, q.A, q.B, q.C, q.X,
                             o.x0_given != 0);
     setups[i] = S;
-    kern::BatchItem& it = items[i];
+    kern::BatchItem& it = all[i];
     it.Ah = S.Ah;
     it.Bh = S.Bh;
     it.Zc = S.Zc;
@@ -115,158 +172,197 @@ int gmres_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opt
     it.N = N;
     it.ldv = ldv;
     it.p = (int)q.p;
-    it.chunk0 = (int)chunk0;
-    it.nchunks = (int)chunks_of(N);
-    chunk0 += it.nchunks;
-    const int v = kern::batch_apply_variant(q.s);
-    kern::BatchApplyRef r;
-    r.item = i;
-    r.tile0 = plan.ntiles[v];
-    plan.ntiles[v] += kern::batch_apply_tiles(v, q.n, q.s, (int)q.p, &r.nrt, &r.nct);
-    plan.refs[v].push_back(r);
   }
-  plan.total_chunks = (int)chunk0;
-  kern::BatchItem* d_items = ws.take<kern::BatchItem>(count);
-  kern::BatchState* d_state = ws.take<kern::BatchState>(count);
-  double* d_part = ws.take<double>((int64_t)plan.total_chunks * plan.ldp);
-  kern::BatchApplyRef* d_refs[kVariants];
-  for (int v = 0; v < kVariants; ++v) d_refs[v] = ws.take<kern::BatchApplyRef>(count);
-  int* d_j = ws.take<int>(1);
-  std::vector<kern::BatchState> hstate(count);
-  std::memset(hstate.data(), 0, sizeof(kern::BatchState) * count);
+  for (auto& G : groups) {
+    const int gc = (int)G.ids.size();
+    G.plan.count = gc;
+    G.plan.m = m;
+    G.plan.ldp = m + 3;
+    int64_t chunk0 = 0;
+    for (int k = 0; k < gc; ++k) {
+      const tsylv_problem& q = probs[G.ids[k]];
+      kern::BatchItem it = all[G.ids[k]];
+      it.chunk0 = (int)chunk0;
+      it.nchunks = (int)chunks_of(it.N);
+      chunk0 += it.nchunks;
+      G.items.push_back(it);
+      const int v = kern::batch_apply_variant(q.s);
+      kern::BatchApplyRef r;
+      r.item = k;
+      r.tile0 = G.plan.ntiles[v];
+      G.plan.ntiles[v] += kern::batch_apply_tiles(v, q.n, q.s, (int)q.p, &r.nrt, &r.nct);
+      G.plan.refs[v].push_back(r);
+    }
+    G.plan.total_chunks = (int)chunk0;
+    G.d_items = ws.take<kern::BatchItem>(gc);
+    G.d_state = ws.take<kern::BatchState>(gc);
+    G.d_part = ws.take<double>((int64_t)G.plan.total_chunks * G.plan.ldp);
+    for (int v = 0; v < kVariants; ++v) G.d_refs[v] = ws.take<kern::BatchApplyRef>(gc);
+    G.d_j = ws.take<int>(1);
+    G.flags.assign(gc, kern::BatchState{});
+  }
   // The tables live in pageable host vectors: blocking copies once the
-  // stream is idle (the setups above are done), then the batch's kernels.
+  // stream is idle (the setups above are done), then the groups' kernels.
   TSYLV_HIP(hipStreamSynchronize(st));
-  TSYLV_HIP(hipMemcpy(d_items, items.data(), sizeof(kern::BatchItem) * count,
-                      hipMemcpyHostToDevice));
-  TSYLV_HIP(hipMemcpy(d_state, hstate.data(), sizeof(kern::BatchState) * count,
-                      hipMemcpyHostToDevice));
-  for (int v = 0; v < kVariants; ++v)
-    if (!plan.refs[v].empty())
-      TSYLV_HIP(hipMemcpy(d_refs[v], plan.refs[v].data(),
-                          sizeof(kern::BatchApplyRef) * plan.refs[v].size(),
-                          hipMemcpyHostToDevice));
-  kern::batch_set_j(d_j, 0, st);
-
-  auto apply_all = [&](int mode, hipStream_t s) {
+  for (auto& G : groups) {
+    const int gc = (int)G.ids.size();
+    TSYLV_HIP(hipMemcpy(G.d_items, G.items.data(), sizeof(kern::BatchItem) * gc,
+                        hipMemcpyHostToDevice));
+    TSYLV_HIP(hipMemcpy(G.d_state, G.flags.data(), sizeof(kern::BatchState) * gc,
+                        hipMemcpyHostToDevice));
     for (int v = 0; v < kVariants; ++v)
-      if (!plan.refs[v].empty())
-        kern::batch_apply(d_items, d_refs[v], (int)plan.refs[v].size(), plan.ntiles[v], v,
-                          d_state, d_j, mode, s);
+      if (!G.plan.refs[v].empty())
+        TSYLV_HIP(hipMemcpy(G.d_refs[v], G.plan.refs[v].data(),
+                            sizeof(kern::BatchApplyRef) * G.plan.refs[v].size(),
+                            hipMemcpyHostToDevice));
+    TSYLV_HIP(hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
+  }
+
+  auto apply_all = [&](Group& G, int mode, hipStream_t s) {
+    for (int v = 0; v < kVariants; ++v)
+      if (!G.plan.refs[v].empty())
+        kern::batch_apply(G.d_items, G.d_refs[v], (int)G.plan.refs[v].size(), G.plan.ntiles[v],
+                          v, G.d_state, G.d_j, mode, s);
   };
-  auto residual = [&](int reduce_mode, hipStream_t s) {
-    apply_all(kern::BM_RESID, s);
-    kern::batch_dots(d_items, count, plan.total_chunks, d_state, d_j, d_part, plan.ldp,
+  auto residual = [&](Group& G, int reduce_mode, hipStream_t s) {
+    const int gc = G.plan.count;
+    apply_all(G, kern::BM_RESID, s);
+    kern::batch_dots(G.d_items, gc, G.plan.total_chunks, G.d_state, G.d_j, G.d_part, G.plan.ldp,
                      kern::BM_RESID, s);
-    kern::batch_reduce(d_items, count, d_state, d_j, d_part, plan.ldp, reduce_mode, m, o.tol,
-                       o.max_cycles, s);
-    kern::batch_scale(d_items, count, plan.total_chunks, d_state, d_j, kern::BM_RESID, s);
+    kern::batch_reduce(G.d_items, gc, G.d_state, G.d_j, G.d_part, G.plan.ldp, reduce_mode, m,
+                       o.tol, o.max_cycles, s);
+    kern::batch_scale(G.d_items, gc, G.plan.total_chunks, G.d_state, G.d_j, kern::BM_RESID, s);
   };
-  auto step = [&](hipStream_t s) {
-    apply_all(kern::BM_STEP, s);
+  auto step = [&](Group& G, hipStream_t s) {
+    const int gc = G.plan.count;
+    apply_all(G, kern::BM_STEP, s);
     for (int pass = 0; pass < 2; ++pass) {
       // the second pass runs only for the instances whose first pass cancelled
       const int md = pass == 0 ? kern::BM_STEP : kern::BM_PASS2;
-      kern::batch_dots(d_items, count, plan.total_chunks, d_state, d_j, d_part, plan.ldp, md, s);
-      kern::batch_reduce(d_items, count, d_state, d_j, d_part, plan.ldp, md, m, o.tol,
+      kern::batch_dots(G.d_items, gc, G.plan.total_chunks, G.d_state, G.d_j, G.d_part,
+                       G.plan.ldp, md, s);
+      kern::batch_reduce(G.d_items, gc, G.d_state, G.d_j, G.d_part, G.plan.ldp, md, m, o.tol,
                          o.max_cycles, s);
-      kern::batch_update(d_items, count, plan.total_chunks, d_state, d_j, md, s);
+      kern::batch_update(G.d_items, gc, G.plan.total_chunks, G.d_state, G.d_j, md, s);
     }
-    kern::batch_dots(d_items, count, plan.total_chunks, d_state, d_j, d_part, plan.ldp,
+    kern::batch_dots(G.d_items, gc, G.plan.total_chunks, G.d_state, G.d_j, G.d_part, G.plan.ldp,
                      kern::BM_WNORM, s);
-    kern::batch_reduce(d_items, count, d_state, d_j, d_part, plan.ldp, kern::BM_WNORM, m, o.tol,
-                       o.max_cycles, s);
-    kern::batch_scale(d_items, count, plan.total_chunks, d_state, d_j, kern::BM_STEP, s);
-    kern::batch_advance(d_j, s);
+    kern::batch_reduce(G.d_items, gc, G.d_state, G.d_j, G.d_part, G.plan.ldp, kern::BM_WNORM, m,
+                       o.tol, o.max_cycles, s);
+    kern::batch_scale(G.d_items, gc, G.plan.total_chunks, G.d_state, G.d_j, kern::BM_STEP, s);
+    kern::batch_advance(G.d_j, s);
+  };
+  auto read_state = [&](Group& G) {
+    TSYLV_HIP(hipStreamSynchronize(G.stream));
+    TSYLV_HIP(hipMemcpy(G.flags.data(), G.d_state, sizeof(kern::BatchState) * G.plan.count,
+                        hipMemcpyDeviceToHost));
+    G.live = G.stepping = false;
+    for (auto& f : G.flags) {
+      G.live = G.live || !f.done;
+      G.stepping = G.stepping || f.active;
+    }
   };
 
-  // ||C|| and the initial residual (X0 = 0 or the given X0)
-  kern::batch_dots(d_items, count, plan.total_chunks, d_state, d_j, d_part, plan.ldp,
-                   kern::BM_CNORM, st);
-  kern::batch_reduce(d_items, count, d_state, d_j, d_part, plan.ldp, kern::BM_CNORM, m, o.tol,
-                     o.max_cycles, st);
-  residual(kern::BM_RESID0, st);
-
-  // one step as a graph, captured on a private stream and replayed on ours
-  hipGraphExec_t exec = nullptr;
-  hipStream_t cap = nullptr;
-  struct Cleanup {
-    hipGraphExec_t* e;
-    hipStream_t* c;
-    ~Cleanup() {
-      if (*e) (void)hipGraphExecDestroy(*e);
-      if (*c) (void)hipStreamDestroy(*c);
-    }
-  } cleanup{&exec, &cap};
-  if (use_graph) {
-    TSYLV_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipGraph_t graph = nullptr;
-    TSYLV_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    try {
-      step(cap);
-    } catch (...) {
-      (void)hipStreamEndCapture(cap, &graph);
-      if (graph) (void)hipGraphDestroy(graph);
-      throw;
-    }
-    TSYLV_HIP(hipStreamEndCapture(cap, &graph));
-    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    TSYLV_HIP(e);
+  // ||C|| and the initial residual (X0 = 0 or the given X0), per group
+  for (auto& G : groups) {
+    kern::batch_set_j(G.d_j, 0, G.stream);
+    kern::batch_dots(G.d_items, G.plan.count, G.plan.total_chunks, G.d_state, G.d_j, G.d_part,
+                     G.plan.ldp, kern::BM_CNORM, G.stream);
+    kern::batch_reduce(G.d_items, G.plan.count, G.d_state, G.d_j, G.d_part, G.plan.ldp,
+                       kern::BM_CNORM, m, o.tol, o.max_cycles, G.stream);
+    residual(G, kern::BM_RESID0, G.stream);
   }
 
-  std::vector<kern::BatchState> flags(count);
-  kern::BatchState* h_flags = flags.data();
-  auto read_state = [&]() {
-    TSYLV_HIP(hipStreamSynchronize(st));
-    TSYLV_HIP(hipMemcpy(h_flags, d_state, sizeof(kern::BatchState) * count,
-                        hipMemcpyDeviceToHost));
-  };
-  read_state();
+  // each group's step as a graph, captured on a private stream and replayed
+  // on the group's stream
+  if (use_graph) {
+    hipStream_t cap = nullptr;
+    TSYLV_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    struct CapStream {
+      hipStream_t s;
+      ~CapStream() { (void)hipStreamDestroy(s); }
+    } cap_guard{cap};
+    for (auto& G : groups) {
+      hipGraph_t graph = nullptr;
+      TSYLV_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      try {
+        step(G, cap);
+      } catch (...) {
+        (void)hipStreamEndCapture(cap, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      TSYLV_HIP(hipStreamEndCapture(cap, &graph));
+      const hipError_t e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      TSYLV_HIP(e);
+    }
+  }
+
+  for (auto& G : groups) read_state(G);
   for (int cycle = 0; cycle < o.max_cycles; ++cycle) {
-    int live = 0;
-    for (int i = 0; i < count; ++i) live += h_flags[i].done ? 0 : 1;
-    if (live == 0) break;
-    kern::batch_set_j(d_j, 0, st);
-    for (int j = 0; j < m; ++j) {
-      if (use_graph)
-        TSYLV_HIP(hipGraphLaunch(exec, st));
-      else
-        step(st);
-      if ((j + 1) % kCheckEvery == 0 && j + 1 < m) {
-        read_state();
-        int stepping = 0;
-        for (int i = 0; i < count; ++i) stepping += h_flags[i].active;
-        if (stepping == 0) break;
+    bool any = false;
+    for (auto& G : groups) {
+      G.stepping = G.live;
+      if (G.live) {
+        kern::batch_set_j(G.d_j, 0, G.stream);
+        any = true;
       }
     }
-    kern::batch_backsub(d_items, count, d_state, m, st);
-    kern::batch_update(d_items, count, plan.total_chunks, d_state, d_j, kern::BM_XUPDATE, st);
-    residual(kern::BM_RESID, st);
-    read_state();
+    if (!any) break;
+    for (int j = 0; j < m; ++j) {
+      for (auto& G : groups) {
+        if (!G.stepping) continue;
+        if (use_graph)
+          TSYLV_HIP(hipGraphLaunch(G.exec, G.stream));
+        else
+          step(G, G.stream);
+      }
+      if ((j + 1) % kCheckEvery == 0 && j + 1 < m) {
+        bool more = false;
+        for (auto& G : groups)
+          if (G.stepping) {
+            read_state(G);
+            more = more || G.stepping;
+          }
+        if (!more) break;
+      }
+    }
+    for (auto& G : groups) {
+      if (!G.live) continue;
+      kern::batch_backsub(G.d_items, G.plan.count, G.d_state, m, G.stream);
+      kern::batch_update(G.d_items, G.plan.count, G.plan.total_chunks, G.d_state, G.d_j,
+                         kern::BM_XUPDATE, G.stream);
+      residual(G, kern::BM_RESID, G.stream);
+    }
+    for (auto& G : groups)
+      if (G.live) read_state(G);
   }
 
   // ---- Algorithm 1 step 3: X = inverse transform of the planes ----
+  for (auto& G : groups) TSYLV_HIP(hipStreamSynchronize(G.stream));
   for (int i = 0; i < count; ++i)
-    kern::tube_xform_f64(items[i].Zx, probs[i].X, setups[i].xf_inv, probs[i].n * probs[i].s,
+    kern::tube_xform_f64(all[i].Zx, probs[i].X, setups[i].xf_inv, probs[i].n * probs[i].s,
                          (int)probs[i].p, st);
-  read_state();
+  TSYLV_HIP(hipStreamSynchronize(st));
+  for (auto& G : groups) read_state(G);
   const double secs =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   int worst = TSYLV_OK;
-  for (int i = 0; i < count; ++i) {
-    const kern::BatchState& S = h_flags[i];
-    tsylv_info& inf = infos[i];
-    std::memset(&inf, 0, sizeof(inf));
-    inf.status = S.done ? S.status : TSYLV_NOT_CONVERGED;
-    inf.steps = S.steps;
-    inf.cycles = S.cycles;
-    inf.outer = 0;
-    inf.relres_true = S.cnorm > 0.0 ? S.beta / S.cnorm : 0.0;
-    inf.relres_est = inf.relres_true;
-    inf.seconds = secs;
-    if (inf.status != TSYLV_OK) worst = TSYLV_NOT_CONVERGED;
-  }
+  for (auto& G : groups)
+    for (size_t k = 0; k < G.ids.size(); ++k) {
+      const kern::BatchState& S = G.flags[k];
+      tsylv_info& inf = infos[G.ids[k]];
+      std::memset(&inf, 0, sizeof(inf));
+      inf.status = S.done ? S.status : TSYLV_NOT_CONVERGED;
+      inf.steps = S.steps;
+      inf.cycles = S.cycles;
+      inf.outer = 0;
+      inf.relres_true = S.cnorm > 0.0 ? S.beta / S.cnorm : 0.0;
+      inf.relres_est = inf.relres_true;
+      inf.seconds = secs;
+      if (inf.status != TSYLV_OK) worst = TSYLV_NOT_CONVERGED;
+    }
   return worst;
 }
 
