@@ -192,10 +192,24 @@ def tiny_latency(tsylv, workloads, reps=100):
         ok_d = ok_d and info_d.status == 0 and info_d.relres_true <= 1e-12
         if r >= 10:
             lat_d.append(dt)
+    # and through the batched engine as a batch of one (tGMRES(63): device
+    # Givens, the step replayed from a graph, a host check every 8 steps)
+    ob = tsylv.default_opts(tsylv.GMRES, m=63, tol=1e-12, max_cycles=4)
+    lat_b, ok_b = [], True
+    for r in range(reps + 10):
+        t0 = time.perf_counter()
+        info_b = ctx.gmres_batch([(Ad, Bd, Cd, Xd)], opts=ob)[0]
+        dt = time.perf_counter() - t0
+        ok_b = ok_b and info_b.status == 0 and info_b.relres_true <= 1e-12
+        if r >= 10:
+            lat_b.append(dt)
     torch.cuda.synchronize()
     ctx.close()
     return {"workload": "dense 8x8x4 (A slices N(0,1)/sqrt(8) + 4I on slice 1, B N(0,1)/sqrt(6) "
                         "- 4I), unrestarted tGMRES to relres 1e-12",
+            "batched_engine": {"valid": bool(ok_b), "steps": info_b.steps,
+                               "latency_us": {"p50": float(np.percentile(lat_b, 50) * 1e6),
+                                              "p99": float(np.percentile(lat_b, 99) * 1e6)}},
             "valid": bool(ok), "solves": reps, "steps": info.steps,
             "latency_us": {"p50": float(np.percentile(lat, 50) * 1e6),
                            "p99": float(np.percentile(lat, 99) * 1e6)},
