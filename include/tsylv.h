@@ -44,7 +44,9 @@ typedef enum {
   TSYLV_METHOD_GMRES = 0, /* tGMRES(m), Algorithm 3                        */
   TSYLV_METHOD_FOM = 1,   /* tFOM(m), Algorithm 3                          */
   TSYLV_METHOD_TBA = 2,   /* TBAS(m), Algorithm 8 (block size s)           */
-  TSYLV_METHOD_TBS = 3    /* t-Bartels-Stewart direct solve, Algorithm 5   */
+  TSYLV_METHOD_TBS = 3,   /* t-Bartels-Stewart direct solve, Algorithm 5   */
+  TSYLV_METHOD_GMRES_BATCHED = 4 /* tGMRES(m) served in lockstep batches
+                                    (tsylv_submit only; see below)          */
 } tsylv_method;
 
 typedef enum {
@@ -206,13 +208,17 @@ int tsylv_generate(tsylv_ctx* ctx, uint64_t seed, int64_t n, int64_t s, int64_t 
 
 /* Asynchronous solves (continuous batching).  A request is admitted when its
  * workspace fits in the arena; admitted requests are stepped together on the
- * GPU.  The pointers in the request must stay valid until tsylv_poll returns
+ * GPU.  Requests of method TSYLV_METHOD_GMRES_BATCHED (FP64, m <= 63, X0 =
+ * 0) that wait in the queue together with equal options are admitted as one
+ * lockstep batch (tsylv_gmres_batch: one launch per step stage for all of
+ * them, the step replayed from a HIP graph, Givens on the device); each
+ * result is bitwise the batch-of-one solve of its instance.  The pointers in the request must stay valid until tsylv_poll returns
  * a final status for its ticket.  A request with A, B and C all NULL solves
  * the synthetic instance of `gen_seed` (tsylv_generate), drawn on the device
  * inside its setup transforms, so that the spatial tensors are never stored
  * (p <= 64; the generation counts in the request's latency). */
 typedef struct {
-  int method;                 /* tsylv_method (GMRES, FOM or TBS)            */
+  int method;                 /* tsylv_method (GMRES, FOM, TBS, GMRES_BATCHED) */
   int64_t n, s, p;
   const double* A;            /* device pointers, layout as above           */
   const double* B;

@@ -104,10 +104,10 @@ struct Group {
 
 }  // namespace
 
-int gmres_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts& o,
-                tsylv_info* infos, bool use_graph) {
+int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
+                const uint64_t* const* gens, const tsylv_opts& o, tsylv_info* infos,
+                bool use_graph) {
   const auto t0 = std::chrono::steady_clock::now();
-  hipStream_t st = ctx.stream;
   const int m = o.m;
 
   // ---- groups: up to kGroups, balanced by apply work (n^2 s p) ----
@@ -152,7 +152,7 @@ int gmres_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opt
     const int64_t N = q.n * q.s * q.p;
     const int64_t ldv = (N + 63) / 64 * 64;
     Setup S = setup_fourier(ctx, st, false, ws, q.n, q.s, q.p, q.A, q.B, q.C, q.X,
-                            o.x0_given != 0);
+                            o.x0_given != 0, gens ? gens[i] : nullptr);
     setups[i] = S;
     kern::BatchItem& it = all[i];
     it.Ah = S.Ah;
@@ -201,21 +201,24 @@ int gmres_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opt
     G.d_j = ws.take<int>(1);
     G.flags.assign(gc, kern::BatchState{});
   }
-  // The tables live in pageable host vectors: blocking copies once the
-  // stream is idle (the setups above are done), then the groups' kernels.
+  // The tables live in pageable host vectors: copied on the group's stream,
+  // which then waits for them (never through the legacy default stream,
+  // which another thread's graph capture would make fail); the group's
+  // stream first waits for the setups on st.
   TSYLV_HIP(hipStreamSynchronize(st));
   for (auto& G : groups) {
     const int gc = (int)G.ids.size();
-    TSYLV_HIP(hipMemcpy(G.d_items, G.items.data(), sizeof(kern::BatchItem) * gc,
-                        hipMemcpyHostToDevice));
-    TSYLV_HIP(hipMemcpy(G.d_state, G.flags.data(), sizeof(kern::BatchState) * gc,
-                        hipMemcpyHostToDevice));
+    TSYLV_HIP(hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
+    TSYLV_HIP(hipMemcpyAsync(G.d_items, G.items.data(), sizeof(kern::BatchItem) * gc,
+                             hipMemcpyHostToDevice, G.stream));
+    TSYLV_HIP(hipMemcpyAsync(G.d_state, G.flags.data(), sizeof(kern::BatchState) * gc,
+                             hipMemcpyHostToDevice, G.stream));
     for (int v = 0; v < kVariants; ++v)
       if (!G.plan.refs[v].empty())
-        TSYLV_HIP(hipMemcpy(G.d_refs[v], G.plan.refs[v].data(),
-                            sizeof(kern::BatchApplyRef) * G.plan.refs[v].size(),
-                            hipMemcpyHostToDevice));
-    TSYLV_HIP(hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
+        TSYLV_HIP(hipMemcpyAsync(G.d_refs[v], G.plan.refs[v].data(),
+                                 sizeof(kern::BatchApplyRef) * G.plan.refs[v].size(),
+                                 hipMemcpyHostToDevice, G.stream));
+    TSYLV_HIP(hipStreamSynchronize(G.stream));
   }
 
   auto apply_all = [&](Group& G, int mode, hipStream_t s) {
@@ -253,9 +256,9 @@ int gmres_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opt
     kern::batch_advance(G.d_j, s);
   };
   auto read_state = [&](Group& G) {
+    TSYLV_HIP(hipMemcpyAsync(G.flags.data(), G.d_state, sizeof(kern::BatchState) * G.plan.count,
+                             hipMemcpyDeviceToHost, G.stream));
     TSYLV_HIP(hipStreamSynchronize(G.stream));
-    TSYLV_HIP(hipMemcpy(G.flags.data(), G.d_state, sizeof(kern::BatchState) * G.plan.count,
-                        hipMemcpyDeviceToHost));
     G.live = G.stepping = false;
     for (auto& f : G.flags) {
       G.live = G.live || !f.done;

@@ -259,7 +259,7 @@ int tsylv_gmres_batch(tsylv_ctx* ctx, int count, const tsylv_problem* probs,
   return guarded([&]() {
     std::lock_guard<std::mutex> lk(ctx->c.sync_mu);
     set_device(ctx);
-    return gmres_batch(ctx->c, count, probs, o, infos, use_graph);
+    return gmres_batch(ctx->c, ctx->c.stream, count, probs, nullptr, o, infos, use_graph);
   });
 }
 
@@ -285,7 +285,10 @@ int tsylv_submit(tsylv_ctx* ctx, const tsylv_request* req, uint64_t* ticket) {
   if (!(given || generated) || !r.X || !dims_ok(r.n, r.s, r.p)) return TSYLV_EINVAL;
   if (generated && r.p > kern::kGenXformMaxP) return TSYLV_EINVAL;
   if (r.method != TSYLV_METHOD_GMRES && r.method != TSYLV_METHOD_FOM &&
-      r.method != TSYLV_METHOD_TBS)
+      r.method != TSYLV_METHOD_TBS && r.method != TSYLV_METHOD_GMRES_BATCHED)
+    return TSYLV_EINVAL;
+  if (r.method == TSYLV_METHOD_GMRES_BATCHED &&
+      (r.opts.refine || r.opts.m > kern::kBatchMaxM || r.opts.x0_given))
     return TSYLV_EINVAL;
   if (r.method == TSYLV_METHOD_TBS && (!tbs_dims_ok(r.n, r.s) || r.opts.refine))
     return TSYLV_EINVAL;

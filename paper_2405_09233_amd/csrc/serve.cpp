@@ -15,6 +15,16 @@
 // theirs.  Each solve runs exactly the kernels and host arithmetic of a
 // synchronous call (the same KrylovTask; reductions are fixed-order), so its
 // result is bitwise the same alone or in a mix.
+//
+// Requests of method GMRES_BATCHED that wait at the head of the queue with
+// equal options are admitted together, up to kMaxBatch of them and as many as
+// the arena holds, as one lockstep batch (batch.cpp) that takes one slot and
+// runs on a worker thread on the slot's stream, its steps launched eagerly
+// (a graph capture on the worker would make the caller's concurrent work on
+// the legacy default stream fail); the scheduler posts every result of the
+// batch when the worker ends.  An instance's result in a batch is bitwise its
+// batch-of-one result (graph or eager: the same kernels).
+#include <atomic>
 #include <condition_variable>
 #include <deque>
 #include <memory>
@@ -35,6 +45,23 @@ constexpr int kSlots = 8;
 // KrylovTask::pinned_doubles for m <= 1000 (a device-driven cycle, m <= 63,
 // needs at most 7 * 65 + 2 + 65 * 64 + 2 of them)
 constexpr size_t kPinnedPerSlot = 7 * (1000 + 2) + 2;
+constexpr int kMaxBatch = 512;
+
+bool same_batch_opts(const tsylv_opts& a, const tsylv_opts& b) {
+  return a.m == b.m && a.tol == b.tol && a.max_cycles == b.max_cycles;
+}
+
+// A lockstep batch of GMRES_BATCHED requests, run by a worker thread.
+struct BatchJob {
+  std::vector<uint64_t> tickets;
+  std::vector<tsylv_request> reqs;
+  std::vector<tsylv_problem> probs;
+  std::vector<const uint64_t*> gens;
+  std::vector<tsylv_info> infos;
+  std::thread th;
+  std::atomic<bool> finished{false};
+  int error = 0;  // an error of the whole batch
+};
 }  // namespace
 
 struct Scheduler {
@@ -63,6 +90,7 @@ struct Scheduler {
     std::unique_ptr<KrylovTask> task;
     int error = 0;
     bool in_flight = false;  // a phase is enqueued and not yet completed
+    std::unique_ptr<BatchJob> job;  // a lockstep batch instead of one task
   };
   std::vector<Active> active;
   std::vector<int> free_slots;
@@ -108,6 +136,10 @@ struct Scheduler {
   void admit() {
     std::unique_lock<std::mutex> lk(mu);
     while (!queue.empty() && !free_slots.empty()) {
+      if (queue.front().r.method == TSYLV_METHOD_GMRES_BATCHED) {
+        if (!admit_batch(lk)) break;
+        continue;
+      }
       Queued q = queue.front();
       const size_t need = krylov_workspace_bytes(q.r.method, q.r.n, q.r.s, q.r.p, q.r.opts);
       if (need > ctx.arena.capacity()) {  // can never fit
@@ -145,6 +177,89 @@ struct Scheduler {
     }
   }
 
+  // The GMRES_BATCHED requests at the head of the queue with the options of
+  // the first one, as many as fit in the arena, become one batch on a free
+  // slot.  Returns false when the head must wait for memory.  Called with mu
+  // held (lk); returns with it held.
+  bool admit_batch(std::unique_lock<std::mutex>& lk) {
+    const tsylv_opts o = queue.front().r.opts;
+    std::vector<tsylv_problem> probs;
+    size_t k = 0;
+    for (; k < queue.size() && (int)k < kMaxBatch; ++k) {
+      const tsylv_request& r = queue[k].r;
+      if (r.method != TSYLV_METHOD_GMRES_BATCHED || !same_batch_opts(r.opts, o)) break;
+      probs.push_back(tsylv_problem{r.n, r.s, r.p, r.A, r.B, r.C, r.X});
+    }
+    // the longest prefix whose workspace fits
+    const size_t free_b = ctx.arena.largest_free();
+    size_t take = k;
+    while (take > 0 && batch_workspace_bytes((int)take, probs.data(), o) > free_b) --take;
+    if (take == 0) {
+      if (batch_workspace_bytes(1, probs.data(), o) > ctx.arena.capacity()) {  // never fits
+        tsylv_info inf{};
+        inf.status = TSYLV_ENOMEM;
+        done[queue.front().ticket] = {TSYLV_ENOMEM, inf};
+        queue.pop_front();
+        return true;
+      }
+      return false;
+    }
+    std::unique_ptr<BatchJob> job(new BatchJob());
+    for (size_t i = 0; i < take; ++i) {
+      job->tickets.push_back(queue.front().ticket);
+      job->reqs.push_back(queue.front().r);
+      queue.pop_front();
+    }
+    job->probs.assign(probs.begin(), probs.begin() + (long)take);
+    job->infos.resize(take);
+    for (size_t i = 0; i < take; ++i)
+      job->gens.push_back(job->reqs[i].A ? nullptr : &job->reqs[i].gen_seed);
+    const int slot = free_slots.back();
+    free_slots.pop_back();
+    lk.unlock();
+    BatchJob* jp = job.get();
+    hipStream_t st = streams[slot];
+    jp->th = std::thread([this, jp, st, o]() {
+      try {
+        TSYLV_HIP(hipSetDevice(ctx.device));
+        // launched eagerly: a graph capture on this worker thread would make
+        // the caller's concurrent work on the legacy default stream fail
+        gmres_batch(ctx, st, (int)jp->probs.size(), jp->probs.data(), jp->gens.data(), o,
+                    jp->infos.data(), false);
+      } catch (const Error& e) {
+        jp->error = e.status;
+      } catch (...) {
+        jp->error = TSYLV_EHIP;
+      }
+      jp->finished.store(true);
+    });
+    Active a{jp->tickets[0], slot, nullptr, 0};
+    a.job = std::move(job);
+    active.push_back(std::move(a));
+    lk.lock();
+    return true;
+  }
+
+  // A finished batch: every result posted (an arena shortfall puts the
+  // requests back at the head of the queue instead).
+  void retire_batch(Active& a) {
+    BatchJob& j = *a.job;
+    if (j.th.joinable()) j.th.join();
+    if (j.error == TSYLV_ENOMEM && active.size() > 1) {  // others hold memory: retry
+      std::lock_guard<std::mutex> g(mu);
+      if (!stopping) {
+        for (size_t i = j.tickets.size(); i-- > 0;) queue.push_front({j.tickets[i], j.reqs[i]});
+        return;
+      }
+    }
+    for (size_t i = 0; i < j.tickets.size(); ++i) {
+      if (j.error)
+        finish(j.tickets[i], j.error, nullptr);
+      else
+        finish(j.tickets[i], j.infos[i].status, &j.infos[i]);
+    }
+  }
+
   void run() {
     (void)hipSetDevice(ctx.device);
     for (;;) {
@@ -159,6 +274,7 @@ struct Scheduler {
       }
       bool progressed = false;
       for (auto& a : active) {
+        if (a.job) continue;
         if (a.error || !a.task) continue;
         try {
           if (a.in_flight) {
@@ -184,6 +300,19 @@ struct Scheduler {
       // retire finished and failed solves; their workspace returns to the arena
       for (size_t i = 0; i < active.size();) {
         Active& a = active[i];
+        if (a.job) {
+          if (!a.job->finished.load()) {
+            ++i;
+            continue;
+          }
+          retire_batch(a);
+          {
+            std::lock_guard<std::mutex> g(mu);
+            free_slots.push_back(a.slot);
+          }
+          active.erase(active.begin() + (long)i);
+          continue;
+        }
         const bool fin = a.error || (a.task && a.task->done());
         if (!fin) {
           ++i;

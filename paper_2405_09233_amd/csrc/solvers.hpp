@@ -38,8 +38,11 @@ int krylov_solve(Ctx& ctx, int method, int64_t n, int64_t s, int64_t p, const do
 
 // Batched lockstep tGMRES (batch.cpp): FP64, restart length o.m <= 63.
 size_t batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o);
-int gmres_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts& o,
-                tsylv_info* infos, bool use_graph);
+// On stream `st`; gens (may be null): gens[i] non-null draws instance i as
+// the synthetic instance of seed *gens[i] (its A, B, C are not read).
+int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
+                const uint64_t* const* gens, const tsylv_opts& o, tsylv_info* infos,
+                bool use_graph);
 
 // Autotuner (tune.cpp): times every tile variant of the apply at (n, s, p)
 // in precision `prec` (`reps` launches each), stores the fastest in

@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtsylv.so")
 
 FP64, FP32, BF16 = 0, 1, 2
-GMRES, FOM, TBA, TBS = 0, 1, 2, 3
+GMRES, FOM, TBA, TBS, GMRES_BATCHED = 0, 1, 2, 3, 4
 APPLY = -1
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "EINVAL", -2: "ENOMEM",

@@ -1,0 +1,168 @@
+"""GPU tests of serving in lockstep batches (requests of method
+TSYLV_METHOD_GMRES_BATCHED through tsylv_submit / tsylv_poll).
+
+* Requests that wait together are solved as one batch; every result must
+  be bitwise the batch-of-one solve of its instance (tsylv_gmres_batch with
+  that instance alone), with plain tGMRES requests interleaved in the queue
+  (they split the batches), and the small ones match the oracle's Kronecker
+  solution.
+* Seed-only requests draw their instance on the device inside the batch.
+* Admission by the arena: with an arena that holds a few instances at a
+  time the queue drains in several batches with the same results.
+* Malformed requests are rejected; closing the context with batches in
+  flight finishes them.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+from oracle import kron
+from paper_2405_09233_amd import tsylv, workloads
+from gpu_util import dev, host, say, rel
+
+
+def wait_all(ctx, tickets, timeout=120.0):
+    out, t0 = {}, time.time()
+    pending = list(tickets)
+    while pending:
+        for t in list(pending):
+            st, info = ctx.poll(t)
+            if st != 2:
+                out[t] = (st, info)
+                pending.remove(t)
+        assert time.time() - t0 < timeout, "serving loop did not finish"
+        time.sleep(0.001)
+    return out
+
+
+def make(count, seed0):
+    rng = np.random.default_rng(seed0)
+    out = []
+    for i in range(count):
+        n, s, p = int(rng.integers(6, 80)), int(rng.integers(1, 13)), int(rng.integers(1, 10))
+        out.append((n, s, p, workloads.dense_shifted(n, s, p, seed=seed0 + i)))
+    return out
+
+
+def submit_all(ctx, reqs, opts, plain_every=0):
+    """Submits every instance as a GMRES_BATCHED request (and, with
+    plain_every, every plain_every-th one also as a plain tGMRES request).
+    Returns the batched requests' device tensors, their tickets, and the
+    plain requests' tickets with their tensors (kept referenced)."""
+    import torch
+    batched, tickets, plain = [], [], []
+    for i, (n, s, p, (A, B, C)) in enumerate(reqs):
+        Ad, Bd, Cd = dev(A), dev(B), dev(C)
+        X = torch.zeros_like(Cd)
+        batched.append((Ad, Bd, Cd, X))
+        tickets.append(ctx.submit(Ad, Bd, Cd, X, method=tsylv.GMRES_BATCHED, opts=opts))
+        if plain_every and i % plain_every == 0:
+            Xp = torch.zeros_like(Cd)
+            plain.append((ctx.submit(Ad, Bd, Cd, Xp, method=tsylv.GMRES, m=20, tol=1e-10),
+                          (Ad, Bd, Cd, Xp)))
+    return batched, tickets, plain
+
+
+@pytest.mark.gpu
+def test_batched_requests_equal_batch_of_one():
+    import torch
+    say("serve batched: 24 requests with plain ones interleaved")
+    c = tsylv.Context(4 << 30, device=0)
+    try:
+        reqs = make(24, 900)
+        opts = tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-11, max_cycles=100)
+        batched, tickets, plain = submit_all(c, reqs, opts, plain_every=5)
+        res = wait_all(c, tickets + [t for t, _ in plain])
+        assert all(res[t][0] == 0 for t, _ in plain)
+        for i, t in enumerate(tickets):
+            st, info = res[t]
+            assert st == 0, info.as_dict()
+            Ad, Bd, Cd, X = batched[i]
+            X1 = torch.zeros_like(Cd)
+            i1 = c.gmres_batch([(Ad, Bd, Cd, X1)], opts=opts)[0]
+            assert torch.equal(X, X1), i
+            assert (info.steps, info.cycles, info.relres_true) == (i1.steps, i1.cycles,
+                                                                   i1.relres_true)
+        for i in range(3):
+            n, s, p, (A, B, C) = reqs[i]
+            assert rel(host(batched[i][3]), kron.kron_solve(A, B, C)) <= 1e-8
+    finally:
+        c.close()
+
+
+@pytest.mark.gpu
+def test_batched_seed_only_requests():
+    import torch
+    say("serve batched: seed-only requests")
+    c = tsylv.Context(2 << 30, device=0)
+    try:
+        opts = tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-10)
+        shapes = [(40, 6, 5), (64, 12, 8), (25, 3, 2), (90, 16, 4)]
+        Xs = [tsylv.empty_device(sh, "cuda:0").zero_() for sh in shapes]
+        tickets = [c.submit(None, None, None, X, method=tsylv.GMRES_BATCHED, opts=opts,
+                            seed=50 + k) for k, X in enumerate(Xs)]
+        res = wait_all(c, tickets)
+        for k, (sh, X, t) in enumerate(zip(shapes, Xs, tickets)):
+            assert res[t][0] == 0, res[t][1].as_dict()
+            A, B, C = c.generate(50 + k, *sh)
+            X1 = torch.zeros_like(C)
+            c.gmres_batch([(A, B, C, X1)], opts=opts)
+            assert torch.equal(X, X1), k
+    finally:
+        c.close()
+
+
+@pytest.mark.gpu
+def test_batched_admission_by_arena_budget():
+    import torch
+    say("serve batched: small arena")
+    reqs = make(12, 950)
+    opts = tsylv.default_opts(tsylv.GMRES, m=20, tol=1e-10)
+    probs = [(dev(A), dev(B), dev(C)) for _, _, _, (A, B, C) in reqs]
+    one = max(tsylv.Context.batch_workspace_bytes(
+        [(a, b, cc, torch.zeros_like(cc))], opts=opts) for a, b, cc in probs)
+    c = tsylv.Context(3 * one + (1 << 20), device=0)
+    try:
+        Xs = [torch.zeros_like(cc) for _, _, cc in probs]
+        tickets = [c.submit(a, b, cc, X, method=tsylv.GMRES_BATCHED, opts=opts)
+                   for (a, b, cc), X in zip(probs, Xs)]
+        res = wait_all(c, tickets)
+        ref = tsylv.Context(1 << 30, device=0)
+        try:
+            for (a, b, cc), X, t in zip(probs, Xs, tickets):
+                assert res[t][0] == 0, res[t][1].as_dict()
+                X1 = torch.zeros_like(cc)
+                ref.gmres_batch([(a, b, cc, X1)], opts=opts)
+                assert torch.equal(X, X1)
+        finally:
+            ref.close()
+    finally:
+        c.close()
+
+
+@pytest.mark.gpu
+def test_batched_malformed_and_close_in_flight():
+    import torch
+    c = tsylv.Context(1 << 30, device=0)
+    A, B, C = workloads.dense_shifted(10, 3, 4, seed=3)
+    Ad, Bd, Cd = dev(A), dev(B), dev(C)
+    X = torch.zeros_like(Cd)
+    with pytest.raises(tsylv.TsylvError):
+        c.submit(Ad, Bd, Cd, X, method=tsylv.GMRES_BATCHED, m=64)
+    with pytest.raises(tsylv.TsylvError):
+        c.submit(Ad, Bd, Cd, X, method=tsylv.GMRES_BATCHED, refine=1, prec=tsylv.FP32)
+    o = tsylv.default_opts(tsylv.GMRES, x0_given=1)
+    with pytest.raises(tsylv.TsylvError):
+        c.submit(Ad, Bd, Cd, X, method=tsylv.GMRES_BATCHED, opts=o)
+    keep = []
+    for i in range(30):
+        A, B, C = workloads.dense_shifted(48, 8, 4, seed=960 + i)
+        t = (dev(A), dev(B), dev(C))
+        Xi = torch.zeros_like(t[2])
+        keep.append(t + (Xi,))
+        c.submit(*t, Xi, method=tsylv.GMRES_BATCHED, m=10, tol=1e-12)
+    t0 = time.time()
+    c.close()  # finishes admitted batches, cancels the queued requests
+    assert time.time() - t0 < 60
