@@ -218,7 +218,7 @@ def tiny_latency(tsylv, workloads, reps=100):
                                    "p99": float(np.percentile(lat_d, 99) * 1e6)}}}
 
 
-def _open_loop(tsylv, ctx, pool, o, rate, duration, rng):
+def _open_loop(tsylv, ctx, pool, o, rate, duration, rng, method=None):
     """Poisson arrivals (exponential gaps, `rate` per second, for `duration`
     seconds) over a pool of (A, B, C, X, ...) instances; an instance still in
     flight is not resubmitted.  Latency runs from the scheduled arrival to the
@@ -243,7 +243,8 @@ def _open_loop(tsylv, ctx, pool, o, rate, duration, rng):
                 break  # every instance in flight: try again on the next pass
             Ad, Bd, Cd, Xd = pool[nxt][:4]
             busy[nxt] = True
-            inflight[ctx.submit(Ad, Bd, Cd, Xd, method=tsylv.GMRES, opts=o)] = (nxt, arrivals[i])
+            inflight[ctx.submit(Ad, Bd, Cd, Xd, method=method if method is not None else tsylv.GMRES,
+                                opts=o)] = (nxt, arrivals[i])
             i += 1
         for t in list(inflight):
             st, info = ctx.poll(t)
@@ -257,7 +258,7 @@ def _open_loop(tsylv, ctx, pool, o, rate, duration, rng):
     return np.array(lat), bad, time.perf_counter() - t0
 
 
-def _batch(tsylv, ctx, pool, o):
+def _batch(tsylv, ctx, pool, o, method=None):
     """Every instance of the pool submitted at once; the serving loop drains
     them.  Returns (solves/s = len(pool) / time to the last completion,
     failures, completion times in s).  A fixed batch weighs every size of the
@@ -267,7 +268,8 @@ def _batch(tsylv, ctx, pool, o):
     pending = {}
     for k, inst in enumerate(pool):
         Ad, Bd, Cd, Xd = inst[:4]
-        pending[ctx.submit(Ad, Bd, Cd, Xd, method=tsylv.GMRES, opts=o)] = k
+        pending[ctx.submit(Ad, Bd, Cd, Xd, method=method if method is not None else tsylv.GMRES,
+                           opts=o)] = k
     done, bad = [], 0
     while pending:
         for t in list(pending):
@@ -308,17 +310,20 @@ def serving(tsylv, workloads, rate, duration, npool=96, seed=50):
         "fp64": tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-8, max_cycles=2000),
         "bf16": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.BF16, inner_m=24,
                                    inner_tol=1e-4, tol=1e-8, max_outer=300),
+        # FP64 requests served in lockstep batches (method GMRES_BATCHED)
+        "fp64_batched": tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-8, max_cycles=2000),
     }
+    methods = {"fp64": tsylv.GMRES, "bf16": tsylv.GMRES, "fp64_batched": tsylv.GMRES_BATCHED}
     out = {"recipe": "n log-uniform [128, 1024], s log-uniform [8, 64], p uniform {4..16}, "
                      "dense instances with p-scaled noise, Poisson arrivals %.0f/s for %.0f s, "
                      "tol 1e-8, at most 8 solves on the GPU at once; batch: the pool of %d "
                      "submitted at once" % (rate, duration, npool)}
     for name, o in opts.items():
         ctx = tsylv.Context(16 << 30, device=0)
-        lat, bad, span = _open_loop(tsylv, ctx, pool, o, rate, duration, rng)
+        lat, bad, span = _open_loop(tsylv, ctx, pool, o, rate, duration, rng, methods[name])
         ctx.close()
         ctx = tsylv.Context(16 << 30, device=0)
-        cap, bad_cap, _ = _batch(tsylv, ctx, pool, o)
+        cap, bad_cap, _ = _batch(tsylv, ctx, pool, o, methods[name])
         ctx.close()
         out[name] = {"requests": int(len(lat)), "failed": int(bad),
                      "throughput_per_s": float(len(lat) / span),
