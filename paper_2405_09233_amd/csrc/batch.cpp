@@ -41,6 +41,14 @@ namespace {
 
 constexpr int kCheckEvery = 8;
 constexpr int kVariants = 3;
+// the apply tile variants a batch uses (the FP64 defaults by s), by slot
+constexpr int kVariantIds[kVariants] = {9, 1, 2};
+
+int variant_slot(int v) {
+  for (int k = 0; k < kVariants; ++k)
+    if (kVariantIds[k] == v) return k;
+  throw Error(TSYLV_EINVAL, "batch: tile variant without a slot");
+}
 constexpr int kGroups = 1;  // independent lockstep groups per batch (see above)
 
 struct BatchPlan {
@@ -186,11 +194,11 @@ int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
       it.nchunks = (int)chunks_of(it.N);
       chunk0 += it.nchunks;
       G.items.push_back(it);
-      const int v = kern::batch_apply_variant(q.s);
+      const int vid = kern::batch_apply_variant(q.s), v = variant_slot(vid);
       kern::BatchApplyRef r;
       r.item = k;
       r.tile0 = G.plan.ntiles[v];
-      G.plan.ntiles[v] += kern::batch_apply_tiles(v, q.n, q.s, (int)q.p, &r.nrt, &r.nct);
+      G.plan.ntiles[v] += kern::batch_apply_tiles(vid, q.n, q.s, (int)q.p, &r.nrt, &r.nct);
       G.plan.refs[v].push_back(r);
     }
     G.plan.total_chunks = (int)chunk0;
@@ -225,7 +233,7 @@ int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
     for (int v = 0; v < kVariants; ++v)
       if (!G.plan.refs[v].empty())
         kern::batch_apply(G.d_items, G.d_refs[v], (int)G.plan.refs[v].size(), G.plan.ntiles[v],
-                          v, G.d_state, G.d_j, mode, s);
+                          kVariantIds[v], G.d_state, G.d_j, mode, s);
   };
   auto residual = [&](Group& G, int reduce_mode, hipStream_t s) {
     const int gc = G.plan.count;

@@ -343,6 +343,8 @@ void launch_variant(int v, ApplyArgs<Tag> a, hipStream_t st) {
     case 5: launch_apply<Tag, 128, 32, 2, 2>(a, st); break;
     case 6: launch_apply<Tag, 32, 64, 1, 2, 32>(a, st); break;  // 32-deep k panels
     case 7: launch_apply<Tag, 64, 32, 1, 2, 32>(a, st); break;
+    case 8: launch_apply<Tag, 128, 16, 2, 1, 32>(a, st); break;
+    case 9: launch_apply<Tag, 64, 16, 1, 1, 32>(a, st); break;
     default: throw Error(TSYLV_EINVAL, "apply: unknown tile variant");
   }
 }
@@ -352,7 +354,10 @@ void launch_variant(int v, ApplyArgs<Tag> a, hipStream_t st) {
 // faster at n = 4096, s = 64).
 template <typename Tag>
 int default_variant(int64_t s) {
-  if (s <= 16) return 0;
+  // FP64 at s <= 16 streams its operator (HBM-bound): 64 x 16 tiles with
+  // 32-deep k panels keep more of it in flight (1.09 vs 1.27 ms at n = 4096,
+  // p = 32)
+  if (s <= 16) return std::is_same<Tag, double>::value ? 9 : 0;
   if (s <= 32) return 1;
   return std::is_same<Tag, float>::value ? 3 : 2;
 }
@@ -361,7 +366,7 @@ int default_variant(int64_t s) {
 // tiles in refs, ascending).  STEP: W = M(V_j) for the stepping instances;
 // RESID: V_0 = Zc - M(Zx) for the instances not done.
 // (The mode is a template parameter, as in the batched vector kernels.)
-template <int TM, int TN, int RB, int CB, int MODE>
+template <int TM, int TN, int RB, int CB, int TK, int MODE>
 __global__ __launch_bounds__(NT) void apply_batch_kernel(const BatchItem* __restrict__ items,
                                                          const BatchApplyRef* __restrict__ refs,
                                                          int nref, int total,
@@ -369,7 +374,6 @@ __global__ __launch_bounds__(NT) void apply_batch_kernel(const BatchItem* __rest
                                                          const int* __restrict__ jp) {
   using M = Mma<double>;
   using L = typename M::L;
-  constexpr int TK = M::TK;
   __shared__ L As[2][TK][TM + M::PADA];
   __shared__ L Bs[2][TK][TN + M::PADB];
   const int t = xcd_tile(blockIdx.x, total);
@@ -440,15 +444,15 @@ void apply_f32(const float* Ah, const float* Bh, const float* V, float* out, con
   apply_any<float>(Ah, Bh, V, out, Y, alpha, beta, n, s, p, Bh != nullptr, variant, st);
 }
 
-template <int TM, int TN, int RB, int CB>
+template <int TM, int TN, int RB, int CB, int TK = Mma<double>::TK>
 static void launch_batch(const BatchItem* items, const BatchApplyRef* refs, int nref, int total,
                          BatchState* st, const int* jp, int mode, hipStream_t s) {
   if (mode == BM_STEP)
-    hipLaunchKernelGGL((apply_batch_kernel<TM, TN, RB, CB, BM_STEP>), dim3(total), dim3(NT), 0, s,
-                       items, refs, nref, total, st, jp);
-  else if (mode == BM_RESID)
-    hipLaunchKernelGGL((apply_batch_kernel<TM, TN, RB, CB, BM_RESID>), dim3(total), dim3(NT), 0,
+    hipLaunchKernelGGL((apply_batch_kernel<TM, TN, RB, CB, TK, BM_STEP>), dim3(total), dim3(NT), 0,
                        s, items, refs, nref, total, st, jp);
+  else if (mode == BM_RESID)
+    hipLaunchKernelGGL((apply_batch_kernel<TM, TN, RB, CB, TK, BM_RESID>), dim3(total), dim3(NT),
+                       0, s, items, refs, nref, total, st, jp);
   else
     throw Error(TSYLV_EINVAL, "batch apply: mode");
 }
@@ -460,6 +464,7 @@ void batch_apply(const BatchItem* items, const BatchApplyRef* refs, int nref, in
     case 0: launch_batch<128, 16, 2, 1>(items, refs, nref, total_tiles, st, jp, mode, st_); break;
     case 1: launch_batch<64, 32, 1, 2>(items, refs, nref, total_tiles, st, jp, mode, st_); break;
     case 2: launch_batch<32, 64, 1, 2>(items, refs, nref, total_tiles, st, jp, mode, st_); break;
+    case 9: launch_batch<64, 16, 1, 1, 32>(items, refs, nref, total_tiles, st, jp, mode, st_); break;
     default: throw Error(TSYLV_EINVAL, "batch apply: unsupported tile variant");
   }
   TSYLV_LAUNCH_CHECK();
@@ -469,13 +474,20 @@ void batch_apply(const BatchItem* items, const BatchApplyRef* refs, int nref, in
 // instance computes the same bits in any batch.
 int batch_apply_variant(int64_t s) { return default_variant<double>(s); }
 int batch_apply_tiles(int variant, int64_t n, int64_t s, int p, int* nrt, int* nct) {
-  static const int tm[3] = {128, 64, 32}, tn[3] = {16, 32, 64};
-  *nrt = (int)((n + tm[variant] - 1) / tm[variant]);
-  *nct = (int)((s + tn[variant] - 1) / tn[variant]);
+  int tm, tn;
+  switch (variant) {
+    case 0: tm = 128; tn = 16; break;
+    case 1: tm = 64; tn = 32; break;
+    case 2: tm = 32; tn = 64; break;
+    case 9: tm = 64; tn = 16; break;
+    default: throw Error(TSYLV_EINVAL, "batch apply: unsupported tile variant");
+  }
+  *nrt = (int)((n + tm - 1) / tm);
+  *nct = (int)((s + tn - 1) / tn);
   return num_slices(p) * *nrt * *nct;
 }
 
-int apply_variant_count(int prec) { return prec == TSYLV_BF16 ? 4 : 8; }
+int apply_variant_count(int prec) { return prec == TSYLV_BF16 ? 4 : 10; }
 
 int apply_default_variant(int prec, int64_t s) {
   if (prec == TSYLV_FP64) return default_variant<double>(s);
