@@ -35,6 +35,7 @@
 
 #include "krylov_task.hpp"
 #include "runtime.hpp"
+#include "sched_policy.hpp"
 #include "serve.hpp"
 #include "solvers.hpp"
 
@@ -132,24 +133,47 @@ struct Scheduler {
     done[ticket] = {status, i};
   }
 
-  // Admits queued requests (FIFO) while slots and arena memory allow.
+  // Admits queued requests while slots and arena memory allow, as the
+  // admission policy (sched_policy.hpp) decides.
   void admit() {
     std::unique_lock<std::mutex> lk(mu);
-    while (!queue.empty() && !free_slots.empty()) {
-      if (queue.front().r.method == TSYLV_METHOD_GMRES_BATCHED) {
-        if (!admit_batch(lk)) break;
+    for (;;) {
+      // the batched requests at the head as problems, for the batch sizes
+      std::vector<tsylv_problem> probs;
+      for (size_t i = 0; i < queue.size() && (int)i < kMaxBatch &&
+                         queue[i].r.method == TSYLV_METHOD_GMRES_BATCHED;
+           ++i) {
+        const tsylv_request& r = queue[i].r;
+        probs.push_back(tsylv_problem{r.n, r.s, r.p, r.A, r.B, r.C, r.X});
+      }
+      policy::QueueView v;
+      v.size = queue.size();
+      v.batched = [&](size_t i) { return queue[i].r.method == TSYLV_METHOD_GMRES_BATCHED; };
+      v.batchable = [&](size_t i, size_t j) {
+        return same_batch_opts(queue[i].r.opts, queue[j].r.opts);
+      };
+      v.need_single = [&](size_t i) {
+        const tsylv_request& r = queue[i].r;
+        return krylov_workspace_bytes(r.method, r.n, r.s, r.p, r.opts);
+      };
+      v.need_batch = [&](size_t k) {
+        return batch_workspace_bytes((int)k, probs.data(), queue.front().r.opts);
+      };
+      const policy::Decision d = policy::next_admission(
+          v, free_slots.size(), ctx.arena.largest_free(), ctx.arena.capacity(), kMaxBatch);
+      if (d.kind == policy::Kind::Wait) return;
+      if (d.kind == policy::Kind::Reject) {
+        tsylv_info inf{};
+        inf.status = TSYLV_ENOMEM;
+        done[queue.front().ticket] = {TSYLV_ENOMEM, inf};
+        queue.pop_front();
+        continue;
+      }
+      if (d.kind == policy::Kind::Batch) {
+        start_batch(lk, d.count);
         continue;
       }
       Queued q = queue.front();
-      const size_t need = krylov_workspace_bytes(q.r.method, q.r.n, q.r.s, q.r.p, q.r.opts);
-      if (need > ctx.arena.capacity()) {  // can never fit
-        queue.pop_front();
-        tsylv_info inf{};
-        inf.status = TSYLV_ENOMEM;
-        done[q.ticket] = {TSYLV_ENOMEM, inf};
-        continue;
-      }
-      if (need > ctx.arena.largest_free()) break;  // wait for memory, keep FIFO order
       queue.pop_front();
       const int slot = free_slots.back();
       free_slots.pop_back();
@@ -166,7 +190,7 @@ struct Scheduler {
           lk.lock();
           queue.push_front(q);
           free_slots.push_back(slot);
-          break;
+          return;
         }
         a.error = e.status;
       } catch (...) {
@@ -177,42 +201,21 @@ struct Scheduler {
     }
   }
 
-  // The GMRES_BATCHED requests at the head of the queue with the options of
-  // the first one, as many as fit in the arena, become one batch on a free
-  // slot.  Returns false when the head must wait for memory.  Called with mu
-  // held (lk); returns with it held.
-  bool admit_batch(std::unique_lock<std::mutex>& lk) {
+  // The first `count` requests of the queue (batched, with equal options)
+  // become one batch on a free slot.  Called with mu held (lk); returns with
+  // it held.
+  void start_batch(std::unique_lock<std::mutex>& lk, size_t count) {
     const tsylv_opts o = queue.front().r.opts;
-    std::vector<tsylv_problem> probs;
-    size_t k = 0;
-    for (; k < queue.size() && (int)k < kMaxBatch; ++k) {
-      const tsylv_request& r = queue[k].r;
-      if (r.method != TSYLV_METHOD_GMRES_BATCHED || !same_batch_opts(r.opts, o)) break;
-      probs.push_back(tsylv_problem{r.n, r.s, r.p, r.A, r.B, r.C, r.X});
-    }
-    // the longest prefix whose workspace fits
-    const size_t free_b = ctx.arena.largest_free();
-    size_t take = k;
-    while (take > 0 && batch_workspace_bytes((int)take, probs.data(), o) > free_b) --take;
-    if (take == 0) {
-      if (batch_workspace_bytes(1, probs.data(), o) > ctx.arena.capacity()) {  // never fits
-        tsylv_info inf{};
-        inf.status = TSYLV_ENOMEM;
-        done[queue.front().ticket] = {TSYLV_ENOMEM, inf};
-        queue.pop_front();
-        return true;
-      }
-      return false;
-    }
     std::unique_ptr<BatchJob> job(new BatchJob());
-    for (size_t i = 0; i < take; ++i) {
+    for (size_t i = 0; i < count; ++i) {
+      const tsylv_request& r = queue.front().r;
       job->tickets.push_back(queue.front().ticket);
-      job->reqs.push_back(queue.front().r);
+      job->reqs.push_back(r);
+      job->probs.push_back(tsylv_problem{r.n, r.s, r.p, r.A, r.B, r.C, r.X});
       queue.pop_front();
     }
-    job->probs.assign(probs.begin(), probs.begin() + (long)take);
-    job->infos.resize(take);
-    for (size_t i = 0; i < take; ++i)
+    job->infos.resize(count);
+    for (size_t i = 0; i < count; ++i)
       job->gens.push_back(job->reqs[i].A ? nullptr : &job->reqs[i].gen_seed);
     const int slot = free_slots.back();
     free_slots.pop_back();
@@ -237,7 +240,6 @@ struct Scheduler {
     a.job = std::move(job);
     active.push_back(std::move(a));
     lk.lock();
-    return true;
   }
 
   // A finished batch: every result posted (an arena shortfall puts the
