@@ -17,9 +17,9 @@ Contents (each function cites the passage of the paper it follows):
   system on tiny inputs.
 
 Every routine works in float64 (complex128 where the paper's objects are
-complex) with numpy's own summation order.  Readings of passages that are
-ambiguous or garbled in the paper are listed in the design doc and repeated in
-the docstrings where they apply.
+complex) with numpy's own summation order.  Where a passage of the paper is
+ambiguous or garbled, the docstring of the routine that depends on it states
+the reading taken.
 """
 
 from . import tproduct, krylov, tbs, kron  # noqa: F401
