@@ -25,6 +25,7 @@
 // batch when the worker ends.  An instance's result in a batch is bitwise its
 // batch-of-one result (graph or eager: the same kernels).
 #include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <memory>
@@ -264,6 +265,7 @@ struct Scheduler {
 
   void run() {
     (void)hipSetDevice(ctx.device);
+    int idle_passes = 0;
     for (;;) {
       admit();
       {
@@ -298,7 +300,15 @@ struct Scheduler {
           a.error = TSYLV_EHIP;
         }
       }
-      if (!progressed) std::this_thread::yield();
+      // nothing ready: yield, and after a while of nothing back off briefly
+      // (a phase takes tens of microseconds at least) instead of spinning
+      if (progressed) {
+        idle_passes = 0;
+      } else if (++idle_passes < 256) {
+        std::this_thread::yield();
+      } else {
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+      }
       // retire finished and failed solves; their workspace returns to the arena
       for (size_t i = 0; i < active.size();) {
         Active& a = active[i];
