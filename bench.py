@@ -310,10 +310,13 @@ def serving(tsylv, workloads, rate, duration, npool=96, seed=50):
         "fp64": tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-8, max_cycles=2000),
         "bf16": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.BF16, inner_m=24,
                                    inner_tol=1e-4, tol=1e-8, max_outer=300),
+        "fp32": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.FP32, inner_m=24,
+                                   inner_tol=1e-4, tol=1e-8, max_outer=300),
         # FP64 requests served in lockstep batches (method GMRES_BATCHED)
         "fp64_batched": tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-8, max_cycles=2000),
     }
-    methods = {"fp64": tsylv.GMRES, "bf16": tsylv.GMRES, "fp64_batched": tsylv.GMRES_BATCHED}
+    methods = {"fp64": tsylv.GMRES, "bf16": tsylv.GMRES, "fp32": tsylv.GMRES,
+               "fp64_batched": tsylv.GMRES_BATCHED}
     out = {"recipe": "n log-uniform [128, 1024], s log-uniform [8, 64], p uniform {4..16}, "
                      "dense instances with p-scaled noise, Poisson arrivals %.0f/s for %.0f s, "
                      "tol 1e-8, at most 8 solves on the GPU at once; batch: the pool of %d "
@@ -394,6 +397,8 @@ def serving_full(tsylv, rate=40.0, duration=10.0, nbatch=128, seed=50):
         "fp64": tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-8, max_cycles=2000),
         "bf16": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.BF16, inner_m=24,
                                    inner_tol=1e-4, tol=1e-8, max_outer=300),
+        "fp32": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.FP32, inner_m=24,
+                                   inner_tol=1e-4, tol=1e-8, max_outer=300),
     }
     out = {"recipe": "n log-uniform [128, 4096], s log-uniform [8, 256], p uniform {4..64}; each "
                      "request carries its id as seed and draws its dense p-scaled-noise instance "
@@ -420,6 +425,8 @@ def serving_full(tsylv, rate=40.0, duration=10.0, nbatch=128, seed=50):
                 name, nbatch, nbatch / span_b, rate, len(lat), out[name]["latency_ms"]["p50"],
                 out[name]["latency_ms"]["p99"], bad_b, bad))
     out["bf16_vs_fp64_batch"] = (out["bf16"]["batch_solves_per_s"]
+                                 / max(out["fp64"]["batch_solves_per_s"], 1e-30))
+    out["fp32_vs_fp64_batch"] = (out["fp32"]["batch_solves_per_s"]
                                  / max(out["fp64"]["batch_solves_per_s"], 1e-30))
     return out
 
