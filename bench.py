@@ -53,12 +53,14 @@ def log(*a):
 def apply_work(n, s, p, elem):
     """Algorithmic flops and HBM bytes of one facewise apply
     W = Ahat V - V Bhat on the half spectrum: real slices (DC, and Nyquist for
-    even p) cost 2(n^2 s + n s^2) flops, complex slices 8(n^2 s + n s^2);
+    even p) cost 2(n^2 s + n s^2) flops, complex slices 6(n^2 s + n s^2)
+    (three real products in Gauss's form, as the FP64/FP32 kernels compute
+    them; the HBM-bound BF16 kernel spends four);
     bytes = the p planes of Ahat and Bhat (elem bytes each) read once, V read
     and W written once (vector element size vbytes)."""
     n_real = 2 if p % 2 == 0 else 1
     n_cplx = (p - n_real) // 2
-    flops = (2 * n_real + 8 * n_cplx) * (n * n * s + n * s * s)
+    flops = (2 * n_real + 6 * n_cplx) * (n * n * s + n * s * s)
     ab, vb = elem
     bytes_ = p * (ab * (n * n + s * s) + 2 * vb * n * s)
     return flops, bytes_

@@ -9,9 +9,13 @@
 // K = n + s:
 //     W_k = [ Ahat_k | -V_k ] [ V_k ; Bhat_k ],
 // so the whole apply is a batched complex GEMM with the small V_k Bhat_k
-// term riding in the last K panels.  A complex product is four real MFMAs
-// per block (Re += Ar Vr - Ai Vi, Im += Ar Vi + Ai Vr).  The Tubal Block
-// Arnoldi process needs Ahat_k V_k alone (useB = 0, K = n).
+// term riding in the last K panels.  A complex product is three real MFMAs
+// per block (Gauss's three-multiplication form: T1 = Ar Vr, T2 = Ai Vi,
+// T3 = (Ar + Ai)(Vr + Vi), then Re = T1 - T2 and Im = T3 - T1 - T2 in the
+// epilogue), a quarter fewer matrix-core cycles than the four-product form
+// at the same operand traffic; the operand sums are formed per fragment from
+// the LDS panels.  The Tubal Block Arnoldi process needs Ahat_k V_k alone
+// (useB = 0, K = n).
 //
 // Tiling: a workgroup (4 waves) owns a TM x TN tile of W_k and streams the
 // TM rows of [Ahat_k | -V_k] once through LDS in TK-deep panels; the
@@ -59,7 +63,6 @@ struct Mma<double> {
   __device__ static L neg(L x) { return -x; }
   template <int LD>
   __device__ static frag ld(const L (*S)[LD], int ks, int lk, int i) { return S[ks + lk][i]; }
-  __device__ static frag negf(frag x) { return -x; }
   __device__ static acc_t mma(frag a, frag b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -85,7 +88,6 @@ struct Mma<float> {
   __device__ static L neg(L x) { return -x; }
   template <int LD>
   __device__ static frag ld(const L (*S)[LD], int ks, int lk, int i) { return S[ks + lk][i]; }
-  __device__ static frag negf(frag x) { return -x; }
   __device__ static acc_t mma(frag a, frag b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -155,13 +157,15 @@ __device__ __forceinline__ void apply_tile(
   const int wr = wave % WR, wc = wave / WR;
   const int lr = lane & 15, lk = lane >> 4;
 
-  acc_t accr[RB][CB], acci[RB][CB];
+  // real slices: accr = Ar Vr; complex: accr = T1, acci = T2, accs = T3
+  acc_t accr[RB][CB], acci[RB][CB], accs[RB][CB];
 #pragma unroll
   for (int i = 0; i < RB; ++i)
 #pragma unroll
     for (int j = 0; j < CB; ++j) {
       accr[i][j] = M::zero();
       acci[i][j] = M::zero();
+      accs[i][j] = M::zero();
     }
 
   L pa_r[NA], pa_i[NA], pb_r[NB], pb_i[NB];
@@ -235,14 +239,14 @@ __device__ __forceinline__ void apply_tile(
     if (k0 + TK < K) load_panels(k0 + TK);  // in flight during the MFMAs below
 #pragma unroll
     for (int ks = 0; ks < TK; ks += KB) {
-      frag far_[RB], fai[RB], fain[RB], fbr[CB], fbi[CB];
+      frag far_[RB], fai[RB], fas[RB], fbr[CB], fbi[CB], fbs[CB];
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
         const int row = (wr * RB + i) * 16 + lr;
         far_[i] = M::template ld<TM + M::PADA>(As[0], ks, lk, row);
         if (CPLX) {
           fai[i] = M::template ld<TM + M::PADA>(As[1], ks, lk, row);
-          fain[i] = M::negf(fai[i]);
+          fas[i] = far_[i] + fai[i];
         }
       }
 #pragma unroll
@@ -250,26 +254,23 @@ __device__ __forceinline__ void apply_tile(
         // ks is a multiple of 4, so (ks + lk) & SWB == ks & SWB
         const int col = ((wc * CB + j) * 16 + lr) ^ (ks & M::SWB);
         fbr[j] = M::template ld<TN + M::PADB>(Bs[0], ks, lk, col);
-        if (CPLX) fbi[j] = M::template ld<TN + M::PADB>(Bs[1], ks, lk, col);
+        if (CPLX) {
+          fbi[j] = M::template ld<TN + M::PADB>(Bs[1], ks, lk, col);
+          fbs[j] = fbr[j] + fbi[j];
+        }
       }
-      // Dependent MFMAs on one accumulator are kept apart: a full sweep
-      // over the blocks separates the two updates of every accumulator.
+      // Every accumulator is updated once per k step, so a full sweep over
+      // the blocks separates dependent MFMAs.
 #pragma unroll
       for (int i = 0; i < RB; ++i)
 #pragma unroll
         for (int j = 0; j < CB; ++j) {
           accr[i][j] = M::mma(far_[i], fbr[j], accr[i][j]);
-          if (CPLX) acci[i][j] = M::mma(far_[i], fbi[j], acci[i][j]);
-        }
-      if (CPLX) {
-#pragma unroll
-        for (int i = 0; i < RB; ++i)
-#pragma unroll
-          for (int j = 0; j < CB; ++j) {
-            accr[i][j] = M::mma(fain[i], fbi[j], accr[i][j]);
-            acci[i][j] = M::mma(fai[i], fbr[j], acci[i][j]);
+          if (CPLX) {
+            acci[i][j] = M::mma(fai[i], fbi[j], acci[i][j]);
+            accs[i][j] = M::mma(fas[i], fbs[j], accs[i][j]);
           }
-      }
+        }
     }
     __syncthreads();
   }
@@ -291,14 +292,19 @@ __device__ __forceinline__ void apply_tile(
         const int64_t row = m0 + (wr * RB + i) * 16 + M::row(r, lk);
         if (row >= n) continue;
         const int64_t off = row + n * col;
-        double vr = a.alpha * (double)accr[i][j][r];
-        if (a.beta != 0.0) vr = fma(a.beta, (double)Yr[off], vr);
-        Or[off] = (TV)vr;
+        const double t1 = (double)accr[i][j][r];
+        double vr;
         if (CPLX) {
-          double vi = a.alpha * (double)acci[i][j][r];
+          const double t2 = (double)acci[i][j][r];
+          vr = a.alpha * (t1 - t2);
+          double vi = a.alpha * ((double)accs[i][j][r] - t1 - t2);
           if (a.beta != 0.0) vi = fma(a.beta, (double)Yi[off], vi);
           Oi[off] = (TV)vi;
+        } else {
+          vr = a.alpha * t1;
         }
+        if (a.beta != 0.0) vr = fma(a.beta, (double)Yr[off], vr);
+        Or[off] = (TV)vr;
       }
     }
 }
@@ -349,17 +355,18 @@ void launch_variant(int v, ApplyArgs<Tag> a, hipStream_t st) {
   }
 }
 
-// Without a tuned choice: a column tile as wide as s needs (up to 64), so
-// small s does not waste MFMA work; FP32 at s > 32 takes 64 x 64 tiles (5 %
-// faster at n = 4096, s = 64).
+// Without a tuned choice: a column tile as wide as s needs, so small s does
+// not waste MFMA work; at s > 32 FP64 takes 64 x 32 tiles (2.81 vs 2.87 ms
+// for 32 x 64 at n = 4096, s = 64, p = 32) and FP32 64 x 64 (17.1 vs 18.0 ms
+// for 64 x 32 at n = 8192, s = 128, p = 64).
 template <typename Tag>
 int default_variant(int64_t s) {
   // FP64 at s <= 16 streams its operator (HBM-bound): 64 x 16 tiles with
-  // 32-deep k panels keep more of it in flight (1.09 vs 1.27 ms at n = 4096,
-  // p = 32)
+  // 32-deep k panels keep more of it in flight (1.01 vs 1.48 ms for
+  // 128 x 16 at n = 4096, p = 32)
   if (s <= 16) return std::is_same<Tag, double>::value ? 9 : 0;
   if (s <= 32) return 1;
-  return std::is_same<Tag, float>::value ? 3 : 2;
+  return std::is_same<Tag, float>::value ? 3 : 1;
 }
 
 // Batched apply: the tiles of many instances in one launch (their first

@@ -415,23 +415,24 @@ __device__ __forceinline__ void bf16_wg_tasks(const Bf16Args& a, const WgPlan& p
 #pragma unroll
       for (int u = 0; u < P; ++u) {
         const int d = u % D;
-        bf8 br[CB], bi[CB];
+        bf8 mai[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (CPLX) mai[r] = neg8(ai[d][r]);
+        // one column block's V fragments at a time (fewer live registers,
+        // so a deeper operator ring fits)
 #pragma unroll
         for (int j = 0; j < CB; ++j) {
-          br[j] = frag(buf, u, 0, j);
-          if (CPLX) bi[j] = frag(buf, u, 1, j);
-        }
+          const bf8 br = frag(buf, u, 0, j);
+          bf8 bi;
+          if (CPLX) bi = frag(buf, u, 1, j);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          bf8 mai;
-          if (CPLX) mai = neg8(ai[d][r]);
-#pragma unroll
-          for (int j = 0; j < CB; ++j) {
-            accr[r][j] = mma(ar[d][r], br[j], accr[r][j]);
+          for (int r = 0; r < R; ++r) {
+            accr[r][j] = mma(ar[d][r], br, accr[r][j]);
             if (CPLX) {
-              acci[r][j] = mma(ar[d][r], bi[j], acci[r][j]);
-              accr[r][j] = mma(mai, bi[j], accr[r][j]);
-              acci[r][j] = mma(ai[d][r], br[j], acci[r][j]);
+              acci[r][j] = mma(ar[d][r], bi, acci[r][j]);
+              accr[r][j] = mma(mai[r], bi, accr[r][j]);
+              acci[r][j] = mma(ai[d][r], br, acci[r][j]);
             }
           }
         }
@@ -552,6 +553,10 @@ void tile_operator_bf16(const double* Ah, uint16_t* At, int64_t n, int p, hipStr
 // Variants (column blocks, ring depth, phase length, waves, row blocks per
 // wave), the autotuner's candidates; the default per s is the best of a
 // sweep at n = 4096, p = 32, s = 16 / 32 / 64 and n = 8192, p = 64, s = 128.
+// Deeper rings and longer phases (4/4/4/8/2, 4/2/8/8/2) fit in registers but
+// measured the same as variant 2 at n = 4096, s = 64, p = 32 (the kernel is
+// not short of loads in flight there), and two 4-wave workgroups per CU
+// (4/2/2/4/2), 1 % faster alone, 3 % slower inside a solve.
 template <bool TIO>
 void launch_cfg(const Bf16Args& a, int variant, hipStream_t st) {
   static int ncu_cached[64] = {};
