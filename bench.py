@@ -42,7 +42,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "tGMRES solves/s at relres 1e-8, mixed vs FP64; p50/p99 solve latency"
 PEAKS = {  # MI355X dense peaks, FLOP/s
-    "fp64": 78.6e12, "mixed": 157.3e12, "bf16": 2.5e15}
+    "fp64": 78.6e12, "mixed": 157.3e12, "bf16": 2.5e15, "tba": 78.6e12}
 PEAK_HBM = 8.0e12
 
 
@@ -703,7 +703,8 @@ def main():
     # basis that way (fused Gram-Schmidt: inner_m + 1 <= 64), else FP32
     bf16_tiled = (os.environ.get("TSYLV_BF16_BASIS") != "fp32"
                   and path_opts["bf16"].inner_m + 1 <= 64) if best == "bf16" else False
-    elem = {"fp64": (8, 8), "mixed": (4, 4), "bf16": (2, 2) if bf16_tiled else (2, 4)}[best]
+    elem = {"fp64": (8, 8), "mixed": (4, 4), "bf16": (2, 2) if bf16_tiled else (2, 4),
+            "tba": (8, 8)}[best]
     flops, bytes_ = apply_work(n, s, p, elem)
     avg_s = r["apply_avg_ms"] / 1e3
     achieved_flops = flops / avg_s
@@ -716,6 +717,8 @@ def main():
         roofline = {"bound": "mfma", "achieved": achieved_flops / 1e12, "peak": peak / 1e12,
                     "unit": "TFLOP/s", "frac": achieved_flops / peak}
     kernel = {"fp64": "apply_mfma_kernel<double> (FP64 slice products)",
+              "tba": "apply_mfma_kernel<double> (FP64 A-only slice products; counted with the "
+                     "small V Bhat term, which this apply skips)",
               "mixed": "apply_mfma_kernel<float> (FP32 slice products)",
               "bf16": ("apply_bf16_wg_kernel (BF16 slice products on tiled BF16 vectors; "
                        "one launch per apply call)") if bf16_tiled else
@@ -726,7 +729,7 @@ def main():
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_bytes_per_launch": bytes_})
 
-    dtype = {"fp64": "f64", "mixed": "f32 (inner) + f64 (refinement)",
+    dtype = {"fp64": "f64", "tba": "f64", "mixed": "f32 (inner) + f64 (refinement)",
              "bf16": "bf16 x bf16 -> f32 (inner; BF16 basis) + f64 (refinement)"
              if bf16_tiled else "bf16 x bf16 -> f32 (inner) + f64 (refinement)"}[best]
     out = {
