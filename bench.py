@@ -10,7 +10,7 @@ Paths timed (each: W warm-up solves, then K timed solves):
   fp64      restarted tGMRES(30), everything FP64
   mixed     FP64 iterative refinement; each correction one tGMRES(32) cycle
             with FP32 basis vectors and FP32 MFMA slice products
-  bf16      the same (tGMRES(24) cycles) with BF16 slice products (FP32
+  bf16      the same (tGMRES(28) cycles) with BF16 slice products (FP32
             accumulation) and the inner basis kept as tiled BF16 vectors
             (TSYLV_BF16_BASIS=fp32 keeps FP32 vectors instead)
   tba       TBAS(10), reported beside them (not a candidate for `value`)
@@ -599,7 +599,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--m", type=int, default=30)
     ap.add_argument("--inner-m", type=int, default=0,
-                    help="inner restart length of the refined paths (default: 24 for the "
+                    help="inner restart length of the refined paths (default: 28 for the "
                          "BF16 path, 32 for the FP32 path, the fastest in a sweep of 16..48)")
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -668,7 +668,7 @@ def main():
                                     inner_m=args.inner_m or 32,
                                     inner_tol=args.inner_tol, tol=args.tol, max_outer=2000),
         "bf16": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.BF16,
-                                   inner_m=args.inner_m or 24,
+                                   inner_m=args.inner_m or 28,
                                    inner_tol=args.inner_tol, tol=args.tol, max_outer=300),
         # TBAS(10), reported beside the tGMRES paths (not a candidate for value)
         "tba": tsylv.default_opts(tsylv.TBA, m=10, tol=args.tol, max_cycles=500),
