@@ -357,7 +357,8 @@ void launch_variant(int v, ApplyArgs<Tag> a, hipStream_t st) {
 
 // Without a tuned choice: a column tile as wide as s needs, so small s does
 // not waste MFMA work; at s > 32 FP64 takes 64 x 32 tiles (2.81 vs 2.87 ms
-// for 32 x 64 at n = 4096, s = 64, p = 32) and FP32 64 x 64 (17.1 vs 18.0 ms
+// for 32 x 64 at n = 4096, s = 64, p = 32), FP32 64 x 32 up to s = 64 (1.32
+// vs 1.39 ms for 64 x 64 at that shape) and 64 x 64 beyond (17.1 vs 18.0 ms
 // for 64 x 32 at n = 8192, s = 128, p = 64).
 template <typename Tag>
 int default_variant(int64_t s) {
@@ -366,7 +367,7 @@ int default_variant(int64_t s) {
   // 128 x 16 at n = 4096, p = 32)
   if (s <= 16) return std::is_same<Tag, double>::value ? 9 : 0;
   if (s <= 32) return 1;
-  return std::is_same<Tag, float>::value ? 3 : 1;
+  return (std::is_same<Tag, float>::value && s > 64) ? 3 : 1;
 }
 
 // Batched apply: the tiles of many instances in one launch (their first
