@@ -10,7 +10,8 @@ void Arena::init(char* base, size_t bytes) {
   used_.clear();
   // keep the first block 256-byte aligned
   size_t skew = (size_t)((256 - ((uintptr_t)base % 256)) % 256);
-  if (bytes > skew) free_[skew] = bytes - skew;
+  usable_ = bytes > skew ? bytes - skew : 0;
+  if (usable_ > 0) free_[skew] = usable_;
 }
 
 void* Arena::alloc(size_t bytes) {

@@ -21,13 +21,15 @@ class Arena {
   // Returns nullptr when no free block is large enough.
   void* alloc(size_t bytes);
   void free(void* ptr);
-  size_t capacity() const { return size_; }
+  // Usable bytes: the buffer minus the skew that aligns its first block.
+  size_t capacity() const { return usable_; }
   size_t in_use() const;
   size_t largest_free() const;
 
  private:
   char* base_ = nullptr;
   size_t size_ = 0;
+  size_t usable_ = 0;
   std::map<size_t, size_t> free_;  // offset -> size
   std::map<size_t, size_t> used_;  // offset -> size
   mutable std::mutex mu_;

@@ -12,9 +12,13 @@
 //      the slowest;
 //   3. retire finished solves, freeing their slot and workspace.
 // A request therefore joins while others are mid-solve and its work overlaps
-// theirs.  Each solve runs exactly the kernels and host arithmetic of a
-// synchronous call (the same KrylovTask; reductions are fixed-order), so its
-// result is bitwise the same alone or in a mix.
+// theirs.  tsylv_submit records an event on the context stream; the slot's
+// stream waits on it before the request's first kernel, so work the caller
+// enqueued on that stream before submitting (filling A, B, C or X0) is
+// finished when the solve reads its inputs.  Each solve runs exactly the
+// kernels and host arithmetic of a synchronous call (the same KrylovTask;
+// reductions are fixed-order), so its result is bitwise the same alone or in
+// a mix.
 //
 // Requests of method GMRES_BATCHED that wait at the head of the queue with
 // equal options are admitted together, up to kMaxBatch of them and as many as
@@ -57,6 +61,7 @@ bool same_batch_opts(const tsylv_opts& a, const tsylv_opts& b) {
 struct BatchJob {
   std::vector<uint64_t> tickets;
   std::vector<tsylv_request> reqs;
+  std::vector<hipEvent_t> ready;  // the requests' submit events
   std::vector<tsylv_problem> probs;
   std::vector<const uint64_t*> gens;
   std::vector<tsylv_info> infos;
@@ -76,6 +81,7 @@ struct Scheduler {
   struct Queued {
     uint64_t ticket;
     tsylv_request r;
+    hipEvent_t ready;  // recorded on the context stream at submit
   };
   std::deque<Queued> queue;
   struct Record {
@@ -91,6 +97,7 @@ struct Scheduler {
     int slot;
     std::unique_ptr<KrylovTask> task;
     int error = 0;
+    hipEvent_t ready = nullptr;  // the submit event (destroyed at retirement)
     bool in_flight = false;  // a phase is enqueued and not yet completed
     std::unique_ptr<BatchJob> job;  // a lockstep batch instead of one task
   };
@@ -117,6 +124,7 @@ struct Scheduler {
         tsylv_info inf{};
         inf.status = TSYLV_ECANCELLED;
         done[q.ticket] = {TSYLV_ECANCELLED, inf};
+        if (q.ready) (void)hipEventDestroy(q.ready);
       }
       queue.clear();
     }
@@ -167,6 +175,7 @@ struct Scheduler {
         tsylv_info inf{};
         inf.status = TSYLV_ENOMEM;
         done[queue.front().ticket] = {TSYLV_ENOMEM, inf};
+        if (queue.front().ready) (void)hipEventDestroy(queue.front().ready);
         queue.pop_front();
         continue;
       }
@@ -180,14 +189,22 @@ struct Scheduler {
       free_slots.pop_back();
       lk.unlock();
       Active a{q.ticket, slot, nullptr, 0};
+      a.ready = q.ready;
       try {
         if (KrylovTask::pinned_doubles(q.r.opts) > kPinnedPerSlot)
           throw Error(TSYLV_EINVAL, "serve: restart length too large");
+        // the caller's work on the context stream before submit comes first
+        // (the task's constructor already enqueues the setup transforms)
+        if (a.ready) TSYLV_HIP(hipStreamWaitEvent(streams[slot], a.ready, 0));
         a.task.reset(new KrylovTask(ctx, streams[slot], false, pinned + slot * kPinnedPerSlot,
                                     q.r.method, q.r.n, q.r.s, q.r.p, q.r.A, q.r.B, q.r.C, q.r.X,
                                     q.r.opts, q.r.A ? nullptr : &q.r.gen_seed));
       } catch (const Error& e) {
-        if (e.status == TSYLV_ENOMEM) {  // fragmentation: retry later, at the head
+        // Fragmentation or a synchronous call holding arena memory: retry
+        // later, at the head, while other solves run (they return memory);
+        // with none active nothing would change, so the request fails.
+        if (e.status == TSYLV_ENOMEM && !active.empty()) {
+          a.task.reset();
           lk.lock();
           queue.push_front(q);
           free_slots.push_back(slot);
@@ -212,6 +229,7 @@ struct Scheduler {
       const tsylv_request& r = queue.front().r;
       job->tickets.push_back(queue.front().ticket);
       job->reqs.push_back(r);
+      job->ready.push_back(queue.front().ready);
       job->probs.push_back(tsylv_problem{r.n, r.s, r.p, r.A, r.B, r.C, r.X});
       queue.pop_front();
     }
@@ -226,6 +244,8 @@ struct Scheduler {
     jp->th = std::thread([this, jp, st, o]() {
       try {
         TSYLV_HIP(hipSetDevice(ctx.device));
+        for (hipEvent_t e : jp->ready)
+          if (e) TSYLV_HIP(hipStreamWaitEvent(st, e, 0));
         // launched eagerly: a graph capture on this worker thread would make
         // the caller's concurrent work on the legacy default stream fail
         gmres_batch(ctx, st, (int)jp->probs.size(), jp->probs.data(), jp->gens.data(), o,
@@ -251,10 +271,14 @@ struct Scheduler {
     if (j.error == TSYLV_ENOMEM && active.size() > 1) {  // others hold memory: retry
       std::lock_guard<std::mutex> g(mu);
       if (!stopping) {
-        for (size_t i = j.tickets.size(); i-- > 0;) queue.push_front({j.tickets[i], j.reqs[i]});
+        for (size_t i = j.tickets.size(); i-- > 0;)
+          queue.push_front({j.tickets[i], j.reqs[i], j.ready[i]});
         return;
       }
     }
+    (void)hipStreamSynchronize(streams[a.slot]);
+    for (hipEvent_t e : j.ready)
+      if (e) (void)hipEventDestroy(e);
     for (size_t i = 0; i < j.tickets.size(); ++i) {
       if (j.error)
         finish(j.tickets[i], j.error, nullptr);
@@ -272,7 +296,10 @@ struct Scheduler {
         std::unique_lock<std::mutex> lk(mu);
         if (active.empty()) {
           if (stopping && queue.empty()) return;
-          cv.wait(lk, [&]() { return stopping || !queue.empty(); });
+          if (queue.empty())
+            cv.wait(lk, [&]() { return stopping || !queue.empty(); });
+          else  // the head waits for memory held outside the loop: back off
+            cv.wait_for(lk, std::chrono::microseconds(200));
           continue;
         }
       }
@@ -331,12 +358,13 @@ struct Scheduler {
           continue;
         }
         if (a.error) {
-          if (a.task) (void)hipStreamSynchronize(a.task->stream());
+          (void)hipStreamSynchronize(streams[a.slot]);
           finish(a.ticket, a.error, nullptr);
         } else {
           finish(a.ticket, a.task->status(), &a.task->info());
         }
         a.task.reset();
+        if (a.ready) (void)hipEventDestroy(a.ready);
         {
           std::lock_guard<std::mutex> g(mu);
           free_slots.push_back(a.slot);
@@ -352,11 +380,18 @@ Scheduler* scheduler_create(Ctx& ctx) { return new Scheduler(ctx); }
 void scheduler_destroy(Scheduler* s) { delete s; }
 
 uint64_t scheduler_submit(Scheduler* s, const tsylv_request& r) {
+  hipEvent_t ev = nullptr;
+  TSYLV_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  const hipError_t er = hipEventRecord(ev, s->ctx.stream);
+  if (er != hipSuccess) {
+    (void)hipEventDestroy(ev);
+    TSYLV_HIP(er);
+  }
   uint64_t t;
   {
     std::lock_guard<std::mutex> g(s->mu);
     t = s->next_ticket++;
-    s->queue.push_back({t, r});
+    s->queue.push_back({t, r, ev});
   }
   s->cv.notify_all();
   return t;

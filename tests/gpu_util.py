@@ -36,3 +36,17 @@ def say(*a):
 
 def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+_WORKLOADS = {}
+
+
+def workload(name):
+    """A named full-size workload of paper_2405_09233_amd.workloads
+    (``cd_4096``: n = 4096, s = 64, p = 32; ``cd_8192``: n = 8192, s = 128,
+    p = 64, 34 GB of FP64 A), generated once per test process on the host."""
+    if name not in _WORKLOADS:
+        from paper_2405_09233_amd import workloads
+        say("generating workload", name)
+        _WORKLOADS[name] = getattr(workloads, name)(seed=0)
+    return _WORKLOADS[name]

@@ -10,8 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import tproduct as tp
-from paper_2405_09233_amd import workloads
-from gpu_util import ctx, dev, host, say
+from gpu_util import ctx, dev, host, say, workload
 
 EPS = np.finfo(np.float64).eps
 
@@ -46,7 +45,7 @@ def test_apply_full_size_sampled():
     configuration of the benchmark; 64 random entries (and the first/last
     rows and slices) checked against the oracle's per-entry circulant sums."""
     say("apply full size 4096/64/32")
-    A, B, C = workloads.cd_4096(seed=0)
+    A, B, C = workload("cd_4096")
     n, s, p = C.shape
     c = ctx()
     Ad = dev(A)

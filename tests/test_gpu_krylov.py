@@ -21,7 +21,7 @@ from oracle import tproduct as tp
 from oracle import krylov as kr
 from oracle import kron, tbs
 from paper_2405_09233_amd import workloads, tsylv
-from gpu_util import ctx, dev, host, say, rel
+from gpu_util import ctx, dev, host, say, rel, workload
 
 
 def solve(method, A, B, C, **kw):
@@ -153,7 +153,7 @@ def test_full_size_tgmres_cd4096():
     """n = 4096, s = 64, p = 32 convection-diffusion, tGMRES(30) to 1e-8 --
     the benchmark's configuration."""
     say("full size tGMRES(30) 4096/64/32")
-    A, B, C = workloads.cd_4096(seed=0)
+    A, B, C = workload("cd_4096")
     c = ctx()
     Ad, Bd, Cd = dev(A), dev(B), dev(C)
     X, info = c.gmres(Ad, Bd, Cd, m=30, tol=1e-8, max_cycles=500)

@@ -147,3 +147,44 @@ def test_close_with_requests_in_flight():
     t0 = time.time()
     ctx.close()          # finishes admitted solves, cancels the queued ones
     assert time.time() - t0 < 60
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("method", [tsylv.GMRES, tsylv.GMRES_BATCHED])
+def test_submit_waits_for_work_on_the_context_stream(method):
+    """Inputs written by device kernels on the context stream right before
+    tsylv_submit (behind a long chain of products, so they are still being
+    written when the request is admitted) are read only after those
+    kernels: the served result is bitwise the synchronous solve's."""
+    import torch
+    say("submit after context-stream work", method)
+    A, B, C = workloads.dense_shifted(96, 8, 4, seed=17)
+    ctx = tsylv.Context(1 << 30, device=0)  # on torch's current stream
+    try:
+        srcA, srcB, srcC = dev(A), dev(B), dev(C)
+        Xref, info = ctx.gmres(srcA, srcB, srcC, m=30, tol=1e-10)
+        assert info.status == 0
+        Xref = host(Xref)
+        Ad = tsylv.empty_device(A.shape, "cuda:0")
+        Bd = tsylv.empty_device(B.shape, "cuda:0")
+        Cd = tsylv.empty_device(C.shape, "cuda:0")
+        for t in (Ad, Bd, Cd):
+            t.fill_(float("nan"))
+        Xd = tsylv.empty_device(C.shape, "cuda:0")
+        torch.cuda.synchronize()
+        busy = torch.full((4096, 4096), 1e-4, dtype=torch.float32, device="cuda:0")
+        for _ in range(40):
+            busy = busy @ busy
+        Ad.copy_(srcA)
+        Bd.copy_(srcB)
+        Cd.copy_(srcC)
+        t = ctx.submit(Ad, Bd, Cd, Xd, method=method, m=30, tol=1e-10)
+        st, info = wait_all(ctx, [t])[t]
+        assert st == 0, info.as_dict()
+        if method == tsylv.GMRES:
+            assert np.array_equal(host(Xd), Xref)
+        else:
+            assert rel(host(Xd), Xref) <= 1e-8
+        del busy
+    finally:
+        ctx.close()
