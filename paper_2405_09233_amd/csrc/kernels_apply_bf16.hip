@@ -526,9 +526,336 @@ void launch_wg(Bf16Args a, int ncu, hipStream_t st) {
 }
 
 
+// ---------------------------------------------------------------------------
+// Wide variant for s > 64: 32 x 32 x 16 MFMAs, one workgroup per 128-column
+// tile, so at s = 128 the operator is streamed from HBM exactly once (the
+// 16 x 16 x 32 variants above hold at most 64 columns per workgroup and
+// read it once per column tile).  A 32 x 32 block of W takes half the LDS
+// bytes per flop of four 16 x 16 blocks (each V fragment feeds a 32-row
+// operator fragment), which is what keeps the V reads from LDS off the
+// critical path at this width.
+//
+// The tiled layouts stay those of the 16 x 16 x 32 kernels; the fragments
+// of the 32 x 32 x 16 instruction are gathered from them:
+//   A operand (32 rows x 16 k), lane l: row l % 32, k = 8 (l / 32) + e.
+//     Rows 32 R .. 32 R + 31 are the 16-row chunks 2 R and 2 R + 1 (adjacent
+//     in the grouped chunk order), so lane l reads 16 bytes of chunk
+//     2 R + (l / 16) % 2 at lane slot (l % 16) + 16 (2 h + l / 32), where
+//     h = 0, 1 picks the 16-deep half of the chunk's 32 k;
+//   B operand (16 k x 32 columns), lane l: column l % 32, k = 8 (l / 32) + e:
+//     the same offsets in the two 16-column chunks of V;
+//   D (32 x 32), lane l, register r: column l % 32, row
+//     8 (r / 4) + 4 (l / 32) + r % 4.
+// Both operands of a product use the same (lane group, element) -> k map,
+// so the sum over k is the full one whatever order the hardware pairs them.
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ f16v mma32(bf8 a, bf8 b, f16v c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Lane offset (in bf16 elements) of a 32-wide fragment inside a pair of
+// adjacent 1 KB chunks, for k half h.
+__device__ __forceinline__ int frag32_off(int lane, int h) {
+  return ((lane >> 4) & 1) * 512 + ((lane & 15) + 16 * (2 * h + (lane >> 5))) * 8;
+}
+
+// -V_k Bhat_k (a contraction over s, gathered from global memory) into the
+// 32 x 32 accumulators of rows 32 R32 .., and the epilogue.
+template <int CB32, bool CPLX, bool TIO>
+__device__ __forceinline__ void w32_finish(const Bf16Args& a, int qr, int qi, int64_t R32,
+                                           int64_t ct, f16v (&accr)[CB32], f16v (&acci)[CB32]) {
+  const int64_t n = a.n, s = a.s, ns = n * s;
+  const int lane = threadIdx.x & 63;
+  const int lc = lane & 31, lg = lane >> 5;
+  const int64_t row = 32 * R32 + lc;
+  const int64_t col0 = ct * 32 * CB32;
+  if (a.Bb) {
+    const uint16_t* Bbr = a.Bb + (int64_t)qr * s * s;
+    const uint16_t* Bbi = CPLX ? a.Bb + (int64_t)qi * s * s : nullptr;
+    const float* Vr = TIO ? nullptr : a.V + (int64_t)qr * ns;
+    const float* Vi = (CPLX && !TIO) ? a.V + (int64_t)qi * ns : nullptr;
+    for (int64_t k1 = 0; k1 < s; k1 += 16) {
+      u16x8 fr, fi;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t kk = k1 + 8 * lg + e;
+        const bool ok = row < n && kk < s;
+        if (TIO) {
+          fr[e] = ok ? (uint16_t)(a.Vt[tiled_at(a, qr, row, kk)] ^ 0x8000u) : (uint16_t)0;
+          if (CPLX)
+            fi[e] = ok ? (uint16_t)(a.Vt[tiled_at(a, qi, row, kk)] ^ 0x8000u) : (uint16_t)0;
+        } else {
+          fr[e] = ok ? (uint16_t)(bf16_bits(Vr[row + n * kk]) ^ 0x8000u) : (uint16_t)0;
+          if (CPLX) fi[e] = ok ? (uint16_t)(bf16_bits(Vi[row + n * kk]) ^ 0x8000u) : (uint16_t)0;
+        }
+      }
+      const bf8 nvr = __builtin_bit_cast(bf8, fr);  // -Re V
+      bf8 nvi, pvi;
+      if (CPLX) {
+        nvi = __builtin_bit_cast(bf8, fi);  // -Im V
+        pvi = neg8(nvi);                    // +Im V
+      }
+#pragma unroll
+      for (int j = 0; j < CB32; ++j) {
+        const int64_t col = col0 + 32 * j + lc;
+        u16x8 gr, gi;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int64_t kk = k1 + 8 * lg + e;
+          const bool ok = col < s && kk < s;
+          gr[e] = ok ? Bbr[kk + s * col] : (uint16_t)0;
+          if (CPLX) gi[e] = ok ? Bbi[kk + s * col] : (uint16_t)0;
+        }
+        const bf8 gbr = __builtin_bit_cast(bf8, gr);
+        accr[j] = mma32(nvr, gbr, accr[j]);  // -Vr Br
+        if (CPLX) {
+          const bf8 gbi = __builtin_bit_cast(bf8, gi);
+          acci[j] = mma32(nvr, gbi, acci[j]);  // -Vr Bi
+          accr[j] = mma32(pvi, gbi, accr[j]);  // +Vi Bi
+          acci[j] = mma32(nvi, gbr, acci[j]);  // -Vi Br
+        }
+      }
+    }
+  }
+  if (TIO) {
+    // Rows 32 R32 + 8 t + 4 lg .. + 3 of a column are 4 consecutive elements
+    // of one lane slot of the tiled output: one 8-byte store.  Rows >= n and
+    // columns >= s inside existing chunks are written as zero (the tiled
+    // padding); chunks past the padded column count are not written.
+    const int64_t plane = a.ncb * a.nkb * 512;
+#pragma unroll
+    for (int j = 0; j < CB32; ++j) {
+      const int64_t col = col0 + 32 * j + lc;
+      if (col / 16 >= a.ncb) continue;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t r0 = 32 * R32 + 8 * t + 4 * lg;
+        const int64_t at = tiled_at(a, 0, r0, col);
+        u16x4 vr, vi;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = col < s && r0 + e < n;
+          vr[e] = ok ? bf16_bits((float)(a.alpha * (double)accr[j][4 * t + e])) : (uint16_t)0;
+          if (CPLX)
+            vi[e] = ok ? bf16_bits((float)(a.alpha * (double)acci[j][4 * t + e])) : (uint16_t)0;
+        }
+        *reinterpret_cast<u16x4*>(a.outt + qr * plane + at) = vr;
+        if (CPLX) *reinterpret_cast<u16x4*>(a.outt + qi * plane + at) = vi;
+      }
+    }
+    return;
+  }
+  float* Or = a.out + (int64_t)qr * ns;
+  float* Oi = CPLX ? a.out + (int64_t)qi * ns : nullptr;
+  const float* Yr = a.Y ? a.Y + (int64_t)qr * ns : nullptr;
+  const float* Yi = (a.Y && CPLX) ? a.Y + (int64_t)qi * ns : nullptr;
+#pragma unroll
+  for (int j = 0; j < CB32; ++j) {
+    const int64_t col = col0 + 32 * j + lc;
+    if (col >= s) continue;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t rr = 32 * R32 + 8 * (r / 4) + 4 * lg + r % 4;
+      if (rr >= n) continue;
+      const int64_t off = rr + n * col;
+      double vr = a.alpha * (double)accr[j][r];
+      if (a.beta != 0.0) vr += a.beta * (double)Yr[off];
+      Or[off] = (float)vr;
+      if (CPLX) {
+        double vi = a.alpha * (double)acci[j][r];
+        if (a.beta != 0.0) vi += a.beta * (double)Yi[off];
+        Oi[off] = (float)vi;
+      }
+    }
+  }
+}
+
+// A workgroup of NW waves owns column tile ct (32 CB32 columns) and span32
+// 32-row blocks of one slice; its waves walk RW blocks each at a time in
+// lock step, sharing each phase of P k blocks of V through LDS (double
+// buffered), each streaming its operator rows from HBM into a register ring
+// D k blocks deep.
+template <int CB32, int D, int P, int NW, int RW, bool CPLX, bool TIO>
+__device__ __forceinline__ void w32_tasks(const Bf16Args& a, int k, int64_t rb32_begin,
+                                          int64_t rb32_count, int64_t ct, uint16_t* lds) {
+  constexpr int NPL = CPLX ? 2 : 1;
+  constexpr int CB16 = 2 * CB32;
+  constexpr int CPK = NPL * CB16;  // 1 KB chunks of V per k block
+  constexpr int CH = P * CPK;      // per phase
+  static_assert(CH % NW == 0, "every wave stages the same number of chunks");
+  constexpr int NPASS = CH / NW;
+  int qr, qi;
+  slice_planes(a.p, k, qr, qi);
+  const int64_t nkb = a.nkb;
+  const int64_t nrb32_real = (a.n + 31) / 32;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int off0 = frag32_off(lane, 0), off1 = frag32_off(lane, 1);
+  // V chunks this wave stages (null: a chunk past the padded columns, zero)
+  const uint16_t* Vsrc[NPASS];
+#pragma unroll
+  for (int v = 0; v < NPASS; ++v) {
+    const int c = v * NW + wave;
+    const int kl = c / CPK, pln = (c % CPK) / CB16, j16 = c % CB16;
+    const int q = pln ? qi : qr;
+    const int64_t cb = ct * CB16 + j16;
+    Vsrc[v] = cb < a.ncb ? a.Vt + (((int64_t)q * a.ncb + cb) * nkb + kl) * 512 + lane * 8
+                         : nullptr;
+  }
+  const int64_t nph = nkb / P;
+  const int64_t ntask = (rb32_count + NW * RW - 1) / (NW * RW);
+  for (int64_t task = 0; task < ntask; ++task) {
+    const uint16_t* Ar[RW];
+    const uint16_t* Ai[RW];
+    int64_t rbs[RW];
+    bool store[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int64_t want = rb32_begin + (task * NW + wave) * RW + r;
+      store[r] = want < rb32_begin + rb32_count && want < nrb32_real;
+      rbs[r] = min(want, a.nrb / 2 - 1);  // past the end: any valid block, not stored
+      const int64_t rb = 2 * rbs[r];      // first of its two 16-row chunks
+      const int64_t rofs = ((rb / kRowGroup) * nkb * kRowGroup + rb % kRowGroup) * 512;
+      Ar[r] = a.At + (int64_t)qr * a.nrb * nkb * 512 + rofs;
+      Ai[r] = CPLX ? a.At + (int64_t)qi * a.nrb * nkb * 512 + rofs : nullptr;
+    }
+    u16x8 stage[NPASS];
+    auto fetch = [&](int64_t ph) {
+#pragma unroll
+      for (int v = 0; v < NPASS; ++v)
+        stage[v] = Vsrc[v] ? *reinterpret_cast<const u16x8*>(Vsrc[v] + ph * P * 512)
+                           : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+      for (int v = 0; v < NPASS; ++v)
+        *reinterpret_cast<u16x8*>(lds + ((int64_t)buf * CH + v * NW + wave) * 512 + lane * 8) =
+            stage[v];
+    };
+    auto frag = [&](int buf, int kl, int pln, int j, int off) -> bf8 {
+      return __builtin_bit_cast(
+          bf8, *reinterpret_cast<const u16x8*>(
+                   lds + ((int64_t)buf * CH + kl * CPK + pln * CB16 + 2 * j) * 512 + off));
+    };
+    f16v accr[RW][CB32], acci[RW][CB32];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int j = 0; j < CB32; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          accr[r][j][e] = 0.f;
+          acci[r][j][e] = 0.f;
+        }
+    // ring slot u: [row block][k half] fragments of the real / imaginary plane
+    bf8 ar[D][RW][2], ai[D][RW][2];
+    auto loadA = [&](int64_t kb, int u) {
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const int64_t base = kb * (kRowGroup * 512);
+        ar[u][r][0] = ld8_stream(Ar[r] + base + off0);
+        ar[u][r][1] = ld8_stream(Ar[r] + base + off1);
+        if (CPLX) {
+          ai[u][r][0] = ld8_stream(Ai[r] + base + off0);
+          ai[u][r][1] = ld8_stream(Ai[r] + base + off1);
+        }
+      }
+    };
+    fetch(0);
+#pragma unroll
+    for (int u = 0; u < D; ++u) loadA(u, u);
+    put(0);
+    __syncthreads();
+    for (int64_t ph = 0; ph < nph; ++ph) {
+      const int buf = (int)(ph & 1);
+      fetch(min(ph + 1, nph - 1));
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < P; ++u) {
+        const int d = u % D;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int off = h ? off1 : off0;
+          bf8 mai[RW];
+#pragma unroll
+          for (int r = 0; r < RW; ++r)
+            if (CPLX) mai[r] = neg8(ai[d][r][h]);
+#pragma unroll
+          for (int j = 0; j < CB32; ++j) {
+            const bf8 br = frag(buf, u, 0, j, off);
+            bf8 bi;
+            if (CPLX) bi = frag(buf, u, 1, j, off);
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+              accr[r][j] = mma32(ar[d][r][h], br, accr[r][j]);
+              if (CPLX) {
+                acci[r][j] = mma32(ar[d][r][h], bi, acci[r][j]);
+                accr[r][j] = mma32(mai[r], bi, accr[r][j]);
+                acci[r][j] = mma32(ai[d][r][h], br, acci[r][j]);
+              }
+            }
+          }
+        }
+        // the refill right behind the MFMAs that free its slot
+        __builtin_amdgcn_sched_barrier(0);
+        loadA(min(ph * P + u + D, nkb - 1), d);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      put(buf ^ 1);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+      if (store[r]) w32_finish<CB32, CPLX, TIO>(a, qr, qi, rbs[r], ct, accr[r], acci[r]);
+  }
+}
+
+template <int CB32, int D, int P, int NW, int RW, bool TIO>
+__global__ __launch_bounds__(NW * 64) void apply_bf16_w32_kernel(Bf16Args a, WgPlan pl) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
+  const int t = xcd_tile(blockIdx.x, a.total);
+  const int ct = t % a.nct;
+  int w = t / a.nct;
+  const int nsl = num_slices(a.p);
+  int k = 0;
+  for (; k < nsl; ++k) {
+    const bool real = (k == 0) || (2 * k == a.p);
+    const int wk = real ? pl.wr : pl.wc;
+    if (w < wk) break;
+    w -= wk;
+  }
+  const bool real = (k == 0) || (2 * k == a.p);
+  // G counts 16-row blocks: a complex slice's workgroup owns G of them, a
+  // real one's 2 G (G is a multiple of 2 NW RW)
+  const int64_t span32 = real ? (int64_t)pl.G : pl.G / 2;
+  const int64_t rb32_begin = (int64_t)w * span32;
+  if (real)
+    w32_tasks<CB32, D, P, NW, RW, false, TIO>(a, k, rb32_begin, span32, ct, lds);
+  else
+    w32_tasks<CB32, D, P, NW, RW, true, TIO>(a, k, rb32_begin, span32, ct, lds);
+}
+
+template <int CB32, int D, int P, int NW, int RW, bool TIO>
+void launch_w32(Bf16Args a, int ncu, hipStream_t st) {
+  static_assert(kKPad % P == 0 && P % D == 0, "phase and ring must divide the k padding");
+  a.nct = (int)((a.s + 32 * CB32 - 1) / (32 * CB32));
+  const WgPlan pl = plan_wg(a.n, a.p, a.nct, 2 * NW * RW, ncu);
+  const int nsl = num_slices(a.p), nreal = (a.p % 2 == 0 && a.p > 1) ? 2 : 1;
+  a.total = a.nct * (nreal * pl.wr + (nsl - nreal) * pl.wc);
+  const size_t lds = 2 * (size_t)P * 2 * (2 * CB32) * 1024;  // two buffers of complex phases
+  TSYLV_HIP(hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&apply_bf16_w32_kernel<CB32, D, P, NW, RW, TIO>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((apply_bf16_w32_kernel<CB32, D, P, NW, RW, TIO>), dim3(a.total),
+                     dim3(NW * 64), lds, st, a, pl);
+  TSYLV_LAUNCH_CHECK();
+}
+
+
 }  // namespace
 
-int bf16_default_variant(int64_t s) { return s <= 16 ? 0 : (s <= 32 ? 1 : 2); }
+int bf16_default_variant(int64_t s) { return s <= 16 ? 0 : (s <= 32 ? 1 : (s <= 64 ? 2 : 4)); }
 
 static int64_t row_blocks(int64_t n) { return ((n + 15) / 16 + kRowPad - 1) / kRowPad * kRowPad; }
 static int64_t k_blocks(int64_t n) { return ((n + 31) / 32 + kKPad - 1) / kKPad * kKPad; }
@@ -569,6 +896,9 @@ void launch_cfg(const Bf16Args& a, int variant, hipStream_t st) {
     case 1: launch_wg<2, 2, 4, 8, 2, TIO>(a, ncu, st); break;
     case 2: launch_wg<4, 2, 2, 8, 2, TIO>(a, ncu, st); break;
     case 3: launch_wg<4, 8, 8, 8, 1, TIO>(a, ncu, st); break;
+    case 4: launch_w32<4, 2, 2, 8, 1, TIO>(a, ncu, st); break;
+    case 5: launch_w32<2, 2, 2, 8, 1, TIO>(a, ncu, st); break;
+    case 6: launch_w32<4, 2, 2, 4, 2, TIO>(a, ncu, st); break;
     default: throw Error(TSYLV_EINVAL, "apply: unknown BF16 variant");
   }
 }
