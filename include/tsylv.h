@@ -58,7 +58,9 @@ typedef enum {
   TSYLV_EBREAKDOWN = -3,   /* non-invertible tube in Normalization (TBA)    */
   TSYLV_ESINGULAR = -4,    /* singular projected problem                    */
   TSYLV_EHIP = -5,         /* HIP runtime error                             */
-  TSYLV_ECANCELLED = -6    /* request dropped (context destroyed)           */
+  TSYLV_ECANCELLED = -6,   /* request dropped (context destroyed)           */
+  TSYLV_ESCRATCH = -7      /* sizes beyond the static scratch of
+                              tsylv_apply_noalloc                           */
 } tsylv_status;
 
 /* Solver options (Algorithm 3 and Algorithm 8 inputs: m, Iter_max, tol, X0). */
@@ -125,6 +127,24 @@ size_t tsylv_workspace_bytes(int method, int64_t n, int64_t s, int64_t p,
 int tsylv_apply(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p,
                 const double* A, const double* B, const double* X, double* Y,
                 int prec);
+
+/* tsylv_apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same Y = A*X - X*B with every intermediate buffer in a static device
+ * array of tsylv_noalloc_scratch_bytes() (256 MiB) that each GPU the library
+ * runs on holds until the process ends; the call allocates nothing and takes
+ * no context.  Runs on the current HIP device, enqueued on `hip_stream` (a
+ * hipStream_t; NULL = the null stream), and returns without synchronising:
+ * Y is ready when the stream reaches this point.  Default tile shapes (no
+ * tuning table).  Every call on a GPU shares that GPU's scratch, so calls
+ * that overlap on one GPU (on different streams, or from threads with no
+ * ordering between them) race; calls in order on one stream do not.
+ * TSYLV_ESCRATCH (and nothing enqueued) when the sizes need more scratch
+ * than that (the workspace of tsylv_apply, tsylv_workspace_bytes(-1, ...));
+ * TSYLV_EINVAL for bad sizes, pointers or precision. */
+size_t tsylv_noalloc_scratch_bytes(void);
+int tsylv_apply_noalloc(void* hip_stream, int64_t n, int64_t s, int64_t p, const double* A,
+                        const double* B, const double* X, double* Y, int prec);
 
 /* tFOM(m), Algorithm 3 of section 3 (Galerkin condition, section 3.2). */
 int tsylv_fom(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A,

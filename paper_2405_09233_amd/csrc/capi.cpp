@@ -405,6 +405,8 @@ const char* tsylv_strerror(int status) {
     case TSYLV_ESINGULAR: return "singular (projected) problem";
     case TSYLV_EHIP: return "HIP runtime error";
     case TSYLV_ECANCELLED: return "cancelled";
+    case TSYLV_ESCRATCH:
+      return "sizes exceed the static scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }

@@ -61,6 +61,26 @@ class Workspace {
   size_t used_ = 0;
 };
 
+// Bump allocator over a device buffer the caller provides (no arena): the
+// scratch of the allocation-free entry points.
+class Carve {
+ public:
+  Carve(char* base, size_t bytes) : base_(base), bytes_(bytes) {}
+  template <typename T>
+  T* take(int64_t count) {
+    size_t b = (size_t)round_up((int64_t)(count * sizeof(T)), 256);
+    if (used_ + b > bytes_) throw Error(TSYLV_ENOMEM, "scratch plan exceeded");
+    T* p = reinterpret_cast<T*>(base_ + used_);
+    used_ += b;
+    return p;
+  }
+
+ private:
+  char* base_;
+  size_t bytes_;
+  size_t used_ = 0;
+};
+
 struct Scheduler;  // serving loop (serve.cpp)
 
 // HIP-event timing of kernel families (tsylv_profile).

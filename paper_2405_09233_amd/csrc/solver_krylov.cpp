@@ -1163,55 +1163,77 @@ size_t apply_workspace_bytes(int64_t n, int64_t s, int64_t p) {
          Workspace::bytes_for(kern::bf16_vtiled_elems(n, s, (int)p), 2);
 }
 
-int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
-                  const double* X, double* Y, int prec) {
-  hipStream_t st = ctx.stream;
+namespace {
+
+// Algorithm 1 for Y = A*X - X*B with the slice products in `prec`: every
+// buffer taken from `ws` (an arena workspace or a caller's scratch); the
+// slice-product launch is timed when `ctx` is given and profiling is on.
+template <class WS>
+void apply_core(WS& ws, hipStream_t st, Ctx* ctx, int64_t n, int64_t s, int64_t p,
+                const double* A, const double* B, const double* X, double* Y, int prec,
+                int variant) {
   const int64_t N = n * s * p;
-  Workspace ws(ctx.arena, apply_workspace_bytes(n, s, p));
-  double* Ah = ws.take<double>(p * n * n);
-  double* Bh = ws.take<double>(p * s * s);
-  double* xf_op = ws.take<double>(p * p);
-  double* xf_fwd = ws.take<double>(p * p);
-  double* xf_inv = ws.take<double>(p * p);
-  double* Zx = ws.take<double>(N);
-  double* Zy = ws.take<double>(N);
+  double* Ah = ws.template take<double>(p * n * n);
+  double* Bh = ws.template take<double>(p * s * s);
+  double* xf_op = ws.template take<double>(p * p);
+  double* xf_fwd = ws.template take<double>(p * p);
+  double* xf_inv = ws.template take<double>(p * p);
+  double* Zx = ws.template take<double>(N);
+  double* Zy = ws.template take<double>(N);
   kern::build_xform(xf_op, (int)p, XF_OPERATOR, st);
   kern::build_xform(xf_fwd, (int)p, XF_FORWARD, st);
   kern::build_xform(xf_inv, (int)p, XF_INVERSE, st);
   kern::tube_xform_f64(A, Ah, xf_op, n * n, (int)p, st);
   kern::tube_xform_f64(B, Bh, xf_op, s * s, (int)p, st);
   kern::tube_xform_f64(X, Zx, xf_fwd, n * s, (int)p, st);
+  const int kid = prec == TSYLV_FP64 ? TSYLV_K_APPLY : TSYLV_K_APPLY_LOW;
+  const bool prof = ctx && ctx->prof.on(kid);
   if (prec == TSYLV_FP64) {
-    ProfScope ps(ctx, TSYLV_K_APPLY, st);
-    kern::apply_f64(Ah, Bh, Zx, Zy, nullptr, 1.0, 0.0, n, s, (int)p, st,
-                    ctx.tune.get(TSYLV_FP64, n, s, p));
+    if (prof) ctx->prof.begin(kid, st);
+    kern::apply_f64(Ah, Bh, Zx, Zy, nullptr, 1.0, 0.0, n, s, (int)p, st, variant);
+    if (prof) ctx->prof.end(kid, st);
   } else {
-    float* Vf = ws.take<float>(N);
-    float* Wf = ws.take<float>(N);
+    float* Vf = ws.template take<float>(N);
+    float* Wf = ws.template take<float>(N);
     kern::convert_f64_f32(Zx, Vf, N, st);
     if (prec == TSYLV_BF16) {
-      uint16_t* Ab = ws.take<uint16_t>(kern::bf16_tiled_elems(n, (int)p));
-      uint16_t* Bb = reinterpret_cast<uint16_t*>(ws.take<float>(p * s * s));
+      uint16_t* Ab = ws.template take<uint16_t>(kern::bf16_tiled_elems(n, (int)p));
+      uint16_t* Bb = reinterpret_cast<uint16_t*>(ws.template take<float>(p * s * s));
       kern::tile_operator_bf16(Ah, Ab, n, (int)p, st);
       kern::convert_f64_bf16(Bh, Bb, p * s * s, st);
-      uint16_t* Vt = ws.take<uint16_t>(kern::bf16_vtiled_elems(n, s, (int)p));
-      ProfScope ps(ctx, TSYLV_K_APPLY_LOW, st);
-      kern::apply_bf16(Ab, Bb, Vf, Vt, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st,
-                       ctx.tune.get(TSYLV_BF16, n, s, p));
+      uint16_t* Vt = ws.template take<uint16_t>(kern::bf16_vtiled_elems(n, s, (int)p));
+      if (prof) ctx->prof.begin(kid, st);
+      kern::apply_bf16(Ab, Bb, Vf, Vt, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st, variant);
+      if (prof) ctx->prof.end(kid, st);
     } else {
-      float* Af = ws.take<float>(p * n * n);
-      float* Bf = ws.take<float>(p * s * s);
+      float* Af = ws.template take<float>(p * n * n);
+      float* Bf = ws.template take<float>(p * s * s);
       kern::convert_f64_f32(Ah, Af, p * n * n, st);
       kern::convert_f64_f32(Bh, Bf, p * s * s, st);
-      ProfScope ps(ctx, TSYLV_K_APPLY_LOW, st);
-      kern::apply_f32(Af, Bf, Vf, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st,
-                      ctx.tune.get(TSYLV_FP32, n, s, p));
+      if (prof) ctx->prof.begin(kid, st);
+      kern::apply_f32(Af, Bf, Vf, Wf, nullptr, 1.0, 0.0, n, s, (int)p, st, variant);
+      if (prof) ctx->prof.end(kid, st);
     }
     kern::convert_f32_f64(Wf, Zy, N, st);
   }
   kern::tube_xform_f64(Zy, Y, xf_inv, n * s, (int)p, st);
+}
+
+}  // namespace
+
+int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
+                  const double* X, double* Y, int prec) {
+  Workspace ws(ctx.arena, apply_workspace_bytes(n, s, p));
+  apply_core(ws, ctx.stream, &ctx, n, s, p, A, B, X, Y, prec, ctx.tune.get(prec, n, s, p));
   ctx.sync();
   return TSYLV_OK;
+}
+
+void apply_spatial_into(char* buf, size_t bytes, hipStream_t st, int64_t n, int64_t s,
+                        int64_t p, const double* A, const double* B, const double* X, double* Y,
+                        int prec) {
+  Carve c(buf, bytes);
+  apply_core(c, st, nullptr, n, s, p, A, B, X, Y, prec, -1);
 }
 
 }  // namespace tsylv

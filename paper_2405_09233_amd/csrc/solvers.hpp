@@ -30,6 +30,11 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
 size_t apply_workspace_bytes(int64_t n, int64_t s, int64_t p);
 int apply_spatial(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
                   const double* X, double* Y, int prec);
+// The same with every buffer carved from `buf` (bytes >= apply_workspace_bytes),
+// enqueued on `st` without synchronising; default tiles.
+void apply_spatial_into(char* buf, size_t bytes, hipStream_t st, int64_t n, int64_t s,
+                        int64_t p, const double* A, const double* B, const double* X, double* Y,
+                        int prec);
 
 size_t krylov_workspace_bytes(int method, int64_t n, int64_t s, int64_t p, const tsylv_opts& o);
 int krylov_solve(Ctx& ctx, int method, int64_t n, int64_t s, int64_t p, const double* A,

@@ -24,7 +24,7 @@ GMRES, FOM, TBA, TBS, GMRES_BATCHED = 0, 1, 2, 3, 4
 APPLY = -1
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "EINVAL", -2: "ENOMEM",
-          -3: "EBREAKDOWN", -4: "ESINGULAR", -5: "EHIP", -6: "ECANCELLED"}
+          -3: "EBREAKDOWN", -4: "ESINGULAR", -5: "EHIP", -6: "ECANCELLED", -7: "ESCRATCH"}
 
 
 class Opts(ctypes.Structure):
@@ -103,6 +103,10 @@ _SIGS = {
     "tsylv_tune_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "tsylv_tune_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "tsylv_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Info)]),
+    "tsylv_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "tsylv_apply_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "tsylv_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "tsylv_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "tsylv_profile_families": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint]),
@@ -181,6 +185,29 @@ def apply_variants(prec):
     if n < 0:
         raise TsylvError(n, "tsylv_apply_variants")
     return n
+
+
+def apply_noalloc(A, B, X, Y=None, prec=FP64, stream=None):
+    """tsylv_apply_noalloc: Y = A*X - X*B on the tensors' device with the
+    library's static scratch (no device allocation inside the call),
+    enqueued on `stream` (default: torch's current stream) without waiting.
+    Y (allocated here when None) is ready once that stream reaches the call."""
+    import torch
+    n, _, p = A.shape
+    s = B.shape[0]
+    if Y is None:
+        Y = empty_device((n, s, p), A.device)
+    st = stream if stream is not None else torch.cuda.current_stream(A.device)
+    with torch.cuda.device(A.device):
+        rc = load().tsylv_apply_noalloc(ctypes.c_void_p(st.cuda_stream), n, s, p, _ptr(A),
+                                        _ptr(B), _ptr(X), _ptr(Y), prec)
+    if rc != 0:
+        raise TsylvError(rc, "tsylv_apply_noalloc")
+    return Y
+
+
+def noalloc_scratch_bytes():
+    return load().tsylv_noalloc_scratch_bytes()
 
 
 def _ptr(t):
