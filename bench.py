@@ -6,22 +6,37 @@ spatial A, B, C (mode-3 DFT of A, B, C, the Krylov iteration in the Fourier
 planes, inverse DFT of X) to device-resident spatial X.  Inputs are synthetic
 (paper_2405_09233_amd/workloads.py) and already in HBM when timing starts.
 
-Paths timed (each: W warm-up solves, then K timed solves):
-  fp64      restarted tGMRES(30), everything FP64
-  mixed     FP64 iterative refinement; each correction one tGMRES(32) cycle
-            with FP32 basis vectors and FP32 MFMA slice products
-  bf16      the same (tGMRES(28) cycles) with BF16 slice products (FP32
-            accumulation) and the inner basis kept as tiled BF16 vectors
-            (TSYLV_BF16_BASIS=fp32 keeps FP32 vectors instead)
-  tba       TBAS(10), reported beside them (not a candidate for `value`)
-A path counts only if every timed solve reaches true FP64 relres <= tol.
-`value` is the solves/s of the fastest valid tGMRES path; every path is
-reported.  Two further measurements ride along (skip with --no-extra):
+The configuration that gives `value` (--config, default cd8192): the
+convection-diffusion operator family at n = 8192 (128 x 64 grid), s = 128,
+p = 64; paths timed there:
+  bf16            FP64 iterative refinement; each correction one tGMRES(40)
+                  cycle (inner tol 1e-4) with BF16 slice products (FP32
+                  accumulation) and the inner basis kept as tiled BF16 vectors
+                  -- W warm-up and K timed solves
+  mixed           the same with FP32 basis vectors and FP32 slice products
+  bf16_fp32basis  the BF16 path with FP32 inner basis vectors
+                  (1 warm-up, min(K, 2) timed solves each)
+  fp64            plain FP64 tGMRES(40) (no warm-up, 1 timed solve: tens of
+                  seconds per solve)
+Every solve runs to true FP64 relres <= tol, 5e-9 by default: the metric
+asks for 1e-8, and at 1e-8 the solutions of this operator are still about
+1.2e-7 from the exact one (the forward error is about 12 times the
+residual here), above the 1e-7 bar of the refined path; 5e-9 leaves a
+margin.  err_vs_fp64 of every path is its solution's relative distance to
+the FP64 solution continued to relres 1e-11.  A path counts only if every
+timed solve reaches the tolerance, and a refined path only if its
+err_vs_fp64 is <= 1e-7 (the FP64 paths' own error at the same residual is
+reported beside them).
+`value` is the solves/s of the fastest valid refined path.  The n = 4096, s = 64, p = 32 configuration
+(tGMRES(30), inner 32 / 28, and TBAS(10)) is reported under "cd4096" (--also).
+Further measurements ride along (skip with --no-extra):
   tiny      the 8 x 8 x 4 dense case, unrestarted tGMRES to 1e-12: latency,
             and the same instance through the t-Bartels-Stewart direct solve
-  serving   open-loop Poisson arrivals of small requests of uneven (n, s, p)
+  serving   open-loop Poisson arrivals of requests of uneven (n, s, p)
             through tsylv_submit / tsylv_poll (the serving loop): p50/p99
-            latency and throughput, FP64 and BF16-refined.
+            latency and throughput, FP64 and refined
+  batched   the lockstep batched engine against the serving loop and one
+            solve after another
 
 Prints ONE JSON line.  The roofline object is for the dominant kernel of the
 path that gives `value` (the facewise slice-product kernel), timed live with
@@ -52,15 +67,17 @@ def log(*a):
 
 def apply_work(n, s, p, elem):
     """Algorithmic flops and HBM bytes of one facewise apply
-    W = Ahat V - V Bhat on the half spectrum: real slices (DC, and Nyquist for
-    even p) cost 2(n^2 s + n s^2) flops, complex slices 6(n^2 s + n s^2)
-    (three real products in Gauss's form, as the FP64/FP32 kernels compute
-    them; the HBM-bound BF16 kernel spends four);
+    W = Ahat V - V Bhat on the half spectrum, the method's own count: real
+    slices (DC, and Nyquist for even p) cost 2(n^2 s + n s^2) flops, complex
+    slices 8(n^2 s + n s^2) (four real products per complex product), i.e.
+    4(n^2 s + n s^2)(p - 1) for even p.  (The FP64/FP32 kernels compute complex
+    products as three real products, Gauss's form, so they execute 3/4 of the
+    complex part; the count here is the algorithm's, not the kernel's.)
     bytes = the p planes of Ahat and Bhat (elem bytes each) read once, V read
     and W written once (vector element size vbytes)."""
     n_real = 2 if p % 2 == 0 else 1
     n_cplx = (p - n_real) // 2
-    flops = (2 * n_real + 6 * n_cplx) * (n * n * s + n * s * s)
+    flops = (2 * n_real + 8 * n_cplx) * (n * n * s + n * s * s)
     ab, vb = elem
     bytes_ = p * (ab * (n * n + s * s) + 2 * vb * n * s)
     return flops, bytes_
@@ -517,18 +534,47 @@ def batched(tsylv, kind="large", count=64, m=30, seed=40):
     return out
 
 
-def measured_traffic(path, shape, tiled):
+# The two operator configurations.  cd8192 is the mixed-precision
+# configuration (inner tGMRES(40) at tol 1e-4 inside FP64 refinement, against
+# plain FP64 tGMRES(40)) and gives `value`; cd4096 is reported beside it.
+CONFIGS = {
+    "cd8192": {"grid": (128, 64), "s": 128, "p": 64, "m": 40,
+               "inner": {"mixed": 40, "bf16": 40, "bf16_fp32basis": 40},
+               "paths": ["bf16", "mixed", "bf16_fp32basis", "fp64"]},
+    "cd4096": {"grid": (64, 64), "s": 64, "p": 32, "m": 30,
+               "inner": {"mixed": 32, "bf16": 28},
+               "paths": ["fp64", "mixed", "bf16", "tba"]},
+}
+KERNEL_NAMES = {
+    "fp64": "apply_mfma_kernel<double> (FP64 slice products)",
+    "tba": "apply_mfma_kernel<double> (FP64 A-only slice products; counted with the small "
+           "V Bhat term, which this apply skips)",
+    "mixed": "apply_mfma_kernel<float> (FP32 slice products)",
+    "bf16": "apply_bf16_wg_kernel (BF16 slice products on tiled BF16 vectors; one launch per "
+            "apply call)",
+    "bf16_fp32basis": "tile_v_bf16_kernel + apply_bf16_wg_kernel (BF16 slice products on FP32 "
+                      "vectors; both launches of one apply call are timed)",
+}
+DTYPES = {"fp64": "f64", "tba": "f64", "mixed": "f32 (inner) + f64 (refinement)",
+          "bf16": "bf16 x bf16 -> f32 (inner; BF16 basis) + f64 (refinement)",
+          "bf16_fp32basis": "bf16 x bf16 -> f32 (inner; FP32 basis) + f64 (refinement)"}
+# HBM counter summaries (FETCH_SIZE / WRITE_SIZE per apply call) by path and shape
+TRAFFIC_FILES = {("bf16", (4096, 64, 32)): "apply_bf16_traffic_cd4096_s64_p32.md",
+                 ("bf16", (8192, 128, 64)): "apply_bf16_traffic_cd8192_s128_p64.md"}
+
+
+def measured_traffic(path, shape):
     """HBM bytes per apply call from the committed counter summary, or None
-    for another path or shape, for the FP32-vector form of the BF16 path, or
-    when the kernel source has changed since the counters were taken."""
-    if path != "bf16" or not tiled or tuple(shape) != (4096, 64, 32):
+    when there is none for the path and shape, or when the kernel source has
+    changed since the counters were taken."""
+    fname = TRAFFIC_FILES.get((path, tuple(shape)))
+    if fname is None:
         return None
     import hashlib
     import re
     here = os.path.dirname(os.path.abspath(__file__))
     try:
-        txt = open(os.path.join(here, "profiles",
-                                "apply_bf16_traffic_cd4096_s64_p32.md")).read()
+        txt = open(os.path.join(here, "profiles", fname)).read()
         src = open(os.path.join(here, "paper_2405_09233_amd", "csrc",
                                 "kernels_apply_bf16.hip"), "rb").read()
     except OSError:
@@ -540,56 +586,199 @@ def measured_traffic(path, shape, tiled):
     return float(t.group(1))
 
 
+def path_opts(tsylv, cfg, name, tol, inner_tol):
+    m, inner = cfg["m"], cfg["inner"]
+    if name == "fp64":
+        return tsylv.default_opts(tsylv.GMRES, m=m, tol=tol, max_cycles=5000)
+    if name == "mixed":
+        return tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.FP32, inner_m=inner["mixed"],
+                                  inner_tol=inner_tol, tol=tol, max_outer=2000)
+    if name in ("bf16", "bf16_fp32basis"):
+        return tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.BF16, inner_m=inner[name],
+                                  inner_tol=inner_tol, tol=tol, max_outer=500)
+    if name == "tba":
+        return tsylv.default_opts(tsylv.TBA, m=10, tol=tol, max_cycles=500)
+    raise KeyError(name)
+
+
 def run_path(ctx, tsylv, dev_in, opts, steps, warmup, name):
+    """W warm-up solves, then K timed solves of one path (HIP events time
+    the dominant slice-product family live on the library's stream), then one
+    more solve with every kernel family timed for the time split."""
     import torch
     Ad, Bd, Cd, Xd = dev_in
     solve = ctx.tba if name == "tba" else ctx.gmres
-    for w in range(warmup):
-        _, info = solve(Ad, Bd, Cd, X=Xd, opts=opts)
-        log("%s warmup %d: status=%d steps=%d cycles=%d relres=%.3e %.3fs"
-            % (name, w, info.status, info.steps, info.cycles, info.relres_true, info.seconds))
-    # Only the dominant slice-product family is timed inside the timed
-    # region (each timed launch adds two event records to the stream); the
-    # time split comes from one more solve with every family timed.
-    dom_k = tsylv.K_APPLY_LOW if name in ("bf16", "mixed") else tsylv.K_APPLY
-    ctx.profile(True, families=[dom_k])
-    lat, infos = [], []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(steps):
-        ts = time.perf_counter()
-        _, info = solve(Ad, Bd, Cd, X=Xd, opts=opts)
-        lat.append(time.perf_counter() - ts)
-        infos.append(info.as_dict())
-        log("%s solve %d: status=%d steps=%d cycles=%d relres=%.3e %.3fs"
-            % (name, k, info.status, info.steps, info.cycles, info.relres_true, lat[-1]))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    dom_l, dom_ms = ctx.profile_read(dom_k)
-    ctx.profile(False)
-    ctx.profile(True)
-    solve(Ad, Bd, Cd, X=Xd, opts=opts)
-    la, ms_apply = ctx.profile_read(tsylv.K_APPLY)
-    ll, ms_low = ctx.profile_read(tsylv.K_APPLY_LOW)
-    lo, ms_ortho = ctx.profile_read(tsylv.K_ORTHO)
-    lx, ms_xform = ctx.profile_read(tsylv.K_XFORM)
-    ctx.profile(False)
+    env_before = os.environ.get("TSYLV_BF16_BASIS")
+    if name == "bf16_fp32basis":
+        os.environ["TSYLV_BF16_BASIS"] = "fp32"
+    try:
+        for w in range(warmup):
+            _, info = solve(Ad, Bd, Cd, X=Xd, opts=opts)
+            log("%s warmup %d: status=%d steps=%d cycles=%d relres=%.3e %.3fs"
+                % (name, w, info.status, info.steps, info.cycles, info.relres_true,
+                   info.seconds))
+        dom_k = tsylv.K_APPLY_LOW if opts.refine else tsylv.K_APPLY
+        # a path timed on one solve (tens of seconds) times every family in
+        # that solve instead of paying for one more
+        split_in_timed = steps == 1
+        if split_in_timed:
+            ctx.profile(True)
+        else:
+            ctx.profile(True, families=[dom_k])
+        lat, infos = [], []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(steps):
+            ts = time.perf_counter()
+            _, info = solve(Ad, Bd, Cd, X=Xd, opts=opts)
+            lat.append(time.perf_counter() - ts)
+            infos.append(info.as_dict())
+            log("%s solve %d: status=%d steps=%d cycles=%d outer=%d relres=%.3e %.3fs"
+                % (name, k, info.status, info.steps, info.cycles, info.outer,
+                   info.relres_true, lat[-1]))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        X_final = Xd.clone()
+        dom_l, dom_ms = ctx.profile_read(dom_k)
+        if not split_in_timed:
+            ctx.profile(False)
+            ctx.profile(True)
+            solve(Ad, Bd, Cd, X=Xd, opts=opts)
+        la, ms_apply = ctx.profile_read(tsylv.K_APPLY)
+        ll, ms_low = ctx.profile_read(tsylv.K_APPLY_LOW)
+        lo, ms_ortho = ctx.profile_read(tsylv.K_ORTHO)
+        lx, ms_xform = ctx.profile_read(tsylv.K_XFORM)
+        ctx.profile(False)
+    finally:
+        if env_before is None:
+            os.environ.pop("TSYLV_BF16_BASIS", None)
+        else:
+            os.environ["TSYLV_BF16_BASIS"] = env_before
     ok = all(i["status"] == 0 and i["relres_true"] <= opts.tol for i in infos)
     return {
         "valid": ok,
         "solves_per_s": steps / elapsed,
         "ms_per_solve": elapsed / steps * 1e3,
+        "reps": {"warmup": warmup, "timed": steps},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3)},
         "steps": infos[-1]["steps"], "cycles": infos[-1]["cycles"],
         "outer": infos[-1]["outer"], "relres_true": infos[-1]["relres_true"],
+        "inner_m": opts.inner_m if opts.refine else None,
         "applies_per_solve": la + ll,
         "apply_launches": dom_l, "apply_avg_ms": dom_ms / max(1, dom_l),
-        # one extra solve, every kernel family timed (outside the timed region)
+        # every kernel family timed: one extra solve outside the timed region,
+        # or the timed solve itself when only one was timed
+        "time_split_in_timed_solve": split_in_timed,
         "time_split_ms_per_solve": {"apply_fp64": ms_apply, "apply_low": ms_low,
                                     "orthogonalisation": ms_ortho, "dft": ms_xform},
         "elapsed_s": elapsed,
-    }
+    }, X_final
+
+
+def roofline_of(name, r, n, s, p, bf16_tiled):
+    """Roofline object of a path's dominant kernel: the method's algorithmic
+    work per apply call divided by the live-timed average call."""
+    elem = {"fp64": (8, 8), "tba": (8, 8), "mixed": (4, 4),
+            "bf16": (2, 2) if bf16_tiled else (2, 4), "bf16_fp32basis": (2, 4)}[name]
+    flops, bytes_ = apply_work(n, s, p, elem)
+    avg_s = r["apply_avg_ms"] / 1e3
+    if name.startswith("bf16"):
+        ach = bytes_ / avg_s
+        out = {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+               "frac": ach / PEAK_HBM}
+    else:
+        peak = PEAKS["mixed" if name == "mixed" else "fp64"]
+        ach = flops / avg_s
+        out = {"bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+               "frac": ach / peak}
+    kname = KERNEL_NAMES[name] if (name != "bf16" or bf16_tiled) else KERNEL_NAMES[
+        "bf16_fp32basis"]
+    out.update({"traffic": measured_traffic(name, (n, s, p)) if bf16_tiled or name != "bf16"
+                else None,
+                "kernel": kname, "avg_launch_ms": r["apply_avg_ms"],
+                "launches": r["apply_launches"], "algorithmic_flops_per_launch": flops,
+                "algorithmic_bytes_per_launch": bytes_})
+    return out
+
+
+def run_config(tsylv, workloads, key, args, headline):
+    """Every path of one operator configuration on one context.  Returns
+    (per-path results, the host tensors, the context-free extras)."""
+    import torch
+    cfg = CONFIGS[key]
+    nx, ny = cfg["grid"]
+    t0 = time.perf_counter()
+    A, B, C = workloads.convection_diffusion(nx, ny, cfg["s"], cfg["p"], seed=0)
+    n, s, p = C.shape
+    log("%s: generated n=%d s=%d p=%d in %.1fs" % (key, n, s, p, time.perf_counter() - t0))
+    dev = "cuda:0"
+    Ad, Bd, Cd = (tsylv.to_device(T, dev) for T in (A, B, C))
+    Xd = tsylv.empty_device((n, s, p), dev)
+    paths = [x for x in (args.paths.split(",") if args.paths else cfg["paths"])
+             if x in cfg["paths"]]
+    opts = {x: path_opts(tsylv, cfg, x, args.tol, args.inner_tol) for x in paths}
+    method = {x: (tsylv.TBA if x == "tba" else tsylv.GMRES) for x in paths}
+    need = max(tsylv.workspace_bytes(method[x], n, s, p, opts[x]) for x in paths)
+    ctx = tsylv.Context(need + (256 << 20), device=0)
+    tuned = {}
+    if not args.no_tune:
+        precs = [("fp64", tsylv.FP64)]
+        if "mixed" in paths:
+            precs.append(("fp32", tsylv.FP32))
+        if any(x.startswith("bf16") for x in paths):
+            precs.append(("bf16", tsylv.BF16))
+        for pname, prec in precs:
+            bv, ms = ctx.autotune(n, s, p, prec=prec, reps=5)
+            tuned[pname] = {"best": bv, "ms": ms}
+            log("%s autotune %s: variant %d (%s ms)" % (key, pname, bv,
+                                                       ", ".join("%.3f" % x for x in ms)))
+    res, finals = {}, {}
+    for name in paths:
+        if headline and name == "bf16":
+            st_, wu_ = args.steps, args.warmup
+        elif name == "fp64" and headline:
+            st_, wu_ = 1, 0  # tens of seconds per solve at this size
+        elif name == "tba":
+            st_, wu_ = 1, 0  # seconds per solve
+        elif headline:
+            st_, wu_ = min(args.steps, 2), 1
+        else:
+            st_, wu_ = min(args.steps, 3), 1
+        res[name], finals[name] = run_path(ctx, tsylv, (Ad, Bd, Cd, Xd), opts[name], st_, wu_,
+                                           name)
+    # err_vs_fp64: every path's solution against the FP64 tGMRES solution
+    # continued (x0 = the timed FP64 solve's X) to relres 1e-11
+    if "fp64" in finals and not args.no_err:
+        Xref = finals["fp64"].clone()
+        oref = path_opts(tsylv, cfg, "fp64", 1e-11, args.inner_tol)
+        oref.x0_given = 1
+        t1 = time.perf_counter()
+        _, iref = ctx.gmres(Ad, Bd, Cd, X=Xref, opts=oref)
+        log("%s: FP64 reference to %.0e: status %d, %d more steps, relres %.2e, %.1fs" % (
+            key, 1e-11, iref.status, iref.steps, iref.relres_true, time.perf_counter() - t1))
+        nref = float(torch.linalg.vector_norm(Xref))
+        for name, Xp in finals.items():
+            e = float(torch.linalg.vector_norm(Xp - Xref)) / nref
+            res[name]["err_vs_fp64"] = e
+            if name in ("fp64", "tba"):
+                # the FP64 paths are the comparison, their error is reported
+                res[name]["err_bar"] = None
+            else:
+                # the refined paths' bar: their solution within 1e-7
+                res[name]["err_bar"] = 1e-7
+                res[name]["err_ok"] = e <= 1e-7
+                res[name]["valid"] = res[name]["valid"] and e <= 1e-7
+            log("%s %s: err vs FP64 reference %.3e" % (key, name, e))
+        res["fp64_reference"] = {"tol": 1e-11, "status": iref.status,
+                                 "relres_true": iref.relres_true, "extra_steps": iref.steps}
+        del Xref
+    del finals
+    ctx.close()
+    del Ad, Bd, Cd, Xd
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res, (A, B, C), tuned
 
 
 def main():
@@ -597,13 +786,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--m", type=int, default=30)
-    ap.add_argument("--inner-m", type=int, default=0,
-                    help="inner restart length of the refined paths (default: 28 for the "
-                         "BF16 path, 32 for the FP32 path, the fastest in a sweep of 16..48)")
     ap.add_argument("--inner-tol", type=float, default=1e-4)
-    ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--paths", default="fp64,mixed,bf16,tba")
+    ap.add_argument("--tol", type=float, default=5e-9,
+                    help="true relative residual every timed solve must reach (<= the metric's "
+                         "1e-8, with the margin that keeps the refined solutions within 1e-7 "
+                         "of the FP64 solution)")
+    ap.add_argument("--config", default="cd8192", choices=sorted(CONFIGS),
+                    help="the configuration that gives `value`")
+    ap.add_argument("--also", default="cd4096",
+                    help="configurations reported beside it (comma list, '' for none)")
+    ap.add_argument("--paths", default="",
+                    help="restrict every configuration to these paths (comma list)")
+    ap.add_argument("--no-err", action="store_true",
+                    help="skip the FP64 reference solve behind err_vs_fp64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the tiny and serving runs")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -615,9 +810,6 @@ def main():
                     help="skip the batch at the full serving sizes")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving measurements")
-    ap.add_argument("--grid", type=int, nargs=2, default=[64, 64])
-    ap.add_argument("--s", type=int, default=64)
-    ap.add_argument("--p", type=int, default=32)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times "
                          "(reference kernel for the HBM byte counters)")
@@ -654,87 +846,22 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    nx, ny = args.grid
-    t0 = time.perf_counter()
-    A, B, C = workloads.convection_diffusion(nx, ny, args.s, args.p, seed=0)
+    key = args.config
+    cfg = CONFIGS[key]
+    res, (A, B, C), tuned = run_config(tsylv, workloads, key, args, headline=True)
     n, s, p = C.shape
-    log("generated n=%d s=%d p=%d in %.1fs" % (n, s, p, time.perf_counter() - t0))
-    dev = "cuda:0"
-    Ad, Bd, Cd = (tsylv.to_device(T, dev) for T in (A, B, C))
-    Xd = tsylv.empty_device((n, s, p), dev)
-    path_opts = {
-        "fp64": tsylv.default_opts(tsylv.GMRES, m=args.m, tol=args.tol, max_cycles=2000),
-        "mixed": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.FP32,
-                                    inner_m=args.inner_m or 32,
-                                    inner_tol=args.inner_tol, tol=args.tol, max_outer=2000),
-        "bf16": tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.BF16,
-                                   inner_m=args.inner_m or 28,
-                                   inner_tol=args.inner_tol, tol=args.tol, max_outer=300),
-        # TBAS(10), reported beside the tGMRES paths (not a candidate for value)
-        "tba": tsylv.default_opts(tsylv.TBA, m=10, tol=args.tol, max_cycles=500),
-    }
-    method = {"fp64": tsylv.GMRES, "mixed": tsylv.GMRES, "bf16": tsylv.GMRES, "tba": tsylv.TBA}
-    paths = [x for x in args.paths.split(",") if x]
-    need = max(tsylv.workspace_bytes(method[x], n, s, p, path_opts[x]) for x in paths)
-    ctx = tsylv.Context(need + (64 << 20), device=0)
-    # tile shapes of the apply picked by the autotuner for this shape (every
-    # later apply of the shape on the context uses the choice)
-    tuned = {}
-    if not args.no_tune:
-        precs = [("fp64", tsylv.FP64)]
-        if "mixed" in paths:
-            precs.append(("fp32", tsylv.FP32))
-        if "bf16" in paths:
-            precs.append(("bf16", tsylv.BF16))
-        for pname, prec in precs:
-            bv, ms = ctx.autotune(n, s, p, prec=prec, reps=5)
-            tuned[pname] = {"best": bv, "ms": ms}
-            log("autotune %s: variant %d (%s ms)" % (pname, bv, ", ".join("%.3f" % x for x in ms)))
-    res = {}
-    for name in paths:
-        # one TBAS solve takes seconds: two timed solves, no warm-up
-        st_, wu_ = (min(args.steps, 2), 0) if name == "tba" else (args.steps, args.warmup)
-        res[name] = run_path(ctx, tsylv, (Ad, Bd, Cd, Xd), path_opts[name], st_, wu_, name)
-
-    valid = [x for x in paths if res[x]["valid"] and x != "tba"]
-    best = max(valid, key=lambda x: res[x]["solves_per_s"]) if valid else paths[0]
-    r = res[best]
-    # the BF16 path's vectors are tiled BF16 when the library keeps its inner
-    # basis that way (fused Gram-Schmidt: inner_m + 1 <= 64), else FP32
-    bf16_tiled = (os.environ.get("TSYLV_BF16_BASIS") != "fp32"
-                  and path_opts["bf16"].inner_m + 1 <= 64) if best == "bf16" else False
-    elem = {"fp64": (8, 8), "mixed": (4, 4), "bf16": (2, 2) if bf16_tiled else (2, 4),
-            "tba": (8, 8)}[best]
-    flops, bytes_ = apply_work(n, s, p, elem)
-    avg_s = r["apply_avg_ms"] / 1e3
-    achieved_flops = flops / avg_s
-    achieved_bw = bytes_ / avg_s
-    if best == "bf16":
-        roofline = {"bound": "hbm", "achieved": achieved_bw / 1e9, "peak": PEAK_HBM / 1e9,
-                    "unit": "GB/s", "frac": achieved_bw / PEAK_HBM}
-    else:
-        peak = PEAKS[best]
-        roofline = {"bound": "mfma", "achieved": achieved_flops / 1e12, "peak": peak / 1e12,
-                    "unit": "TFLOP/s", "frac": achieved_flops / peak}
-    kernel = {"fp64": "apply_mfma_kernel<double> (FP64 slice products)",
-              "tba": "apply_mfma_kernel<double> (FP64 A-only slice products; counted with the "
-                     "small V Bhat term, which this apply skips)",
-              "mixed": "apply_mfma_kernel<float> (FP32 slice products)",
-              "bf16": ("apply_bf16_wg_kernel (BF16 slice products on tiled BF16 vectors; "
-                       "one launch per apply call)") if bf16_tiled else
-                      ("tile_v_bf16_kernel + apply_bf16_wg_kernel (BF16 slice products; "
-                       "both launches of one apply call are timed)")}[best]
-    roofline.update({"traffic": measured_traffic(best, (n, s, p), bf16_tiled), "kernel": kernel,
-                     "avg_launch_ms": r["apply_avg_ms"], "launches": r["apply_launches"],
-                     "algorithmic_flops_per_launch": flops,
-                     "algorithmic_bytes_per_launch": bytes_})
-
-    dtype = {"fp64": "f64", "tba": "f64", "mixed": "f32 (inner) + f64 (refinement)",
-             "bf16": "bf16 x bf16 -> f32 (inner; BF16 basis) + f64 (refinement)"
-             if bf16_tiled else "bf16 x bf16 -> f32 (inner) + f64 (refinement)"}[best]
+    refined = [x for x in res if x in ("bf16", "mixed", "bf16_fp32basis") and res[x]["valid"]]
+    best = max(refined, key=lambda x: res[x]["solves_per_s"]) if refined else None
+    r = res[best] if best else next(v for k, v in res.items() if "valid" in v)
+    bname = best or next(k for k, v in res.items() if "valid" in v)
+    bf16_tiled = bname == "bf16" and os.environ.get("TSYLV_BF16_BASIS") != "fp32" and \
+        cfg["inner"]["bf16"] + 1 <= 64
+    roofline = roofline_of(bname, r, n, s, p, bf16_tiled)
+    nx, ny = cfg["grid"]
+    fp = res.get("fp64")
     out = {
         "metric": METRIC,
-        "value": r["solves_per_s"] if r["valid"] else 0.0,
+        "value": r["solves_per_s"] if best else 0.0,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -743,24 +870,52 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": dtype,
+        "dtype": DTYPES[bname],
         "data": "synthetic",
         "config": {"workload": "convection-diffusion n=%d (%dx%d grid, mu=1, c=(10,10), +8I) + "
-                               "dense N(0,1e-4) slices, s=%d, p=%d; tGMRES to true relres %.0e "
-                               "(path %s)" % (n, nx, ny, s, p, args.tol, best),
-                   "n": n, "s": s, "p": p, "m": args.m,
-                   "inner_m": path_opts[best].inner_m if best != "fp64" else None,
-                   "tol": args.tol, "path": best},
+                               "dense N(0,1e-4) slices, s=%d, p=%d; FP64 refinement around "
+                               "inner tGMRES(%d) at tol %.0e vs plain FP64 tGMRES(%d), to true "
+                               "relres %.0e (path %s)" % (
+                                   n, nx, ny, s, p, cfg["inner"].get(bname, cfg["m"]),
+                                   args.inner_tol, cfg["m"], args.tol, bname),
+                   "n": n, "s": s, "p": p, "m": cfg["m"],
+                   "inner_m": cfg["inner"].get(bname), "inner_tol": args.inner_tol,
+                   "tol": args.tol, "path": bname},
         "latency_ms": r["latency_ms"],
+        "err_vs_fp64": r.get("err_vs_fp64"),
         "paths": res,
-        "mixed_vs_fp64": (res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"]
-                          if "mixed" in res and "fp64" in res else None),
-        "bf16_vs_fp64": (res["bf16"]["solves_per_s"] / res["fp64"]["solves_per_s"]
-                         if "bf16" in res and "fp64" in res else None),
+        "mixed_vs_fp64": (r["solves_per_s"] / fp["solves_per_s"]) if (best and fp) else None,
+        "fp32_vs_fp64": (res["mixed"]["solves_per_s"] / fp["solves_per_s"]
+                         if "mixed" in res and fp else None),
+        "bf16_vs_fp64": (res["bf16"]["solves_per_s"] / fp["solves_per_s"]
+                         if "bf16" in res and fp else None),
         "roofline": roofline,
         "autotune": tuned,
     }
-    ctx.close()
+    if not args.no_cpu:
+        log("timing the oracle sample on the host ...")
+        fpr = fp or r
+        out["cpu_baseline"] = cpu_baseline(A, B, C, fpr["applies_per_solve"],
+                                           (cfg["m"] + 1) / 2.0)
+    del A, B, C
+    for other in [x for x in args.also.split(",") if x and x != key]:
+        ores, (oA, oB, oC), otuned = run_config(tsylv, workloads, other, args, headline=False)
+        on, os_, op_ = oC.shape
+        orefined = [x for x in ores if x in ("bf16", "mixed") and ores[x].get("valid")]
+        obest = max(orefined, key=lambda x: ores[x]["solves_per_s"]) if orefined else None
+        ofp = ores.get("fp64")
+        entry = {"paths": ores, "autotune": otuned,
+                 "mixed_vs_fp64": (ores[obest]["solves_per_s"] / ofp["solves_per_s"]
+                                   if obest and ofp else None)}
+        if obest:
+            entry["roofline"] = roofline_of(obest, ores[obest], on, os_, op_,
+                                            obest == "bf16" and CONFIGS[other]["inner"]["bf16"]
+                                            + 1 <= 64)
+        if not args.no_cpu and ofp:
+            entry["cpu_fft_baseline"] = cpu_fft_baseline(oA, oB, oC, ofp["applies_per_solve"],
+                                                         (CONFIGS[other]["m"] + 1) / 2.0)
+        out[other] = entry
+        del oA, oB, oC
     if not args.no_extra:
         log("tiny case latency ...")
         out["tiny"] = tiny_latency(tsylv, workloads)
@@ -773,12 +928,6 @@ def main():
         if not args.no_serve_full:
             log("serving at full sizes ...")
             out["serving"]["full_sizes"] = serving_full(tsylv)
-    if not args.no_cpu:
-        log("timing the oracle sample on the host ...")
-        fp = res.get("fp64", r)
-        out["cpu_baseline"] = cpu_baseline(A, B, C, fp["applies_per_solve"], (args.m + 1) / 2.0)
-        out["cpu_fft_baseline"] = cpu_fft_baseline(A, B, C, fp["applies_per_solve"],
-                                                   (args.m + 1) / 2.0)
     print(json.dumps(out), flush=True)
 
 

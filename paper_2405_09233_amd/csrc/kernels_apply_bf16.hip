@@ -767,13 +767,20 @@ __device__ __forceinline__ void w32_tasks(const Bf16Args& a, int k, int64_t rb32
     for (int u = 0; u < D; ++u) loadA(u, u);
     put(0);
     __syncthreads();
-    for (int64_t ph = 0; ph < nph; ++ph) {
+    // Super-phases of L = lcm(P, D) k blocks, so that the ring slot of every
+    // k block is known at compile time (it is kb % D) whatever P and D are.
+    constexpr int L = (P % D == 0) ? P : ((D % P == 0) ? D : P * D);
+    static_assert(kKPad % L == 0, "a super-phase must divide the k padding");
+    for (int64_t sp = 0; sp < nkb / L; ++sp)
+#pragma unroll
+    for (int q = 0; q < L / P; ++q) {
+      const int64_t ph = sp * (L / P) + q;
       const int buf = (int)(ph & 1);
       fetch(min(ph + 1, nph - 1));
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < P; ++u) {
-        const int d = u % D;
+        const int d = (q * P + u) % D;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int off = h ? off1 : off0;
@@ -838,7 +845,7 @@ __global__ __launch_bounds__(NW * 64) void apply_bf16_w32_kernel(Bf16Args a, WgP
 
 template <int CB32, int D, int P, int NW, int RW, bool TIO>
 void launch_w32(Bf16Args a, int ncu, hipStream_t st) {
-  static_assert(kKPad % P == 0 && P % D == 0, "phase and ring must divide the k padding");
+  static_assert(kKPad % P == 0 && kKPad % D == 0, "phase and ring must divide the k padding");
   a.nct = (int)((a.s + 32 * CB32 - 1) / (32 * CB32));
   const WgPlan pl = plan_wg(a.n, a.p, a.nct, 2 * NW * RW, ncu);
   const int nsl = num_slices(a.p), nreal = (a.p % 2 == 0 && a.p > 1) ? 2 : 1;
@@ -899,6 +906,9 @@ void launch_cfg(const Bf16Args& a, int variant, hipStream_t st) {
     case 4: launch_w32<4, 2, 2, 8, 1, TIO>(a, ncu, st); break;
     case 5: launch_w32<2, 2, 2, 8, 1, TIO>(a, ncu, st); break;
     case 6: launch_w32<4, 2, 2, 4, 2, TIO>(a, ncu, st); break;
+    case 7: launch_w32<4, 4, 2, 4, 1, TIO>(a, ncu, st); break;
+    case 8: launch_w32<4, 8, 2, 4, 1, TIO>(a, ncu, st); break;
+    case 9: launch_w32<2, 4, 2, 8, 1, TIO>(a, ncu, st); break;
     default: throw Error(TSYLV_EINVAL, "apply: unknown BF16 variant");
   }
 }
