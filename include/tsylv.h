@@ -45,8 +45,11 @@ typedef enum {
   TSYLV_METHOD_FOM = 1,   /* tFOM(m), Algorithm 3                          */
   TSYLV_METHOD_TBA = 2,   /* TBAS(m), Algorithm 8 (block size s)           */
   TSYLV_METHOD_TBS = 3,   /* t-Bartels-Stewart direct solve, Algorithm 5   */
-  TSYLV_METHOD_GMRES_BATCHED = 4 /* tGMRES(m) served in lockstep batches
-                                    (tsylv_submit only; see below)          */
+  TSYLV_METHOD_GMRES_BATCHED = 4, /* tGMRES(m) served in lockstep batches
+                                     (tsylv_submit only; see below)         */
+  TSYLV_METHOD_AUTO = 5  /* tsylv_submit only: the t-Bartels-Stewart direct
+                            solve when n, s <= 64 and the request is FP64
+                            without refinement, else tGMRES(m)              */
 } tsylv_method;
 
 typedef enum {
@@ -206,6 +209,26 @@ typedef struct {
 size_t tsylv_batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_opts* opts);
 int tsylv_gmres_batch(tsylv_ctx* ctx, int count, const tsylv_problem* probs,
                       const tsylv_opts* opts, tsylv_info* infos);
+
+/* t-Bartels-Stewart (Algorithm 5 of section 4, with the t-Schur
+ * decomposition of Algorithm 4) for a batch of small independent instances
+ * (1 <= n, s <= 64, 1 <= p <= 4096 each; sizes may differ), in one pass:
+ * one launch transforms every A, B and C (mode-3 DFT), one solves every
+ * Fourier slice of every instance (one wavefront per (instance, slice):
+ * complex Schur forms, triangular Sylvester back substitution), two form the
+ * FP64 residual C - M(X) of every instance in the Fourier planes and its
+ * norm, one transforms every X back; the host synchronises once.  Only
+ * opts->tol is read (opts may be NULL: 1e-8).  infos[i]: TSYLV_OK when
+ * instance i's true relative residual (relres_true) is <= tol, else
+ * TSYLV_NOT_CONVERGED with the direct solution in X; TSYLV_ESINGULAR when a
+ * slice's spectra of Ahat and Bhat meet, TSYLV_EBREAKDOWN when a Schur
+ * iteration does not converge; seconds is the whole batch's time.  Returns
+ * TSYLV_OK when every instance is TSYLV_OK, TSYLV_NOT_CONVERGED otherwise,
+ * or an error of the whole batch (TSYLV_EINVAL, TSYLV_ENOMEM, TSYLV_EHIP).
+ * Synchronous on the context stream. */
+size_t tsylv_tbs_batch_workspace_bytes(int count, const tsylv_problem* probs);
+int tsylv_tbs_batch(tsylv_ctx* ctx, int count, const tsylv_problem* probs,
+                    const tsylv_opts* opts, tsylv_info* infos);
 
 /* Synthetic instances drawn on the device (a project addition for serving
  * workloads; not in the paper).  Writes the dense instance of `seed`:

@@ -31,6 +31,16 @@ int guarded(F&& f) {
   }
 }
 
+// A size query that never throws (0 on any failure).
+template <typename F>
+size_t guarded_size(F&& f) {
+  try {
+    return f();
+  } catch (...) {
+    return 0;
+  }
+}
+
 bool dims_ok(int64_t n, int64_t s, int64_t p) {
   return n > 0 && s > 0 && p > 0 && n <= (int64_t(1) << 20) && s <= (int64_t(1) << 20) &&
          p <= 4096;
@@ -263,6 +273,26 @@ int tsylv_gmres_batch(tsylv_ctx* ctx, int count, const tsylv_problem* probs,
   });
 }
 
+size_t tsylv_tbs_batch_workspace_bytes(int count, const tsylv_problem* probs) {
+  if (count < 1 || count > (1 << 20) || !probs) return 0;
+  return guarded_size([&]() { return tbs_batch_workspace_bytes(count, probs); });
+}
+
+int tsylv_tbs_batch(tsylv_ctx* ctx, int count, const tsylv_problem* probs, const tsylv_opts* opts,
+                    tsylv_info* infos) {
+  if (!ctx || !infos || !probs || count < 1 || count > (1 << 20)) return TSYLV_EINVAL;
+  if (tbs_batch_workspace_bytes(count, probs) == 0) return TSYLV_EINVAL;
+  tsylv_opts o;
+  tsylv_default_opts(TSYLV_METHOD_TBS, &o);
+  if (opts) o.tol = opts->tol;
+  if (!(o.tol >= 0.0)) return TSYLV_EINVAL;
+  return guarded([&]() {
+    std::lock_guard<std::mutex> lk(ctx->c.sync_mu);
+    set_device(ctx);
+    return tbs_batch(ctx->c, count, probs, o, infos);
+  });
+}
+
 int tsylv_generate(tsylv_ctx* ctx, uint64_t seed, int64_t n, int64_t s, int64_t p, double* A,
                    double* B, double* C) {
   if (!ctx || !dims_ok(n, s, p)) return TSYLV_EINVAL;
@@ -280,7 +310,12 @@ int tsylv_generate(tsylv_ctx* ctx, uint64_t seed, int64_t n, int64_t s, int64_t 
 
 int tsylv_submit(tsylv_ctx* ctx, const tsylv_request* req, uint64_t* ticket) {
   if (!ctx || !req || !ticket) return TSYLV_EINVAL;
-  const tsylv_request& r = *req;
+  tsylv_request r = *req;
+  // AUTO: the direct solve for small FP64 instances, tGMRES otherwise
+  if (r.method == TSYLV_METHOD_AUTO)
+    r.method = (tbs_dims_ok(r.n, r.s) && !r.opts.refine && r.opts.prec == TSYLV_FP64)
+                   ? TSYLV_METHOD_TBS
+                   : TSYLV_METHOD_GMRES;
   const bool given = r.A && r.B && r.C, generated = !r.A && !r.B && !r.C;
   if (!(given || generated) || !r.X || !dims_ok(r.n, r.s, r.p)) return TSYLV_EINVAL;
   if (generated && r.p > kern::kGenXformMaxP) return TSYLV_EINVAL;

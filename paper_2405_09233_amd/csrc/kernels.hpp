@@ -94,6 +94,35 @@ void apply_bf16_tiled(const uint16_t* At, const uint16_t* Bb, const bf16t* V, bf
 // tbs_max_size().  `scratch` holds 2 tbs_scratch_complex(n, s, p) doubles;
 // *info (device int, zero on entry) is raised to 1 if a Schur iteration did
 // not converge and to 2 if a slice's triangular equation is singular.
+// Arguments of one instance of the direct solve (device pointers).
+struct TbsArgs {
+  const double* Ah;  // operator planes (p planes n x n)
+  const double* Bh;  // p planes s x s
+  const double* Zc;  // right-hand side planes (p planes n x s)
+  double* Zx;        // solution planes
+  double2* scr;      // per slice: S (s x s), V (s x s), G (n x s), F (n x s)
+  int* info;         // raised to 1 (Schur did not converge) or 2 (singular)
+  int n, s, p;
+};
+// Many instances at once: d_args[count] (device), d_first[count + 1] the
+// prefix sums of the instances' slice counts (total_slices = d_first[count]);
+// one wavefront per (instance, slice) solves, then the FP64 residual in the
+// Fourier planes: d_norms[2 i] = ||C - M(X)||^2, d_norms[2 i + 1] = ||C||^2
+// of instance i (d_part: 2 total_slices doubles).
+void tbs_batch(const TbsArgs* d_args, const int* d_first, int count, int total_slices,
+               double* d_part, double* d_norms, hipStream_t st);
+// Tube transforms of many tensors in one launch (descriptor d: out[q E + e]
+// = sum_j M[q p + j] in[j E + e]); d_bfirst[d] the first of its
+// ceil(E / 256) blocks, total_blocks = d_bfirst[ndesc].
+struct XformDesc {
+  const double* in;
+  double* out;
+  const double* M;
+  int64_t E;
+  int p;
+};
+void batch_xform(const XformDesc* d_descs, const int* d_bfirst, int ndesc, int total_blocks,
+                 hipStream_t st);
 int tbs_max_size();
 int64_t tbs_scratch_complex(int64_t n, int64_t s, int p);
 void tbs_solve(const double* Ah, const double* Bh, const double* Zc, double* Zx, int64_t n,
@@ -206,6 +235,30 @@ int proj_max_block();
 int64_t proj_u_stride(int s, int m);
 void proj_solve(const double* Hm, const double* lam, const double* D, double* z, double* Wrk,
                 double* U, int* info, int ms, int s, int m, int nsys, hipStream_t st);
+
+// Device small linear algebra of a TBAS cycle (kernels_tba.hip).  Planar
+// matrices use the half-spectrum plane layout (p planes, s x s or J x s,
+// column-major); Hm, Hlast, D, W, Winv and z are interleaved complex.
+//  cholqr_pass: one shifted-Cholesky-QR pass per slice: Rinv = R^{-1},
+//    Racc = R Racc (first pass: Racc = R, and the diagonal of G shifted by
+//    shift_factor trace(G)); *flag |= 1 on a pivot <= rel_tol max diag.
+//  tube_test: *flag |= 1 when a diagonal tube of Racc is not invertible.
+//  hm_column: block column j of Hm from G1 + G2 and the QR factor Rq (to
+//    Hlast for the last column).
+//  proj_rhs: D_k = H0_k W_k.  proj_y: Y_k = Z_k Winv_k (planar) and
+//    est[k] = ||Hlast_k Y_k(last block row)||^2.  proj_check: *flag |= 1 on
+//    a zero pivot or a non-finite solution.
+int cholqr_max_block();
+void cholqr_pass(const double* G, double* Rinv, double* Racc, int s, int p, double shift_factor,
+                 bool first, double rel_tol, int* flag, hipStream_t st);
+void tube_test(const double* Racc, int s, int p, bool scaled, int* flag, hipStream_t st);
+void hm_column(const double* G1, const double* G2, const double* Rq, double* Hm, double* Hlast,
+               int j, int s, int m, int p, hipStream_t st);
+void proj_rhs(const double* H0, const double* W, double* D, int s, int p, hipStream_t st);
+void proj_y(const double* z, const double* Winv, const double* Hlast, double* Y, double* est,
+            int s, int m, int p, hipStream_t st);
+void proj_check(const int* info, const double* z, int64_t nsys, int64_t nz, int* flag,
+                hipStream_t st);
 
 // Number of K splits zgemm uses when given a partial buffer, and the size of
 // that buffer in doubles.

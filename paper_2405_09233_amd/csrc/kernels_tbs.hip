@@ -214,22 +214,13 @@ __device__ bool schur_wave(double2* W, double2* U, double2* v, int n) {
   return true;
 }
 
-struct TbsArgs {
-  const double* Ah;  // operator planes (p planes n x n)
-  const double* Bh;  // p planes s x s
-  const double* Zc;  // right-hand side planes (p planes n x s)
-  double* Zx;        // solution planes
-  double2* scr;      // per slice: S (s x s), V (s x s), G (n x s), F (n x s)
-  int* info;         // raised to 1 (Schur did not converge) or 2 (singular)
-  int n, s, p;
-};
-
-__global__ __launch_bounds__(64) void tbs_slice_kernel(TbsArgs a) {
+// Slice k of one instance, by the one wavefront of the workgroup.
+__device__ void tbs_slice(const TbsArgs& a, int k) {
   extern __shared__ __attribute__((aligned(16))) double2 tbs_lds[];
   double2* W = tbs_lds;
   double2* U = W + kTbsLd * kTbsMax;
   double2* v = U + kTbsLd * kTbsMax;
-  const int k = blockIdx.x, lane = threadIdx.x;
+  const int lane = threadIdx.x;
   const int n = a.n, s = a.s;
   int qr, qi;
   slice_planes(a.p, k, qr, qi);
@@ -335,9 +326,142 @@ __global__ __launch_bounds__(64) void tbs_slice_kernel(TbsArgs a) {
   if (lane == 0 && any) atomicMax(a.info, any);
 }
 
+__global__ __launch_bounds__(64) void tbs_slice_kernel(TbsArgs a) { tbs_slice(a, blockIdx.x); }
+
+// Many instances in one launch: workgroup b serves slice b - first[i] of
+// the instance i whose range [first[i], first[i + 1]) holds b.
+__global__ __launch_bounds__(64) void tbs_batch_slice_kernel(const TbsArgs* __restrict__ args,
+                                                             const int* __restrict__ first,
+                                                             int count) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {  // last instance with first[i] <= b
+    const int mid = (lo + hi + 1) / 2;
+    if (first[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  tbs_slice(args[lo], b - first[lo]);
+}
+
+// Residual of the direct solve in the Fourier planes, per (instance,
+// slice): R_k = Chat_k - (Ahat_k Xhat_k - Xhat_k Bhat_k) on the scaled
+// planes, so that sum_k ||R_k||^2 over the stored reals is ||C - M(X)||^2
+// (Parseval); part[2 (first[i] + k)] receives slice k's ||R_k||^2 and
+// part[2 (first[i] + k) + 1] its ||Chat_k||^2.  One wavefront per slice,
+// lane = row.
+__global__ __launch_bounds__(64) void tbs_batch_residual_kernel(const TbsArgs* __restrict__ args,
+                                                                const int* __restrict__ first,
+                                                                int count,
+                                                                double* __restrict__ part) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (first[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const TbsArgs& a = args[lo];
+  const int k = b - first[lo], lane = threadIdx.x;
+  const int n = a.n, s = a.s;
+  int qr, qi;
+  slice_planes(a.p, k, qr, qi);
+  const int64_t ns = (int64_t)n * s, nn = (int64_t)n * n, ss = (int64_t)s * s;
+  auto pl = [&](const double* P, int64_t plane, int64_t off) -> double2 {
+    return make_double2(P[qr * plane + off], qi >= 0 ? P[qi * plane + off] : 0.0);
+  };
+  double rr = 0.0, cc = 0.0;
+  if (lane < n) {
+    for (int j = 0; j < s; ++j) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int l = 0; l < n; ++l)
+        acc = cadd(acc, cmul(pl(a.Ah, nn, lane + (int64_t)n * l), pl(a.Zx, ns, l + (int64_t)n * j)));
+      for (int l = 0; l < s; ++l)
+        acc = csub(acc, cmul(pl(a.Zx, ns, lane + (int64_t)n * l), pl(a.Bh, ss, l + (int64_t)s * j)));
+      const double2 c = pl(a.Zc, ns, lane + (int64_t)n * j);
+      const double2 r = csub(c, acc);
+      rr += r.x * r.x + (qi >= 0 ? r.y * r.y : 0.0);
+      cc += c.x * c.x + (qi >= 0 ? c.y * c.y : 0.0);
+    }
+  }
+  // fixed-order wave sums
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    rr += __shfl_xor(rr, off, 64);
+    cc += __shfl_xor(cc, off, 64);
+  }
+  if (lane == 0) {
+    part[2 * (int64_t)b] = rr;
+    part[2 * (int64_t)b + 1] = cc;
+  }
+}
+
+// out[2 i] = sum_k ||R_k||^2, out[2 i + 1] = sum_k ||Chat_k||^2 of instance
+// i, in slice order.
+__global__ void tbs_batch_norms_kernel(const double* __restrict__ part,
+                                       const int* __restrict__ first, int count,
+                                       double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double rr = 0.0, cc = 0.0;
+  for (int b = first[i]; b < first[i + 1]; ++b) {
+    rr += part[2 * (int64_t)b];
+    cc += part[2 * (int64_t)b + 1];
+  }
+  out[2 * i] = rr;
+  out[2 * i + 1] = cc;
+}
+
+// Tube transforms of many tensors in one launch: descriptor d maps the
+// tubes of its tensor, out[q E + e] = sum_j M[q p + j] in[j E + e], with
+// blocks [bfirst[d], bfirst[d + 1]) of 256 tubes each.
+__global__ __launch_bounds__(256) void batch_xform_kernel(const XformDesc* __restrict__ descs,
+                                                          const int* __restrict__ bfirst,
+                                                          int ndesc) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (bfirst[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const XformDesc& d = descs[lo];
+  const int64_t e = (int64_t)(b - bfirst[lo]) * 256 + threadIdx.x;
+  if (e >= d.E) return;
+  const int p = d.p;
+  for (int q = 0; q < p; ++q) {
+    double acc = 0.0;
+    for (int j = 0; j < p; ++j) acc = fma(d.M[q * p + j], d.in[j * d.E + e], acc);
+    d.out[q * d.E + e] = acc;
+  }
+}
+
 }  // namespace
 
 int tbs_max_size() { return kTbsMax; }
+
+void tbs_batch(const TbsArgs* d_args, const int* d_first, int count, int total_slices,
+               double* d_part, double* d_norms, hipStream_t st) {
+  const size_t lds = (2 * (size_t)kTbsLd * kTbsMax + kTbsMax) * sizeof(double2);
+  TSYLV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tbs_batch_slice_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(tbs_batch_slice_kernel, dim3(total_slices), dim3(64), lds, st, d_args,
+                     d_first, count);
+  TSYLV_LAUNCH_CHECK();
+  hipLaunchKernelGGL(tbs_batch_residual_kernel, dim3(total_slices), dim3(64), 0, st, d_args,
+                     d_first, count, d_part);
+  TSYLV_LAUNCH_CHECK();
+  hipLaunchKernelGGL(tbs_batch_norms_kernel, dim3((count + 63) / 64), dim3(64), 0, st, d_part,
+                     d_first, count, d_norms);
+  TSYLV_LAUNCH_CHECK();
+}
+
+void batch_xform(const XformDesc* d_descs, const int* d_bfirst, int ndesc, int total_blocks,
+                 hipStream_t st) {
+  if (total_blocks <= 0) return;
+  hipLaunchKernelGGL(batch_xform_kernel, dim3(total_blocks), dim3(256), 0, st, d_descs, d_bfirst,
+                     ndesc);
+  TSYLV_LAUNCH_CHECK();
+}
 
 int64_t tbs_scratch_complex(int64_t n, int64_t s, int p) {
   return (int64_t)num_slices(p) * (2 * s * s + 2 * n * s);

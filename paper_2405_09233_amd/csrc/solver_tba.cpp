@@ -75,21 +75,6 @@ void pack(const cplx* in, int p, int k, int rows, int cols, double* buf) {
   }
 }
 
-// Page-locked host memory for the per-step transfers of a solve.
-struct PinnedBuf {
-  double* p = nullptr;
-  explicit PinnedBuf(size_t count) {
-    void* h = nullptr;
-    TSYLV_HIP(hipHostMalloc(&h, std::max<size_t>(count, 1) * sizeof(double), hipHostMallocDefault));
-    p = static_cast<double*>(h);
-  }
-  ~PinnedBuf() {
-    if (p) (void)hipHostFree(p);
-  }
-  PinnedBuf(const PinnedBuf&) = delete;
-  PinnedBuf& operator=(const PinnedBuf&) = delete;
-};
-
 template <typename F>
 void parallel_slices(int ph, F&& f) {
   int nt = (int)std::thread::hardware_concurrency();
@@ -125,10 +110,19 @@ int64_t tba_partial_elems(int64_t n, int64_t s, int64_t p, int m) {
 }
 
 // Device buffers of the projected solve (interleaved complex doubles).
+// The device-resident cycle: projected solve and Tubal-QR factorisations on
+// the GPU (s <= 64).  `out` is the one block read back per cycle: ||R||^2,
+// the estimate terms of every slice and the flags (QR of R0, QR of step j,
+// projected solve).
 struct ProjWS {
   double *Hm = nullptr, *lam = nullptr, *D = nullptr, *z = nullptr, *Wrk = nullptr, *U = nullptr;
+  double *W = nullptr, *Winv = nullptr, *Hlast = nullptr, *G2 = nullptr, *H0 = nullptr,
+         *Rq = nullptr, *out = nullptr;
   int* info = nullptr;
-  static bool possible(int64_t s) { return s <= kern::proj_max_block(); }
+  static bool possible(int64_t s) {
+    return s <= kern::proj_max_block() && s <= kern::cholqr_max_block();
+  }
+  static int64_t out_doubles(int64_t p, int m) { return 1 + num_slices((int)p) + (m + 3); }
   static size_t bytes(int64_t s, int64_t p, int m) {
     if (!possible(s)) return 0;
     const int64_t ph = num_slices((int)p), ms = (int64_t)m * s, nsys = ph * s;
@@ -136,7 +130,9 @@ struct ProjWS {
            Workspace::bytes_for(2 * ph * s * s, 8) + Workspace::bytes_for(2 * nsys * ms, 8) +
            Workspace::bytes_for(2 * nsys * s * ms, 8) +
            Workspace::bytes_for(2 * nsys * kern::proj_u_stride((int)s, m), 8) +
-           Workspace::bytes_for(nsys, 4);
+           Workspace::bytes_for(nsys, 4) + 3 * Workspace::bytes_for(2 * ph * s * s, 8) +
+           Workspace::bytes_for(p * ms * s, 8) + 2 * Workspace::bytes_for(p * s * s, 8) +
+           Workspace::bytes_for(out_doubles(p, m), 8);
   }
   void carve(Workspace& ws, int64_t s, int64_t p, int m) {
     if (!possible(s)) return;
@@ -148,6 +144,13 @@ struct ProjWS {
     Wrk = ws.take<double>(2 * nsys * s * ms);
     U = ws.take<double>(2 * nsys * kern::proj_u_stride((int)s, m));
     info = ws.take<int>(nsys);
+    W = ws.take<double>(2 * ph * s * s);
+    Winv = ws.take<double>(2 * ph * s * s);
+    Hlast = ws.take<double>(2 * ph * s * s);
+    G2 = ws.take<double>(p * ms * s);
+    H0 = ws.take<double>(p * s * s);
+    Rq = ws.take<double>(p * s * s);
+    out = ws.take<double>(out_doubles(p, m));
   }
 };
 
@@ -258,6 +261,38 @@ size_t tba_workspace_bytes(int64_t n, int64_t s, int64_t p, int m) {
   return tba_ws_bytes(n, s, p, m);
 }
 
+namespace {
+
+// Device Tubal-QR of the n x s block Win into Qout (may alias Win): three
+// shifted-Cholesky-QR passes with the small factorisations on the device;
+// Racc receives R (planar s x s per slice); *flag |= 1 on a failed
+// factorisation or a non-invertible tube.  No host synchronisation.
+void tubal_qr_dev(Ctx& ctx, const TbaWS& w, const double* Win, double* Qout, double* Racc,
+                  bool scaled, int* flag) {
+  const int s = (int)w.s, p = (int)w.p;
+  const int64_t n = w.n, ns = n * w.s, ss = w.s * w.s;
+  const double shift_factor = 11.0 * ((double)n * s + (double)s * (s + 1)) * kEps;
+  constexpr int kPasses = 3;
+  const double* src = Win;
+  for (int pass = 0; pass < kPasses; ++pass) {
+    kern::zgemm(kern::dense_pmat(src, ns, n), true, kern::dense_pmat(src, ns, n), w.Gq, ss,
+                w.s, w.s, w.s, n, 1.0, 0.0, p, w.partial, ctx.stream);
+    kern::cholqr_pass(w.Gq, w.Rinv, Racc, s, p, shift_factor, pass == 0, 1e3 * kEps * kEps,
+                      flag, ctx.stream);
+    double* dst = ((kPasses - 1 - pass) % 2 == 0) ? Qout : w.T;
+    if (dst == src) dst = (dst == w.T) ? Qout : w.T;
+    kern::zgemm(kern::dense_pmat(src, ns, n), false, kern::dense_pmat(w.Rinv, ss, w.s), dst, ns,
+                n, n, w.s, w.s, 1.0, 0.0, p, nullptr, ctx.stream);
+    src = dst;
+  }
+  if (src != Qout)
+    TSYLV_HIP(hipMemcpyAsync(Qout, src, w.N * sizeof(double), hipMemcpyDeviceToDevice,
+                             ctx.stream));
+  kern::tube_test(Racc, s, p, scaled, flag, ctx.stream);
+}
+
+}  // namespace
+
 int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
               const double* C, double* X, const tsylv_opts& o, tsylv_info& info) {
   auto t0 = std::chrono::steady_clock::now();
@@ -314,39 +349,6 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
                                     Wk[k].data(), Wik[k].data());
     });
     for (int k = 0; k < ph; ++k) dev_proj = dev_proj && kap[k] < 1e8;
-    if (dev_proj)
-      TSYLV_HIP(hipMemcpyAsync(pw.lam, lam_all.data(), lam_all.size() * sizeof(cplx),
-                               hipMemcpyHostToDevice, st));
-  }
-  // page-locked staging for everything that crosses PCIe every step / cycle
-  const size_t nss = (size_t)p * ss, nG = (size_t)p * ms * s;
-  const size_t nHm = (size_t)ph * msi * msi, nD = (size_t)ph * ss, nz = (size_t)ph * si * msi,
-               ninfo = (size_t)ph * si;
-  size_t total = 2 * nss + 3 * nG;
-  if (dev_proj) total += 2 * (nHm + nD + nz) + (ninfo + 1) / 2;
-  PinnedBuf pin(total);
-  double* q = pin.p;
-  double* qr_buf = q;
-  q += nss;
-  double* qr_rinv = q;
-  q += nss;
-  double* hG = q;
-  q += nG;
-  double* hG2 = q;
-  q += nG;
-  double* hY = q;
-  q += nG;
-  std::fill(hY, hY + nG, 0.0);
-  cplx *hHm = nullptr, *hD = nullptr, *hz = nullptr;
-  int* hinfo = nullptr;
-  if (dev_proj) {
-    hHm = reinterpret_cast<cplx*>(q);
-    q += 2 * nHm;
-    hD = reinterpret_cast<cplx*>(q);
-    q += 2 * nD;
-    hz = reinterpret_cast<cplx*>(q);
-    q += 2 * nz;
-    hinfo = reinterpret_cast<int*>(q);
   }
   info.steps = info.cycles = info.outer = 0;
   info.res_hist_len = 0;
@@ -359,153 +361,242 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
     info.seconds = seconds_since(t0);
     return TSYLV_OK;
   }
-  std::vector<std::vector<cplx>> Hk(ph, std::vector<cplx>((size_t)(ms + s) * ms));
-  std::vector<std::vector<cplx>> H0(ph, std::vector<cplx>((size_t)ss));
-  std::vector<std::vector<cplx>> Rq(ph, std::vector<cplx>((size_t)ss));
   int status = TSYLV_NOT_CONVERGED;
 
-  for (int cycle = 0;; ++cycle) {
-    // R0 = C - M(X0) (Algorithm 8 step 2)
-    if (cycle == 0 && !o.x0_given) {
-      TSYLV_HIP(hipMemcpyAsync(w.R, S.Zc, w.N * sizeof(double), hipMemcpyDeviceToDevice, st));
-    } else {
-      ProfScope ps(ctx, TSYLV_K_APPLY, st);
-      kern::apply_f64(S.Ah, S.Bh, S.Zx, w.R, S.Zc, -1.0, 1.0, n, s, (int)p, st, var64);
+  if (dev_proj) {
+    // eigenvalues and eigenvector bases of the Bhat_k (once per solve)
+    std::vector<cplx> hW((size_t)ph * ss), hWi((size_t)ph * ss);
+    for (int k = 0; k < ph; ++k) {
+      std::copy(Wk[k].begin(), Wk[k].end(), hW.begin() + (size_t)k * ss);
+      std::copy(Wik[k].begin(), Wik[k].end(), hWi.begin() + (size_t)k * ss);
     }
-    info.relres_true = std::sqrt(dev_norm2(ctx, w, w.R)) / cnorm;
-    if (info.relres_true <= o.tol) {
-      status = TSYLV_OK;
-      break;
-    }
-    if (cycle >= o.max_cycles) break;
-    info.cycles++;
-    // Algorithm 7 step 2: [V_1, H0] = Tubal-QR(R0)
-    if (!tubal_qr(ctx, w, w.R, w.V(0), H0, true, qr_buf, qr_rinv))
-      throw Error(TSYLV_EBREAKDOWN, "Tubal-QR(R0)");
-    for (auto& h : Hk) std::fill(h.begin(), h.end(), cplx(0.0));
-    for (int j = 0; j < m; ++j) {
-      const int64_t J = (int64_t)(j + 1) * s;
-      double* W = w.V(j + 1);
-      {
+    TSYLV_HIP(hipMemcpyAsync(pw.lam, lam_all.data(), lam_all.size() * sizeof(cplx),
+                             hipMemcpyHostToDevice, st));
+    TSYLV_HIP(hipMemcpyAsync(pw.W, hW.data(), hW.size() * sizeof(cplx), hipMemcpyHostToDevice, st));
+    TSYLV_HIP(hipMemcpyAsync(pw.Winv, hWi.data(), hWi.size() * sizeof(cplx),
+                             hipMemcpyHostToDevice, st));
+    ctx.sync();  // the host vectors go out of scope
+    // The cycle out block: [0] ||R||^2, [1 .. ph] estimate terms, then the
+    // int flags (QR of R0, QR of steps 0 .. m-1, projected solve).
+    const int64_t nout = ProjWS::out_doubles(p, m);
+    double* hout = ctx.host_buffer((size_t)nout);
+    int* dflags = reinterpret_cast<int*>(pw.out + 1 + ph);
+    const int nflags = m + 2;
+    bool pending = false;  // a finished cycle whose flags are in `out`
+    for (int cycle = 0;; ++cycle) {
+      // R0 = C - M(X0) (Algorithm 8 step 2) and its norm, read back with the
+      // previous cycle's flags and estimate: the one host round trip of a
+      // cycle
+      if (cycle == 0 && !o.x0_given) {
+        TSYLV_HIP(hipMemcpyAsync(w.R, S.Zc, w.N * sizeof(double), hipMemcpyDeviceToDevice, st));
+      } else {
         ProfScope ps(ctx, TSYLV_K_APPLY, st);
-        kern::apply_f64(S.Ah, nullptr, w.V(j), W, nullptr, 1.0, 0.0, n, s, (int)p, st,
-                        var64);  // A only
+        kern::apply_f64(S.Ah, S.Bh, S.Zx, w.R, S.Zc, -1.0, 1.0, n, s, (int)p, st, var64);
       }
-      // block CGS2: H_{0..j, j} = V^H W (twice), W -= V H
-      const kern::PMat Vb{w.basis, ns, n, s, w.ldv};
-      if (ctx.prof.on(TSYLV_K_ORTHO)) ctx.prof.begin(TSYLV_K_ORTHO, st);
-      for (int pass = 0; pass < 2; ++pass) {
-        kern::zgemm(Vb, true, kern::dense_pmat(W, ns, n), w.G, J * s, J, J, s, n, 1.0, 0.0,
-                    (int)p, w.partial, st);
-        kern::zgemm(Vb, false, kern::dense_pmat(w.G, J * s, J), W, ns, n, n, s, J, -1.0, 1.0,
-                    (int)p, nullptr, st);
-        double* dst = pass == 0 ? hG : hG2;
-        TSYLV_HIP(hipMemcpyAsync(dst, w.G, (size_t)p * J * s * 8, hipMemcpyDeviceToHost, st));
-      }
-      if (ctx.prof.on(TSYLV_K_ORTHO)) ctx.prof.end(TSYLV_K_ORTHO, st);
+      kern::mdot_partial((const double*)nullptr, 0, 0, w.R, w.N, w.part, 2, 1, st);
+      kern::reduce_partials(w.part, w.nchunks, 2, 1, pw.out, st);
+      TSYLV_HIP(hipMemcpyAsync(hout, pw.out, nout * sizeof(double), hipMemcpyDeviceToHost, st));
       ctx.sync();
-      const int Ji = (int)J;
-      parallel_slices(ph, [&](int k) {
-        std::vector<cplx> g1((size_t)Ji * si), g2((size_t)Ji * si);
-        unpack(hG, (int)p, k, Ji, si, g1.data());
-        unpack(hG2, (int)p, k, Ji, si, g2.data());
-        const int ldh = msi + si;
-        for (int c = 0; c < si; ++c)
-          for (int r = 0; r < Ji; ++r)
-            Hk[k][r + (size_t)ldh * (j * si + c)] = g1[r + (size_t)Ji * c] + g2[r + (size_t)Ji * c];
-      });
-      // Tubal-QR(W) -> V_{j+1}, H_{j+1,j}
-      const bool qr_ok = tubal_qr(ctx, w, W, W, Rq, false, qr_buf, qr_rinv);
-      if (!qr_ok) {
-        if (j < m - 1) throw Error(TSYLV_EBREAKDOWN, "Tubal-QR in TBA");
-        for (auto& r : Rq) std::fill(r.begin(), r.end(), cplx(0.0));  // H_{m+1,m} = 0
+      if (pending) {
+        const int* hf = reinterpret_cast<const int*>(hout + 1 + ph);
+        if (hf[0]) throw Error(TSYLV_EBREAKDOWN, "Tubal-QR(R0)");
+        for (int j = 0; j + 1 < m; ++j)
+          if (hf[1 + j]) throw Error(TSYLV_EBREAKDOWN, "Tubal-QR in TBA");
+        if (hf[m + 1]) throw Error(TSYLV_ESINGULAR, "projected Sylvester equation");
+        double est2 = 0.0;
+        if (!hf[m])  // a breakdown in the last QR means H_{m+1,m} = 0
+          for (int k = 0; k < ph; ++k) est2 += hout[1 + k];
+        info.relres_est = std::sqrt(est2) / cnorm;
+        if (o.res_hist && info.res_hist_len < o.res_hist_cap)
+          o.res_hist[info.res_hist_len++] = info.relres_est;
       }
-      for (int k = 0; k < ph; ++k) {
-        const int ldh = msi + si;
-        for (int c = 0; c < si; ++c)
-          for (int r = 0; r < si; ++r)
-            Hk[k][(size_t)(J + r) + (size_t)ldh * (j * si + c)] = Rq[k][r + (size_t)si * c];
+      info.relres_true = std::sqrt(hout[0]) / cnorm;
+      if (info.relres_true <= o.tol) {
+        status = TSYLV_OK;
+        break;
       }
-      info.steps++;
-    }
-    // Algorithm 8 step 3(b): H_m Y - Y B = [H0; 0] per slice
-    std::vector<int> good(ph, 1);
-    double est2 = 0.0;
-    std::vector<double> est_k(ph, 0.0);
-    auto finish_slice = [&](int k, const std::vector<cplx>& Yk) {
-      const int ldh = msi + si;
-      pack(Yk.data(), (int)p, k, msi, si, hY);
-      // residual estimate: || H_{m+1,m} Y_m ||_F for this slice
-      double e = 0.0;
-      for (int c = 0; c < si; ++c)
-        for (int r = 0; r < si; ++r) {
-          cplx v = 0.0;
-          for (int l = 0; l < si; ++l)
-            v += Hk[k][(size_t)(msi + r) + (size_t)ldh * ((m - 1) * si + l)] *
-                 Yk[(size_t)((m - 1) * si + l) + (size_t)msi * c];
-          e += (k == 0 || 2 * k == (int)p) ? v.real() * v.real() : std::norm(v);
+      if (cycle >= o.max_cycles) break;
+      info.cycles++;
+      TSYLV_HIP(hipMemsetAsync(dflags, 0, nflags * sizeof(int), st));
+      TSYLV_HIP(hipMemsetAsync(pw.Hm, 0, (size_t)ph * ms * ms * sizeof(cplx), st));
+      // Algorithm 7 step 2: [V_1, H0] = Tubal-QR(R0)
+      tubal_qr_dev(ctx, w, w.R, w.V(0), pw.H0, true, dflags);
+      for (int j = 0; j < m; ++j) {
+        const int64_t J = (int64_t)(j + 1) * s;
+        double* W = w.V(j + 1);
+        {
+          ProfScope ps(ctx, TSYLV_K_APPLY, st);
+          kern::apply_f64(S.Ah, nullptr, w.V(j), W, nullptr, 1.0, 0.0, n, s, (int)p, st,
+                          var64);  // A only
         }
-      est_k[k] = e;
-    };
-    bool dev_done = false;
-    if (dev_proj) {
-      // device: (Hm_k - lam_{k,j} I) z_{k,j} = (H0_k W_k) e_j, then Y_k = Z_k W_k^{-1}
-      parallel_slices(ph, [&](int k) {
-        const int ldh = msi + si;
-        for (int c = 0; c < msi; ++c)
-          for (int r = 0; r < msi; ++r)
-            hHm[(size_t)k * msi * msi + r + (size_t)msi * c] = Hk[k][r + (size_t)ldh * c];
-        host::matmul(H0[k].data(), Wk[k].data(), &hD[(size_t)k * ss], si, si, si);
-      });
-      TSYLV_HIP(hipMemcpyAsync(pw.Hm, hHm, nHm * sizeof(cplx), hipMemcpyHostToDevice, st));
-      TSYLV_HIP(hipMemcpyAsync(pw.D, hD, nD * sizeof(cplx), hipMemcpyHostToDevice, st));
-      kern::proj_solve(pw.Hm, pw.lam, pw.D, pw.z, pw.Wrk, pw.U, pw.info, msi, si, m, ph * si, st);
-      TSYLV_HIP(hipMemcpyAsync(hz, pw.z, nz * sizeof(cplx), hipMemcpyDeviceToHost, st));
-      TSYLV_HIP(hipMemcpyAsync(hinfo, pw.info, ninfo * sizeof(int), hipMemcpyDeviceToHost, st));
-      ctx.sync();
-      bool fine = true;
-      for (size_t i = 0; i < ninfo; ++i) fine = fine && hinfo[i] == 0;
-      for (size_t i = 0; fine && i < nz; ++i)
-        fine = std::isfinite(hz[i].real()) && std::isfinite(hz[i].imag());
-      if (fine) {
+        // block CGS2: H_{0..j, j} = V^H W (twice), W -= V H
+        const kern::PMat Vb{w.basis, ns, n, s, w.ldv};
+        if (ctx.prof.on(TSYLV_K_ORTHO)) ctx.prof.begin(TSYLV_K_ORTHO, st);
+        for (int pass = 0; pass < 2; ++pass) {
+          double* G = pass == 0 ? w.G : pw.G2;
+          kern::zgemm(Vb, true, kern::dense_pmat(W, ns, n), G, J * s, J, J, s, n, 1.0, 0.0,
+                      (int)p, w.partial, st);
+          kern::zgemm(Vb, false, kern::dense_pmat(G, J * s, J), W, ns, n, n, s, J, -1.0, 1.0,
+                      (int)p, nullptr, st);
+        }
+        if (ctx.prof.on(TSYLV_K_ORTHO)) ctx.prof.end(TSYLV_K_ORTHO, st);
+        // Tubal-QR(W) -> V_{j+1}, H_{j+1,j}
+        tubal_qr_dev(ctx, w, W, W, pw.Rq, false, dflags + 1 + j);
+        kern::hm_column(w.G, pw.G2, pw.Rq, pw.Hm, pw.Hlast, j, si, m, (int)p, st);
+        info.steps++;
+      }
+      // Algorithm 8 step 3(b): Hm Y - Y Bhat = [H0; 0] per slice, through
+      // the shifted systems (Hm_k - lam_{k,j} I) z = (H0_k W_k) e_j, then
+      // Y_k = Z_k W_k^{-1} and the estimate ||H_{m+1,m} E_m^T Y||
+      kern::proj_rhs(pw.H0, pw.W, pw.D, si, (int)p, st);
+      kern::proj_solve(pw.Hm, pw.lam, pw.D, pw.z, pw.Wrk, pw.U, pw.info, msi, si, m, ph * si,
+                       st);
+      kern::proj_check(pw.info, pw.z, (int64_t)ph * si, (int64_t)ph * si * msi,
+                       dflags + m + 1, st);
+      kern::proj_y(pw.z, pw.Winv, pw.Hlast, w.Y, pw.out + 1, si, m, (int)p, st);
+      // Algorithm 8 step 3(c): X = X0 + V_m Y
+      kern::zgemm(kern::PMat{w.basis, ns, n, s, w.ldv}, false, kern::dense_pmat(w.Y, ms * s, ms),
+                  S.Zx, ns, n, n, s, ms, 1.0, 1.0, (int)p, nullptr, st);
+      pending = true;
+    }
+  } else {
+    // Host path (s > 64, an ill-conditioned eigenvector basis of some Bhat_k,
+    // or TSYLV_TBA_HOST_PROJECTED=1): Tubal-QR factorisations and the
+    // projected solves (Bartels-Stewart with the Schur form of Bhat_k) on
+    // the host, every step's small results copied back.
+    const size_t nss = (size_t)p * ss, nG = (size_t)p * ms * s;
+    const size_t total = 2 * nss + 3 * nG;
+    std::vector<double> stage(total);
+    double* q = stage.data();
+    double* qr_buf = q;
+    q += nss;
+    double* qr_rinv = q;
+    q += nss;
+    double* hG = q;
+    q += nG;
+    double* hG2 = q;
+    q += nG;
+    double* hY = q;
+    q += nG;
+    std::fill(hY, hY + nG, 0.0);
+    std::vector<std::vector<cplx>> Hk(ph, std::vector<cplx>((size_t)(ms + s) * ms));
+    std::vector<std::vector<cplx>> H0(ph, std::vector<cplx>((size_t)ss));
+    std::vector<std::vector<cplx>> Rq(ph, std::vector<cplx>((size_t)ss));
+
+    for (int cycle = 0;; ++cycle) {
+      // R0 = C - M(X0) (Algorithm 8 step 2)
+      if (cycle == 0 && !o.x0_given) {
+        TSYLV_HIP(hipMemcpyAsync(w.R, S.Zc, w.N * sizeof(double), hipMemcpyDeviceToDevice, st));
+      } else {
+        ProfScope ps(ctx, TSYLV_K_APPLY, st);
+        kern::apply_f64(S.Ah, S.Bh, S.Zx, w.R, S.Zc, -1.0, 1.0, n, s, (int)p, st, var64);
+      }
+      info.relres_true = std::sqrt(dev_norm2(ctx, w, w.R)) / cnorm;
+      if (info.relres_true <= o.tol) {
+        status = TSYLV_OK;
+        break;
+      }
+      if (cycle >= o.max_cycles) break;
+      info.cycles++;
+      // Algorithm 7 step 2: [V_1, H0] = Tubal-QR(R0)
+      if (!tubal_qr(ctx, w, w.R, w.V(0), H0, true, qr_buf, qr_rinv))
+        throw Error(TSYLV_EBREAKDOWN, "Tubal-QR(R0)");
+      for (auto& h : Hk) std::fill(h.begin(), h.end(), cplx(0.0));
+      for (int j = 0; j < m; ++j) {
+        const int64_t J = (int64_t)(j + 1) * s;
+        double* W = w.V(j + 1);
+        {
+          ProfScope ps(ctx, TSYLV_K_APPLY, st);
+          kern::apply_f64(S.Ah, nullptr, w.V(j), W, nullptr, 1.0, 0.0, n, s, (int)p, st,
+                          var64);  // A only
+        }
+        // block CGS2: H_{0..j, j} = V^H W (twice), W -= V H
+        const kern::PMat Vb{w.basis, ns, n, s, w.ldv};
+        if (ctx.prof.on(TSYLV_K_ORTHO)) ctx.prof.begin(TSYLV_K_ORTHO, st);
+        for (int pass = 0; pass < 2; ++pass) {
+          kern::zgemm(Vb, true, kern::dense_pmat(W, ns, n), w.G, J * s, J, J, s, n, 1.0, 0.0,
+                      (int)p, w.partial, st);
+          kern::zgemm(Vb, false, kern::dense_pmat(w.G, J * s, J), W, ns, n, n, s, J, -1.0, 1.0,
+                      (int)p, nullptr, st);
+          double* dst = pass == 0 ? hG : hG2;
+          TSYLV_HIP(hipMemcpyAsync(dst, w.G, (size_t)p * J * s * 8, hipMemcpyDeviceToHost, st));
+        }
+        if (ctx.prof.on(TSYLV_K_ORTHO)) ctx.prof.end(TSYLV_K_ORTHO, st);
+        ctx.sync();
+        const int Ji = (int)J;
         parallel_slices(ph, [&](int k) {
-          std::vector<cplx> Yk((size_t)msi * si);
-          host::matmul(&hz[(size_t)k * si * msi], Wik[k].data(), Yk.data(), msi, si, si);
+          std::vector<cplx> g1((size_t)Ji * si), g2((size_t)Ji * si);
+          unpack(hG, (int)p, k, Ji, si, g1.data());
+          unpack(hG2, (int)p, k, Ji, si, g2.data());
+          const int ldh = msi + si;
+          for (int c = 0; c < si; ++c)
+            for (int r = 0; r < Ji; ++r)
+              Hk[k][r + (size_t)ldh * (j * si + c)] = g1[r + (size_t)Ji * c] + g2[r + (size_t)Ji * c];
+        });
+        // Tubal-QR(W) -> V_{j+1}, H_{j+1,j}
+        const bool qr_ok = tubal_qr(ctx, w, W, W, Rq, false, qr_buf, qr_rinv);
+        if (!qr_ok) {
+          if (j < m - 1) throw Error(TSYLV_EBREAKDOWN, "Tubal-QR in TBA");
+          for (auto& r : Rq) std::fill(r.begin(), r.end(), cplx(0.0));  // H_{m+1,m} = 0
+        }
+        for (int k = 0; k < ph; ++k) {
+          const int ldh = msi + si;
+          for (int c = 0; c < si; ++c)
+            for (int r = 0; r < si; ++r)
+              Hk[k][(size_t)(J + r) + (size_t)ldh * (j * si + c)] = Rq[k][r + (size_t)si * c];
+        }
+        info.steps++;
+      }
+      // Algorithm 8 step 3(b): H_m Y - Y B = [H0; 0] per slice
+      std::vector<int> good(ph, 1);
+      double est2 = 0.0;
+      std::vector<double> est_k(ph, 0.0);
+      auto finish_slice = [&](int k, const std::vector<cplx>& Yk) {
+        const int ldh = msi + si;
+        pack(Yk.data(), (int)p, k, msi, si, hY);
+        // residual estimate: || H_{m+1,m} Y_m ||_F for this slice
+        double e = 0.0;
+        for (int c = 0; c < si; ++c)
+          for (int r = 0; r < si; ++r) {
+            cplx v = 0.0;
+            for (int l = 0; l < si; ++l)
+              v += Hk[k][(size_t)(msi + r) + (size_t)ldh * ((m - 1) * si + l)] *
+                   Yk[(size_t)((m - 1) * si + l) + (size_t)msi * c];
+            e += (k == 0 || 2 * k == (int)p) ? v.real() * v.real() : std::norm(v);
+          }
+        est_k[k] = e;
+      };
+      {
+        // host: Bartels-Stewart with the Schur form of Bhat_k (Algorithm 5)
+        parallel_slices(ph, [&](int k) {
+          const int ldh = msi + si;
+          std::vector<cplx> Hm((size_t)msi * msi), Bk((size_t)si * si), C1((size_t)msi * si, 0.0),
+              Yk((size_t)msi * si);
+          for (int c = 0; c < msi; ++c)
+            for (int r = 0; r < msi; ++r) Hm[r + (size_t)msi * c] = Hk[k][r + (size_t)ldh * c];
+          unpack(hB.data(), (int)p, k, si, si, Bk.data());
+          for (int c = 0; c < si; ++c)
+            for (int r = 0; r < si; ++r) C1[r + (size_t)msi * c] = H0[k][r + (size_t)si * c];
+          if (!host::sylvester_banded(Hm.data(), msi, si, Bk.data(), si, C1.data(), Yk.data())) {
+            good[k] = 0;
+            return;
+          }
           finish_slice(k, Yk);
         });
-        dev_done = true;
       }
+      for (int k = 0; k < ph; ++k) {
+        if (!good[k]) throw Error(TSYLV_ESINGULAR, "projected Sylvester equation");
+        est2 += est_k[k];
+      }
+      info.relres_est = std::sqrt(est2) / cnorm;
+      if (o.res_hist && info.res_hist_len < o.res_hist_cap)
+        o.res_hist[info.res_hist_len++] = info.relres_est;
+      // Algorithm 8 step 3(c): X = X0 + V_m Y
+      TSYLV_HIP(hipMemcpyAsync(w.Y, hY, nG * 8, hipMemcpyHostToDevice, st));
+      kern::zgemm(kern::PMat{w.basis, ns, n, s, w.ldv}, false, kern::dense_pmat(w.Y, ms * s, ms),
+                  S.Zx, ns, n, n, s, ms, 1.0, 1.0, (int)p, nullptr, st);
+      ctx.sync();
     }
-    if (!dev_done) {
-      // host: Bartels-Stewart with the Schur form of Bhat_k (Algorithm 5)
-      parallel_slices(ph, [&](int k) {
-        const int ldh = msi + si;
-        std::vector<cplx> Hm((size_t)msi * msi), Bk((size_t)si * si), C1((size_t)msi * si, 0.0),
-            Yk((size_t)msi * si);
-        for (int c = 0; c < msi; ++c)
-          for (int r = 0; r < msi; ++r) Hm[r + (size_t)msi * c] = Hk[k][r + (size_t)ldh * c];
-        unpack(hB.data(), (int)p, k, si, si, Bk.data());
-        for (int c = 0; c < si; ++c)
-          for (int r = 0; r < si; ++r) C1[r + (size_t)msi * c] = H0[k][r + (size_t)si * c];
-        if (!host::sylvester_banded(Hm.data(), msi, si, Bk.data(), si, C1.data(), Yk.data())) {
-          good[k] = 0;
-          return;
-        }
-        finish_slice(k, Yk);
-      });
-    }
-    for (int k = 0; k < ph; ++k) {
-      if (!good[k]) throw Error(TSYLV_ESINGULAR, "projected Sylvester equation");
-      est2 += est_k[k];
-    }
-    info.relres_est = std::sqrt(est2) / cnorm;
-    if (o.res_hist && info.res_hist_len < o.res_hist_cap)
-      o.res_hist[info.res_hist_len++] = info.relres_est;
-    // Algorithm 8 step 3(c): X = X0 + V_m Y
-    TSYLV_HIP(hipMemcpyAsync(w.Y, hY, nG * 8, hipMemcpyHostToDevice, st));
-    kern::zgemm(kern::PMat{w.basis, ns, n, s, w.ldv}, false, kern::dense_pmat(w.Y, ms * s, ms),
-                S.Zx, ns, n, n, s, ms, 1.0, 1.0, (int)p, nullptr, st);
-    ctx.sync();
   }
   {
     ProfScope ps(ctx, TSYLV_K_XFORM, st);

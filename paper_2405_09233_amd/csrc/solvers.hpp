@@ -43,6 +43,11 @@ int krylov_solve(Ctx& ctx, int method, int64_t n, int64_t s, int64_t p, const do
 
 // Batched lockstep tGMRES (batch.cpp): FP64, restart length o.m <= 63.
 size_t batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o);
+// Batched t-Bartels-Stewart (tbs_batch.cpp): 0 bytes when an instance is
+// outside 1 <= n, s <= 64, 1 <= p <= 4096 or has a null pointer.
+size_t tbs_batch_workspace_bytes(int count, const tsylv_problem* probs);
+int tbs_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts& o,
+              tsylv_info* infos);
 // On stream `st`; gens (may be null): gens[i] non-null draws instance i as
 // the synthetic instance of seed *gens[i] (its A, B, C are not read).
 int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,

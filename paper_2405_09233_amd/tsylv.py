@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtsylv.so")
 
 FP64, FP32, BF16 = 0, 1, 2
-GMRES, FOM, TBA, TBS, GMRES_BATCHED = 0, 1, 2, 3, 4
+GMRES, FOM, TBA, TBS, GMRES_BATCHED, AUTO = 0, 1, 2, 3, 4, 5
 APPLY = -1
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "EINVAL", -2: "ENOMEM",
@@ -91,6 +91,9 @@ _SIGS = {
                                                       ctypes.POINTER(Opts)]),
     "tsylv_gmres_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                          ctypes.POINTER(Opts), ctypes.c_void_p]),
+    "tsylv_tbs_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_void_p]),
+    "tsylv_tbs_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.POINTER(Opts), ctypes.c_void_p]),
     "tsylv_apply_variants": (ctypes.c_int, [ctypes.c_int]),
     "tsylv_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.c_int64, ctypes.c_int, ctypes.c_int,
@@ -316,6 +319,22 @@ class Context:
         if st < 0 and raise_on_error:
             raise TsylvError(st, "tsylv_gmres_batch")
         return list(infos)
+
+    def tbs_batch(self, items, tol=1e-8, raise_on_error=True):
+        """Batched t-Bartels-Stewart over `items`, a list of (A, B, C, X)
+        device tensors of small instances (n, s <= 64); X receives each
+        solution.  Returns the list of per-instance Info records."""
+        probs = self._problems(items)
+        o = default_opts(TBS, tol=tol)
+        infos = (Info * len(items))()
+        st = load().tsylv_tbs_batch(self.handle, len(items), probs, ctypes.byref(o), infos)
+        if st < 0 and raise_on_error:
+            raise TsylvError(st, "tsylv_tbs_batch")
+        return list(infos)
+
+    @staticmethod
+    def tbs_batch_workspace_bytes(items):
+        return load().tsylv_tbs_batch_workspace_bytes(len(items), Context._problems(items))
 
     @staticmethod
     def batch_workspace_bytes(items, opts=None, **kw):

@@ -111,3 +111,84 @@ def test_served_tbs_equals_synchronous():
                 time.sleep(0.001)
             assert st == 0, info.as_dict()
         assert np.array_equal(host(Xa), host(Xs))
+
+
+@pytest.mark.gpu
+def test_tbs_batch_mixed_sizes_match_oracle():
+    """tsylv_tbs_batch over 48 instances of uneven size (n, s in [1, 64], p
+    in [1, 8]) with one singular instance in the middle: every regular
+    instance within 1e-9 of the oracle's t-Bartels-Stewart solution, with a
+    true relative residual below 1e-11 and within 1e-12 of its own single
+    tsylv_tbs solve; the singular one is reported as TSYLV_ESINGULAR and
+    changes nothing for the others."""
+    say("tbs batch 48 mixed")
+    rng = np.random.default_rng(77)
+    c = ctx()
+    cases, items = [], []
+    for i in range(48):
+        if i == 20:
+            n, s, p = 6, 4, 3
+            A = np.zeros((n, n, p), order="F")
+            B = np.zeros((s, s, p), order="F")
+            A[:, :, 0] = 2.0 * np.eye(n) + np.triu(np.ones((n, n)), 1)
+            B[:, :, 0] = 2.0 * np.eye(s)
+            C = np.asfortranarray(np.ones((n, s, p)))
+        else:
+            n, s, p = int(rng.integers(1, 65)), int(rng.integers(1, 65)), int(rng.integers(1, 9))
+            if i == 0:
+                n, s, p = 1, 1, 1
+            A, B, C = workloads.dense_shifted(n, s, p, seed=900 + i)
+        cases.append((A, B, C))
+        items.append((dev(A), dev(B), dev(C), tsylv.empty_device(C.shape, "cuda:0")))
+    infos = c.tbs_batch(items, tol=1e-11, raise_on_error=False)
+    for i, ((A, B, C), it, info) in enumerate(zip(cases, items, infos)):
+        if i == 20:
+            assert info.status == -4, info.as_dict()
+            continue
+        assert info.status == 0, (i, A.shape, B.shape, info.as_dict())
+        assert info.relres_true <= 1e-11
+        X = host(it[3])
+        assert rel(X, tbs.t_bartels_stewart(A, B, C)) <= 1e-9, i
+        Xs, _ = c.tbs(it[0], it[1], it[2])
+        assert rel(X, host(Xs)) <= 1e-12, i
+
+
+@pytest.mark.gpu
+def test_tbs_batch_rejects_large_instances():
+    A, B, C = workloads.dense_shifted(65, 4, 2, seed=1)
+    items = [(dev(A), dev(B), dev(C), tsylv.empty_device(C.shape, "cuda:0"))]
+    with pytest.raises(tsylv.TsylvError):
+        ctx().tbs_batch(items)
+
+
+@pytest.mark.gpu
+def test_served_auto_routes_small_requests_to_the_direct_solve():
+    """Method AUTO in the serving loop: a small FP64 request is solved by
+    t-Bartels-Stewart (no Krylov steps, bitwise the synchronous tsylv_tbs),
+    a larger one by tGMRES."""
+    import torch
+    say("served AUTO routing")
+    c = ctx()
+    A, B, C = workloads.dense_shifted(24, 10, 4, seed=301)
+    Ad, Bd, Cd = dev(A), dev(B), dev(C)
+    Xs, _ = c.tbs(Ad, Bd, Cd)
+    Xa = torch.zeros_like(Cd)
+    A2, B2, C2 = workloads.dense_shifted(100, 8, 3, seed=302)
+    A2d, B2d, C2d = dev(A2), dev(B2), dev(C2)
+    Xb = torch.zeros_like(C2d)
+    ta = c.submit(Ad, Bd, Cd, Xa, method=tsylv.AUTO, tol=1e-10)
+    tb = c.submit(A2d, B2d, C2d, Xb, method=tsylv.AUTO, m=30, tol=1e-10)
+    out = {}
+    deadline = time.time() + 60.0
+    for t in (ta, tb):
+        while True:
+            st, info = c.poll(t)
+            if st != 2:
+                break
+            assert time.time() < deadline, "serving loop did not finish"
+            time.sleep(0.001)
+        assert st == 0, info.as_dict()
+        out[t] = info
+    assert out[ta].steps == 0 and np.array_equal(host(Xa), host(Xs))
+    assert out[tb].steps > 0
+    assert rel(host(Xb), tbs.t_bartels_stewart(A2, B2, C2)) <= 1e-8
