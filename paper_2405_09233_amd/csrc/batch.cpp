@@ -14,8 +14,9 @@
 //                                                Givens, stop test
 //   scale                                        V_{j+1} = W / ||W||
 //   advance                                      j += 1 (device counter)
-// Since j lives in device memory, the step is captured once as a HIP graph
-// and replayed m times per cycle; the host reads the instances' flags every
+// Since j lives in device memory, the step is recorded once as a HIP graph
+// (kernel nodes added directly, no stream capture) and replayed m times per
+// cycle; the host reads the instances' flags every
 // kCheckEvery steps to end a cycle early when no instance is stepping.  At
 // a cycle's end: y = R^{-1} g, X += V y, the true residual R = C - M(X), and
 // the restart test of Algorithm 3 -- again one launch each for the batch.
@@ -284,26 +285,23 @@ int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
     residual(G, kern::BM_RESID0, G.stream);
   }
 
-  // each group's step as a graph, captured on a private stream and replayed
-  // on the group's stream
+  // each group's step as a graph of kernel nodes, recorded (not captured
+  // from a stream: nothing another thread does meanwhile can invalidate it)
+  // and replayed on the group's stream
   if (use_graph) {
-    hipStream_t cap = nullptr;
-    TSYLV_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    struct CapStream {
-      hipStream_t s;
-      ~CapStream() { (void)hipStreamDestroy(s); }
-    } cap_guard{cap};
     for (auto& G : groups) {
       hipGraph_t graph = nullptr;
-      TSYLV_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      TSYLV_HIP(hipGraphCreate(&graph, 0));
+      GraphRecorder rec{graph, nullptr};
+      graph_recorder() = &rec;
       try {
-        step(G, cap);
+        step(G, G.stream);
       } catch (...) {
-        (void)hipStreamEndCapture(cap, &graph);
-        if (graph) (void)hipGraphDestroy(graph);
+        graph_recorder() = nullptr;
+        (void)hipGraphDestroy(graph);
         throw;
       }
-      TSYLV_HIP(hipStreamEndCapture(cap, &graph));
+      graph_recorder() = nullptr;
       const hipError_t e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       TSYLV_HIP(e);

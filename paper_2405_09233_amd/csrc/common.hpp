@@ -7,6 +7,8 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <tuple>
+#include <utility>
 
 #include "../../include/tsylv.h"
 
@@ -65,5 +67,47 @@ enum XformKind {
 };
 
 inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Kernel launches that can be recorded into a graph instead of enqueued.
+// While a GraphRecorder is installed on the calling thread, klaunch adds a
+// kernel node behind the previous one (the nodes form a chain, the order of
+// the launches) and enqueues nothing; otherwise it launches on `st`.  A
+// graph built this way involves no stream capture, so work that other
+// threads issue meanwhile (on the legacy default stream, say) cannot
+// invalidate it.
+struct GraphRecorder {
+  hipGraph_t graph = nullptr;
+  hipGraphNode_t last = nullptr;
+};
+GraphRecorder*& graph_recorder();  // the calling thread's recorder (or null)
+
+template <typename Tuple, size_t... I>
+inline void kparam_ptrs(Tuple& t, void** out, std::index_sequence<I...>) {
+  ((out[I] = static_cast<void*>(&std::get<I>(t))), ...);
+}
+
+template <typename... P, typename... A>
+inline void klaunch(void (*kernel)(P...), dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                    A&&... args) {
+  GraphRecorder* r = graph_recorder();
+  if (!r) {
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, std::forward<A>(args)...);
+    return;
+  }
+  std::tuple<P...> vals(std::forward<A>(args)...);
+  void* ptrs[sizeof...(P) + 1];
+  kparam_ptrs(vals, ptrs, std::index_sequence_for<P...>{});
+  hipKernelNodeParams np{};
+  np.func = reinterpret_cast<void*>(kernel);
+  np.gridDim = grid;
+  np.blockDim = block;
+  np.sharedMemBytes = (unsigned)lds;
+  np.kernelParams = ptrs;
+  np.extra = nullptr;
+  hipGraphNode_t node = nullptr;
+  TSYLV_HIP(hipGraphAddKernelNode(&node, r->graph, r->last ? &r->last : nullptr,
+                                  r->last ? 1 : 0, &np));
+  r->last = node;
+}
 
 }  // namespace tsylv

@@ -456,11 +456,11 @@ template <int TM, int TN, int RB, int CB, int TK = Mma<double>::TK>
 static void launch_batch(const BatchItem* items, const BatchApplyRef* refs, int nref, int total,
                          BatchState* st, const int* jp, int mode, hipStream_t s) {
   if (mode == BM_STEP)
-    hipLaunchKernelGGL((apply_batch_kernel<TM, TN, RB, CB, TK, BM_STEP>), dim3(total), dim3(NT), 0,
-                       s, items, refs, nref, total, st, jp);
+    klaunch(apply_batch_kernel<TM, TN, RB, CB, TK, BM_STEP>, dim3(total), dim3(NT), 0, s, items,
+            refs, nref, total, st, jp);
   else if (mode == BM_RESID)
-    hipLaunchKernelGGL((apply_batch_kernel<TM, TN, RB, CB, TK, BM_RESID>), dim3(total), dim3(NT),
-                       0, s, items, refs, nref, total, st, jp);
+    klaunch(apply_batch_kernel<TM, TN, RB, CB, TK, BM_RESID>, dim3(total), dim3(NT), 0, s, items,
+            refs, nref, total, st, jp);
   else
     throw Error(TSYLV_EINVAL, "batch apply: mode");
 }

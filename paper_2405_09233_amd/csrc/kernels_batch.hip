@@ -341,19 +341,19 @@ void batch_dots(const BatchItem* items, int count, int total_chunks, const Batch
   const dim3 g(total_chunks), b(kBT);
   switch (mode) {
     case BM_STEP:
-      hipLaunchKernelGGL(batch_dots_kernel<BM_STEP>, g, b, 0, s, items, count, st, jp, part, ldp);
+      klaunch(batch_dots_kernel<BM_STEP>, g, b, 0, s, items, count, st, jp, part, ldp);
       break;
     case BM_PASS2:
-      hipLaunchKernelGGL(batch_dots_kernel<BM_PASS2>, g, b, 0, s, items, count, st, jp, part, ldp);
+      klaunch(batch_dots_kernel<BM_PASS2>, g, b, 0, s, items, count, st, jp, part, ldp);
       break;
     case BM_WNORM:
-      hipLaunchKernelGGL(batch_dots_kernel<BM_WNORM>, g, b, 0, s, items, count, st, jp, part, ldp);
+      klaunch(batch_dots_kernel<BM_WNORM>, g, b, 0, s, items, count, st, jp, part, ldp);
       break;
     case BM_RESID:
-      hipLaunchKernelGGL(batch_dots_kernel<BM_RESID>, g, b, 0, s, items, count, st, jp, part, ldp);
+      klaunch(batch_dots_kernel<BM_RESID>, g, b, 0, s, items, count, st, jp, part, ldp);
       break;
     case BM_CNORM:
-      hipLaunchKernelGGL(batch_dots_kernel<BM_CNORM>, g, b, 0, s, items, count, st, jp, part, ldp);
+      klaunch(batch_dots_kernel<BM_CNORM>, g, b, 0, s, items, count, st, jp, part, ldp);
       break;
     default:
       throw Error(TSYLV_EINVAL, "batch_dots: mode");
@@ -369,7 +369,7 @@ void batch_reduce(const BatchItem* items, int count, BatchState* st, const int* 
   switch (mode) {
 #define TSYLV_REDUCE_CASE(M)                                                                  \
   case M:                                                                                     \
-    hipLaunchKernelGGL(batch_reduce_kernel<M>, g, b, 0, s, items, st, jp, part, ldp, m, tol, \
+    klaunch(batch_reduce_kernel<M>, g, b, 0, s, items, st, jp, part, ldp, m, tol, \
                        max_cycles);                                                           \
     break;
     TSYLV_REDUCE_CASE(BM_STEP)
@@ -390,11 +390,11 @@ void batch_update(const BatchItem* items, int count, int total_chunks, const Bat
   if (total_chunks <= 0) return;
   const dim3 g(total_chunks), b(kBT);
   if (mode == BM_STEP)
-    hipLaunchKernelGGL(batch_update_kernel<BM_STEP>, g, b, 0, s, items, count, st, jp);
+    klaunch(batch_update_kernel<BM_STEP>, g, b, 0, s, items, count, st, jp);
   else if (mode == BM_PASS2)
-    hipLaunchKernelGGL(batch_update_kernel<BM_PASS2>, g, b, 0, s, items, count, st, jp);
+    klaunch(batch_update_kernel<BM_PASS2>, g, b, 0, s, items, count, st, jp);
   else if (mode == BM_XUPDATE)
-    hipLaunchKernelGGL(batch_update_kernel<BM_XUPDATE>, g, b, 0, s, items, count, st, jp);
+    klaunch(batch_update_kernel<BM_XUPDATE>, g, b, 0, s, items, count, st, jp);
   else
     throw Error(TSYLV_EINVAL, "batch_update: mode");
   TSYLV_LAUNCH_CHECK();
@@ -405,9 +405,9 @@ void batch_scale(const BatchItem* items, int count, int total_chunks, const Batc
   if (total_chunks <= 0) return;
   const dim3 g(total_chunks), b(kBT);
   if (mode == BM_STEP)
-    hipLaunchKernelGGL(batch_scale_kernel<BM_STEP>, g, b, 0, s, items, count, st, jp);
+    klaunch(batch_scale_kernel<BM_STEP>, g, b, 0, s, items, count, st, jp);
   else if (mode == BM_RESID)
-    hipLaunchKernelGGL(batch_scale_kernel<BM_RESID>, g, b, 0, s, items, count, st, jp);
+    klaunch(batch_scale_kernel<BM_RESID>, g, b, 0, s, items, count, st, jp);
   else
     throw Error(TSYLV_EINVAL, "batch_scale: mode");
   TSYLV_LAUNCH_CHECK();
@@ -416,17 +416,17 @@ void batch_scale(const BatchItem* items, int count, int total_chunks, const Batc
 void batch_backsub(const BatchItem* items, int count, const BatchState* st, int m,
                    hipStream_t s) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(batch_backsub_kernel, dim3(count), dim3(64), 0, s, items, st, m);
+  klaunch(batch_backsub_kernel, dim3(count), dim3(64), 0, s, items, st, m);
   TSYLV_LAUNCH_CHECK();
 }
 
 void batch_set_j(int* jp, int value, hipStream_t s) {
-  hipLaunchKernelGGL(batch_set_j_kernel, dim3(1), dim3(64), 0, s, jp, value);
+  klaunch(batch_set_j_kernel, dim3(1), dim3(64), 0, s, jp, value);
   TSYLV_LAUNCH_CHECK();
 }
 
 void batch_advance(int* jp, hipStream_t s) {
-  hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(64), 0, s, jp);
+  klaunch(batch_advance_kernel, dim3(1), dim3(64), 0, s, jp);
   TSYLV_LAUNCH_CHECK();
 }
 

@@ -2,6 +2,11 @@
 
 namespace tsylv {
 
+GraphRecorder*& graph_recorder() {
+  static thread_local GraphRecorder* r = nullptr;
+  return r;
+}
+
 void Arena::init(char* base, size_t bytes) {
   std::lock_guard<std::mutex> g(mu_);
   base_ = base;

@@ -23,12 +23,14 @@
 // Requests of method GMRES_BATCHED that wait at the head of the queue with
 // equal options are admitted together, up to kMaxBatch of them and as many as
 // the arena holds, as one lockstep batch (batch.cpp) that takes one slot and
-// runs on a worker thread on the slot's stream, its steps launched eagerly
-// (a graph capture on the worker would make the caller's concurrent work on
-// the legacy default stream fail); the scheduler posts every result of the
-// batch when the worker ends.  An instance's result in a batch is bitwise its
-// batch-of-one result (graph or eager: the same kernels).
+// runs on a worker thread on the slot's stream, its step replayed from a
+// graph of kernel nodes recorded on the worker (no stream capture, so the
+// caller's concurrent work on the legacy default stream cannot interfere);
+// the scheduler posts every result of the batch when the worker ends.  An
+// instance's result in a batch is bitwise its batch-of-one result (graph or
+// eager: the same kernels).
 #include <atomic>
+#include <cstdlib>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -246,10 +248,10 @@ struct Scheduler {
         TSYLV_HIP(hipSetDevice(ctx.device));
         for (hipEvent_t e : jp->ready)
           if (e) TSYLV_HIP(hipStreamWaitEvent(st, e, 0));
-        // launched eagerly: a graph capture on this worker thread would make
-        // the caller's concurrent work on the legacy default stream fail
+        // the step replayed from a recorded graph (TSYLV_BATCH_GRAPH=0: eager)
+        const char* g = std::getenv("TSYLV_BATCH_GRAPH");
         gmres_batch(ctx, st, (int)jp->probs.size(), jp->probs.data(), jp->gens.data(), o,
-                    jp->infos.data(), false);
+                    jp->infos.data(), !(g && g[0] == '0'));
       } catch (const Error& e) {
         jp->error = e.status;
       } catch (...) {

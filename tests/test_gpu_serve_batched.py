@@ -166,3 +166,44 @@ def test_batched_malformed_and_close_in_flight():
     t0 = time.time()
     c.close()  # finishes admitted batches, cancels the queued requests
     assert time.time() - t0 < 60
+
+
+@pytest.mark.gpu
+def test_served_batches_replay_recorded_graphs_while_the_caller_works(monkeypatch):
+    """Served lockstep batches replay their step from a recorded HIP graph
+    while the calling thread keeps the legacy default stream busy with its
+    own kernels and synchronisations (the case that a stream capture on the
+    worker could not survive): every result is bitwise the same as with the
+    steps launched eagerly (TSYLV_BATCH_GRAPH=0), over several batches."""
+    import torch
+    say("serve batched: graph vs eager with caller work on the default stream")
+    reqs = make(16, 1300)
+    opts = tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-11, max_cycles=100)
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("TSYLV_BATCH_GRAPH", mode)
+        c = tsylv.Context(2 << 30, device=0)
+        try:
+            batched, tickets, _ = submit_all(c, reqs, opts)
+            busy = torch.full((2048, 2048), 1e-4, dtype=torch.float32, device="cuda:0")
+            pending = set(tickets)
+            res = {}
+            t0 = time.time()
+            while pending:
+                busy = busy @ busy  # the caller's own work on its stream
+                torch.cuda.synchronize()
+                for t in list(pending):
+                    st, info = c.poll(t)
+                    if st != 2:
+                        res[t] = (st, info)
+                        pending.discard(t)
+                assert time.time() - t0 < 120, "serving loop did not finish"
+            for t in tickets:
+                assert res[t][0] == 0, res[t][1].as_dict()
+            out[mode] = [host(b[3]) for b in batched]
+        finally:
+            c.close()
+    for a, b in zip(out["1"], out["0"]):
+        assert np.array_equal(a, b)
+    n, s, p, (A, B, C) = reqs[0]
+    assert rel(out["1"][0], kron.kron_solve(A, B, C)) <= 1e-8
