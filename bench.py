@@ -375,7 +375,7 @@ def _served_generated(tsylv, ctx, o, sizes, ids, arrivals=None):
     failures, span in s)."""
     t0 = time.perf_counter()
     pending = {}  # ticket -> (X, arrival)
-    lat, bad, i = [], 0, 0
+    lat, svc, bad, i = [], [], 0, 0
     while i < len(sizes) or pending:
         now = time.perf_counter() - t0
         while i < len(sizes) and (arrivals is None or arrivals[i] <= now):
@@ -389,13 +389,14 @@ def _served_generated(tsylv, ctx, o, sizes, ids, arrivals=None):
             if st != 2:
                 _, ta = pending.pop(t)
                 lat.append(time.perf_counter() - t0 - ta)
+                svc.append(info.seconds)  # from admission to completion
                 if st != 0 or info.relres_true > 1e-8:
                     bad += 1
         time.sleep(0.0002)
-    return np.array(lat), bad, time.perf_counter() - t0
+    return np.array(lat), bad, time.perf_counter() - t0, np.array(svc)
 
 
-def serving_full(tsylv, rate=40.0, duration=10.0, nbatch=128, seed=50):
+def serving_full(tsylv, rate=40.0, duration=10.0, nbatch=128, seed=50, names=None):
     """Serving at the recipe's full sizes: n log-uniform in [128, 4096], s
     log-uniform in [8, 256], p uniform in {4..64}; every request carries only
     a seed (its id) and draws its dense p-scaled-noise instance on the device
@@ -426,10 +427,13 @@ def serving_full(tsylv, rate=40.0, duration=10.0, nbatch=128, seed=50):
                      "Poisson arrivals %.0f/s for %.0f s (%d requests)" %
                      (mean_a / 1e9, nbatch, rate, duration, len(arrivals))}
     for name, o in opts.items():
+        if names and name not in names:
+            continue
         ctx = tsylv.Context(200 << 30, device=0)
-        done, bad_b, span_b = _served_generated(tsylv, ctx, o, batch, np.arange(nbatch))
-        lat, bad, span = _served_generated(tsylv, ctx, o, stream,
-                                           nbatch + np.arange(len(stream)), arrivals)
+        done, bad_b, span_b, _ = _served_generated(tsylv, ctx, o, batch, np.arange(nbatch))
+        lat, bad, span, service = _served_generated(tsylv, ctx, o, stream,
+                                                    nbatch + np.arange(len(stream)), arrivals)
+        queue = np.maximum(lat - service, 0.0)
         ctx.close()
         out[name] = {"batch_solves_per_s": float(nbatch / span_b), "batch_failed": int(bad_b),
                      "batch_completion_s": {"p50": float(np.percentile(done, 50)),
@@ -438,15 +442,23 @@ def serving_full(tsylv, rate=40.0, duration=10.0, nbatch=128, seed=50):
                      "throughput_per_s": float(len(lat) / span),
                      "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                                     "p99": float(np.percentile(lat, 99) * 1e3),
-                                    "mean": float(lat.mean() * 1e3)}}
+                                    "mean": float(lat.mean() * 1e3)},
+                     # latency = queueing delay (arrival to admission) + service
+                     # (admission to completion, the request's own solve)
+                     "queue_ms": {"p50": float(np.percentile(queue, 50) * 1e3),
+                                  "p99": float(np.percentile(queue, 99) * 1e3)},
+                     "service_ms": {"p50": float(np.percentile(service, 50) * 1e3),
+                                    "p99": float(np.percentile(service, 99) * 1e3)}}
         log("serving (full sizes) %s: batch of %d: %.1f solves/s; Poisson %.0f/s: %d requests, "
             "p50 %.1f ms, p99 %.1f ms; failed %d + %d" % (
                 name, nbatch, nbatch / span_b, rate, len(lat), out[name]["latency_ms"]["p50"],
                 out[name]["latency_ms"]["p99"], bad_b, bad))
-    out["bf16_vs_fp64_batch"] = (out["bf16"]["batch_solves_per_s"]
-                                 / max(out["fp64"]["batch_solves_per_s"], 1e-30))
-    out["fp32_vs_fp64_batch"] = (out["fp32"]["batch_solves_per_s"]
-                                 / max(out["fp64"]["batch_solves_per_s"], 1e-30))
+    if "fp64" in out and "bf16" in out:
+        out["bf16_vs_fp64_batch"] = (out["bf16"]["batch_solves_per_s"]
+                                     / max(out["fp64"]["batch_solves_per_s"], 1e-30))
+    if "fp64" in out and "fp32" in out:
+        out["fp32_vs_fp64_batch"] = (out["fp32"]["batch_solves_per_s"]
+                                     / max(out["fp64"]["batch_solves_per_s"], 1e-30))
     return out
 
 
@@ -810,6 +822,15 @@ def main():
                     help="skip the batch at the full serving sizes")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving measurements")
+    ap.add_argument("--serve-full-rate", type=float, default=40.0,
+                    help="Poisson arrival rate of the full-size serving run (requests/s)")
+    ap.add_argument("--serve-full-seconds", type=float, default=10.0,
+                    help="length of the full-size serving run (s)")
+    ap.add_argument("--serve-full-paths", default="",
+                    help="precisions of the full-size serving run (comma list of fp64, bf16, "
+                         "fp32; default all)")
+    ap.add_argument("--no-small-serve", action="store_true",
+                    help="with --serve-only: skip the small-size serving runs")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times "
                          "(reference kernel for the HBM byte counters)")
@@ -839,10 +860,14 @@ def main():
                                       "small": batched(tsylv, "small", 256)}}), flush=True)
         return
 
+    full_names = [x for x in args.serve_full_paths.split(",") if x] or None
     if args.serve_only:
-        out = {"serving": serving(tsylv, workloads, args.serve_rate, args.serve_seconds)}
+        out = {"serving": {} if args.no_small_serve else
+               serving(tsylv, workloads, args.serve_rate, args.serve_seconds)}
         if not args.no_serve_full:
-            out["serving"]["full_sizes"] = serving_full(tsylv)
+            out["serving"]["full_sizes"] = serving_full(tsylv, args.serve_full_rate,
+                                                        args.serve_full_seconds,
+                                                        names=full_names)
         print(json.dumps(out), flush=True)
         return
 
@@ -927,7 +952,9 @@ def main():
                               "small": batched(tsylv, "small", 256)}
         if not args.no_serve_full:
             log("serving at full sizes ...")
-            out["serving"]["full_sizes"] = serving_full(tsylv)
+            out["serving"]["full_sizes"] = serving_full(tsylv, args.serve_full_rate,
+                                                        args.serve_full_seconds,
+                                                        names=full_names)
     print(json.dumps(out), flush=True)
 
 
