@@ -204,6 +204,27 @@ __global__ void f64_to_bf16_kernel(const double* __restrict__ in, uint16_t* __re
     out[i] = f64_to_bf16_bits(in[i]);
 }
 
+// Pseudo-random operands for timing (the autotuner): value i is a uniform
+// number in [-1, 1) from the splitmix64 finaliser of seed + i, stored as
+// FP64, FP32 or BF16 (elem = 8, 4, 2 bytes).
+__global__ void fill_random_kernel(void* __restrict__ buf, int64_t count, int elem,
+                                   uint64_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    if (elem == 8)
+      static_cast<double*>(buf)[i] = u;
+    else if (elem == 4)
+      static_cast<float*>(buf)[i] = (float)u;
+    else
+      static_cast<uint16_t*>(buf)[i] = f64_to_bf16_bits(u);
+  }
+}
+
 // ------------------------------------------------------------ multi-vector
 
 constexpr int kChunk = 4096;  // elements per mdot chunk
@@ -973,6 +994,13 @@ void convert_f32_f64(const float* in, double* out, int64_t count, hipStream_t st
 void convert_f64_bf16(const double* in, uint16_t* out, int64_t count, hipStream_t st) {
   hipLaunchKernelGGL(f64_to_bf16_kernel, dim3(stream_grid(count)), dim3(kBlock), 0, st, in, out,
                      count);
+  TSYLV_LAUNCH_CHECK();
+}
+
+void fill_random(void* buf, int64_t count, int elem, uint64_t seed, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(fill_random_kernel, dim3(stream_grid(count)), dim3(kBlock), 0, st, buf,
+                     count, elem, seed);
   TSYLV_LAUNCH_CHECK();
 }
 
