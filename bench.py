@@ -478,71 +478,85 @@ def batched_shapes(kind, count, seed):
     return shapes
 
 
-def batched(tsylv, kind="large", count=64, m=30, seed=40):
+def batched(tsylv, kind="large", count=256, m=30, seed=40, precs=("fp64", "fp32")):
     """A batched workload: `count` independent instances of the sizes of
     batched_shapes(kind), instance i the dense p-scaled-noise instance of
-    Philox seed 4000 + i drawn on the device (tsylv_generate); FP64
-    tGMRES(m) to 1e-8.  Timed three ways on the same instances: the batched
-    lockstep solve (one launch per step stage for all), the serving loop (all
-    submitted at once, up to 8 overlapping solves), and one synchronous solve
-    after another."""
+    Philox seed 4000 + i drawn on the device (tsylv_generate); tGMRES(m) to
+    1e-8, in FP64 and as FP64 refinement around FP32 inner tGMRES(m) cycles.
+    Timed three ways on the same instances per precision: tsylv_gmres_batch
+    (small FP64 instances in lockstep, the rest as concurrent solves on eight
+    streams), the serving loop (all submitted at once, up to 8 overlapping
+    solves), and one synchronous solve after another."""
     import torch
     shapes = batched_shapes(kind, count, seed)
-    opts = tsylv.default_opts(tsylv.GMRES, m=m, tol=1e-8, max_cycles=500)
     ctx0 = tsylv.Context(64 << 20, device=0)
     items = []
     for k, (n, s, p) in enumerate(shapes):
         A, B, C = ctx0.generate(4000 + k, n, s, p)
         items.append((A, B, C, torch.zeros_like(C)))
     ctx0.close()
-    need = tsylv.Context.batch_workspace_bytes(items, opts=opts)
-    ctx = tsylv.Context(need + (256 << 20), device=0)
     sizes = {"large": "n = 32 round(U[256, 2048] / 32), s U{16..128}, p {8, 16, 32}",
              "small": "n U{32..256}, s U{2..16}, p U{2..8}"}[kind]
     out = {"workload": "%d instances, %s (rng seed %d), dense p-scaled-noise instances drawn "
-                       "on the device (Philox seeds 4000 + i), FP64 tGMRES(%d) to 1e-8; A %.2f GB "
+                       "on the device (Philox seeds 4000 + i), tGMRES(%d) to 1e-8; A %.2f GB "
                        "in total" % (count, sizes, seed, m,
-                                     sum(n * n * p * 8 for n, s, p in shapes) / 1e9)}
-    # warm-up on two instances (code objects, graph path)
-    ctx.gmres_batch(items[:2], opts=opts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = ctx.gmres_batch(items, opts=opts, raise_on_error=False)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    okb = all(i.status == 0 and i.relres_true <= 1e-8 for i in infos)
-    out["batched"] = {"solves_per_s": count / tb, "seconds": tb, "valid": bool(okb),
-                      "steps_total": int(sum(i.steps for i in infos))}
-    log("batched %s: lockstep batch %.3f s (%.1f solves/s, valid %s)"
-        % (kind, tb, count / tb, okb))
-    ctx.close()
-    ctx = tsylv.Context(max(tsylv.workspace_bytes(tsylv.GMRES, n, s, p, opts)
-                            for n, s, p in shapes) * 8 + (256 << 20), device=0)
-    t0 = time.perf_counter()
-    tickets = [ctx.submit(A, B, C, X, method=tsylv.GMRES, opts=opts) for A, B, C, X in items]
-    oks = True
-    for t in tickets:
-        while True:
-            st, info = ctx.poll(t)
-            if st != 2:
-                break
-            time.sleep(0.0002)
-        oks = oks and st == 0 and info.relres_true <= 1e-8
-    ts = time.perf_counter() - t0
-    out["serving_loop"] = {"solves_per_s": count / ts, "seconds": ts, "valid": bool(oks)}
-    log("batched %s: serving loop %.3f s (%.1f solves/s)" % (kind, ts, count / ts))
-    t0 = time.perf_counter()
-    okq = True
-    for A, B, C, X in items:
-        _, info = ctx.gmres(A, B, C, X=X, opts=opts)
-        okq = okq and info.status == 0 and info.relres_true <= 1e-8
-    torch.cuda.synchronize()
-    tq = time.perf_counter() - t0
-    ctx.close()
-    out["sequential"] = {"solves_per_s": count / tq, "seconds": tq, "valid": bool(okq)}
-    log("batched %s: one after another %.3f s (%.1f solves/s)" % (kind, tq, count / tq))
-    out["batched_vs_sequential"] = tq / tb
-    out["batched_vs_serving"] = ts / tb
+                                     sum(n * n * p * 8 for n, s, p in shapes) / 1e9),
+           "lockstep_instances": int(sum(1 for n, s, p in shapes if n * s * p <= (1 << 18)))}
+    all_opts = {"fp64": tsylv.default_opts(tsylv.GMRES, m=m, tol=1e-8, max_cycles=500),
+                "fp32": tsylv.default_opts(tsylv.GMRES, m=m, refine=1, prec=tsylv.FP32,
+                                           inner_m=m, inner_tol=1e-4, tol=1e-8,
+                                           max_outer=500)}
+    for name in precs:
+        opts = all_opts[name]
+        res = {}
+        need = tsylv.Context.batch_workspace_bytes(items, opts=opts)
+        ctx = tsylv.Context(need + (256 << 20), device=0)
+        # warm-up on two instances (code objects, graph path)
+        ctx.gmres_batch(items[:2], opts=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = ctx.gmres_batch(items, opts=opts, raise_on_error=False)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        okb = all(i.status == 0 and i.relres_true <= 1e-8 for i in infos)
+        res["batched"] = {"solves_per_s": count / tb, "seconds": tb, "valid": bool(okb),
+                          "steps_total": int(sum(i.steps for i in infos))}
+        log("batched %s %s: tsylv_gmres_batch %.3f s (%.1f solves/s, valid %s)"
+            % (kind, name, tb, count / tb, okb))
+        ctx.close()
+        ctx = tsylv.Context(max(tsylv.workspace_bytes(tsylv.GMRES, n, s, p, opts)
+                                for n, s, p in shapes) * 8 + (256 << 20), device=0)
+        t0 = time.perf_counter()
+        tickets = [ctx.submit(A, B, C, X, method=tsylv.GMRES, opts=opts)
+                   for A, B, C, X in items]
+        oks = True
+        for t in tickets:
+            while True:
+                st, info = ctx.poll(t)
+                if st != 2:
+                    break
+                time.sleep(0.0002)
+            oks = oks and st == 0 and info.relres_true <= 1e-8
+        ts = time.perf_counter() - t0
+        res["serving_loop"] = {"solves_per_s": count / ts, "seconds": ts, "valid": bool(oks)}
+        log("batched %s %s: serving loop %.3f s (%.1f solves/s)" % (kind, name, ts, count / ts))
+        t0 = time.perf_counter()
+        okq = True
+        for A, B, C, X in items:
+            _, info = ctx.gmres(A, B, C, X=X, opts=opts)
+            okq = okq and info.status == 0 and info.relres_true <= 1e-8
+        torch.cuda.synchronize()
+        tq = time.perf_counter() - t0
+        ctx.close()
+        res["sequential"] = {"solves_per_s": count / tq, "seconds": tq, "valid": bool(okq)}
+        log("batched %s %s: one after another %.3f s (%.1f solves/s)"
+            % (kind, name, tq, count / tq))
+        res["batched_vs_sequential"] = tq / tb
+        res["batched_vs_serving"] = ts / tb
+        out[name] = res
+    if "fp64" in out and "fp32" in out:
+        out["fp32_vs_fp64_batched"] = (out["fp32"]["batched"]["solves_per_s"]
+                                       / out["fp64"]["batched"]["solves_per_s"])
     return out
 
 
@@ -688,7 +702,7 @@ def run_path(ctx, tsylv, dev_in, opts, steps, warmup, name):
     }, X_final
 
 
-def roofline_of(name, r, n, s, p, bf16_tiled):
+def roofline_of(name, r, n, s, p, bf16_tiled, variant=None):
     """Roofline object of a path's dominant kernel: the method's algorithmic
     work per apply call divided by the live-timed average call."""
     elem = {"fp64": (8, 8), "tba": (8, 8), "mixed": (4, 4),
@@ -706,6 +720,13 @@ def roofline_of(name, r, n, s, p, bf16_tiled):
                "frac": ach / peak}
     kname = KERNEL_NAMES[name] if (name != "bf16" or bf16_tiled) else KERNEL_NAMES[
         "bf16_fp32basis"]
+    if name.startswith("bf16"):
+        # BF16 variants 0-3 are the 16 x 16 x 32 kernel's tiles, 4 and up the
+        # 32 x 32 x 16 wide kernel's (the library's default for s > 64)
+        wide = (s > 64) if variant is None else (variant >= 4)
+        if wide:
+            kname = kname.replace("apply_bf16_wg_kernel", "apply_bf16_w32_kernel")
+        out["variant"] = variant
     out.update({"traffic": measured_traffic(name, (n, s, p)) if bf16_tiled or name != "bf16"
                 else None,
                 "kernel": kname, "avg_launch_ms": r["apply_avg_ms"],
@@ -856,8 +877,9 @@ def main():
         del src, dst
 
     if args.batched_only:
-        print(json.dumps({"batched": {"large": batched(tsylv, "large", 64),
-                                      "small": batched(tsylv, "small", 256)}}), flush=True)
+        print(json.dumps({"batched": {"large": batched(tsylv, "large", 256),
+                                      "small": batched(tsylv, "small", 256,
+                                                       precs=("fp64",))}}), flush=True)
         return
 
     full_names = [x for x in args.serve_full_paths.split(",") if x] or None
@@ -881,7 +903,8 @@ def main():
     bname = best or next(k for k, v in res.items() if "valid" in v)
     bf16_tiled = bname == "bf16" and os.environ.get("TSYLV_BF16_BASIS") != "fp32" and \
         cfg["inner"]["bf16"] + 1 <= 64
-    roofline = roofline_of(bname, r, n, s, p, bf16_tiled)
+    roofline = roofline_of(bname, r, n, s, p, bf16_tiled,
+                           tuned.get("bf16", {}).get("best") if bname.startswith("bf16") else None)
     nx, ny = cfg["grid"]
     fp = res.get("fp64")
     out = {
@@ -935,7 +958,9 @@ def main():
         if obest:
             entry["roofline"] = roofline_of(obest, ores[obest], on, os_, op_,
                                             obest == "bf16" and CONFIGS[other]["inner"]["bf16"]
-                                            + 1 <= 64)
+                                            + 1 <= 64,
+                                            otuned.get("bf16", {}).get("best")
+                                            if obest.startswith("bf16") else None)
         if not args.no_cpu and ofp:
             entry["cpu_fft_baseline"] = cpu_fft_baseline(oA, oB, oC, ofp["applies_per_solve"],
                                                          (CONFIGS[other]["m"] + 1) / 2.0)
@@ -948,8 +973,8 @@ def main():
         out["serving"] = serving(tsylv, workloads, args.serve_rate, args.serve_seconds)
         if not args.no_batched:
             log("batched workload ...")
-            out["batched"] = {"large": batched(tsylv, "large", 64),
-                              "small": batched(tsylv, "small", 256)}
+            out["batched"] = {"large": batched(tsylv, "large", 256),
+                              "small": batched(tsylv, "small", 256, precs=("fp64",))}
         if not args.no_serve_full:
             log("serving at full sizes ...")
             out["serving"]["full_sizes"] = serving_full(tsylv, args.serve_full_rate,

@@ -184,20 +184,27 @@ int tsylv_tbs(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A,
 
 /* Batched solves (a project addition for workloads of many independent
  * instances of uneven size; the method per instance is Algorithm 3 --
- * restarted tGMRES(m) -- with the Arnoldi process of Algorithm 2 done as
- * classical Gram-Schmidt applied twice and the Givens update of section
- * 3.3).  All instances advance in lockstep: every kernel launch of an
- * Arnoldi step serves the whole batch (work items over the instances'
- * tiles and vector chunks), the Givens rotations and the stop tests run on
- * the device, and one step is captured as a HIP graph and replayed, so the
- * host synchronises a few times per cycle rather than per instance and
- * step.  Instances stop individually (their work items turn idle).
- * opts: FP64 only (refine = 0), 1 <= m <= 63; tol, max_cycles and x0_given
+ * restarted tGMRES(m) -- optionally inside FP64 iterative refinement as in
+ * tsylv_gmres).  Each instance runs on the executor that suits it, chosen
+ * from the instance alone:
+ *   - small FP64 instances (n s p <= 2^18) advance in lockstep: every kernel
+ *     launch of an Arnoldi step serves all of them (work items over the
+ *     instances' tiles and vector chunks; classical Gram-Schmidt applied
+ *     twice), the Givens rotations and the stop tests run on the device,
+ *     and the step is recorded once as a HIP graph and replayed, so the host
+ *     synchronises a few times per cycle rather than per instance and step;
+ *   - larger instances, and every instance of a refined batch (refine = 1,
+ *     prec FP32 or BF16), run as independent solves on up to eight streams
+ *     at once, each advanced as its stream finishes a phase, so that the
+ *     apply of one overlaps the Gram-Schmidt sweeps of another; each such
+ *     result is bitwise the synchronous tsylv_gmres solve with these opts.
+ * opts: 1 <= m <= 63; tol, max_cycles, x0_given and the refinement options
  * as for tsylv_gmres (opts may be NULL: m = 30).  Each instance's result
  * does not depend on the rest of the batch (it is bitwise the same alone).
  * infos[i] receives instance i's record (seconds: the whole batch).
  * Returns TSYLV_OK when every instance converged, TSYLV_NOT_CONVERGED when
- * some did not (see infos), or an error for the batch. */
+ * some did not or failed (see infos), or an error for the batch.
+ * tsylv_batch_workspace_bytes: the arena bytes the call needs. */
 typedef struct {
   int64_t n, s, p;
   const double* A;  /* device pointers, layout as above */

@@ -139,6 +139,7 @@ int tsylv_destroy(tsylv_ctx* ctx) {
     }
     (void)hipStreamSynchronize(ctx->c.stream);
     if (ctx->c.pinned) (void)hipHostFree(ctx->c.pinned);
+    if (ctx->c.task_pinned) (void)hipHostFree(ctx->c.task_pinned);
     if (ctx->c.owns_arena) (void)hipFree(ctx->c.arena_ptr);
     delete ctx;
     return (int)TSYLV_OK;
@@ -239,7 +240,8 @@ int tsylv_tba(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A, 
 
 static bool batch_ok(int count, const tsylv_problem* probs, const tsylv_opts& o) {
   if (count < 1 || count > 65536 || !probs) return false;
-  if (o.refine || o.m < 1 || o.m > kern::kBatchMaxM || !opts_ok(o) || o.res_hist) return false;
+  if (o.m < 1 || o.m > kern::kBatchMaxM || !opts_ok(o) || o.res_hist || o.x0_given > 1)
+    return false;
   int64_t chunks = 0;
   for (int i = 0; i < count; ++i) {
     const tsylv_problem& q = probs[i];

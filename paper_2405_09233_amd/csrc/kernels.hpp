@@ -32,6 +32,10 @@ void gen_tensor_f64(const GenTensor& g, double* out, int64_t E, int p, hipStream
 void tube_xform_gen_f64(const GenTensor& g, double* out, const double* M, int64_t E, int p,
                         hipStream_t st);
 
+// `count` pseudo-random values uniform in [-1, 1) (splitmix64 of seed + i),
+// stored with `elem` bytes each (8: FP64, 4: FP32, 2: BF16); timing operands.
+void fill_random(void* buf, int64_t count, int elem, uint64_t seed, hipStream_t st);
+
 // Down-conversion of `count` doubles (round to nearest even).
 void convert_f64_f32(const double* in, float* out, int64_t count, hipStream_t st);
 void convert_f64_bf16(const double* in, uint16_t* out, int64_t count, hipStream_t st);

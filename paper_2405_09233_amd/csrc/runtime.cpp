@@ -79,6 +79,19 @@ Workspace::Workspace(Arena& arena, size_t bytes) : arena_(arena), bytes_(bytes) 
 
 Workspace::~Workspace() { arena_.free(base_); }
 
+double* Ctx::task_buffer(size_t count) {
+  if (count > task_pinned_count) {
+    if (task_pinned) TSYLV_HIP(hipHostFree(task_pinned));
+    task_pinned = nullptr;
+    task_pinned_count = 0;
+    void* h = nullptr;
+    TSYLV_HIP(hipHostMalloc(&h, count * sizeof(double), hipHostMallocDefault));
+    task_pinned = static_cast<double*>(h);
+    task_pinned_count = count;
+  }
+  return task_pinned;
+}
+
 double* Ctx::host_buffer(size_t count) {
   if (count > pinned_count)
     throw Error(TSYLV_EINVAL, "host staging buffer too small (restart length too large)");

@@ -139,7 +139,13 @@ struct Ctx {
   Profiler prof;
   TuneTable tune;
 
+  // pinned host staging of the batch's stream executor (created on first
+  // use, kept until the context is destroyed)
+  double* task_pinned = nullptr;
+  size_t task_pinned_count = 0;
+
   double* host_buffer(size_t count);  // grows the pinned buffer as needed
+  double* task_buffer(size_t count);
   void sync() { TSYLV_HIP(hipStreamSynchronize(stream)); }
 };
 

@@ -12,6 +12,11 @@
   {8, 16, 32}) with restarts: both to 1e-11, solutions within 1e-8.
 * Per-instance stopping: instances that cannot converge in the cycles given
   report TSYLV_NOT_CONVERGED while the others converge; X0 is honoured.
+* The executor by instance: small FP64 instances take the lockstep
+  kernels, large ones and every refined solve (FP32 / BF16 inner cycles)
+  the stream executor; a large instance's result is bitwise the synchronous
+  tsylv_gmres solve, a refined batch's results are bitwise the refined
+  single solves and match the oracle.
 * Malformed batches are rejected.
 """
 
@@ -129,6 +134,51 @@ def test_malformed_batches_are_rejected():
     with pytest.raises(tsylv.TsylvError):
         c.gmres_batch(items, m=64)
     with pytest.raises(tsylv.TsylvError):
-        c.gmres_batch(items, refine=1, prec=tsylv.FP32)
-    with pytest.raises(tsylv.TsylvError):
         c.gmres_batch([])
+
+
+@pytest.mark.gpu
+def test_mixed_batch_executors_by_instance():
+    """FP64 batch with small instances (lockstep) and large ones (n s p >
+    2^18: the stream executor): the large ones are bitwise the synchronous
+    tsylv_gmres solves, the small ones bitwise their batch-of-one solves."""
+    import torch
+    shapes = [(512, 96, 8), (30, 6, 3), (1024, 40, 8), (40, 20, 5)]
+    say("batch executors", shapes)
+    c = ctx()
+    _, items = _batch(shapes, 800)
+    infos = c.gmres_batch(items, m=20, tol=1e-11, max_cycles=200)
+    for k, ((Ad, Bd, Cd, X), info) in enumerate(zip(items, infos)):
+        assert info.status == 0, info.as_dict()
+        n, s, p = shapes[k]
+        if n * s * p > (1 << 18):
+            Xs, i1 = c.gmres(Ad, Bd, Cd, m=20, tol=1e-11, max_cycles=200)
+            assert torch.equal(Xs, X), k
+            assert i1.steps == info.steps
+        else:
+            X1 = torch.zeros_like(Cd)
+            c.gmres_batch([(Ad, Bd, Cd, X1)], m=20, tol=1e-11, max_cycles=200)
+            assert torch.equal(X1, X), k
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", [tsylv.FP32, tsylv.BF16])
+def test_refined_batch(prec):
+    """Refined batches (FP64 refinement around inner tGMRES cycles in FP32
+    or BF16): every instance bitwise its refined single solve, within 1e-7
+    of the oracle's Kronecker solution for the small ones, relres 1e-10."""
+    import torch
+    shapes = [(30, 6, 3), (12, 5, 4), (256, 48, 8), (9, 40, 2)]
+    say("refined batch", prec, shapes)
+    data, items = _batch(shapes, 900)
+    c = ctx()
+    o = tsylv.default_opts(tsylv.GMRES, m=30, refine=1, prec=prec, inner_m=20, inner_tol=1e-4,
+                           tol=1e-10, max_outer=300)
+    infos = c.gmres_batch(items, opts=o)
+    for k, ((A, B, C), (Ad, Bd, Cd, X), info) in enumerate(zip(data, items, infos)):
+        assert info.status == 0, (k, info.as_dict())
+        assert info.relres_true <= 1e-10 and info.outer >= 1
+        Xs, _ = c.gmres(Ad, Bd, Cd, opts=o)
+        assert torch.equal(Xs, X), k
+        if A.shape[0] * B.shape[0] * A.shape[2] <= 900:
+            assert rel(host(X), kron.kron_solve(A, B, C)) <= 1e-7

@@ -96,8 +96,10 @@ def test_batch_workspace_query():
     assert lib.tsylv_batch_workspace_bytes(0, probs, ctypes.byref(o)) == 0
     o.m = 64  # beyond the batch's restart limit
     assert lib.tsylv_batch_workspace_bytes(2, probs, ctypes.byref(o)) == 0
+    # refined batches run as concurrent single solves: their workspaces
     o = tsylv.default_opts(tsylv.GMRES, refine=1, prec=tsylv.FP32)
-    assert lib.tsylv_batch_workspace_bytes(2, probs, ctypes.byref(o)) == 0
+    single = [tsylv.workspace_bytes(tsylv.GMRES, n, s, p, o) for n, s, p in [(100, 8, 5), (40, 3, 2)]]
+    assert lib.tsylv_batch_workspace_bytes(2, probs, ctypes.byref(o)) == sum(single)
 
 
 def test_strerror():
