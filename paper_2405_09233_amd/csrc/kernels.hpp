@@ -232,13 +232,17 @@ inline PMat dense_pmat(const double* base, int64_t plane, int64_t ld) {
 // Hm: p_h interleaved-complex ms x ms column-major slices, lower bandwidth s
 // (block upper Hessenberg); lam: nsys shifts; D: p_h interleaved s x s
 // slices, column j = the first s rows of system (k, j)'s right-hand side
-// (the rest is zero); z: nsys x ms, receives the solutions; Wrk (nsys s ms)
-// and U (nsys proj_u_stride(s, m)) complex scratch; info: nsys flags, 1 where
-// a pivot vanished.  Requires 1 <= s <= proj_max_block(), ms = m s.
+// (the rest is zero); z: nsys x ms, receives the solutions; Wrk (2 nsys s ms)
+// and U (nsys proj_u_stride(s, m)) complex scratch, G (proj_g_doubles(s,
+// nsys) doubles) scratch for each panel's L^{-1} and row permutation; info:
+// nsys flags, 1 where a pivot vanished.  Requires 1 <= s <= proj_max_block(),
+// ms = m s.
 int proj_max_block();
 int64_t proj_u_stride(int s, int m);
+int64_t proj_g_doubles(int s, int nsys);
 void proj_solve(const double* Hm, const double* lam, const double* D, double* z, double* Wrk,
-                double* U, int* info, int ms, int s, int m, int nsys, hipStream_t st);
+                double* U, double* G, int* info, int ms, int s, int m, int nsys,
+                hipStream_t st);
 
 // Device small linear algebra of a TBAS cycle (kernels_tba.hip).  Planar
 // matrices use the half-spectrum plane layout (p planes, s x s or J x s,

@@ -10,10 +10,17 @@
 // (lower bandwidth s).  Each system is solved by block LU with s x s blocks:
 // panel b is the 2s x s block column [row block b as updated so far; row
 // block b + 1 as built], factorised with partial pivoting inside the panel
-// (band-limited pivoting, as in banded LU), applied on the fly to the
-// right-hand side and, through explicit L11^{-1} and L21, to the trailing
-// columns of the two block rows.  The finished row blocks of U are kept for
-// the back substitution.  One workgroup per system; the panel lives in LDS.
+// (band-limited pivoting, as in banded LU) and applied on the fly to the
+// right-hand side.  With the panel's row permutation T of the two block
+// rows and G = L^{-1} [I_s; 0] = [L11^{-1}; -L21 L11^{-1}], the trailing
+// columns become [U12; next row block] = G T_top + [0; T_bot]: one dense
+// 2s x s by s x (trailing columns) product per panel, on the FP64 matrix
+// cores.  The finished row blocks of U are kept for the back substitution.
+// Per panel two launches: the factorisation (one workgroup per system, the
+// panel in registers) and the trailing product (many workgroups per
+// system).
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace tsylv {
@@ -23,7 +30,6 @@ namespace {
 
 constexpr int kPB = 256;     // threads per workgroup
 constexpr int kPMax = 64;    // largest block size s handled here
-constexpr int kTC = 8;       // trailing columns per tile
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -43,19 +49,60 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   const double r = b.x / b.y, d = b.y + b.x * r;
   return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
 }
-__device__ __forceinline__ double cnorm2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// Largest key over each 16-lane row of the wave (every lane of a row ends
+// with it): max with the lanes at xor 1 and xor 2 inside each quad, then
+// with the mirrored lane inside each half row and inside the row.
+__device__ __forceinline__ unsigned max_dpp(unsigned k) {
+  unsigned o;
+  o = (unsigned)__builtin_amdgcn_update_dpp((int)k, (int)k, 0xB1, 0xF, 0xF, false);  // quad [1,0,3,2]
+  k = o > k ? o : k;
+  o = (unsigned)__builtin_amdgcn_update_dpp((int)k, (int)k, 0x4E, 0xF, 0xF, false);  // quad [2,3,0,1]
+  k = o > k ? o : k;
+  o = (unsigned)__builtin_amdgcn_update_dpp((int)k, (int)k, 0x141, 0xF, 0xF, false);  // half mirror
+  k = o > k ? o : k;
+  o = (unsigned)__builtin_amdgcn_update_dpp((int)k, (int)k, 0x140, 0xF, 0xF, false);  // row mirror
+  return o > k ? o : k;
+}
+// x of lane `lane` (a wave-uniform index)
+__device__ __forceinline__ double2 read_lane(double2 x, int lane) {
+  const int l = __builtin_amdgcn_readfirstlane(lane);
+  return make_double2(
+      __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x.x), l),
+                       __builtin_amdgcn_readlane(__double2loint(x.x), l)),
+      __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x.y), l),
+                       __builtin_amdgcn_readlane(__double2loint(x.y), l)));
+}
+
+// 1 / b with the larger component of b scaled to one (Smith's scaling: no
+// overflow or underflow in forming |b|^2)
+__device__ __forceinline__ double2 crecip(double2 b) {
+  if (fabs(b.x) >= fabs(b.y)) {
+    const double r = b.y / b.x, inv = 1.0 / (b.x + b.y * r);
+    return make_double2(inv, -r * inv);
+  }
+  const double r = b.x / b.y, inv = 1.0 / (b.y + b.x * r);
+  return make_double2(r * inv, -inv);
+}
 
 struct ProjArgs {
   const double2* Hm;  // p_h slices of ms x ms, column-major
   const double2* lam; // nsys shifts, system k s + j
   const double2* D;   // p_h slices of s x s: first s rows of the right-hand sides
   double2* z;         // nsys x ms: right-hand side, then solution
-  double2* Wrk;       // nsys x (s x ms): the current row block
+  double2* Wrk;       // 2 x nsys x (s x ms): the current row block, ping-pong by panel
   double2* U;         // nsys x ustride: finished row blocks of U
   int* info;          // nsys flags (1: zero pivot)
+  double* G;          // nsys x g_sys_doubles(s): G and the permutation of a panel
   int ms, s, m, nsys;
   int64_t ustride;
 };
+
+// Row block b of system sys as updated by the panels before it (panel b
+// reads buffer b % 2, its trailing update writes buffer (b + 1) % 2).
+__device__ __forceinline__ double2* wrk(const ProjArgs& a, int b, int sys) {
+  return a.Wrk + ((int64_t)(b & 1) * a.nsys + sys) * a.s * a.ms;
+}
 
 __device__ __forceinline__ int64_t uoff(const ProjArgs& a, int b) {
   return (int64_t)a.s * a.s * ((int64_t)b * a.m - (int64_t)b * (b - 1) / 2);
@@ -84,207 +131,419 @@ __global__ void proj_init_kernel(ProjArgs a) {
   }
 }
 
-// Panel b of every system.  Dynamic LDS: P (2 kPMax x kPMax), tile
-// (2 kPMax x kTC), r2 (2 kPMax), tmp (kPMax), perm/piv.
-__global__ __launch_bounds__(kPB) void proj_panel_kernel(ProjArgs a, int b) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  constexpr int LD = 2 * kPMax;
-  double2* P = reinterpret_cast<double2*>(smem);
-  double2* tile = P + LD * kPMax;
-  double2* r2 = tile + LD * kTC;
-  double2* tmp = r2 + LD;
-  int* piv = reinterpret_cast<int*>(tmp + kPMax);
-  int* perm = piv + kPMax;
-  int* sflag = perm + LD;
-  double* wbest = reinterpret_cast<double*>(sflag + 4);
+// Row permutation and G = L^{-1} [I_s; 0] of panel b, per system: G's
+// top s rows are L11^{-1}, its bottom s rows -L21 L11^{-1}, stored in the
+// operand order of v_mfma_f64_16x16x4 (element (i, k) of row block i / 16
+// and k-step k / 4 in lane i % 16 + 16 (k % 4)); rows and columns padded to
+// sp = s rounded up to 16 (top rows 0 .. sp-1, bottom rows sp .. 2 sp - 1),
+// Re plane then Im plane, then 2 kPMax ints of the permutation.
+__host__ __device__ inline int pad16(int s) { return (s + 15) & ~15; }
+__host__ __device__ inline int64_t g_sys_doubles(int s) {
+  return 4 * (int64_t)pad16(s) * pad16(s) + kPMax;
+}
+
+__device__ __forceinline__ int xcd_tile(int b, int total) {
+  const int q = total / 8, r = total % 8;
+  const int x = b % 8;
+  return x * q + (x < r ? x : r) + b / 8;
+}
+
+// The panel kernel's thread grid: thread (tr, tc) holds rows tr + kTR i
+// (i < kRI) and columns tc + kTC j (j < kCJ) of the 2s x s panel in
+// registers; consecutive threads hold consecutive rows (coalesced loads).
+constexpr int kLB = 512;
+constexpr int kTR = 32, kTC = kLB / kTR;
+constexpr int kRI = 2 * kPMax / kTR, kCJ = kPMax / kTC;
+
+// Runs body(std::integral_constant<int, c / kTC>) for the column slot of
+// c, so that register arrays are only ever indexed at compile time.
+template <typename F>
+__device__ __forceinline__ void with_slot(int c, F&& body) {
+  static_assert(kCJ == 4, "one case per column slot");
+  switch (c / kTC) {
+    case 0: body(std::integral_constant<int, 0>{}); break;
+    case 1: body(std::integral_constant<int, 1>{}); break;
+    case 2: body(std::integral_constant<int, 2>{}); break;
+    default: body(std::integral_constant<int, 3>{}); break;
+  }
+}
+
+// Panel b of every system, one workgroup each, the panel in registers:
+// LU with partial pivoting inside the panel (band-limited pivoting, as in
+// banded LU), applied on the fly to the right-hand side; the finished U
+// block; then, for the trailing update, the row permutation and
+// G = L^{-1} [I_s; 0] by forward substitution, formed in place: column l of
+// L is broadcast at step l and never read again, so its registers take
+// column l of G.  Three barriers per LU column, one per substitution step;
+// only the pivot row and the multipliers pass through LDS.
+__global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
+  __shared__ double2 prow[kPMax], crow[kPMax];
+  __shared__ double2 lcol[2][2 * kPMax];
+  __shared__ double2 grow[2][kPMax];
+  __shared__ double2 r2[2 * kPMax];
+  __shared__ int perm[2 * kPMax];
+  __shared__ int spiv;
+  __shared__ double sbest;
 
   const int sys = blockIdx.x, tid = threadIdx.x;
+  const int tr = tid % kTR, tc = tid / kTR;
   const int s = a.s, ms = a.ms, m = a.m;
   const int k = sys / s;
-  const double2 lamv = a.lam[sys];
   const bool has_bot = b + 1 < m;
   const int nr = has_bot ? 2 * s : s;
   const int col0 = b * s;
   const double2* Hk = a.Hm + (int64_t)k * ms * ms;
-  double2* W = a.Wrk + (int64_t)sys * s * ms;
+  const double2* W = wrk(a, b, sys);
   double2* zs = a.z + (int64_t)sys * ms;
-  // row r of the panel: r < s current row block b, else original row (b+1)s + r - s
-  for (int e = tid; e < nr * s; e += kPB) {
-    const int r = e % nr, c = e / nr;
-    P[r + LD * c] = r < s ? W[r + (int64_t)s * (col0 + c)]
-                          : Hk[(int64_t)(col0 + s + r - s) + (int64_t)ms * (col0 + c)];
+  const double2 zero = make_double2(0.0, 0.0);
+
+  // row r of the panel: r < s the current row block b, else row
+  // (b + 1) s + r - s of Hm (block column b, off the diagonal: no shift)
+  double2 v[kRI][kCJ];
+#pragma unroll
+  for (int i = 0; i < kRI; ++i)
+#pragma unroll
+    for (int j = 0; j < kCJ; ++j) {
+      const int r = tr + kTR * i, c = tc + kTC * j;
+      double2 x = zero;
+      if (r < nr && c < s)
+        x = r < s ? W[r + (int64_t)s * (col0 + c)]
+                  : Hk[(int64_t)(col0 + r) + (int64_t)ms * (col0 + c)];
+      v[i][j] = x;
+    }
+  for (int i = tid; i < nr; i += kLB) {
+    r2[i] = zs[col0 + i];
+    perm[i] = i;
   }
-  for (int i = tid; i < nr; i += kPB) r2[i] = zs[col0 + i];  // rows b s .. b s + nr - 1
-  if (tid == 0) sflag[0] = 0;
+
+  // Pivot of column `col`: largest |Re| + |Im| of v(r, col) over r >= col
+  // (the complex magnitude of LAPACK's izamax), smallest row on ties, found
+  // by the kTR = 32 owners of the column -- one half of a wave -- and left
+  // in spiv / sbest for the next barrier.  Each lane packs its best as a
+  // 32-bit key: the top bits of the magnitude (sign, exponent and 13
+  // mantissa bits of the double: ordered like the magnitude, so the pivot
+  // is within a factor 1 + 2^-13 of the largest) over 127 - row; the keys
+  // meet in four DPP steps inside each 16-lane row and two lane reads.
+  auto pivot_search = [&](int col) {
+    with_slot(col, [&](auto slot) {
+      constexpr int JC = decltype(slot)::value;
+      if (tc + kTC * JC != col) return;
+      unsigned key = 0u;
+#pragma unroll
+      for (int i = 0; i < kRI; ++i) {
+        const int r = tr + kTR * i;
+        if (r >= col && r < nr) {
+          const double mag = fabs(v[i][JC].x) + fabs(v[i][JC].y);
+          const unsigned kk = ((unsigned)__double2hiint(mag) & ~0x7Fu) | (unsigned)(127 - r);
+          key = kk > key ? kk : key;
+        }
+      }
+      key = max_dpp(key);
+      const int base = __builtin_amdgcn_readfirstlane(32 * (tc & 1));
+      const unsigned k0 = (unsigned)__builtin_amdgcn_readlane((int)key, base);
+      const unsigned k1 = (unsigned)__builtin_amdgcn_readlane((int)key, base + 16);
+      const unsigned kw = k0 > k1 ? k0 : k1;
+      if (tr == 0) {
+        spiv = 127 - (int)(kw & 0x7Fu);
+        sbest = __hiloint2double((int)(kw & ~0x7Fu), 0);
+      }
+    });
+  };
+  pivot_search(0);
   __syncthreads();
+  bool singular = false;  // a zero or non-finite pivot met so far (same in every thread)
 
+  // Two barriers per column: (A) the old rows c and pr and the multipliers
+  // to LDS -- the owners of column c, one group of kTR lanes, get the pivot
+  // and the old v(c, c) by shuffles; (B) the swap, the rank-1 update and the
+  // next column's pivot search.
   for (int c = 0; c < s; ++c) {
-    if (tid < 64) {  // pivot: largest |P(r, c)| over r >= c, smallest index on ties
-      double best = -1.0;
-      int bi = c;
-      for (int r = c + tid; r < nr; r += 64) {
-        const double v = cnorm2(P[r + LD * c]);
-        if (v > best) {
-          best = v;
-          bi = r;
+    // (no candidate won only if the column is NaN: keep row c; the flag
+    // reports the breakdown)
+    const int pr = (spiv >= c && spiv < nr) ? spiv : c;
+    singular = singular || !(sbest > 0.0) || !isfinite(sbest);
+#pragma unroll
+    for (int i = 0; i < kRI; ++i) {
+      const int r = tr + kTR * i;
+      if (r == c)
+#pragma unroll
+        for (int j = 0; j < kCJ; ++j) crow[tc + kTC * j] = v[i][j];
+      if (r == pr)
+#pragma unroll
+        for (int j = 0; j < kCJ; ++j) prow[tc + kTC * j] = v[i][j];
+    }
+    with_slot(c, [&](auto slot) {
+      constexpr int JC = decltype(slot)::value;
+      if (tc + kTC * JC != c) return;
+      // the pivot v(pr, c) and the old v(c, c), read from their owners' lanes
+      double2 xp = zero, xc = zero;
+#pragma unroll
+      for (int i = 0; i < kRI; ++i) {
+        if (i == pr / kTR) xp = v[i][JC];
+        if (i == c / kTR) xc = v[i][JC];
+      }
+      const int base = __builtin_amdgcn_readfirstlane(32 * (tc & 1));
+      const double2 d = read_lane(xp, base + pr % kTR);
+      const double2 occ = read_lane(xc, base + c % kTR);
+      // one reciprocal of the pivot per column: the multipliers are products
+      const double2 dinv = singular ? make_double2(1.0, 0.0) : crecip(d);
+#pragma unroll
+      for (int i = 0; i < kRI; ++i) {
+        const int r = tr + kTR * i;
+        if (r > c && r < nr) {
+          double2 x = v[i][JC];
+          if (r == pr) x = occ;  // row pr takes the old row c
+          const double2 l = cmul(x, dinv);
+          v[i][JC] = l;
+          lcol[0][r] = l;
         }
       }
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
+    });
+    if (tid == 0) {
+      const double2 t = r2[c];
+      r2[c] = r2[pr];
+      r2[pr] = t;
+      const int q = perm[c];
+      perm[c] = perm[pr];
+      perm[pr] = q;
+    }
+    __syncthreads();
+    // swap (column c of the rows below c already holds the multipliers)
+#pragma unroll
+    for (int i = 0; i < kRI; ++i) {
+      const int r = tr + kTR * i;
+      if (r == c) {
+#pragma unroll
+        for (int j = 0; j < kCJ; ++j) v[i][j] = prow[tc + kTC * j];
+      } else if (r == pr) {
+#pragma unroll
+        for (int j = 0; j < kCJ; ++j)
+          if (tc + kTC * j != c) v[i][j] = crow[tc + kTC * j];
+      }
+    }
+    // rank-1 update of the rows below c, columns right of c, and the rhs
+#pragma unroll
+    for (int i = 0; i < kRI; ++i) {
+      const int r = tr + kTR * i;
+      if (r > c && r < nr) {
+        const double2 l = lcol[0][r];
+#pragma unroll
+        for (int j = 0; j < kCJ; ++j) {
+          const int cc = tc + kTC * j;
+          if (cc > c && cc < s) v[i][j] = csub(v[i][j], cmul(l, prow[cc]));
         }
       }
-      if (tid == 0) {
-        piv[c] = bi;
-        wbest[0] = best;
-        if (!(best > 0.0) || !isfinite(best)) sflag[0] = 1;
-      }
     }
-    __syncthreads();
-    const int pr = piv[c];
-    if (pr != c) {
-      for (int cc = tid; cc <= s; cc += kPB) {
-        if (cc < s) {
-          const double2 t = P[c + LD * cc];
-          P[c + LD * cc] = P[pr + LD * cc];
-          P[pr + LD * cc] = t;
-        } else {
-          const double2 t = r2[c];
-          r2[c] = r2[pr];
-          r2[pr] = t;
-        }
-      }
-    }
-    __syncthreads();
-    const double2 d = sflag[0] ? make_double2(1.0, 0.0) : P[c + LD * c];
-    for (int r = c + 1 + tid; r < nr; r += kPB) P[r + LD * c] = cdiv(P[r + LD * c], d);
-    __syncthreads();
-    // rank-1 update of the rows below c, columns c+1 .. s-1 and the right-hand side
-    const int rows = nr - c - 1, cols = s - c;  // column index s - c - 1 + ... ; last = rhs
-    for (int e = tid; e < rows * cols; e += kPB) {
-      const int r = c + 1 + e % rows, q = e / rows;  // q in [0, cols): column c+1+q or rhs
-      const double2 l = P[r + LD * c];
-      if (q < cols - 1) {
-        const int cc = c + 1 + q;
-        P[r + LD * cc] = csub(P[r + LD * cc], cmul(l, P[c + LD * cc]));
-      } else {
-        r2[r] = csub(r2[r], cmul(l, r2[c]));
-      }
-    }
+    for (int r = c + 1 + tid; r < nr; r += kLB) r2[r] = csub(r2[r], cmul(lcol[0][r], r2[c]));
+    if (c + 1 < s) pivot_search(c + 1);
     __syncthreads();
   }
-  if (tid == 0 && sflag[0]) a.info[sys] = 1;
+  if (tid == 0 && singular) a.info[sys] = 1;
 
-  // finished U block (s x s, zero below the diagonal) and the eliminated rhs
+  // the finished U block (s x s, zero below the diagonal), the eliminated rhs
   double2* Ub = a.U + (int64_t)sys * a.ustride + uoff(a, b);
-  for (int e = tid; e < s * s; e += kPB) {
-    const int r = e % s, c = e / s;
-    Ub[r + (int64_t)s * c] = r <= c ? P[r + LD * c] : make_double2(0.0, 0.0);
-  }
-  for (int i = tid; i < nr; i += kPB) zs[col0 + i] = r2[i];
+#pragma unroll
+  for (int i = 0; i < kRI; ++i)
+#pragma unroll
+    for (int j = 0; j < kCJ; ++j) {
+      const int r = tr + kTR * i, c = tc + kTC * j;
+      if (r < s && c < s) {
+        // (a value select: a select between the array element and another
+        // lvalue would take the array's address and keep it out of registers)
+        double2 x = v[i][j];
+        if (r > c) x = zero;
+        Ub[r + (int64_t)s * c] = x;
+      }
+    }
+  for (int i = tid; i < nr; i += kLB) zs[col0 + i] = r2[i];
   if (!has_bot) return;
 
-  // L11 (unit lower, top s rows) inverted in place, column by column from the
-  // right: X(i, j) = -(L(i, j) + sum_{j<l<i} X(i, l) L(l, j)).
-  for (int j = s - 2; j >= 0; --j) {
-    for (int i = j + 1 + tid; i < s; i += kPB) tmp[i] = P[i + LD * j];
+  const int sp = pad16(s), nks = sp / 4, nrbt = sp / 8;
+  double* Gs = a.G + (int64_t)sys * g_sys_doubles(s);
+  const int64_t gim = (int64_t)nrbt * nks * 64;  // Im plane offset
+  int* Gp = reinterpret_cast<int*>(Gs + 4 * (int64_t)sp * sp);
+  for (int i = tid; i < nr; i += kLB) Gp[i] = perm[i];
+
+  // G = L^{-1} [I_s; 0]: for l = 0 .. s-1, rows r > l of columns <= l
+  // lose L(r, l) G(l, :)
+  for (int l = 0; l < s; ++l) {
+    const int q = l & 1;
+    with_slot(l, [&](auto slot) {
+      constexpr int JL = decltype(slot)::value;
+      if (tc + kTC * JL == l) {
+#pragma unroll
+        for (int i = 0; i < kRI; ++i) {
+          const int r = tr + kTR * i;
+          if (r < nr) {
+            if (r > l) lcol[q][r] = v[i][JL];
+            v[i][JL] = make_double2(r == l ? 1.0 : 0.0, 0.0);
+          }
+        }
+      }
+    });
+#pragma unroll
+    for (int i = 0; i < kRI; ++i)
+      if (tr + kTR * i == l)
+#pragma unroll
+        for (int j = 0; j < kCJ; ++j) {
+          const int cc = tc + kTC * j;
+          if (cc <= l) grow[q][cc] = v[i][j];
+        }
     __syncthreads();
-    for (int i = j + 1 + tid; i < s; i += kPB) {
-      double2 t = tmp[i];
-      for (int l = j + 1; l < i; ++l) t = cadd(t, cmul(P[i + LD * l], tmp[l]));
-      P[i + LD * j] = make_double2(-t.x, -t.y);
+#pragma unroll
+    for (int i = 0; i < kRI; ++i) {
+      const int r = tr + kTR * i;
+      if (r > l && r < nr) {
+        const double2 x = lcol[q][r];
+#pragma unroll
+        for (int j = 0; j < kCJ; ++j) {
+          const int cc = tc + kTC * j;
+          if (cc <= l) v[i][j] = csub(v[i][j], cmul(x, grow[q][cc]));
+        }
+      }
     }
+  }
+
+  // G to its fragment order; padding rows and columns are zero
+  if (sp != s) {
+    for (int64_t e = tid; e < 4 * (int64_t)sp * sp; e += kLB) Gs[e] = 0.0;
     __syncthreads();
   }
-  if (tid == 0) {
-    for (int r = 0; r < nr; ++r) perm[r] = r;
-    for (int c = 0; c < s; ++c) {
-      const int t = perm[c];
-      perm[c] = perm[piv[c]];
-      perm[piv[c]] = t;
+#pragma unroll
+  for (int i = 0; i < kRI; ++i)
+#pragma unroll
+    for (int j = 0; j < kCJ; ++j) {
+      const int r = tr + kTR * i, c = tc + kTC * j;
+      if (r < nr && c < s) {
+        const int gr = r < s ? r : sp + (r - s);
+        const int64_t off = ((int64_t)(gr / 16) * nks + c / 4) * 64 + (gr % 16) + 16 * (c % 4);
+        Gs[off] = v[i][j].x;
+        Gs[gim + off] = v[i][j].y;
+      }
     }
+}
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kTB = 512;  // threads of the trailing kernel: one wave per 16-row block
+constexpr int kTW = 64;   // columns per workgroup (four MFMA column blocks)
+
+// Trailing update of panel b: for the columns of one tile of one system,
+//   [U12; A22'] = G T_top + [0; T_bot],
+// T the panel's row permutation of the two block rows (the current row
+// block and row block b + 1 of Hm, shifted on the diagonal).  Wave w owns
+// row block w of the 2 sp rows (its G fragments in registers) and all four
+// column blocks; T_top passes through LDS once per workgroup (Re and Im
+// planes), T_bot goes straight into the bottom waves' accumulators;
+// v_mfma_f64_16x16x4 in planar complex form, and the blocks of the top
+// half above the diagonal of L11^{-1} (zero) are skipped.  Workgroups of
+// one system are consecutive in the XCD-aware order, so the system's G is
+// read from one L2.
+__global__ __launch_bounds__(kTB, 4) void proj_trail_kernel(ProjArgs a, int b, int ntile) {
+  __shared__ double Tt[2][kPMax][kTW + 2];
+  __shared__ int sperm[2 * kPMax];
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int sys = t / ntile, tile = t % ntile;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int rb = tid >> 6;  // this wave's row block
+  const int lr = lane & 15, lk = lane >> 4;
+  const int s = a.s, ms = a.ms;
+  const int sp = pad16(s), nks = sp / 4, nrbt = sp / 8, nrb_top = sp / 16;
+  const int col0 = b * s;
+  const int k = sys / s;
+  const double2 lamv = a.lam[sys];
+  const double2* Hk = a.Hm + (int64_t)k * ms * ms;
+  const double2* W = wrk(a, b, sys);
+  double2* Wn = wrk(a, b + 1, sys);  // the next row block, in the other buffer
+  double2* Ub = a.U + (int64_t)sys * a.ustride + uoff(a, b);
+  const double* Gs = a.G + (int64_t)sys * g_sys_doubles(s);
+  const int64_t gim = (int64_t)nrbt * nks * 64;
+  const int* Gp = reinterpret_cast<const int*>(Gs + 4 * (int64_t)sp * sp);
+  const int c0 = col0 + s + tile * kTW;  // first column of the tile
+  const bool live = rb < nrbt;           // waves past the padded rows idle
+  const bool top = rb < nrb_top;
+
+  for (int i = tid; i < 2 * s; i += kTB) sperm[i] = Gp[i];
+  // row q (0 .. 2s-1) of the unpermuted two-block-row stack at column gc
+  auto stack = [&](int q, int gc) -> double2 {
+    if (q < s) return W[q + (int64_t)s * gc];
+    const int grow = col0 + q;  // (b + 1) s + q - s
+    double2 x = Hk[grow + (int64_t)ms * gc];
+    if (grow == gc) x = csub(x, lamv);
+    return x;
+  };
+  double gr[16], gi[16];
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) {
+    const bool ok = live && ks < nks;
+    const int64_t off = ((int64_t)rb * nks + ks) * 64 + lane;
+    gr[ks] = ok ? Gs[off] : 0.0;
+    gi[ks] = ok ? Gs[gim + off] : 0.0;
+  }
+  __syncthreads();  // sperm
+
+  // T_top to LDS (rows s .. sp-1 zero)
+  for (int e = tid; e < sp * kTW; e += kTB) {
+    const int r = e % sp, c = e / sp, gc = c0 + c;
+    double2 x = make_double2(0.0, 0.0);
+    if (r < s && gc < ms) x = stack(sperm[r], gc);
+    Tt[0][r][c] = x.x;
+    Tt[1][r][c] = x.y;
   }
   __syncthreads();
-
-  // trailing columns (b+1) s .. ms-1 of the two block rows, kTC at a time
-  for (int col = col0 + s; col < ms; col += kTC) {
-    for (int e = tid; e < nr * kTC; e += kPB) {
-      const int r = e % nr, cc = e / nr, gc = col + cc;
-      double2 v = make_double2(0.0, 0.0);
-      if (gc < ms) {
-        const int orow = perm[r];
-        if (orow < s) {
-          v = W[orow + (int64_t)s * gc];
-        } else {
-          const int grow = col0 + orow;  // (b+1) s + orow - s
-          v = Hk[grow + (int64_t)ms * gc];
-          if (grow == gc) v = csub(v, lamv);
-        }
+  if (!live) return;
+  // two column blocks at a time (half the accumulators: two workgroups fit
+  // a CU, one's staging under the other's products); T_bot goes straight
+  // into the bottom waves' accumulators (D element (i, j) of a block: lane
+  // j + 16 (i % 4), register i / 4)
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    d4 accr[2], acci[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int gc = c0 + 16 * (2 * half + h) + lr;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rr = 16 * rb + 4 * q + lk - sp;  // bottom-half row
+        double2 x = make_double2(0.0, 0.0);
+        if (!top && rr < s && gc < ms) x = stack(sperm[s + rr], gc);
+        accr[h][q] = x.x;
+        acci[h][q] = x.y;
       }
-      tile[r + LD * cc] = v;
     }
-    __syncthreads();
-    // Thread (rr, g): row rr, tile columns g, g + G, ... (at most CPT of
-    // them), so each L entry read from LDS serves all of the thread's columns.
-    constexpr int CPT = kTC / (kPB / kPMax);
-    const int G = kPB / s, rr = tid % s, g = tid / s;
-    const bool act = g < G;
-    // U rows: L11^{-1} times the top half (X holds L11^{-1} below the diagonal)
-    double2 acc[CPT];
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int cc = g + G * q;
-      acc[q] = (act && cc < kTC) ? tile[rr + LD * cc] : make_double2(0.0, 0.0);
-    }
-    if (act) {
-#pragma unroll 4
-      for (int l = 0; l < rr; ++l) {
-        const double2 x = P[rr + LD * l];
+    for (int ks = 0; ks < 16; ++ks) {
+      if (ks < nks && (!top || ks <= 4 * rb + 3)) {
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-          const int cc = g + G * q;
-          if (cc < kTC) acc[q] = cadd(acc[q], cmul(x, tile[l + LD * cc]));
+        for (int h = 0; h < 2; ++h) {
+          const int cc = 16 * (2 * half + h) + lr;
+          const double fr = Tt[0][4 * ks + lk][cc];
+          const double fi = Tt[1][4 * ks + lk][cc];
+          accr[h] = mfma64(gr[ks], fr, accr[h]);
+          accr[h] = mfma64(gi[ks], -fi, accr[h]);
+          acci[h] = mfma64(gr[ks], fi, acci[h]);
+          acci[h] = mfma64(gi[ks], fr, acci[h]);
         }
       }
     }
-    __syncthreads();
-    if (act) {
 #pragma unroll
-      for (int q = 0; q < CPT; ++q) {
-        const int cc = g + G * q, gc = col + cc;
-        if (cc < kTC) {
-          tile[rr + LD * cc] = acc[q];
-          if (gc < ms) Ub[rr + (int64_t)s * (gc - col0)] = acc[q];
+    for (int h = 0; h < 2; ++h) {
+      const int gc = c0 + 16 * (2 * half + h) + lr;
+      if (gc >= ms) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = 16 * rb + 4 * q + lk;
+        const double2 x = make_double2(accr[h][q], acci[h][q]);
+        if (top) {
+          if (row < s) Ub[row + (int64_t)s * (gc - col0)] = x;
+        } else if (row - sp < s) {
+          Wn[(row - sp) + (int64_t)s * gc] = x;
         }
       }
     }
-    __syncthreads();
-    // next row block: bottom half minus L21 times the U rows
-    if (act) {
-#pragma unroll
-      for (int q = 0; q < CPT; ++q) {
-        const int cc = g + G * q;
-        acc[q] = cc < kTC ? tile[s + rr + LD * cc] : make_double2(0.0, 0.0);
-      }
-#pragma unroll 4
-      for (int l = 0; l < s; ++l) {
-        const double2 x = P[s + rr + LD * l];
-#pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-          const int cc = g + G * q;
-          if (cc < kTC) acc[q] = csub(acc[q], cmul(x, tile[l + LD * cc]));
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < CPT; ++q) {
-        const int cc = g + G * q, gc = col + cc;
-        if (cc < kTC && gc < ms) W[rr + (int64_t)s * gc] = acc[q];
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -345,8 +604,11 @@ int proj_max_block() { return kPMax; }
 
 int64_t proj_u_stride(int s, int m) { return (int64_t)s * s * ((int64_t)m * (m + 1) / 2); }
 
+int64_t proj_g_doubles(int s, int nsys) { return (int64_t)nsys * g_sys_doubles(s); }
+
 void proj_solve(const double* Hm, const double* lam, const double* D, double* z, double* Wrk,
-                double* U, int* info, int ms, int s, int m, int nsys, hipStream_t st) {
+                double* U, double* G, int* info, int ms, int s, int m, int nsys,
+                hipStream_t st) {
   if (s < 1 || s > kPMax || ms != m * s || nsys < 1)
     throw Error(TSYLV_EINVAL, "projected solve: unsupported sizes");
   ProjArgs a;
@@ -357,6 +619,7 @@ void proj_solve(const double* Hm, const double* lam, const double* D, double* z,
   a.Wrk = reinterpret_cast<double2*>(Wrk);
   a.U = reinterpret_cast<double2*>(U);
   a.info = info;
+  a.G = G;
   a.ms = ms;
   a.s = s;
   a.m = m;
@@ -366,13 +629,15 @@ void proj_solve(const double* Hm, const double* lam, const double* D, double* z,
   const int gi = (int)std::min<int64_t>((work + 255) / 256, 16384);
   hipLaunchKernelGGL(proj_init_kernel, dim3(gi), dim3(256), 0, st, a);
   TSYLV_LAUNCH_CHECK();
-  constexpr int LD = 2 * kPMax;
-  const size_t lds_panel = sizeof(double2) * ((size_t)LD * kPMax + (size_t)LD * kTC + LD + kPMax) +
-                           sizeof(int) * (kPMax + LD + 4) + 16;
-  TSYLV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&proj_panel_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_panel));
   for (int b = 0; b < m; ++b) {
-    hipLaunchKernelGGL(proj_panel_kernel, dim3(nsys), dim3(kPB), lds_panel, st, a, b);
+    hipLaunchKernelGGL(proj_lu_kernel, dim3(nsys), dim3(kLB), 0, st, a, b);
+    TSYLV_LAUNCH_CHECK();
+    const int cols = ms - (b + 1) * s;  // trailing columns of the panel
+    if (cols <= 0) continue;
+    const int ntile = (cols + kTW - 1) / kTW;
+    const int64_t total = (int64_t)nsys * ntile;
+    if (total > 0x7fffffff) throw Error(TSYLV_EINVAL, "projected solve: too many systems");
+    hipLaunchKernelGGL(proj_trail_kernel, dim3((unsigned)total), dim3(kTB), 0, st, a, b, ntile);
     TSYLV_LAUNCH_CHECK();
   }
   const size_t lds_back = sizeof(double2) * ((size_t)ms + kPB + kPMax);

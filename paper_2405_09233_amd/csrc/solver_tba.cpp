@@ -115,7 +115,8 @@ int64_t tba_partial_elems(int64_t n, int64_t s, int64_t p, int m) {
 // the estimate terms of every slice and the flags (QR of R0, QR of step j,
 // projected solve).
 struct ProjWS {
-  double *Hm = nullptr, *lam = nullptr, *D = nullptr, *z = nullptr, *Wrk = nullptr, *U = nullptr;
+  double *Hm = nullptr, *lam = nullptr, *D = nullptr, *z = nullptr, *Wrk = nullptr, *U = nullptr,
+         *Gp = nullptr;
   double *W = nullptr, *Winv = nullptr, *Hlast = nullptr, *G2 = nullptr, *H0 = nullptr,
          *Rq = nullptr, *out = nullptr;
   int* info = nullptr;
@@ -128,8 +129,9 @@ struct ProjWS {
     const int64_t ph = num_slices((int)p), ms = (int64_t)m * s, nsys = ph * s;
     return Workspace::bytes_for(2 * ph * ms * ms, 8) + Workspace::bytes_for(2 * nsys, 8) +
            Workspace::bytes_for(2 * ph * s * s, 8) + Workspace::bytes_for(2 * nsys * ms, 8) +
-           Workspace::bytes_for(2 * nsys * s * ms, 8) +
+           Workspace::bytes_for(2 * 2 * nsys * s * ms, 8) +
            Workspace::bytes_for(2 * nsys * kern::proj_u_stride((int)s, m), 8) +
+           Workspace::bytes_for(kern::proj_g_doubles((int)s, (int)nsys), 8) +
            Workspace::bytes_for(nsys, 4) + 3 * Workspace::bytes_for(2 * ph * s * s, 8) +
            Workspace::bytes_for(p * ms * s, 8) + 2 * Workspace::bytes_for(p * s * s, 8) +
            Workspace::bytes_for(out_doubles(p, m), 8);
@@ -141,8 +143,9 @@ struct ProjWS {
     lam = ws.take<double>(2 * nsys);
     D = ws.take<double>(2 * ph * s * s);
     z = ws.take<double>(2 * nsys * ms);
-    Wrk = ws.take<double>(2 * nsys * s * ms);
+    Wrk = ws.take<double>(2 * 2 * nsys * s * ms);  // two buffers (ping-pong by panel)
     U = ws.take<double>(2 * nsys * kern::proj_u_stride((int)s, m));
+    Gp = ws.take<double>(kern::proj_g_doubles((int)s, (int)nsys));
     info = ws.take<int>(nsys);
     W = ws.take<double>(2 * ph * s * s);
     Winv = ws.take<double>(2 * ph * s * s);
@@ -449,8 +452,8 @@ int tba_solve(Ctx& ctx, int64_t n, int64_t s, int64_t p, const double* A, const 
       // the shifted systems (Hm_k - lam_{k,j} I) z = (H0_k W_k) e_j, then
       // Y_k = Z_k W_k^{-1} and the estimate ||H_{m+1,m} E_m^T Y||
       kern::proj_rhs(pw.H0, pw.W, pw.D, si, (int)p, st);
-      kern::proj_solve(pw.Hm, pw.lam, pw.D, pw.z, pw.Wrk, pw.U, pw.info, msi, si, m, ph * si,
-                       st);
+      kern::proj_solve(pw.Hm, pw.lam, pw.D, pw.z, pw.Wrk, pw.U, pw.Gp, pw.info, msi, si, m,
+                       ph * si, st);
       kern::proj_check(pw.info, pw.z, (int64_t)ph * si, (int64_t)ph * si * msi,
                        dflags + m + 1, st);
       kern::proj_y(pw.z, pw.Winv, pw.Hlast, w.Y, pw.out + 1, si, m, (int)p, st);

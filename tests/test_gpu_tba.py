@@ -124,13 +124,15 @@ def test_medium_dense_vs_tbs():
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("n,s,p,m", [(24, 3, 3, 3), (40, 5, 6, 3), (200, 16, 4, 4), (260, 64, 3, 3),
-                                     (140, 65, 2, 1), (96, 1, 5, 7)])
+                                     (140, 65, 2, 1), (96, 1, 5, 7), (300, 40, 2, 3),
+                                     (200, 20, 3, 5)])
 def test_device_and_host_projected_solves_agree(n, s, p, m, monkeypatch):
     """The projected equation of a TBAS cycle solved on the device (Bhat_k
     diagonalised, p_h s shifted block-Hessenberg systems) and on the host
     (Bartels-Stewart with the Schur form of Bhat_k): the same cycle iterate.
-    s = 65 exceeds the device kernel's block limit and takes the host path in
-    both runs."""
+    s = 40 and 20 leave padding in the device kernels' 16-wide blocks; s = 65
+    exceeds the device kernel's block limit and takes the host path in both
+    runs."""
     say("tba projected device vs host", n, s, p, m)
     A, B, C = workloads.dense_shifted(n, s, p, seed=n + s)
     Xd, idv = gpu_tba(A, B, C, m=m, tol=1e-300, max_cycles=1)
@@ -147,8 +149,12 @@ def test_ex3_ordering_matches_the_oracle():
     """The paper's convection-diffusion experiment family (section 6; n =
     1000, s = 3, p = 2, mu = 1e-3 -- the paper does not give mu), against the
     oracle's counts in tests/golden/ex3_counts.json (written by
-    make_ex3_counts.py from the oracle alone): TBAS(10) reaches 1e-6 in about
-    as many restart cycles as the oracle's TBAS(10), tGMRES(10) stalls where
+    make_ex3_counts.py from the oracle alone): TBAS(10) reaches 1e-6 in as
+    many restart cycles as the oracle's TBAS(10) takes on C perturbed at the
+    rounding level (the count of this slowly converging case moves by tens
+    of percent under a one-ulp change of C, so the bar is the range of the
+    oracle's counts, unperturbed and for five perturbations, widened by
+    15 %), tGMRES(10) stalls where
     the oracle's does (same residual after the same number of cycles), and
     tFOM(10) does worse than tGMRES(10) (the oracle's diverges or meets a
     singular projected system) -- the ordering TBAS < tGMRES < tFOM of the
@@ -165,8 +171,10 @@ def test_ex3_ordering_matches_the_oracle():
     X, it = c.tba(Ad, Bd, Cd, m=10, tol=1e-6, max_cycles=1000)
     say("  TBAS cycles", it.cycles, "oracle", gold["tbas"]["cycles"])
     assert it.status == 0 and it.relres_true <= 1e-6, it.as_dict()
-    assert gold["tbas"]["converged"]
-    assert abs(it.cycles - gold["tbas"]["cycles"]) <= 0.1 * gold["tbas"]["cycles"]
+    assert gold["tbas"]["converged"] and all(gold["tbas"]["perturbed"]["converged"])
+    counts = [gold["tbas"]["cycles"]] + gold["tbas"]["perturbed"]["cycles"]
+    say("  oracle counts (unperturbed, perturbed)", counts)
+    assert 0.85 * min(counts) <= it.cycles <= 1.15 * max(counts)
     R = C - host(c.apply(Ad, Bd, X))
     assert np.linalg.norm(R) / np.linalg.norm(C) <= 1.05e-6
     ng = gold["tgmres"]["cycles"]
