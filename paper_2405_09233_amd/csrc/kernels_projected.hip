@@ -177,11 +177,10 @@ __device__ __forceinline__ void with_slot(int c, F&& body) {
 // column l of G.  Three barriers per LU column, one per substitution step;
 // only the pivot row and the multipliers pass through LDS.
 __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
-  __shared__ double2 prow[kPMax], crow[kPMax];
+  __shared__ double2 prow[kPMax + 1], crow[kPMax + 1];  // + the rows' right-hand side
+  __shared__ int prow_o, crow_o;                        // and original row index
   __shared__ double2 lcol[2][2 * kPMax];
   __shared__ double2 grow[2][kPMax];
-  __shared__ double2 r2[2 * kPMax];
-  __shared__ int perm[2 * kPMax];
   __shared__ int spiv;
   __shared__ double sbest;
 
@@ -211,9 +210,16 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
                   : Hk[(int64_t)(col0 + r) + (int64_t)ms * (col0 + c)];
       v[i][j] = x;
     }
-  for (int i = tid; i < nr; i += kLB) {
-    r2[i] = zs[col0 + i];
-    perm[i] = i;
+  // the right-hand side and the original index of each row travel with the
+  // row: held by the row's owner in column group 0
+  double2 rhs[kRI];
+  int org[kRI];
+#pragma unroll
+  for (int i = 0; i < kRI; ++i) {
+    const int r = tr + kTR * i;
+    rhs[i] = zero;
+    if (tc == 0 && r < nr) rhs[i] = zs[col0 + r];
+    org[i] = r;
   }
 
   // Pivot of column `col`: largest |Re| + |Im| of v(r, col) over r >= col
@@ -255,8 +261,9 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
 
   // Two barriers per column: (A) the old rows c and pr and the multipliers
   // to LDS -- the owners of column c, one group of kTR lanes, get the pivot
-  // and the old v(c, c) by shuffles; (B) the swap, the rank-1 update and the
-  // next column's pivot search.
+  // and the old v(c, c) by lane reads; (B) the swap, the rank-1 update and
+  // the next column's pivot search.  Each phase issues its LDS reads
+  // together and applies them with selects, so a step waits on LDS once.
   for (int c = 0; c < s; ++c) {
     // (no candidate won only if the column is NaN: keep row c; the flag
     // reports the breakdown)
@@ -265,12 +272,22 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
 #pragma unroll
     for (int i = 0; i < kRI; ++i) {
       const int r = tr + kTR * i;
-      if (r == c)
+      if (r == c) {
 #pragma unroll
         for (int j = 0; j < kCJ; ++j) crow[tc + kTC * j] = v[i][j];
-      if (r == pr)
+        if (tc == 0) {
+          crow[kPMax] = rhs[i];
+          crow_o = org[i];
+        }
+      }
+      if (r == pr) {
 #pragma unroll
         for (int j = 0; j < kCJ; ++j) prow[tc + kTC * j] = v[i][j];
+        if (tc == 0) {
+          prow[kPMax] = rhs[i];
+          prow_o = org[i];
+        }
+      }
     }
     with_slot(c, [&](auto slot) {
       constexpr int JC = decltype(slot)::value;
@@ -299,42 +316,44 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
         }
       }
     });
-    if (tid == 0) {
-      const double2 t = r2[c];
-      r2[c] = r2[pr];
-      r2[pr] = t;
-      const int q = perm[c];
-      perm[c] = perm[pr];
-      perm[pr] = q;
-    }
     __syncthreads();
-    // swap (column c of the rows below c already holds the multipliers)
+    double2 pv[kCJ], cv[kCJ], lv[kRI];
+#pragma unroll
+    for (int j = 0; j < kCJ; ++j) {
+      pv[j] = prow[tc + kTC * j];
+      cv[j] = crow[tc + kTC * j];
+    }
+#pragma unroll
+    for (int i = 0; i < kRI; ++i) lv[i] = lcol[0][tr + kTR * i];
+    const double2 px = prow[kPMax], cx = crow[kPMax];
+    const int po = prow_o, co = crow_o;
+    // swap (column c of the rows below c already holds the multipliers),
+    // then the rank-1 update of the rows below c, columns right of c, and
+    // of the right-hand side
 #pragma unroll
     for (int i = 0; i < kRI; ++i) {
       const int r = tr + kTR * i;
       if (r == c) {
 #pragma unroll
-        for (int j = 0; j < kCJ; ++j) v[i][j] = prow[tc + kTC * j];
+        for (int j = 0; j < kCJ; ++j) v[i][j] = pv[j];
+        rhs[i] = px;
+        org[i] = po;
       } else if (r == pr) {
 #pragma unroll
         for (int j = 0; j < kCJ; ++j)
-          if (tc + kTC * j != c) v[i][j] = crow[tc + kTC * j];
+          if (tc + kTC * j != c) v[i][j] = cv[j];
+        rhs[i] = cx;
+        org[i] = co;
       }
-    }
-    // rank-1 update of the rows below c, columns right of c, and the rhs
-#pragma unroll
-    for (int i = 0; i < kRI; ++i) {
-      const int r = tr + kTR * i;
       if (r > c && r < nr) {
-        const double2 l = lcol[0][r];
 #pragma unroll
         for (int j = 0; j < kCJ; ++j) {
           const int cc = tc + kTC * j;
-          if (cc > c && cc < s) v[i][j] = csub(v[i][j], cmul(l, prow[cc]));
+          if (cc > c && cc < s) v[i][j] = csub(v[i][j], cmul(lv[i], pv[j]));
         }
+        rhs[i] = csub(rhs[i], cmul(lv[i], px));
       }
     }
-    for (int r = c + 1 + tid; r < nr; r += kLB) r2[r] = csub(r2[r], cmul(lcol[0][r], r2[c]));
     if (c + 1 < s) pivot_search(c + 1);
     __syncthreads();
   }
@@ -355,14 +374,22 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
         Ub[r + (int64_t)s * c] = x;
       }
     }
-  for (int i = tid; i < nr; i += kLB) zs[col0 + i] = r2[i];
+#pragma unroll
+  for (int i = 0; i < kRI; ++i) {
+    const int r = tr + kTR * i;
+    if (tc == 0 && r < nr) zs[col0 + r] = rhs[i];
+  }
   if (!has_bot) return;
 
   const int sp = pad16(s), nks = sp / 4, nrbt = sp / 8;
   double* Gs = a.G + (int64_t)sys * g_sys_doubles(s);
   const int64_t gim = (int64_t)nrbt * nks * 64;  // Im plane offset
   int* Gp = reinterpret_cast<int*>(Gs + 4 * (int64_t)sp * sp);
-  for (int i = tid; i < nr; i += kLB) Gp[i] = perm[i];
+#pragma unroll
+  for (int i = 0; i < kRI; ++i) {
+    const int r = tr + kTR * i;
+    if (tc == 0 && r < nr) Gp[r] = org[i];
+  }
 
   // G = L^{-1} [I_s; 0]: for l = 0 .. s-1, rows r > l of columns <= l
   // lose L(r, l) G(l, :)
@@ -390,15 +417,19 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
           if (cc <= l) grow[q][cc] = v[i][j];
         }
     __syncthreads();
+    double2 gv[kCJ], lv[kRI];
+#pragma unroll
+    for (int j = 0; j < kCJ; ++j) gv[j] = grow[q][tc + kTC * j];
+#pragma unroll
+    for (int i = 0; i < kRI; ++i) lv[i] = lcol[q][tr + kTR * i];
 #pragma unroll
     for (int i = 0; i < kRI; ++i) {
       const int r = tr + kTR * i;
       if (r > l && r < nr) {
-        const double2 x = lcol[q][r];
 #pragma unroll
         for (int j = 0; j < kCJ; ++j) {
           const int cc = tc + kTC * j;
-          if (cc <= l) v[i][j] = csub(v[i][j], cmul(x, grow[q][cc]));
+          if (cc <= l) v[i][j] = csub(v[i][j], cmul(lv[i], gv[j]));
         }
       }
     }
