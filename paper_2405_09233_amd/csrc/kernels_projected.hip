@@ -155,6 +155,19 @@ constexpr int kLB = 512;
 constexpr int kTR = 32, kTC = kLB / kTR;
 constexpr int kRI = 2 * kPMax / kTR, kCJ = kPMax / kTC;
 
+// Runs body(std::integral_constant<int, J>) for J = 0 .. kCJ - 1 in order:
+// loops over the columns of slot J (columns kTC J .. kTC J + kTC - 1 of the
+// thread grid) see J at compile time, so register arrays are only ever
+// indexed at compile time and no branch merges them.
+template <typename F>
+__device__ __forceinline__ void for_each_slot(F&& body) {
+  static_assert(kCJ == 4, "one call per column slot");
+  body(std::integral_constant<int, 0>{});
+  body(std::integral_constant<int, 1>{});
+  body(std::integral_constant<int, 2>{});
+  body(std::integral_constant<int, 3>{});
+}
+
 // Runs body(std::integral_constant<int, c / kTC>) for the column slot of
 // c, so that register arrays are only ever indexed at compile time.
 template <typename F>
@@ -171,16 +184,26 @@ __device__ __forceinline__ void with_slot(int c, F&& body) {
 // Panel b of every system, one workgroup each, the panel in registers:
 // LU with partial pivoting inside the panel (band-limited pivoting, as in
 // banded LU), applied on the fly to the right-hand side; the finished U
-// block; then, for the trailing update, the row permutation and
+// block; then, for the trailing update, the row order and
 // G = L^{-1} [I_s; 0] by forward substitution, formed in place: column l of
 // L is broadcast at step l and never read again, so its registers take
-// column l of G.  Three barriers per LU column, one per substitution step;
-// only the pivot row and the multipliers pass through LDS.
+// column l of G.
+//
+// Rows are never moved: each row records the step at which it became the
+// pivot (its position in the factorisation's row order), the last s
+// unpivoted rows taking positions s .. 2s-1 in row order.  The multipliers
+// of pivoted rows are zero and the pivot row is broadcast with its columns
+// up to c zeroed, so every thread updates all its entries with no
+// conditions.  Two barriers per LU column, one per substitution step; only
+// the pivot row and the multipliers pass through LDS.
+constexpr int kUnpivoted = 1 << 20;  // position of a row not yet pivoted
+constexpr int kOutside = 1 << 21;    // position of a thread slot past the panel's rows
+
 __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
-  __shared__ double2 prow[kPMax + 1], crow[kPMax + 1];  // + the rows' right-hand side
-  __shared__ int prow_o, crow_o;                        // and original row index
-  __shared__ double2 lcol[2][2 * kPMax];
-  __shared__ double2 grow[2][kPMax];
+  __shared__ double2 prow[kPMax + 1];     // pivot row: its columns, then its right-hand side
+  __shared__ double2 lcol[2][2 * kPMax];  // multipliers / L columns by row (zero where none)
+  __shared__ double2 grow[2][kPMax];      // row l of G (columns past l zero)
+  __shared__ unsigned left[4];            // rows never pivoted (bit r of word r / 32)
   __shared__ int spiv;
   __shared__ double sbest;
 
@@ -210,35 +233,37 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
                   : Hk[(int64_t)(col0 + r) + (int64_t)ms * (col0 + c)];
       v[i][j] = x;
     }
-  // the right-hand side and the original index of each row travel with the
-  // row: held by the row's owner in column group 0
+  // the right-hand side of each row, held by the row's owner in column
+  // group 0 (zero elsewhere), and each row's position
   double2 rhs[kRI];
-  int org[kRI];
+  int pos[kRI];
 #pragma unroll
   for (int i = 0; i < kRI; ++i) {
     const int r = tr + kTR * i;
     rhs[i] = zero;
     if (tc == 0 && r < nr) rhs[i] = zs[col0 + r];
-    org[i] = r;
+    pos[i] = r < nr ? kUnpivoted : kOutside;
   }
+  for (int e = tid; e < 2 * 2 * kPMax; e += kLB) lcol[e / (2 * kPMax)][e % (2 * kPMax)] = zero;
+  if (tid < 4) left[tid] = 0u;
 
-  // Pivot of column `col`: largest |Re| + |Im| of v(r, col) over r >= col
-  // (the complex magnitude of LAPACK's izamax), smallest row on ties, found
-  // by the kTR = 32 owners of the column -- one half of a wave -- and left
-  // in spiv / sbest for the next barrier.  Each lane packs its best as a
-  // 32-bit key: the top bits of the magnitude (sign, exponent and 13
-  // mantissa bits of the double: ordered like the magnitude, so the pivot
-  // is within a factor 1 + 2^-13 of the largest) over 127 - row; the keys
-  // meet in four DPP steps inside each 16-lane row and two lane reads.
-  auto pivot_search = [&](int col) {
-    with_slot(col, [&](auto slot) {
-      constexpr int JC = decltype(slot)::value;
-      if (tc + kTC * JC != col) return;
+  // Pivot of column `col`: largest |Re| + |Im| of v(r, col) over the
+  // unpivoted rows (the complex magnitude of LAPACK's izamax), smallest row
+  // on ties, found by the kTR = 32 owners of the column -- one half of a
+  // wave -- and left in spiv / sbest for the next barrier.  Each lane packs
+  // its best as a 32-bit key: the top bits of the magnitude (sign, exponent
+  // and 13 mantissa bits of the double: ordered like the magnitude, so the
+  // pivot is within a factor 1 + 2^-13 of the largest) over 127 - row; the
+  // keys meet in four DPP steps inside each 16-lane row and two lane reads.
+  auto pivot_search = [&](auto slot, int col) {
+    constexpr int JC = decltype(slot)::value;
+    if (tc + kTC * JC != col) return;
+    {
       unsigned key = 0u;
 #pragma unroll
       for (int i = 0; i < kRI; ++i) {
         const int r = tr + kTR * i;
-        if (r >= col && r < nr) {
+        if (pos[i] == kUnpivoted) {
           const double mag = fabs(v[i][JC].x) + fabs(v[i][JC].y);
           const unsigned kk = ((unsigned)__double2hiint(mag) & ~0x7Fu) | (unsigned)(127 - r);
           key = kk > key ? kk : key;
@@ -253,131 +278,119 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
         spiv = 127 - (int)(kw & 0x7Fu);
         sbest = __hiloint2double((int)(kw & ~0x7Fu), 0);
       }
-    });
+    }
   };
-  pivot_search(0);
+  pivot_search(std::integral_constant<int, 0>{}, 0);
   __syncthreads();
   bool singular = false;  // a zero or non-finite pivot met so far (same in every thread)
 
-  // Two barriers per column: (A) the old rows c and pr and the multipliers
-  // to LDS -- the owners of column c, one group of kTR lanes, get the pivot
-  // and the old v(c, c) by lane reads; (B) the swap, the rank-1 update and
-  // the next column's pivot search.  Each phase issues its LDS reads
-  // together and applies them with selects, so a step waits on LDS once.
-  for (int c = 0; c < s; ++c) {
-    // (no candidate won only if the column is NaN: keep row c; the flag
-    // reports the breakdown)
-    const int pr = (spiv >= c && spiv < nr) ? spiv : c;
+  for_each_slot([&](auto slot) {
+  constexpr int JC = decltype(slot)::value;
+  for (int cl = 0; cl < kTC; ++cl) {
+    const int c = kTC * JC + cl;
+    if (c >= s) break;
+    // the pivot row: an unpivoted row (a column of NaN picks no candidate,
+    // which the flag reports; any unpivoted row then serves)
+    int pr = spiv;
     singular = singular || !(sbest > 0.0) || !isfinite(sbest);
+    // (A) the pivot row to LDS, the multipliers of column c
 #pragma unroll
     for (int i = 0; i < kRI; ++i) {
-      const int r = tr + kTR * i;
-      if (r == c) {
-#pragma unroll
-        for (int j = 0; j < kCJ; ++j) crow[tc + kTC * j] = v[i][j];
-        if (tc == 0) {
-          crow[kPMax] = rhs[i];
-          crow_o = org[i];
-        }
-      }
-      if (r == pr) {
+      if (tr + kTR * i == pr) {
 #pragma unroll
         for (int j = 0; j < kCJ; ++j) prow[tc + kTC * j] = v[i][j];
-        if (tc == 0) {
-          prow[kPMax] = rhs[i];
-          prow_o = org[i];
-        }
+        if (tc == 0) prow[kPMax] = rhs[i];
       }
     }
-    with_slot(c, [&](auto slot) {
-      constexpr int JC = decltype(slot)::value;
-      if (tc + kTC * JC != c) return;
-      // the pivot v(pr, c) and the old v(c, c), read from their owners' lanes
-      double2 xp = zero, xc = zero;
+    if (tc + kTC * JC == c) {
+      double2 xp = zero;
 #pragma unroll
-      for (int i = 0; i < kRI; ++i) {
-        if (i == pr / kTR) xp = v[i][JC];
-        if (i == c / kTR) xc = v[i][JC];
-      }
+      for (int i = 0; i < kRI; ++i)
+        if (tr + kTR * i == pr) xp = v[i][JC];
       const int base = __builtin_amdgcn_readfirstlane(32 * (tc & 1));
-      const double2 d = read_lane(xp, base + pr % kTR);
-      const double2 occ = read_lane(xc, base + c % kTR);
+      const double2 d = read_lane(xp, base + (pr & (kTR - 1)));
       // one reciprocal of the pivot per column: the multipliers are products
       const double2 dinv = singular ? make_double2(1.0, 0.0) : crecip(d);
 #pragma unroll
       for (int i = 0; i < kRI; ++i) {
         const int r = tr + kTR * i;
-        if (r > c && r < nr) {
-          double2 x = v[i][JC];
-          if (r == pr) x = occ;  // row pr takes the old row c
-          const double2 l = cmul(x, dinv);
+        double2 l = zero;
+        if (pos[i] == kUnpivoted && r != pr) {
+          l = cmul(v[i][JC], dinv);
           v[i][JC] = l;
-          lcol[0][r] = l;
         }
+        lcol[0][r] = l;
       }
-    });
+    }
     __syncthreads();
-    double2 pv[kCJ], cv[kCJ], lv[kRI];
+    // (B) rank-1 update of every entry: pivoted rows have multiplier zero,
+    // the pivot row's columns up to c are zeroed
+    double2 pv[kCJ], lv[kRI];
 #pragma unroll
     for (int j = 0; j < kCJ; ++j) {
       pv[j] = prow[tc + kTC * j];
-      cv[j] = crow[tc + kTC * j];
+      if (tc + kTC * j <= c) pv[j] = zero;
     }
+    const double2 px = prow[kPMax];
 #pragma unroll
     for (int i = 0; i < kRI; ++i) lv[i] = lcol[0][tr + kTR * i];
-    const double2 px = prow[kPMax], cx = crow[kPMax];
-    const int po = prow_o, co = crow_o;
-    // swap (column c of the rows below c already holds the multipliers),
-    // then the rank-1 update of the rows below c, columns right of c, and
-    // of the right-hand side
 #pragma unroll
     for (int i = 0; i < kRI; ++i) {
-      const int r = tr + kTR * i;
-      if (r == c) {
 #pragma unroll
-        for (int j = 0; j < kCJ; ++j) v[i][j] = pv[j];
-        rhs[i] = px;
-        org[i] = po;
-      } else if (r == pr) {
-#pragma unroll
-        for (int j = 0; j < kCJ; ++j)
-          if (tc + kTC * j != c) v[i][j] = cv[j];
-        rhs[i] = cx;
-        org[i] = co;
-      }
-      if (r > c && r < nr) {
-#pragma unroll
-        for (int j = 0; j < kCJ; ++j) {
-          const int cc = tc + kTC * j;
-          if (cc > c && cc < s) v[i][j] = csub(v[i][j], cmul(lv[i], pv[j]));
-        }
-        rhs[i] = csub(rhs[i], cmul(lv[i], px));
+      for (int j = 0; j < kCJ; ++j) v[i][j] = csub(v[i][j], cmul(lv[i], pv[j]));
+      rhs[i] = csub(rhs[i], cmul(lv[i], px));
+      if (tr + kTR * i == pr) pos[i] = c;
+    }
+    if (c + 1 < s) {
+      if (cl + 1 < kTC) {
+        pivot_search(slot, c + 1);
+      } else if constexpr (JC + 1 < kCJ) {
+        pivot_search(std::integral_constant<int, JC + 1>{}, c + 1);
       }
     }
-    if (c + 1 < s) pivot_search(c + 1);
     __syncthreads();
   }
+  });
   if (tid == 0 && singular) a.info[sys] = 1;
+
+  // positions s .. 2s-1 of the rows never pivoted, in row order
+#pragma unroll
+  for (int i = 0; i < kRI; ++i) {
+    const int r = tr + kTR * i;
+    if (tc == 0 && pos[i] == kUnpivoted) atomicOr(&left[r / 32], 1u << (r % 32));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kRI; ++i) {
+    const int r = tr + kTR * i;
+    if (pos[i] == kUnpivoted) {
+      int below = 0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w)
+        below += __popc(w < r / 32 ? left[w] : (w == r / 32 ? left[w] & ((1u << (r % 32)) - 1u) : 0u));
+      pos[i] = s + below;
+    }
+  }
 
   // the finished U block (s x s, zero below the diagonal), the eliminated rhs
   double2* Ub = a.U + (int64_t)sys * a.ustride + uoff(a, b);
 #pragma unroll
-  for (int i = 0; i < kRI; ++i)
+  for (int i = 0; i < kRI; ++i) {
+    const int p = pos[i];
+    if (p < s) {
 #pragma unroll
-    for (int j = 0; j < kCJ; ++j) {
-      const int r = tr + kTR * i, c = tc + kTC * j;
-      if (r < s && c < s) {
-        // (a value select: a select between the array element and another
-        // lvalue would take the array's address and keep it out of registers)
-        double2 x = v[i][j];
-        if (r > c) x = zero;
-        Ub[r + (int64_t)s * c] = x;
+      for (int j = 0; j < kCJ; ++j) {
+        const int c = tc + kTC * j;
+        if (c < s) {
+          // (a value select: a select between the array element and another
+          // lvalue would take the array's address and keep it out of registers)
+          double2 x = v[i][j];
+          if (p > c) x = zero;
+          Ub[p + (int64_t)s * c] = x;
+        }
       }
     }
-#pragma unroll
-  for (int i = 0; i < kRI; ++i) {
-    const int r = tr + kTR * i;
-    if (tc == 0 && r < nr) zs[col0 + r] = rhs[i];
+    if (tc == 0 && p < nr) zs[col0 + p] = rhs[i];
   }
   if (!has_bot) return;
 
@@ -388,33 +401,36 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
 #pragma unroll
   for (int i = 0; i < kRI; ++i) {
     const int r = tr + kTR * i;
-    if (tc == 0 && r < nr) Gp[r] = org[i];
+    if (tc == 0 && pos[i] < nr) Gp[pos[i]] = r;
   }
 
-  // G = L^{-1} [I_s; 0]: for l = 0 .. s-1, rows r > l of columns <= l
-  // lose L(r, l) G(l, :)
-  for (int l = 0; l < s; ++l) {
+  // G = L^{-1} [I_s; 0] in the factorisation's row order: for l = 0 ..
+  // s-1, the rows at positions past l lose L(., l) G(l, :); the broadcast
+  // column is zero at positions up to l, the broadcast row past column l
+  for_each_slot([&](auto slot) {
+  constexpr int JL = decltype(slot)::value;
+  for (int ll = 0; ll < kTC; ++ll) {
+    const int l = kTC * JL + ll;
+    if (l >= s) break;
     const int q = l & 1;
-    with_slot(l, [&](auto slot) {
-      constexpr int JL = decltype(slot)::value;
-      if (tc + kTC * JL == l) {
+    if (tc + kTC * JL == l) {
 #pragma unroll
-        for (int i = 0; i < kRI; ++i) {
-          const int r = tr + kTR * i;
-          if (r < nr) {
-            if (r > l) lcol[q][r] = v[i][JL];
-            v[i][JL] = make_double2(r == l ? 1.0 : 0.0, 0.0);
-          }
-        }
+      for (int i = 0; i < kRI; ++i) {
+        const int r = tr + kTR * i;
+        double2 x = zero;
+        if (pos[i] > l && pos[i] < nr) x = v[i][JL];
+        lcol[q][r] = x;
+        v[i][JL] = make_double2(pos[i] == l ? 1.0 : 0.0, 0.0);
       }
-    });
+    }
 #pragma unroll
     for (int i = 0; i < kRI; ++i)
-      if (tr + kTR * i == l)
+      if (pos[i] == l)
 #pragma unroll
         for (int j = 0; j < kCJ; ++j) {
-          const int cc = tc + kTC * j;
-          if (cc <= l) grow[q][cc] = v[i][j];
+          double2 x = v[i][j];
+          if (tc + kTC * j > l) x = zero;
+          grow[q][tc + kTC * j] = x;
         }
     __syncthreads();
     double2 gv[kCJ], lv[kRI];
@@ -423,17 +439,11 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
 #pragma unroll
     for (int i = 0; i < kRI; ++i) lv[i] = lcol[q][tr + kTR * i];
 #pragma unroll
-    for (int i = 0; i < kRI; ++i) {
-      const int r = tr + kTR * i;
-      if (r > l && r < nr) {
+    for (int i = 0; i < kRI; ++i)
 #pragma unroll
-        for (int j = 0; j < kCJ; ++j) {
-          const int cc = tc + kTC * j;
-          if (cc <= l) v[i][j] = csub(v[i][j], cmul(lv[i], gv[j]));
-        }
-      }
-    }
+      for (int j = 0; j < kCJ; ++j) v[i][j] = csub(v[i][j], cmul(lv[i], gv[j]));
   }
+  });
 
   // G to its fragment order; padding rows and columns are zero
   if (sp != s) {
@@ -444,9 +454,9 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
   for (int i = 0; i < kRI; ++i)
 #pragma unroll
     for (int j = 0; j < kCJ; ++j) {
-      const int r = tr + kTR * i, c = tc + kTC * j;
-      if (r < nr && c < s) {
-        const int gr = r < s ? r : sp + (r - s);
+      const int p = pos[i], c = tc + kTC * j;
+      if (p < nr && c < s) {
+        const int gr = p < s ? p : sp + (p - s);
         const int64_t off = ((int64_t)(gr / 16) * nks + c / 4) * 64 + (gr % 16) + 16 * (c % 4);
         Gs[off] = v[i][j].x;
         Gs[gim + off] = v[i][j].y;
