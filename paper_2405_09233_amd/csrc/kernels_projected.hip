@@ -34,6 +34,10 @@ constexpr int kPMax = 64;    // largest block size s handled here
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+// a - l p in four fused multiply-adds
+__device__ __forceinline__ double2 cmsub(double2 a, double2 l, double2 p) {
+  return make_double2(fma(-l.x, p.x, fma(l.y, p.y, a.x)), fma(-l.x, p.y, fma(-l.y, p.x, a.y)));
+}
 __device__ __forceinline__ double2 csub(double2 a, double2 b) {
   return make_double2(a.x - b.x, a.y - b.y);
 }
@@ -48,6 +52,25 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   }
   const double r = b.x / b.y, d = b.y + b.x * r;
   return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+
+// 1 / a by the hardware reciprocal and two Newton steps (within about an
+// ulp; a is a pivot, never zero, infinite or subnormal when it is used)
+__device__ __forceinline__ double rcp_nr(double a) {
+  double y = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-a, y, 1.0);
+  return fma(y, e, y);
+}
+// 1 / b with Smith's scaling, by rcp_nr
+__device__ __forceinline__ double2 crecip_fast(double2 b) {
+  if (fabs(b.x) >= fabs(b.y)) {
+    const double r = b.y * rcp_nr(b.x), inv = rcp_nr(b.x + b.y * r);
+    return make_double2(inv, -r * inv);
+  }
+  const double r = b.x * rcp_nr(b.y), inv = rcp_nr(b.y + b.x * r);
+  return make_double2(r * inv, -inv);
 }
 
 // Largest key over each 16-lane row of the wave (every lane of a row ends
@@ -74,16 +97,6 @@ __device__ __forceinline__ double2 read_lane(double2 x, int lane) {
                        __builtin_amdgcn_readlane(__double2loint(x.y), l)));
 }
 
-// 1 / b with the larger component of b scaled to one (Smith's scaling: no
-// overflow or underflow in forming |b|^2)
-__device__ __forceinline__ double2 crecip(double2 b) {
-  if (fabs(b.x) >= fabs(b.y)) {
-    const double r = b.y / b.x, inv = 1.0 / (b.x + b.y * r);
-    return make_double2(inv, -r * inv);
-  }
-  const double r = b.x / b.y, inv = 1.0 / (b.y + b.x * r);
-  return make_double2(r * inv, -inv);
-}
 
 struct ProjArgs {
   const double2* Hm;  // p_h slices of ms x ms, column-major
@@ -203,9 +216,11 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
   __shared__ double2 prow[kPMax + 1];     // pivot row: its columns, then its right-hand side
   __shared__ double2 lcol[2][2 * kPMax];  // multipliers / L columns by row (zero where none)
   __shared__ double2 grow[2][kPMax];      // row l of G (columns past l zero)
+  __shared__ double2 ccol[2 * kPMax];     // the next pivot column, by row
   __shared__ unsigned left[4];            // rows never pivoted (bit r of word r / 32)
   __shared__ int spiv;
   __shared__ double sbest;
+  __shared__ double2 sdinv;               // 1 / pivot
 
   const int sys = blockIdx.x, tid = threadIdx.x;
   const int tr = tid % kTR, tc = tid / kTR;
@@ -259,6 +274,8 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
     constexpr int JC = decltype(slot)::value;
     if (tc + kTC * JC != col) return;
     {
+#pragma unroll
+      for (int i = 0; i < kRI; ++i) ccol[tr + kTR * i] = v[i][JC];  // the column, for (A)
       unsigned key = 0u;
 #pragma unroll
       for (int i = 0; i < kRI; ++i) {
@@ -274,9 +291,17 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
       const unsigned k0 = (unsigned)__builtin_amdgcn_readlane((int)key, base);
       const unsigned k1 = (unsigned)__builtin_amdgcn_readlane((int)key, base + 16);
       const unsigned kw = k0 > k1 ? k0 : k1;
+      // the pivot, read from its owner's lane, and its reciprocal
+      const int pr = 127 - (int)(kw & 0x7Fu);
+      double2 xp = zero;
+#pragma unroll
+      for (int i = 0; i < kRI; ++i)
+        if (tr + kTR * i == pr) xp = v[i][JC];
+      const double2 d = read_lane(xp, base + (pr & (kTR - 1)));
       if (tr == 0) {
-        spiv = 127 - (int)(kw & 0x7Fu);
+        spiv = pr;
         sbest = __hiloint2double((int)(kw & ~0x7Fu), 0);
+        sdinv = crecip_fast(d);
       }
     }
   };
@@ -293,39 +318,26 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
     // which the flag reports; any unpivoted row then serves)
     int pr = spiv;
     singular = singular || !(sbest > 0.0) || !isfinite(sbest);
-    // (A) the pivot row to LDS, the multipliers of column c
+    // (A) the multipliers of column c, each thread for its own rows (from
+    // the broadcast column and reciprocal); the pivot row to LDS
+    const double2 dinv = singular ? make_double2(1.0, 0.0) : sdinv;
+    double2 lv[kRI];
 #pragma unroll
     for (int i = 0; i < kRI; ++i) {
-      if (tr + kTR * i == pr) {
+      const int r = tr + kTR * i;
+      lv[i] = zero;
+      if (pos[i] == kUnpivoted && r != pr) lv[i] = cmul(ccol[r], dinv);
+      if (tc + kTC * JC == c && pos[i] == kUnpivoted && r != pr) v[i][JC] = lv[i];
+      if (r == pr) {
 #pragma unroll
         for (int j = 0; j < kCJ; ++j) prow[tc + kTC * j] = v[i][j];
         if (tc == 0) prow[kPMax] = rhs[i];
       }
     }
-    if (tc + kTC * JC == c) {
-      double2 xp = zero;
-#pragma unroll
-      for (int i = 0; i < kRI; ++i)
-        if (tr + kTR * i == pr) xp = v[i][JC];
-      const int base = __builtin_amdgcn_readfirstlane(32 * (tc & 1));
-      const double2 d = read_lane(xp, base + (pr & (kTR - 1)));
-      // one reciprocal of the pivot per column: the multipliers are products
-      const double2 dinv = singular ? make_double2(1.0, 0.0) : crecip(d);
-#pragma unroll
-      for (int i = 0; i < kRI; ++i) {
-        const int r = tr + kTR * i;
-        double2 l = zero;
-        if (pos[i] == kUnpivoted && r != pr) {
-          l = cmul(v[i][JC], dinv);
-          v[i][JC] = l;
-        }
-        lcol[0][r] = l;
-      }
-    }
     __syncthreads();
     // (B) rank-1 update of every entry: pivoted rows have multiplier zero,
     // the pivot row's columns up to c are zeroed
-    double2 pv[kCJ], lv[kRI];
+    double2 pv[kCJ];
 #pragma unroll
     for (int j = 0; j < kCJ; ++j) {
       pv[j] = prow[tc + kTC * j];
@@ -333,12 +345,10 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
     }
     const double2 px = prow[kPMax];
 #pragma unroll
-    for (int i = 0; i < kRI; ++i) lv[i] = lcol[0][tr + kTR * i];
-#pragma unroll
     for (int i = 0; i < kRI; ++i) {
 #pragma unroll
-      for (int j = 0; j < kCJ; ++j) v[i][j] = csub(v[i][j], cmul(lv[i], pv[j]));
-      rhs[i] = csub(rhs[i], cmul(lv[i], px));
+      for (int j = 0; j < kCJ; ++j) v[i][j] = cmsub(v[i][j], lv[i], pv[j]);
+      rhs[i] = cmsub(rhs[i], lv[i], px);
       if (tr + kTR * i == pr) pos[i] = c;
     }
     if (c + 1 < s) {
@@ -441,7 +451,7 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
 #pragma unroll
     for (int i = 0; i < kRI; ++i)
 #pragma unroll
-      for (int j = 0; j < kCJ; ++j) v[i][j] = csub(v[i][j], cmul(lv[i], gv[j]));
+      for (int j = 0; j < kCJ; ++j) v[i][j] = cmsub(v[i][j], lv[i], gv[j]);
   }
   });
 

@@ -5,12 +5,15 @@ mu = 1e-3: the paper does not give mu, so Table 1 itself is not reproduced;
 these counts pin the qualitative ordering the table reports, TBAS ahead of
 tGMRES ahead of tFOM).  Calls only the oracle and the input generator.
 
-The restart count of TBAS(10) on this slowly converging case depends on
-rounding: the oracle's own count moves by tens of percent when C is
-perturbed by one unit in the last place.  The script therefore also records
-the oracle's counts for five such perturbations (C times 1 + 1e-15 xi, xi
-standard normal from numpy's default_rng(seed), seeds 1..5), and the GPU's
-count is compared against that spread.
+The restart count of TBAS(10) on this case is decided at the rounding
+level: its residual first grows (to about 2e3 by cycle 100) and then falls
+along a path that rounding changes, so the oracle's own count moves by
+tens of percent when C is perturbed by one unit in the last place, while
+the first 100 cycles agree to four digits.  The script records the
+oracle's counts for five such perturbations (C times 1 + 1e-15 xi, xi
+standard normal from numpy's default_rng(seed), seeds 1..5) and the
+unperturbed run's residual estimates of the first 100 cycles, which are
+what the GPU test holds its own to.
 
     python tests/golden/make_ex3_counts.py      (about five minutes, 5 processes)
 """
@@ -29,6 +32,7 @@ from paper_2405_09233_amd import workloads  # noqa: E402
 N, S, P, MU, M, TOL = 1000, 3, 2, 1e-3, 10, 1e-6
 GMRES_CYCLES, FOM_CYCLES = 100, 20
 PERTURB_EPS, PERTURB_SEEDS = 1e-15, (1, 2, 3, 4, 5)
+HIST_CYCLES = 100
 
 
 def _tbas_cycles(seed):
@@ -62,6 +66,7 @@ def main():
                 "experiment are not given)",
         "tbas": {"cycles": it["cycles"], "converged": it["converged"],
                  "relres_true": it["relres_true"],
+                 "est_hist_first": [float(x) for x in it["est_hist"][:HIST_CYCLES]],
                  "perturbed": {"eps": PERTURB_EPS, "seeds": list(PERTURB_SEEDS),
                                "cycles": [q["cycles"] for q in perturbed],
                                "converged": [bool(q["converged"]) for q in perturbed]}},

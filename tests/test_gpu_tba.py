@@ -149,12 +149,13 @@ def test_ex3_ordering_matches_the_oracle():
     """The paper's convection-diffusion experiment family (section 6; n =
     1000, s = 3, p = 2, mu = 1e-3 -- the paper does not give mu), against the
     oracle's counts in tests/golden/ex3_counts.json (written by
-    make_ex3_counts.py from the oracle alone): TBAS(10) reaches 1e-6 in as
-    many restart cycles as the oracle's TBAS(10) takes on C perturbed at the
-    rounding level (the count of this slowly converging case moves by tens
-    of percent under a one-ulp change of C, so the bar is the range of the
-    oracle's counts, unperturbed and for five perturbations, widened by
-    15 %), tGMRES(10) stalls where
+    make_ex3_counts.py from the oracle alone): TBAS(10) follows the
+    oracle's TBAS(10) cycle by cycle over the first 100 cycles (the
+    residual estimate of the proposition of section 5.2, within 1e-6
+    relative to cycle 50 and 1e-3 to cycle 100, while the residual grows to
+    about 2e3) and then reaches 1e-6 (the count itself is decided at the
+    rounding level: the oracle's moves between 312 and 467 cycles under
+    one-ulp changes of C, so it is not compared), tGMRES(10) stalls where
     the oracle's does (same residual after the same number of cycles), and
     tFOM(10) does worse than tGMRES(10) (the oracle's diverges or meets a
     singular projected system) -- the ordering TBAS < tGMRES < tFOM of the
@@ -168,13 +169,23 @@ def test_ex3_ordering_matches_the_oracle():
     A, B, C = workloads.ex3(1000, 3, 2, mu=1e-3)
     c = ctx()
     Ad, Bd, Cd = dev(A), dev(B), dev(C)
-    X, it = c.tba(Ad, Bd, Cd, m=10, tol=1e-6, max_cycles=1000)
-    say("  TBAS cycles", it.cycles, "oracle", gold["tbas"]["cycles"])
+    import ctypes
+    hist = (ctypes.c_double * 1000)()
+    o = tsylv.default_opts(tsylv.TBA, m=10, tol=1e-6, max_cycles=1000)
+    o.res_hist = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+    o.res_hist_cap = 1000
+    X, it = c.tba(Ad, Bd, Cd, opts=o)
+    say("  TBAS cycles", it.cycles, "oracle", gold["tbas"]["cycles"], "perturbed oracle",
+        gold["tbas"]["perturbed"]["cycles"])
     assert it.status == 0 and it.relres_true <= 1e-6, it.as_dict()
     assert gold["tbas"]["converged"] and all(gold["tbas"]["perturbed"]["converged"])
-    counts = [gold["tbas"]["cycles"]] + gold["tbas"]["perturbed"]["cycles"]
-    say("  oracle counts (unperturbed, perturbed)", counts)
-    assert 0.85 * min(counts) <= it.cycles <= 1.15 * max(counts)
+    ref = np.array(gold["tbas"]["est_hist_first"])
+    got = np.array(hist[:min(it.res_hist_len, len(ref))])
+    assert len(got) == len(ref), (len(got), len(ref))
+    dev_ = np.abs(got / ref - 1.0)
+    say("  estimate history vs oracle: max rel diff to cycle 50 %.2e, to 100 %.2e"
+        % (dev_[:50].max(), dev_.max()))
+    assert dev_[:50].max() <= 1e-6 and dev_.max() <= 1e-3
     R = C - host(c.apply(Ad, Bd, X))
     assert np.linalg.norm(R) / np.linalg.norm(C) <= 1.05e-6
     ng = gold["tgmres"]["cycles"]
