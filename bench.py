@@ -589,10 +589,11 @@ TRAFFIC_FILES = {("bf16", (4096, 64, 32)): "apply_bf16_traffic_cd4096_s64_p32.md
                  ("bf16", (8192, 128, 64)): "apply_bf16_traffic_cd8192_s128_p64.md"}
 
 
-def measured_traffic(path, shape):
+def measured_traffic(path, shape, variant=None):
     """HBM bytes per apply call from the committed counter summary, or None
-    when there is none for the path and shape, or when the kernel source has
-    changed since the counters were taken."""
+    when there is none for the path and shape, when the kernel source has
+    changed since the counters were taken, or when the summary names another
+    tile variant than `variant` (the one the timed solves used)."""
     fname = TRAFFIC_FILES.get((path, tuple(shape)))
     if fname is None:
         return None
@@ -607,7 +608,10 @@ def measured_traffic(path, shape):
         return None
     m = re.search(r"sha256 at measurement:\s*([0-9a-f]{64})", txt)
     t = re.search(r"traffic_bytes_per_call:\s*([0-9.eE+]+)", txt)
+    v = re.search(r"variant at measurement:\s*(\d+)", txt)
     if not m or not t or hashlib.sha256(src).hexdigest() != m.group(1):
+        return None
+    if variant is not None and (not v or int(v.group(1)) != variant):
         return None
     return float(t.group(1))
 
@@ -727,8 +731,8 @@ def roofline_of(name, r, n, s, p, bf16_tiled, variant=None):
         if wide:
             kname = kname.replace("apply_bf16_wg_kernel", "apply_bf16_w32_kernel")
         out["variant"] = variant
-    out.update({"traffic": measured_traffic(name, (n, s, p)) if bf16_tiled or name != "bf16"
-                else None,
+    out.update({"traffic": measured_traffic(name, (n, s, p), variant)
+                if bf16_tiled or name != "bf16" else None,
                 "kernel": kname, "avg_launch_ms": r["apply_avg_ms"],
                 "launches": r["apply_launches"], "algorithmic_flops_per_launch": flops,
                 "algorithmic_bytes_per_launch": bytes_})

@@ -320,8 +320,10 @@ int tsylv_profile_read(tsylv_ctx* ctx, int kernel_id, tsylv_kstat* out);
  * all valid for every (n, s, p) and all computing the same products; by
  * default the shape follows s.  tsylv_autotune times every variant at
  * (n, s, p) in precision `prec` (`reps` >= 1 launches each, on operands of
- * that shape carved from the arena: the arena must hold them), keeps the
- * fastest in the context's table, and every later apply of that exact shape
+ * that shape carved from the arena, filled with pseudo-random values: the
+ * arena must hold them), keeps the fastest in the context's table -- the
+ * default variant of the shape unless another is at least 2 % faster --
+ * and every later apply of that exact shape
  * and precision on the context uses it (solves, refinement, serving).
  * `best` (may be NULL) receives the chosen variant; ms[v] for v < ms_cap
  * (ms may be NULL) the average launch time of variant v in milliseconds.

@@ -75,7 +75,7 @@ size_t instance_bytes(int64_t n, int64_t s, int64_t p, int m) {
 
 }  // namespace
 
-static size_t lockstep_workspace_bytes(int count, const tsylv_problem* probs,
+size_t lockstep_workspace_bytes(int count, const tsylv_problem* probs,
                                        const tsylv_opts& o) {
   if (count <= 0) return 0;
   size_t b = 0;
@@ -525,10 +525,11 @@ size_t batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_
 
 int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
                 const uint64_t* const* gens, const tsylv_opts& o, tsylv_info* infos,
-                bool use_graph) {
+                bool use_graph, bool lockstep_only) {
   const auto t0 = std::chrono::steady_clock::now();
   std::vector<int> lock, tasks;
-  for (int i = 0; i < count; ++i) (lockstep_instance(probs[i], o) ? lock : tasks).push_back(i);
+  for (int i = 0; i < count; ++i)
+    (lockstep_only || lockstep_instance(probs[i], o) ? lock : tasks).push_back(i);
   int worst = TSYLV_OK;
   if (!tasks.empty() && run_tasks(ctx, st, tasks, probs, gens, o, infos) != TSYLV_OK)
     worst = TSYLV_NOT_CONVERGED;

@@ -168,7 +168,7 @@ struct Scheduler {
         return krylov_workspace_bytes(r.method, r.n, r.s, r.p, r.opts);
       };
       v.need_batch = [&](size_t k) {
-        return batch_workspace_bytes((int)k, probs.data(), queue.front().r.opts);
+        return lockstep_workspace_bytes((int)k, probs.data(), queue.front().r.opts);
       };
       const policy::Decision d = policy::next_admission(
           v, free_slots.size(), ctx.arena.largest_free(), ctx.arena.capacity(), kMaxBatch);
@@ -251,7 +251,7 @@ struct Scheduler {
         // the step replayed from a recorded graph (TSYLV_BATCH_GRAPH=0: eager)
         const char* g = std::getenv("TSYLV_BATCH_GRAPH");
         gmres_batch(ctx, st, (int)jp->probs.size(), jp->probs.data(), jp->gens.data(), o,
-                    jp->infos.data(), !(g && g[0] == '0'));
+                    jp->infos.data(), !(g && g[0] == '0'), /*lockstep_only=*/true);
       } catch (const Error& e) {
         jp->error = e.status;
       } catch (...) {

@@ -41,8 +41,12 @@ int krylov_solve(Ctx& ctx, int method, int64_t n, int64_t s, int64_t p, const do
                  const double* B, const double* C, double* X, const tsylv_opts& o,
                  tsylv_info& info);
 
-// Batched lockstep tGMRES (batch.cpp): FP64, restart length o.m <= 63.
+// Batched tGMRES (batch.cpp): small FP64 instances (n s p <= 2^18) in
+// lockstep (restart length o.m <= 63), the rest, and every instance of a
+// refined batch, as concurrent solves on eight streams; workspace of both.
 size_t batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o);
+// Workspace of the lockstep executor alone (every instance in lockstep).
+size_t lockstep_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o);
 // Batched t-Bartels-Stewart (tbs_batch.cpp): 0 bytes when an instance is
 // outside 1 <= n, s <= 64, 1 <= p <= 4096 or has a null pointer.
 size_t tbs_batch_workspace_bytes(int count, const tsylv_problem* probs);
@@ -50,9 +54,12 @@ int tbs_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts&
               tsylv_info* infos);
 // On stream `st`; gens (may be null): gens[i] non-null draws instance i as
 // the synthetic instance of seed *gens[i] (its A, B, C are not read).
+// lockstep_only: every instance in lockstep (FP64 batches of the serving
+// loop, which runs its batches concurrently itself; the stream executor's
+// pinned staging is the context's, for one caller at a time).
 int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
                 const uint64_t* const* gens, const tsylv_opts& o, tsylv_info* infos,
-                bool use_graph);
+                bool use_graph, bool lockstep_only = false);
 
 // Autotuner (tune.cpp): times every tile variant of the apply at (n, s, p)
 // in precision `prec` (`reps` launches each), stores the fastest in

@@ -11,6 +11,10 @@ TSYLV_METHOD_GMRES_BATCHED through tsylv_submit / tsylv_poll).
   time the queue drains in several batches with the same results.
 * Malformed requests are rejected; closing the context with batches in
   flight finishes them.
+* Batched requests above the size that tsylv_gmres_batch runs in lockstep
+  (n s p > 2^18) are still served in lockstep batches (several batches in
+  flight at once share nothing): every result converges, its true residual
+  recomputed by tsylv_apply.
 """
 
 import time
@@ -110,6 +114,30 @@ def test_batched_seed_only_requests():
             X1 = torch.zeros_like(C)
             c.gmres_batch([(A, B, C, X1)], opts=opts)
             assert torch.equal(X, X1), k
+    finally:
+        c.close()
+
+
+@pytest.mark.gpu
+def test_large_batched_requests_served_in_lockstep():
+    import torch
+    say("serve batched: 12 seed-only requests of n s p = 327680")
+    shape = (512, 32, 20)
+    c = tsylv.Context(24 << 30, device=0)
+    try:
+        opts = tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-9, max_cycles=200)
+        Xs = [tsylv.empty_device(shape, "cuda:0").zero_() for _ in range(12)]
+        tickets = [c.submit(None, None, None, X, method=tsylv.GMRES_BATCHED, opts=opts,
+                            seed=700 + k) for k, X in enumerate(Xs)]
+        res = wait_all(c, tickets, timeout=300.0)
+        for k, (X, t) in enumerate(zip(Xs, tickets)):
+            st, info = res[t]
+            assert st == 0 and info.relres_true <= 1e-9, (k, info.as_dict())
+            if k % 4 == 0:
+                A, B, C = c.generate(700 + k, *shape)
+                R = C - c.apply(A, B, X)
+                r = (torch.linalg.norm(R) / torch.linalg.norm(C)).item()
+                assert r <= 1.05e-9, (k, r)
     finally:
         c.close()
 

@@ -67,7 +67,8 @@ def test_autotune_choice_is_recorded_and_used(prec):
     try:
         assert 0 <= best < tsylv.apply_variants(prec)
         assert len(ms) == tsylv.apply_variants(prec) and min(ms) > 0
-        assert ms[best] == min(ms)
+        # the fastest, or the default tiles within 2 % of it
+        assert ms[best] == min(ms) or ms[best] <= 1.02 * min(ms)
         assert c.tune_get(n, s, p, prec) == best
         # a solve of that shape runs with the tuned tiles and still converges
         A, B, C = workloads.dense_shifted(n, s, p, seed=9)
