@@ -28,15 +28,57 @@ class SingularProjected(Exception):
 
 
 # --------------------------------------------------------------------------
+# One modified Gram-Schmidt process for the three orthogonalisations
+# --------------------------------------------------------------------------
+
+def _gram_schmidt(count, basis, candidate, coef, remove, finish):
+    """Modified Gram-Schmidt over any space with an inner product.
+
+    Starting from `basis` (a list, extended in place), for j = 0, 1, ...,
+    count - 1: w = candidate(j, basis) is made orthogonal to the basis one
+    element at a time, in the order of the basis (c_i = coef(b_i, w), then
+    w = remove(w, b_i, c_i)), and finish(j, w, coefs) returns (unit, size,
+    stop): the new basis element (None when there is none), the coefficient
+    of w along it, and whether the process ends after column j.
+
+    The scalar Arnoldi process of section 3.1 (basis seeded with the
+    normalised start, candidate M of basis element j, real coefficients),
+    the tubal QR of section 5.1 (empty start, candidate the next lateral
+    slice, tube coefficients) and the tubal block Arnoldi process (seeded
+    with the first block, candidate A times block j, s x s x p tubal
+    coefficients) are this one process with different operations.
+
+    Returns the list of columns (coefs, size), one per completed j.
+    """
+    columns = []
+    for j in range(count):
+        w = candidate(j, basis)
+        coefs = []
+        for b in list(basis):
+            c = coef(b, w)
+            w = remove(w, b, c)
+            coefs.append(c)
+        unit, size, stop = finish(j, w, coefs)
+        columns.append((coefs, size))
+        if unit is not None:
+            basis.append(unit)
+        if stop:
+            break
+    return columns
+
+
+# --------------------------------------------------------------------------
 # Algorithm 2: tArnoldi
 # --------------------------------------------------------------------------
 
 def tarnoldi(Mop, V, m, on_step=None):
-    """Tensor tArnoldi (Algorithm 2) with modified Gram-Schmidt as printed.
+    """Tensor tArnoldi (Algorithm 2): the Arnoldi process of M with modified
+    Gram-Schmidt -- the Krylov basis V_1 = V / ||V||_F, V_2, ... and the
+    Hessenberg matrix of the coefficients.
 
-    Reading: the algorithm lists A as input but applies M (step 3(a)); M is
-    used.  A zero h_{j+1,j} is detected as h_{j+1,j} <= 16 eps ||M(V_j)||_F
-    (happy breakdown: the process stops with j columns).
+    Reading: the algorithm lists A as input but applies M; M is used.  A
+    zero h_{j+1,j} is detected as h_{j+1,j} <= 16 eps ||M(V_j)||_F (happy
+    breakdown: the process stops with j columns).
 
     ``on_step(j, H)`` (optional) is called after column j (0-based) of the
     Hessenberg matrix is complete and may return True to stop early.
@@ -45,28 +87,33 @@ def tarnoldi(Mop, V, m, on_step=None):
     breakdown), the (k+1) x k Hessenberg matrix, the images M(V_j), and k,
     the number of completed steps.
     """
-    beta = fnorm(V)
-    Vs = [V / beta]
+    Vs = [V / fnorm(V)]
     H = np.zeros((m + 1, m))
-    Ws = []
-    for j in range(m):
-        W = Mop(Vs[j])
+    Ws, wnorm0 = [], []
+
+    def candidate(j, basis):
+        W = Mop(basis[j])
         Ws.append(W.copy())
-        wnorm0 = fnorm(W)
-        for i in range(j + 1):
-            H[i, j] = inner(Vs[i], W)
-            W = W - H[i, j] * Vs[i]
+        wnorm0.append(fnorm(W))
+        return W
+
+    def finish(j, W, coefs):
+        H[:j + 1, j] = coefs
         H[j + 1, j] = fnorm(W)
-        stop = False
-        if H[j + 1, j] <= 16 * EPS * wnorm0:
+        unit, stop = None, False
+        if H[j + 1, j] <= 16 * EPS * wnorm0[j]:
             H[j + 1, j] = 0.0
             stop = True
         else:
-            Vs.append(W / H[j + 1, j])
+            unit = W / H[j + 1, j]
         if on_step is not None and on_step(j, H[:j + 2, :j + 1]):
             stop = True
-        if stop:
-            return Vs, H[:j + 2, :j + 1], Ws, j + 1
+        return unit, H[j + 1, j], stop
+
+    k = len(_gram_schmidt(m, Vs, candidate, lambda b, W: inner(b, W),
+                          lambda W, b, c: W - c * b, finish))
+    if k < m:
+        return Vs, H[:k + 1, :k], Ws, k
     return Vs, H, Ws, m
 
 
@@ -246,36 +293,41 @@ def normalization(W, breakdown_tol=16 * EPS):
 
 def tubal_qr(Amat):
     """Tubal-QR factorisation A = Q * R (Theorem and Algorithm 6 of
-    section 5.1) by tubal modified Gram-Schmidt.
+    section 5.1): modified Gram-Schmidt of the lateral slices A_1..A_s with
+    tube-valued coefficients r_ij = Q_i^T * A_j, each remainder split by
+    Normalization into Q_j and the tube r_jj.
 
-    Reading of the garbled loops: for j = 1..s, W = A_j; for i = 1..j-1,
-    r_ij = Q_i^T * W and W -= Q_i * r_ij; then [Q_j, r_jj] =
-    Normalization(W).  R[i, j, :] is the tube r_ij; R is upper triangular
-    in every frontal slice.
+    Reading of the garbled loops: the coefficients of slice j are taken
+    against Q_1..Q_{j-1} in order, each removed before the next is formed.
+    R[i, j, :] is the tube r_ij; R is upper triangular in every frontal
+    slice.
     """
     n, s, p = Amat.shape
-    Q = np.zeros((n, s, p))
     R = np.zeros((s, s, p))
-    for j in range(s):
-        W = Amat[:, j:j + 1, :].copy()
-        for i in range(j):
-            Qi = Q[:, i:i + 1, :]
-            rij = tprod(ttrans(Qi), W)                  # 1 x 1 x p
-            W = W - tprod(Qi, rij)
+
+    def finish(j, W, coefs):
+        for i, rij in enumerate(coefs):
             R[i, j, :] = rij.reshape(p)
         Qj, a = normalization(W)
-        Q[:, j:j + 1, :] = Qj
         R[j, j, :] = a
+        return Qj, a, False
+
+    Qs = []
+    _gram_schmidt(s, Qs, lambda j, basis: Amat[:, j:j + 1, :].copy(),
+                  lambda Qi, W: tprod(ttrans(Qi), W), lambda W, Qi, r: W - tprod(Qi, r),
+                  finish)
+    Q = np.concatenate(Qs, axis=1) if Qs else np.zeros((n, 0, p))
     return Q, R
 
 
 def tba(A, V, m):
-    """Tubal Block Arnoldi (Algorithm 7 of section 5.1).
+    """Tubal Block Arnoldi (Algorithm 7 of section 5.1): the block Arnoldi
+    process of A with tube-valued (s x s x p) coefficients H_ij = V_i^T * W
+    removed block by block (modified Gram-Schmidt), each remainder split by
+    Tubal-QR into the next block and H_{j+1,j}.
 
-    Reading: W = A * V_j uses A, not M (as printed; B enters only the
-    projected equation of TBAS).  Block modified Gram-Schmidt with
-    tube-valued coefficients H_ij = V_i^T * W, W -= V_i * H_ij, then
-    [V_{j+1}, H_{j+1,j}] = Tubal-QR(W).
+    Reading: W = A * V_j uses A, not M (B enters only the projected
+    equation of TBAS).
 
     Returns (Vb, Hbig, H0): the blocks V_1..V_{m+1} (each n x s x p), the
     block Hessenberg tensor of size (m+1)s x ms x p, and H0 from
@@ -283,17 +335,19 @@ def tba(A, V, m):
     """
     n, s, p = V.shape
     V1, H0 = tubal_qr(V)
-    Vb = [V1]
     Hbig = np.zeros(((m + 1) * s, m * s, p))
-    for j in range(m):
-        W = tprod(A, Vb[j])
-        for i in range(j + 1):
-            Hij = tprod(ttrans(Vb[i]), W)
-            W = W - tprod(Vb[i], Hij)
+
+    def finish(j, W, coefs):
+        for i, Hij in enumerate(coefs):
             Hbig[i * s:(i + 1) * s, j * s:(j + 1) * s, :] = Hij
         Vn, Hn = tubal_qr(W)
-        Vb.append(Vn)
         Hbig[(j + 1) * s:(j + 2) * s, j * s:(j + 1) * s, :] = Hn
+        return Vn, Hn, False
+
+    Vb = [V1]
+    _gram_schmidt(m, Vb, lambda j, basis: tprod(A, basis[j]),
+                  lambda Vi, W: tprod(ttrans(Vi), W), lambda W, Vi, H: W - tprod(Vi, H),
+                  finish)
     return Vb, Hbig, H0
 
 
