@@ -31,15 +31,6 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) b
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
-// a / b by Smith's scaling
-__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
-  if (fabs(b.x) >= fabs(b.y)) {
-    const double r = b.y / b.x, d = b.x + b.y * r;
-    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
-  }
-  const double r = b.x / b.y, d = b.y + b.x * r;
-  return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
-}
 
 __device__ __forceinline__ double2 pget(const double* P, int qr, int qi, int64_t plane,
                                         int64_t off) {
@@ -62,16 +53,15 @@ __global__ __launch_bounds__(kTB) void cholqr_pass_kernel(const double* __restri
                                                           double* __restrict__ Racc, int s, int p,
                                                           double shift_factor, int first,
                                                           double rel_tol, int* flag) {
-  __shared__ double2 R[kTMax * kTMax];   // Gram, then its Cholesky factor
-  __shared__ double2 Ri[kTMax * kTMax];  // R^{-1}, then the new Racc
-  __shared__ double sh[2];
-  __shared__ int bad;
+  __shared__ double2 R[kTMax * kTMax];  // Gram, then its Cholesky factor (upper part)
+  __shared__ double2 X[kTMax * kTMax];  // R^{-1}, then the previous Racc
+  __shared__ double rs[kTMax];          // the factor's diagonal
+  __shared__ double sh[1];
   const int k = blockIdx.x, t = threadIdx.x;
   int qr, qi;
   slice_planes(p, k, qr, qi);
   const int64_t ss = (int64_t)s * s;
   for (int e = t; e < s * s; e += kTB) R[e] = pget(G, qr, qi, ss, e);
-  if (t == 0) bad = 0;
   __syncthreads();
   if (t == 0) {
     double tr = 0.0, dmax = 0.0;
@@ -80,37 +70,29 @@ __global__ __launch_bounds__(kTB) void cholqr_pass_kernel(const double* __restri
       for (int i = 0; i < s; ++i) R[i + s * i].x += shift_factor * tr;
     for (int i = 0; i < s; ++i) dmax = fmax(dmax, R[i + s * i].x);
     sh[0] = dmax;
-    if (!(dmax > 0.0)) bad = 1;
   }
   __syncthreads();
   const double dmax = sh[0];
-  // right-looking Cholesky G = R^H R (R upper): row j of R, then the
-  // trailing update G(i, l) -= conj(R(j, i)) R(j, l), j < i <= l
+  // Right-looking Cholesky G = R^H R (R upper), one barrier per column: the
+  // pivot d_j = G(j, j) is read by every thread; the trailing entries lose
+  // conj(G(j, i)) G(j, l) / d_j with row j as it stands (unscaled), and the
+  // rows are scaled by 1 / sqrt(d_j) at the end (row j is not touched after
+  // step j).
+  bool bad = !(dmax > 0.0);
   for (int j = 0; j < s && !bad; ++j) {
-    if (t == 0) {
-      const double d = R[j + s * j].x;
-      if (!(d > rel_tol * dmax)) {
-        bad = 1;
-      } else {
-        sh[1] = sqrt(d);
-        R[j + s * j] = make_double2(sh[1], 0.0);
-      }
+    const double d = R[j + s * j].x;
+    if (!(d > rel_tol * dmax)) {
+      bad = true;
+      break;
     }
-    __syncthreads();
-    if (bad) break;
-    const double rjj = sh[1];
-    for (int l = j + 1 + t; l < s; l += kTB) {
-      const double2 v = R[j + s * l];
-      R[j + s * l] = make_double2(v.x / rjj, v.y / rjj);
-    }
-    __syncthreads();
+    const double dinv = 1.0 / d;
     const int w = s - j - 1;
     for (int e = t; e < w * w; e += kTB) {
       const int i = j + 1 + e % w, l = j + 1 + e / w;
       if (i > l) continue;
       const double2 u = cconjmul(R[j + s * i], R[j + s * l]);
-      R[i + s * l].x -= u.x;
-      R[i + s * l].y -= u.y;
+      R[i + s * l].x -= u.x * dinv;
+      R[i + s * l].y -= u.y * dinv;
     }
     __syncthreads();
   }
@@ -118,27 +100,49 @@ __global__ __launch_bounds__(kTB) void cholqr_pass_kernel(const double* __restri
     if (t == 0) atomicOr(flag, 1);
     return;
   }
-  // R^{-1} by back substitution, one column per thread
-  for (int j = t; j < s; j += kTB) {
-    for (int i = j + 1; i < s; ++i) Ri[i + s * j] = make_double2(0.0, 0.0);
-    Ri[j + s * j] = cdiv(make_double2(1.0, 0.0), R[j + s * j]);
-    for (int i = j - 1; i >= 0; --i) {
-      double2 acc = make_double2(0.0, 0.0);
-      for (int l = i + 1; l <= j; ++l) {
-        const double2 u = cmul(R[i + s * l], Ri[l + s * j]);
-        acc.x += u.x;
-        acc.y += u.y;
+  for (int i = t; i < s; i += kTB) rs[i] = sqrt(R[i + s * i].x);
+  __syncthreads();
+  for (int e = t; e < s * s; e += kTB) {
+    const int i = e % s, l = e / s;
+    if (i < l) {
+      const double2 v = R[e];
+      R[e] = make_double2(v.x / rs[i], v.y / rs[i]);
+    } else if (i == l) {
+      R[e] = make_double2(rs[i], 0.0);
+    }
+  }
+  __syncthreads();
+  // R^{-1} = X column by column, by back substitution: column j belongs to
+  // the four adjacent lanes 4 j .. 4 j + 3 of one wave (lane g takes the rows
+  // i = g mod 4), so each column is finished inside its wave in program
+  // order, with no barrier: for kk = j .. 0, x_kk = X(kk, j) / R(kk, kk),
+  // then X(i, j) -= R(i, kk) x_kk for i < kk.
+  {
+    const int j = t >> 2, g = t & 3;
+    if (j < s) {
+      for (int i = g; i < s; i += 4) X[i + s * j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+      for (int kk = j; kk >= 0; --kk) {
+        const double2 xc = X[kk + s * j];
+        const double2 xk = make_double2(xc.x / rs[kk], xc.y / rs[kk]);
+        if (g == 0) X[kk + s * j] = xk;
+        for (int i = g; i < kk; i += 4) {
+          const double2 u = cmul(R[i + s * kk], xk);
+          X[i + s * j].x -= u.x;
+          X[i + s * j].y -= u.y;
+        }
       }
-      Ri[i + s * j] = cdiv(make_double2(-acc.x, -acc.y), R[i + s * i]);
     }
   }
   __syncthreads();
   for (int e = t; e < s * s; e += kTB) {
     const int i = e % s, j = e / s;
-    pput(Rinv, qr, qi, ss, e, i <= j ? Ri[e] : make_double2(0.0, 0.0));
+    pput(Rinv, qr, qi, ss, e, i <= j ? X[e] : make_double2(0.0, 0.0));
   }
   __syncthreads();
-  // Racc <- R Racc (both upper triangular): into Ri, then out
+  // Racc <- R Racc (both upper triangular), the previous Racc staged in X
+  if (!first)
+    for (int e = t; e < s * s; e += kTB) X[e] = pget(Racc, qr, qi, ss, e);
+  __syncthreads();
   for (int e = t; e < s * s; e += kTB) {
     const int i = e % s, j = e / s;
     double2 acc = make_double2(0.0, 0.0);
@@ -147,16 +151,14 @@ __global__ __launch_bounds__(kTB) void cholqr_pass_kernel(const double* __restri
         acc = R[e];
       } else {
         for (int l = i; l <= j; ++l) {
-          const double2 u = cmul(R[i + s * l], pget(Racc, qr, qi, ss, l + (int64_t)s * j));
+          const double2 u = cmul(R[i + s * l], X[l + s * j]);
           acc.x += u.x;
           acc.y += u.y;
         }
       }
     }
-    Ri[e] = acc;
+    pput(Racc, qr, qi, ss, e, acc);
   }
-  __syncthreads();
-  for (int e = t; e < s * s; e += kTB) pput(Racc, qr, qi, ss, e, Ri[e]);
 }
 
 // The Normalization's tube test on the diagonal of the accumulated R: tube
@@ -229,51 +231,86 @@ __global__ void proj_rhs_kernel(const double* __restrict__ H0, const double2* __
   }
 }
 
-// Y_k = Z_k Winv_k (ms x s per slice; column j of Z_k is system k s + j of
-// z) into the planar layout of the basis update (real slices keep the real
-// part), and est[k] = || Hlast_k Y_k(rows (m-1) s ..) ||_F^2 (zero where
-// `last_zero` says the last QR broke down).
-__global__ void proj_y_kernel(const double2* __restrict__ z, const double2* __restrict__ Winv,
-                              const double2* __restrict__ Hlast, double* __restrict__ Y,
-                              double* __restrict__ est, int s, int m, int p) {
-  __shared__ double2 Yl[kTMax * kTMax];  // the last row block of Y_k
-  __shared__ double red[kTB];
-  const int k = blockIdx.x;
+// Y_k = Z_k W_k^{-1} for the rows of one 64-row chunk of one slice (grid:
+// slices x chunks), W_k^{-1} staged in LDS; thread t takes row t % 64 of
+// the chunk and the columns t / 64 + 4 q.
+constexpr int kYRows = 64;
+__global__ __launch_bounds__(256) void proj_y_kernel(const double2* __restrict__ z,
+                                                     const double2* __restrict__ Winv,
+                                                     double* __restrict__ Y, int s, int m, int p) {
+  __shared__ double2 Wl[kTMax * kTMax];
+  const int k = blockIdx.y, t = threadIdx.x;
   int qr, qi;
   slice_planes(p, k, qr, qi);
   const int ms = m * s;
   const int64_t ss = (int64_t)s * s, yplane = (int64_t)ms * s;
+  for (int e = t; e < s * s; e += 256) Wl[e] = Winv[k * ss + e];
+  __syncthreads();
+  const int r = blockIdx.x * kYRows + (t % kYRows);
+  if (r >= ms) return;
   const double2* Z = z + (int64_t)k * s * ms;
-  for (int e = threadIdx.x; e < ms * s; e += blockDim.x) {
-    const int r = e % ms, c = e / ms;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int l = 0; l < s; ++l) {
-      const double2 u = cmul(Z[(int64_t)l * ms + r], Winv[k * ss + l + s * c]);
-      acc.x += u.x;
-      acc.y += u.y;
+  constexpr int kCols = kTMax / 4;
+  double2 acc[kCols];
+#pragma unroll
+  for (int q = 0; q < kCols; ++q) acc[q] = make_double2(0.0, 0.0);
+  const int c0 = t / kYRows;
+  for (int l = 0; l < s; ++l) {
+    const double2 zv = Z[(int64_t)l * ms + r];
+#pragma unroll
+    for (int q = 0; q < kCols; ++q) {
+      const int c = c0 + 4 * q;
+      if (c < s) {
+        const double2 u = cmul(zv, Wl[l + s * c]);
+        acc[q].x += u.x;
+        acc[q].y += u.y;
+      }
     }
-    pput(Y, qr, qi, yplane, e, acc);
-    if (r >= ms - s) Yl[(r - (ms - s)) + s * c] = qi < 0 ? make_double2(acc.x, 0.0) : acc;
+  }
+#pragma unroll
+  for (int q = 0; q < kCols; ++q) {
+    const int c = c0 + 4 * q;
+    if (c < s) pput(Y, qr, qi, yplane, r + (int64_t)ms * c, acc[q]);
+  }
+}
+
+// The estimate of the proposition of section 5.2 for slice blockIdx.x:
+// est[k] = ||Hlast_k Y_k(last s rows, :)||_F^2 (real slices: the real part).
+__global__ __launch_bounds__(kTB) void proj_est_kernel(const double* __restrict__ Y,
+                                                       const double2* __restrict__ Hlast,
+                                                       double* __restrict__ est, int s, int m,
+                                                       int p) {
+  __shared__ double2 Hl[kTMax * kTMax];
+  __shared__ double2 Yl[kTMax * kTMax];
+  __shared__ double red[kTB];
+  const int k = blockIdx.x, t = threadIdx.x;
+  int qr, qi;
+  slice_planes(p, k, qr, qi);
+  const int ms = m * s;
+  const int64_t ss = (int64_t)s * s, yplane = (int64_t)ms * s;
+  for (int e = t; e < s * s; e += kTB) {
+    const int r = e % s, c = e / s;
+    Hl[e] = Hlast[k * ss + e];
+    Yl[e] = pget(Y, qr, qi, yplane, (ms - s + r) + (int64_t)ms * c);
   }
   __syncthreads();
   double part = 0.0;
-  for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
+  for (int e = t; e < s * s; e += kTB) {
     const int r = e % s, c = e / s;
     double2 v = make_double2(0.0, 0.0);
     for (int l = 0; l < s; ++l) {
-      const double2 u = cmul(Hlast[k * ss + r + s * l], Yl[l + s * c]);
+      const double2 u = cmul(Hl[r + s * l], Yl[l + s * c]);
       v.x += u.x;
       v.y += u.y;
     }
     part += qi < 0 ? v.x * v.x : v.x * v.x + v.y * v.y;
   }
-  red[threadIdx.x] = part;
+  red[t] = part;
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w /= 2) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+  for (int w = kTB / 2; w > 0; w /= 2) {
+    if (t < w) red[t] += red[t + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) est[k] = red[0];
+  if (t == 0) est[k] = red[0];
 }
 
 // flag[1] <- 1 when a projected system had a zero pivot or a non-finite
@@ -326,9 +363,13 @@ void proj_rhs(const double* H0, const double* W, double* D, int s, int p, hipStr
 void proj_y(const double* z, const double* Winv, const double* Hlast, double* Y, double* est,
             int s, int m, int p, hipStream_t st) {
   if (s < 1 || s > kTMax) throw Error(TSYLV_EINVAL, "proj_y: block too large");
-  hipLaunchKernelGGL(proj_y_kernel, dim3(num_slices(p)), dim3(kTB), 0, st,
+  const int chunks = (m * s + kYRows - 1) / kYRows;
+  hipLaunchKernelGGL(proj_y_kernel, dim3(chunks, num_slices(p)), dim3(256), 0, st,
                      reinterpret_cast<const double2*>(z), reinterpret_cast<const double2*>(Winv),
-                     reinterpret_cast<const double2*>(Hlast), Y, est, s, m, p);
+                     Y, s, m, p);
+  TSYLV_LAUNCH_CHECK();
+  hipLaunchKernelGGL(proj_est_kernel, dim3(num_slices(p)), dim3(kTB), 0, st, Y,
+                     reinterpret_cast<const double2*>(Hlast), est, s, m, p);
   TSYLV_LAUNCH_CHECK();
 }
 
