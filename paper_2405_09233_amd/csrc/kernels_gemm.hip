@@ -57,15 +57,15 @@ __device__ __forceinline__ int xcd_tile(int b, int total) {
   return x * q + (x < r ? x : r) + b / 8;
 }
 
-template <int TM, int TN, int RB, int CB, bool CPLX, bool CONJA>
+template <int TM, int TN, int RB, int CB, bool CPLX, bool CONJA, int NTH>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int k, int mt, int nt, int split,
                                           double (*As)[TK][TM + 1], double (*Bs)[TK][TN + 1]) {
   constexpr int WR = TM / (16 * RB);
   constexpr int WC = TN / (16 * CB);
-  static_assert(WR * WC == NT / 64, "4 waves");
-  constexpr int NA = TM * TK / NT;
-  constexpr int NB = TK * TN / NT;
-  static_assert(NA * NT == TM * TK && NB * NT == TK * TN, "panel split");
+  static_assert(WR * WC == NTH / 64, "one wave per RB x CB block group");
+  constexpr int NA = TM * TK / NTH;
+  constexpr int NB = TK * TN / NTH;
+  static_assert(NA * NTH == TM * TK && NB * NTH == TK * TN, "panel split");
 
   int qr, qi;
   slice_planes(g.p, k, qr, qi);
@@ -89,7 +89,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int k, int mt, int 
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      const int idx = tid + NT * u;
+      const int idx = tid + NTH * u;
       // op(A)(m, kk): contiguous along kk for the conjugate transpose, along m otherwise
       const int m = CONJA ? idx / TK : idx % TM;
       const int kk = CONJA ? idx % TK : idx / TM;
@@ -108,7 +108,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int k, int mt, int 
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int idx = tid + NT * u;
+      const int idx = tid + NTH * u;
       const int kk = idx % TK, c = idx / TK;
       const int64_t gk = k0 + kk, gc = c0 + c;
       double vr = 0.0, vi = 0.0;
@@ -124,7 +124,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int k, int mt, int 
   auto store = [&]() {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      const int idx = tid + NT * u;
+      const int idx = tid + NTH * u;
       const int m = CONJA ? idx / TK : idx % TM;
       const int kk = CONJA ? idx % TK : idx / TM;
       As[0][kk][m] = pa_r[u];
@@ -132,7 +132,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int k, int mt, int 
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
-      const int idx = tid + NT * u;
+      const int idx = tid + NTH * u;
       const int kk = idx % TK, c = idx / TK;
       Bs[0][kk][c] = pb_r[u];
       if (CPLX) Bs[1][kk][c] = pb_i[u];
@@ -215,8 +215,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int k, int mt, int 
     }
 }
 
-template <int TM, int TN, int RB, int CB, bool CONJA>
-__global__ __launch_bounds__(NT) void zgemm_kernel(GemmArgs g) {
+template <int TM, int TN, int RB, int CB, bool CONJA, int NTH>
+__global__ __launch_bounds__(NTH) void zgemm_kernel(GemmArgs g) {
   __shared__ double As[2][TK][TM + 1];
   __shared__ double Bs[2][TK][TN + 1];
   const int t = xcd_tile(blockIdx.x, g.total);
@@ -226,9 +226,9 @@ __global__ __launch_bounds__(NT) void zgemm_kernel(GemmArgs g) {
   const int k = t / (g.nnt * g.nmt * g.ksplit);
   const bool real_slice = (k == 0) || (2 * k == g.p);
   if (real_slice)
-    gemm_tile<TM, TN, RB, CB, false, CONJA>(g, k, mt, nt, split, As, Bs);
+    gemm_tile<TM, TN, RB, CB, false, CONJA, NTH>(g, k, mt, nt, split, As, Bs);
   else
-    gemm_tile<TM, TN, RB, CB, true, CONJA>(g, k, mt, nt, split, As, Bs);
+    gemm_tile<TM, TN, RB, CB, true, CONJA, NTH>(g, k, mt, nt, split, As, Bs);
 }
 
 // C = alpha * sum_split partial + beta * C over all p planes (fixed order).
@@ -248,15 +248,17 @@ __global__ void splitk_reduce_kernel(const double* __restrict__ partial, int ksp
   }
 }
 
-template <int TM, int TN, int RB, int CB>
+template <int TM, int TN, int RB, int CB, int NTH = NT>
 void launch(GemmArgs g, hipStream_t st) {
   g.nmt = (int)((g.M + TM - 1) / TM);
   g.nnt = (int)((g.N + TN - 1) / TN);
   g.total = num_slices(g.p) * g.nmt * g.nnt * g.ksplit;
   if (g.conjA)
-    hipLaunchKernelGGL((zgemm_kernel<TM, TN, RB, CB, true>), dim3(g.total), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL((zgemm_kernel<TM, TN, RB, CB, true, NTH>), dim3(g.total), dim3(NTH), 0,
+                       st, g);
   else
-    hipLaunchKernelGGL((zgemm_kernel<TM, TN, RB, CB, false>), dim3(g.total), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL((zgemm_kernel<TM, TN, RB, CB, false, NTH>), dim3(g.total), dim3(NTH), 0,
+                       st, g);
   TSYLV_LAUNCH_CHECK();
 }
 
@@ -267,7 +269,7 @@ int64_t zgemm_partial_elems(int64_t M, int64_t N, int64_t K, int p) {
 }
 
 int zgemm_splits(int64_t M, int64_t N, int64_t K, int p) {
-  const int64_t tm = N <= 16 ? 128 : (N <= 32 ? 64 : 32);
+  const int64_t tm = N <= 16 ? 128 : 64;
   const int64_t tn = N <= 16 ? 16 : (N <= 32 ? 32 : 64);
   const int64_t tiles = num_slices(p) * ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
   int64_t split = (2048 + tiles - 1) / tiles;
@@ -302,8 +304,8 @@ void zgemm(const PMat& A, bool conjA, const PMat& B, double* C, int64_t planeC, 
     launch<128, 16, 2, 1>(g, st);
   else if (N <= 32)
     launch<64, 32, 1, 2>(g, st);
-  else
-    launch<32, 64, 1, 2>(g, st);
+  else  // 64 x 64 tiles of 8 waves (16 x 32 each): twice the products per loaded byte
+    launch<64, 64, 1, 2, 512>(g, st);
   if (g.ksplit > 1) {
     const int64_t tot = (int64_t)p * M * N;
     int blocks = (int)std::min<int64_t>((tot + 255) / 256, 4096);
