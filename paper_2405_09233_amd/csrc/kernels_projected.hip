@@ -44,16 +44,6 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) {
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
   return make_double2(a.x + b.x, a.y + b.y);
 }
-// a / b by Smith's scaling (no overflow for |b| near the range limits)
-__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
-  if (fabs(b.x) >= fabs(b.y)) {
-    const double r = b.y / b.x, d = b.x + b.y * r;
-    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
-  }
-  const double r = b.x / b.y, d = b.y + b.x * r;
-  return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
-}
-
 // 1 / a by the hardware reciprocal and two Newton steps (within about an
 // ulp; a is a pivot, never zero, infinite or subnormal when it is used)
 __device__ __forceinline__ double rcp_nr(double a) {
@@ -330,16 +320,18 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
       if (tc + kTC * JC == c && pos[i] == kUnpivoted && r != pr) v[i][JC] = lv[i];
       if (r == pr) {
 #pragma unroll
-        for (int j = 0; j < kCJ; ++j) prow[tc + kTC * j] = v[i][j];
+        for (int j = JC; j < kCJ; ++j) prow[tc + kTC * j] = v[i][j];
         if (tc == 0) prow[kPMax] = rhs[i];
       }
     }
     __syncthreads();
     // (B) rank-1 update of every entry: pivoted rows have multiplier zero,
-    // the pivot row's columns up to c are zeroed
+    // the pivot row's columns up to c are zeroed.  The slots before JC hold
+    // only columns before c (zero in the broadcast row), so they are left
+    // as they are.
     double2 pv[kCJ];
 #pragma unroll
-    for (int j = 0; j < kCJ; ++j) {
+    for (int j = JC; j < kCJ; ++j) {
       pv[j] = prow[tc + kTC * j];
       if (tc + kTC * j <= c) pv[j] = zero;
     }
@@ -347,7 +339,7 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
 #pragma unroll
     for (int i = 0; i < kRI; ++i) {
 #pragma unroll
-      for (int j = 0; j < kCJ; ++j) v[i][j] = cmsub(v[i][j], lv[i], pv[j]);
+      for (int j = JC; j < kCJ; ++j) v[i][j] = cmsub(v[i][j], lv[i], pv[j]);
       rhs[i] = cmsub(rhs[i], lv[i], px);
       if (tr + kTR * i == pr) pos[i] = c;
     }
@@ -433,11 +425,13 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
         v[i][JL] = make_double2(pos[i] == l ? 1.0 : 0.0, 0.0);
       }
     }
+    // (the slots past JL hold only columns past l, zero in the broadcast
+    // row: they are neither sent nor updated)
 #pragma unroll
     for (int i = 0; i < kRI; ++i)
       if (pos[i] == l)
 #pragma unroll
-        for (int j = 0; j < kCJ; ++j) {
+        for (int j = 0; j <= JL; ++j) {
           double2 x = v[i][j];
           if (tc + kTC * j > l) x = zero;
           grow[q][tc + kTC * j] = x;
@@ -445,13 +439,13 @@ __global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
     __syncthreads();
     double2 gv[kCJ], lv[kRI];
 #pragma unroll
-    for (int j = 0; j < kCJ; ++j) gv[j] = grow[q][tc + kTC * j];
+    for (int j = 0; j <= JL; ++j) gv[j] = grow[q][tc + kTC * j];
 #pragma unroll
     for (int i = 0; i < kRI; ++i) lv[i] = lcol[q][tr + kTR * i];
 #pragma unroll
     for (int i = 0; i < kRI; ++i)
 #pragma unroll
-      for (int j = 0; j < kCJ; ++j) v[i][j] = cmsub(v[i][j], lv[i], gv[j]);
+      for (int j = 0; j <= JL; ++j) v[i][j] = cmsub(v[i][j], lv[i], gv[j]);
   }
   });
 
@@ -599,52 +593,68 @@ __global__ __launch_bounds__(kTB, 4) void proj_trail_kernel(ProjArgs a, int b, i
 }
 
 // Back substitution U z = y per system, row block by row block from the
-// bottom; z is kept in LDS (ms complex values).
+// bottom; z is kept in LDS (ms complex values).  Per row block: its product
+// with the solved part of z (every thread, eight column loads in flight),
+// the diagonal block's upper triangle staged in LDS by the same pass, then
+// the triangular solve by one wave, column by column: lane r holds row r's
+// remainder, at column q lane q's remainder times 1 / U(q, q) is z(q),
+// broadcast by a lane read, and the rows above subtract U(r, q) z(q).
+constexpr int kBU = 8;  // column loads in flight per thread
+
 __global__ __launch_bounds__(kPB) void proj_back_kernel(ProjArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  double2* zl = reinterpret_cast<double2*>(smem);      // ms
-  double2* part = zl + a.ms;                           // kPB
-  double2* t = part + kPB;                             // kPMax
+  double2* zl = reinterpret_cast<double2*>(smem);  // ms
+  double2* part = zl + a.ms;                       // kPB
+  double2* ud = part + kPB;                        // s (s + 1) / 2, column q at q (q + 1) / 2
   const int sys = blockIdx.x, tid = threadIdx.x;
   const int s = a.s, ms = a.ms, m = a.m;
+  const double2 zero = make_double2(0.0, 0.0);
   double2* zs = a.z + (int64_t)sys * ms;
   for (int i = tid; i < ms; i += kPB) zl[i] = zs[i];
   __syncthreads();
-  const int groups = kPB / s;  // threads per row of the mat-vec
+  const int groups = kPB / s;  // threads per row of the product
   for (int b = m - 1; b >= 0; --b) {
     const double2* Ub = a.U + (int64_t)sys * a.ustride + uoff(a, b);
-    const int c0 = (b + 1) * s;  // columns already solved
+    for (int e = tid; e < s * s; e += kPB) {
+      const int r = e % s, q = e / s;
+      if (r <= q) ud[q * (q + 1) / 2 + r] = Ub[e];
+    }
     if (tid < s * groups) {
       const int r = tid % s, g = tid / s;
-      double2 acc = make_double2(0.0, 0.0);
-      for (int c = c0 + g; c < ms; c += groups)
-        acc = cadd(acc, cmul(Ub[r + (int64_t)s * (c - b * s)], zl[c]));
-      part[tid] = acc;
-    }
-    __syncthreads();
-    if (tid < s) {
-      double2 acc = zl[b * s + tid];
-      for (int g = 0; g < groups; ++g) acc = csub(acc, part[tid + s * g]);
-      t[tid] = acc;
-    }
-    __syncthreads();
-    // triangular solve with the s x s diagonal block, one wave: lane q holds
-    // z(b s + q); row r's sum over the solved lanes q > r is a wave reduction
-    if (tid < 64) {
-      double2 zq = make_double2(0.0, 0.0);
-      for (int r = s - 1; r >= 0; --r) {
-        double2 acc = make_double2(0.0, 0.0);
-        if (tid > r && tid < s) acc = cmul(Ub[r + (int64_t)s * tid], zq);
-        for (int off = 32; off >= 1; off >>= 1) {
-          acc.x += __shfl_xor(acc.x, off, 64);
-          acc.y += __shfl_xor(acc.y, off, 64);
-        }
-        const double2 zr = cdiv(csub(t[r], acc), Ub[r + (int64_t)s * r]);
-        if (tid == r) zq = zr;
+      const double2* Ur = Ub + r - (int64_t)s * b * s;  // element (r, c) at Ur[s c]
+      double2 acc[kBU];
+#pragma unroll
+      for (int u = 0; u < kBU; ++u) acc[u] = zero;
+      int c = (b + 1) * s + g;
+      for (; c + (kBU - 1) * groups < ms; c += kBU * groups) {
+        double2 uv[kBU];
+#pragma unroll
+        for (int u = 0; u < kBU; ++u) uv[u] = Ur[(int64_t)s * (c + u * groups)];
+#pragma unroll
+        for (int u = 0; u < kBU; ++u) acc[u] = cmsub(acc[u], uv[u], zl[c + u * groups]);
       }
-      if (tid < s) zl[b * s + tid] = zq;
+      for (; c < ms; c += groups) acc[0] = cmsub(acc[0], Ur[(int64_t)s * c], zl[c]);
+#pragma unroll
+      for (int u = 1; u < kBU; ++u) acc[0] = cadd(acc[0], acc[u]);
+      part[tid] = acc[0];  // minus the row's sum
     }
     __syncthreads();
+    if (tid < 64) {
+      double2 rem = zero, dinv = zero, zr = zero;
+      if (tid < s) {
+        rem = zl[b * s + tid];
+        for (int g = 0; g < groups; ++g) rem = cadd(rem, part[tid + s * g]);
+        dinv = crecip_fast(ud[tid * (tid + 1) / 2 + tid]);
+      }
+      for (int q = s - 1; q >= 0; --q) {
+        const double2 w = cmul(rem, dinv);
+        const double2 zq = read_lane(w, q);
+        if (tid == q) zr = w;
+        if (tid < q) rem = cmsub(rem, ud[q * (q + 1) / 2 + tid], zq);
+      }
+      if (tid < s) zl[b * s + tid] = zr;
+    }
+    __syncthreads();  // z(b) written, the diagonal block and partials read
   }
   for (int i = tid; i < ms; i += kPB) zs[i] = zl[i];
 }
@@ -691,7 +701,7 @@ void proj_solve(const double* Hm, const double* lam, const double* D, double* z,
     hipLaunchKernelGGL(proj_trail_kernel, dim3((unsigned)total), dim3(kTB), 0, st, a, b, ntile);
     TSYLV_LAUNCH_CHECK();
   }
-  const size_t lds_back = sizeof(double2) * ((size_t)ms + kPB + kPMax);
+  const size_t lds_back = sizeof(double2) * ((size_t)ms + kPB + (size_t)s * (s + 1) / 2);
   if (lds_back > 160 * 1024) throw Error(TSYLV_EINVAL, "projected solve: ms too large");
   TSYLV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&proj_back_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_back));
