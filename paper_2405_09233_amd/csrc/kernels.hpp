@@ -282,6 +282,20 @@ void zgemm(const PMat& A, bool conjA, const PMat& B, double* C, int64_t planeC, 
            hipStream_t st);
 
 
+// ---- small instances: a whole restarted solve in one workgroup ----------
+// (kernels_tiny.hip)  tiny_krylov_fits: n s p, the operator planes, the
+// iterate and two basis vectors fit the workgroup's LDS (n s p <= 8192,
+// m <= 1024, m n s p <= 2^18).  tiny_krylov: restarted tGMRES(m) (fom = false) or tFOM(m) on
+// the Fourier planes Ah, Bh (p planes), Zc (C, orthonormal planes), with X
+// in Zx (X0 on entry when x0_given); basis: (m + 1) n s p doubles, Rg: m m
+// doubles, hist: hist_cap estimates (may be null); out receives the record
+// [status, steps, cycles, relres_true, relres_est, fom_fallback, hist_len].
+bool tiny_krylov_fits(int64_t n, int64_t s, int64_t p, int m);
+constexpr int kTinyRecord = 8;
+void tiny_krylov(const double* Ah, const double* Bh, const double* Zc, double* Zx, double* basis,
+                 double* Rg, double* hist, int hist_cap, double* out, int n, int s, int p, int m,
+                 int max_cycles, bool fom, bool x0_given, double tol, hipStream_t st);
+
 // ---- batched lockstep tGMRES (many independent instances per launch) ----
 //
 // Every launch serves all instances of a batch: blockIdx.x runs over the

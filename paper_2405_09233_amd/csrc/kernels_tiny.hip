@@ -1,0 +1,354 @@
+// Restarted tGMRES(m) and tFOM(m) (Algorithm 3) of one small instance in
+// one workgroup: the whole solve -- every restart cycle, every Arnoldi step
+// and the true residual after each cycle -- in a single launch.  For
+// instances of a few hundred to a few thousand unknowns a step of the
+// multi-launch driver is a handful of dependent launches and a host round
+// trip (tens of microseconds); here it is a handful of barriers.
+//
+// The process is the multi-launch driver's: vectors in the orthonormal
+// Fourier planes (M acts slice by slice as Ahat_k V_k - V_k Bhat_k, eq. (5)),
+// classical Gram-Schmidt with one reorthogonalisation, the breakdown test
+// h_{j+1,j} <= 16 eps ||M v_j||, progressive Givens QR of the Hessenberg
+// matrix with the tGMRES estimate |gamma_{j+1}| (section 3.3), the restart
+// test on the true residual C - M(X).  tFOM's y solves the square system
+// H_k y = beta e1 (section 3.2) through the same rotations: the first k-1 of
+// them make H_k upper triangular with the last diagonal entry and the last
+// right-hand side entry taken before the k-th rotation, so its estimate
+// h_{k+1,k} |y_k| needs no factorisation of its own.
+//
+// Storage: the iterate, the operator planes, the rotations and as many
+// basis vectors as fit in LDS; the other basis vectors and the rotated
+// Hessenberg columns in global memory (reached through flat pointers).
+// Sums over a vector are fixed-order (eight lanes per sum, a fixed tree):
+// runs are bitwise reproducible.
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace tsylv {
+namespace kern {
+
+namespace {
+
+constexpr int kYT = 256;           // threads of the workgroup
+constexpr int kYD = 8;             // lanes that share one dot product
+constexpr int kYS = kYT / kYD;     // dot products per pass
+constexpr int kYLds = 160 * 1024;  // LDS of one workgroup (bytes)
+constexpr int64_t kYMaxN = 8192;   // largest n s p handled here
+constexpr int kYMaxM = 1024;       // longest restart handled here
+constexpr int64_t kYMaxMN = 1 << 18;  // largest m n s p (bounds a cycle's basis work)
+constexpr int kYScal = 16;         // scalars exchanged through LDS
+
+struct TinyArgs {
+  const double* Ah;  // p planes of n x n (unscaled Fourier slices)
+  const double* Bh;  // p planes of s x s
+  const double* Zc;  // C in orthonormal planes (N)
+  double* Zx;        // X0 on entry when x0_given, X on exit (N)
+  double* Vg;        // (m + 1) N: the basis slots that do not fit in LDS
+  double* Rg;        // m x m: rotated Hessenberg columns (column j: j + 1 entries)
+  double* hist;      // hist_cap relative residual estimates
+  double* out;       // result record of kTinyRecord doubles
+  double tol;
+  int n, s, p, m, max_cycles, fom, x0_given, hist_cap, lslots;
+};
+
+// LDS doubles besides the basis slots: X, the operator planes, cs, sn, g,
+// two projections, the current column, the scalars.
+int64_t fixed_doubles(int64_t n, int64_t s, int64_t p, int m) {
+  return n * s * p + p * (n * n + s * s) + 6 * ((int64_t)m + 2) + kYScal;
+}
+
+// w = M(v) = Ahat v - v Bhat, slice by slice on the planes (slice 0 and,
+// for even p, slice p/2 real; slice k otherwise planes 2k-1 (Re), 2k (Im)).
+__device__ void tiny_apply(int n, int s, int p, const double* A, const double* B, const double* v,
+                           double* w) {
+  const int ns = n * s, ph = p / 2 + 1;
+  for (int it = threadIdx.x; it < ph * ns; it += kYT) {
+    const int k = it / ns, e = it % ns, i = e % n, c = e / n;
+    const bool real = k == 0 || 2 * k == p;
+    const int qr = k == 0 ? 0 : (real ? p - 1 : 2 * k - 1);
+    const double* Ar = A + (int64_t)qr * n * n;
+    const double* Br = B + (int64_t)qr * s * s;
+    const double* Vr = v + (int64_t)qr * ns;
+    if (real) {
+      double acc = 0.0;
+      for (int l = 0; l < n; ++l) acc = fma(Ar[i + n * l], Vr[l + n * c], acc);
+      for (int l = 0; l < s; ++l) acc = fma(-Vr[i + n * l], Br[l + s * c], acc);
+      w[(int64_t)qr * ns + e] = acc;
+    } else {
+      const double* Ai = Ar + n * n;
+      const double* Bi = Br + s * s;
+      const double* Vi = Vr + ns;
+      double re = 0.0, im = 0.0;
+      for (int l = 0; l < n; ++l) {
+        const double ar = Ar[i + n * l], ai = Ai[i + n * l];
+        const double vr = Vr[l + n * c], vi = Vi[l + n * c];
+        re = fma(ar, vr, re);
+        re = fma(-ai, vi, re);
+        im = fma(ar, vi, im);
+        im = fma(ai, vr, im);
+      }
+      for (int l = 0; l < s; ++l) {
+        const double vr = Vr[i + n * l], vi = Vi[i + n * l];
+        const double br = Br[l + s * c], bi = Bi[l + s * c];
+        re = fma(-vr, br, re);
+        re = fma(vi, bi, re);
+        im = fma(-vr, bi, im);
+        im = fma(-vi, br, im);
+      }
+      w[(int64_t)qr * ns + e] = re;
+      w[(int64_t)(qr + 1) * ns + e] = im;
+    }
+  }
+}
+
+// out[i] = x_i . y for i < cnt (x_i = vec(i)): kYD adjacent lanes per sum,
+// each over the elements of its residue class, then a fixed tree.
+template <typename Vec>
+__device__ void tiny_dots(Vec vec, int cnt, const double* y, int N, double* out) {
+  const int part = threadIdx.x % kYD, slot = threadIdx.x / kYD;
+  for (int i0 = 0; i0 < cnt; i0 += kYS) {
+    const int i = i0 + slot;
+    double acc = 0.0;
+    if (i < cnt) {
+      const double* x = vec(i);
+      for (int e = part; e < N; e += kYD) acc = fma(x[e], y[e], acc);
+    }
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 4);
+    if (part == 0 && i < cnt) out[i] = acc;
+  }
+}
+
+// w -= sum_{i < cnt} h_i x_i, in index order per element
+template <typename Vec>
+__device__ void tiny_sub(double* w, Vec vec, int cnt, const double* h, int N) {
+  for (int e = threadIdx.x; e < N; e += kYT) {
+    double acc = w[e];
+    for (int i = 0; i < cnt; ++i) acc = fma(-h[i], vec(i)[e], acc);
+    w[e] = acc;
+  }
+}
+
+// R y = r for the k x k upper triangular R (column l at R + m l), with the
+// last diagonal entry dlast and the last right-hand side entry rlast in
+// place of R's and r's; false on a zero diagonal (or, if `finite`, a
+// non-finite y).
+__device__ bool tiny_back(const double* R, int m, int k, const double* r, double dlast,
+                          double rlast, bool finite, double* y) {
+  for (int ii = k - 1; ii >= 0; --ii) {
+    double t = ii == k - 1 ? rlast : r[ii];
+    for (int l = ii + 1; l < k; ++l) t -= R[ii + (int64_t)m * l] * y[l];
+    const double d = ii == k - 1 ? dlast : R[ii + (int64_t)m * ii];
+    if (d == 0.0) return false;
+    y[ii] = t / d;
+    if (finite && !isfinite(y[ii])) return false;
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(kYT) void tiny_krylov_kernel(TinyArgs a) {
+  extern __shared__ double lds[];
+  const int t = threadIdx.x;
+  const int n = a.n, s = a.s, p = a.p, m = a.m, N = n * s * p;
+  double* X = lds;
+  double* A = X + N;
+  double* B = A + (int64_t)p * n * n;
+  double* cs = B + (int64_t)p * s * s;
+  double* sn = cs + (m + 2);
+  double* g = sn + (m + 2);
+  double* h1 = g + (m + 2);
+  double* h2 = h1 + (m + 2);  // second projection; y at the end of a cycle
+  double* col = h2 + (m + 2);
+  double* sc = col + (m + 2);
+  double* Vl = sc + kYScal;
+  auto slot = [&](int i) -> double* {
+    return i < a.lslots ? Vl + (int64_t)i * N : a.Vg + (int64_t)i * N;
+  };
+
+  for (int e = t; e < p * n * n; e += kYT) A[e] = a.Ah[e];
+  for (int e = t; e < p * s * s; e += kYT) B[e] = a.Bh[e];
+  for (int e = t; e < N; e += kYT) X[e] = a.x0_given ? a.Zx[e] : 0.0;
+  if (t < kYScal) sc[t] = 0.0;
+  __syncthreads();
+  tiny_dots([&](int) { return a.Zc; }, 1, a.Zc, N, sc);
+  __syncthreads();
+  const double cnorm = sqrt(sc[0]);
+  const double stop = a.tol * cnorm;
+
+  int status = TSYLV_NOT_CONVERGED, steps = 0, cycles = 0;
+  double rt = 0.0, est = 0.0;
+  bool any_est = false;
+  if (cnorm == 0.0) {
+    for (int e = t; e < N; e += kYT) X[e] = 0.0;
+    status = TSYLV_OK;
+  } else {
+    for (;;) {
+      // R = C - M(X) into slot 0 (Algorithm 3 step 3; C itself for X0 = 0)
+      double* R = slot(0);
+      if (cycles == 0 && !a.x0_given) {
+        for (int e = t; e < N; e += kYT) R[e] = a.Zc[e];
+      } else {
+        tiny_apply(n, s, p, A, B, X, R);
+        __syncthreads();
+        for (int e = t; e < N; e += kYT) R[e] = a.Zc[e] - R[e];
+      }
+      __syncthreads();
+      tiny_dots([&](int) { return R; }, 1, R, N, sc + 1);
+      __syncthreads();
+      const double beta = sqrt(sc[1]);
+      rt = beta / cnorm;
+      if (rt <= a.tol) {
+        status = TSYLV_OK;
+        break;
+      }
+      if (cycles >= a.max_cycles) break;
+      ++cycles;
+      const double ib = 1.0 / beta;
+      for (int e = t; e < N; e += kYT) R[e] *= ib;
+      if (t == 0) g[0] = beta;
+      __syncthreads();
+
+      // Arnoldi steps (Algorithm 2 step 3) with the Givens update
+      int k = 0;
+      for (int j = 0; j < m; ++j) {
+        double* W = slot(j + 1);
+        tiny_apply(n, s, p, A, B, slot(j), W);
+        __syncthreads();
+        tiny_dots(slot, j + 2, W, N, h1);  // h1[0..j] and ||W||^2 in h1[j + 1]
+        __syncthreads();
+        tiny_sub(W, slot, j + 1, h1, N);
+        __syncthreads();
+        tiny_dots(slot, j + 1, W, N, h2);
+        __syncthreads();
+        tiny_sub(W, slot, j + 1, h2, N);
+        __syncthreads();
+        tiny_dots([&](int) { return W; }, 1, W, N, sc + 2);
+        __syncthreads();
+        const double w0 = sqrt(h1[j + 1]);
+        double hn = sqrt(sc[2]);
+        const bool brk = !(hn > 16.0 * 2.220446049250313e-16 * w0);  // h_{j+1,j} = 0
+        if (brk) hn = 0.0;
+        ++steps;
+        if (t == 0) {
+          for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+          for (int i = 0; i < j; ++i) {
+            const double x = col[i], y = col[i + 1];
+            col[i] = cs[i] * x + sn[i] * y;
+            col[i + 1] = -sn[i] * x + cs[i] * y;
+          }
+          const double aa = col[j];
+          const double r = hypot(aa, hn);
+          double c = 1.0, sv = 0.0;
+          if (r != 0.0) {
+            c = aa / r;
+            sv = hn / r;
+          }
+          cs[j] = c;
+          sn[j] = sv;
+          col[j] = r;
+          for (int i = 0; i <= j; ++i) a.Rg[i + (int64_t)m * j] = col[i];
+          const double gj = g[j];
+          g[j] = c * gj;
+          g[j + 1] = -sv * gj;
+          double e = fabs(g[j + 1]);
+          if (a.fom) e = aa != 0.0 ? hn * fabs(gj / aa) : __builtin_inf();
+          sc[3] = e;
+          sc[4] = gj;  // last right-hand side entry of the square system
+          sc[5] = aa;  // its last diagonal entry
+          if (steps - 1 < a.hist_cap) a.hist[steps - 1] = e / cnorm;
+        }
+        __syncthreads();
+        est = sc[3];
+        any_est = true;
+        k = j + 1;
+        if (brk || est <= stop || k >= m) break;
+        const double ih = 1.0 / hn;
+        for (int e = t; e < N; e += kYT) W[e] *= ih;
+        __syncthreads();
+      }
+
+      // y (Algorithm 3 step 4(b)), then X += V_k y (step 4(c))
+      double* y = h2;
+      if (t == 0) {
+        bool ok = false;
+        if (a.fom) {
+          ok = tiny_back(a.Rg, m, k, g, sc[5], sc[4], true, y);
+          if (!ok) sc[7] += 1.0;  // tFOM cycle falls back to the tGMRES solution
+        }
+        if (!ok) ok = tiny_back(a.Rg, m, k, g, a.Rg[(k - 1) + (int64_t)m * (k - 1)], g[k - 1],
+                                false, y);
+        sc[6] = ok ? 0.0 : 1.0;
+      }
+      __syncthreads();
+      if (sc[6] != 0.0) {
+        status = TSYLV_ESINGULAR;
+        break;
+      }
+      for (int e = t; e < N; e += kYT) {
+        double acc = X[e];
+        for (int i = 0; i < k; ++i) acc = fma(y[i], slot(i)[e], acc);
+        X[e] = acc;
+      }
+      __syncthreads();
+    }
+  }
+
+  for (int e = t; e < N; e += kYT) a.Zx[e] = X[e];
+  if (t == 0) {
+    a.out[0] = status;
+    a.out[1] = steps;
+    a.out[2] = cycles;
+    a.out[3] = rt;
+    a.out[4] = any_est ? est / cnorm : 0.0;
+    a.out[5] = sc[7];
+    a.out[6] = steps < a.hist_cap ? steps : a.hist_cap;
+  }
+}
+
+}  // namespace
+
+bool tiny_krylov_fits(int64_t n, int64_t s, int64_t p, int m) {
+  const int64_t N = n * s * p;
+  if (n < 1 || s < 1 || p < 1 || m < 1 || N > kYMaxN || m > kYMaxM || m * N > kYMaxMN)
+    return false;
+  return (fixed_doubles(n, s, p, m) + 2 * N) * (int64_t)sizeof(double) <= kYLds;
+}
+
+void tiny_krylov(const double* Ah, const double* Bh, const double* Zc, double* Zx, double* basis,
+                 double* Rg, double* hist, int hist_cap, double* out, int n, int s, int p, int m,
+                 int max_cycles, bool fom, bool x0_given, double tol, hipStream_t st) {
+  if (!tiny_krylov_fits(n, s, p, m)) throw Error(TSYLV_EINVAL, "tiny Krylov: sizes too large");
+  const int64_t N = (int64_t)n * s * p;
+  const int64_t fixed = fixed_doubles(n, s, p, m);
+  const int64_t fit = (kYLds / (int64_t)sizeof(double) - fixed) / N;
+  const int lslots = (int)std::min<int64_t>(m + 1, fit);
+  const size_t lds = (size_t)(fixed + lslots * N) * sizeof(double);
+  TinyArgs a;
+  a.Ah = Ah;
+  a.Bh = Bh;
+  a.Zc = Zc;
+  a.Zx = Zx;
+  a.Vg = basis;
+  a.Rg = Rg;
+  a.hist = hist;
+  a.out = out;
+  a.tol = tol;
+  a.n = n;
+  a.s = s;
+  a.p = p;
+  a.m = m;
+  a.max_cycles = max_cycles;
+  a.fom = fom ? 1 : 0;
+  a.x0_given = x0_given ? 1 : 0;
+  a.hist_cap = hist ? hist_cap : 0;
+  a.lslots = lslots;
+  TSYLV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tiny_krylov_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(tiny_krylov_kernel, dim3(1), dim3(kYT), lds, st, a);
+  TSYLV_LAUNCH_CHECK();
+}
+
+}  // namespace kern
+}  // namespace tsylv

@@ -342,6 +342,25 @@ static int device_cycle_mode(const tsylv_opts& o) {
 }
 static bool device_cycle(const tsylv_opts& o) { return device_cycle_mode(o) != 0; }
 
+// Plain FP64 tGMRES / tFOM of a small instance run whole in one workgroup
+// (kern::tiny_krylov) unless TSYLV_KRYLOV_TINY=0.
+static bool tiny_path(int method, int64_t n, int64_t s, int64_t p, const tsylv_opts& o) {
+  if (o.refine || (method != TSYLV_METHOD_GMRES && method != TSYLV_METHOD_FOM)) return false;
+  const char* f = std::getenv("TSYLV_KRYLOV_TINY");
+  if (f && f[0] == '0') return false;
+  return kern::tiny_krylov_fits(n, s, p, o.m);
+}
+static int64_t tiny_hist_len(const tsylv_opts& o) {
+  if (!o.res_hist || o.res_hist_cap <= 0) return 0;
+  return std::min<int64_t>(o.res_hist_cap, (int64_t)std::max(o.max_cycles, 0) * o.m);
+}
+static size_t tiny_bytes(int64_t N, const tsylv_opts& o) {
+  return Workspace::bytes_for((int64_t)(o.m + 1) * N, 8) +
+         Workspace::bytes_for((int64_t)o.m * o.m, 8) +
+         Workspace::bytes_for(kern::kTinyRecord, 8) +
+         Workspace::bytes_for(std::max<int64_t>(tiny_hist_len(o), 1), 8);
+}
+
 size_t krylov_workspace_bytes(int method, int64_t n, int64_t s, int64_t p, const tsylv_opts& o) {
   const int64_t N = n * s * p;
   size_t b = setup_bytes(n, s, p);
@@ -349,6 +368,7 @@ size_t krylov_workspace_bytes(int method, int64_t n, int64_t s, int64_t p, const
     return b + CycleWS<double>::bytes(N, 1) +
            Workspace::bytes_for(2 * kern::tbs_scratch_complex(n, s, (int)p), 8) +
            Workspace::bytes_for(1, sizeof(int));
+  if (tiny_path(method, n, s, p, o)) return b + tiny_bytes(N, o);
   if (!o.refine) return b + CycleWS<double>::bytes(N, o.m);
   b += Workspace::bytes_for(N, 8);  // FP64 residual
   const bool dc = device_cycle(o);
@@ -395,6 +415,12 @@ struct KrylovState {
   RedBuf* red = nullptr;
   double* tbs_scratch = nullptr;  // method TBS: Schur factors and products per slice
   int* tbs_flag = nullptr;        // method TBS: 0, or 1 / 2 (Schur failure / singular)
+  // small instances solved whole in one workgroup (tiny_path): basis slots
+  // past its LDS, rotated Hessenberg columns, the result record and the
+  // estimates; the record comes back through the pinned buffer
+  bool tiny = false;
+  double *tiny_basis = nullptr, *tiny_R = nullptr, *tiny_out = nullptr, *tiny_hist = nullptr;
+  double* tiny_pinned = nullptr;
 
   Phase phase = SETUP;
   int status = TSYLV_NOT_CONVERGED;
@@ -444,7 +470,14 @@ struct KrylovState {
     delayed = delayed_cgs2(o);
     devcyc = device_cycle(o);
     dcmode = device_cycle_mode(o);
-    if (method == TSYLV_METHOD_TBS) {
+    tiny = tiny_path(method, n, s, p, o);
+    if (tiny) {
+      tiny_basis = ws.take<double>((int64_t)(o.m + 1) * N);
+      tiny_R = ws.take<double>((int64_t)o.m * o.m);
+      tiny_out = ws.take<double>(kern::kTinyRecord);
+      tiny_hist = ws.take<double>(std::max<int64_t>(tiny_hist_len(o), 1));
+      tiny_pinned = pinned;
+    } else if (method == TSYLV_METHOD_TBS) {
       w64.carve(ws, N, 1, pinned);
       red = &w64.red;
       tbs_scratch = ws.take<double>(2 * kern::tbs_scratch_complex(n, s, (int)p));
@@ -963,9 +996,45 @@ struct KrylovState {
       status = info.relres_true <= o.tol ? TSYLV_OK : TSYLV_NOT_CONVERGED;
   }
 
+  // Small instances: Algorithm 3 whole in one launch, the inverse DFT of X
+  // and the result record back in one copy.
+  void enqueue_tiny() {
+    kern::tiny_krylov(S.Ah, S.Bh, S.Zc, S.Zx, tiny_basis, tiny_R, tiny_hist,
+                      (int)tiny_hist_len(o), tiny_out, (int)n, (int)s, (int)p, o.m,
+                      std::max(o.max_cycles, 0), method == TSYLV_METHOD_FOM, o.x0_given != 0,
+                      o.tol, st);
+    {
+      ProfScope ps(ctx, TSYLV_K_XFORM, st, prof);
+      kern::tube_xform_f64(S.Zx, X, S.xf_inv, n * s, (int)p, st);
+    }
+    TSYLV_HIP(hipMemcpyAsync(tiny_pinned, tiny_out, kern::kTinyRecord * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+  }
+
+  void complete_tiny() {
+    const double* r = tiny_pinned;
+    status = (int)r[0];
+    info.steps = (int)r[1];
+    info.cycles = (int)r[2];
+    info.relres_true = r[3];
+    info.relres_est = r[4];
+    info.fom_fallback = (int)r[5];
+    const int hl = (int)r[6];
+    if (hl > 0 && o.res_hist) {
+      TSYLV_HIP(hipMemcpyAsync(o.res_hist, tiny_hist, hl * sizeof(double),
+                               hipMemcpyDeviceToHost, st));
+      TSYLV_HIP(hipStreamSynchronize(st));
+    }
+    info.res_hist_len = hl;
+  }
+
   void enqueue() {
     switch (phase) {
       case SETUP:
+        if (tiny) {
+          enqueue_tiny();
+          break;
+        }
         if (method == TSYLV_METHOD_TBS) {
           enqueue_direct();
           break;
@@ -1042,6 +1111,13 @@ struct KrylovState {
   void complete() {
     switch (phase) {
       case SETUP:
+        if (tiny) {
+          complete_tiny();
+          phase = DONE;
+          info.status = status;
+          info.seconds = seconds_since(t0);
+          break;
+        }
         if (method == TSYLV_METHOD_TBS) {
           complete_direct();
           phase = DONE;
