@@ -31,8 +31,7 @@ namespace kern {
 namespace {
 
 constexpr int kYT = 256;           // threads of the workgroup
-constexpr int kYD = 8;             // lanes that share one dot product
-constexpr int kYS = kYT / kYD;     // dot products per pass
+constexpr int kYD = 8;             // fewest lanes that share one dot product
 constexpr int kYLds = 160 * 1024;  // LDS of one workgroup (bytes)
 constexpr int64_t kYMaxN = 8192;   // largest n s p handled here
 constexpr int kYMaxM = 1024;       // longest restart handled here
@@ -72,7 +71,9 @@ __device__ void tiny_apply(int n, int s, int p, const double* A, const double* B
     const double* Vr = v + (int64_t)qr * ns;
     if (real) {
       double acc = 0.0;
+#pragma unroll 4
       for (int l = 0; l < n; ++l) acc = fma(Ar[i + n * l], Vr[l + n * c], acc);
+#pragma unroll 4
       for (int l = 0; l < s; ++l) acc = fma(-Vr[i + n * l], Br[l + s * c], acc);
       w[(int64_t)qr * ns + e] = acc;
     } else {
@@ -80,6 +81,7 @@ __device__ void tiny_apply(int n, int s, int p, const double* A, const double* B
       const double* Bi = Br + s * s;
       const double* Vi = Vr + ns;
       double re = 0.0, im = 0.0;
+#pragma unroll 4
       for (int l = 0; l < n; ++l) {
         const double ar = Ar[i + n * l], ai = Ai[i + n * l];
         const double vr = Vr[l + n * c], vi = Vi[l + n * c];
@@ -88,6 +90,7 @@ __device__ void tiny_apply(int n, int s, int p, const double* A, const double* B
         im = fma(ar, vi, im);
         im = fma(ai, vr, im);
       }
+#pragma unroll 4
       for (int l = 0; l < s; ++l) {
         const double vr = Vr[i + n * l], vi = Vi[i + n * l];
         const double br = Br[l + s * c], bi = Bi[l + s * c];
@@ -102,41 +105,94 @@ __device__ void tiny_apply(int n, int s, int p, const double* A, const double* B
   }
 }
 
-// out[i] = x_i . y for i < cnt (x_i = vec(i)): kYD adjacent lanes per sum,
-// each over the elements of its residue class, then a fixed tree.
+// out[i] = x_i . y for i < cnt (x_i = vec(i)): L adjacent lanes per sum
+// (the largest power of two with L cnt <= kYT, 8 <= L <= 64), four partial
+// sums per lane over its elements (loads of four elements in flight), then
+// a fixed tree.
 template <typename Vec>
 __device__ void tiny_dots(Vec vec, int cnt, const double* y, int N, double* out) {
-  const int part = threadIdx.x % kYD, slot = threadIdx.x / kYD;
-  for (int i0 = 0; i0 < cnt; i0 += kYS) {
-    const int i = i0 + slot;
-    double acc = 0.0;
+  int L = 64;
+  while (L > kYD && L * cnt > kYT) L >>= 1;
+  const int part = threadIdx.x % L, grp = threadIdx.x / L, per = kYT / L;
+  for (int i0 = 0; i0 < cnt; i0 += per) {
+    const int i = i0 + grp;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     if (i < cnt) {
       const double* x = vec(i);
-      for (int e = part; e < N; e += kYD) acc = fma(x[e], y[e], acc);
+      int e = part;
+      for (; e + 3 * L < N; e += 4 * L) {
+        a0 = fma(x[e], y[e], a0);
+        a1 = fma(x[e + L], y[e + L], a1);
+        a2 = fma(x[e + 2 * L], y[e + 2 * L], a2);
+        a3 = fma(x[e + 3 * L], y[e + 3 * L], a3);
+      }
+      for (; e < N; e += L) a0 = fma(x[e], y[e], a0);
     }
-    acc += __shfl_xor(acc, 1);
-    acc += __shfl_xor(acc, 2);
-    acc += __shfl_xor(acc, 4);
+    double acc = (a0 + a1) + (a2 + a3);
+    for (int o = 1; o < L; o <<= 1) acc += __shfl_xor(acc, o);
     if (part == 0 && i < cnt) out[i] = acc;
   }
 }
 
-// w -= sum_{i < cnt} h_i x_i, in index order per element
+// w -= sum_{i < cnt} h_i x_i, in index order per element; with wsq, each
+// wave's sum of the new w^2 (a fixed tree) to wsq[wave].
 template <typename Vec>
-__device__ void tiny_sub(double* w, Vec vec, int cnt, const double* h, int N) {
+__device__ void tiny_sub(double* w, Vec vec, int cnt, const double* h, int N, double* wsq) {
+  double sq = 0.0;
   for (int e = threadIdx.x; e < N; e += kYT) {
     double acc = w[e];
+#pragma unroll 4
     for (int i = 0; i < cnt; ++i) acc = fma(-h[i], vec(i)[e], acc);
     w[e] = acc;
+    sq = fma(acc, acc, sq);
+  }
+  if (wsq) {
+    for (int o = 1; o < 64; o <<= 1) sq += __shfl_xor(sq, o);
+    if ((threadIdx.x & 63) == 0) wsq[threadIdx.x >> 6] = sq;
   }
 }
 
-// R y = r for the k x k upper triangular R (column l at R + m l), with the
-// last diagonal entry dlast and the last right-hand side entry rlast in
-// place of R's and r's; false on a zero diagonal (or, if `finite`, a
-// non-finite y).
-__device__ bool tiny_back(const double* R, int m, int k, const double* r, double dlast,
-                          double rlast, bool finite, double* y) {
+// x of lane `l` (wave-uniform)
+__device__ __forceinline__ double rlane(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
+// y of R y = r for the k x k upper triangular R (column l at R + m l), with
+// the last diagonal entry dlast and the last right-hand side entry rlast in
+// place of R's and r's.  Wave 0, row i in lane i (k <= 64), column by
+// column from the last, the next column's entries loaded ahead.  Returns
+// false on a zero diagonal (or, if `finite`, a non-finite y).
+__device__ bool tiny_back_wave(const double* R, int m, int k, const double* r, double dlast,
+                               double rlast, bool finite, double* y) {
+  const int lane = threadIdx.x;
+  double tr = lane < k ? (lane == k - 1 ? rlast : r[lane]) : 0.0;
+  double yv = 0.0;
+  double rn = lane < k ? R[lane + (int64_t)m * (k - 1)] : 0.0;
+  bool ok = true;
+  for (int l = k - 1; l >= 0; --l) {
+    const double rc = rn;  // column l, rows 0 .. l
+    rn = (l > 0 && lane < l) ? R[lane + (int64_t)m * (l - 1)] : 0.0;
+    const double d = l == k - 1 ? dlast : rlane(rc, l);
+    if (d == 0.0) {
+      ok = false;
+      break;
+    }
+    const double yl = rlane(tr, l) / d;
+    if (finite && !isfinite(yl)) {
+      ok = false;
+      break;
+    }
+    if (lane == l) yv = yl;
+    if (lane < l) tr = fma(-rc, yl, tr);
+  }
+  if (lane < k) y[lane] = yv;
+  return ok;
+}
+
+// The same solve by one thread, for k > 64.
+__device__ bool tiny_back_serial(const double* R, int m, int k, const double* r, double dlast,
+                                 double rlast, bool finite, double* y) {
   for (int ii = k - 1; ii >= 0; --ii) {
     double t = ii == k - 1 ? rlast : r[ii];
     for (int l = ii + 1; l < k; ++l) t -= R[ii + (int64_t)m * l] * y[l];
@@ -163,6 +219,9 @@ __global__ __launch_bounds__(kYT) void tiny_krylov_kernel(TinyArgs a) {
   double* col = h2 + (m + 2);
   double* sc = col + (m + 2);
   double* Vl = sc + kYScal;
+  // basis slot i: in LDS for i < lslots, else in global memory; steps whose
+  // slots are all in LDS use lslot, so that their accesses are LDS accesses
+  auto lslot = [&](int i) -> double* { return Vl + (int64_t)i * N; };
   auto slot = [&](int i) -> double* {
     return i < a.lslots ? Vl + (int64_t)i * N : a.Vg + (int64_t)i * N;
   };
@@ -177,16 +236,77 @@ __global__ __launch_bounds__(kYT) void tiny_krylov_kernel(TinyArgs a) {
   const double cnorm = sqrt(sc[0]);
   const double stop = a.tol * cnorm;
 
+  // One Arnoldi step (Algorithm 2 step 3) and its Givens update; returns
+  // true when the cycle ends at this step.
   int status = TSYLV_NOT_CONVERGED, steps = 0, cycles = 0;
   double rt = 0.0, est = 0.0;
   bool any_est = false;
+  auto step = [&](auto vs, int j) -> bool {
+    double* W = vs(j + 1);
+    tiny_apply(n, s, p, A, B, vs(j), W);
+    __syncthreads();
+    tiny_dots(vs, j + 2, W, N, h1);  // h1[0..j], and ||W||^2 in h1[j + 1]
+    __syncthreads();
+    tiny_sub(W, vs, j + 1, h1, N, (double*)nullptr);
+    __syncthreads();
+    tiny_dots(vs, j + 1, W, N, h2);
+    __syncthreads();
+    tiny_sub(W, vs, j + 1, h2, N, sc + 8);  // ||w||^2 by wave in sc[8..11]
+    __syncthreads();
+    const double w0 = sqrt(h1[j + 1]);
+    double hn = sqrt(((sc[8] + sc[9]) + sc[10]) + sc[11]);
+    const bool brk = !(hn > 16.0 * 2.220446049250313e-16 * w0);  // h_{j+1,j} = 0
+    if (brk) hn = 0.0;
+    ++steps;
+    // V_{j+1} = W / h_{j+1,j} (Algorithm 2 step 3(e)); unused if the cycle
+    // ends here
+    if (!brk) {
+      const double ih = 1.0 / hn;
+      for (int e = t; e < N; e += kYT) W[e] *= ih;
+    }
+    if (t == 0) {
+      // the earlier rotations on column j, the rotated entries to Rg
+      double carry = h1[0] + h2[0];
+#pragma unroll 4
+      for (int i = 0; i < j; ++i) {
+        const double y = h1[i + 1] + h2[i + 1];
+        const double c = cs[i], sv = sn[i];
+        a.Rg[i + (int64_t)m * j] = c * carry + sv * y;
+        carry = -sv * carry + c * y;
+      }
+      const double aa = carry;
+      const double r = hypot(aa, hn);
+      double c = 1.0, sv = 0.0;
+      if (r != 0.0) {
+        c = aa / r;
+        sv = hn / r;
+      }
+      cs[j] = c;
+      sn[j] = sv;
+      a.Rg[j + (int64_t)m * j] = r;
+      const double gj = g[j];
+      g[j] = c * gj;
+      g[j + 1] = -sv * gj;
+      double e = fabs(g[j + 1]);
+      if (a.fom) e = aa != 0.0 ? hn * fabs(gj / aa) : __builtin_inf();
+      sc[3] = e;
+      sc[4] = gj;  // last right-hand side entry of the square system
+      sc[5] = aa;  // its last diagonal entry
+      if (steps - 1 < a.hist_cap) a.hist[steps - 1] = e / cnorm;
+    }
+    __syncthreads();
+    est = sc[3];
+    any_est = true;
+    return brk || est <= stop || j + 1 >= m;
+  };
+
   if (cnorm == 0.0) {
     for (int e = t; e < N; e += kYT) X[e] = 0.0;
     status = TSYLV_OK;
   } else {
     for (;;) {
       // R = C - M(X) into slot 0 (Algorithm 3 step 3; C itself for X0 = 0)
-      double* R = slot(0);
+      double* R = lslot(0);
       if (cycles == 0 && !a.x0_given) {
         for (int e = t; e < N; e += kYT) R[e] = a.Zc[e];
       } else {
@@ -210,86 +330,47 @@ __global__ __launch_bounds__(kYT) void tiny_krylov_kernel(TinyArgs a) {
       if (t == 0) g[0] = beta;
       __syncthreads();
 
-      // Arnoldi steps (Algorithm 2 step 3) with the Givens update
       int k = 0;
       for (int j = 0; j < m; ++j) {
-        double* W = slot(j + 1);
-        tiny_apply(n, s, p, A, B, slot(j), W);
-        __syncthreads();
-        tiny_dots(slot, j + 2, W, N, h1);  // h1[0..j] and ||W||^2 in h1[j + 1]
-        __syncthreads();
-        tiny_sub(W, slot, j + 1, h1, N);
-        __syncthreads();
-        tiny_dots(slot, j + 1, W, N, h2);
-        __syncthreads();
-        tiny_sub(W, slot, j + 1, h2, N);
-        __syncthreads();
-        tiny_dots([&](int) { return W; }, 1, W, N, sc + 2);
-        __syncthreads();
-        const double w0 = sqrt(h1[j + 1]);
-        double hn = sqrt(sc[2]);
-        const bool brk = !(hn > 16.0 * 2.220446049250313e-16 * w0);  // h_{j+1,j} = 0
-        if (brk) hn = 0.0;
-        ++steps;
-        if (t == 0) {
-          for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-          for (int i = 0; i < j; ++i) {
-            const double x = col[i], y = col[i + 1];
-            col[i] = cs[i] * x + sn[i] * y;
-            col[i + 1] = -sn[i] * x + cs[i] * y;
-          }
-          const double aa = col[j];
-          const double r = hypot(aa, hn);
-          double c = 1.0, sv = 0.0;
-          if (r != 0.0) {
-            c = aa / r;
-            sv = hn / r;
-          }
-          cs[j] = c;
-          sn[j] = sv;
-          col[j] = r;
-          for (int i = 0; i <= j; ++i) a.Rg[i + (int64_t)m * j] = col[i];
-          const double gj = g[j];
-          g[j] = c * gj;
-          g[j + 1] = -sv * gj;
-          double e = fabs(g[j + 1]);
-          if (a.fom) e = aa != 0.0 ? hn * fabs(gj / aa) : __builtin_inf();
-          sc[3] = e;
-          sc[4] = gj;  // last right-hand side entry of the square system
-          sc[5] = aa;  // its last diagonal entry
-          if (steps - 1 < a.hist_cap) a.hist[steps - 1] = e / cnorm;
-        }
-        __syncthreads();
-        est = sc[3];
-        any_est = true;
         k = j + 1;
-        if (brk || est <= stop || k >= m) break;
-        const double ih = 1.0 / hn;
-        for (int e = t; e < N; e += kYT) W[e] *= ih;
-        __syncthreads();
+        if (j + 2 <= a.lslots ? step(lslot, j) : step(slot, j)) break;
       }
 
-      // y (Algorithm 3 step 4(b)), then X += V_k y (step 4(c))
+      // y (Algorithm 3 step 4(b)): tFOM's square system, or (tGMRES, and
+      // tFOM's fallback) the least-squares problem
       double* y = h2;
-      if (t == 0) {
+      if (t < 64) {
         bool ok = false;
-        if (a.fom) {
-          ok = tiny_back(a.Rg, m, k, g, sc[5], sc[4], true, y);
-          if (!ok) sc[7] += 1.0;  // tFOM cycle falls back to the tGMRES solution
+        const double dg = a.Rg[(k - 1) + (int64_t)m * (k - 1)];
+        if (k <= 64) {
+          if (a.fom) ok = tiny_back_wave(a.Rg, m, k, g, sc[5], sc[4], true, y);
+          if (a.fom && !ok && t == 0) sc[7] += 1.0;  // falls back to the tGMRES solution
+          if (!ok) ok = tiny_back_wave(a.Rg, m, k, g, dg, g[k - 1], false, y);
+        } else if (t == 0) {
+          if (a.fom) ok = tiny_back_serial(a.Rg, m, k, g, sc[5], sc[4], true, y);
+          if (a.fom && !ok) sc[7] += 1.0;
+          if (!ok) ok = tiny_back_serial(a.Rg, m, k, g, dg, g[k - 1], false, y);
         }
-        if (!ok) ok = tiny_back(a.Rg, m, k, g, a.Rg[(k - 1) + (int64_t)m * (k - 1)], g[k - 1],
-                                false, y);
-        sc[6] = ok ? 0.0 : 1.0;
+        if (t == 0) sc[6] = ok ? 0.0 : 1.0;
       }
       __syncthreads();
       if (sc[6] != 0.0) {
         status = TSYLV_ESINGULAR;
         break;
       }
-      for (int e = t; e < N; e += kYT) {
-        double acc = X[e];
-        for (int i = 0; i < k; ++i) acc = fma(y[i], slot(i)[e], acc);
-        X[e] = acc;
+      // X += V_k y (step 4(c))
+      if (k <= a.lslots) {
+        for (int e = t; e < N; e += kYT) {
+          double acc = X[e];
+          for (int i = 0; i < k; ++i) acc = fma(y[i], lslot(i)[e], acc);
+          X[e] = acc;
+        }
+      } else {
+        for (int e = t; e < N; e += kYT) {
+          double acc = X[e];
+          for (int i = 0; i < k; ++i) acc = fma(y[i], slot(i)[e], acc);
+          X[e] = acc;
+        }
       }
       __syncthreads();
     }
