@@ -30,8 +30,9 @@ reported beside them).
 `value` is the solves/s of the fastest valid refined path.  The n = 4096, s = 64, p = 32 configuration
 (tGMRES(30), inner 32 / 28, and TBAS(10)) is reported under "cd4096" (--also).
 Further measurements ride along (skip with --no-extra):
-  tiny      the 8 x 8 x 4 dense case, unrestarted tGMRES to 1e-12: latency,
-            and the same instance through the t-Bartels-Stewart direct solve
+  tiny      the 8 x 8 x 4 dense case, unrestarted tGMRES to 1e-12: latency
+            of the single-workgroup solve and of the multi-launch driver, and
+            the same instance through the t-Bartels-Stewart direct solve
   serving   open-loop Poisson arrivals of requests of uneven (n, s, p)
             through tsylv_submit / tsylv_poll (the serving loop): p50/p99
             latency and throughput, FP64 and refined
@@ -202,6 +203,20 @@ def tiny_latency(tsylv, workloads, reps=100):
         ok = ok and info.status == 0 and info.relres_true <= 1e-12
         if r >= 10:
             lat.append(dt)
+    # the same solve through the multi-launch driver (a host round trip per
+    # Arnoldi step) instead of the single-workgroup kernel
+    os.environ["TSYLV_KRYLOV_TINY"] = "0"
+    lat_m, ok_m = [], True
+    try:
+        for r in range(reps + 10):
+            t0 = time.perf_counter()
+            _, info_m = ctx.gmres(Ad, Bd, Cd, X=Xd, opts=o)
+            dt = time.perf_counter() - t0
+            ok_m = ok_m and info_m.status == 0 and info_m.relres_true <= 1e-12
+            if r >= 10:
+                lat_m.append(dt)
+    finally:
+        del os.environ["TSYLV_KRYLOV_TINY"]
     # the same instance through the t-Bartels-Stewart direct solve
     lat_d, ok_d = [], True
     for r in range(reps + 10):
@@ -230,8 +245,12 @@ def tiny_latency(tsylv, workloads, reps=100):
                                "latency_us": {"p50": float(np.percentile(lat_b, 50) * 1e6),
                                               "p99": float(np.percentile(lat_b, 99) * 1e6)}},
             "valid": bool(ok), "solves": reps, "steps": info.steps,
+            "path": "one workgroup runs the whole solve (one launch)",
             "latency_us": {"p50": float(np.percentile(lat, 50) * 1e6),
                            "p99": float(np.percentile(lat, 99) * 1e6)},
+            "multi_launch": {"valid": bool(ok_m), "steps": info_m.steps,
+                             "latency_us": {"p50": float(np.percentile(lat_m, 50) * 1e6),
+                                            "p99": float(np.percentile(lat_m, 99) * 1e6)}},
             "tbs": {"valid": bool(ok_d), "relres_true": info_d.relres_true,
                     "latency_us": {"p50": float(np.percentile(lat_d, 50) * 1e6),
                                    "p99": float(np.percentile(lat_d, 99) * 1e6)}}}
