@@ -309,8 +309,10 @@ __device__ __forceinline__ void apply_tile(
     }
 }
 
-template <typename Tag, int TM, int TN, int RB, int CB, int TK>
-__global__ __launch_bounds__(NT) void apply_mfma_kernel(ApplyArgs<Tag> a) {
+// MINW: waves per SIMD the register allocation must leave room for (1: the
+// compiler's choice).
+template <typename Tag, int TM, int TN, int RB, int CB, int TK, int MINW>
+__global__ __launch_bounds__(NT, MINW) void apply_mfma_kernel(ApplyArgs<Tag> a) {
   using L = typename Mma<Tag>::L;
   __shared__ L As[2][TK][TM + Mma<Tag>::PADA];
   __shared__ L Bs[2][TK][TN + Mma<Tag>::PADB];
@@ -325,13 +327,13 @@ __global__ __launch_bounds__(NT) void apply_mfma_kernel(ApplyArgs<Tag> a) {
     apply_tile<Tag, TM, TN, RB, CB, TK, true>(a, k, rt, ct, As, Bs);
 }
 
-template <typename Tag, int TM, int TN, int RB, int CB, int TK = Mma<Tag>::TK>
+template <typename Tag, int TM, int TN, int RB, int CB, int TK = Mma<Tag>::TK, int MINW = 1>
 void launch_apply(ApplyArgs<Tag> a, hipStream_t st) {
   a.nrt = (int)((a.n + TM - 1) / TM);
   a.nct = (int)((a.s + TN - 1) / TN);
   a.total = num_slices(a.p) * a.nrt * a.nct;
-  hipLaunchKernelGGL((apply_mfma_kernel<Tag, TM, TN, RB, CB, TK>), dim3(a.total), dim3(NT), 0, st,
-                     a);
+  hipLaunchKernelGGL((apply_mfma_kernel<Tag, TM, TN, RB, CB, TK, MINW>), dim3(a.total), dim3(NT),
+                     0, st, a);
   TSYLV_LAUNCH_CHECK();
 }
 
@@ -351,23 +353,33 @@ void launch_variant(int v, ApplyArgs<Tag> a, hipStream_t st) {
     case 7: launch_apply<Tag, 64, 32, 1, 2, 32>(a, st); break;
     case 8: launch_apply<Tag, 128, 16, 2, 1, 32>(a, st); break;
     case 9: launch_apply<Tag, 64, 16, 1, 1, 32>(a, st); break;
+    // registers capped for three / four waves per SIMD
+    case 10: launch_apply<Tag, 64, 32, 1, 2, 16, 3>(a, st); break;
+    case 11: launch_apply<Tag, 64, 32, 1, 2, 16, 4>(a, st); break;
+    case 12: launch_apply<Tag, 32, 64, 1, 2, 16, 3>(a, st); break;
+    case 13: launch_apply<Tag, 64, 64, 1, 4, 16, 2>(a, st); break;
     default: throw Error(TSYLV_EINVAL, "apply: unknown tile variant");
   }
 }
 
 // Without a tuned choice: a column tile as wide as s needs, so small s does
-// not waste MFMA work; at s > 32 FP64 takes 64 x 32 tiles (2.81 vs 2.87 ms
-// for 32 x 64 at n = 4096, s = 64, p = 32), FP32 64 x 32 up to s = 64 (1.32
-// vs 1.39 ms for 64 x 64 at that shape) and 64 x 64 beyond (17.1 vs 18.0 ms
-// for 64 x 32 at n = 8192, s = 128, p = 64).
+// not waste MFMA work.  FP64 above s = 16 takes the tiles whose registers
+// are capped so that three waves share a SIMD (two with the compiler's
+// allocation of 212 registers): 64 x 32 up to s = 64 (2.41 vs 2.90 ms
+// uncapped at n = 4096, s = 64, p = 32) and 64 x 64 at two waves beyond
+// (32.4 vs 40.4 ms for the uncapped 64 x 32 at n = 8192, s = 128, p = 64).
+// FP32 (at most 196 registers, four waves already) keeps 64 x 32 up to
+// s = 64 (1.35 vs 1.40 ms for 64 x 64 at n = 4096) and 64 x 64 beyond
+// (17.2 vs 18.2 ms for 64 x 32 at n = 8192).
 template <typename Tag>
 int default_variant(int64_t s) {
+  constexpr bool f64 = std::is_same<Tag, double>::value;
   // FP64 at s <= 16 streams its operator (HBM-bound): 64 x 16 tiles with
-  // 32-deep k panels keep more of it in flight (1.01 vs 1.48 ms for
+  // 32-deep k panels keep more of it in flight (1.06 vs 1.49 ms for
   // 128 x 16 at n = 4096, p = 32)
-  if (s <= 16) return std::is_same<Tag, double>::value ? 9 : 0;
-  if (s <= 32) return 1;
-  return (std::is_same<Tag, float>::value && s > 64) ? 3 : 1;
+  if (s <= 16) return f64 ? 9 : 0;
+  if (s <= 64) return f64 ? 10 : 1;
+  return f64 ? 13 : 3;
 }
 
 // Batched apply: the tiles of many instances in one launch (their first
@@ -480,7 +492,9 @@ void batch_apply(const BatchItem* items, const BatchApplyRef* refs, int nref, in
 
 // Tile shape of an instance in a batched apply: the default of its s, so an
 // instance computes the same bits in any batch.
-int batch_apply_variant(int64_t s) { return default_variant<double>(s); }
+// the batched kernel's tiles (batch_apply_tiles): 64 x 16 with 32-deep k
+// panels up to s = 16, 64 x 32 beyond
+int batch_apply_variant(int64_t s) { return s <= 16 ? 9 : 1; }
 int batch_apply_tiles(int variant, int64_t n, int64_t s, int p, int* nrt, int* nct) {
   int tm, tn;
   switch (variant) {
@@ -495,7 +509,7 @@ int batch_apply_tiles(int variant, int64_t n, int64_t s, int p, int* nrt, int* n
   return num_slices(p) * *nrt * *nct;
 }
 
-int apply_variant_count(int prec) { return prec == TSYLV_BF16 ? 10 : 10; }
+int apply_variant_count(int prec) { return prec == TSYLV_BF16 ? 10 : 14; }
 
 int apply_default_variant(int prec, int64_t s) {
   if (prec == TSYLV_FP64) return default_variant<double>(s);
