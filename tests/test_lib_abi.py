@@ -125,3 +125,21 @@ def test_tbs_workspace_bounds():
     assert tsylv.workspace_bytes(tsylv.TBS, 8, 65, 4) == 0
     small = tsylv.workspace_bytes(tsylv.TBS, 8, 6, 4)
     assert tsylv.workspace_bytes(tsylv.TBS, 8, 6, 8) > small
+
+
+def test_default_apply_variant_is_host_logic():
+    """The tile variant an untuned apply takes (host logic, no GPU): capped
+    64 x 16 tiles for FP64 at small s from n = 2048 on, the 32-deep
+    uncapped ones below, capped 64 x 32 up to s = 64, 64 x 64 beyond; bad
+    precisions and sizes are rejected."""
+    v = tsylv.apply_default_variant
+    assert v(tsylv.FP64, 4096, 16) == 15 and v(tsylv.FP64, 1024, 16) == 9
+    assert v(tsylv.FP64, 4096, 64) == 10 and v(tsylv.FP64, 8192, 128) == 13
+    assert v(tsylv.FP32, 4096, 64) == 1 and v(tsylv.FP32, 8192, 128) == 3
+    for prec in (tsylv.FP64, tsylv.FP32, tsylv.BF16):
+        for n, s in ((8, 1), (300, 24), (4096, 200)):
+            assert 0 <= v(prec, n, s) < tsylv.apply_variants(prec)
+    with pytest.raises(tsylv.TsylvError):
+        v(7, 100, 10)
+    with pytest.raises(tsylv.TsylvError):
+        v(tsylv.FP64, 0, 10)
