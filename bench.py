@@ -84,6 +84,35 @@ def apply_work(n, s, p, elem):
     return flops, bytes_
 
 
+def apply_shape(tsylv, spec, reps):
+    """One apply shape on its own: every FP64 / FP32 tile variant timed by
+    tsylv_autotune (reps launches each on random operands of the shape in the
+    arena, HIP events), the default variant's average launch against the
+    algorithmic bytes and flops of apply_work.  With rocprofv3 around it, the
+    kernel trace and the byte counters of each variant's launches."""
+    name, n, s, p = spec.split(":")
+    n, s, p = int(n), int(s), int(p)
+    prec = {"fp64": tsylv.FP64, "fp32": tsylv.FP32}[name]
+    eb = 8 if name == "fp64" else 4
+    flops, nbytes = apply_work(n, s, p, (eb, eb))
+    need = eb * p * (n * n + s * s + 3 * n * s) + (512 << 20)
+    ctx = tsylv.Context(need, device=0)
+    default = tsylv.apply_default_variant(prec, n, s)
+    best, ms = ctx.autotune(n, s, p, prec=prec, reps=max(reps, 3))
+    ctx.close()
+    d = ms[default]
+    log("apply %s n=%d s=%d p=%d: default variant %d %.3f ms (%.0f GB/s, %.1f%% of HBM); "
+        "fastest %d %.3f ms" % (name, n, s, p, default, d, nbytes / d / 1e6,
+                                100 * nbytes / d / 1e-3 / PEAK_HBM, best, ms[best]))
+    return {"apply_shape": {"prec": name, "n": n, "s": s, "p": p, "reps": max(reps, 3),
+                            "default_variant": default, "fastest_variant": best,
+                            "ms_per_variant": ms, "algorithmic_bytes": nbytes,
+                            "algorithmic_flops": flops,
+                            "default": {"ms": d, "GB_per_s": nbytes / d / 1e6,
+                                        "hbm_frac": nbytes / (d * 1e-3) / PEAK_HBM,
+                                        "TFLOP_per_s": flops / (d * 1e-3) / 1e12}}}
+
+
 def cpu_baseline(A, B, C, applies_per_solve, avg_basis):
     """The oracle (FP64 numpy: circulant-sum T-product, MGS tArnoldi) timed on a
     bounded sample of the benchmark workload: frontal slice 0 of M(V) (1/p of
@@ -875,6 +904,11 @@ def main():
                          "fp32; default all)")
     ap.add_argument("--no-small-serve", action="store_true",
                     help="with --serve-only: skip the small-size serving runs")
+    ap.add_argument("--apply-shape", default="",
+                    help="PREC:N:S:P (prec fp64 or fp32): time every tile variant of the "
+                         "Fourier-plane apply at that shape (--steps launches each, the "
+                         "autotuner's random operands) and report the HBM rate of the "
+                         "default one; nothing else runs")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB three times "
                          "(reference kernel for the HBM byte counters)")
@@ -898,6 +932,10 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 x %d MiB" % args.copy_calib_mib)
         del src, dst
+
+    if args.apply_shape:
+        print(json.dumps(apply_shape(tsylv, args.apply_shape, args.steps)), flush=True)
+        return
 
     if args.batched_only:
         print(json.dumps({"batched": {"large": batched(tsylv, "large", 256),

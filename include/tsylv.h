@@ -335,6 +335,10 @@ int tsylv_autotune(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, int prec, in
 int tsylv_tune_set(tsylv_ctx* ctx, int prec, int64_t n, int64_t s, int64_t p, int variant);
 /* The entry of a shape in *variant (-1: none, the default is used). */
 int tsylv_tune_get(tsylv_ctx* ctx, int prec, int64_t n, int64_t s, int64_t p, int* variant);
+/* The variant an apply of precision `prec` with n rows and s columns takes
+ * when the table has no entry for its shape (>= 0), or TSYLV_EINVAL for an
+ * unknown precision or n, s < 1. */
+int tsylv_apply_default_variant(int prec, int64_t n, int64_t s);
 /* Write the table to a text file (a header line "tsylv-tune 1", then one
  * line "prec n s p variant" per entry) / merge such a file into the table
  * (TSYLV_EINVAL, and nothing merged, when any line is malformed). */

@@ -376,6 +376,12 @@ int tsylv_apply_variants(int prec) {
   return kern::apply_variant_count(prec);
 }
 
+int tsylv_apply_default_variant(int prec, int64_t n, int64_t s) {
+  if ((prec != TSYLV_FP64 && prec != TSYLV_FP32 && prec != TSYLV_BF16) || n < 1 || s < 1)
+    return TSYLV_EINVAL;
+  return kern::apply_default_variant(prec, n, s);
+}
+
 int tsylv_autotune(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, int prec, int reps,
                    int* best, float* ms, int ms_cap) {
   if (!ctx || !dims_ok(n, s, p) || tsylv_apply_variants(prec) < 0 || reps < 1 || reps > 1000 ||

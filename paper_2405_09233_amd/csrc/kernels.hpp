@@ -55,7 +55,7 @@ void apply_f32(const float* Ah, const float* Bh, const float* V, float* out, con
                double alpha, double beta, int64_t n, int64_t s, int p, hipStream_t st,
                int variant = -1);
 int apply_variant_count(int prec);             // tsylv_prec
-int apply_default_variant(int prec, int64_t s);
+int apply_default_variant(int prec, int64_t n, int64_t s);
 int bf16_default_variant(int64_t s);
 
 // BF16 operator planes (BF16 MFMA, the vectors rounded to BF16 on the way

@@ -358,6 +358,9 @@ void launch_variant(int v, ApplyArgs<Tag> a, hipStream_t st) {
     case 11: launch_apply<Tag, 64, 32, 1, 2, 16, 4>(a, st); break;
     case 12: launch_apply<Tag, 32, 64, 1, 2, 16, 3>(a, st); break;
     case 13: launch_apply<Tag, 64, 64, 1, 4, 16, 2>(a, st); break;
+    case 14: launch_apply<Tag, 64, 16, 1, 1, 16, 3>(a, st); break;
+    case 15: launch_apply<Tag, 64, 16, 1, 1, 16, 4>(a, st); break;
+    case 16: launch_apply<Tag, 64, 16, 1, 1, 32, 2>(a, st); break;
     default: throw Error(TSYLV_EINVAL, "apply: unknown tile variant");
   }
 }
@@ -372,12 +375,16 @@ void launch_variant(int v, ApplyArgs<Tag> a, hipStream_t st) {
 // s = 64 (1.35 vs 1.40 ms for 64 x 64 at n = 4096) and 64 x 64 beyond
 // (17.2 vs 18.2 ms for 64 x 32 at n = 8192).
 template <typename Tag>
-int default_variant(int64_t s) {
+int default_variant(int64_t n, int64_t s) {
   constexpr bool f64 = std::is_same<Tag, double>::value;
-  // FP64 at s <= 16 streams its operator (HBM-bound): 64 x 16 tiles with
-  // 32-deep k panels keep more of it in flight (1.06 vs 1.49 ms for
-  // 128 x 16 at n = 4096, p = 32)
-  if (s <= 16) return f64 ? 9 : 0;
+  // FP64 at small s streams its operator (HBM-bound): from n = 2048 on,
+  // 64 x 16 tiles with 16-deep k panels at four waves per SIMD keep the most
+  // of it in flight (0.90 ms = 4.8 TB/s at n = 4096, s = 16, p = 32,
+  // against 1.06 ms with 32-deep panels at two waves and 1.49 ms for
+  // 128 x 16; 0.25 vs 0.29 ms for the capped 64 x 32 at n = 2048, s = 24,
+  // p = 16); smaller operators (a few k panels per tile) run 3-6 % faster
+  // with the 32-deep panels
+  if (s <= 24) return f64 ? (n >= 2048 ? 15 : (s <= 16 ? 9 : 10)) : (s <= 16 ? 0 : 1);
   if (s <= 64) return f64 ? 10 : 1;
   return f64 ? 13 : 3;
 }
@@ -386,8 +393,8 @@ int default_variant(int64_t s) {
 // tiles in refs, ascending).  STEP: W = M(V_j) for the stepping instances;
 // RESID: V_0 = Zc - M(Zx) for the instances not done.
 // (The mode is a template parameter, as in the batched vector kernels.)
-template <int TM, int TN, int RB, int CB, int TK, int MODE>
-__global__ __launch_bounds__(NT) void apply_batch_kernel(const BatchItem* __restrict__ items,
+template <int TM, int TN, int RB, int CB, int TK, int MODE, int MINW>
+__global__ __launch_bounds__(NT, MINW) void apply_batch_kernel(const BatchItem* __restrict__ items,
                                                          const BatchApplyRef* __restrict__ refs,
                                                          int nref, int total,
                                                          const BatchState* __restrict__ st,
@@ -447,7 +454,7 @@ void apply_any(const typename Store<Tag>::T* Ah, const typename Store<Tag>::T* B
   if (useB && Bh == nullptr) throw Error(TSYLV_EINVAL, "apply: missing Bhat");
   ApplyArgs<Tag> a{Ah, Bh, V, out, beta != 0.0 ? Y : nullptr, alpha, beta, n, s, p,
                    useB ? 1 : 0, 0, 0, 0};
-  launch_variant<Tag>(variant >= 0 ? variant : default_variant<Tag>(s), a, st);
+  launch_variant<Tag>(variant >= 0 ? variant : default_variant<Tag>(n, s), a, st);
 }
 
 }  // namespace
@@ -464,15 +471,15 @@ void apply_f32(const float* Ah, const float* Bh, const float* V, float* out, con
   apply_any<float>(Ah, Bh, V, out, Y, alpha, beta, n, s, p, Bh != nullptr, variant, st);
 }
 
-template <int TM, int TN, int RB, int CB, int TK = Mma<double>::TK>
+template <int TM, int TN, int RB, int CB, int TK = Mma<double>::TK, int MINW = 1>
 static void launch_batch(const BatchItem* items, const BatchApplyRef* refs, int nref, int total,
                          BatchState* st, const int* jp, int mode, hipStream_t s) {
   if (mode == BM_STEP)
-    klaunch(apply_batch_kernel<TM, TN, RB, CB, TK, BM_STEP>, dim3(total), dim3(NT), 0, s, items,
-            refs, nref, total, st, jp);
+    klaunch(apply_batch_kernel<TM, TN, RB, CB, TK, BM_STEP, MINW>, dim3(total), dim3(NT), 0, s,
+            items, refs, nref, total, st, jp);
   else if (mode == BM_RESID)
-    klaunch(apply_batch_kernel<TM, TN, RB, CB, TK, BM_RESID>, dim3(total), dim3(NT), 0, s, items,
-            refs, nref, total, st, jp);
+    klaunch(apply_batch_kernel<TM, TN, RB, CB, TK, BM_RESID, MINW>, dim3(total), dim3(NT), 0, s,
+            items, refs, nref, total, st, jp);
   else
     throw Error(TSYLV_EINVAL, "batch apply: mode");
 }
@@ -482,7 +489,14 @@ void batch_apply(const BatchItem* items, const BatchApplyRef* refs, int nref, in
   if (nref <= 0 || total_tiles <= 0) return;
   switch (variant) {
     case 0: launch_batch<128, 16, 2, 1>(items, refs, nref, total_tiles, st, jp, mode, st_); break;
-    case 1: launch_batch<64, 32, 1, 2>(items, refs, nref, total_tiles, st, jp, mode, st_); break;
+    // 64 x 32 with the register cap of the single-instance default (three
+    // waves per SIMD); 64 x 16 keeps 32-deep panels, uncapped: the batched
+    // instances with s <= 16 are small (few k panels, latency-bound), and
+    // the capped 16-deep form ran the 256-instance small mix at 5.9k
+    // instead of 7.6k solves/s
+    case 1:
+      launch_batch<64, 32, 1, 2, 16, 3>(items, refs, nref, total_tiles, st, jp, mode, st_);
+      break;
     case 2: launch_batch<32, 64, 1, 2>(items, refs, nref, total_tiles, st, jp, mode, st_); break;
     case 9: launch_batch<64, 16, 1, 1, 32>(items, refs, nref, total_tiles, st, jp, mode, st_); break;
     default: throw Error(TSYLV_EINVAL, "batch apply: unsupported tile variant");
@@ -492,8 +506,8 @@ void batch_apply(const BatchItem* items, const BatchApplyRef* refs, int nref, in
 
 // Tile shape of an instance in a batched apply: the default of its s, so an
 // instance computes the same bits in any batch.
-// the batched kernel's tiles (batch_apply_tiles): 64 x 16 with 32-deep k
-// panels up to s = 16, 64 x 32 beyond
+// the batched kernel's tiles (batch_apply_tiles): 64 x 16 up to s = 16,
+// 64 x 32 beyond
 int batch_apply_variant(int64_t s) { return s <= 16 ? 9 : 1; }
 int batch_apply_tiles(int variant, int64_t n, int64_t s, int p, int* nrt, int* nct) {
   int tm, tn;
@@ -509,11 +523,11 @@ int batch_apply_tiles(int variant, int64_t n, int64_t s, int p, int* nrt, int* n
   return num_slices(p) * *nrt * *nct;
 }
 
-int apply_variant_count(int prec) { return prec == TSYLV_BF16 ? 10 : 14; }
+int apply_variant_count(int prec) { return prec == TSYLV_BF16 ? 10 : 17; }
 
-int apply_default_variant(int prec, int64_t s) {
-  if (prec == TSYLV_FP64) return default_variant<double>(s);
-  if (prec == TSYLV_FP32) return default_variant<float>(s);
+int apply_default_variant(int prec, int64_t n, int64_t s) {
+  if (prec == TSYLV_FP64) return default_variant<double>(n, s);
+  if (prec == TSYLV_FP32) return default_variant<float>(n, s);
   return bf16_default_variant(s);
 }
 

@@ -154,7 +154,7 @@ int autotune(Ctx& ctx, int64_t n, int64_t s, int64_t p, int prec, int reps, int*
   // The default tiles stay unless another variant is at least 2 % faster:
   // closer timings are within the launch-to-launch spread, and a flip on
   // noise changes the solve's kernel for nothing.
-  const int dv = kern::apply_default_variant(prec, s);
+  const int dv = kern::apply_default_variant(prec, n, s);
   if (dv >= 0 && dv < nv && times[dv] <= 1.02f * bms) bi = dv;
   ctx.tune.set(prec, n, s, p, bi);
   if (best) *best = bi;

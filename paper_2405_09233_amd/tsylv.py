@@ -94,6 +94,7 @@ _SIGS = {
     "tsylv_tbs_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_void_p]),
     "tsylv_tbs_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                        ctypes.POINTER(Opts), ctypes.c_void_p]),
+    "tsylv_apply_default_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_int64, ctypes.c_int64]),
     "tsylv_apply_variants": (ctypes.c_int, [ctypes.c_int]),
     "tsylv_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.c_int64, ctypes.c_int, ctypes.c_int,
@@ -188,6 +189,14 @@ def apply_variants(prec):
     if n < 0:
         raise TsylvError(n, "tsylv_apply_variants")
     return n
+
+
+def apply_default_variant(prec, n, s):
+    """The apply tile variant of a shape without a tuning-table entry."""
+    v = load().tsylv_apply_default_variant(prec, n, s)
+    if v < 0:
+        raise TsylvError(v, "tsylv_apply_default_variant")
+    return v
 
 
 def apply_noalloc(A, B, X, Y=None, prec=FP64, stream=None):
