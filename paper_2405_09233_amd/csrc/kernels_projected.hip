@@ -202,7 +202,9 @@ __device__ __forceinline__ void with_slot(int c, F&& body) {
 constexpr int kUnpivoted = 1 << 20;  // position of a row not yet pivoted
 constexpr int kOutside = 1 << 21;    // position of a thread slot past the panel's rows
 
-__global__ __launch_bounds__(kLB) void proj_lu_kernel(ProjArgs a, int b) {
+// (registers capped for two workgroups per CU: 128 with 11 spilled outside
+// the column loop, 0.43 against 0.60 ms per launch at one workgroup per CU)
+__global__ __launch_bounds__(kLB, 4) void proj_lu_kernel(ProjArgs a, int b) {
   __shared__ double2 prow[kPMax + 1];     // pivot row: its columns, then its right-hand side
   __shared__ double2 lcol[2][2 * kPMax];  // multipliers / L columns by row (zero where none)
   __shared__ double2 grow[2][kPMax];      // row l of G (columns past l zero)
