@@ -24,6 +24,10 @@ namespace {
 
 constexpr int kTB = 256;    // threads per workgroup
 constexpr int kTMax = 64;   // largest block size s
+// threads of a Cholesky-QR pass (one workgroup per slice: few workgroups,
+// so each is given the most threads) and lanes per column of R^{-1}
+constexpr int kQB = 1024;
+constexpr int kQL = kQB / kTMax;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -48,7 +52,7 @@ __device__ __forceinline__ void pput(double* P, int qr, int qi, int64_t plane, i
 // diagonal is shifted by shift_factor * trace(G).  A pivot that is not
 // above rel_tol * max_i G(i, i) sets *flag (and leaves the outputs
 // undefined).
-__global__ __launch_bounds__(kTB) void cholqr_pass_kernel(const double* __restrict__ G,
+__global__ __launch_bounds__(kQB) void cholqr_pass_kernel(const double* __restrict__ G,
                                                           double* __restrict__ Rinv,
                                                           double* __restrict__ Racc, int s, int p,
                                                           double shift_factor, int first,
@@ -61,7 +65,7 @@ __global__ __launch_bounds__(kTB) void cholqr_pass_kernel(const double* __restri
   int qr, qi;
   slice_planes(p, k, qr, qi);
   const int64_t ss = (int64_t)s * s;
-  for (int e = t; e < s * s; e += kTB) R[e] = pget(G, qr, qi, ss, e);
+  for (int e = t; e < s * s; e += kQB) R[e] = pget(G, qr, qi, ss, e);
   __syncthreads();
   if (t == 0) {
     double tr = 0.0, dmax = 0.0;
@@ -87,7 +91,7 @@ __global__ __launch_bounds__(kTB) void cholqr_pass_kernel(const double* __restri
     }
     const double dinv = 1.0 / d;
     const int w = s - j - 1;
-    for (int e = t; e < w * w; e += kTB) {
+    for (int e = t; e < w * w; e += kQB) {
       const int i = j + 1 + e % w, l = j + 1 + e / w;
       if (i > l) continue;
       const double2 u = cconjmul(R[j + s * i], R[j + s * l]);
@@ -100,9 +104,9 @@ __global__ __launch_bounds__(kTB) void cholqr_pass_kernel(const double* __restri
     if (t == 0) atomicOr(flag, 1);
     return;
   }
-  for (int i = t; i < s; i += kTB) rs[i] = sqrt(R[i + s * i].x);
+  for (int i = t; i < s; i += kQB) rs[i] = sqrt(R[i + s * i].x);
   __syncthreads();
-  for (int e = t; e < s * s; e += kTB) {
+  for (int e = t; e < s * s; e += kQB) {
     const int i = e % s, l = e / s;
     if (i < l) {
       const double2 v = R[e];
@@ -113,19 +117,20 @@ __global__ __launch_bounds__(kTB) void cholqr_pass_kernel(const double* __restri
   }
   __syncthreads();
   // R^{-1} = X column by column, by back substitution: column j belongs to
-  // the four adjacent lanes 4 j .. 4 j + 3 of one wave (lane g takes the rows
-  // i = g mod 4), so each column is finished inside its wave in program
-  // order, with no barrier: for kk = j .. 0, x_kk = X(kk, j) / R(kk, kk),
-  // then X(i, j) -= R(i, kk) x_kk for i < kk.
+  // the kQL adjacent lanes kQL j .. kQL j + kQL - 1 of one wave (lane g takes
+  // the rows i = g mod kQL), so each column is finished inside its wave in
+  // program order, with no barrier: for kk = j .. 0, x_kk = X(kk, j) /
+  // R(kk, kk), then X(i, j) -= R(i, kk) x_kk for i < kk.
   {
-    const int j = t >> 2, g = t & 3;
+    static_assert(64 % kQL == 0, "a column's lanes lie in one wave");
+    const int j = t / kQL, g = t % kQL;
     if (j < s) {
-      for (int i = g; i < s; i += 4) X[i + s * j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+      for (int i = g; i < s; i += kQL) X[i + s * j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
       for (int kk = j; kk >= 0; --kk) {
         const double2 xc = X[kk + s * j];
         const double2 xk = make_double2(xc.x / rs[kk], xc.y / rs[kk]);
         if (g == 0) X[kk + s * j] = xk;
-        for (int i = g; i < kk; i += 4) {
+        for (int i = g; i < kk; i += kQL) {
           const double2 u = cmul(R[i + s * kk], xk);
           X[i + s * j].x -= u.x;
           X[i + s * j].y -= u.y;
@@ -134,16 +139,16 @@ __global__ __launch_bounds__(kTB) void cholqr_pass_kernel(const double* __restri
     }
   }
   __syncthreads();
-  for (int e = t; e < s * s; e += kTB) {
+  for (int e = t; e < s * s; e += kQB) {
     const int i = e % s, j = e / s;
     pput(Rinv, qr, qi, ss, e, i <= j ? X[e] : make_double2(0.0, 0.0));
   }
   __syncthreads();
   // Racc <- R Racc (both upper triangular), the previous Racc staged in X
   if (!first)
-    for (int e = t; e < s * s; e += kTB) X[e] = pget(Racc, qr, qi, ss, e);
+    for (int e = t; e < s * s; e += kQB) X[e] = pget(Racc, qr, qi, ss, e);
   __syncthreads();
-  for (int e = t; e < s * s; e += kTB) {
+  for (int e = t; e < s * s; e += kQB) {
     const int i = e % s, j = e / s;
     double2 acc = make_double2(0.0, 0.0);
     if (i <= j) {
@@ -333,7 +338,7 @@ int cholqr_max_block() { return kTMax; }
 void cholqr_pass(const double* G, double* Rinv, double* Racc, int s, int p, double shift_factor,
                  bool first, double rel_tol, int* flag, hipStream_t st) {
   if (s < 1 || s > kTMax) throw Error(TSYLV_EINVAL, "cholqr_pass: block too large");
-  hipLaunchKernelGGL(cholqr_pass_kernel, dim3(num_slices(p)), dim3(kTB), 0, st, G, Rinv, Racc,
+  hipLaunchKernelGGL(cholqr_pass_kernel, dim3(num_slices(p)), dim3(kQB), 0, st, G, Rinv, Racc,
                      s, p, shift_factor, first ? 1 : 0, rel_tol, flag);
   TSYLV_LAUNCH_CHECK();
 }
