@@ -891,6 +891,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default apply tiles")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--batched-only", action="store_true", help="run only the batched workload")
+    ap.add_argument("--tiny-only", action="store_true",
+                    help="run only the 8 x 8 x 4 latency measurements")
     ap.add_argument("--no-serve-full", action="store_true",
                     help="skip the batch at the full serving sizes")
     ap.add_argument("--serve-only", action="store_true",
@@ -935,6 +937,10 @@ def main():
 
     if args.apply_shape:
         print(json.dumps(apply_shape(tsylv, args.apply_shape, args.steps)), flush=True)
+        return
+
+    if args.tiny_only:
+        print(json.dumps({"tiny": tiny_latency(tsylv, workloads)}), flush=True)
         return
 
     if args.batched_only:
