@@ -36,8 +36,9 @@ Further measurements ride along (skip with --no-extra):
   serving   open-loop Poisson arrivals of requests of uneven (n, s, p)
             through tsylv_submit / tsylv_poll (the serving loop): p50/p99
             latency and throughput, FP64 and refined
-  batched   the lockstep batched engine against the serving loop and one
-            solve after another
+  batched   the batched engine (its lockstep, single-workgroup and stream
+            executors) against the serving loop and one solve after another,
+            on large, small and tiny instance mixes
 
 Prints ONE JSON line.  The roofline object is for the dominant kernel of the
 path that gives `value` (the facewise slice-product kernel), timed live with
@@ -513,13 +514,17 @@ def serving_full(tsylv, rate=40.0, duration=10.0, nbatch=128, seed=50, names=Non
 def batched_shapes(kind, count, seed):
     """Instance sizes of the batched workloads (numpy default_rng(seed)):
     'large' n = 32 round(U[256, 2048] / 32), s U{16..128}, p {8, 16, 32};
-    'small' n U{32..256}, s U{2..16}, p U{2..8}."""
+    'small' n U{32..256}, s U{2..16}, p U{2..8};
+    'tiny' n U{4..24}, s U{2..8}, p U{2..8} (the 8 x 8 x 4 case's scale)."""
     rng = np.random.default_rng(seed)
     shapes = []
     for _ in range(count):
         if kind == "large":
             shapes.append((int(32 * round(rng.uniform(256, 2048) / 32)),
                            int(rng.integers(16, 129)), int(rng.choice([8, 16, 32]))))
+        elif kind == "tiny":
+            shapes.append((int(rng.integers(4, 25)), int(rng.integers(2, 9)),
+                           int(rng.integers(2, 9))))
         else:
             shapes.append((int(rng.integers(32, 257)), int(rng.integers(2, 17)),
                            int(rng.integers(2, 9))))
@@ -544,11 +549,14 @@ def batched(tsylv, kind="large", count=256, m=30, seed=40, precs=("fp64", "fp32"
         items.append((A, B, C, torch.zeros_like(C)))
     ctx0.close()
     sizes = {"large": "n = 32 round(U[256, 2048] / 32), s U{16..128}, p {8, 16, 32}",
-             "small": "n U{32..256}, s U{2..16}, p U{2..8}"}[kind]
+             "small": "n U{32..256}, s U{2..16}, p U{2..8}",
+             "tiny": "n U{4..24}, s U{2..8}, p U{2..8}"}[kind]
     out = {"workload": "%d instances, %s (rng seed %d), dense p-scaled-noise instances drawn "
                        "on the device (Philox seeds 4000 + i), tGMRES(%d) to 1e-8; A %.2f GB "
                        "in total" % (count, sizes, seed, m,
                                      sum(n * n * p * 8 for n, s, p in shapes) / 1e9),
+           # instances with n s p <= 2^18: the lockstep executor, or the
+           # single-workgroup one for those it fits
            "lockstep_instances": int(sum(1 for n, s, p in shapes if n * s * p <= (1 << 18)))}
     all_opts = {"fp64": tsylv.default_opts(tsylv.GMRES, m=m, tol=1e-8, max_cycles=500),
                 "fp32": tsylv.default_opts(tsylv.GMRES, m=m, refine=1, prec=tsylv.FP32,
@@ -559,8 +567,10 @@ def batched(tsylv, kind="large", count=256, m=30, seed=40, precs=("fp64", "fp32"
         res = {}
         need = tsylv.Context.batch_workspace_bytes(items, opts=opts)
         ctx = tsylv.Context(need + (256 << 20), device=0)
-        # warm-up on two instances (code objects, graph path)
-        ctx.gmres_batch(items[:2], opts=opts)
+        # warm-up (code objects, graph path): two instances of the large mix,
+        # the whole batch of the small ones (whose timed batch is tens of
+        # milliseconds, so that first-use costs would otherwise dominate it)
+        ctx.gmres_batch(items[:2] if kind == "large" else items, opts=opts)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         infos = ctx.gmres_batch(items, opts=opts, raise_on_error=False)
@@ -946,7 +956,9 @@ def main():
     if args.batched_only:
         print(json.dumps({"batched": {"large": batched(tsylv, "large", 256),
                                       "small": batched(tsylv, "small", 256,
-                                                       precs=("fp64",))}}), flush=True)
+                                                       precs=("fp64",)),
+                                      "tiny": batched(tsylv, "tiny", 256,
+                                                      precs=("fp64",))}}), flush=True)
         return
 
     full_names = [x for x in args.serve_full_paths.split(",") if x] or None
@@ -1041,7 +1053,8 @@ def main():
         if not args.no_batched:
             log("batched workload ...")
             out["batched"] = {"large": batched(tsylv, "large", 256),
-                              "small": batched(tsylv, "small", 256, precs=("fp64",))}
+                              "small": batched(tsylv, "small", 256, precs=("fp64",)),
+                              "tiny": batched(tsylv, "tiny", 256, precs=("fp64",))}
         if not args.no_serve_full:
             log("serving at full sizes ...")
             out["serving"]["full_sizes"] = serving_full(tsylv, args.serve_full_rate,

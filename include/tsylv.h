@@ -187,7 +187,13 @@ int tsylv_tbs(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A,
  * restarted tGMRES(m) -- optionally inside FP64 iterative refinement as in
  * tsylv_gmres).  Each instance runs on the executor that suits it, chosen
  * from the instance alone:
- *   - small FP64 instances (n s p <= 2^18) advance in lockstep: every kernel
+ *   - FP64 instances small enough for a whole solve in one workgroup (those
+ *     tsylv_gmres itself solves that way: n s p, the operator planes and
+ *     two basis vectors within the workgroup's LDS, m n s p <= 2^18) are
+ *     solved by one launch for all of them, a workgroup per instance
+ *     running its whole Algorithm 3; each result is bitwise the
+ *     tsylv_gmres solve with these opts;
+ *   - other small FP64 instances (n s p <= 2^18) advance in lockstep: every kernel
  *     launch of an Arnoldi step serves all of them (work items over the
  *     instances' tiles and vector chunks; classical Gram-Schmidt applied
  *     twice), the Givens rotations and the stop tests run on the device,
@@ -260,9 +266,11 @@ int tsylv_generate(tsylv_ctx* ctx, uint64_t seed, int64_t n, int64_t s, int64_t 
  * workspace fits in the arena; admitted requests are stepped together on the
  * GPU.  Requests of method TSYLV_METHOD_GMRES_BATCHED (FP64, m <= 63, X0 =
  * 0) that wait in the queue together with equal options are admitted as one
- * lockstep batch (tsylv_gmres_batch: one launch per step stage for all of
- * them, the step replayed from a HIP graph, Givens on the device); each
- * result is bitwise the batch-of-one solve of its instance.  The pointers in the request must stay valid until tsylv_poll returns
+ * batch run by tsylv_gmres_batch's in-GPU executors (instances that fit one
+ * workgroup: one launch for all of them; the others in lockstep: one launch
+ * per step stage for all of them, the step replayed from a HIP graph,
+ * Givens on the device); each result is bitwise the batch-of-one solve of
+ * its instance.  The pointers in the request must stay valid until tsylv_poll returns
  * a final status for its ticket.  A request with A, B and C all NULL solves
  * the synthetic instance of `gen_seed` (tsylv_generate), drawn on the device
  * inside its setup transforms, so that the spatial tensors are never stored

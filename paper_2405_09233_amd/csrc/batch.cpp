@@ -28,6 +28,7 @@
 // the GPU) and slower small batches (more launches), so one group is used.
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -401,6 +402,132 @@ bool lockstep_instance(const tsylv_problem& q, const tsylv_opts& o) {
   return !o.refine && q.n * q.s * q.p <= kLockstepMaxElems;
 }
 
+// Instances small enough for a whole solve in one workgroup (the single
+// solve's criterion, kern::tiny_krylov_fits; TSYLV_KRYLOV_TINY=0 turns it
+// off here too) are solved by one launch for all of them.
+bool tiny_instance(const tsylv_problem& q, const tsylv_opts& o) {
+  if (o.refine) return false;
+  const char* f = std::getenv("TSYLV_KRYLOV_TINY");
+  if (f && f[0] == '0') return false;
+  return kern::tiny_krylov_fits(q.n, q.s, q.p, o.m);
+}
+
+size_t tiny_batch_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o) {
+  if (count <= 0) return 0;
+  size_t b = Workspace::bytes_for((int64_t)count, sizeof(kern::TinyJob)) +
+             Workspace::bytes_for((int64_t)count * kern::kTinyRecord, 8);
+  for (int i = 0; i < count; ++i) {
+    const int64_t N = probs[i].n * probs[i].s * probs[i].p;
+    b += setup_bytes(probs[i].n, probs[i].s, probs[i].p) +
+         Workspace::bytes_for((int64_t)(o.m + 1) * N, 8) +
+         Workspace::bytes_for((int64_t)o.m * o.m, 8);
+  }
+  return b;
+}
+
+// The single-workgroup executor: every instance's setup transforms, one
+// launch that runs each instance's whole restarted tGMRES(m) in a
+// workgroup of its own (Algorithm 3 on the device, kern::tiny_krylov_batch),
+// the inverse transforms, one copy of the result records.  It runs on a
+// stream of its own, ordered after the caller's stream, beside the lockstep
+// executor (whose instances fill the rest of the GPU); finish() waits for
+// it.  An instance's arithmetic is that of its single solve (tsylv_gmres
+// takes the same kernel for it), in any batch.
+class TinyExec {
+ public:
+  TinyExec(Ctx& ctx, hipStream_t parent, int count, const tsylv_problem* probs,
+           const uint64_t* const* gens, const tsylv_opts& o)
+      : ws_(ctx.arena, tiny_batch_bytes(count, probs, o)), count_(count) {
+    TSYLV_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+    TSYLV_HIP(hipEventCreateWithFlags(&ready_, hipEventDisableTiming));
+    TSYLV_HIP(hipEventRecord(ready_, parent));
+    TSYLV_HIP(hipStreamWaitEvent(s_, ready_, 0));
+    setups_.resize(count);
+    jobs_.resize(count);
+    rec_ = ws_.take<double>((int64_t)count * kern::kTinyRecord);
+    size_t lds = 0;
+    for (int i = 0; i < count; ++i)
+      lds = std::max(lds, kern::tiny_krylov_lds(probs[i].n, probs[i].s, probs[i].p, o.m));
+    for (int i = 0; i < count; ++i) {
+      const tsylv_problem& q = probs[i];
+      const int64_t N = q.n * q.s * q.p;
+      setups_[i] = setup_fourier(ctx, s_, false, ws_, q.n, q.s, q.p, q.A, q.B, q.C, q.X,
+                                 o.x0_given != 0, gens ? gens[i] : nullptr);
+      kern::TinyJob& j = jobs_[i];
+      j.Ah = setups_[i].Ah;
+      j.Bh = setups_[i].Bh;
+      j.Zc = setups_[i].Zc;
+      j.Zx = setups_[i].Zx;
+      j.Vg = ws_.take<double>((int64_t)(o.m + 1) * N);
+      j.Rg = ws_.take<double>((int64_t)o.m * o.m);
+      j.hist = nullptr;
+      j.hist_cap = 0;
+      j.out = rec_ + (int64_t)i * kern::kTinyRecord;
+      j.tol = o.tol;
+      j.n = (int)q.n;
+      j.s = (int)q.s;
+      j.p = (int)q.p;
+      j.m = o.m;
+      j.max_cycles = std::max(o.max_cycles, 0);
+      j.fom = 0;
+      j.x0_given = o.x0_given != 0 ? 1 : 0;
+      j.lslots = kern::tiny_krylov_slots(q.n, q.s, q.p, o.m, lds);
+    }
+    kern::TinyJob* d_jobs = ws_.take<kern::TinyJob>(count);
+    // (jobs_ stays until the stream has been waited for)
+    TSYLV_HIP(hipMemcpyAsync(d_jobs, jobs_.data(), sizeof(kern::TinyJob) * count,
+                             hipMemcpyHostToDevice, s_));
+    kern::tiny_krylov_batch(d_jobs, count, lds, s_);
+    for (int i = 0; i < count; ++i)
+      kern::tube_xform_f64(setups_[i].Zx, probs[i].X, setups_[i].xf_inv,
+                           probs[i].n * probs[i].s, (int)probs[i].p, s_);
+  }
+  ~TinyExec() {
+    if (s_) {
+      (void)hipStreamSynchronize(s_);
+      (void)hipStreamDestroy(s_);
+    }
+    if (ready_) (void)hipEventDestroy(ready_);
+  }
+  TinyExec(const TinyExec&) = delete;
+  TinyExec& operator=(const TinyExec&) = delete;
+
+  // Waits for the launch; the records to infos (in the batch's order) and
+  // the caller's stream ordered after this executor's work.  Returns
+  // TSYLV_OK or TSYLV_NOT_CONVERGED (some instance did not converge).
+  int finish(hipStream_t parent, tsylv_info* infos) {
+    std::vector<double> h((size_t)count_ * kern::kTinyRecord);
+    TSYLV_HIP(hipMemcpyAsync(h.data(), rec_, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             s_));
+    TSYLV_HIP(hipStreamSynchronize(s_));
+    TSYLV_HIP(hipEventRecord(ready_, s_));
+    TSYLV_HIP(hipStreamWaitEvent(parent, ready_, 0));
+    int worst = TSYLV_OK;
+    for (int i = 0; i < count_; ++i) {
+      const double* r = h.data() + (size_t)i * kern::kTinyRecord;
+      tsylv_info& in = infos[i];
+      in = tsylv_info{};
+      in.status = (int)r[0];
+      in.steps = (int)r[1];
+      in.cycles = (int)r[2];
+      in.relres_true = r[3];
+      in.relres_est = r[4];
+      in.fom_fallback = (int)r[5];
+      if (in.status != TSYLV_OK) worst = TSYLV_NOT_CONVERGED;
+    }
+    return worst;
+  }
+
+ private:
+  Workspace ws_;
+  int count_;
+  hipStream_t s_ = nullptr;
+  hipEvent_t ready_ = nullptr;
+  std::vector<Setup> setups_;
+  std::vector<kern::TinyJob> jobs_;
+  double* rec_ = nullptr;
+};
+
 // Up to kTaskStreams solves at a time, each a KrylovTask (the synchronous
 // solve's object) on its own stream, advanced as its stream finishes a
 // phase; admitted in order while the arena holds their workspaces.
@@ -506,33 +633,59 @@ int run_tasks(Ctx& ctx, hipStream_t st, const std::vector<int>& ids, const tsylv
 }  // namespace
 
 size_t batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o) {
-  std::vector<tsylv_problem> lock;
+  std::vector<tsylv_problem> lock, tiny;
   std::vector<size_t> task_bytes;
   for (int i = 0; i < count; ++i) {
-    if (lockstep_instance(probs[i], o))
+    if (tiny_instance(probs[i], o))
+      tiny.push_back(probs[i]);
+    else if (lockstep_instance(probs[i], o))
       lock.push_back(probs[i]);
     else
       task_bytes.push_back(
           krylov_workspace_bytes(TSYLV_METHOD_GMRES, probs[i].n, probs[i].s, probs[i].p, o));
   }
   // the stream executor runs first, up to kTaskStreams workspaces at once;
-  // the lockstep batch after it
+  // the lockstep batch after it, then the single-workgroup one
   std::sort(task_bytes.begin(), task_bytes.end(), std::greater<size_t>());
   size_t tb = 0;
   for (size_t k = 0; k < task_bytes.size() && k < (size_t)kTaskStreams; ++k) tb += task_bytes[k];
-  return std::max(tb, lockstep_workspace_bytes((int)lock.size(), lock.data(), o));
+  // then the lockstep and single-workgroup executors side by side
+  return std::max(tb, lockstep_workspace_bytes((int)lock.size(), lock.data(), o) +
+                          tiny_batch_bytes((int)tiny.size(), tiny.data(), o));
+}
+
+size_t served_batch_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o) {
+  std::vector<tsylv_problem> lock, tiny;
+  for (int i = 0; i < count; ++i) (tiny_instance(probs[i], o) ? tiny : lock).push_back(probs[i]);
+  return lockstep_workspace_bytes((int)lock.size(), lock.data(), o) +
+         tiny_batch_bytes((int)tiny.size(), tiny.data(), o);
 }
 
 int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
                 const uint64_t* const* gens, const tsylv_opts& o, tsylv_info* infos,
-                bool use_graph, bool lockstep_only) {
+                bool use_graph, bool no_streams) {
   const auto t0 = std::chrono::steady_clock::now();
-  std::vector<int> lock, tasks;
-  for (int i = 0; i < count; ++i)
-    (lockstep_only || lockstep_instance(probs[i], o) ? lock : tasks).push_back(i);
+  std::vector<int> lock, tasks, tiny;
+  for (int i = 0; i < count; ++i) {
+    if (tiny_instance(probs[i], o))
+      tiny.push_back(i);
+    else
+      (no_streams || lockstep_instance(probs[i], o) ? lock : tasks).push_back(i);
+  }
   int worst = TSYLV_OK;
   if (!tasks.empty() && run_tasks(ctx, st, tasks, probs, gens, o, infos) != TSYLV_OK)
     worst = TSYLV_NOT_CONVERGED;
+  // the single-workgroup executor launches first and runs beside the
+  // lockstep batch
+  std::vector<tsylv_problem> tp;
+  std::vector<const uint64_t*> tg;
+  for (int i : tiny) {
+    tp.push_back(probs[i]);
+    tg.push_back(gens ? gens[i] : nullptr);
+  }
+  std::unique_ptr<TinyExec> tex;
+  if (!tiny.empty())
+    tex.reset(new TinyExec(ctx, st, (int)tiny.size(), tp.data(), gens ? tg.data() : nullptr, o));
   if (!lock.empty()) {
     std::vector<tsylv_problem> lp;
     std::vector<const uint64_t*> lg;
@@ -545,6 +698,11 @@ int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
                        li.data(), use_graph) != TSYLV_OK)
       worst = TSYLV_NOT_CONVERGED;
     for (size_t k = 0; k < lock.size(); ++k) infos[lock[k]] = li[k];
+  }
+  if (tex) {
+    std::vector<tsylv_info> ti(tiny.size());
+    if (tex->finish(st, ti.data()) != TSYLV_OK) worst = TSYLV_NOT_CONVERGED;
+    for (size_t k = 0; k < tiny.size(); ++k) infos[tiny[k]] = ti[k];
   }
   const double secs =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -295,6 +295,26 @@ constexpr int kTinyRecord = 8;
 void tiny_krylov(const double* Ah, const double* Bh, const double* Zc, double* Zx, double* basis,
                  double* Rg, double* hist, int hist_cap, double* out, int n, int s, int p, int m,
                  int max_cycles, bool fom, bool x0_given, double tol, hipStream_t st);
+// Many such solves in one launch, one workgroup per job (each job's fields
+// as the arguments of tiny_krylov; lslots from tiny_krylov_slots for the
+// launch's LDS size).  tiny_krylov_lds: the LDS bytes that hold every basis
+// slot of a shape (at most the workgroup's LDS); a batch launches with the
+// largest of its jobs'.
+struct TinyJob {
+  const double* Ah;
+  const double* Bh;
+  const double* Zc;
+  double* Zx;
+  double* Vg;
+  double* Rg;
+  double* hist;
+  double* out;
+  double tol;
+  int n, s, p, m, max_cycles, fom, x0_given, hist_cap, lslots;
+};
+size_t tiny_krylov_lds(int64_t n, int64_t s, int64_t p, int m);
+int tiny_krylov_slots(int64_t n, int64_t s, int64_t p, int m, size_t lds);
+void tiny_krylov_batch(const TinyJob* jobs, int count, size_t lds, hipStream_t st);
 
 // ---- batched lockstep tGMRES (many independent instances per launch) ----
 //

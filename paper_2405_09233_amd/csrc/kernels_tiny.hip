@@ -38,18 +38,13 @@ constexpr int kYMaxM = 1024;       // longest restart handled here
 constexpr int64_t kYMaxMN = 1 << 18;  // largest m n s p (bounds a cycle's basis work)
 constexpr int kYScal = 16;         // scalars exchanged through LDS
 
-struct TinyArgs {
-  const double* Ah;  // p planes of n x n (unscaled Fourier slices)
-  const double* Bh;  // p planes of s x s
-  const double* Zc;  // C in orthonormal planes (N)
-  double* Zx;        // X0 on entry when x0_given, X on exit (N)
-  double* Vg;        // (m + 1) N: the basis slots that do not fit in LDS
-  double* Rg;        // m x m: rotated Hessenberg columns (column j: j + 1 entries)
-  double* hist;      // hist_cap relative residual estimates
-  double* out;       // result record of kTinyRecord doubles
-  double tol;
-  int n, s, p, m, max_cycles, fom, x0_given, hist_cap, lslots;
-};
+// One solve's arguments (TinyJob): the p planes of Ahat (n x n) and Bhat
+// (s x s), unscaled Fourier slices; C in orthonormal planes (N = n s p);
+// X0 on entry when x0_given and X on exit in Zx; Vg: (m + 1) N doubles for
+// the basis slots past the lslots in LDS; Rg: m x m, the rotated Hessenberg
+// columns (column j: j + 1 entries); hist: hist_cap relative residual
+// estimates; out: the result record of kTinyRecord doubles.
+using TinyArgs = TinyJob;
 
 // LDS doubles besides the basis slots: X, the operator planes, cs, sn, g,
 // two projections, the current column, the scalars.
@@ -204,7 +199,7 @@ __device__ bool tiny_back_serial(const double* R, int m, int k, const double* r,
   return true;
 }
 
-__global__ __launch_bounds__(kYT) void tiny_krylov_kernel(TinyArgs a) {
+__device__ void tiny_solve(const TinyArgs& a) {
   extern __shared__ double lds[];
   const int t = threadIdx.x;
   const int n = a.n, s = a.s, p = a.p, m = a.m, N = n * s * p;
@@ -388,6 +383,14 @@ __global__ __launch_bounds__(kYT) void tiny_krylov_kernel(TinyArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kYT) void tiny_krylov_kernel(TinyArgs a) { tiny_solve(a); }
+
+// One workgroup per job of a batch.
+__global__ __launch_bounds__(kYT) void tiny_krylov_batch_kernel(const TinyArgs* __restrict__ jobs) {
+  const TinyArgs a = jobs[blockIdx.x];
+  tiny_solve(a);
+}
+
 }  // namespace
 
 bool tiny_krylov_fits(int64_t n, int64_t s, int64_t p, int m) {
@@ -395,6 +398,26 @@ bool tiny_krylov_fits(int64_t n, int64_t s, int64_t p, int m) {
   if (n < 1 || s < 1 || p < 1 || m < 1 || N > kYMaxN || m > kYMaxM || m * N > kYMaxMN)
     return false;
   return (fixed_doubles(n, s, p, m) + 2 * N) * (int64_t)sizeof(double) <= kYLds;
+}
+
+size_t tiny_krylov_lds(int64_t n, int64_t s, int64_t p, int m) {
+  const int64_t need = (fixed_doubles(n, s, p, m) + (int64_t)(m + 1) * n * s * p) * 8;
+  return (size_t)std::min<int64_t>(need, kYLds);
+}
+
+int tiny_krylov_slots(int64_t n, int64_t s, int64_t p, int m, size_t lds) {
+  const int64_t N = n * s * p;
+  const int64_t fit = ((int64_t)lds / (int64_t)sizeof(double) - fixed_doubles(n, s, p, m)) / N;
+  return (int)std::min<int64_t>(m + 1, fit);
+}
+
+void tiny_krylov_batch(const TinyJob* jobs, int count, size_t lds, hipStream_t st) {
+  if (count <= 0) return;
+  if (lds > (size_t)kYLds) throw Error(TSYLV_EINVAL, "tiny Krylov batch: LDS too large");
+  TSYLV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&tiny_krylov_batch_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(tiny_krylov_batch_kernel, dim3(count), dim3(kYT), lds, st, jobs);
+  TSYLV_LAUNCH_CHECK();
 }
 
 void tiny_krylov(const double* Ah, const double* Bh, const double* Zc, double* Zx, double* basis,

@@ -22,13 +22,14 @@
 //
 // Requests of method GMRES_BATCHED that wait at the head of the queue with
 // equal options are admitted together, up to kMaxBatch of them and as many as
-// the arena holds, as one lockstep batch (batch.cpp) that takes one slot and
-// runs on a worker thread on the slot's stream, its step replayed from a
-// graph of kernel nodes recorded on the worker (no stream capture, so the
-// caller's concurrent work on the legacy default stream cannot interfere);
-// the scheduler posts every result of the batch when the worker ends.  An
-// instance's result in a batch is bitwise its batch-of-one result (graph or
-// eager: the same kernels).
+// the arena holds, as one batch (batch.cpp, without its stream executor)
+// that takes one slot and runs on a worker thread on the slot's stream:
+// instances that fit one workgroup in one launch, the others in lockstep,
+// the lockstep step replayed from a graph of kernel nodes recorded on the
+// worker (no stream capture, so the caller's concurrent work on the legacy
+// default stream cannot interfere); the scheduler posts every result of the
+// batch when the worker ends.  An instance's result in a batch is bitwise
+// its batch-of-one result (graph or eager: the same kernels).
 #include <atomic>
 #include <cstdlib>
 #include <chrono>
@@ -59,7 +60,7 @@ bool same_batch_opts(const tsylv_opts& a, const tsylv_opts& b) {
   return a.m == b.m && a.tol == b.tol && a.max_cycles == b.max_cycles;
 }
 
-// A lockstep batch of GMRES_BATCHED requests, run by a worker thread.
+// A batch of GMRES_BATCHED requests, run by a worker thread.
 struct BatchJob {
   std::vector<uint64_t> tickets;
   std::vector<tsylv_request> reqs;
@@ -101,7 +102,7 @@ struct Scheduler {
     int error = 0;
     hipEvent_t ready = nullptr;  // the submit event (destroyed at retirement)
     bool in_flight = false;  // a phase is enqueued and not yet completed
-    std::unique_ptr<BatchJob> job;  // a lockstep batch instead of one task
+    std::unique_ptr<BatchJob> job;  // a batch instead of one task
   };
   std::vector<Active> active;
   std::vector<int> free_slots;
@@ -168,7 +169,7 @@ struct Scheduler {
         return krylov_workspace_bytes(r.method, r.n, r.s, r.p, r.opts);
       };
       v.need_batch = [&](size_t k) {
-        return lockstep_workspace_bytes((int)k, probs.data(), queue.front().r.opts);
+        return served_batch_bytes((int)k, probs.data(), queue.front().r.opts);
       };
       const policy::Decision d = policy::next_admission(
           v, free_slots.size(), ctx.arena.largest_free(), ctx.arena.capacity(), kMaxBatch);
@@ -251,7 +252,7 @@ struct Scheduler {
         // the step replayed from a recorded graph (TSYLV_BATCH_GRAPH=0: eager)
         const char* g = std::getenv("TSYLV_BATCH_GRAPH");
         gmres_batch(ctx, st, (int)jp->probs.size(), jp->probs.data(), jp->gens.data(), o,
-                    jp->infos.data(), !(g && g[0] == '0'), /*lockstep_only=*/true);
+                    jp->infos.data(), !(g && g[0] == '0'), /*no_streams=*/true);
       } catch (const Error& e) {
         jp->error = e.status;
       } catch (...) {

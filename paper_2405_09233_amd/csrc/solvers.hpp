@@ -41,12 +41,15 @@ int krylov_solve(Ctx& ctx, int method, int64_t n, int64_t s, int64_t p, const do
                  const double* B, const double* C, double* X, const tsylv_opts& o,
                  tsylv_info& info);
 
-// Batched tGMRES (batch.cpp): small FP64 instances (n s p <= 2^18) in
+// Batched tGMRES (batch.cpp): FP64 instances that fit one workgroup solved
+// whole by one launch, other small FP64 instances (n s p <= 2^18) in
 // lockstep (restart length o.m <= 63), the rest, and every instance of a
-// refined batch, as concurrent solves on eight streams; workspace of both.
+// refined batch, as concurrent solves on eight streams; workspace of all.
 size_t batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o);
 // Workspace of the lockstep executor alone (every instance in lockstep).
 size_t lockstep_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o);
+// Workspace of a batch run without the stream executor (no_streams).
+size_t served_batch_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o);
 // Batched t-Bartels-Stewart (tbs_batch.cpp): 0 bytes when an instance is
 // outside 1 <= n, s <= 64, 1 <= p <= 4096 or has a null pointer.
 size_t tbs_batch_workspace_bytes(int count, const tsylv_problem* probs);
@@ -54,12 +57,15 @@ int tbs_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts&
               tsylv_info* infos);
 // On stream `st`; gens (may be null): gens[i] non-null draws instance i as
 // the synthetic instance of seed *gens[i] (its A, B, C are not read).
-// lockstep_only: every instance in lockstep (FP64 batches of the serving
-// loop, which runs its batches concurrently itself; the stream executor's
-// pinned staging is the context's, for one caller at a time).
+// no_streams: no stream executor -- the instances it would take run in
+// lockstep (FP64 batches of the serving loop, which runs its batches
+// concurrently itself; the stream executor's pinned staging is the
+// context's, for one caller at a time); instances that fit one workgroup
+// keep that executor, so a served instance computes what its batch of one
+// does.
 int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
                 const uint64_t* const* gens, const tsylv_opts& o, tsylv_info* infos,
-                bool use_graph, bool lockstep_only = false);
+                bool use_graph, bool no_streams = false);
 
 // Autotuner (tune.cpp): times every tile variant of the apply at (n, s, p)
 // in precision `prec` (`reps` launches each), stores the fastest in

@@ -18,6 +18,10 @@
   tsylv_gmres solve, a refined batch's results are bitwise the refined
   single solves and match the oracle.
 * Malformed batches are rejected.
+
+Instances small enough for the single-workgroup executor are sent to the
+lockstep kernels here (TSYLV_KRYLOV_TINY=0 for every test of this module):
+that executor has its own tests (test_gpu_tiny.py).
 """
 
 import os
@@ -30,6 +34,11 @@ from paper_2405_09233_amd import tsylv, workloads
 from gpu_util import ctx, dev, host, say, rel
 
 SMALL = [(12, 5, 4), (20, 18, 3), (9, 40, 2), (30, 6, 1), (16, 10, 5), (25, 3, 7)]
+
+
+@pytest.fixture(autouse=True)
+def _lockstep_and_stream_executors(monkeypatch):
+    monkeypatch.setenv("TSYLV_KRYLOV_TINY", "0")
 
 
 def _batch(shapes, seed0):

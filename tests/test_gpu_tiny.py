@@ -14,7 +14,10 @@ driver instead.  Bars:
   * a happy breakdown (the Krylov space exhausts the n s p unknowns before
     m steps) gives the exact solution;
   * the residual-estimate history has one entry per step and decreases
-    within each tGMRES cycle.
+    within each tGMRES cycle;
+  * tsylv_gmres_batch solves such instances in one launch, one workgroup
+    each: every result bitwise the single solve's (the same kernel), alone
+    or in a batch, next to instances that take the lockstep executor.
 """
 
 import time
@@ -143,3 +146,69 @@ def test_tiny_latency_below_multi_launch(monkeypatch):
     say("8x8x4 unrestarted tGMRES p50: one workgroup %.1f us, multi-launch %.1f us"
         % (t_tiny * 1e6, t_multi * 1e6))
     assert t_tiny < 0.5 * t_multi
+
+
+def _items(shapes, seed0):
+    import torch
+    data, items = [], []
+    for k, (n, s, p) in enumerate(shapes):
+        A, B, C = workloads.dense_shifted(n, s, p, seed=seed0 + k)
+        Cd = dev(C)
+        data.append((A, B, C))
+        items.append((dev(A), dev(B), Cd, torch.zeros_like(Cd)))
+    return data, items
+
+
+@pytest.mark.gpu
+def test_batch_of_small_instances_in_one_launch():
+    import torch
+    # ragged sizes, p odd and even, and one whose basis spills to global memory
+    shapes = [(8, 6, 4), (12, 5, 3), (9, 4, 1), (10, 3, 2), (16, 5, 6), (40, 6, 5), (20, 7, 4)]
+    say("tiny batch", shapes)
+    c = ctx()
+    data, items = _items(shapes, 1200)
+    infos = c.gmres_batch(items, m=30, tol=1e-11, max_cycles=100)
+    for k, ((A, B, C), (Ad, Bd, Cd, X), info) in enumerate(zip(data, items, infos)):
+        assert info.status == 0, (k, info.as_dict())
+        assert info.relres_true <= 1e-11
+        assert rel(host(X), kron.kron_solve(A, B, C)) <= 1e-8
+        Xs, i1 = c.gmres(Ad, Bd, Cd, m=30, tol=1e-11, max_cycles=100)
+        assert torch.equal(X, Xs), k
+        assert (i1.steps, i1.cycles, i1.relres_true) == (info.steps, info.cycles,
+                                                         info.relres_true)
+    # alone as a batch of one
+    Ad, Bd, Cd, X = items[5]
+    Xa = torch.zeros_like(Cd)
+    ia = c.gmres_batch([(Ad, Bd, Cd, Xa)], m=30, tol=1e-11, max_cycles=100)[0]
+    assert torch.equal(Xa, X) and ia.steps == infos[5].steps
+
+
+@pytest.mark.gpu
+def test_batch_mixes_single_workgroup_and_lockstep(monkeypatch):
+    import torch
+    shapes = [(8, 6, 4), (200, 16, 8), (14, 9, 3), (128, 12, 5)]
+    say("tiny + lockstep batch", shapes)
+    c = ctx()
+    data, items = _items(shapes, 1300)
+    infos = c.gmres_batch(items, m=20, tol=1e-11, max_cycles=200)
+    assert all(i.status == 0 for i in infos), [i.as_dict() for i in infos]
+    for (A, B, C), (Ad, Bd, Cd, X), info in zip(data, items, infos):
+        assert info.relres_true <= 1e-11
+        Xs, _ = c.gmres(Ad, Bd, Cd, m=20, tol=1e-11, max_cycles=200)
+        assert rel(host(X), host(Xs)) <= 1e-8
+    for k in (0, 2):  # the small ones: bitwise their single solves
+        Ad, Bd, Cd, X = items[k]
+        Xs, _ = c.gmres(Ad, Bd, Cd, m=20, tol=1e-11, max_cycles=200)
+        assert torch.equal(X, Xs), k
+    # per-instance stopping and X0, as in the lockstep executor
+    for it in items:
+        it[3].zero_()
+    i2 = c.gmres_batch(items, m=2, tol=1e-12, max_cycles=1, raise_on_error=False)
+    assert all(i.status == 1 and i.cycles == 1 and i.steps == 2 for i in i2)
+    o = tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-11, max_cycles=100)
+    o.x0_given = 1
+    i3 = c.gmres_batch(items, opts=o)
+    assert all(i.status == 0 for i in i3)
+    for (A, B, C), (_, _, _, X) in zip(data, items):
+        if A.shape[0] <= 16:
+            assert rel(host(X), kron.kron_solve(A, B, C)) <= 1e-8

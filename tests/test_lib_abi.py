@@ -80,19 +80,27 @@ def test_default_opts_and_workspace_query():
     assert tsylv.workspace_bytes(tsylv.APPLY, 8, 6, 4, None) > 0
 
 
-def test_batch_workspace_query():
-    """The batch plan's byte count without a device: each instance's
-    Fourier setup and basis plus the shared tables; malformed batches give 0."""
+def test_batch_workspace_query(monkeypatch):
+    """The batch plan's byte count without a device: each lockstep
+    instance's Fourier setup and basis plus the shared tables; an instance
+    small enough for the single-workgroup executor (run after the lockstep
+    batch, in a workspace of its own) needs its setup and basis; malformed
+    batches give 0."""
     probs = (tsylv.Problem * 2)()
-    for k, (n, s, p) in enumerate([(100, 8, 5), (40, 3, 2)]):
+    shapes = [(100, 8, 5), (40, 3, 2)]
+    for k, (n, s, p) in enumerate(shapes):
         probs[k].n, probs[k].s, probs[k].p = n, s, p
         probs[k].A = probs[k].B = probs[k].C = probs[k].X = 4096  # never dereferenced
     o = tsylv.default_opts(tsylv.GMRES, m=20)
     lib = tsylv.load()
+    floors = [8 * (p * n * n + p * s * s + 3 * p * p + (o.m + 4) * n * s * p)
+              for n, s, p in shapes]
     b = lib.tsylv_batch_workspace_bytes(2, probs, ctypes.byref(o))
-    floor = sum(8 * (p * n * n + p * s * s + 3 * p * p + (o.m + 4) * n * s * p)
-                for n, s, p in [(100, 8, 5), (40, 3, 2)])
-    assert b >= floor
+    assert b >= max(floors)
+    monkeypatch.setenv("TSYLV_KRYLOV_TINY", "0")  # both instances in lockstep
+    b = lib.tsylv_batch_workspace_bytes(2, probs, ctypes.byref(o))
+    assert b >= sum(floors)
+    monkeypatch.delenv("TSYLV_KRYLOV_TINY")
     assert lib.tsylv_batch_workspace_bytes(0, probs, ctypes.byref(o)) == 0
     o.m = 64  # beyond the batch's restart limit
     assert lib.tsylv_batch_workspace_bytes(2, probs, ctypes.byref(o)) == 0
