@@ -31,6 +31,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <memory>
 #include <thread>
 #include <vector>
@@ -402,6 +403,10 @@ bool lockstep_instance(const tsylv_problem& q, const tsylv_opts& o) {
   return !o.refine && q.n * q.s * q.p <= kLockstepMaxElems;
 }
 
+int xform_blocks(int64_t E) {
+  return (int)((E + kern::kBatchXformBlock - 1) / kern::kBatchXformBlock);
+}
+
 // Instances small enough for a whole solve in one workgroup (the single
 // solve's criterion, kern::tiny_krylov_fits; TSYLV_KRYLOV_TINY=0 turns it
 // off here too) are solved by one launch for all of them.
@@ -414,8 +419,13 @@ bool tiny_instance(const tsylv_problem& q, const tsylv_opts& o) {
 
 size_t tiny_batch_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o) {
   if (count <= 0) return 0;
+  // (per instance: its Fourier setup, which bounds what the shared
+  // transform matrices and X0 planes take; at most four forward and one
+  // inverse transform descriptor)
   size_t b = Workspace::bytes_for((int64_t)count, sizeof(kern::TinyJob)) +
-             Workspace::bytes_for((int64_t)count * kern::kTinyRecord, 8);
+             Workspace::bytes_for((int64_t)count * kern::kTinyRecord, 8) +
+             Workspace::bytes_for(5 * (int64_t)count, sizeof(kern::XformDesc)) +
+             Workspace::bytes_for(5 * (int64_t)count + 2, sizeof(int));
   for (int i = 0; i < count; ++i) {
     const int64_t N = probs[i].n * probs[i].s * probs[i].p;
     b += setup_bytes(probs[i].n, probs[i].s, probs[i].p) +
@@ -442,22 +452,67 @@ class TinyExec {
     TSYLV_HIP(hipEventCreateWithFlags(&ready_, hipEventDisableTiming));
     TSYLV_HIP(hipEventRecord(ready_, parent));
     TSYLV_HIP(hipStreamWaitEvent(s_, ready_, 0));
-    setups_.resize(count);
     jobs_.resize(count);
     rec_ = ws_.take<double>((int64_t)count * kern::kTinyRecord);
     size_t lds = 0;
     for (int i = 0; i < count; ++i)
       lds = std::max(lds, kern::tiny_krylov_lds(probs[i].n, probs[i].s, probs[i].p, o.m));
+    // Algorithm 1 step 1 for every stored instance in one launch (with one
+    // set of transform matrices per distinct p and one zero fill of their
+    // X0 planes), Algorithm 1 step 3 for every X in another; an instance
+    // whose tensors are generated takes the single solve's setup.
+    const bool x0 = o.x0_given != 0;
+    struct Mats {
+      double *op, *fwd, *inv;
+    };
+    std::map<int64_t, Mats> mats;
+    auto mats_of = [&](int64_t p) {
+      auto it = mats.find(p);
+      if (it != mats.end()) return it->second;
+      const Mats M{ws_.take<double>(p * p), ws_.take<double>(p * p), ws_.take<double>(p * p)};
+      kern::build_xform(M.op, (int)p, XF_OPERATOR, s_);
+      kern::build_xform(M.fwd, (int)p, XF_FORWARD, s_);
+      kern::build_xform(M.inv, (int)p, XF_INVERSE, s_);
+      mats.emplace(p, M);
+      return M;
+    };
+    int64_t zx_total = 0;
+    for (int i = 0; i < count; ++i)
+      if (!(gens && gens[i])) zx_total += probs[i].n * probs[i].s * probs[i].p;
+    double* zx = ws_.take<double>(zx_total);
+    if (zx_total > 0 && !x0)
+      TSYLV_HIP(hipMemsetAsync(zx, 0, zx_total * sizeof(double), s_));
+    std::vector<kern::XformDesc> fwd, inv;
     for (int i = 0; i < count; ++i) {
       const tsylv_problem& q = probs[i];
       const int64_t N = q.n * q.s * q.p;
-      setups_[i] = setup_fourier(ctx, s_, false, ws_, q.n, q.s, q.p, q.A, q.B, q.C, q.X,
-                                 o.x0_given != 0, gens ? gens[i] : nullptr);
       kern::TinyJob& j = jobs_[i];
-      j.Ah = setups_[i].Ah;
-      j.Bh = setups_[i].Bh;
-      j.Zc = setups_[i].Zc;
-      j.Zx = setups_[i].Zx;
+      const double* xf_inv;
+      if (gens && gens[i]) {
+        const Setup S = setup_fourier(ctx, s_, false, ws_, q.n, q.s, q.p, q.A, q.B, q.C, q.X,
+                                      x0, gens[i]);
+        j.Ah = S.Ah;
+        j.Bh = S.Bh;
+        j.Zc = S.Zc;
+        j.Zx = S.Zx;
+        xf_inv = S.xf_inv;
+      } else {
+        const Mats M = mats_of(q.p);
+        double* Ah = ws_.take<double>(q.p * q.n * q.n);
+        double* Bh = ws_.take<double>(q.p * q.s * q.s);
+        double* Zc = ws_.take<double>(N);
+        j.Ah = Ah;
+        j.Bh = Bh;
+        j.Zc = Zc;
+        j.Zx = zx;
+        zx += N;
+        fwd.push_back({q.A, Ah, M.op, q.n * q.n, (int)q.p});
+        fwd.push_back({q.B, Bh, M.op, q.s * q.s, (int)q.p});
+        fwd.push_back({q.C, Zc, M.fwd, q.n * q.s, (int)q.p});
+        if (x0) fwd.push_back({q.X, j.Zx, M.fwd, q.n * q.s, (int)q.p});
+        xf_inv = M.inv;
+      }
+      inv.push_back({j.Zx, q.X, xf_inv, q.n * q.s, (int)q.p});
       j.Vg = ws_.take<double>((int64_t)(o.m + 1) * N);
       j.Rg = ws_.take<double>((int64_t)o.m * o.m);
       j.hist = nullptr;
@@ -470,17 +525,31 @@ class TinyExec {
       j.m = o.m;
       j.max_cycles = std::max(o.max_cycles, 0);
       j.fom = 0;
-      j.x0_given = o.x0_given != 0 ? 1 : 0;
+      j.x0_given = x0 ? 1 : 0;
       j.lslots = kern::tiny_krylov_slots(q.n, q.s, q.p, o.m, lds);
     }
+    // descriptor tables: the forward ones, then the inverse ones with block
+    // offsets of their own (host copies stay members until the stream has
+    // been waited for)
+    descs_ = fwd;
+    descs_.insert(descs_.end(), inv.begin(), inv.end());
+    bfirst_.assign(descs_.size() + 2, 0);
+    const size_t nf = fwd.size();
+    for (size_t d = 0; d < nf; ++d) bfirst_[d + 1] = bfirst_[d] + xform_blocks(fwd[d].E);
+    for (size_t d = 0; d < inv.size(); ++d)
+      bfirst_[nf + 2 + d] = bfirst_[nf + 1 + d] + xform_blocks(inv[d].E);
     kern::TinyJob* d_jobs = ws_.take<kern::TinyJob>(count);
-    // (jobs_ stays until the stream has been waited for)
+    kern::XformDesc* d_desc = ws_.take<kern::XformDesc>((int64_t)descs_.size());
+    int* d_bf = ws_.take<int>((int64_t)bfirst_.size());
     TSYLV_HIP(hipMemcpyAsync(d_jobs, jobs_.data(), sizeof(kern::TinyJob) * count,
                              hipMemcpyHostToDevice, s_));
+    TSYLV_HIP(hipMemcpyAsync(d_desc, descs_.data(), sizeof(kern::XformDesc) * descs_.size(),
+                             hipMemcpyHostToDevice, s_));
+    TSYLV_HIP(hipMemcpyAsync(d_bf, bfirst_.data(), sizeof(int) * bfirst_.size(),
+                             hipMemcpyHostToDevice, s_));
+    kern::batch_xform(d_desc, d_bf, (int)nf, bfirst_[nf], s_);
     kern::tiny_krylov_batch(d_jobs, count, lds, s_);
-    for (int i = 0; i < count; ++i)
-      kern::tube_xform_f64(setups_[i].Zx, probs[i].X, setups_[i].xf_inv,
-                           probs[i].n * probs[i].s, (int)probs[i].p, s_);
+    kern::batch_xform(d_desc + nf, d_bf + nf + 1, (int)inv.size(), bfirst_.back(), s_);
   }
   ~TinyExec() {
     if (s_) {
@@ -523,8 +592,9 @@ class TinyExec {
   int count_;
   hipStream_t s_ = nullptr;
   hipEvent_t ready_ = nullptr;
-  std::vector<Setup> setups_;
   std::vector<kern::TinyJob> jobs_;
+  std::vector<kern::XformDesc> descs_;
+  std::vector<int> bfirst_;
   double* rec_ = nullptr;
 };
 

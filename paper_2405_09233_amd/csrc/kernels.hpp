@@ -117,7 +117,9 @@ void tbs_batch(const TbsArgs* d_args, const int* d_first, int count, int total_s
                double* d_part, double* d_norms, hipStream_t st);
 // Tube transforms of many tensors in one launch (descriptor d: out[q E + e]
 // = sum_j M[q p + j] in[j E + e]); d_bfirst[d] the first of its
-// ceil(E / 256) blocks, total_blocks = d_bfirst[ndesc].
+// ceil(E / kBatchXformBlock) blocks, total_blocks = d_bfirst[ndesc].  The
+// fma order is that of tube_xform_f64, so both give the same bits.
+constexpr int kBatchXformBlock = 256;
 struct XformDesc {
   const double* in;
   double* out;

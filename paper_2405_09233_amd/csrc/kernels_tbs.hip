@@ -413,10 +413,9 @@ __global__ void tbs_batch_norms_kernel(const double* __restrict__ part,
 
 // Tube transforms of many tensors in one launch: descriptor d maps the
 // tubes of its tensor, out[q E + e] = sum_j M[q p + j] in[j E + e], with
-// blocks [bfirst[d], bfirst[d + 1]) of 256 tubes each.
-__global__ __launch_bounds__(256) void batch_xform_kernel(const XformDesc* __restrict__ descs,
-                                                          const int* __restrict__ bfirst,
-                                                          int ndesc) {
+// blocks [bfirst[d], bfirst[d + 1]) of kBatchXformBlock tubes each.
+__global__ __launch_bounds__(kBatchXformBlock) void batch_xform_kernel(
+    const XformDesc* __restrict__ descs, const int* __restrict__ bfirst, int ndesc) {
   const int b = blockIdx.x;
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
@@ -425,7 +424,7 @@ __global__ __launch_bounds__(256) void batch_xform_kernel(const XformDesc* __res
     else hi = mid - 1;
   }
   const XformDesc& d = descs[lo];
-  const int64_t e = (int64_t)(b - bfirst[lo]) * 256 + threadIdx.x;
+  const int64_t e = (int64_t)(b - bfirst[lo]) * kBatchXformBlock + threadIdx.x;
   if (e >= d.E) return;
   const int p = d.p;
   for (int q = 0; q < p; ++q) {
@@ -458,8 +457,8 @@ void tbs_batch(const TbsArgs* d_args, const int* d_first, int count, int total_s
 void batch_xform(const XformDesc* d_descs, const int* d_bfirst, int ndesc, int total_blocks,
                  hipStream_t st) {
   if (total_blocks <= 0) return;
-  hipLaunchKernelGGL(batch_xform_kernel, dim3(total_blocks), dim3(256), 0, st, d_descs, d_bfirst,
-                     ndesc);
+  hipLaunchKernelGGL(batch_xform_kernel, dim3(total_blocks), dim3(kBatchXformBlock), 0, st,
+                     d_descs, d_bfirst, ndesc);
   TSYLV_LAUNCH_CHECK();
 }
 

@@ -20,9 +20,9 @@ namespace tsylv {
 
 namespace {
 
-constexpr int kXformBlock = 256;
-
-int64_t blocks_of(int64_t E) { return (E + kXformBlock - 1) / kXformBlock; }
+int64_t blocks_of(int64_t E) {
+  return (E + kern::kBatchXformBlock - 1) / kern::kBatchXformBlock;
+}
 
 bool tbs_batch_dims_ok(const tsylv_problem& q) {
   return q.n >= 1 && q.s >= 1 && q.n <= kern::tbs_max_size() && q.s <= kern::tbs_max_size() &&
