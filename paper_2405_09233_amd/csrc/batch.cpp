@@ -448,8 +448,10 @@ class TinyExec {
   TinyExec(Ctx& ctx, hipStream_t parent, int count, const tsylv_problem* probs,
            const uint64_t* const* gens, const tsylv_opts& o)
       : ws_(ctx.arena, tiny_batch_bytes(count, probs, o)), count_(count) {
-    TSYLV_HIP(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
-    TSYLV_HIP(hipEventCreateWithFlags(&ready_, hipEventDisableTiming));
+    TSYLV_HIP(hipStreamCreateWithFlags(&own_.s, hipStreamNonBlocking));
+    TSYLV_HIP(hipEventCreateWithFlags(&own_.ready, hipEventDisableTiming));
+    s_ = own_.s;
+    ready_ = own_.ready;
     TSYLV_HIP(hipEventRecord(ready_, parent));
     TSYLV_HIP(hipStreamWaitEvent(s_, ready_, 0));
     jobs_.resize(count);
@@ -551,13 +553,6 @@ class TinyExec {
     kern::tiny_krylov_batch(d_jobs, count, lds, s_);
     kern::batch_xform(d_desc + nf, d_bf + nf + 1, (int)inv.size(), bfirst_.back(), s_);
   }
-  ~TinyExec() {
-    if (s_) {
-      (void)hipStreamSynchronize(s_);
-      (void)hipStreamDestroy(s_);
-    }
-    if (ready_) (void)hipEventDestroy(ready_);
-  }
   TinyExec(const TinyExec&) = delete;
   TinyExec& operator=(const TinyExec&) = delete;
 
@@ -588,7 +583,25 @@ class TinyExec {
   }
 
  private:
+  // The stream and event, waited for and released before the workspace is
+  // returned to the arena (members go in reverse order, also when the
+  // constructor throws after work was enqueued).
+  struct OwnStream {
+    hipStream_t s = nullptr;
+    hipEvent_t ready = nullptr;
+    OwnStream() = default;
+    OwnStream(const OwnStream&) = delete;
+    OwnStream& operator=(const OwnStream&) = delete;
+    ~OwnStream() {
+      if (s) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+      }
+      if (ready) (void)hipEventDestroy(ready);
+    }
+  };
   Workspace ws_;
+  OwnStream own_;
   int count_;
   hipStream_t s_ = nullptr;
   hipEvent_t ready_ = nullptr;
