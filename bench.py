@@ -537,9 +537,11 @@ def batched(tsylv, kind="large", count=256, m=30, seed=40, precs=("fp64", "fp32"
     Philox seed 4000 + i drawn on the device (tsylv_generate); tGMRES(m) to
     1e-8, in FP64 and as FP64 refinement around FP32 inner tGMRES(m) cycles.
     Timed three ways on the same instances per precision: tsylv_gmres_batch
-    (small FP64 instances in lockstep, the rest as concurrent solves on eight
-    streams), the serving loop (all submitted at once, up to 8 overlapping
-    solves), and one synchronous solve after another."""
+    (FP64 instances that fit one workgroup in one launch, other small FP64
+    instances in lockstep, the rest as concurrent solves on eight streams),
+    the serving loop (plain tGMRES requests all submitted at once: up to 8
+    overlapping solves, the ones that fit one workgroup joining batches as
+    they queue up), and one synchronous solve after another."""
     import torch
     shapes = batched_shapes(kind, count, seed)
     ctx0 = tsylv.Context(64 << 20, device=0)

@@ -270,7 +270,11 @@ int tsylv_generate(tsylv_ctx* ctx, uint64_t seed, int64_t n, int64_t s, int64_t 
  * workgroup: one launch for all of them; the others in lockstep: one launch
  * per step stage for all of them, the step replayed from a HIP graph,
  * Givens on the device); each result is bitwise the batch-of-one solve of
- * its instance.  The pointers in the request must stay valid until tsylv_poll returns
+ * its instance.  Plain tGMRES requests (FP64, m <= 63) whose instance fits
+ * the one-workgroup solve join such batches too (consecutive requests with
+ * equal m, tol, max_cycles and x0_given): they run the kernel of their
+ * synchronous solve, so each result is bitwise tsylv_gmres's, and `seconds`
+ * is the batch's wall time.  The pointers in the request must stay valid until tsylv_poll returns
  * a final status for its ticket.  A request with A, B and C all NULL solves
  * the synthetic instance of `gen_seed` (tsylv_generate), drawn on the device
  * inside its setup transforms, so that the spatial tensors are never stored

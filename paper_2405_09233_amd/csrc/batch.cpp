@@ -737,6 +737,10 @@ size_t batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_
                           tiny_batch_bytes((int)tiny.size(), tiny.data(), o));
 }
 
+bool batch_solves_whole(const tsylv_problem& q, const tsylv_opts& o) {
+  return tiny_instance(q, o);
+}
+
 size_t served_batch_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o) {
   std::vector<tsylv_problem> lock, tiny;
   for (int i = 0; i < count; ++i) (tiny_instance(probs[i], o) ? tiny : lock).push_back(probs[i]);

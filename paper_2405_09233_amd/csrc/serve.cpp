@@ -20,8 +20,9 @@
 // reductions are fixed-order), so its result is bitwise the same alone or in
 // a mix.
 //
-// Requests of method GMRES_BATCHED that wait at the head of the queue with
-// equal options are admitted together, up to kMaxBatch of them and as many as
+// Requests of method GMRES_BATCHED, and tGMRES requests small enough for the
+// single-workgroup solve, that wait at the head of the queue with equal
+// options are admitted together, up to kMaxBatch of them and as many as
 // the arena holds, as one batch (batch.cpp, without its stream executor)
 // that takes one slot and runs on a worker thread on the slot's stream:
 // instances that fit one workgroup in one launch, the others in lockstep,
@@ -57,10 +58,20 @@ constexpr size_t kPinnedPerSlot = 7 * (1000 + 2) + 2;
 constexpr int kMaxBatch = 512;
 
 bool same_batch_opts(const tsylv_opts& a, const tsylv_opts& b) {
-  return a.m == b.m && a.tol == b.tol && a.max_cycles == b.max_cycles;
+  return a.m == b.m && a.tol == b.tol && a.max_cycles == b.max_cycles &&
+         a.x0_given == b.x0_given;
 }
 
-// A batch of GMRES_BATCHED requests, run by a worker thread.
+// Requests that join batches: GMRES_BATCHED ones, and tGMRES requests whose
+// instance a batch solves whole in one workgroup (the same kernel as their
+// single solve, so the same bits, with many instances per launch).
+bool batch_request(const tsylv_request& r) {
+  if (r.method == TSYLV_METHOD_GMRES_BATCHED) return true;
+  return r.method == TSYLV_METHOD_GMRES && !r.opts.refine && r.opts.m <= kern::kBatchMaxM &&
+         batch_solves_whole(tsylv_problem{r.n, r.s, r.p, r.A, r.B, r.C, r.X}, r.opts);
+}
+
+// A batch of requests (GMRES_BATCHED, small tGMRES), run by a worker thread.
 struct BatchJob {
   std::vector<uint64_t> tickets;
   std::vector<tsylv_request> reqs;
@@ -152,15 +163,14 @@ struct Scheduler {
     for (;;) {
       // the batched requests at the head as problems, for the batch sizes
       std::vector<tsylv_problem> probs;
-      for (size_t i = 0; i < queue.size() && (int)i < kMaxBatch &&
-                         queue[i].r.method == TSYLV_METHOD_GMRES_BATCHED;
+      for (size_t i = 0; i < queue.size() && (int)i < kMaxBatch && batch_request(queue[i].r);
            ++i) {
         const tsylv_request& r = queue[i].r;
         probs.push_back(tsylv_problem{r.n, r.s, r.p, r.A, r.B, r.C, r.X});
       }
       policy::QueueView v;
       v.size = queue.size();
-      v.batched = [&](size_t i) { return queue[i].r.method == TSYLV_METHOD_GMRES_BATCHED; };
+      v.batched = [&](size_t i) { return batch_request(queue[i].r); };
       v.batchable = [&](size_t i, size_t j) {
         return same_batch_opts(queue[i].r.opts, queue[j].r.opts);
       };

@@ -50,6 +50,9 @@ size_t batch_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_
 size_t lockstep_workspace_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o);
 // Workspace of a batch run without the stream executor (no_streams).
 size_t served_batch_bytes(int count, const tsylv_problem* probs, const tsylv_opts& o);
+// True when a batch solves this instance whole in one workgroup (the single
+// solve's criterion): its result is then bitwise that of tsylv_gmres.
+bool batch_solves_whole(const tsylv_problem& q, const tsylv_opts& o);
 // Batched t-Bartels-Stewart (tbs_batch.cpp): 0 bytes when an instance is
 // outside 1 <= n, s <= 64, 1 <= p <= 4096 or has a null pointer.
 size_t tbs_batch_workspace_bytes(int count, const tsylv_problem* probs);

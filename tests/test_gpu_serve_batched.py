@@ -11,6 +11,8 @@ TSYLV_METHOD_GMRES_BATCHED through tsylv_submit / tsylv_poll).
   time the queue drains in several batches with the same results.
 * Malformed requests are rejected; closing the context with batches in
   flight finishes them.
+* Plain tGMRES requests small enough for the single-workgroup solve join
+  the batches, with the synchronous solve's bits.
 * Batched requests above the size that tsylv_gmres_batch runs in lockstep
   (n s p > 2^18) are still served in lockstep batches (several batches in
   flight at once share nothing): every result converges, its true residual
@@ -235,3 +237,64 @@ def test_served_batches_replay_recorded_graphs_while_the_caller_works(monkeypatc
         assert np.array_equal(a, b)
     n, s, p, (A, B, C) = reqs[0]
     assert rel(out["1"][0], kron.kron_solve(A, B, C)) <= 1e-8
+
+
+@pytest.mark.gpu
+def test_small_gmres_requests_join_batches():
+    """Plain tGMRES requests small enough for the single-workgroup solve
+    join the served batches (with GMRES_BATCHED requests of equal options,
+    and with an initial guess): each result is bitwise the synchronous
+    tsylv_gmres solve of its instance, with the same steps, cycles and
+    residuals; larger tGMRES requests in the same queue run as single solves
+    with the same guarantee.  Requests of one batch report the batch's wall
+    time, so equal `seconds` show that batches formed."""
+    import torch
+    say("serve: small tGMRES requests in batches")
+    c = tsylv.Context(2 << 30, device=0)
+    try:
+        rng = np.random.default_rng(1700)
+        plain = tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-11, max_cycles=100)
+        guess = tsylv.default_opts(tsylv.GMRES, m=30, tol=1e-11, max_cycles=100, x0_given=1)
+        items = []
+        for i in range(56):
+            if i in (13, 33, 50):
+                n, s, p = 200, 12, 6  # n s p = 14400: beyond the one-workgroup solve
+            else:
+                n, s, p = (int(rng.integers(4, 25)), int(rng.integers(2, 9)),
+                           int(rng.integers(2, 9)))
+            A, B, C = workloads.dense_shifted(n, s, p, seed=1700 + i)
+            Ad, Bd, Cd = dev(A), dev(B), dev(C)
+            # runs of each kind (a batch is a run of requests with equal
+            # options at the head of the queue)
+            kind = "plain" if i < 24 else ("batched" if i < 40 else "guess")
+            X0 = torch.zeros_like(Cd)  # the library layout (Cd's strides)
+            if kind == "guess":
+                X0.copy_(0.1 * torch.randn(Cd.shape, dtype=torch.float64, device="cuda:0"))
+            X = torch.empty_like(X0)
+            X.copy_(X0)
+            items.append((kind, Ad, Bd, Cd, X0, X))
+        torch.cuda.synchronize()
+        tickets = []
+        for kind, Ad, Bd, Cd, X0, X in items:
+            method = tsylv.GMRES_BATCHED if kind == "batched" else tsylv.GMRES
+            tickets.append(c.submit(Ad, Bd, Cd, X, method=method,
+                                    opts=guess if kind == "guess" else plain))
+        res = wait_all(c, tickets)
+        secs = {}
+        for (kind, Ad, Bd, Cd, X0, X), t in zip(items, tickets):
+            st, info = res[t]
+            assert st == 0, (kind, info.as_dict())
+            if kind == "batched":
+                X1 = torch.zeros_like(Cd)
+                i1 = c.gmres_batch([(Ad, Bd, Cd, X1)], opts=plain)[0]
+            else:
+                X1 = X0.clone()
+                _, i1 = c.gmres(Ad, Bd, Cd, X=X1, opts=guess if kind == "guess" else plain)
+            assert torch.equal(X, X1), (kind, tuple(Cd.shape))
+            assert (info.steps, info.cycles, info.relres_true) == (i1.steps, i1.cycles,
+                                                                   i1.relres_true)
+            if kind != "batched" and Cd.numel() <= 8192:
+                secs[info.seconds] = secs.get(info.seconds, 0) + 1
+        assert max(secs.values()) >= 2, secs
+    finally:
+        c.close()
