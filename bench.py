@@ -903,6 +903,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default apply tiles")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--batched-only", action="store_true", help="run only the batched workload")
+    ap.add_argument("--batched-kinds", default="large,small,tiny",
+                    help="with --batched-only: the mixes to run (large, small, tiny)")
     ap.add_argument("--tiny-only", action="store_true",
                     help="run only the 8 x 8 x 4 latency measurements")
     ap.add_argument("--no-serve-full", action="store_true",
@@ -956,11 +958,12 @@ def main():
         return
 
     if args.batched_only:
-        print(json.dumps({"batched": {"large": batched(tsylv, "large", 256),
-                                      "small": batched(tsylv, "small", 256,
-                                                       precs=("fp64",)),
-                                      "tiny": batched(tsylv, "tiny", 256,
-                                                      precs=("fp64",))}}), flush=True)
+        kinds = [k for k in args.batched_kinds.split(",") if k]
+        out = {}
+        for kind in kinds:
+            out[kind] = (batched(tsylv, "large", 256) if kind == "large" else
+                         batched(tsylv, kind, 256, precs=("fp64",)))
+        print(json.dumps({"batched": out}), flush=True)
         return
 
     full_names = [x for x in args.serve_full_paths.split(",") if x] or None
