@@ -20,6 +20,18 @@
  * the best iterate in X.  No exception crosses this boundary.  A context is
  * not thread-safe, except that tsylv_submit and tsylv_poll may be called from
  * any thread.
+ *
+ * Environment switches (read at each call; each selects another code path
+ * for the same mathematics, for comparisons and measurements):
+ *   TSYLV_KRYLOV_TINY=0         no single-workgroup solve of small instances
+ *                               (tGMRES/tFOM, batches, served requests)
+ *   TSYLV_KRYLOV_CGS2=1         three-sweep CGS2 instead of the delayed form
+ *   TSYLV_KRYLOV_DEVICE_CYCLE   refined solves' inner cycles on the device:
+ *                               1 (default) after a full cycle, 2 always, 0 never
+ *   TSYLV_BF16_BASIS=fp32       BF16-refined solves keep an FP32 inner basis
+ *   TSYLV_BATCH_GRAPH=0         lockstep batch steps launched, not replayed
+ *                               from a recorded HIP graph (bitwise the same)
+ *   TSYLV_TBA_HOST_PROJECTED=1  TBAS's projected equation solved on the host
  */
 #ifndef TSYLV_H
 #define TSYLV_H
