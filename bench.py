@@ -652,8 +652,10 @@ TRAFFIC_FILES = {("bf16", (4096, 64, 32)): "apply_bf16_traffic_cd4096_s64_p32.md
 def measured_traffic(path, shape, variant=None):
     """HBM bytes per apply call from the committed counter summary, or None
     when there is none for the path and shape, when the kernel source has
-    changed since the counters were taken, or when the summary names another
-    tile variant than `variant` (the one the timed solves used)."""
+    changed since the counters were taken, or when the summary has no count
+    for tile variant `variant` (the one the timed solves used).  A summary
+    gives one count per variant it measured ("traffic_bytes_per_call
+    variant V: B" lines), or one count for the variant it names."""
     fname = TRAFFIC_FILES.get((path, tuple(shape)))
     if fname is None:
         return None
@@ -667,11 +669,15 @@ def measured_traffic(path, shape, variant=None):
     except OSError:
         return None
     m = re.search(r"sha256 at measurement:\s*([0-9a-f]{64})", txt)
+    if not m or hashlib.sha256(src).hexdigest() != m.group(1):
+        return None
+    per = {int(a): float(b) for a, b in
+           re.findall(r"traffic_bytes_per_call variant (\d+):\s*([0-9.eE+]+)", txt)}
+    if per:
+        return per.get(variant) if variant is not None else None
     t = re.search(r"traffic_bytes_per_call:\s*([0-9.eE+]+)", txt)
     v = re.search(r"variant at measurement:\s*(\d+)", txt)
-    if not m or not t or hashlib.sha256(src).hexdigest() != m.group(1):
-        return None
-    if variant is not None and (not v or int(v.group(1)) != variant):
+    if not t or (variant is not None and (not v or int(v.group(1)) != variant)):
         return None
     return float(t.group(1))
 

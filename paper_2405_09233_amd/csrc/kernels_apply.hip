@@ -523,7 +523,7 @@ int batch_apply_tiles(int variant, int64_t n, int64_t s, int p, int* nrt, int* n
   return num_slices(p) * *nrt * *nct;
 }
 
-int apply_variant_count(int prec) { return prec == TSYLV_BF16 ? 10 : 17; }
+int apply_variant_count(int prec) { return prec == TSYLV_BF16 ? 11 : 17; }
 
 int apply_default_variant(int prec, int64_t n, int64_t s) {
   if (prec == TSYLV_FP64) return default_variant<double>(n, s);

@@ -862,7 +862,7 @@ void launch_w32(Bf16Args a, int ncu, hipStream_t st) {
 
 }  // namespace
 
-int bf16_default_variant(int64_t s) { return s <= 16 ? 0 : (s <= 32 ? 1 : (s <= 64 ? 2 : 4)); }
+int bf16_default_variant(int64_t s) { return s <= 16 ? 0 : (s <= 32 ? 1 : (s <= 64 ? 2 : 10)); }
 
 static int64_t row_blocks(int64_t n) { return ((n + 15) / 16 + kRowPad - 1) / kRowPad * kRowPad; }
 static int64_t k_blocks(int64_t n) { return ((n + 31) / 32 + kKPad - 1) / kKPad * kKPad; }
@@ -890,7 +890,11 @@ void tile_operator_bf16(const double* Ah, uint16_t* At, int64_t n, int p, hipStr
 // Deeper rings and longer phases (4/4/4/8/2, 4/2/8/8/2) fit in registers but
 // measured the same as variant 2 at n = 4096, s = 64, p = 32 (the kernel is
 // not short of loads in flight there), and two 4-wave workgroups per CU
-// (4/2/2/4/2), 1 % faster alone, 3 % slower inside a solve.
+// (4/2/2/4/2), 1 % faster alone, 3 % slower inside a solve.  Above s = 64
+// the wide kernel with phases of one k block (variant 10) is the default:
+// its staging needs 10 fewer registers (245 against 255) and it ran 2 %
+// faster than the same kernel with two-block phases (variant 4) at
+// n = 8192, s = 128, p = 64, despite a barrier per k block.
 template <bool TIO>
 void launch_cfg(const Bf16Args& a, int variant, hipStream_t st) {
   static int ncu_cached[64] = {};
@@ -909,6 +913,7 @@ void launch_cfg(const Bf16Args& a, int variant, hipStream_t st) {
     case 7: launch_w32<4, 4, 2, 4, 1, TIO>(a, ncu, st); break;
     case 8: launch_w32<4, 8, 2, 4, 1, TIO>(a, ncu, st); break;
     case 9: launch_w32<2, 4, 2, 8, 1, TIO>(a, ncu, st); break;
+    case 10: launch_w32<4, 2, 1, 8, 1, TIO>(a, ncu, st); break;
     default: throw Error(TSYLV_EINVAL, "apply: unknown BF16 variant");
   }
 }
