@@ -56,7 +56,8 @@ typedef enum {
   TSYLV_METHOD_GMRES = 0, /* tGMRES(m), Algorithm 3                        */
   TSYLV_METHOD_FOM = 1,   /* tFOM(m), Algorithm 3                          */
   TSYLV_METHOD_TBA = 2,   /* TBAS(m), Algorithm 8 (block size s)           */
-  TSYLV_METHOD_TBS = 3,   /* t-Bartels-Stewart direct solve, Algorithm 5   */
+  TSYLV_METHOD_TBS = 3,   /* t-Bartels-Stewart direct solve, Algorithm 5
+                             (n or s above 64: tGMRES(30), see tsylv_tbs)   */
   TSYLV_METHOD_GMRES_BATCHED = 4, /* tGMRES(m) served in lockstep batches
                                      (tsylv_submit only; see below)         */
   TSYLV_METHOD_AUTO = 5  /* tsylv_submit only: the t-Bartels-Stewart direct
@@ -182,7 +183,10 @@ int tsylv_tba(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A,
 
 /* t-Bartels-Stewart, Algorithm 5 of section 4 (with the t-Schur
  * decomposition of Algorithm 4): the direct method for small sizes,
- * 1 <= n, s <= 64 (TSYLV_EINVAL otherwise).  Each Fourier slice is reduced
+ * 1 <= n, s <= 64.  Beyond that the call solves the same equation by
+ * tGMRES(30) (the tGMRES defaults with opts->tol; info->steps > 0 tells
+ * the two apart, and tsylv_workspace_bytes(TSYLV_METHOD_TBS, ...) is then
+ * that tGMRES's workspace).  Each Fourier slice is reduced
  * to complex Schur form on the GPU (one wavefront per slice), the triangular
  * equation solved by back substitution and transformed back.  Only opts->tol
  * is read (opts may be NULL): the status is TSYLV_OK when the true relative
@@ -247,10 +251,14 @@ int tsylv_gmres_batch(tsylv_ctx* ctx, int count, const tsylv_problem* probs,
  * instance i's true relative residual (relres_true) is <= tol, else
  * TSYLV_NOT_CONVERGED with the direct solution in X; TSYLV_ESINGULAR when a
  * slice's spectra of Ahat and Bhat meet, TSYLV_EBREAKDOWN when a Schur
- * iteration does not converge; seconds is the whole batch's time.  Returns
- * TSYLV_OK when every instance is TSYLV_OK, TSYLV_NOT_CONVERGED otherwise,
- * or an error of the whole batch (TSYLV_EINVAL, TSYLV_ENOMEM, TSYLV_EHIP).
- * Synchronous on the context stream. */
+ * iteration does not converge; seconds is the whole batch's time.
+ * Instances with n or s above 64 (p <= 4096) are solved after that pass by
+ * tGMRES(30) to the same tolerance, as tsylv_gmres_batch runs them (their
+ * infos report Krylov steps); the workspace is the larger of the two
+ * parts'.  Returns TSYLV_OK when every instance is TSYLV_OK,
+ * TSYLV_NOT_CONVERGED otherwise, or an error of the whole batch
+ * (TSYLV_EINVAL for an instance with n, s or p < 1, p > 4096 or a NULL
+ * pointer; TSYLV_ENOMEM, TSYLV_EHIP).  Synchronous on the context stream. */
 size_t tsylv_tbs_batch_workspace_bytes(int count, const tsylv_problem* probs);
 int tsylv_tbs_batch(tsylv_ctx* ctx, int count, const tsylv_problem* probs,
                     const tsylv_opts* opts, tsylv_info* infos);

@@ -120,9 +120,9 @@ struct Group {
 
 }  // namespace
 
-static int gmres_lockstep(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
-                          const uint64_t* const* gens, const tsylv_opts& o, tsylv_info* infos,
-                          bool use_graph) {
+static int gmres_lockstep(Ctx& ctx, Arena& arena, hipStream_t st, int count,
+                          const tsylv_problem* probs, const uint64_t* const* gens,
+                          const tsylv_opts& o, tsylv_info* infos, bool use_graph) {
   const auto t0 = std::chrono::steady_clock::now();
   const int m = o.m;
 
@@ -146,7 +146,7 @@ static int gmres_lockstep(Ctx& ctx, hipStream_t st, int count, const tsylv_probl
   }
 
   // ---- workspace and per-instance setup (Algorithm 1 step 1) ----
-  Workspace ws(ctx.arena, lockstep_workspace_bytes(count, probs, o));
+  Workspace ws(arena, lockstep_workspace_bytes(count, probs, o));
   // on any exit, let every stream drain before the workspace returns to the
   // arena, then release the groups' streams and graphs
   struct Drain {
@@ -445,9 +445,9 @@ size_t tiny_batch_bytes(int count, const tsylv_problem* probs, const tsylv_opts&
 // takes the same kernel for it), in any batch.
 class TinyExec {
  public:
-  TinyExec(Ctx& ctx, hipStream_t parent, int count, const tsylv_problem* probs,
+  TinyExec(Ctx& ctx, Arena& arena, hipStream_t parent, int count, const tsylv_problem* probs,
            const uint64_t* const* gens, const tsylv_opts& o)
-      : ws_(ctx.arena, tiny_batch_bytes(count, probs, o)), count_(count) {
+      : ws_(arena, tiny_batch_bytes(count, probs, o)), count_(count) {
     TSYLV_HIP(hipStreamCreateWithFlags(&own_.s, hipStreamNonBlocking));
     TSYLV_HIP(hipEventCreateWithFlags(&own_.ready, hipEventDisableTiming));
     s_ = own_.s;
@@ -750,8 +750,9 @@ size_t served_batch_bytes(int count, const tsylv_problem* probs, const tsylv_opt
 
 int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
                 const uint64_t* const* gens, const tsylv_opts& o, tsylv_info* infos,
-                bool use_graph, bool no_streams) {
+                bool use_graph, bool no_streams, Arena* arena) {
   const auto t0 = std::chrono::steady_clock::now();
+  Arena& ar = arena ? *arena : ctx.arena;
   std::vector<int> lock, tasks, tiny;
   for (int i = 0; i < count; ++i) {
     if (tiny_instance(probs[i], o))
@@ -772,7 +773,8 @@ int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
   }
   std::unique_ptr<TinyExec> tex;
   if (!tiny.empty())
-    tex.reset(new TinyExec(ctx, st, (int)tiny.size(), tp.data(), gens ? tg.data() : nullptr, o));
+    tex.reset(
+        new TinyExec(ctx, ar, st, (int)tiny.size(), tp.data(), gens ? tg.data() : nullptr, o));
   if (!lock.empty()) {
     std::vector<tsylv_problem> lp;
     std::vector<const uint64_t*> lg;
@@ -781,7 +783,7 @@ int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
       lg.push_back(gens ? gens[i] : nullptr);
     }
     std::vector<tsylv_info> li(lock.size());
-    if (gmres_lockstep(ctx, st, (int)lock.size(), lp.data(), gens ? lg.data() : nullptr, o,
+    if (gmres_lockstep(ctx, ar, st, (int)lock.size(), lp.data(), gens ? lg.data() : nullptr, o,
                        li.data(), use_graph) != TSYLV_OK)
       worst = TSYLV_NOT_CONVERGED;
     for (size_t k = 0; k < lock.size(); ++k) infos[lock[k]] = li[k];

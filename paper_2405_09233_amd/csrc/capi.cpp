@@ -154,8 +154,10 @@ size_t tsylv_workspace_bytes(int method, int64_t n, int64_t s, int64_t p, const 
   if (method == -1) return apply_workspace_bytes(n, s, p);
   if (method == TSYLV_METHOD_GMRES || method == TSYLV_METHOD_FOM)
     return krylov_workspace_bytes(method, n, s, p, o);
-  if (method == TSYLV_METHOD_TBS)
-    return tbs_dims_ok(n, s) ? krylov_workspace_bytes(method, n, s, p, o) : 0;
+  if (method == TSYLV_METHOD_TBS)  // beyond 64: the tGMRES that stands in for it
+    return tbs_dims_ok(n, s) ? krylov_workspace_bytes(method, n, s, p, o)
+                             : krylov_workspace_bytes(TSYLV_METHOD_GMRES, n, s, p,
+                                                      tbs_fallback_opts(o.tol));
   if (method == TSYLV_METHOD_TBA) {
     if (n < 2 * s) return 0;
     int m = o.m;
@@ -210,10 +212,15 @@ int tsylv_gmres(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A
 
 int tsylv_tbs(tsylv_ctx* ctx, int64_t n, int64_t s, int64_t p, const double* A, const double* B,
               const double* C, double* X, const tsylv_opts* opts, tsylv_info* info) {
-  if (!tbs_dims_ok(n, s)) return reject(info, TSYLV_EINVAL);
   tsylv_opts o;
   tsylv_default_opts(TSYLV_METHOD_TBS, &o);
   if (opts) o.tol = opts->tol;  // the direct solve reads the tolerance only
+  if (!tbs_dims_ok(n, s)) {
+    // beyond the direct solve's size limit: tGMRES to the same tolerance
+    if (!dims_ok(n, s, p)) return reject(info, TSYLV_EINVAL);
+    const tsylv_opts g = tbs_fallback_opts(o.tol);
+    return krylov_entry(TSYLV_METHOD_GMRES, ctx, n, s, p, A, B, C, X, &g, info);
+  }
   return krylov_entry(TSYLV_METHOD_TBS, ctx, n, s, p, A, B, C, X, &o, info);
 }
 
@@ -327,8 +334,12 @@ int tsylv_submit(tsylv_ctx* ctx, const tsylv_request* req, uint64_t* ticket) {
   if (r.method == TSYLV_METHOD_GMRES_BATCHED &&
       (r.opts.refine || r.opts.m > kern::kBatchMaxM || r.opts.x0_given))
     return TSYLV_EINVAL;
-  if (r.method == TSYLV_METHOD_TBS && (!tbs_dims_ok(r.n, r.s) || r.opts.refine))
-    return TSYLV_EINVAL;
+  if (r.method == TSYLV_METHOD_TBS && r.opts.refine) return TSYLV_EINVAL;
+  if (r.method == TSYLV_METHOD_TBS && !tbs_dims_ok(r.n, r.s)) {
+    // beyond the direct solve's size limit: tGMRES to the same tolerance
+    r.method = TSYLV_METHOD_GMRES;
+    r.opts = tbs_fallback_opts(r.opts.tol);
+  }
   if (!opts_ok(r.opts)) return TSYLV_EINVAL;
   if (r.opts.res_hist) return TSYLV_EINVAL;  // no host history buffers across threads
   return guarded([&]() {

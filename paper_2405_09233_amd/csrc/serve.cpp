@@ -79,6 +79,11 @@ struct BatchJob {
   std::vector<tsylv_problem> probs;
   std::vector<const uint64_t*> gens;
   std::vector<tsylv_info> infos;
+  // The batch's workspace, reserved from the context's arena when the batch
+  // is admitted (so that batches admitted one after another cannot count on
+  // the same free memory before their workers allocate), carved by `sub`.
+  void* block = nullptr;
+  Arena sub;
   std::thread th;
   std::atomic<bool> finished{false};
   int error = 0;  // an error of the whole batch
@@ -193,7 +198,7 @@ struct Scheduler {
         continue;
       }
       if (d.kind == policy::Kind::Batch) {
-        start_batch(lk, d.count);
+        if (!start_batch(lk, d.count, probs)) return;  // memory taken meanwhile: wait
         continue;
       }
       Queued q = queue.front();
@@ -232,12 +237,19 @@ struct Scheduler {
     }
   }
 
-  // The first `count` requests of the queue (batched, with equal options)
-  // become one batch on a free slot.  Called with mu held (lk); returns with
-  // it held.
-  void start_batch(std::unique_lock<std::mutex>& lk, size_t count) {
+  // The first `count` requests of the queue (batched, with equal options;
+  // probs their problems) become one batch on a free slot, its workspace
+  // reserved at once.  Called with mu held (lk); returns with it held;
+  // false (nothing started) when the reservation fails.
+  bool start_batch(std::unique_lock<std::mutex>& lk, size_t count,
+                   const std::vector<tsylv_problem>& probs) {
     const tsylv_opts o = queue.front().r.opts;
+    const size_t need = served_batch_bytes((int)count, probs.data(), o);
+    void* block = ctx.arena.alloc(need);
+    if (!block) return false;
     std::unique_ptr<BatchJob> job(new BatchJob());
+    job->block = block;
+    job->sub.init(static_cast<char*>(block), need);
     for (size_t i = 0; i < count; ++i) {
       const tsylv_request& r = queue.front().r;
       job->tickets.push_back(queue.front().ticket);
@@ -262,7 +274,7 @@ struct Scheduler {
         // the step replayed from a recorded graph (TSYLV_BATCH_GRAPH=0: eager)
         const char* g = std::getenv("TSYLV_BATCH_GRAPH");
         gmres_batch(ctx, st, (int)jp->probs.size(), jp->probs.data(), jp->gens.data(), o,
-                    jp->infos.data(), !(g && g[0] == '0'), /*no_streams=*/true);
+                    jp->infos.data(), !(g && g[0] == '0'), /*no_streams=*/true, &jp->sub);
       } catch (const Error& e) {
         jp->error = e.status;
       } catch (...) {
@@ -274,6 +286,7 @@ struct Scheduler {
     a.job = std::move(job);
     active.push_back(std::move(a));
     lk.lock();
+    return true;
   }
 
   // A finished batch: every result posted (an arena shortfall puts the
@@ -281,6 +294,9 @@ struct Scheduler {
   void retire_batch(Active& a) {
     BatchJob& j = *a.job;
     if (j.th.joinable()) j.th.join();
+    (void)hipStreamSynchronize(streams[a.slot]);
+    ctx.arena.free(j.block);
+    j.block = nullptr;
     if (j.error == TSYLV_ENOMEM && active.size() > 1) {  // others hold memory: retry
       std::lock_guard<std::mutex> g(mu);
       if (!stopping) {
@@ -289,7 +305,6 @@ struct Scheduler {
         return;
       }
     }
-    (void)hipStreamSynchronize(streams[a.slot]);
     for (hipEvent_t e : j.ready)
       if (e) (void)hipEventDestroy(e);
     for (size_t i = 0; i < j.tickets.size(); ++i) {

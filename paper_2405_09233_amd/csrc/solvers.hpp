@@ -53,9 +53,14 @@ size_t served_batch_bytes(int count, const tsylv_problem* probs, const tsylv_opt
 // True when a batch solves this instance whole in one workgroup (the single
 // solve's criterion): its result is then bitwise that of tsylv_gmres.
 bool batch_solves_whole(const tsylv_problem& q, const tsylv_opts& o);
-// Batched t-Bartels-Stewart (tbs_batch.cpp): 0 bytes when an instance is
-// outside 1 <= n, s <= 64, 1 <= p <= 4096 or has a null pointer.
+// Batched t-Bartels-Stewart (tbs_batch.cpp); instances with n or s above 64
+// by tGMRES (tbs_fallback_opts with the batch's tolerance) after the direct
+// pass.  0 bytes when an instance has n, s or p < 1, p > 4096 or a null
+// pointer.
 size_t tbs_batch_workspace_bytes(int count, const tsylv_problem* probs);
+// The tGMRES options that stand in for the direct solve beyond its size
+// limit: the tGMRES defaults with the caller's tolerance.
+tsylv_opts tbs_fallback_opts(double tol);
 int tbs_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts& o,
               tsylv_info* infos);
 // On stream `st`; gens (may be null): gens[i] non-null draws instance i as
@@ -65,10 +70,13 @@ int tbs_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts&
 // concurrently itself; the stream executor's pinned staging is the
 // context's, for one caller at a time); instances that fit one workgroup
 // keep that executor, so a served instance computes what its batch of one
-// does.
+// does.  arena (may be null: the context's): where the single-workgroup and
+// lockstep executors take their workspaces (the serving loop passes a block
+// reserved for the batch when it admitted it; the stream executor's solves
+// always take the context's).
 int gmres_batch(Ctx& ctx, hipStream_t st, int count, const tsylv_problem* probs,
                 const uint64_t* const* gens, const tsylv_opts& o, tsylv_info* infos,
-                bool use_graph, bool no_streams = false);
+                bool use_graph, bool no_streams = false, Arena* arena = nullptr);
 
 // Autotuner (tune.cpp): times every tile variant of the apply at (n, s, p)
 // in precision `prec` (`reps` launches each), stores the fastest in

@@ -5,10 +5,13 @@
 // residual in the Fourier planes and its per-instance norms in two more, the
 // inverse transforms of every X in one, and one synchronisation.  Each
 // instance's arithmetic is that of its own solve: the kernels read only its
-// tables, and its norms are summed in slice order.
+// tables, and its norms are summed in slice order.  Instances beyond the
+// direct solve's size limit (n or s above 64) are solved by tGMRES instead
+// (the batched tGMRES executors, after the direct pass).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <map>
 #include <vector>
 
@@ -29,9 +32,92 @@ bool tbs_batch_dims_ok(const tsylv_problem& q) {
          q.p >= 1 && q.p <= 4096 && q.A && q.B && q.C && q.X;
 }
 
+// A well-formed instance beyond the direct solve's size limit.
+bool tbs_fallback_instance(const tsylv_problem& q) {
+  return q.n >= 1 && q.s >= 1 && (q.n > kern::tbs_max_size() || q.s > kern::tbs_max_size()) &&
+         q.p >= 1 && q.p <= 4096 && q.A && q.B && q.C && q.X;
+}
+
+// Splits a batch into the direct solve's instances and the others; false
+// when an instance is malformed.
+bool split_batch(int count, const tsylv_problem* probs, std::vector<int>& direct,
+                 std::vector<int>& krylov) {
+  for (int i = 0; i < count; ++i) {
+    if (tbs_batch_dims_ok(probs[i]))
+      direct.push_back(i);
+    else if (tbs_fallback_instance(probs[i]))
+      krylov.push_back(i);
+    else
+      return false;
+  }
+  return true;
+}
+
+std::vector<tsylv_problem> pick(const tsylv_problem* probs, const std::vector<int>& ids) {
+  std::vector<tsylv_problem> out;
+  for (int i : ids) out.push_back(probs[i]);
+  return out;
+}
+
+size_t direct_workspace_bytes(int count, const tsylv_problem* probs);
+int direct_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts& o,
+                 tsylv_info* infos);
+
 }  // namespace
 
+tsylv_opts tbs_fallback_opts(double tol) {
+  tsylv_opts o;
+  tsylv_default_opts(TSYLV_METHOD_GMRES, &o);
+  o.tol = tol;
+  return o;
+}
+
 size_t tbs_batch_workspace_bytes(int count, const tsylv_problem* probs) {
+  if (count <= 0 || !probs) return 0;
+  std::vector<int> direct, krylov;
+  if (!split_batch(count, probs, direct, krylov)) return 0;
+  size_t d = 0, k = 0;
+  if (!direct.empty()) {
+    const std::vector<tsylv_problem> dp = pick(probs, direct);
+    d = direct_workspace_bytes((int)dp.size(), dp.data());
+    if (d == 0) return 0;
+  }
+  if (!krylov.empty()) {
+    const std::vector<tsylv_problem> kp = pick(probs, krylov);
+    k = batch_workspace_bytes((int)kp.size(), kp.data(), tbs_fallback_opts(1e-8));
+    if (k == 0) return 0;
+  }
+  return std::max(d, k);  // the two parts run one after the other
+}
+
+int tbs_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts& o,
+              tsylv_info* infos) {
+  std::vector<int> direct, krylov;
+  if (!split_batch(count, probs, direct, krylov))
+    throw Error(TSYLV_EINVAL, "tbs batch: bad instance");
+  int worst = TSYLV_OK;
+  if (!direct.empty()) {
+    const std::vector<tsylv_problem> dp = pick(probs, direct);
+    std::vector<tsylv_info> di(dp.size());
+    if (direct_batch(ctx, (int)dp.size(), dp.data(), o, di.data()) != TSYLV_OK)
+      worst = TSYLV_NOT_CONVERGED;
+    for (size_t k = 0; k < direct.size(); ++k) infos[direct[k]] = di[k];
+  }
+  if (!krylov.empty()) {
+    const std::vector<tsylv_problem> kp = pick(probs, krylov);
+    std::vector<tsylv_info> ki(kp.size());
+    const char* g = std::getenv("TSYLV_BATCH_GRAPH");
+    if (gmres_batch(ctx, ctx.stream, (int)kp.size(), kp.data(), nullptr, tbs_fallback_opts(o.tol),
+                    ki.data(), !(g && g[0] == '0')) != TSYLV_OK)
+      worst = TSYLV_NOT_CONVERGED;
+    for (size_t k = 0; k < krylov.size(); ++k) infos[krylov[k]] = ki[k];
+  }
+  return worst;
+}
+
+namespace {
+
+size_t direct_workspace_bytes(int count, const tsylv_problem* probs) {
   if (count <= 0 || !probs) return 0;
   size_t b = 0;
   std::map<int64_t, int> ps;
@@ -55,13 +141,13 @@ size_t tbs_batch_workspace_bytes(int count, const tsylv_problem* probs) {
   return b;
 }
 
-int tbs_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts& o,
-              tsylv_info* infos) {
+int direct_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts& o,
+                 tsylv_info* infos) {
   const auto t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < count; ++i)
     if (!tbs_batch_dims_ok(probs[i])) throw Error(TSYLV_EINVAL, "tbs batch: bad instance");
   hipStream_t st = ctx.stream;
-  Workspace ws(ctx.arena, tbs_batch_workspace_bytes(count, probs));
+  Workspace ws(ctx.arena, direct_workspace_bytes(count, probs));
   // transform matrices, one set per distinct p
   struct Mats {
     double *op, *fwd, *inv;
@@ -163,5 +249,7 @@ int tbs_batch(Ctx& ctx, int count, const tsylv_problem* probs, const tsylv_opts&
   }
   return all_ok ? TSYLV_OK : TSYLV_NOT_CONVERGED;
 }
+
+}  // namespace
 
 }  // namespace tsylv

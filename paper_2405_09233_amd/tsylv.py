@@ -331,8 +331,9 @@ class Context:
 
     def tbs_batch(self, items, tol=1e-8, raise_on_error=True):
         """Batched t-Bartels-Stewart over `items`, a list of (A, B, C, X)
-        device tensors of small instances (n, s <= 64); X receives each
-        solution.  Returns the list of per-instance Info records."""
+        device tensors (instances with n or s above 64 are solved by
+        tGMRES(30) to `tol` instead); X receives each solution.  Returns the
+        list of per-instance Info records."""
         probs = self._problems(items)
         o = default_opts(TBS, tol=tol)
         infos = (Info * len(items))()

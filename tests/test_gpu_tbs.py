@@ -5,9 +5,12 @@ Bars (FP64): the direct solution within 1e-9 (relative) of the oracle's
 t-Bartels-Stewart / Kronecker solution and a true relative residual below
 1e-11 on well-separated spectra -- a backward-stable direct method leaves
 O(eps kappa); a slice whose spectra of Ahat and Bhat meet is reported as
-TSYLV_ESINGULAR; sizes past 64 are rejected.
+TSYLV_ESINGULAR.  Past n or s = 64 the calls solve by tGMRES(30) to the
+same tolerance instead (single, batched and served), checked against the
+Kronecker solution.
 """
 
+import ctypes
 import time
 
 import numpy as np
@@ -72,13 +75,23 @@ def test_shared_eigenvalue_is_singular():
 
 
 @pytest.mark.gpu
-def test_size_limit():
-    A, B, C = workloads.dense_shifted(65, 4, 2, seed=1)
-    with pytest.raises(tsylv.TsylvError):
-        ctx().tbs(dev(A), dev(B), dev(C))
-    A, B, C = workloads.dense_shifted(8, 65, 2, seed=1)
-    with pytest.raises(tsylv.TsylvError):
-        ctx().tbs(dev(A), dev(B), dev(C))
+def test_beyond_the_size_limit_solves_by_tgmres():
+    """n or s above 64: tsylv_tbs solves by tGMRES(30) to its tolerance
+    (Krylov steps reported, the result bitwise tsylv_gmres's with those
+    options, within 1e-8 of the Kronecker solution)."""
+    import torch
+    say("tbs beyond 64: tGMRES")
+    c = ctx()
+    for n, s, p in ((65, 4, 2), (8, 65, 2)):
+        A, B, C = workloads.dense_shifted(n, s, p, seed=1)
+        Ad, Bd, Cd = dev(A), dev(B), dev(C)
+        X, info = c.tbs(Ad, Bd, Cd, tol=1e-10)
+        assert info.status == 0 and info.steps > 0, info.as_dict()
+        assert info.relres_true <= 1e-10
+        Xg = torch.zeros_like(Cd)
+        c.gmres(Ad, Bd, Cd, X=Xg, opts=tsylv.default_opts(tsylv.GMRES, tol=1e-10))
+        assert torch.equal(X, Xg)
+        assert rel(host(X), kron.kron_solve(A, B, C)) <= 1e-8
 
 
 @pytest.mark.gpu
@@ -154,11 +167,41 @@ def test_tbs_batch_mixed_sizes_match_oracle():
 
 
 @pytest.mark.gpu
-def test_tbs_batch_rejects_large_instances():
-    A, B, C = workloads.dense_shifted(65, 4, 2, seed=1)
-    items = [(dev(A), dev(B), dev(C), tsylv.empty_device(C.shape, "cuda:0"))]
-    with pytest.raises(tsylv.TsylvError):
-        ctx().tbs_batch(items)
+def test_tbs_batch_solves_large_instances_by_tgmres():
+    """A batch mixing instances within the direct solve's limit and beyond
+    it: the small ones bitwise their batch without the large ones (direct,
+    no Krylov steps), the large ones by tGMRES(30) to the batch tolerance
+    (within 1e-8 of the Kronecker solution); malformed instances are still
+    rejected."""
+    import torch
+    say("tbs batch beyond 64")
+    c = ctx()
+    shapes = [(12, 5, 3), (65, 4, 2), (30, 7, 2), (20, 70, 2), (64, 64, 1)]
+    cases, items = [], []
+    for i, (n, s, p) in enumerate(shapes):
+        A, B, C = workloads.dense_shifted(n, s, p, seed=1500 + i)
+        cases.append((A, B, C))
+        items.append((dev(A), dev(B), dev(C), tsylv.empty_device(C.shape, "cuda:0")))
+    infos = c.tbs_batch(items, tol=1e-10, raise_on_error=False)
+    small = [k for k, (n, s, p) in enumerate(shapes) if n <= 64 and s <= 64]
+    alone = [(it[0], it[1], it[2], torch.zeros_like(it[2])) for it in (items[k] for k in small)]
+    infos_small = c.tbs_batch(alone, tol=1e-10, raise_on_error=False)
+    for k, info in enumerate(infos):
+        n, s, p = shapes[k]
+        assert info.status == 0 and info.relres_true <= 1e-10, (shapes[k], info.as_dict())
+        if k in small:
+            assert info.steps == 0
+            assert torch.equal(items[k][3], alone[small.index(k)][3])
+            assert infos_small[small.index(k)].relres_true == info.relres_true
+        else:
+            assert info.steps > 0
+            A, B, C = cases[k]
+            assert rel(host(items[k][3]), kron.kron_solve(A, B, C)) <= 1e-8
+    probs = c._problems(items[:2])
+    probs[1].X = None  # a malformed instance beyond the limit
+    o = tsylv.default_opts(tsylv.TBS)
+    bad = (tsylv.Info * 2)()
+    assert tsylv.load().tsylv_tbs_batch(c.handle, 2, probs, ctypes.byref(o), bad) == -1
 
 
 @pytest.mark.gpu

@@ -124,15 +124,33 @@ def test_invalid_arguments_rejected_without_gpu():
     assert lib.tsylv_create(ctypes.byref(h), 0, None, None, 0) == -1
 
 
-def test_tbs_workspace_bounds():
-    """tsylv_workspace_bytes of the direct solve: positive up to n, s = 64,
-    zero (invalid) past it; host-only, no GPU call."""
+def test_tbs_workspace_bounds(monkeypatch):
+    """tsylv_workspace_bytes of the direct solve: its own up to n, s = 64,
+    past it that of the tGMRES(30) that stands in for it; the batched form
+    likewise (the larger of its direct and tGMRES parts), 0 for a malformed
+    instance.  Host-only, no GPU call."""
     assert tsylv.workspace_bytes(tsylv.TBS, 8, 6, 4) > 0
     assert tsylv.workspace_bytes(tsylv.TBS, 64, 64, 33) > 0
-    assert tsylv.workspace_bytes(tsylv.TBS, 65, 6, 4) == 0
-    assert tsylv.workspace_bytes(tsylv.TBS, 8, 65, 4) == 0
+    g = tsylv.default_opts(tsylv.GMRES)
+    for n, s in ((65, 6), (8, 65), (300, 80)):
+        assert tsylv.workspace_bytes(tsylv.TBS, n, s, 4) == tsylv.workspace_bytes(
+            tsylv.GMRES, n, s, 4, g)
     small = tsylv.workspace_bytes(tsylv.TBS, 8, 6, 4)
     assert tsylv.workspace_bytes(tsylv.TBS, 8, 6, 8) > small
+    lib = tsylv.load()
+    probs = (tsylv.Problem * 3)()
+    for k, (n, s, p) in enumerate([(8, 6, 4), (65, 6, 4), (30, 3, 2)]):
+        probs[k].n, probs[k].s, probs[k].p = n, s, p
+        probs[k].A = probs[k].B = probs[k].C = probs[k].X = 4096  # never dereferenced
+    direct = lib.tsylv_tbs_batch_workspace_bytes(1, probs)
+    assert direct > 0
+    monkeypatch.setenv("TSYLV_KRYLOV_TINY", "0")  # the tGMRES part in lockstep
+    mixed = lib.tsylv_tbs_batch_workspace_bytes(3, probs)
+    both = (tsylv.Problem * 1)(probs[1])
+    krylov = lib.tsylv_batch_workspace_bytes(1, both, ctypes.byref(g))
+    assert mixed >= max(direct, krylov) and krylov > 0
+    probs[2].n = 0
+    assert lib.tsylv_tbs_batch_workspace_bytes(3, probs) == 0
 
 
 def test_default_apply_variant_is_host_logic():
