@@ -402,12 +402,13 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-// out[col(k)] = sum over the block of acc[k], for the columns this lane's
-// group owns; cols[k] < 0 skips k.  One barrier.
-template <int NA>
-__device__ __forceinline__ void oblock_store(const double (&acc)[NA], const int (&cols)[NA],
-                                             int ncols, const double* __restrict__ scale,
-                                             double* __restrict__ out) {
+// Block sums of acc[k] into columns cols[k] (< 0 skips k) of `ncols`, the
+// columns this lane's group owns; column c's sum r goes to out[pos(c)]
+// (skipped when pos(c) < 0) as put(c, r).  One barrier.
+template <int NA, typename Pos, typename Put>
+__device__ __forceinline__ void oblock_reduce(const double (&acc)[NA], const int (&cols)[NA],
+                                              int ncols, Pos pos, Put put,
+                                              double* __restrict__ out) {
   constexpr int MAXC = NA * kOGroups;
   __shared__ double red[kOWaves][MAXC];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -421,8 +422,19 @@ __device__ __forceinline__ void oblock_store(const double (&acc)[NA], const int 
     double r = red[0][c];
 #pragma unroll
     for (int q = 1; q < kOWaves; ++q) r += red[q][c];
-    out[c] = scale ? r * scale[c] : r;
+    const int at = pos(c);
+    if (at >= 0) out[at] = put(c, r);
   }
+}
+
+// out[col(k)] = sum over the block of acc[k] (times scale[col] if given).
+template <int NA>
+__device__ __forceinline__ void oblock_store(const double (&acc)[NA], const int (&cols)[NA],
+                                             int ncols, const double* __restrict__ scale,
+                                             double* __restrict__ out) {
+  oblock_reduce<NA>(
+      acc, cols, ncols, [](int c) { return c; },
+      [scale](int c, double r) { return scale ? r * scale[c] : r; }, out);
 }
 
 // Loads this lane's EPL elements of its group's VPW vectors for the tile at
@@ -629,13 +641,17 @@ __global__ __launch_bounds__(kBlock) void ortho_update_kernel(
 // ---- delayed reorthogonalisation (one projection sweep + one update sweep
 // per Arnoldi step; see the Krylov driver) ---------------------------------
 
-// part[c] = [sigma_i V_i . u (i < nv), sigma_i V_i . w (i < nv), u . w,
-//            u . u, w . w] over chunk c (2 nv + 3 values).
+// part[c] = [sigma_i V_i . u (i < nvt), sigma_i V_i . w (i < nvt), u . w,
+//            u . u, w . w] over chunk c (2 nvt + 3 values).  One launch
+// covers the nv vectors i0 .. i0 + nv - 1 of the nvt (V and sigma point at
+// vector i0) and, when `scalars`, the last three values; each vector's sum
+// is the same whichever launch covers it (its lane group and element order
+// depend on its index only).
 template <typename T, int VPW, int EPL>
 __global__ __launch_bounds__(kBlock) void ortho_dots2_kernel(
     const T* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ sigma,
     const T* __restrict__ u, const T* __restrict__ w, int64_t N, double* __restrict__ part,
-    int ldp) {
+    int ldp, int i0, int nvt, int scalars) {
   constexpr int TE = 16 * EPL;
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -689,7 +705,15 @@ __global__ __launch_bounds__(kBlock) void ortho_dots2_kernel(
   cols[2 * VPW] = (g == 0) ? 2 * nv : -1;
   cols[2 * VPW + 1] = (g == 0) ? 2 * nv + 1 : -1;
   cols[2 * VPW + 2] = (g == 0) ? 2 * nv + 2 : -1;
-  oblock_store<2 * VPW + 3>(all, cols, 2 * nv + 3, nullptr, out);
+  // local column c: V . u of vector c < nv, V . w of vector c - nv < nv, then
+  // the three scalars
+  oblock_reduce<2 * VPW + 3>(
+      all, cols, 2 * nv + 3,
+      [=](int c) {
+        return c < nv ? i0 + c
+                      : (c < 2 * nv ? nvt + i0 + (c - nv) : (scalars ? 2 * nvt + (c - 2 * nv) : -1));
+      },
+      [](int, double r) { return r; }, out);
 }
 
 // coef = [ac (nv), bc (nv), alpha, gamma] (FP64):
@@ -1176,24 +1200,52 @@ void ortho_update(const bf16t* V, int64_t ldv, int nv, const double* h, const do
 }
 
 template <typename T>
+static void ortho_dots2_part(const T* V, int64_t ldv, int nv, const double* sigma, const T* u,
+                             const T* w, int64_t N, double* part, int ldp, int i0, int nvt,
+                             bool scalars, hipStream_t st) {
+  const dim3 grid(ortho_chunks(N)), block(kBlock);
+  constexpr int EPL = ortho_epl<T>();
+  const T* Vi = V + (int64_t)i0 * ldv;
+  const double* si = sigma + i0;
+  const int sc = scalars ? 1 : 0;
+  switch (ortho_vpw(nv)) {
+#define F(K)                                                                               \
+  case K:                                                                                  \
+    hipLaunchKernelGGL((ortho_dots2_kernel<T, K, EPL>), grid, block, 0, st, Vi, ldv, nv, si, \
+                       u, w, N, part, ldp, i0, nvt, sc);                                   \
+    break;
+    TSYLV_OVPW_CASES(F)
+#undef F
+  }
+  TSYLV_LAUNCH_CHECK();
+}
+
+// Above ortho_dots2_split<T>() vectors the sweep is two launches (that many
+// vectors with the scalars, then the rest): one launch over all of them
+// would need more than 168 VGPRs (the FP64 sums of 2 VPW vectors per lane
+// and their widened values), two waves per SIMD and too few loads in
+// flight (3.9 against 5.7 TB/s for BF16 vectors at n s p = 6.7e7); the
+// split re-reads u and w once more and computes the same bits.  BF16 vectors
+// reach that at VPW = 10 (193 VGPRs), FP32 and FP64 ones at VPW = 12.
+template <typename T>
+constexpr int ortho_dots2_split() {
+  return sizeof(T) == 2 ? 8 * kOGroups : 10 * kOGroups;
+}
+
+template <typename T>
 static void ortho_dots2_any(const T* V, int64_t ldv, int nv, const double* sigma, const T* u,
                             const T* w, int64_t N, double* part, int ldp, hipStream_t st) {
   if (nv < 1 || 2 * nv + 3 > ldp) throw Error(TSYLV_EINVAL, "ortho: bad vector count");
   if (N <= 0) return;
   ortho_check(V, ldv, w);
   ortho_check(V, ldv, u);
-  const dim3 grid(ortho_chunks(N)), block(kBlock);
-  constexpr int EPL = ortho_epl<T>();
-  switch (ortho_vpw(nv)) {
-#define F(K)                                                                                   \
-  case K:                                                                                      \
-    hipLaunchKernelGGL((ortho_dots2_kernel<T, K, EPL>), grid, block, 0, st, V, ldv, nv, sigma, \
-                       u, w, N, part, ldp);                                                    \
-    break;
-    TSYLV_OVPW_CASES(F)
-#undef F
+  constexpr int split = ortho_dots2_split<T>();
+  if (nv <= split) {
+    ortho_dots2_part(V, ldv, nv, sigma, u, w, N, part, ldp, 0, nv, true, st);
+    return;
   }
-  TSYLV_LAUNCH_CHECK();
+  ortho_dots2_part(V, ldv, split, sigma, u, w, N, part, ldp, 0, nv, true, st);
+  ortho_dots2_part(V, ldv, nv - split, sigma, u, w, N, part, ldp, split, nv, false, st);
 }
 
 template <typename T>
