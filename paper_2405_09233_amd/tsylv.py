@@ -124,8 +124,13 @@ EXPORTED = sorted(_SIGS)
 
 
 def load(path=None):
-    """Load libtsylv.so (once).  Raises OSError if it is missing."""
+    """Load libtsylv.so (once).  Raises OSError if it is missing.  torch is
+    imported first: it brings its own copy of the HIP runtime, and the
+    library must bind to that one (loaded first, the library would bind to
+    the system's copy, and torch's streams and memory would not be valid in
+    it)."""
     global _lib
+    import torch  # noqa: F401  (the HIP runtime the library binds to)
     with _lock:
         if _lib is None:
             p = path or LIB_PATH
