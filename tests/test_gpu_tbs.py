@@ -167,6 +167,31 @@ def test_tbs_batch_mixed_sizes_match_oracle():
 
 
 @pytest.mark.gpu
+def test_served_tbs_beyond_the_limit_solves_by_tgmres():
+    """A TBS request with n above 64 through the serving loop: solved by
+    the tGMRES that stands in for the direct solve, bitwise the synchronous
+    tsylv_tbs result, with Krylov steps reported."""
+    import torch
+    say("served tbs beyond 64")
+    c = ctx()
+    A, B, C = workloads.dense_shifted(70, 5, 3, seed=1600)
+    Ad, Bd, Cd = dev(A), dev(B), dev(C)
+    Xs, info_s = c.tbs(Ad, Bd, Cd, tol=1e-10)
+    assert info_s.status == 0 and info_s.steps > 0, info_s.as_dict()
+    Xa = torch.zeros_like(Cd)
+    t = c.submit(Ad, Bd, Cd, Xa, method=tsylv.TBS, tol=1e-10)
+    deadline = time.time() + 60.0
+    while True:
+        st, info = c.poll(t)
+        if st != 2:
+            break
+        assert time.time() < deadline, "serving loop did not finish"
+        time.sleep(0.001)
+    assert st == 0 and info.steps == info_s.steps, info.as_dict()
+    assert torch.equal(Xa, Xs)
+
+
+@pytest.mark.gpu
 def test_tbs_batch_solves_large_instances_by_tgmres():
     """A batch mixing instances within the direct solve's limit and beyond
     it: the small ones bitwise their batch without the large ones (direct,
